@@ -1,0 +1,627 @@
+"""Plain FP64 CPU oracle for the space-time (p,delta)-Navier-Stokes smoothing step.
+
+TEST INFRASTRUCTURE ONLY.  Imported by ``tests/``, by ``__graft_entry__.smoke()``
+and by the ``cpu_baseline`` leg of ``bench.py``; never by the product package,
+and it shares no code with the HIP path.  The element-level arithmetic is plain
+C in ``pns_oracle.c`` (per-cell quadrature loops, no sum factorisation); this
+module adds the global pieces with numpy / scipy library primitives:
+
+* right Gauss-Radau nodes and the temporal matrices M_t, K_t, m_t
+  (Sec. 3.1 "Gauss-Radau temporal nodes", Sec. 5.2 definitions of M_t, K_t, m_t);
+* assembled spatial blocks J_mu and the slab Jacobian J_n,
+  eq. (slab-underint-jac);
+* Vanka cell patches, the exact patch matrices R_K A R_K^T and the finest-level
+  surrogate patches with coefficients frozen at the slab midpoint,
+  eq. (surrogate-diag) (Sec. 6.3);
+* one additive Vanka smoothing step, eq. (stmg-vanka-update);
+* the nested Q2 / P1disc prolongation, Galerkin coarse operators
+  A_l = P^T A_{l+1} P (Sec. 6.3 "Hierarchy and coarse operators") and the
+  V-cycle with a dense LU on the coarsest level.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field as dcfield
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+PICARD, EXACT_NEWTON, MODIFIED_NEWTON = 0, 1, 2
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SRC_PATH = os.path.join(_HERE, "pns_oracle.c")
+
+
+def build(verbose: bool = False) -> str:
+    """Compile the C part of the oracle (plain gcc, -O2, no fast-math)."""
+    import subprocess
+
+    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fno-fast-math", "-ffp-contract=off",
+           SRC_PATH, "-o", LIB_PATH, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    return LIB_PATH
+
+
+class _CProblem(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("n", ctypes.c_int * 3),
+        ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+        ("nt", ctypes.c_int), ("kt", ctypes.c_double * 16),
+        ("wt", ctypes.c_double * 4), ("mt", ctypes.c_double * 4),
+        ("tau", ctypes.c_double),
+        ("p", ctypes.c_double), ("delta", ctypes.c_double),
+        ("nu", ctypes.c_double), ("nu_inf", ctypes.c_double),
+        ("gamma1", ctypes.c_double), ("gamma2", ctypes.c_double),
+        ("sigma_max", ctypes.c_double),
+        ("convection", ctypes.c_int), ("qsign", ctypes.c_int), ("lin", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER(_CProblem)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        for name, args in [
+            ("orc_num_nodes", [P]), ("orc_num_cells", [P]),
+            ("orc_spatial_size", [P]), ("orc_local_size", [P]),
+        ]:
+            getattr(L, name).argtypes = args
+            getattr(L, name).restype = ctypes.c_int
+        L.orc_stress.argtypes = [P, dp, dp]
+        L.orc_tangent.argtypes = [P, ctypes.c_int, dp, dp, dp]
+        L.orc_local_dofs.argtypes = [P, ctypes.c_int, ip]
+        L.orc_element_matrix.argtypes = [P, ctypes.c_int, dp, dp]
+        L.orc_element_mass.argtypes = [P, ctypes.c_int, dp]
+        L.orc_all_element_matrices.argtypes = [P, dp, dp]
+        L.orc_apply.argtypes = [P, dp, dp, dp]
+        L.orc_element_form.argtypes = [P, ctypes.c_int, dp, dp, dp, dp]
+        L.orc_residual.argtypes = [P, dp, dp, dp, dp]
+        for f in ("orc_stress", "orc_tangent", "orc_local_dofs", "orc_element_matrix",
+                  "orc_element_mass", "orc_all_element_matrices", "orc_apply",
+                  "orc_element_form", "orc_residual"):
+            getattr(L, f).restype = None
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ------------------------------------------------------------------ time
+
+def radau_right(k: int):
+    """Right-sided (k+1)-point Gauss-Radau rule on [0,1] (Sec. 3.1): the nodes are
+    the roots of P_{k+1} - P_k on [-1,1] (which include +1), mapped to [0,1];
+    weights integrate the nodal Lagrange basis exactly."""
+    from numpy.polynomial import legendre as L
+
+    if k == 0:
+        return np.array([1.0]), np.array([1.0])
+    c = np.zeros(k + 2)
+    c[k + 1] = 1.0
+    c[k] = -1.0
+    r = np.sort(np.real(L.legroots(c)))
+    nodes = 0.5 * (r + 1.0)
+    nodes[-1] = 1.0
+    gx, gw = L.leggauss(k + 2)
+    gx = 0.5 * (gx + 1.0)
+    gw = 0.5 * gw
+    w = np.array([np.sum(gw * lagrange(nodes, i, gx)) for i in range(k + 1)])
+    return nodes, w
+
+
+def lagrange(nodes, i, t):
+    t = np.asarray(t, dtype=np.float64)
+    v = np.ones_like(t)
+    for j, tj in enumerate(nodes):
+        if j != i:
+            v = v * (t - tj) / (nodes[i] - tj)
+    return v
+
+
+def lagrange_der(nodes, i, t):
+    t = np.asarray(t, dtype=np.float64)
+    tot = np.zeros_like(t)
+    for m, tm in enumerate(nodes):
+        if m == i:
+            continue
+        v = np.ones_like(t) / (nodes[i] - tm)
+        for j, tj in enumerate(nodes):
+            if j != i and j != m:
+                v = v * (t - tj) / (nodes[i] - tj)
+        tot = tot + v
+    return tot
+
+
+def time_matrices(k: int):
+    """Reference M_t, K_t, m_t of Sec. 5.2:
+    (M_t)_ij = int xi_j xi_i, (K_t)_ij = int xi_j' xi_i + xi_j(0) xi_i(0),
+    (m_t)_i = xi_i(0), with xi the Radau Lagrange basis.  Integrals by a
+    Gauss-Legendre rule exact for the polynomial degree involved."""
+    from numpy.polynomial import legendre as L
+
+    nodes, _ = radau_right(k)
+    n = k + 1
+    gx, gw = L.leggauss(k + 2)
+    gx = 0.5 * (gx + 1.0)
+    gw = 0.5 * gw
+    M = np.zeros((n, n))
+    K = np.zeros((n, n))
+    m = np.zeros(n)
+    for i in range(n):
+        xi_i = lagrange(nodes, i, gx)
+        m[i] = lagrange(nodes, i, np.array([0.0]))[0]
+        for j in range(n):
+            M[i, j] = np.sum(gw * lagrange(nodes, j, gx) * xi_i)
+            K[i, j] = (np.sum(gw * lagrange_der(nodes, j, gx) * xi_i)
+                       + lagrange(nodes, j, np.array([0.0]))[0] * m[i])
+    return nodes, M, K, m
+
+
+# --------------------------------------------------------------- problem
+
+@dataclass
+class Problem:
+    """Mesh, discretisation and model of one slab (uniform box mesh, Q2/P1disc x dG(k))."""
+    n: tuple
+    lo: tuple = (0.0, 0.0, 0.0)
+    hi: tuple = (1.0, 1.0, 1.0)
+    k_time: int = 1
+    tau: float = 0.01
+    p: float = 1.5
+    delta: float = 1e-2
+    nu: float = 1.0
+    nu_inf: float = 1e-3
+    gamma1: float = 40.0
+    gamma2: float = 40.0
+    sigma_max: float = 1.0
+    convection: int = 1
+    qsign: int = 1
+    lin: int = MODIFIED_NEWTON
+    _c: object = dcfield(default=None, repr=False, compare=False)
+
+    @property
+    def dim(self):
+        return len(self.n)
+
+    def cstruct(self, **override) -> _CProblem:
+        fields = dict(self.__dict__)
+        fields.update(override)
+        s = _CProblem()
+        d = len(fields["n"])
+        s.dim = d
+        for k in range(3):
+            s.n[k] = fields["n"][k] if k < d else 1
+            s.lo[k] = fields["lo"][k]
+            s.hi[k] = fields["hi"][k]
+        _, M, K, m = time_matrices(fields["k_time"])
+        nt = fields["k_time"] + 1
+        s.nt = nt
+        for i in range(nt):
+            s.wt[i] = M[i, i]
+            s.mt[i] = m[i]
+            for j in range(nt):
+                s.kt[i * nt + j] = K[i, j]
+        s.tau = fields["tau"]
+        for name in ("p", "delta", "nu", "nu_inf", "gamma1", "gamma2", "sigma_max"):
+            setattr(s, name, float(fields[name]))
+        s.convection = int(fields["convection"])
+        s.qsign = int(fields["qsign"])
+        s.lin = int(fields["lin"])
+        return s
+
+    def with_(self, **kw) -> "Problem":
+        d = {k: v for k, v in self.__dict__.items() if k != "_c"}
+        d.update(kw)
+        return Problem(**d)
+
+    # sizes
+    @property
+    def nt(self):
+        return self.k_time + 1
+
+    @property
+    def num_nodes(self):
+        return int(np.prod([2 * m + 1 for m in self.n]))
+
+    @property
+    def num_cells(self):
+        return int(np.prod(self.n))
+
+    @property
+    def nv(self):
+        return self.dim * self.num_nodes
+
+    @property
+    def ns(self):
+        return self.nv + (self.dim + 1) * self.num_cells
+
+    @property
+    def nst(self):
+        return self.nt * self.ns
+
+    @property
+    def nloc(self):
+        return self.dim * 3 ** self.dim + self.dim + 1
+
+    @property
+    def h(self):
+        return tuple((self.hi[k] - self.lo[k]) / self.n[k] for k in range(self.dim))
+
+
+def _cs(prob: Problem, **kw):
+    return ctypes.byref(prob.cstruct(**kw))
+
+
+# ------------------------------------------------------- pointwise (L0)
+
+def stress(prob: Problem, A):
+    A = _f64(A)
+    S = np.zeros_like(A)
+    lib().orc_stress(_cs(prob), _dp(A), _dp(S))
+    return S
+
+
+def tangent(prob: Problem, kind: int, A, B):
+    A = _f64(A)
+    B = _f64(B)
+    T = np.zeros_like(B)
+    lib().orc_tangent(_cs(prob), int(kind), _dp(A), _dp(B), _dp(T))
+    return T
+
+
+# ------------------------------------------------------------ elements
+
+def local_dofs(prob: Problem):
+    """(num_cells, nloc) spatial indices: velocity comp c / node a at c*3^d+a,
+    then the d+1 pressure coefficients."""
+    out = np.zeros((prob.num_cells, prob.nloc), dtype=np.int32)
+    cs = _cs(prob)
+    for c in range(prob.num_cells):
+        lib().orc_local_dofs(cs, c, out[c].ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+    return out
+
+
+def element_matrices(prob: Problem, u_spatial, **kw):
+    """All cell matrices of J_mu at velocity state u (length d*num_nodes)."""
+    u = _f64(u_spatial)
+    assert u.size == prob.nv
+    E = np.zeros((prob.num_cells, prob.nloc, prob.nloc))
+    lib().orc_all_element_matrices(_cs(prob, **kw), _dp(u), _dp(E))
+    return E
+
+
+def element_mass(prob: Problem, cell: int = 0):
+    nb = 3 ** prob.dim
+    M = np.zeros((nb, nb))
+    lib().orc_element_mass(_cs(prob), int(cell), _dp(M))
+    return M
+
+
+def assemble_spatial(prob: Problem, u_spatial, **kw):
+    """Assembled spatial block J_mu (ns x ns, CSR) at velocity state u."""
+    E = element_matrices(prob, u_spatial, **kw)
+    dofs = local_dofs(prob)
+    rows = np.repeat(dofs, prob.nloc, axis=1).ravel()
+    cols = np.tile(dofs, (1, prob.nloc)).ravel()
+    return sp.csr_matrix((E.ravel(), (rows, cols)), shape=(prob.ns, prob.ns))
+
+
+def assemble_velocity_mass(prob: Problem):
+    """Velocity mass M_x embedded in the spatial (ns x ns) layout."""
+    nb = 3 ** prob.dim
+    dofs = local_dofs(prob)
+    rows, cols, vals = [], [], []
+    for c in range(prob.num_cells):
+        Mc = element_mass(prob, c)
+        for comp in range(prob.dim):
+            idx = dofs[c, comp * nb:(comp + 1) * nb]
+            rows.append(np.repeat(idx, nb))
+            cols.append(np.tile(idx, nb))
+            vals.append(Mc.ravel())
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(prob.ns, prob.ns))
+
+
+def assemble_slab(prob: Problem, uk_blocks, **kw):
+    """J_n = [K_t (x) M_x, 0; 0, 0] + (tau M_t (x) I) diag(J_1..J_{k+1}),
+    eq. (slab-underint-jac).  uk_blocks: nt velocity states."""
+    _, Mt, Kt, _ = time_matrices(prob.k_time)
+    Mx = assemble_velocity_mass(prob)
+    Js = [assemble_spatial(prob, uk_blocks[m], **kw) for m in range(prob.nt)]
+    blocks = [[None] * prob.nt for _ in range(prob.nt)]
+    for i in range(prob.nt):
+        for j in range(prob.nt):
+            B = Kt[i, j] * Mx
+            if i == j:
+                B = B + prob.tau * Mt[i, i] * Js[i]
+            blocks[i][j] = B
+    return sp.bmat(blocks, format="csr")
+
+
+def split_uk(prob: Problem, uk):
+    uk = _f64(uk)
+    return [uk[m * prob.nv:(m + 1) * prob.nv] for m in range(prob.nt)]
+
+
+# ------------------------------------------------------------- actions
+
+def apply(prob: Problem, uk, x, **kw):
+    """Matrix-free oracle action y = J_n(u_k) x (element matrices built per cell)."""
+    uk = _f64(uk)
+    x = _f64(x)
+    assert uk.size == prob.nt * prob.nv and x.size == prob.nst
+    y = np.zeros(prob.nst)
+    lib().orc_apply(_cs(prob, **kw), _dp(uk), _dp(x), _dp(y))
+    return y
+
+
+def residual(prob: Problem, U, vprev=None, ulag=None, **kw):
+    """Slab residual R_n(U), eq. (slab-underint), f = 0, g_D = 0."""
+    U = _f64(U)
+    R = np.zeros(prob.nst)
+    vp = _f64(vprev) if vprev is not None else None
+    ul = _f64(ulag) if ulag is not None else None
+    lib().orc_residual(_cs(prob, **kw), _dp(U), _dp(vp) if vp is not None else None,
+                       _dp(ul) if ul is not None else None, _dp(R))
+    return R
+
+
+def state_from_velocity(prob: Problem, uk):
+    """Space-time vector whose velocity part is uk (per node) and pressure 0."""
+    U = np.zeros(prob.nst)
+    for m, u in enumerate(split_uk(prob, uk)):
+        U[m * prob.ns:m * prob.ns + prob.nv] = u
+    return U
+
+
+# -------------------------------------------------------------- patches
+
+def cell_patch(prob: Problem, cell: int, node_mask=None):
+    """Space-time index set I_K of the cell patch (Sec. 6.3): every temporal
+    coefficient of the cell's velocity nodes (those kept by node_mask) and of
+    its pressure coefficients.  Order: time node, velocity comp, local node,
+    then pressure."""
+    nb = 3 ** prob.dim
+    ld = local_dofs(prob)[cell]
+    keep = np.arange(nb) if node_mask is None else np.flatnonzero(node_mask)
+    idx = []
+    for m in range(prob.nt):
+        base = m * prob.ns
+        for c in range(prob.dim):
+            idx.extend(base + ld[c * nb + keep])
+        idx.extend(base + ld[prob.dim * nb:])
+    return np.asarray(idx, dtype=np.int64)
+
+
+def all_patches(prob: Problem, node_masks=None):
+    ld = local_dofs(prob)
+    nb = 3 ** prob.dim
+    out = []
+    for c in range(prob.num_cells):
+        keep = np.arange(nb) if node_masks is None else np.flatnonzero(node_masks[c])
+        idx = []
+        for m in range(prob.nt):
+            base = m * prob.ns
+            for comp in range(prob.dim):
+                idx.extend(base + ld[c, comp * nb + keep])
+            idx.extend(base + ld[c, prob.dim * nb:])
+        out.append(np.asarray(idx, dtype=np.int64))
+    return out
+
+
+def representative_velocity(prob: Problem, uk, t_rep: float = 0.5):
+    """u at t_rep of the slab from its Radau nodal values, u_rep = sum_mu xi_mu(t_rep) u_mu."""
+    nodes, _ = radau_right(prob.k_time)
+    blocks = split_uk(prob, uk)
+    return sum(lagrange(nodes, m, np.array([t_rep]))[0] * blocks[m] for m in range(prob.nt))
+
+
+def assemble_surrogate(prob: Problem, uk, t_rep: float = 0.5):
+    """Finest-level operator whose spatial blocks are all frozen at t_rep,
+    eq. (surrogate-diag): diag(J_1..J_{k+1}) -> I (x) J(u_rep)."""
+    ur = representative_velocity(prob, uk, t_rep)
+    return assemble_slab(prob, [ur] * prob.nt)
+
+
+def patch_matrices(A, patches):
+    A = A.tocsr()
+    return [A[idx][:, idx].toarray() for idx in patches]
+
+
+def vanka_step(A, patch_mats, patches, r, d, omega):
+    """One additive Vanka step, eq. (stmg-vanka-update):
+    d <- d + omega sum_K R_K^T (A_K)^{-1} R_K (r - A d), with A_K the given
+    patch matrices, each solved by LU with partial pivoting."""
+    res = r - A @ d
+    corr = np.zeros_like(d)
+    for AK, idx in zip(patch_mats, patches):
+        corr[idx] += sla.lu_solve(sla.lu_factor(AK), res[idx])
+    return d + omega * corr
+
+
+# ----------------------------------------------------------- hierarchy
+
+def prolongation_spatial(coarse: Problem, fine: Problem):
+    """Nested interpolation coarse -> fine: Q2 velocity by evaluating the coarse
+    Q2 function at the fine nodes, P1disc pressure by restricting the coarse
+    linear function to each child cell (exact for nested meshes)."""
+    d = coarse.dim
+    assert all(fine.n[k] == 2 * coarse.n[k] for k in range(d))
+    Hc = coarse.h
+    # velocity
+    nnf = [2 * m + 1 for m in fine.n]
+    nnc = [2 * m + 1 for m in coarse.n]
+    grids = np.meshgrid(*[np.arange(m) for m in nnf], indexing="ij")
+    # lexicographic with x fastest: index = i0 + nnf0*(i1 + nnf1*i2)
+    fidx = [g.ravel(order="F") for g in grids]
+    nf = fidx[0].size
+    xf = [fine.lo[k] + fidx[k] * (fine.h[k] / 2.0) for k in range(d)]
+    cell = [np.minimum(np.floor((xf[k] - coarse.lo[k]) / Hc[k]).astype(np.int64), coarse.n[k] - 1)
+            for k in range(d)]
+    s = [(xf[k] - coarse.lo[k]) / Hc[k] - cell[k] for k in range(d)]
+
+    def q2(a, t):
+        return [2 * (t - .5) * (t - 1), -4 * t * (t - 1), 2 * t * (t - .5)][a]
+
+    frow = np.zeros(nf, dtype=np.int64)
+    stride = 1
+    for k in range(d):
+        frow += fidx[k] * stride
+        stride *= nnf[k]
+    rows, cols, vals = [], [], []
+    for a in range(3 ** d):
+        ak = [(a // 3 ** k) % 3 for k in range(d)]
+        w = np.ones(nf)
+        col = np.zeros(nf, dtype=np.int64)
+        stride = 1
+        for k in range(d):
+            w = w * q2(ak[k], s[k])
+            col += (2 * cell[k] + ak[k]) * stride
+            stride *= nnc[k]
+        nz = np.abs(w) > 0
+        rows.append(frow[nz])
+        cols.append(col[nz])
+        vals.append(w[nz])
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    vals = np.concatenate(vals)
+    Pv = sp.csr_matrix((vals, (rows, cols)), shape=(fine.num_nodes, coarse.num_nodes))
+    Pv.sum_duplicates()
+    # duplicates at nodes shared by coarse cells were not created (each fine
+    # node is assigned to exactly one coarse cell), so Pv is the interpolant.
+    # pressure: fine coefficient (1, (x-xf)/hf, ...) from coarse (1, (x-xc)/H, ...)
+    prow, pcol, pval = [], [], []
+    for fc in range(fine.num_cells):
+        fi = [(fc // int(np.prod(fine.n[:k]))) % fine.n[k] for k in range(d)]
+        ci = [m // 2 for m in fi]
+        cc = 0
+        stride = 1
+        for k in range(d):
+            cc += ci[k] * stride
+            stride *= coarse.n[k]
+        # coarse linear function q = a0 + sum_k a_k (x_k - xc_k)/H_k
+        # on the child: value at child centre and slopes scaled by hf/H
+        for k in range(d + 1):
+            frow_ = fc * (d + 1) + k
+            if k == 0:
+                prow.append(frow_); pcol.append(cc * (d + 1)); pval.append(1.0)
+                for m in range(d):
+                    xf_c = fine.lo[m] + (fi[m] + 0.5) * fine.h[m]
+                    xc_c = coarse.lo[m] + (ci[m] + 0.5) * Hc[m]
+                    prow.append(frow_); pcol.append(cc * (d + 1) + 1 + m)
+                    pval.append((xf_c - xc_c) / Hc[m])
+            else:
+                prow.append(frow_); pcol.append(cc * (d + 1) + k)
+                pval.append(fine.h[k - 1] / Hc[k - 1])
+    Pp = sp.csr_matrix((pval, (prow, pcol)), shape=((d + 1) * fine.num_cells,
+                                                    (d + 1) * coarse.num_cells))
+    return sp.block_diag([Pv] * d + [Pp], format="csr")
+
+
+def prolongation(coarse: Problem, fine: Problem):
+    """Space-time prolongation: identity in time (same dG degree on every level)."""
+    Ps = prolongation_spatial(coarse, fine)
+    return sp.kron(sp.identity(fine.nt), Ps, format="csr")
+
+
+def coarse_problem(prob: Problem) -> Problem:
+    return prob.with_(n=tuple(m // 2 for m in prob.n))
+
+
+@dataclass
+class Hierarchy:
+    probs: list          # level 0 = coarsest
+    A: list              # operators per level
+    P: list              # P[l] : level l -> level l+1
+    patches: list        # per level (all but coarsest)
+    patch_mats: list     # per level (all but coarsest)
+    coarse_lu: object = None
+    pin: list = None
+
+
+def build_hierarchy(prob: Problem, uk, n_levels: int, surrogate: bool = True, node_masks=None):
+    """Levels from coarse (0) to fine (n_levels-1).  Finest operator = exact J_n
+    at u_k; coarse operators Galerkin P^T A P; finest patches from the
+    surrogate operator (midpoint freezing), coarse patches exact."""
+    probs = [prob]
+    for _ in range(n_levels - 1):
+        probs.insert(0, coarse_problem(probs[0]))
+    A = [None] * n_levels
+    A[-1] = assemble_slab(prob, split_uk(prob, uk))
+    P = [None] * (n_levels - 1)
+    for l in range(n_levels - 2, -1, -1):
+        P[l] = prolongation(probs[l], probs[l + 1])
+        A[l] = (P[l].T @ A[l + 1] @ P[l]).tocsr()
+    patches = [None] * n_levels
+    pmats = [None] * n_levels
+    for l in range(1, n_levels):
+        patches[l] = all_patches(probs[l], node_masks if l == n_levels - 1 else None)
+        src = assemble_surrogate(prob, uk) if (l == n_levels - 1 and surrogate) else A[l]
+        pmats[l] = patch_matrices(src, patches[l])
+    H = Hierarchy(probs, A, P, patches, pmats)
+    H.coarse_lu, H.pin = coarse_factor(probs[0], A[0])
+    return H
+
+
+def pressure_pin_indices(prob: Problem):
+    """Constant pressure coefficient of cell 0 at every time node."""
+    return [m * prob.ns + prob.nv for m in range(prob.nt)]
+
+
+def coarse_factor(prob: Problem, A):
+    """Dense LU of the coarsest operator with cell 0's constant pressure
+    coefficient pinned per time node (row and column replaced by identity):
+    with Dirichlet data on the whole boundary the constant pressure of each
+    time node spans the kernel."""
+    Ad = A.toarray()
+    pin = pressure_pin_indices(prob)
+    for i in pin:
+        Ad[i, :] = 0.0
+        Ad[:, i] = 0.0
+        Ad[i, i] = 1.0
+    return sla.lu_factor(Ad), pin
+
+
+def coarse_solve(H: Hierarchy, r):
+    rr = r.copy()
+    rr[H.pin] = 0.0
+    return sla.lu_solve(H.coarse_lu, rr)
+
+
+def vcycle(H: Hierarchy, r, nu1=2, nu2=2, omega=0.5, level=None):
+    """d = V(r): nu1 Vanka steps from d = 0, restrict the defect with P^T,
+    recurse, add the prolongated correction, nu2 Vanka steps; dense LU on the
+    coarsest level."""
+    if level is None:
+        level = len(H.probs) - 1
+    if level == 0:
+        return coarse_solve(H, r)
+    A = H.A[level]
+    d = np.zeros_like(r)
+    for _ in range(nu1):
+        d = vanka_step(A, H.patch_mats[level], H.patches[level], r, d, omega)
+    rc = H.P[level - 1].T @ (r - A @ d)
+    dc = vcycle(H, rc, nu1, nu2, omega, level - 1)
+    d = d + H.P[level - 1] @ dc
+    for _ in range(nu2):
+        d = vanka_step(A, H.patch_mats[level], H.patches[level], r, d, omega)
+    return d
