@@ -1,0 +1,177 @@
+/*
+ * pnsmg.h -- C-ABI of the MI355X space-time multigrid smoothing step for the
+ * time-dependent (p,delta)-Navier-Stokes equations
+ * (Margenberg & Mehlmann, arXiv 2603.28706).
+ *
+ * Discretisation (Sec. 3): uniform quadrilateral mesh of a box, Q2 velocity /
+ * P1disc pressure in space, dG(1) in time with the two right Gauss-Radau nodes
+ * t = 1/3, 1 of the reference slab (Sec. 3.1, Sec. 5.2).  Dirichlet data are
+ * imposed weakly by Nitsche terms on the whole boundary (Sec. 3.2,
+ * eq. def-b-gam) with homogeneous data.
+ *
+ * Vector layout ("canonical"), identical for every vector argument:
+ *   one block per Radau node mu = 0, 1; inside a block the d velocity
+ *   components, each over the (2 n_x + 1)(2 n_y + 1) Q2 nodes in lexicographic
+ *   order (x fastest), then 3 P1disc coefficients per cell (cells
+ *   lexicographic, coefficients of 1, (x - x_c)/h_x, (y - y_c)/h_y).
+ *   A level-l vector has the same layout on the level-l mesh.
+ *
+ * Precision: the context precision (PNS_FP64 or PNS_FP32) is the element type
+ * of every x, y, r, d argument.  The linearisation state u_k is always given
+ * in FP64.  The constitutive power law is evaluated in FP64 in both modes.
+ *
+ * Memory: every pointer named *_dev is a device pointer owned by the caller.
+ * The library allocates no device memory; it works in one caller-provided
+ * workspace (query its size, bind it once).  All calls are asynchronous on the
+ * stream given at creation; they return after enqueueing.  Calls on one
+ * context must not overlap (one stream, one caller at a time).
+ *
+ * Errors: every int-returning call returns PNS_OK (0) or a negative code; the
+ * message of the last error of a context is returned by pns_last_error.  On
+ * error nothing is enqueued and the outputs are unchanged.
+ */
+#ifndef PNSMG_H
+#define PNSMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  PNS_OK = 0,
+  PNS_EINVAL = -1,      /* invalid argument (sizes, model parameters, NULL) */
+  PNS_EWORKSPACE = -2,  /* no workspace bound, or too small / misaligned */
+  PNS_EHIP = -3,        /* a HIP runtime call failed */
+  PNS_ESTATE = -4,      /* call order: no state set / smoother not set up */
+  PNS_ESINGULAR = -5,   /* a patch or the coarse matrix had a zero pivot */
+  PNS_EUNSUPPORTED = -6 /* configuration outside what this build implements */
+};
+
+/* Constitutive tangent of the linearisation (Sec. 4.2-4.4). */
+typedef enum {
+  PNS_PICARD = 0,          /* eta B, eq. (local-tangent-picard) */
+  PNS_EXACT_NEWTON = 1,    /* D S(A) B, eq. (local-tangent-exact) */
+  PNS_MODIFIED_NEWTON = 2  /* stress-clipped rank one, eq. (local-tangent-clip) */
+} pns_lin_kind;
+
+typedef enum { PNS_FP64 = 0, PNS_FP32 = 1 } pns_precision;
+
+/* Box [lo, hi] with n_cells[k] uniform cells per direction; dim must be 2. */
+typedef struct {
+  int dim;
+  int n_cells[3];
+  double lo[3], hi[3];
+} pns_mesh;
+
+/* Q_{k_space} / P_{k_space-1}^disc x dG(k_time) on the slab (t0, t0 + tau].
+ * This build implements k_space = 2, k_time = 1. */
+typedef struct {
+  int k_space;
+  int k_time;
+  double t0, tau;
+} pns_discretization;
+
+/* Model of Sec. 2 / Sec. 3.2:
+ *   S(D) = eta(D) D, eta(D) = nu_inf + nu (delta^2 + |D|^2)^((p-2)/2),
+ *   1 < p <= 2, delta > 0, nu > 0, nu_inf >= 0  (eq. constitutive-law);
+ *   Nitsche penalties gamma1, gamma2 > 0 with h_F = cell size normal to the
+ *   face (eq. def-b-gam); sigma_max >= 0 the stress clip of modified Newton
+ *   (Sec. 4.4); convection = 1 for p-Navier-Stokes, 0 for p-Stokes;
+ *   nitsche_q_sign = +1 makes the Nitsche pressure coupling the transpose of
+ *   the momentum one (-q I in B^s), -1 keeps the printed +q I;
+ *   lin = pns_lin_kind of the Jacobian action. */
+typedef struct {
+  double p, delta, nu, nu_inf;
+  double gamma1, gamma2;
+  double sigma_max;
+  int convection;
+  int nitsche_q_sign;
+  int lin;
+} pns_model;
+
+typedef struct pns_ctx pns_ctx;
+
+/* Create a context for `n_levels` nested meshes (level 0 = the given mesh,
+ * level l has n_cells / 2^l cells per direction, every level keeps dG(1)).
+ * n_cells must be divisible by 2^(n_levels-1).  The dense coarsest solve
+ * (and so pns_vcycle) is available when the coarsest level has at most 40000
+ * space-time unknowns; larger coarsest levels still allow the apply and the
+ * smoother.  `stream` is a hipStream_t (NULL =
+ * default stream).  Returns PNS_EINVAL / PNS_EUNSUPPORTED on bad input. */
+int pns_ctx_create(const pns_mesh* mesh, const pns_discretization* disc, int n_levels,
+                   int precision, void* stream, pns_ctx** out);
+
+void pns_ctx_destroy(pns_ctx* ctx);
+
+/* Message of the last failed call on this context ("" if none). */
+const char* pns_last_error(const pns_ctx* ctx);
+
+/* Sizes of level `level`: out[0] = space-time unknowns, out[1] = cells,
+ * out[2] = velocity unknowns per Radau node, out[3] = spatial unknowns per
+ * Radau node. */
+int pns_level_sizes(const pns_ctx* ctx, int level, int64_t out[4]);
+
+/* Bytes of device workspace the context needs (all levels, smoother data,
+ * coarse inverse) and its required alignment (256). */
+size_t pns_workspace_bytes(const pns_ctx* ctx);
+
+/* Bind a caller-owned device buffer of at least pns_workspace_bytes bytes,
+ * 256-byte aligned; it must stay valid until the context is destroyed or
+ * another buffer is bound.  Binding invalidates state and smoother data. */
+int pns_bind_workspace(pns_ctx* ctx, void* ws_dev, size_t bytes);
+
+/* Set the linearisation point: u_k_dev holds the velocity (FP64) at both
+ * Radau nodes, 2 blocks of d*(2n_x+1)(2n_y+1) values in the canonical
+ * velocity layout.  Copies it into the workspace.  Invalidates the smoother. */
+int pns_set_state(pns_ctx* ctx, const pns_model* model, const double* u_k_dev);
+
+/* y = J_n(u_k) x on level 0, eq. (slab-underint-jac): the temporal mass
+ * coupling K_t (x) M_x plus tau M_t (x) diag(J_1, J_2), each J_mu the spatial
+ * linearisation of Sec. 5.2 (viscous volume term with the selected tangent,
+ * convection, pressure coupling, boundary flux and Nitsche terms) at u_k of
+ * Radau node mu.  Matrix-free; x, y in the context precision, canonical
+ * layout, must not alias. */
+int pns_cell_apply(pns_ctx* ctx, const void* x_dev, void* y_dev);
+
+/* Same operator as pns_cell_apply, y = b - J_n x (the global defect). */
+int pns_cell_defect(pns_ctx* ctx, const void* b_dev, const void* x_dev, void* y_dev);
+
+/* Build the smoother of every level (Sec. 6.3): level 0 patch matrices from
+ * the surrogate operator with all state-dependent coefficients frozen at the
+ * slab midpoint, eq. (surrogate-diag); coarse operators A_{l+1} = P^T A_l P
+ * formed element by element; exact coarse patch matrices; LU-based inverses
+ * of every patch; dense inverse of the coarsest operator with the constant
+ * pressure coefficient of cell 0 pinned at each Radau node.
+ * node_masks (host, may be NULL): one uint16 per level-0 cell, bit a set if
+ * local Q2 node a (a = ax + 3 ay) belongs to that cell's patch; dropped nodes
+ * are removed from the patch (uneven patches).  Returns PNS_ESINGULAR if a
+ * patch has a zero pivot. */
+int pns_vanka_setup(pns_ctx* ctx, const uint16_t* node_masks);
+
+/* n_sweeps additive Vanka steps on level `level`, eq. (stmg-vanka-update):
+ * d <- d + omega sum_K R_K^T A_K^{-1} R_K (r - A_l d), in place on d. */
+int pns_vanka_smooth(pns_ctx* ctx, int level, int n_sweeps, double omega, const void* r_dev,
+                     void* d_dev);
+
+/* d = V(r): one V-cycle over all levels (nu1 pre- and nu2 post-smoothing steps
+ * from d = 0, restriction P^T, coarsest dense solve, prolongation).
+ * PNS_EUNSUPPORTED if the coarsest level exceeds the dense-solve limit. */
+int pns_vcycle(pns_ctx* ctx, int nu1, int nu2, double omega, const void* r_dev, void* d_dev);
+
+/* y = A_l x with the level-l operator (level 0: pns_cell_apply; coarser:
+ * the Galerkin operator applied element by element).  Needs pns_vanka_setup
+ * for level > 0. */
+int pns_level_apply(pns_ctx* ctx, int level, const void* x_dev, void* y_dev);
+
+/* Transfers between level l (fine) and l+1 (coarse): rc = P^T rf and
+ * df += P dc, P the nested Q2 interpolation / P1disc restriction. */
+int pns_restrict(pns_ctx* ctx, int level, const void* rf_dev, void* rc_dev);
+int pns_prolongate_add(pns_ctx* ctx, int level, const void* dc_dev, void* df_dev);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -625,3 +625,76 @@ def vcycle(H: Hierarchy, r, nu1=2, nu2=2, omega=0.5, level=None):
     for _ in range(nu2):
         d = vanka_step(A, H.patch_mats[level], H.patches[level], r, d, omega)
     return d
+
+
+def apply_rows(prob: Problem, uk, x, rows, **kw):
+    """Selected rows of J_n(u_k) x (space-time row indices), each formed from the
+    element matrices of the cells that carry it, so that sampled outputs of a
+    large mesh can be checked without the whole action."""
+    uk = _f64(uk)
+    x = _f64(x)
+    rows = np.asarray(rows, dtype=np.int64)
+    _, _, Kt, _ = time_matrices(prob.k_time)
+    _, w = radau_right(prob.k_time)
+    cs = _cs(prob, **kw)
+    nb = 3 ** prob.dim
+    nloc = prob.nloc
+    ld = np.zeros(prob.nloc, dtype=np.int32)
+    out = np.zeros(rows.size)
+    cache = {}
+
+    def cell_data(c):
+        if c not in cache:
+            lib().orc_local_dofs(cs, int(c), ld.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+            dofs = ld.copy()
+            Es = []
+            for m in range(prob.nt):
+                uloc = _f64(uk[m * prob.nv + dofs[:prob.dim * nb]])
+                E = np.zeros((nloc, nloc))
+                lib().orc_element_matrix(cs, int(c), _dp(uloc), _dp(E))
+                Es.append(E)
+            M = np.zeros((nb, nb))
+            lib().orc_element_mass(cs, int(c), _dp(M))
+            cache[c] = (dofs, Es, M)
+        return cache[c]
+
+    def cells_of(s):
+        """cells whose local unknowns contain spatial index s"""
+        if s >= prob.nv:
+            return [int((s - prob.nv) // (prob.dim + 1))]
+        node = s % prob.num_nodes
+        idx = []
+        r = node
+        for k in range(prob.dim):
+            nn_k = 2 * prob.n[k] + 1
+            idx.append(r % nn_k)
+            r //= nn_k
+        cand = []
+        for k in range(prob.dim):
+            g = idx[k]
+            cand.append([c for c in {(g - 1) // 2, g // 2, (g - 2) // 2 + 1 if g >= 2 else 0}
+                         if 0 <= c < prob.n[k] and 2 * c <= g <= 2 * c + 2])
+        cells = []
+        import itertools
+        for combo in itertools.product(*cand):
+            cid, stride = 0, 1
+            for k in range(prob.dim):
+                cid += combo[k] * stride
+                stride *= prob.n[k]
+            cells.append(cid)
+        return cells
+
+    for t, row in enumerate(rows):
+        mu, s = divmod(int(row), prob.ns)
+        acc = 0.0
+        for c in cells_of(s):
+            dofs, Es, M = cell_data(c)
+            i = int(np.flatnonzero(dofs == s)[0])
+            acc += prob.tau * w[mu] * float(Es[mu][i] @ x[mu * prob.ns + dofs])
+            if i < prob.dim * nb:
+                comp, a = divmod(i, nb)
+                vidx = dofs[comp * nb:(comp + 1) * nb]
+                for nu in range(prob.nt):
+                    acc += Kt[mu, nu] * float(M[a] @ x[nu * prob.ns + vidx])
+        out[t] = acc
+    return out

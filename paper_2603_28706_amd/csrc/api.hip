@@ -1,0 +1,464 @@
+// C-ABI entry points: argument checking, workspace layout, sequencing of the
+// kernels of one smoothing step / V-cycle on the context stream.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pns_internal.h"
+
+using namespace pns;
+
+namespace pns {
+hipError_t launch_pin(int64_t n, double* A, const int64_t* pin, int npin, hipStream_t s);
+hipError_t launch_form_fine_st(const Grid& g, double tau, const double* Es0, const double* Es1,
+                               double* E, hipStream_t s);
+}  // namespace pns
+
+namespace {
+
+struct Level {
+  Grid g;
+  double* E64 = nullptr;  // Galerkin element matrices (FP64), levels >= 1 (and 0 if coarsest)
+  void* E = nullptr;      // same in the context precision
+  void* inv = nullptr;    // patch inverses, column-major, context precision
+  void* res = nullptr;    // defect
+  void* r = nullptr;      // level right-hand side (levels >= 1)
+  void* d = nullptr;      // level correction (levels >= 1)
+};
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kMaxCoarse = 40000;  // dense coarsest inverse limit
+
+}  // namespace
+
+struct pns_ctx {
+  pns_mesh mesh{};
+  pns_discretization disc{};
+  int prec = PNS_FP64;
+  size_t es = 8;
+  int nlev = 1;
+  hipStream_t stream = nullptr;
+  std::vector<Level> lev;
+  Model model{};
+  bool has_state = false, has_smoother = false;
+  std::string err;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  // level-0 data
+  void* uk = nullptr;
+  double* uk64 = nullptr;
+  double* urep = nullptr;
+  double* Es0 = nullptr;
+  double* Es1 = nullptr;
+  double* Esr = nullptr;
+  uint16_t* masks = nullptr;
+  int* status = nullptr;
+  // coarsest level
+  double* Adense = nullptr;
+  double* gjwork = nullptr;
+  int* gjpiv = nullptr;
+  int64_t pin[2] = {-1, -1};
+  bool has_coarse = false;  // the coarsest level is small enough for a dense inverse
+};
+
+namespace {
+
+int fail(pns_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define PNS_HIP(ctx, call)                                                                  \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(ctx, PNS_EHIP, std::string("HIP error: ") + hipGetErrorString(e_) + " at " + \
+                                     #call);                                                \
+  } while (0)
+
+// Lay out (bind == false: only measure) every buffer of the context.
+size_t layout(pns_ctx* c, bool bind) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    char* p = bind ? c->ws + off : nullptr;
+    off += bytes;
+    return p;
+  };
+  const Grid& g0 = c->lev[0].g;
+  const size_t es = c->es;
+  c->uk = take(2 * g0.nv * es);
+  c->uk64 = (double*)take(2 * g0.nv * 8);
+  c->urep = (double*)take(g0.nv * 8);
+  c->Es0 = (double*)take(g0.nc * kNs * kNs * 8);
+  c->Es1 = (double*)take(g0.nc * kNs * kNs * 8);
+  c->Esr = (double*)take(g0.nc * kNs * kNs * 8);
+  c->masks = (uint16_t*)take(g0.nc * sizeof(uint16_t));
+  c->status = (int*)take(sizeof(int) * 4);
+  for (int l = 0; l < c->nlev; ++l) {
+    Level& L = c->lev[l];
+    const bool coarsest = (l == c->nlev - 1);
+    L.inv = take(L.g.nc * kNst * kNst * es);
+    L.res = take(L.g.nst * es);
+    if (l >= 1 || coarsest) {
+      L.E64 = (double*)take(L.g.nc * kNst * kNst * 8);
+      L.E = (es == 8) ? (void*)L.E64 : (void*)take(L.g.nc * kNst * kNst * es);
+    }
+    if (l >= 1) {
+      L.r = take(L.g.nst * es);
+      L.d = take(L.g.nst * es);
+    }
+    if (coarsest && c->has_coarse) {
+      const int64_t n = L.g.nst;
+      c->Adense = (double*)take((size_t)n * n * 8);
+      c->gjwork = (double*)take((size_t)(n + 1) * 8);
+      c->gjpiv = (int*)take((size_t)n * sizeof(int));
+    }
+  }
+  return (off + kAlign - 1) / kAlign * kAlign;
+}
+
+bool check_ctx(pns_ctx* c, bool need_state, bool need_smoother) {
+  if (!c) return false;
+  if (!c->ws) {
+    fail(c, PNS_EWORKSPACE, "no workspace bound");
+    return false;
+  }
+  if (need_state && !c->has_state) {
+    fail(c, PNS_ESTATE, "pns_set_state has not been called");
+    return false;
+  }
+  if (need_smoother && !c->has_smoother) {
+    fail(c, PNS_ESTATE, "pns_vanka_setup has not been called");
+    return false;
+  }
+  return true;
+}
+
+int ctx_code(pns_ctx* c, bool need_state, bool need_smoother) {
+  if (!c) return PNS_EINVAL;
+  if (!c->ws) return PNS_EWORKSPACE;
+  if (need_state && !c->has_state) return PNS_ESTATE;
+  if (need_smoother && !c->has_smoother) return PNS_ESTATE;
+  return PNS_OK;
+}
+
+template <typename T>
+hipError_t defect(pns_ctx* c, int l, const T* b, const T* x, T* y) {
+  Level& L = c->lev[l];
+  if (l == 0)
+    return launch_cell_apply<T>(L.g, c->model, c->disc.tau, (const T*)c->uk, x, b, y, 1, c->stream);
+  return launch_ebe_apply<T>(L.g, (const T*)L.E, x, b, y, 1, c->stream);
+}
+
+template <typename T>
+hipError_t apply_level(pns_ctx* c, int l, const T* x, T* y) {
+  Level& L = c->lev[l];
+  if (l == 0)
+    return launch_cell_apply<T>(L.g, c->model, c->disc.tau, (const T*)c->uk, x, x, y, 0,
+                                c->stream);
+  return launch_ebe_apply<T>(L.g, (const T*)L.E, x, x, y, 0, c->stream);
+}
+
+template <typename T>
+hipError_t smooth(pns_ctx* c, int l, int nsweeps, double omega, const T* r, T* d, bool d_is_zero) {
+  Level& L = c->lev[l];
+  for (int s = 0; s < nsweeps; ++s) {
+    const T* res = r;
+    if (!(s == 0 && d_is_zero)) {
+      hipError_t e = defect<T>(c, l, r, d, (T*)L.res);
+      if (e != hipSuccess) return e;
+      res = (const T*)L.res;
+    }
+    hipError_t e = launch_patch_sweep<T>(L.g, (const T*)L.inv, res, d, omega, c->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t vcycle_level(pns_ctx* c, int l, int nu1, int nu2, double omega, const T* r, T* d) {
+  Level& L = c->lev[l];
+  hipError_t e;
+  if (l == c->nlev - 1) {
+    const int npin = 2;
+    return launch_dense_gemv<T>(L.g.nst, c->Adense, r, d, c->pin, npin, c->stream);
+  }
+  if ((e = launch_fill<T>(L.g.nst, (T)0, d, c->stream)) != hipSuccess) return e;
+  if ((e = smooth<T>(c, l, nu1, omega, r, d, true)) != hipSuccess) return e;
+  const T* res = r;
+  if (nu1 > 0) {
+    if ((e = defect<T>(c, l, r, d, (T*)L.res)) != hipSuccess) return e;
+    res = (const T*)L.res;
+  }
+  Level& C = c->lev[l + 1];
+  if ((e = launch_restrict<T>(L.g, C.g, res, (T*)C.r, c->stream)) != hipSuccess) return e;
+  if ((e = vcycle_level<T>(c, l + 1, nu1, nu2, omega, (const T*)C.r, (T*)C.d)) != hipSuccess)
+    return e;
+  if ((e = launch_prolong_add<T>(L.g, C.g, (const T*)C.d, d, c->stream)) != hipSuccess) return e;
+  return smooth<T>(c, l, nu2, omega, r, d, false);
+}
+
+template <typename T>
+int vanka_setup_impl(pns_ctx* c, const uint16_t* masks) {
+  hipStream_t s = c->stream;
+  const Level& L0 = c->lev[0];
+  PNS_HIP(c, hipMemsetAsync(c->status, 0, sizeof(int), s));
+  if (masks) {
+    PNS_HIP(c, hipMemcpyAsync(c->masks, masks, L0.g.nc * sizeof(uint16_t), hipMemcpyHostToDevice, s));
+    PNS_HIP(c, hipStreamSynchronize(s));
+  }
+  const double* u0 = c->uk64;
+  const double* u1 = c->uk64 + L0.g.nv;
+  PNS_HIP(c, launch_element_matrices(L0.g, c->model, u0, c->Es0, s));
+  PNS_HIP(c, launch_element_matrices(L0.g, c->model, u1, c->Es1, s));
+  PNS_HIP(c, launch_element_matrices(L0.g, c->model, c->urep, c->Esr, s));
+  // level 0: surrogate patches, all state-dependent coefficients at t_rep
+  PNS_HIP(c, launch_fine_patches<T>(L0.g, c->disc.tau, c->Esr, c->Esr, masks ? c->masks : nullptr,
+                                    (T*)L0.inv, c->status, s));
+  // coarse levels: Galerkin element matrices, exact patches
+  for (int l = 1; l < c->nlev; ++l) {
+    Level& L = c->lev[l];
+    if (l == 1)
+      PNS_HIP(c, launch_galerkin_from_fine(L.g, c->disc.tau, c->Es0, c->Es1, L.E64, s));
+    else
+      PNS_HIP(c, launch_galerkin(L.g, c->lev[l - 1].E64, L.E64, s));
+    if (c->es == 4) PNS_HIP(c, launch_convert<float>(L.g.nc * kNst * kNst, L.E64, (float*)L.E, s));
+    PNS_HIP(c, launch_level_patches<T>(L.g, L.E64, (T*)L.inv, c->status, s));
+  }
+  // coarsest level: dense operator, pinned, inverted
+  Level& Lc = c->lev[c->nlev - 1];
+  if (c->nlev == 1) {
+    PNS_HIP(c, launch_form_fine_st(Lc.g, c->disc.tau, c->Es0, c->Es1, Lc.E64, s));
+    if (c->es == 4)
+      PNS_HIP(c, launch_convert<float>(Lc.g.nc * kNst * kNst, Lc.E64, (float*)Lc.E, s));
+  }
+  int st = 0;
+  if (!c->has_coarse) {
+    PNS_HIP(c, hipMemcpyAsync(&st, c->status, sizeof(int), hipMemcpyDeviceToHost, s));
+    PNS_HIP(c, hipStreamSynchronize(s));
+    if (st & 1) return fail(c, PNS_ESINGULAR, "a patch matrix has a zero pivot");
+    c->has_smoother = true;
+    return PNS_OK;
+  }
+  const int64_t n = Lc.g.nst;
+  PNS_HIP(c, hipMemsetAsync(c->Adense, 0, (size_t)n * n * 8, s));
+  PNS_HIP(c, launch_coarse_assemble(Lc.g, Lc.E64, c->Adense, s));
+  c->pin[0] = Lc.g.nv;
+  c->pin[1] = Lc.g.ns + Lc.g.nv;
+  // pin indices must be in device memory for the pin kernel
+  PNS_HIP(c, hipMemcpyAsync(c->gjwork, c->pin, sizeof(c->pin), hipMemcpyHostToDevice, s));
+  PNS_HIP(c, hipStreamSynchronize(s));
+  PNS_HIP(c, launch_pin(n, c->Adense, (const int64_t*)c->gjwork, 2, s));
+  PNS_HIP(c, coarse_invert(n, c->Adense, c->gjwork, c->gjpiv, c->status, s));
+  PNS_HIP(c, hipMemcpyAsync(&st, c->status, sizeof(int), hipMemcpyDeviceToHost, s));
+  PNS_HIP(c, hipStreamSynchronize(s));
+  if (st & 1) return fail(c, PNS_ESINGULAR, "a patch matrix has a zero pivot");
+  if (st & 2) return fail(c, PNS_ESINGULAR, "the coarsest matrix has a zero pivot");
+  c->has_smoother = true;
+  return PNS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pns_ctx_create(const pns_mesh* mesh, const pns_discretization* disc, int n_levels,
+                   int precision, void* stream, pns_ctx** out) {
+  if (!out) return PNS_EINVAL;
+  *out = nullptr;
+  if (!mesh || !disc) return PNS_EINVAL;
+  if (mesh->dim != 2 || disc->k_space != 2 || disc->k_time != 1) return PNS_EUNSUPPORTED;
+  if (precision != PNS_FP64 && precision != PNS_FP32) return PNS_EINVAL;
+  if (!(disc->tau > 0.0) || n_levels < 1 || n_levels > 12) return PNS_EINVAL;
+  const int nx = mesh->n_cells[0], ny = mesh->n_cells[1];
+  if (nx < 1 || ny < 1) return PNS_EINVAL;
+  const double lx = mesh->hi[0] - mesh->lo[0], ly = mesh->hi[1] - mesh->lo[1];
+  if (!(lx > 0.0) || !(ly > 0.0)) return PNS_EINVAL;
+  const int f = 1 << (n_levels - 1);
+  if (nx % f || ny % f || nx / f < 1 || ny / f < 1) return PNS_EINVAL;
+  // tile grid of the level-0 kernel and int cell indices
+  if ((int64_t)nx * ny > (int64_t)1 << 30) return PNS_EUNSUPPORTED;
+  pns_ctx* c = new pns_ctx();
+  c->mesh = *mesh;
+  c->disc = *disc;
+  c->prec = precision;
+  c->es = precision == PNS_FP64 ? 8 : 4;
+  c->nlev = n_levels;
+  c->stream = (hipStream_t)stream;
+  for (int l = 0; l < n_levels; ++l) {
+    Level L;
+    L.g = make_grid(nx >> l, ny >> l, lx, ly);
+    c->lev.push_back(L);
+  }
+  c->has_coarse = c->lev.back().g.nst <= kMaxCoarse;
+  *out = c;
+  return PNS_OK;
+}
+
+void pns_ctx_destroy(pns_ctx* ctx) { delete ctx; }
+
+const char* pns_last_error(const pns_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int pns_level_sizes(const pns_ctx* ctx, int level, int64_t out[4]) {
+  if (!ctx || !out || level < 0 || level >= ctx->nlev) return PNS_EINVAL;
+  const Grid& g = ctx->lev[level].g;
+  out[0] = g.nst;
+  out[1] = g.nc;
+  out[2] = g.nv;
+  out[3] = g.ns;
+  return PNS_OK;
+}
+
+size_t pns_workspace_bytes(const pns_ctx* ctx) {
+  if (!ctx) return 0;
+  pns_ctx tmp = *ctx;
+  return layout(&tmp, false);
+}
+
+int pns_bind_workspace(pns_ctx* ctx, void* ws, size_t bytes) {
+  if (!ctx) return PNS_EINVAL;
+  if (!ws || ((uintptr_t)ws % kAlign) != 0)
+    return fail(ctx, PNS_EWORKSPACE, "workspace pointer NULL or not 256-byte aligned");
+  const size_t need = pns_workspace_bytes(ctx);
+  if (bytes < need)
+    return fail(ctx, PNS_EWORKSPACE,
+                "workspace too small: need " + std::to_string(need) + " bytes");
+  ctx->ws = (char*)ws;
+  ctx->ws_bytes = bytes;
+  layout(ctx, true);
+  ctx->has_state = ctx->has_smoother = false;
+  return PNS_OK;
+}
+
+int pns_set_state(pns_ctx* ctx, const pns_model* md, const double* u_k) {
+  if (!check_ctx(ctx, false, false)) return ctx_code(ctx, false, false);
+  if (!md || !u_k) return fail(ctx, PNS_EINVAL, "NULL model or state");
+  if (!(md->p > 1.0 && md->p <= 2.0)) return fail(ctx, PNS_EINVAL, "p must lie in (1, 2]");
+  if (!(md->delta > 0.0)) return fail(ctx, PNS_EINVAL, "delta must be > 0");
+  if (!(md->nu > 0.0) || !(md->nu_inf >= 0.0)) return fail(ctx, PNS_EINVAL, "need nu > 0, nu_inf >= 0");
+  if (!(md->gamma1 >= 0.0) || !(md->gamma2 >= 0.0)) return fail(ctx, PNS_EINVAL, "negative penalty");
+  if (!(md->sigma_max >= 0.0)) return fail(ctx, PNS_EINVAL, "sigma_max must be >= 0");
+  if (md->lin < 0 || md->lin > 2) return fail(ctx, PNS_EINVAL, "unknown linearisation kind");
+  if (md->nitsche_q_sign != 1 && md->nitsche_q_sign != -1)
+    return fail(ctx, PNS_EINVAL, "nitsche_q_sign must be +1 or -1");
+  Model m;
+  m.p = md->p;
+  m.delta2 = md->delta * md->delta;
+  m.nu = md->nu;
+  m.nu_inf = md->nu_inf;
+  m.expo = 0.5 * (md->p - 2.0);
+  m.sigma_max = md->sigma_max;
+  m.etaD = md->nu_inf + md->nu * std::pow(md->delta, md->p - 2.0);  // eta(D g_D), g_D = 0
+  m.gamma1 = md->gamma1;
+  m.gamma2 = md->gamma2;
+  m.qsign = (double)md->nitsche_q_sign;
+  m.lin = md->lin;
+  m.convection = md->convection ? 1 : 0;
+  ctx->model = m;
+  const Grid& g0 = ctx->lev[0].g;
+  hipStream_t s = ctx->stream;
+  PNS_HIP(ctx, hipMemcpyAsync(ctx->uk64, u_k, 2 * g0.nv * 8, hipMemcpyDeviceToDevice, s));
+  if (ctx->es == 8)
+    PNS_HIP(ctx, hipMemcpyAsync(ctx->uk, u_k, 2 * g0.nv * 8, hipMemcpyDeviceToDevice, s));
+  else
+    PNS_HIP(ctx, launch_convert<float>(2 * g0.nv, ctx->uk64, (float*)ctx->uk, s));
+  PNS_HIP(ctx, launch_state_combine(g0.nv, ctx->uk64, ctx->uk64 + g0.nv, kXiMid[0], kXiMid[1],
+                                    ctx->urep, s));
+  ctx->has_state = true;
+  ctx->has_smoother = false;
+  return PNS_OK;
+}
+
+int pns_cell_apply(pns_ctx* ctx, const void* x, void* y) {
+  if (!check_ctx(ctx, true, false)) return ctx_code(ctx, true, false);
+  if (!x || !y || x == y) return fail(ctx, PNS_EINVAL, "x, y must be distinct non-NULL");
+  if (ctx->es == 8)
+    PNS_HIP(ctx, apply_level<double>(ctx, 0, (const double*)x, (double*)y));
+  else
+    PNS_HIP(ctx, apply_level<float>(ctx, 0, (const float*)x, (float*)y));
+  return PNS_OK;
+}
+
+int pns_cell_defect(pns_ctx* ctx, const void* b, const void* x, void* y) {
+  if (!check_ctx(ctx, true, false)) return ctx_code(ctx, true, false);
+  if (!b || !x || !y || x == y) return fail(ctx, PNS_EINVAL, "b, x, y non-NULL, x != y");
+  if (ctx->es == 8)
+    PNS_HIP(ctx, defect<double>(ctx, 0, (const double*)b, (const double*)x, (double*)y));
+  else
+    PNS_HIP(ctx, defect<float>(ctx, 0, (const float*)b, (const float*)x, (float*)y));
+  return PNS_OK;
+}
+
+int pns_vanka_setup(pns_ctx* ctx, const uint16_t* node_masks) {
+  if (!check_ctx(ctx, true, false)) return ctx_code(ctx, true, false);
+  ctx->has_smoother = false;
+  return ctx->es == 8 ? vanka_setup_impl<double>(ctx, node_masks)
+                      : vanka_setup_impl<float>(ctx, node_masks);
+}
+
+int pns_vanka_smooth(pns_ctx* ctx, int level, int n_sweeps, double omega, const void* r, void* d) {
+  if (!check_ctx(ctx, true, true)) return ctx_code(ctx, true, true);
+  if (level < 0 || level >= ctx->nlev || n_sweeps < 0 || !r || !d || r == d)
+    return fail(ctx, PNS_EINVAL, "bad level, sweep count or vectors");
+  if (ctx->es == 8)
+    PNS_HIP(ctx, smooth<double>(ctx, level, n_sweeps, omega, (const double*)r, (double*)d, false));
+  else
+    PNS_HIP(ctx, smooth<float>(ctx, level, n_sweeps, omega, (const float*)r, (float*)d, false));
+  return PNS_OK;
+}
+
+int pns_vcycle(pns_ctx* ctx, int nu1, int nu2, double omega, const void* r, void* d) {
+  if (!check_ctx(ctx, true, true)) return ctx_code(ctx, true, true);
+  if (nu1 < 0 || nu2 < 0 || !r || !d || r == d)
+    return fail(ctx, PNS_EINVAL, "bad sweep counts or vectors");
+  if (!ctx->has_coarse)
+    return fail(ctx, PNS_EUNSUPPORTED, "coarsest level too large for the dense coarse solve");
+  if (ctx->es == 8)
+    PNS_HIP(ctx, vcycle_level<double>(ctx, 0, nu1, nu2, omega, (const double*)r, (double*)d));
+  else
+    PNS_HIP(ctx, vcycle_level<float>(ctx, 0, nu1, nu2, omega, (const float*)r, (float*)d));
+  return PNS_OK;
+}
+
+int pns_level_apply(pns_ctx* ctx, int level, const void* x, void* y) {
+  if (level == 0) return pns_cell_apply(ctx, x, y);
+  if (!check_ctx(ctx, true, true)) return ctx_code(ctx, true, true);
+  if (level < 0 || level >= ctx->nlev || !x || !y || x == y)
+    return fail(ctx, PNS_EINVAL, "bad level or vectors");
+  if (ctx->es == 8)
+    PNS_HIP(ctx, apply_level<double>(ctx, level, (const double*)x, (double*)y));
+  else
+    PNS_HIP(ctx, apply_level<float>(ctx, level, (const float*)x, (float*)y));
+  return PNS_OK;
+}
+
+int pns_restrict(pns_ctx* ctx, int level, const void* rf, void* rc) {
+  if (!ctx) return PNS_EINVAL;
+  if (level < 0 || level + 1 >= ctx->nlev || !rf || !rc)
+    return fail(ctx, PNS_EINVAL, "bad level or vectors");
+  const Grid& gf = ctx->lev[level].g;
+  const Grid& gc = ctx->lev[level + 1].g;
+  if (ctx->es == 8)
+    PNS_HIP(ctx, launch_restrict<double>(gf, gc, (const double*)rf, (double*)rc, ctx->stream));
+  else
+    PNS_HIP(ctx, launch_restrict<float>(gf, gc, (const float*)rf, (float*)rc, ctx->stream));
+  return PNS_OK;
+}
+
+int pns_prolongate_add(pns_ctx* ctx, int level, const void* dc, void* df) {
+  if (!ctx) return PNS_EINVAL;
+  if (level < 0 || level + 1 >= ctx->nlev || !dc || !df)
+    return fail(ctx, PNS_EINVAL, "bad level or vectors");
+  const Grid& gf = ctx->lev[level].g;
+  const Grid& gc = ctx->lev[level + 1].g;
+  if (ctx->es == 8)
+    PNS_HIP(ctx, launch_prolong_add<double>(gf, gc, (const double*)dc, (double*)df, ctx->stream));
+  else
+    PNS_HIP(ctx, launch_prolong_add<float>(gf, gc, (const float*)dc, (float*)df, ctx->stream));
+  return PNS_OK;
+}
+
+}  // extern "C"

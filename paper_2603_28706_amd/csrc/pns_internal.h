@@ -1,0 +1,114 @@
+// Internal declarations of the MI355X smoothing-step library: context layout,
+// device-side constants of the Q2 / P1disc x dG(1) element, kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/pnsmg.h"
+
+namespace pns {
+
+// ---------------------------------------------------------------- element
+// Reference cell [0,1]^2; Q2 Lagrange basis on the nodes {0, 1/2, 1} per
+// direction; 3-point Gauss-Legendre rule per direction on cells and faces.
+constexpr double kGaussR = 0.38729833462074168852;  // sqrt(3/5) / 2
+constexpr double kGP[3] = {0.5 - kGaussR, 0.5, 0.5 + kGaussR};
+constexpr double kGW[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+
+__host__ __device__ constexpr double q2v(int a, double s) {
+  return a == 0 ? 2.0 * (s - 0.5) * (s - 1.0) : (a == 1 ? -4.0 * s * (s - 1.0) : 2.0 * s * (s - 0.5));
+}
+__host__ __device__ constexpr double q2d(int a, double s) {
+  return a == 0 ? 4.0 * s - 3.0 : (a == 1 ? -8.0 * s + 4.0 : 4.0 * s - 1.0);
+}
+
+// local spatial unknowns of a cell: velocity comp c at node a -> c*9 + a,
+// pressure coefficient j -> 18 + j; space-time local index = mu*21 + spatial.
+constexpr int kNb = 9;
+constexpr int kNs = 21;
+constexpr int kNst = 42;
+
+// dG(1) on right Radau nodes {1/3, 1}: reference K_t (row = test), weights.
+constexpr double kKt[2][2] = {{9.0 / 8.0, 3.0 / 8.0}, {-9.0 / 8.0, 5.0 / 8.0}};
+constexpr double kWt[2] = {0.75, 0.25};
+// Lagrange basis of the Radau nodes at the slab midpoint t = 1/2.
+constexpr double kXiMid[2] = {0.75, 0.25};
+
+// ---------------------------------------------------------------- model
+struct Model {
+  double p, delta2, nu, nu_inf, expo;  // expo = (p-2)/2
+  double sigma_max, etaD, gamma1, gamma2, qsign;
+  int lin, convection;
+};
+
+struct Grid {
+  int nx, ny;
+  double hx, hy;
+  int64_t nn, nc, nv, ns, nst;  // nodes, cells, velocity, spatial, space-time
+};
+
+inline Grid make_grid(int nx, int ny, double lx, double ly) {
+  Grid g;
+  g.nx = nx;
+  g.ny = ny;
+  g.hx = lx / nx;
+  g.hy = ly / ny;
+  g.nn = (int64_t)(2 * nx + 1) * (2 * ny + 1);
+  g.nc = (int64_t)nx * ny;
+  g.nv = 2 * g.nn;
+  g.ns = g.nv + 3 * g.nc;
+  g.nst = 2 * g.ns;
+  return g;
+}
+
+// ---------------------------------------------------------------- launchers
+// apply.hip: matrix-free level-0 operator; mode 0: y = J x, mode 1: y = b - J x
+template <typename T>
+hipError_t launch_cell_apply(const Grid& g, const Model& m, double tau, const T* uk, const T* x,
+                             const T* b, T* y, int mode, hipStream_t s);
+
+// setup.hip
+hipError_t launch_element_matrices(const Grid& g, const Model& m, const double* u, double* Es,
+                                   hipStream_t s);
+hipError_t launch_state_combine(int64_t n, const double* u0, const double* u1, double a0,
+                                double a1, double* out, hipStream_t s);
+template <typename T>
+hipError_t launch_convert(int64_t n, const double* in, T* out, hipStream_t s);
+template <typename T>
+hipError_t launch_fine_patches(const Grid& g, double tau, const double* Es_a, const double* Es_b,
+                               const uint16_t* masks, T* inv, int* status, hipStream_t s);
+template <typename T>
+hipError_t launch_level_patches(const Grid& g, const double* E, T* inv, int* status,
+                                hipStream_t s);
+hipError_t launch_galerkin_from_fine(const Grid& gc, double tau, const double* Es0,
+                                     const double* Es1, double* Ec, hipStream_t s);
+hipError_t launch_galerkin(const Grid& gc, const double* Ef, double* Ec, hipStream_t s);
+hipError_t launch_coarse_assemble(const Grid& g, const double* E, double* Adense,
+                                  hipStream_t s);
+hipError_t coarse_invert(int64_t n, double* A, double* work, int* piv, int* status,
+                         hipStream_t s);
+
+// smooth.hip
+template <typename T>
+hipError_t launch_ebe_apply(const Grid& g, const T* E, const T* x, const T* b, T* y, int mode,
+                            hipStream_t s);
+template <typename T>
+hipError_t launch_patch_sweep(const Grid& g, const T* inv, const T* res, T* d, double omega,
+                              hipStream_t s);
+template <typename T>
+hipError_t launch_restrict(const Grid& gf, const Grid& gc, const T* rf, T* rc, hipStream_t s);
+template <typename T>
+hipError_t launch_prolong_add(const Grid& gf, const Grid& gc, const T* dc, T* df,
+                              hipStream_t s);
+template <typename T>
+hipError_t launch_dense_gemv(int64_t n, const double* Ainv, const T* r, T* d,
+                             const int64_t* pin, int npin, hipStream_t s);
+template <typename T>
+hipError_t launch_fill(int64_t n, T v, T* y, hipStream_t s);
+
+}  // namespace pns

@@ -1,0 +1,642 @@
+// Smoother setup on the GPU (Sec. 6.3):
+// * spatial cell matrices of J_mu at a given velocity state (FP64), used for the
+//   surrogate patches (state frozen at the slab midpoint, eq. surrogate-diag)
+//   and for the exact level-0 element matrices entering the Galerkin product;
+// * patch matrices R_K A R_K^T of cell patches, including the contributions of
+//   the 8 neighbouring cells on shared nodes, inverted by Gauss-Jordan with
+//   partial pivoting in FP64 (one wave per patch, LDS resident);
+// * coarse element matrices E_C = sum_children P_f^T E_f P_f (Galerkin,
+//   A_{l+1} = P^T A_l P restricted cell by cell);
+// * the dense coarsest operator, pinned at the constant pressure coefficient
+//   of cell 0 per Radau node, and its in-place Gauss-Jordan inverse.
+#include "pns_internal.h"
+
+namespace pns {
+namespace {
+
+__device__ __forceinline__ int64_t st_global_index(const Grid& g, int cx, int cy, int l) {
+  // space-time local index l = mu*21 + i  ->  canonical global index
+  const int mu = l / kNs, i = l % kNs;
+  const int NX = 2 * g.nx + 1;
+  if (i < 18) {
+    const int comp = i / 9, a = i % 9;
+    return (int64_t)mu * g.ns + (int64_t)comp * g.nn + (int64_t)(2 * cy + a / 3) * NX +
+           (2 * cx + a % 3);
+  }
+  return (int64_t)mu * g.ns + g.nv + 3 * ((int64_t)cy * g.nx + cx) + (i - 18);
+}
+
+// scalar Q2 mass matrix of a cell, by the 3x3 Gauss rule
+__device__ __forceinline__ double cell_mass(const Grid& g, int a, int b) {
+  double s = 0.0;
+  for (int qy = 0; qy < 3; ++qy)
+    for (int qx = 0; qx < 3; ++qx)
+      s += kGW[qx] * kGW[qy] * q2v(a % 3, kGP[qx]) * q2v(a / 3, kGP[qy]) * q2v(b % 3, kGP[qx]) *
+           q2v(b / 3, kGP[qy]);
+  return s * g.hx * g.hy;
+}
+
+// ----------------------------------------------------------- cell matrices
+
+struct Pt {
+  double xi, et, W, n0, n1, hF;  // reference point, weight, normal (0 inside)
+  double u0, u1, a00, a01, a11, eta, kap;
+};
+
+struct Fld {
+  double v0, v1, g00, g01, g10, g11, q;
+};
+
+__device__ __forceinline__ Fld unit_fld(const Grid& g, int i, double xi, double et) {
+  Fld f{0, 0, 0, 0, 0, 0, 0};
+  if (i < 18) {
+    const int comp = i / 9, a = i % 9, ax = a % 3, ay = a / 3;
+    const double ph = q2v(ax, xi) * q2v(ay, et);
+    const double px = q2d(ax, xi) / g.hx * q2v(ay, et);
+    const double py = q2v(ax, xi) * q2d(ay, et) / g.hy;
+    if (comp == 0) {
+      f.v0 = ph; f.g00 = px; f.g01 = py;
+    } else {
+      f.v1 = ph; f.g10 = px; f.g11 = py;
+    }
+  } else {
+    const int j = i - 18;
+    f.q = j == 0 ? 1.0 : (j == 1 ? xi - 0.5 : et - 0.5);
+  }
+  return f;
+}
+
+__device__ double pair_integrand(const Model& m, const Pt& P, const Fld& x, const Fld& w) {
+  // tangent applied to the trial symmetric gradient
+  const double b00 = x.g00, b01 = 0.5 * (x.g01 + x.g10), b11 = x.g11;
+  const double ab = P.a00 * b00 + 2.0 * P.a01 * b01 + P.a11 * b11;
+  const double T00 = P.eta * b00 + P.kap * ab * P.a00;
+  const double T01 = P.eta * b01 + P.kap * ab * P.a01;
+  const double T11 = P.eta * b11 + P.kap * ab * P.a11;
+  const double d00 = w.g00, d01 = 0.5 * (w.g01 + w.g10), d11 = w.g11;
+  const bool newton = m.lin != PNS_PICARD;
+  double s = 0.0;
+  if (P.n0 == 0.0 && P.n1 == 0.0) {
+    s = T00 * d00 + 2.0 * T01 * d01 + T11 * d11;
+    if (m.convection) {
+      const double X[2] = {x.v0, x.v1}, U[2] = {P.u0, P.u1};
+      const double G[2][2] = {{w.g00, w.g01}, {w.g10, w.g11}};
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+          double c = X[i] * U[j];
+          if (newton) c += U[i] * X[j];
+          s -= c * G[i][j];
+        }
+    }
+    s -= (w.g00 + w.g11) * x.q;
+    s -= (x.g00 + x.g11) * w.q;
+  } else {
+    const double n0 = P.n0, n1 = P.n1;
+    const double un = P.u0 * n0 + P.u1 * n1, xn = x.v0 * n0 + x.v1 * n1, wn = w.v0 * n0 + w.v1 * n1;
+    const double xw = x.v0 * w.v0 + x.v1 * w.v1;
+    if (m.convection) {
+      s += un * xw;
+      if (newton) s += xn * (P.u0 * w.v0 + P.u1 * w.v1);
+      s -= 0.5 * (fabs(un) - un) * xw;
+    }
+    s -= (T00 * n0 + T01 * n1) * w.v0 + (T01 * n0 + T11 * n1) * w.v1;
+    s -= m.etaD * ((d00 * n0 + d01 * n1) * x.v0 + (d01 * n0 + d11 * n1) * x.v1);
+    s += x.q * wn;
+    s += m.qsign * xn * w.q;
+    s += m.gamma1 * m.etaD / P.hF * xw + m.gamma2 / P.hF * xn * wn;
+  }
+  return P.W * s;
+}
+
+__global__ __launch_bounds__(256) void element_matrix_kernel(Grid g, Model m,
+                                                             const double* __restrict__ u,
+                                                             double* __restrict__ Es) {
+  __shared__ double ul[18];
+  __shared__ Pt pts[21];
+  const int64_t cell = blockIdx.x;
+  const int cx = (int)(cell % g.nx), cy = (int)(cell / g.nx);
+  const int t = threadIdx.x;
+  const int NX = 2 * g.nx + 1;
+  if (t < 18) {
+    const int comp = t / 9, a = t % 9;
+    ul[t] = u[(int64_t)comp * g.nn + (int64_t)(2 * cy + a / 3) * NX + 2 * cx + a % 3];
+  }
+  // point list: 9 volume points, then 3 per boundary face
+  int nfaces = 0;
+  int faces[4];
+  if (cx == 0) faces[nfaces++] = 0;
+  if (cx == g.nx - 1) faces[nfaces++] = 1;
+  if (cy == 0) faces[nfaces++] = 2;
+  if (cy == g.ny - 1) faces[nfaces++] = 3;
+  const int npts = 9 + 3 * nfaces;
+  __syncthreads();
+  if (t < npts) {
+    Pt P;
+    if (t < 9) {
+      const int qx = t % 3, qy = t / 3;
+      P.xi = kGP[qx]; P.et = kGP[qy];
+      P.W = kGW[qx] * kGW[qy] * g.hx * g.hy;
+      P.n0 = P.n1 = 0.0; P.hF = 1.0;
+    } else {
+      const int f = faces[(t - 9) / 3], q = (t - 9) % 3;
+      const bool xf = f < 2;
+      P.xi = xf ? (f == 0 ? 0.0 : 1.0) : kGP[q];
+      P.et = xf ? kGP[q] : (f == 2 ? 0.0 : 1.0);
+      P.W = kGW[q] * (xf ? g.hy : g.hx);
+      P.n0 = xf ? (f == 0 ? -1.0 : 1.0) : 0.0;
+      P.n1 = xf ? 0.0 : (f == 2 ? -1.0 : 1.0);
+      P.hF = xf ? g.hx : g.hy;
+    }
+    double u0 = 0, u1 = 0, g00 = 0, g01 = 0, g10 = 0, g11 = 0;
+    for (int a = 0; a < 9; ++a) {
+      const int ax = a % 3, ay = a / 3;
+      const double ph = q2v(ax, P.xi) * q2v(ay, P.et);
+      const double px = q2d(ax, P.xi) / g.hx * q2v(ay, P.et);
+      const double py = q2v(ax, P.xi) * q2d(ay, P.et) / g.hy;
+      u0 += ul[a] * ph; u1 += ul[9 + a] * ph;
+      g00 += ul[a] * px; g01 += ul[a] * py;
+      g10 += ul[9 + a] * px; g11 += ul[9 + a] * py;
+    }
+    P.u0 = u0; P.u1 = u1;
+    P.a00 = g00; P.a01 = 0.5 * (g01 + g10); P.a11 = g11;
+    const double a2 = P.a00 * P.a00 + 2.0 * P.a01 * P.a01 + P.a11 * P.a11;
+    const double D2 = m.delta2 + a2;
+    const double mu = m.nu * pow(D2, m.expo);
+    P.eta = m.nu_inf + mu;
+    double k = 0.0;
+    if (m.lin != PNS_PICARD) {
+      k = (m.p - 2.0) * mu / D2;
+      if (m.lin == PNS_MODIFIED_NEWTON) {
+        const double sig = mu * sqrt(a2);
+        k *= sig > 0.0 ? fmin(1.0, m.sigma_max / sig) : 0.0;
+      }
+    }
+    P.kap = k;
+    pts[t] = P;
+  }
+  __syncthreads();
+  for (int e = t; e < kNs * kNs; e += blockDim.x) {
+    const int i = e / kNs, j = e % kNs;  // row = test i, column = trial j
+    double s = 0.0;
+    for (int q = 0; q < npts; ++q) {
+      const Pt P = pts[q];
+      const Fld w = unit_fld(g, i, P.xi, P.et);
+      const Fld x = unit_fld(g, j, P.xi, P.et);
+      s += pair_integrand(m, P, x, w);
+    }
+    Es[cell * (kNs * kNs) + e] = s;
+  }
+}
+
+__global__ void combine_kernel(int64_t n, const double* a, const double* b, double ca, double cb,
+                               double* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = ca * a[i] + cb * b[i];
+}
+
+template <typename T>
+__global__ void convert_kernel(int64_t n, const double* in, T* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (T)in[i];
+}
+
+// --------------------------------------------------------------- patches
+
+// space-time element entry of the level-0 operator built from spatial cell
+// matrices: K_t[mu][nu] M (same velocity component) + delta_mu,nu tau w_mu Es_mu
+struct FineEntry {
+  Grid g;
+  double tau;
+  const double* Es_a;  // spatial matrices used at Radau node 0
+  const double* Es_b;  // ... at Radau node 1
+  __device__ double operator()(int64_t cell, int r, int c) const {
+    const int mu = r / kNs, i = r % kNs, nu = c / kNs, j = c % kNs;
+    double v = 0.0;
+    if (i < 18 && j < 18 && i / 9 == j / 9) v = kKt[mu][nu] * cell_mass(g, i % 9, j % 9);
+    if (mu == nu) {
+      const double* E = (mu == 0 ? Es_a : Es_b) + cell * (kNs * kNs);
+      v += tau * kWt[mu] * E[i * kNs + j];
+    }
+    return v;
+  }
+};
+
+struct StoredEntry {
+  const double* E;  // 42 x 42 per cell
+  __device__ double operator()(int64_t cell, int r, int c) const {
+    return E[cell * (kNst * kNst) + r * kNst + c];
+  }
+};
+
+// local index of patch-cell unknown l seen from the neighbour at offset (ox,oy);
+// -1 if the neighbour does not carry it
+__device__ __forceinline__ int map_to_neighbour(int l, int ox, int oy) {
+  const int mu = l / kNs, i = l % kNs;
+  if (i >= 18) return (ox == 0 && oy == 0) ? l : -1;
+  const int comp = i / 9, a = i % 9;
+  const int ax = a % 3 - 2 * ox, ay = a / 3 - 2 * oy;
+  if (ax < 0 || ax > 2 || ay < 0 || ay > 2) return -1;
+  return mu * kNs + comp * 9 + ax + 3 * ay;
+}
+
+__device__ __forceinline__ bool dropped(uint16_t mask, int l) {
+  const int i = l % kNs;
+  return i < 18 && !((mask >> (i % 9)) & 1u);
+}
+
+// One wave (64 lanes) assembles and inverts one 42x42 patch matrix.
+template <typename T, typename Entry>
+__global__ __launch_bounds__(64) void patch_kernel(Grid g, Entry entry,
+                                                   const uint16_t* __restrict__ masks,
+                                                   T* __restrict__ inv, int* status) {
+  __shared__ double A[kNst][2 * kNst + 1];
+  __shared__ double fac[kNst];
+  __shared__ double red_v[64];
+  __shared__ int red_i[64];
+  const int64_t K = blockIdx.x;
+  const int cx = (int)(K % g.nx), cy = (int)(K / g.nx);
+  const int t = threadIdx.x;
+  const uint16_t mask = masks ? masks[K] : (uint16_t)0x1ff;
+  for (int e = t; e < kNst * kNst; e += 64) {
+    const int r = e / kNst, c = e % kNst;
+    double v = 0.0;
+    if (dropped(mask, r) || dropped(mask, c)) {
+      v = (r == c) ? 1.0 : 0.0;
+    } else {
+      for (int oy = -1; oy <= 1; ++oy)
+        for (int ox = -1; ox <= 1; ++ox) {
+          const int nx_ = cx + ox, ny_ = cy + oy;
+          if (nx_ < 0 || ny_ < 0 || nx_ >= g.nx || ny_ >= g.ny) continue;
+          const int rr = map_to_neighbour(r, ox, oy), cc = map_to_neighbour(c, ox, oy);
+          if (rr < 0 || cc < 0) continue;
+          v += entry((int64_t)ny_ * g.nx + nx_, rr, cc);
+        }
+    }
+    A[r][c] = v;
+    A[r][kNst + c] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  bool singular = false;
+  for (int k = 0; k < kNst; ++k) {
+    // pivot: largest |A[r][k]|, r >= k
+    double bv = -1.0;
+    int bi = k;
+    if (t >= k && t < kNst) {
+      bv = fabs(A[t][k]);
+      bi = t;
+    }
+    red_v[t] = bv;
+    red_i[t] = bi;
+    __syncthreads();
+    for (int off = 32; off > 0; off >>= 1) {
+      if (t < off) {
+        const double ov = red_v[t + off];
+        const int oi = red_i[t + off];
+        if (ov > red_v[t] || (ov == red_v[t] && oi < red_i[t])) {
+          red_v[t] = ov;
+          red_i[t] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const int p = red_i[0];
+    const double pmax = red_v[0];
+    __syncthreads();
+    if (!(pmax > 0.0)) singular = true;
+    for (int c = t; c < 2 * kNst; c += 64) {
+      const double tmp = A[k][c];
+      A[k][c] = A[p][c];
+      A[p][c] = tmp;
+    }
+    __syncthreads();
+    const double piv = singular ? 1.0 : A[k][k];
+    for (int c = t; c < 2 * kNst; c += 64) A[k][c] /= piv;
+    if (t < kNst) fac[t] = (t == k) ? 0.0 : A[t][k];
+    __syncthreads();
+    for (int e = t; e < kNst * 2 * kNst; e += 64) {
+      const int r = e / (2 * kNst), c = e % (2 * kNst);
+      if (r != k) A[r][c] -= fac[r] * A[k][c];
+    }
+    __syncthreads();
+  }
+  if (singular && t == 0) atomicOr(status, 1);
+  // store the inverse column-major, dropped rows/columns zeroed
+  T* out = inv + K * (kNst * kNst);
+  for (int e = t; e < kNst * kNst; e += 64) {
+    const int c = e / kNst, r = e % kNst;
+    const bool z = dropped(mask, r) || dropped(mask, c);
+    out[e] = z ? (T)0 : (T)A[r][kNst + c];
+  }
+}
+
+// ---------------------------------------------------------------- Galerkin
+
+// local prolongation of child (ox,oy) of a coarse cell: fine local unknown
+// (row) from coarse local unknowns (column), identity in time
+__device__ double prolong_entry(int rf, int cc, int ox, int oy) {
+  const int muf = rf / kNs, i = rf % kNs, muc = cc / kNs, j = cc % kNs;
+  if (muf != muc) return 0.0;
+  if (i < 18 && j < 18) {
+    if (i / 9 != j / 9) return 0.0;
+    const int af = i % 9, ac = j % 9;
+    const double sx = 0.5 * ox + 0.25 * (af % 3), sy = 0.5 * oy + 0.25 * (af / 3);
+    return q2v(ac % 3, sx) * q2v(ac / 3, sy);
+  }
+  if (i >= 18 && j >= 18) {
+    const int pf = i - 18, pc = j - 18;
+    if (pf == 0) return pc == 0 ? 1.0 : (pc == 1 ? 0.5 * (ox - 0.5) : 0.5 * (oy - 0.5));
+    return pf == pc ? 0.5 : 0.0;
+  }
+  return 0.0;
+}
+
+template <typename Entry>
+__global__ __launch_bounds__(256) void galerkin_kernel(Grid gc, Grid gf, Entry fine_entry,
+                                                       double* __restrict__ Ec) {
+  __shared__ double Pf[kNst][kNst + 1];
+  __shared__ double Ef[kNst][kNst + 1];
+  __shared__ double Tm[kNst][kNst + 1];
+  const int64_t C = blockIdx.x;
+  const int cx = (int)(C % gc.nx), cy = (int)(C / gc.nx);
+  const int t = threadIdx.x;
+  constexpr int kPer = (kNst * kNst + 255) / 256;
+  double accv[kPer];
+  for (int q = 0; q < kPer; ++q) accv[q] = 0.0;
+  for (int ch = 0; ch < 4; ++ch) {
+    const int ox = ch & 1, oy = ch >> 1;
+    const int64_t f = (int64_t)(2 * cy + oy) * gf.nx + (2 * cx + ox);
+    for (int e = t; e < kNst * kNst; e += 256) {
+      const int r = e / kNst, c = e % kNst;
+      Pf[r][c] = prolong_entry(r, c, ox, oy);
+      Ef[r][c] = fine_entry(f, r, c);
+    }
+    __syncthreads();
+    for (int e = t; e < kNst * kNst; e += 256) {  // Tm = Ef Pf
+      const int r = e / kNst, c = e % kNst;
+      double s = 0.0;
+      for (int k = 0; k < kNst; ++k) s += Ef[r][k] * Pf[k][c];
+      Tm[r][c] = s;
+    }
+    __syncthreads();
+    for (int q = 0; q < kPer; ++q) {  // Ec += Pf^T Tm
+      const int e = t + 256 * q;
+      if (e < kNst * kNst) {
+        const int r = e / kNst, c = e % kNst;
+        double s = 0.0;
+        for (int k = 0; k < kNst; ++k) s += Pf[k][r] * Tm[k][c];
+        accv[q] += s;
+      }
+    }
+    __syncthreads();
+  }
+  for (int q = 0; q < kPer; ++q) {
+    const int e = t + 256 * q;
+    if (e < kNst * kNst) Ec[C * (kNst * kNst) + e] = accv[q];
+  }
+}
+
+// ------------------------------------------------------------ coarsest level
+
+// dense row r of the assembled level operator (thread per row)
+__global__ void coarse_assemble_kernel(Grid g, const double* __restrict__ E,
+                                       double* __restrict__ A) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= g.nst) return;
+  const int64_t n = g.nst;
+  const int mu = (int)(r / g.ns);
+  const int64_t s = r % g.ns;
+  const int NX = 2 * g.nx + 1;
+  int cxs[2], cys[2], ncx = 0, ncy = 0, lrow_fixed = -1;
+  int gx = 0, gy = 0, comp = 0;
+  if (s < g.nv) {
+    comp = (int)(s / g.nn);
+    const int64_t node = s % g.nn;
+    gx = (int)(node % NX);
+    gy = (int)(node / NX);
+    if (gx % 2 == 0) {
+      if (gx / 2 - 1 >= 0) cxs[ncx++] = gx / 2 - 1;
+      if (gx / 2 < g.nx) cxs[ncx++] = gx / 2;
+    } else {
+      cxs[ncx++] = (gx - 1) / 2;
+    }
+    if (gy % 2 == 0) {
+      if (gy / 2 - 1 >= 0) cys[ncy++] = gy / 2 - 1;
+      if (gy / 2 < g.ny) cys[ncy++] = gy / 2;
+    } else {
+      cys[ncy++] = (gy - 1) / 2;
+    }
+  } else {
+    const int64_t cell = (s - g.nv) / 3;
+    cxs[ncx++] = (int)(cell % g.nx);
+    cys[ncy++] = (int)(cell / g.nx);
+    lrow_fixed = mu * kNs + 18 + (int)((s - g.nv) % 3);
+  }
+  for (int iy = 0; iy < ncy; ++iy)
+    for (int ix = 0; ix < ncx; ++ix) {
+      const int cx = cxs[ix], cy = cys[iy];
+      const int lr = lrow_fixed >= 0
+                         ? lrow_fixed
+                         : mu * kNs + comp * 9 + (gx - 2 * cx) + 3 * (gy - 2 * cy);
+      const double* Er = E + ((int64_t)cy * g.nx + cx) * (kNst * kNst) + (int64_t)lr * kNst;
+      for (int lc = 0; lc < kNst; ++lc) A[r * n + st_global_index(g, cx, cy, lc)] += Er[lc];
+    }
+}
+
+__global__ void pin_kernel(int64_t n, double* A, const int64_t* pin, int npin) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = 0; k < npin; ++k) {
+    const int64_t p = pin[k];
+    A[p * n + i] = (i == p) ? 1.0 : 0.0;
+    A[i * n + p] = (i == p) ? 1.0 : 0.0;
+  }
+}
+
+// Gauss-Jordan, in place, partial row pivoting, one column per step.
+__global__ __launch_bounds__(1024) void gj_pivot_kernel(int64_t n, int64_t k, const double* A,
+                                                        int* piv, double* pval, int* status) {
+  __shared__ double bv[1024];
+  __shared__ int64_t bi[1024];
+  const int t = threadIdx.x;
+  double v = -1.0;
+  int64_t idx = k;
+  for (int64_t r = k + t; r < n; r += 1024) {
+    const double a = fabs(A[r * n + k]);
+    if (a > v) {
+      v = a;
+      idx = r;
+    }
+  }
+  bv[t] = v;
+  bi[t] = idx;
+  __syncthreads();
+  for (int off = 512; off > 0; off >>= 1) {
+    if (t < off && (bv[t + off] > bv[t] || (bv[t + off] == bv[t] && bi[t + off] < bi[t]))) {
+      bv[t] = bv[t + off];
+      bi[t] = bi[t + off];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    piv[k] = (int)bi[0];
+    const double p = A[bi[0] * n + k];
+    if (!(bv[0] > 0.0)) {
+      atomicOr(status, 2);
+      pval[0] = 1.0;
+    } else {
+      pval[0] = p;
+    }
+  }
+}
+
+__global__ void gj_swap_scale_kernel(int64_t n, int64_t k, double* A, const int* piv,
+                                     const double* pval) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int64_t p = piv[k];
+  const double pv = pval[0];
+  const double a = A[p * n + j];
+  if (p != k) A[p * n + j] = A[k * n + j];
+  // row k after the swap, scaled; the pivot column becomes 1/pv (in-place GJ)
+  A[k * n + j] = (j == k) ? 1.0 / pv : a / pv;
+}
+
+__global__ void gj_column_kernel(int64_t n, int64_t k, const double* A, double* colk) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  colk[r] = (r == k) ? 0.0 : A[r * n + k];
+}
+
+__global__ void gj_eliminate_kernel(int64_t n, int64_t k, double* A, const double* colk) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = blockIdx.y;
+  if (j >= n || r == k) return;
+  const double f = colk[r];
+  const double akj = A[k * n + j];
+  if (j == k)
+    A[r * n + j] = -f * akj;
+  else
+    A[r * n + j] -= f * akj;
+}
+
+__global__ void gj_colswap_kernel(int64_t n, int64_t k, double* A, const int* piv) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const int64_t p = piv[k];
+  if (p == k) return;
+  const double a = A[r * n + k];
+  A[r * n + k] = A[r * n + p];
+  A[r * n + p] = a;
+}
+
+__global__ __launch_bounds__(256) void form_fine_st_kernel(Grid g, FineEntry e, double* __restrict__ E) {
+  const int64_t cell = blockIdx.x;
+  for (int idx = threadIdx.x; idx < kNst * kNst; idx += blockDim.x)
+    E[cell * (kNst * kNst) + idx] = e(cell, idx / kNst, idx % kNst);
+}
+
+}  // namespace
+
+hipError_t launch_form_fine_st(const Grid& g, double tau, const double* Es0, const double* Es1,
+                               double* E, hipStream_t s) {
+  FineEntry e{g, tau, Es0, Es1};
+  hipLaunchKernelGGL(form_fine_st_kernel, dim3((unsigned)g.nc), dim3(256), 0, s, g, e, E);
+  return hipGetLastError();
+}
+
+hipError_t launch_element_matrices(const Grid& g, const Model& m, const double* u, double* Es,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(element_matrix_kernel, dim3((unsigned)g.nc), dim3(256), 0, s, g, m, u, Es);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_combine(int64_t n, const double* u0, const double* u1, double a0,
+                                double a1, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(combine_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, u0, u1,
+                     a0, a1, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_convert(int64_t n, const double* in, T* out, hipStream_t s) {
+  hipLaunchKernelGGL(convert_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, in,
+                     out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fine_patches(const Grid& g, double tau, const double* Es_a, const double* Es_b,
+                               const uint16_t* masks, T* inv, int* status, hipStream_t s) {
+  FineEntry e{g, tau, Es_a, Es_b};
+  hipLaunchKernelGGL((patch_kernel<T, FineEntry>), dim3((unsigned)g.nc), dim3(64), 0, s, g, e,
+                     masks, inv, status);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_level_patches(const Grid& g, const double* E, T* inv, int* status,
+                                hipStream_t s) {
+  StoredEntry e{E};
+  hipLaunchKernelGGL((patch_kernel<T, StoredEntry>), dim3((unsigned)g.nc), dim3(64), 0, s, g, e,
+                     (const uint16_t*)nullptr, inv, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_galerkin_from_fine(const Grid& gc, double tau, const double* Es0,
+                                     const double* Es1, double* Ec, hipStream_t s) {
+  Grid gf = make_grid(2 * gc.nx, 2 * gc.ny, 2 * gc.nx * (gc.hx / 2), 2 * gc.ny * (gc.hy / 2));
+  FineEntry e{gf, tau, Es0, Es1};
+  hipLaunchKernelGGL((galerkin_kernel<FineEntry>), dim3((unsigned)gc.nc), dim3(256), 0, s, gc, gf,
+                     e, Ec);
+  return hipGetLastError();
+}
+
+hipError_t launch_galerkin(const Grid& gc, const double* Ef, double* Ec, hipStream_t s) {
+  Grid gf = make_grid(2 * gc.nx, 2 * gc.ny, 2 * gc.nx * (gc.hx / 2), 2 * gc.ny * (gc.hy / 2));
+  StoredEntry e{Ef};
+  hipLaunchKernelGGL((galerkin_kernel<StoredEntry>), dim3((unsigned)gc.nc), dim3(256), 0, s, gc,
+                     gf, e, Ec);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_assemble(const Grid& g, const double* E, double* A, hipStream_t s) {
+  hipLaunchKernelGGL(coarse_assemble_kernel, dim3((unsigned)((g.nst + 127) / 128)), dim3(128), 0,
+                     s, g, E, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_pin(int64_t n, double* A, const int64_t* pin, int npin, hipStream_t s) {
+  hipLaunchKernelGGL(pin_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, A, pin,
+                     npin);
+  return hipGetLastError();
+}
+
+// work: n + 1 doubles (pivot column copy, pivot value); piv: n ints
+hipError_t coarse_invert(int64_t n, double* A, double* work, int* piv, int* status,
+                         hipStream_t s) {
+  double* colk = work;
+  double* pval = work + n;
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  for (int64_t k = 0; k < n; ++k) {
+    hipLaunchKernelGGL(gj_pivot_kernel, dim3(1), dim3(1024), 0, s, n, k, A, piv, pval, status);
+    hipLaunchKernelGGL(gj_swap_scale_kernel, dim3(nb), dim3(256), 0, s, n, k, A, piv, pval);
+    hipLaunchKernelGGL(gj_column_kernel, dim3(nb), dim3(256), 0, s, n, k, A, colk);
+    hipLaunchKernelGGL(gj_eliminate_kernel, dim3(nb, (unsigned)n), dim3(256), 0, s, n, k, A, colk);
+  }
+  for (int64_t k = n - 1; k >= 0; --k)
+    hipLaunchKernelGGL(gj_colswap_kernel, dim3(nb), dim3(256), 0, s, n, k, A, piv);
+  return hipGetLastError();
+}
+
+template hipError_t launch_convert<double>(int64_t, const double*, double*, hipStream_t);
+template hipError_t launch_convert<float>(int64_t, const double*, float*, hipStream_t);
+template hipError_t launch_fine_patches<double>(const Grid&, double, const double*, const double*,
+                                                const uint16_t*, double*, int*, hipStream_t);
+template hipError_t launch_fine_patches<float>(const Grid&, double, const double*, const double*,
+                                               const uint16_t*, float*, int*, hipStream_t);
+template hipError_t launch_level_patches<double>(const Grid&, const double*, double*, int*,
+                                                 hipStream_t);
+template hipError_t launch_level_patches<float>(const Grid&, const double*, float*, int*,
+                                                hipStream_t);
+
+}  // namespace pns

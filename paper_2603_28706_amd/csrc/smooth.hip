@@ -1,0 +1,297 @@
+// Per-iteration smoother and transfer kernels (Sec. 6.3):
+// * coarse-level operator action with Galerkin element matrices (one thread
+//   per output row, gathering the rows of the <= 4 cells that carry it:
+//   every (cell, local row) product is formed exactly once, no atomics);
+// * additive Vanka update d += omega sum_K R_K^T A_K^{-1} R_K res,
+//   eq. (stmg-vanka-update): one wave per patch, the stored inverse streamed
+//   column by column, four colour launches so that patches updating d at the
+//   same time share no unknown;
+// * restriction P^T and prolongation P of the nested Q2 / P1disc spaces;
+// * dense coarsest solve with the stored inverse.
+#include "pns_internal.h"
+
+namespace pns {
+namespace {
+
+__device__ __forceinline__ int64_t gidx(const Grid& g, int cx, int cy, int l) {
+  const int mu = l / kNs, i = l % kNs;
+  const int NX = 2 * g.nx + 1;
+  if (i < 18) {
+    const int comp = i / 9, a = i % 9;
+    return (int64_t)mu * g.ns + (int64_t)comp * g.nn + (int64_t)(2 * cy + a / 3) * NX +
+           (2 * cx + a % 3);
+  }
+  return (int64_t)mu * g.ns + g.nv + 3 * ((int64_t)cy * g.nx + cx) + (i - 18);
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void ebe_apply_kernel(Grid g, const T* __restrict__ E,
+                                                        const T* __restrict__ x,
+                                                        const T* __restrict__ b,
+                                                        T* __restrict__ y) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= g.nst) return;
+  const int mu = (int)(r / g.ns);
+  const int64_t s = r % g.ns;
+  const int NX = 2 * g.nx + 1;
+  int cxs[2], cys[2], ncx = 0, ncy = 0, lfix = -1, gx = 0, gy = 0, comp = 0;
+  if (s < g.nv) {
+    comp = (int)(s / g.nn);
+    const int64_t node = s % g.nn;
+    gx = (int)(node % NX);
+    gy = (int)(node / NX);
+    if ((gx & 1) == 0) {
+      if (gx / 2 - 1 >= 0) cxs[ncx++] = gx / 2 - 1;
+      if (gx / 2 < g.nx) cxs[ncx++] = gx / 2;
+    } else {
+      cxs[ncx++] = gx >> 1;
+    }
+    if ((gy & 1) == 0) {
+      if (gy / 2 - 1 >= 0) cys[ncy++] = gy / 2 - 1;
+      if (gy / 2 < g.ny) cys[ncy++] = gy / 2;
+    } else {
+      cys[ncy++] = gy >> 1;
+    }
+  } else {
+    const int64_t cell = (s - g.nv) / 3;
+    cxs[ncx++] = (int)(cell % g.nx);
+    cys[ncy++] = (int)(cell / g.nx);
+    lfix = mu * kNs + 18 + (int)((s - g.nv) % 3);
+  }
+  T acc = 0;
+  for (int iy = 0; iy < ncy; ++iy)
+    for (int ix = 0; ix < ncx; ++ix) {
+      const int cx = cxs[ix], cy = cys[iy];
+      const int lr = lfix >= 0 ? lfix : mu * kNs + comp * 9 + (gx - 2 * cx) + 3 * (gy - 2 * cy);
+      const T* Er = E + ((int64_t)cy * g.nx + cx) * (kNst * kNst) + (int64_t)lr * kNst;
+#pragma unroll 6
+      for (int lc = 0; lc < kNst; ++lc) acc += Er[lc] * x[gidx(g, cx, cy, lc)];
+    }
+  y[r] = MODE ? b[r] - acc : acc;
+}
+
+// one wave per patch of the colour class (px, py)
+template <typename T>
+__global__ __launch_bounds__(256) void patch_sweep_kernel(Grid g, const T* __restrict__ inv,
+                                                          const T* __restrict__ res,
+                                                          T* __restrict__ d, T omega, int px,
+                                                          int py, int ncx, int ncy) {
+  __shared__ T rhs[4][kNst];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t pid = (int64_t)blockIdx.x * 4 + w;
+  const bool active = pid < (int64_t)ncx * ncy;
+  int cx = 0, cy = 0;
+  int64_t gi = 0;
+  if (active) {
+    cx = px + 2 * (int)(pid % ncx);
+    cy = py + 2 * (int)(pid / ncx);
+    if (lane < kNst) {
+      gi = gidx(g, cx, cy, lane);
+      rhs[w][lane] = res[gi];
+    }
+  }
+  __syncthreads();
+  if (!active || lane >= kNst) return;
+  const T* A = inv + ((int64_t)cy * g.nx + cx) * (kNst * kNst);
+  T acc = 0;
+#pragma unroll 6
+  for (int j = 0; j < kNst; ++j) acc += A[j * kNst + lane] * rhs[w][j];
+  d[gi] += omega * acc;
+}
+
+__device__ __forceinline__ double w1d(int I, int i) {
+  // value of the coarse 1D Q2 nodal basis function I at fine node i
+  if ((i & 1) == 0) return (i >> 1) == I ? 1.0 : 0.0;
+  const int C = i >> 2;
+  const int a = I - 2 * C;
+  if (a < 0 || a > 2) return 0.0;
+  return q2v(a, 0.25 * (i - 4 * C));
+}
+
+template <typename T>
+__global__ void restrict_kernel(Grid gf, Grid gc, const T* __restrict__ rf, T* __restrict__ rc) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= gc.nst) return;
+  const int mu = (int)(r / gc.ns);
+  const int64_t s = r % gc.ns;
+  const T* f = rf + (int64_t)mu * gf.ns;
+  double acc = 0.0;
+  if (s < gc.nv) {
+    const int comp = (int)(s / gc.nn);
+    const int64_t node = s % gc.nn;
+    const int NXc = 2 * gc.nx + 1, NXf = 2 * gf.nx + 1;
+    const int IX = (int)(node % NXc), IY = (int)(node / NXc);
+    for (int iy = 2 * IY - 3; iy <= 2 * IY + 3; ++iy) {
+      if (iy < 0 || iy > 2 * gf.ny) continue;
+      const double wy = w1d(IY, iy);
+      if (wy == 0.0) continue;
+      for (int ix = 2 * IX - 3; ix <= 2 * IX + 3; ++ix) {
+        if (ix < 0 || ix > 2 * gf.nx) continue;
+        const double wx = w1d(IX, ix);
+        if (wx == 0.0) continue;
+        acc += wx * wy * (double)f[(int64_t)comp * gf.nn + (int64_t)iy * NXf + ix];
+      }
+    }
+  } else {
+    const int64_t cell = (s - gc.nv) / 3;
+    const int j = (int)((s - gc.nv) % 3);
+    const int cx = (int)(cell % gc.nx), cy = (int)(cell / gc.nx);
+    for (int oy = 0; oy < 2; ++oy)
+      for (int ox = 0; ox < 2; ++ox) {
+        const int64_t fc = (int64_t)(2 * cy + oy) * gf.nx + (2 * cx + ox);
+        const T* fp = f + gf.nv + 3 * fc;
+        if (j == 0)
+          acc += (double)fp[0];
+        else if (j == 1)
+          acc += 0.5 * (ox - 0.5) * (double)fp[0] + 0.5 * (double)fp[1];
+        else
+          acc += 0.5 * (oy - 0.5) * (double)fp[0] + 0.5 * (double)fp[2];
+      }
+  }
+  rc[r] = (T)acc;
+}
+
+template <typename T>
+__global__ void prolong_add_kernel(Grid gf, Grid gc, const T* __restrict__ dc, T* __restrict__ df) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= gf.nst) return;
+  const int mu = (int)(r / gf.ns);
+  const int64_t s = r % gf.ns;
+  const T* c = dc + (int64_t)mu * gc.ns;
+  double acc = 0.0;
+  if (s < gf.nv) {
+    const int comp = (int)(s / gf.nn);
+    const int64_t node = s % gf.nn;
+    const int NXc = 2 * gc.nx + 1, NXf = 2 * gf.nx + 1;
+    const int ix = (int)(node % NXf), iy = (int)(node / NXf);
+    int Ix[3], Iy[3], nxI = 0, nyI = 0;
+    double wx[3], wy[3];
+    if ((ix & 1) == 0) {
+      Ix[0] = ix >> 1; wx[0] = 1.0; nxI = 1;
+    } else {
+      const int C = ix >> 2;
+      for (int a = 0; a < 3; ++a) { Ix[a] = 2 * C + a; wx[a] = q2v(a, 0.25 * (ix - 4 * C)); }
+      nxI = 3;
+    }
+    if ((iy & 1) == 0) {
+      Iy[0] = iy >> 1; wy[0] = 1.0; nyI = 1;
+    } else {
+      const int C = iy >> 2;
+      for (int a = 0; a < 3; ++a) { Iy[a] = 2 * C + a; wy[a] = q2v(a, 0.25 * (iy - 4 * C)); }
+      nyI = 3;
+    }
+    for (int b = 0; b < nyI; ++b)
+      for (int a = 0; a < nxI; ++a)
+        acc += wx[a] * wy[b] * (double)c[(int64_t)comp * gc.nn + (int64_t)Iy[b] * NXc + Ix[a]];
+  } else {
+    const int64_t fc = (s - gf.nv) / 3;
+    const int j = (int)((s - gf.nv) % 3);
+    const int fx = (int)(fc % gf.nx), fy = (int)(fc / gf.nx);
+    const int ox = fx & 1, oy = fy & 1;
+    const T* cp = c + gc.nv + 3 * ((int64_t)(fy >> 1) * gc.nx + (fx >> 1));
+    if (j == 0)
+      acc = (double)cp[0] + 0.5 * (ox - 0.5) * (double)cp[1] + 0.5 * (oy - 0.5) * (double)cp[2];
+    else
+      acc = 0.5 * (double)cp[j];
+  }
+  df[r] = (T)((double)df[r] + acc);
+}
+
+// d = Ainv r~, r~ = r with the pinned entries zeroed; one wave per row
+template <typename T>
+__global__ __launch_bounds__(256) void dense_gemv_kernel(int64_t n, const double* __restrict__ Ainv,
+                                                         const T* __restrict__ r, T* __restrict__ d,
+                                                         int64_t pin0, int64_t pin1) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  const double* A = Ainv + row * n;
+  double acc = 0.0;
+  for (int64_t j = lane; j < n; j += 64) {
+    const double rv = (j == pin0 || j == pin1) ? 0.0 : (double)r[j];
+    acc += A[j] * rv;
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) d[row] = (T)acc;
+}
+
+template <typename T>
+__global__ void fill_kernel(int64_t n, T v, T* y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = v;
+}
+
+inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_ebe_apply(const Grid& g, const T* E, const T* x, const T* b, T* y, int mode,
+                            hipStream_t s) {
+  if (mode == 0)
+    hipLaunchKernelGGL((ebe_apply_kernel<T, 0>), dim3(nblk(g.nst, 256)), dim3(256), 0, s, g, E, x,
+                       b, y);
+  else
+    hipLaunchKernelGGL((ebe_apply_kernel<T, 1>), dim3(nblk(g.nst, 256)), dim3(256), 0, s, g, E, x,
+                       b, y);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_patch_sweep(const Grid& g, const T* inv, const T* res, T* d, double omega,
+                              hipStream_t s) {
+  for (int c = 0; c < 4; ++c) {
+    const int px = c & 1, py = c >> 1;
+    const int ncx = (g.nx - px + 1) / 2, ncy = (g.ny - py + 1) / 2;
+    const int64_t np = (int64_t)ncx * ncy;
+    if (np == 0) continue;
+    hipLaunchKernelGGL(patch_sweep_kernel<T>, dim3(nblk(np, 4)), dim3(256), 0, s, g, inv, res, d,
+                       (T)omega, px, py, ncx, ncy);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_restrict(const Grid& gf, const Grid& gc, const T* rf, T* rc, hipStream_t s) {
+  hipLaunchKernelGGL(restrict_kernel<T>, dim3(nblk(gc.nst, 256)), dim3(256), 0, s, gf, gc, rf, rc);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_prolong_add(const Grid& gf, const Grid& gc, const T* dc, T* df, hipStream_t s) {
+  hipLaunchKernelGGL(prolong_add_kernel<T>, dim3(nblk(gf.nst, 256)), dim3(256), 0, s, gf, gc, dc,
+                     df);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dense_gemv(int64_t n, const double* Ainv, const T* r, T* d, const int64_t* pin,
+                             int npin, hipStream_t s) {
+  const int64_t p0 = npin > 0 ? pin[0] : -1, p1 = npin > 1 ? pin[1] : -1;
+  hipLaunchKernelGGL(dense_gemv_kernel<T>, dim3(nblk(n, 4)), dim3(256), 0, s, n, Ainv, r, d, p0,
+                     p1);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill(int64_t n, T v, T* y, hipStream_t s) {
+  hipLaunchKernelGGL(fill_kernel<T>, dim3(nblk(n, 256)), dim3(256), 0, s, n, v, y);
+  return hipGetLastError();
+}
+
+#define PNS_INST(T)                                                                              \
+  template hipError_t launch_ebe_apply<T>(const Grid&, const T*, const T*, const T*, T*, int,   \
+                                          hipStream_t);                                          \
+  template hipError_t launch_patch_sweep<T>(const Grid&, const T*, const T*, T*, double,        \
+                                            hipStream_t);                                        \
+  template hipError_t launch_restrict<T>(const Grid&, const Grid&, const T*, T*, hipStream_t);  \
+  template hipError_t launch_prolong_add<T>(const Grid&, const Grid&, const T*, T*,             \
+                                            hipStream_t);                                        \
+  template hipError_t launch_dense_gemv<T>(int64_t, const double*, const T*, T*, const int64_t*, \
+                                           int, hipStream_t);                                    \
+  template hipError_t launch_fill<T>(int64_t, T, T*, hipStream_t);
+PNS_INST(double)
+PNS_INST(float)
+#undef PNS_INST
+
+}  // namespace pns

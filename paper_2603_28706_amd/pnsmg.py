@@ -1,0 +1,203 @@
+"""Thin ctypes binding of libpnsmg.so (include/pnsmg.h).
+
+Argument marshalling only: every step of the smoothing step runs in the HIP
+kernels of the library.  PyTorch provides the device memory (the workspace
+and the vectors) and the stream.  If the library is missing this module
+raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpnsmg.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "pnsmg.h")
+
+PNS_OK, PNS_EINVAL, PNS_EWORKSPACE, PNS_EHIP, PNS_ESTATE, PNS_ESINGULAR, PNS_EUNSUPPORTED = (
+    0, -1, -2, -3, -4, -5, -6)
+PICARD, EXACT_NEWTON, MODIFIED_NEWTON = 0, 1, 2
+FP64, FP32 = 0, 1
+
+
+class PnsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pnsmg error {code}: {msg}")
+        self.code = code
+
+
+class pns_mesh(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n_cells", ctypes.c_int * 3),
+                ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3)]
+
+
+class pns_discretization(ctypes.Structure):
+    _fields_ = [("k_space", ctypes.c_int), ("k_time", ctypes.c_int),
+                ("t0", ctypes.c_double), ("tau", ctypes.c_double)]
+
+
+class pns_model(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_double), ("delta", ctypes.c_double), ("nu", ctypes.c_double),
+                ("nu_inf", ctypes.c_double), ("gamma1", ctypes.c_double),
+                ("gamma2", ctypes.c_double), ("sigma_max", ctypes.c_double),
+                ("convection", ctypes.c_int), ("nitsche_q_sign", ctypes.c_int),
+                ("lin", ctypes.c_int)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+
+
+def header_symbols(path: str = HEADER):
+    """Every function the public header declares."""
+    txt = open(path).read()
+    return sorted(set(re.findall(r"\b(pns_[a-z_0-9]+)\s*\(", txt)))
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP extension {LIB_PATH} is missing: build it with "
+                               "__graft_entry__.build() (hipcc for gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        i, pp = ctypes.c_int, ctypes.POINTER
+        L.pns_ctx_create.argtypes = [pp(pns_mesh), pp(pns_discretization), i, i, _vp,
+                                     pp(_vp)]
+        L.pns_ctx_destroy.argtypes = [_vp]
+        L.pns_ctx_destroy.restype = None
+        L.pns_last_error.argtypes = [_vp]
+        L.pns_last_error.restype = ctypes.c_char_p
+        L.pns_level_sizes.argtypes = [_vp, i, pp(ctypes.c_int64)]
+        L.pns_workspace_bytes.argtypes = [_vp]
+        L.pns_workspace_bytes.restype = ctypes.c_size_t
+        L.pns_bind_workspace.argtypes = [_vp, _vp, ctypes.c_size_t]
+        L.pns_set_state.argtypes = [_vp, pp(pns_model), _vp]
+        L.pns_cell_apply.argtypes = [_vp, _vp, _vp]
+        L.pns_cell_defect.argtypes = [_vp, _vp, _vp, _vp]
+        L.pns_vanka_setup.argtypes = [_vp, _vp]
+        L.pns_vanka_smooth.argtypes = [_vp, i, i, ctypes.c_double, _vp, _vp]
+        L.pns_vcycle.argtypes = [_vp, i, i, ctypes.c_double, _vp, _vp]
+        L.pns_level_apply.argtypes = [_vp, i, _vp, _vp]
+        L.pns_restrict.argtypes = [_vp, i, _vp, _vp]
+        L.pns_prolongate_add.argtypes = [_vp, i, _vp, _vp]
+        for f in ("pns_ctx_create", "pns_level_sizes", "pns_bind_workspace", "pns_set_state",
+                  "pns_cell_apply", "pns_cell_defect", "pns_vanka_setup", "pns_vanka_smooth",
+                  "pns_vcycle", "pns_level_apply", "pns_restrict", "pns_prolongate_add"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """One pns_ctx with its workspace (a torch uint8 tensor on the device)."""
+
+    def __init__(self, n, n_levels=1, precision=FP64, tau=0.01, lo=(0.0, 0.0), hi=(1.0, 1.0),
+                 device="cuda", stream=None):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device)
+        self.precision = precision
+        self.dtype = torch.float64 if precision == FP64 else torch.float32
+        m = pns_mesh()
+        m.dim = 2
+        m.n_cells[0], m.n_cells[1], m.n_cells[2] = int(n[0]), int(n[1]), 1
+        for k in range(2):
+            m.lo[k], m.hi[k] = float(lo[k]), float(hi[k])
+        d = pns_discretization(2, 1, 0.0, float(tau))
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = _vp()
+        rc = lib().pns_ctx_create(ctypes.byref(m), ctypes.byref(d), int(n_levels), int(precision),
+                                  _vp(self.stream.cuda_stream), ctypes.byref(h))
+        if rc != PNS_OK:
+            raise PnsError(rc, "pns_ctx_create rejected the configuration")
+        self.h = h
+        self.n_levels = n_levels
+        nbytes = lib().pns_workspace_bytes(self.h)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self._check(lib().pns_bind_workspace(self.h, _vp(aligned), nbytes))
+        self.workspace_bytes = nbytes
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.pns_ctx_destroy(self.h)
+            self.h = None
+
+    def _check(self, rc):
+        if rc != PNS_OK:
+            raise PnsError(rc, lib().pns_last_error(self.h).decode())
+
+    def sizes(self, level=0):
+        out = (ctypes.c_int64 * 4)()
+        self._check(lib().pns_level_sizes(self.h, level, out))
+        return dict(nst=out[0], cells=out[1], nv=out[2], ns=out[3])
+
+    def vector(self, level=0):
+        return self.torch.zeros(self.sizes(level)["nst"], dtype=self.dtype, device=self.device)
+
+    def _vec(self, t, level=0):
+        assert t.dtype == self.dtype and t.is_contiguous() and t.device.type == "cuda"
+        assert t.numel() == self.sizes(level)["nst"]
+        return _ptr(t)
+
+    # -------------------------------------------------------------- C-ABI
+    def pns_set_state(self, model: dict, uk):
+        md = pns_model(
+            float(model["p"]), float(model["delta"]), float(model.get("nu", 1.0)),
+            float(model.get("nu_inf", 0.0)), float(model.get("gamma1", 40.0)),
+            float(model.get("gamma2", 40.0)), float(model.get("sigma_max", 1.0)),
+            int(model.get("convection", 1)), int(model.get("qsign", 1)),
+            int(model.get("lin", MODIFIED_NEWTON)))
+        assert uk.dtype == self.torch.float64 and uk.is_contiguous()
+        assert uk.numel() == 2 * self.sizes(0)["nv"]
+        self._uk = uk
+        self._check(lib().pns_set_state(self.h, ctypes.byref(md), _ptr(uk)))
+
+    def pns_cell_apply(self, x, y):
+        self._check(lib().pns_cell_apply(self.h, self._vec(x), self._vec(y)))
+
+    def pns_cell_defect(self, b, x, y):
+        self._check(lib().pns_cell_defect(self.h, self._vec(b), self._vec(x), self._vec(y)))
+
+    def pns_vanka_setup(self, node_masks=None):
+        if node_masks is None:
+            self._check(lib().pns_vanka_setup(self.h, None))
+        else:
+            m = np.ascontiguousarray(node_masks, dtype=np.uint16)
+            assert m.size == self.sizes(0)["cells"]
+            self._check(lib().pns_vanka_setup(self.h, m.ctypes.data_as(_vp)))
+
+    def pns_vanka_smooth(self, level, n_sweeps, omega, r, d):
+        self._check(lib().pns_vanka_smooth(self.h, level, n_sweeps, float(omega),
+                                           self._vec(r, level), self._vec(d, level)))
+
+    def pns_vcycle(self, nu1, nu2, omega, r, d):
+        self._check(lib().pns_vcycle(self.h, nu1, nu2, float(omega), self._vec(r), self._vec(d)))
+
+    def pns_level_apply(self, level, x, y):
+        self._check(lib().pns_level_apply(self.h, level, self._vec(x, level), self._vec(y, level)))
+
+    def pns_restrict(self, level, rf, rc):
+        self._check(lib().pns_restrict(self.h, level, self._vec(rf, level),
+                                       self._vec(rc, level + 1)))
+
+    def pns_prolongate_add(self, level, dc, df):
+        self._check(lib().pns_prolongate_add(self.h, level, self._vec(dc, level + 1),
+                                             self._vec(df, level)))
+
+
+def masks_to_bits(masks):
+    """(cells, 9) 0/1 keep-masks -> one uint16 bit field per cell."""
+    masks = np.asarray(masks)
+    return (masks.astype(np.uint16) << np.arange(masks.shape[1], dtype=np.uint16)).sum(
+        axis=1).astype(np.uint16)

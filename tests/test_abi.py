@@ -1,0 +1,68 @@
+"""Host-side checks of the C-ABI library (no GPU needed): the shared object
+loads, exports every function include/pnsmg.h declares, and rejects invalid
+configurations before touching a device."""
+import ctypes
+import os
+
+import pytest
+
+from paper_2603_28706_amd import pnsmg
+
+
+def test_library_exports_every_header_symbol():
+    L = pnsmg.lib()
+    syms = pnsmg.header_symbols()
+    assert len(syms) >= 15
+    for s in syms:
+        assert hasattr(L, s), s
+
+
+def _create(n=(8, 8), levels=1, prec=pnsmg.FP64, tau=0.01, dim=2, k_space=2, k_time=1):
+    m = pnsmg.pns_mesh()
+    m.dim = dim
+    m.n_cells[0], m.n_cells[1], m.n_cells[2] = n[0], n[1], 1
+    m.hi[0] = m.hi[1] = 1.0
+    d = pnsmg.pns_discretization(k_space, k_time, 0.0, tau)
+    h = ctypes.c_void_p()
+    rc = pnsmg.lib().pns_ctx_create(ctypes.byref(m), ctypes.byref(d), levels, prec, None,
+                                    ctypes.byref(h))
+    return rc, h
+
+
+def test_create_rejects_bad_configurations():
+    assert _create(dim=3)[0] == pnsmg.PNS_EUNSUPPORTED
+    assert _create(k_time=2)[0] == pnsmg.PNS_EUNSUPPORTED
+    assert _create(tau=0.0)[0] == pnsmg.PNS_EINVAL
+    assert _create(n=(6, 8), levels=3)[0] == pnsmg.PNS_EINVAL     # not divisible by 4
+    assert _create(n=(4, 4), levels=4)[0] == pnsmg.PNS_EINVAL     # 4 not divisible by 8
+    assert _create(prec=7)[0] == pnsmg.PNS_EINVAL
+    rc, h = _create(n=(256, 256), levels=1)   # apply-only context: no dense coarse solve
+    assert rc == pnsmg.PNS_OK
+    assert pnsmg.lib().pns_workspace_bytes(h) < 4 * 2 ** 30
+    pnsmg.lib().pns_ctx_destroy(h)
+
+
+def test_workspace_query_and_state_errors_without_device():
+    rc, h = _create(n=(16, 16), levels=3)
+    assert rc == pnsmg.PNS_OK
+    L = pnsmg.lib()
+    nbytes = L.pns_workspace_bytes(h)
+    assert nbytes > 0 and nbytes % 256 == 0
+    out = (ctypes.c_int64 * 4)()
+    assert L.pns_level_sizes(h, 0, out) == 0 and out[0] == 2 * (2 * 33 ** 2 + 3 * 256)
+    assert L.pns_level_sizes(h, 2, out) == 0 and out[1] == 16
+    assert L.pns_level_sizes(h, 3, out) == pnsmg.PNS_EINVAL
+    # calls before a workspace is bound fail cleanly
+    x = ctypes.c_void_p(1024)
+    assert L.pns_cell_apply(h, x, ctypes.c_void_p(2048)) == pnsmg.PNS_EWORKSPACE
+    assert L.pns_bind_workspace(h, ctypes.c_void_p(1000), nbytes) == pnsmg.PNS_EWORKSPACE
+    assert L.pns_bind_workspace(h, ctypes.c_void_p(4096), 16) == pnsmg.PNS_EWORKSPACE
+    assert b"workspace" in L.pns_last_error(h)
+    L.pns_ctx_destroy(h)
+
+
+def test_binding_has_no_fallback(monkeypatch, tmp_path):
+    monkeypatch.setattr(pnsmg, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(pnsmg, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        pnsmg.lib()
