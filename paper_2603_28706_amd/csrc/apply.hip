@@ -6,36 +6,41 @@
 // Nitsche terms of eq. def-b-gam).
 //
 // Design (gfx950, wave64):
-// * one workgroup per tile of 15 x 15 owned cells; it also evaluates the
+// * one workgroup per tile of TX x TY owned cells; it also evaluates the
 //   one-cell halo on the low x / low y side, so every node it owns receives all
-//   of its cell contributions inside the workgroup: each output is written
-//   exactly once (no atomics, no zero fill, deterministic);
-// * two threads per cell, one per Radau node mu; the temporal mass coupling
-//   is applied to the nodal values first (w = K_t[mu][0] x_0 + K_t[mu][1] x_1),
-//   so each thread interpolates x_mu (values, gradients), w (values) and
-//   u_k,mu (values, gradients) and tests against its own node only;
-// * sum factorisation over the 3x3 Gauss points, row by row, all in registers;
-//   the 1D basis tables are compile-time constants;
+//   of its cell contributions inside the workgroup and each output is written
+//   exactly once (no global atomics, no zero fill);
+// * the tile's nodal values of x and u_k (both Radau nodes) are staged in LDS
+//   with coalesced row loads;
+// * three threads per (cell, Radau node mu), one per row qy of the 3x3 Gauss
+//   points; a wave holds the two Radau nodes of the 32 cells of one parity
+//   class of the tile (cells of one class share no node, so the LDS atomics of
+//   a wave never collide) for one row qy (wave-uniform); each thread contracts the nodal values along y at its row (sum
+//   factorisation), evaluates values / gradients / tangent / fluxes at its
+//   three points, and forms its share of the 9 nodal results by the transposed
+//   contractions; the temporal mass coupling is applied to nodal values first
+//   (w = K_t[mu][0] x_0 + K_t[mu][1] x_1);
 // * the tangent scalars (Delta^2, mu, eta, clip factor, kappa) are evaluated
 //   in FP64 in both precisions; everything else in the storage type T;
-// * per-node contributions are summed in LDS in four colour phases (cells of
-//   one parity class share no node), then written coalesced.
+// * shares are summed in LDS with LDS atomics (summation order inside a tile
+//   is not fixed), then the owned nodes are written coalesced.
 #include "pns_internal.h"
 
 namespace pns {
 namespace {
 
-constexpr int TX = 15;                 // owned cells per tile and direction
-constexpr int HX = TX + 1;             // evaluated cells (with low-side halo)
-constexpr int BX = 2 * TX + 3;         // LDS node box per direction
-constexpr int kThreads = 2 * HX * HX;  // 512
+constexpr int TX = 15, TY = 7;            // owned cells per tile
+constexpr int HX = TX + 1, HY = TY + 1;   // evaluated cells (with low-side halo)
+constexpr int BX = 2 * TX + 4, BY = 2 * TY + 3;  // LDS node box (x padded to 34)
+constexpr int kCells = HX * HY;           // 128
+constexpr int kThreads = 6 * kCells;      // 768: (cell, mu, qy)
 
 template <int LIN>
 __device__ __forceinline__ void tangent_coef(const Model& m, double a00, double a01, double a11,
                                              double& eta, double& kappa) {
   const double a2 = a00 * a00 + 2.0 * a01 * a01 + a11 * a11;
   const double D2 = m.delta2 + a2;
-  const double mu = m.nu * pow(D2, m.expo);
+  const double mu = m.nu * exp(m.expo * log(D2));
   eta = m.nu_inf + mu;
   if (LIN == PNS_PICARD) {
     kappa = 0.0;
@@ -50,91 +55,94 @@ __device__ __forceinline__ void tangent_coef(const Model& m, double a00, double 
   }
 }
 
-// Boundary face contribution of one cell (Dirichlet faces): value/gradient test
-// coefficients at the 3 face points, contracted directly against the 9 nodes.
+// value held by the partner lane (lane ^ 1): the other Radau node of the cell
+__device__ __forceinline__ float swap_pair(float v) { return __shfl_xor(v, 1); }
+__device__ __forceinline__ double swap_pair(double v) { return __shfl_xor(v, 1); }
+
+// One point of a Dirichlet face of the cell: value / gradient test coefficients,
+// contracted directly against the 9 nodes and added to the LDS sums.
 template <typename T, int LIN, bool CONV>
-__device__ void face_terms(const Model& m, const Grid& g, T sfac, int side, const T* u0, const T* u1,
-                           const T* x0, const T* x1, const T* pp, T* o0, T* o1, T* op) {
+__device__ __forceinline__ void face_point(const Model& m, const Grid& g, T sfac, int side, int q,
+                                        const T (*Xs)[BY][BX], const T (*Us)[BY][BX], int mu,
+                                        int lx0, int ly0, T p0, T p1, T p2,
+                                        double (*acc)[BY][BX], double* pacc) {
   // side: 0 x=0 (n=-e_x), 1 x=1 (n=+e_x), 2 y=0 (n=-e_y), 3 y=1 (n=+e_y)
   const bool xface = side < 2;
   const double nxv = xface ? (side == 0 ? -1.0 : 1.0) : 0.0;
   const double nyv = xface ? 0.0 : (side == 2 ? -1.0 : 1.0);
   const double hF = xface ? g.hx : g.hy;
   const double flen = xface ? g.hy : g.hx;
+  const double xi = xface ? (side == 0 ? 0.0 : 1.0) : kGP[q];
+  const double et = xface ? kGP[q] : (side == 2 ? 0.0 : 1.0);
   const T etaD = (T)m.etaD;
   const T pen1 = (T)(m.gamma1 * m.etaD / hF);
   const T pen2 = (T)(m.gamma2 / hF);
   const T n0 = (T)nxv, n1 = (T)nyv;
+  T vx[3], vy[3], dx[3], dy[3];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    const double xi = xface ? (side == 0 ? 0.0 : 1.0) : kGP[q];
-    const double et = xface ? kGP[q] : (side == 2 ? 0.0 : 1.0);
-    T vx[3], vy[3], dx[3], dy[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      vx[a] = (T)q2v(a, xi);
-      vy[a] = (T)q2v(a, et);
-      dx[a] = (T)(q2d(a, xi) / g.hx);
-      dy[a] = (T)(q2d(a, et) / g.hy);
-    }
-    T U[2] = {0, 0}, GU[2][2] = {{0, 0}, {0, 0}}, X[2] = {0, 0}, GX[2][2] = {{0, 0}, {0, 0}};
-#pragma unroll
-    for (int ay = 0; ay < 3; ++ay)
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        const int a = ax + 3 * ay;
-        const T ph = vx[ax] * vy[ay], px = dx[ax] * vy[ay], py = vx[ax] * dy[ay];
-        U[0] += u0[a] * ph; U[1] += u1[a] * ph;
-        GU[0][0] += u0[a] * px; GU[0][1] += u0[a] * py;
-        GU[1][0] += u1[a] * px; GU[1][1] += u1[a] * py;
-        X[0] += x0[a] * ph; X[1] += x1[a] * ph;
-        GX[0][0] += x0[a] * px; GX[0][1] += x0[a] * py;
-        GX[1][0] += x1[a] * px; GX[1][1] += x1[a] * py;
-      }
-    const T xp = pp[0] + pp[1] * (T)(xi - 0.5) + pp[2] * (T)(et - 0.5);
-    const T a00 = GU[0][0], a01 = (T)0.5 * (GU[0][1] + GU[1][0]), a11 = GU[1][1];
-    const T b00 = GX[0][0], b01 = (T)0.5 * (GX[0][1] + GX[1][0]), b11 = GX[1][1];
-    double eta_d, kap_d;
-    tangent_coef<LIN>(m, (double)a00, (double)a01, (double)a11, eta_d, kap_d);
-    const T eta = (T)eta_d, kap = (T)kap_d;
-    const T ab = a00 * b00 + (T)2 * a01 * b01 + a11 * b11;
-    const T T00 = eta * b00 + kap * ab * a00;
-    const T T01 = eta * b01 + kap * ab * a01;
-    const T T11 = eta * b11 + kap * ab * a11;
-    const T sW = sfac * (T)(kGW[q] * flen);
-    const T un = U[0] * n0 + U[1] * n1;
-    const T xn = X[0] * n0 + X[1] * n1;
-    T F0 = -(T00 * n0 + T01 * n1) + xp * n0 + pen1 * X[0] + pen2 * xn * n0;
-    T F1 = -(T01 * n0 + T11 * n1) + xp * n1 + pen1 * X[1] + pen2 * xn * n1;
-    if (CONV) {
-      const T neg = (T)0.5 * (fabs(un) - un);
-      F0 += un * X[0] - neg * X[0];
-      F1 += un * X[1] - neg * X[1];
-      if (LIN != PNS_PICARD) {
-        F0 += xn * U[0];
-        F1 += xn * U[1];
-      }
-    }
-    F0 *= sW;
-    F1 *= sW;
-    // -eta_D (Dw n).x  ->  coefficient of d_j w_i : -eta_D (x_i n_j + x_j n_i)/2
-    const T c = -sW * etaD * (T)0.5;
-    const T G00 = c * (X[0] * n0 + X[0] * n0), G01 = c * (X[0] * n1 + X[1] * n0);
-    const T G10 = c * (X[1] * n0 + X[0] * n1), G11 = c * (X[1] * n1 + X[1] * n1);
-#pragma unroll
-    for (int ay = 0; ay < 3; ++ay)
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        const int a = ax + 3 * ay;
-        const T ph = vx[ax] * vy[ay], px = dx[ax] * vy[ay], py = vx[ax] * dy[ay];
-        o0[a] += F0 * ph + G00 * px + G01 * py;
-        o1[a] += F1 * ph + G10 * px + G11 * py;
-      }
-    const T P = sW * (T)m.qsign * xn;
-    op[0] += P;
-    op[1] += P * (T)(xi - 0.5);
-    op[2] += P * (T)(et - 0.5);
+  for (int a = 0; a < 3; ++a) {
+    vx[a] = (T)q2v(a, xi);
+    vy[a] = (T)q2v(a, et);
+    dx[a] = (T)(q2d(a, xi) / g.hx);
+    dy[a] = (T)(q2d(a, et) / g.hy);
   }
+  T U[2] = {0, 0}, GU[2][2] = {{0, 0}, {0, 0}}, X[2] = {0, 0}, GX[2][2] = {{0, 0}, {0, 0}};
+#pragma unroll
+  for (int ay = 0; ay < 3; ++ay)
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const T ph = vx[ax] * vy[ay], px = dx[ax] * vy[ay], py = vx[ax] * dy[ay];
+      const T u0 = Us[2 * mu][ly0 + ay][lx0 + ax], u1 = Us[2 * mu + 1][ly0 + ay][lx0 + ax];
+      const T x0 = Xs[2 * mu][ly0 + ay][lx0 + ax], x1 = Xs[2 * mu + 1][ly0 + ay][lx0 + ax];
+      U[0] += u0 * ph; U[1] += u1 * ph;
+      GU[0][0] += u0 * px; GU[0][1] += u0 * py;
+      GU[1][0] += u1 * px; GU[1][1] += u1 * py;
+      X[0] += x0 * ph; X[1] += x1 * ph;
+      GX[0][0] += x0 * px; GX[0][1] += x0 * py;
+      GX[1][0] += x1 * px; GX[1][1] += x1 * py;
+    }
+  const T xp = p0 + p1 * (T)(xi - 0.5) + p2 * (T)(et - 0.5);
+  const T a00 = GU[0][0], a01 = (T)0.5 * (GU[0][1] + GU[1][0]), a11 = GU[1][1];
+  const T b00 = GX[0][0], b01 = (T)0.5 * (GX[0][1] + GX[1][0]), b11 = GX[1][1];
+  double eta_d, kap_d;
+  tangent_coef<LIN>(m, (double)a00, (double)a01, (double)a11, eta_d, kap_d);
+  const T eta = (T)eta_d, kap = (T)kap_d;
+  const T ab = a00 * b00 + (T)2 * a01 * b01 + a11 * b11;
+  const T T00 = eta * b00 + kap * ab * a00;
+  const T T01 = eta * b01 + kap * ab * a01;
+  const T T11 = eta * b11 + kap * ab * a11;
+  const T sW = sfac * (T)(kGW[q] * flen);
+  const T un = U[0] * n0 + U[1] * n1;
+  const T xn = X[0] * n0 + X[1] * n1;
+  T F0 = -(T00 * n0 + T01 * n1) + xp * n0 + pen1 * X[0] + pen2 * xn * n0;
+  T F1 = -(T01 * n0 + T11 * n1) + xp * n1 + pen1 * X[1] + pen2 * xn * n1;
+  if (CONV) {
+    const T neg = (T)0.5 * (fabs(un) - un);
+    F0 += un * X[0] - neg * X[0];
+    F1 += un * X[1] - neg * X[1];
+    if (LIN != PNS_PICARD) {
+      F0 += xn * U[0];
+      F1 += xn * U[1];
+    }
+  }
+  F0 *= sW;
+  F1 *= sW;
+  // -eta_D (Dw n).x  ->  coefficient of d_j w_i : -eta_D (x_i n_j + x_j n_i)/2
+  const T c = -sW * etaD * (T)0.5;
+  const T G00 = c * (X[0] * n0 + X[0] * n0), G01 = c * (X[0] * n1 + X[1] * n0);
+  const T G10 = c * (X[1] * n0 + X[0] * n1), G11 = c * (X[1] * n1 + X[1] * n1);
+#pragma unroll
+  for (int ay = 0; ay < 3; ++ay)
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const T ph = vx[ax] * vy[ay], px = dx[ax] * vy[ay], py = vx[ax] * dy[ay];
+      atomicAdd(&acc[2 * mu][ly0 + ay][lx0 + ax], (double)(F0 * ph + G00 * px + G01 * py));
+      atomicAdd(&acc[2 * mu + 1][ly0 + ay][lx0 + ax], (double)(F1 * ph + G10 * px + G11 * py));
+    }
+  const T P = sW * (T)m.qsign * xn;
+  atomicAdd(&pacc[0], (double)P);
+  atomicAdd(&pacc[1], (double)(P * (T)(xi - 0.5)));
+  atomicAdd(&pacc[2], (double)(P * (T)(et - 0.5)));
 }
 
 template <typename T, int LIN, bool CONV, int MODE>
@@ -143,198 +151,203 @@ __global__ __launch_bounds__(kThreads) void cell_apply_kernel(Grid g, Model m, d
                                                               const T* __restrict__ x,
                                                               const T* __restrict__ b,
                                                               T* __restrict__ y, int tiles_x) {
-  __shared__ T acc[4][BX][BX];  // [mu*2 + comp][local node y][local node x]
+  __shared__ T Xs[4][BY][BX];   // x: [mu*2 + comp]
+  __shared__ T Us[4][BY][BX];   // u_k: [mu*2 + comp]
+  __shared__ double acc[4][BY][BX];  // results: [mu*2 + comp]
+  __shared__ double pacc[2][kCells][3];
   const int tile = blockIdx.x;
   const int cx0 = (tile % tiles_x) * TX;
-  const int cy0 = (tile / tiles_x) * TX;
+  const int cy0 = (tile / tiles_x) * TY;
   const int t = threadIdx.x;
-  const int mu = t & 1;
-  const int lc = t >> 1;
-  const int cx = cx0 - 1 + lc % HX;
-  const int cy = cy0 - 1 + lc / HX;
-  const bool valid = cx >= 0 && cy >= 0 && cx < g.nx && cy < g.ny;
   const int NX = 2 * g.nx + 1;
+  const int gx0 = 2 * (cx0 - 1), gy0 = 2 * (cy0 - 1);
 
-  for (int i = t; i < 4 * BX * BX; i += kThreads) (&acc[0][0][0])[i] = (T)0;
+  // stage x and u_k of the node box, zero the sums
+  for (int i = t; i < 4 * BY * BX; i += kThreads) {
+    const int f = i / (BY * BX), r = i % (BY * BX);
+    const int ly = r / BX, lx = r % BX;
+    const int gx = gx0 + lx, gy = gy0 + ly;
+    T xv = 0, uv = 0;
+    if (gx >= 0 && gy >= 0 && gx <= 2 * g.nx && gy <= 2 * g.ny) {
+      const int64_t gn = (int64_t)gy * NX + gx;
+      xv = x[(int64_t)(f >> 1) * g.ns + (int64_t)(f & 1) * g.nn + gn];
+      uv = uk[(int64_t)(f >> 1) * g.nv + (int64_t)(f & 1) * g.nn + gn];
+    }
+    Xs[f][ly][lx] = xv;
+    Us[f][ly][lx] = uv;
+    acc[f][ly][lx] = 0.0;
+  }
+  for (int i = t; i < 2 * kCells * 3; i += kThreads) (&pacc[0][0][0])[i] = 0.0;
+  __syncthreads();
 
-  T o0[9], o1[9], op[3];
-#pragma unroll
-  for (int a = 0; a < 9; ++a) o0[a] = o1[a] = (T)0;
-  op[0] = op[1] = op[2] = (T)0;
+  // wave w: row qy = w / 4, parity class w % 4; lane: (cell of the class, mu)
+  const int qy = __builtin_amdgcn_readfirstlane(t >> 8);
+  const int color = (t >> 6) & 3, lane = t & 63;
+  const int mu = lane & 1, k = lane >> 1;
+  const int hx = 2 * (k % (HX / 2)) + (color & 1), hy = 2 * (k / (HX / 2)) + (color >> 1);
+  const int lc = hy * HX + hx;
+  const int cx = cx0 - 1 + hx, cy = cy0 - 1 + hy;
+  const bool valid = cx >= 0 && cy >= 0 && cx < g.nx && cy < g.ny;
+  const int lx0 = 2 * hx, ly0 = 2 * hy;
 
-  const int64_t cell = (int64_t)cy * g.nx + cx;
-  if (valid) {
-    T u0[9], u1[9], x0[9], x1[9], w0[9], w1[9], pp[3];
+  // every lane takes part in the pair exchange below, valid or not
+  {
     const int other = 1 - mu;
     const T kself = (T)kKt[mu][mu], koth = (T)kKt[mu][other];
-    const T* um = uk + (int64_t)mu * g.nv;
-    const T* xm = x + (int64_t)mu * g.ns;
-    const T* xo = x + (int64_t)other * g.ns;
-#pragma unroll
-    for (int ay = 0; ay < 3; ++ay)
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        const int a = ax + 3 * ay;
-        const int64_t gn = (int64_t)(2 * cy + ay) * NX + (2 * cx + ax);
-        u0[a] = um[gn];
-        u1[a] = um[g.nn + gn];
-        x0[a] = xm[gn];
-        x1[a] = xm[g.nn + gn];
-        w0[a] = kself * x0[a] + koth * xo[gn];
-        w1[a] = kself * x1[a] + koth * xo[g.nn + gn];
-      }
-#pragma unroll
-    for (int j = 0; j < 3; ++j) pp[j] = xm[g.nv + 3 * cell + j];
-
+    const int64_t cell = (int64_t)(valid ? cy : 0) * g.nx + (valid ? cx : 0);
+    const T* xm = x + (int64_t)mu * g.ns + g.nv + 3 * cell;
+    T pp[3] = {xm[0], xm[1], xm[2]};
     const T sfac = (T)(tau * kWt[mu]);
     const T ihx = (T)(1.0 / g.hx), ihy = (T)(1.0 / g.hy);
     const T area = (T)(g.hx * g.hy);
-    // transposed accumulators: T1[c][qx][ay], T2[c][qx][ay]
-    T T1a[3][3], T2a[3][3], T1b[3][3], T2b[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) T1a[i][j] = T2a[i][j] = T1b[i][j] = T2b[i][j] = (T)0;
 
+    // contraction along y at row qy: f_y[ax] (values), f_d[ax] (y-derivatives)
+    T u0y[3], u0d[3], u1y[3], u1d[3], x0y[3], x0d[3], x1y[3], x1d[3], w0y[3], w1y[3];
 #pragma unroll
-    for (int qy = 0; qy < 3; ++qy) {
-      // contract along y at qy: f_y[ax], f_dy[ax]
-      T u0y[3], u0d[3], u1y[3], u1d[3], x0y[3], x0d[3], x1y[3], x1d[3], w0y[3], w1y[3];
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        u0y[ax] = u0d[ax] = u1y[ax] = u1d[ax] = (T)0;
-        x0y[ax] = x0d[ax] = x1y[ax] = x1d[ax] = w0y[ax] = w1y[ax] = (T)0;
-#pragma unroll
-        for (int ay = 0; ay < 3; ++ay) {
-          const T bv = (T)q2v(ay, kGP[qy]), bd = (T)q2d(ay, kGP[qy]);
-          const int a = ax + 3 * ay;
-          u0y[ax] += bv * u0[a]; u0d[ax] += bd * u0[a];
-          u1y[ax] += bv * u1[a]; u1d[ax] += bd * u1[a];
-          x0y[ax] += bv * x0[a]; x0d[ax] += bd * x0[a];
-          x1y[ax] += bv * x1[a]; x1d[ax] += bd * x1[a];
-          w0y[ax] += bv * w0[a]; w1y[ax] += bv * w1[a];
-        }
-      }
-#pragma unroll
-      for (int qx = 0; qx < 3; ++qx) {
-        T U0 = 0, U1 = 0, U0x = 0, U0y = 0, U1x = 0, U1y = 0;
-        T X0 = 0, X1 = 0, X0x = 0, X0y = 0, X1x = 0, X1y = 0, W0 = 0, W1 = 0;
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-          const T bv = (T)q2v(ax, kGP[qx]), bd = (T)q2d(ax, kGP[qx]);
-          U0 += bv * u0y[ax]; U0x += bd * u0y[ax]; U0y += bv * u0d[ax];
-          U1 += bv * u1y[ax]; U1x += bd * u1y[ax]; U1y += bv * u1d[ax];
-          X0 += bv * x0y[ax]; X0x += bd * x0y[ax]; X0y += bv * x0d[ax];
-          X1 += bv * x1y[ax]; X1x += bd * x1y[ax]; X1y += bv * x1d[ax];
-          W0 += bv * w0y[ax]; W1 += bv * w1y[ax];
-        }
-        U0x *= ihx; U1x *= ihx; X0x *= ihx; X1x *= ihx;
-        U0y *= ihy; U1y *= ihy; X0y *= ihy; X1y *= ihy;
-        const T a00 = U0x, a01 = (T)0.5 * (U0y + U1x), a11 = U1y;
-        const T b00 = X0x, b01 = (T)0.5 * (X0y + X1x), b11 = X1y;
-        double eta_d, kap_d;
-        tangent_coef<LIN>(m, (double)a00, (double)a01, (double)a11, eta_d, kap_d);
-        const T eta = (T)eta_d, kap = (T)kap_d;
-        const T ab = a00 * b00 + (T)2 * a01 * b01 + a11 * b11;
-        const T xp = pp[0] + pp[1] * (T)(kGP[qx] - 0.5) + pp[2] * (T)(kGP[qy] - 0.5);
-        T G00 = eta * b00 + kap * ab * a00 - xp;
-        T G01 = eta * b01 + kap * ab * a01;
-        T G10 = G01;
-        T G11 = eta * b11 + kap * ab * a11 - xp;
-        if (CONV) {
-          G00 -= X0 * U0;
-          G01 -= X0 * U1;
-          G10 -= X1 * U0;
-          G11 -= X1 * U1;
-          if (LIN != PNS_PICARD) {
-            G00 -= U0 * X0;
-            G01 -= U0 * X1;
-            G10 -= U1 * X0;
-            G11 -= U1 * X1;
-          }
-        }
-        const T W = area * (T)(kGW[qx] * kGW[qy]);
-        const T sW = sfac * W;
-        G00 *= sW * ihx; G10 *= sW * ihx;
-        G01 *= sW * ihy; G11 *= sW * ihy;
-        const T V0 = W * W0, V1 = W * W1;
-        const T P = -sW * (X0x + X1y);
-        op[0] += P;
-        op[1] += P * (T)(kGP[qx] - 0.5);
-        op[2] += P * (T)(kGP[qy] - 0.5);
-#pragma unroll
-        for (int ay = 0; ay < 3; ++ay) {
-          const T bv = (T)q2v(ay, kGP[qy]), bd = (T)q2d(ay, kGP[qy]);
-          T1a[qx][ay] += bv * V0 + bd * G01;
-          T2a[qx][ay] += bv * G00;
-          T1b[qx][ay] += bv * V1 + bd * G11;
-          T2b[qx][ay] += bv * G10;
-        }
-      }
+    for (int ax = 0; ax < 3; ++ax) {
+      u0y[ax] = u0d[ax] = u1y[ax] = u1d[ax] = (T)0;
+      x0y[ax] = x0d[ax] = x1y[ax] = x1d[ax] = w0y[ax] = w1y[ax] = (T)0;
     }
 #pragma unroll
-    for (int ay = 0; ay < 3; ++ay)
+    for (int ay = 0; ay < 3; ++ay) {
+      T bv, bd;
+      // row-dependent 1D basis at the Gauss point qy (select, not a table load)
+      bv = qy == 0 ? (T)q2v(ay, kGP[0]) : (qy == 1 ? (T)q2v(ay, kGP[1]) : (T)q2v(ay, kGP[2]));
+      bd = qy == 0 ? (T)q2d(ay, kGP[0]) : (qy == 1 ? (T)q2d(ay, kGP[1]) : (T)q2d(ay, kGP[2]));
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) {
-        T s0 = 0, s1 = 0;
-#pragma unroll
-        for (int qx = 0; qx < 3; ++qx) {
-          const T bv = (T)q2v(ax, kGP[qx]), bd = (T)q2d(ax, kGP[qx]);
-          s0 += bv * T1a[qx][ay] + bd * T2a[qx][ay];
-          s1 += bv * T1b[qx][ay] + bd * T2b[qx][ay];
-        }
-        o0[ax + 3 * ay] = s0;
-        o1[ax + 3 * ay] = s1;
+        const int ly = ly0 + ay, lx = lx0 + ax;
+        const T u0 = Us[2 * mu][ly][lx], u1 = Us[2 * mu + 1][ly][lx];
+        const T x0 = Xs[2 * mu][ly][lx], x1 = Xs[2 * mu + 1][ly][lx];
+        const T w0 = kself * x0 + koth * swap_pair(x0);
+        const T w1 = kself * x1 + koth * swap_pair(x1);
+        u0y[ax] += bv * u0; u0d[ax] += bd * u0;
+        u1y[ax] += bv * u1; u1d[ax] += bd * u1;
+        x0y[ax] += bv * x0; x0d[ax] += bd * x0;
+        x1y[ax] += bv * x1; x1d[ax] += bd * x1;
+        w0y[ax] += bv * w0; w1y[ax] += bv * w1;
       }
-    // Dirichlet faces (the whole boundary)
-    if (cx == 0) face_terms<T, LIN, CONV>(m, g, sfac, 0, u0, u1, x0, x1, pp, o0, o1, op);
-    if (cx == g.nx - 1) face_terms<T, LIN, CONV>(m, g, sfac, 1, u0, u1, x0, x1, pp, o0, o1, op);
-    if (cy == 0) face_terms<T, LIN, CONV>(m, g, sfac, 2, u0, u1, x0, x1, pp, o0, o1, op);
-    if (cy == g.ny - 1) face_terms<T, LIN, CONV>(m, g, sfac, 3, u0, u1, x0, x1, pp, o0, o1, op);
+    }
+    const double gyq = qy == 0 ? kGP[0] : (qy == 1 ? kGP[1] : kGP[2]);
+    const double gwy = qy == 0 ? kGW[0] : (qy == 1 ? kGW[1] : kGW[2]);
+    // per-point coefficients of the tests phi (A*), d/dx phi (B*), d/dy phi (C*)
+    T S1a[3] = {0, 0, 0}, S2a[3] = {0, 0, 0}, S1b[3] = {0, 0, 0}, S2b[3] = {0, 0, 0};
+    T op[3] = {0, 0, 0};
+#pragma unroll
+    for (int qx = 0; qx < 3; ++qx) {
+      T U0 = 0, U1 = 0, U0x = 0, U0y = 0, U1x = 0, U1y = 0;
+      T X0 = 0, X1 = 0, X0x = 0, X0y = 0, X1x = 0, X1y = 0, W0 = 0, W1 = 0;
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        const T bv = (T)q2v(ax, kGP[qx]), bd = (T)q2d(ax, kGP[qx]);
+        U0 += bv * u0y[ax]; U0x += bd * u0y[ax]; U0y += bv * u0d[ax];
+        U1 += bv * u1y[ax]; U1x += bd * u1y[ax]; U1y += bv * u1d[ax];
+        X0 += bv * x0y[ax]; X0x += bd * x0y[ax]; X0y += bv * x0d[ax];
+        X1 += bv * x1y[ax]; X1x += bd * x1y[ax]; X1y += bv * x1d[ax];
+        W0 += bv * w0y[ax]; W1 += bv * w1y[ax];
+      }
+      U0x *= ihx; U1x *= ihx; X0x *= ihx; X1x *= ihx;
+      U0y *= ihy; U1y *= ihy; X0y *= ihy; X1y *= ihy;
+      const T a00 = U0x, a01 = (T)0.5 * (U0y + U1x), a11 = U1y;
+      const T b00 = X0x, b01 = (T)0.5 * (X0y + X1x), b11 = X1y;
+      double eta_d, kap_d;
+      tangent_coef<LIN>(m, (double)a00, (double)a01, (double)a11, eta_d, kap_d);
+      const T eta = (T)eta_d, kap = (T)kap_d;
+      const T ab = a00 * b00 + (T)2 * a01 * b01 + a11 * b11;
+      const T xp = pp[0] + pp[1] * (T)(kGP[qx] - 0.5) + pp[2] * (T)(gyq - 0.5);
+      T G00 = eta * b00 + kap * ab * a00 - xp;
+      T G01 = eta * b01 + kap * ab * a01;
+      T G10 = G01;
+      T G11 = eta * b11 + kap * ab * a11 - xp;
+      if (CONV) {
+        G00 -= X0 * U0;
+        G01 -= X0 * U1;
+        G10 -= X1 * U0;
+        G11 -= X1 * U1;
+        if (LIN != PNS_PICARD) {
+          G00 -= U0 * X0;
+          G01 -= U0 * X1;
+          G10 -= U1 * X0;
+          G11 -= U1 * X1;
+        }
+      }
+      const T W = area * (T)(kGW[qx] * gwy);
+      const T sW = sfac * W;
+      G00 *= sW * ihx; G10 *= sW * ihx;
+      G01 *= sW * ihy; G11 *= sW * ihy;
+      const T V0 = W * W0, V1 = W * W1;
+      const T P = -sW * (X0x + X1y);
+      op[0] += P;
+      op[1] += P * (T)(kGP[qx] - 0.5);
+      op[2] += P * (T)(gyq - 0.5);
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) {
+        const T bv = (T)q2v(ax, kGP[qx]), bd = (T)q2d(ax, kGP[qx]);
+        S1a[ax] += bv * V0 + bd * G00;
+        S2a[ax] += bv * G01;
+        S1b[ax] += bv * V1 + bd * G10;
+        S2b[ax] += bv * G11;
+      }
+    }
+    if (valid) {
+      // this row's share of the nodal results: B[qy][ay] S1[ax] + D[qy][ay] S2[ax]
+#pragma unroll
+      for (int ay = 0; ay < 3; ++ay) {
+        const T bv = qy == 0 ? (T)q2v(ay, kGP[0]) : (qy == 1 ? (T)q2v(ay, kGP[1]) : (T)q2v(ay, kGP[2]));
+        const T bd = qy == 0 ? (T)q2d(ay, kGP[0]) : (qy == 1 ? (T)q2d(ay, kGP[1]) : (T)q2d(ay, kGP[2]));
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          atomicAdd(&acc[2 * mu][ly0 + ay][lx0 + ax], (double)(bv * S1a[ax] + bd * S2a[ax]));
+          atomicAdd(&acc[2 * mu + 1][ly0 + ay][lx0 + ax], (double)(bv * S1b[ax] + bd * S2b[ax]));
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < 3; ++j) atomicAdd(&pacc[mu][lc][j], (double)op[j]);
+      // Dirichlet faces (the whole boundary): point qy of each boundary face
+      if (cx == 0)
+        face_point<T, LIN, CONV>(m, g, sfac, 0, qy, Xs, Us, mu, lx0, ly0, pp[0], pp[1], pp[2],
+                                 acc, pacc[mu][lc]);
+      if (cx == g.nx - 1)
+        face_point<T, LIN, CONV>(m, g, sfac, 1, qy, Xs, Us, mu, lx0, ly0, pp[0], pp[1], pp[2],
+                                 acc, pacc[mu][lc]);
+      if (cy == 0)
+        face_point<T, LIN, CONV>(m, g, sfac, 2, qy, Xs, Us, mu, lx0, ly0, pp[0], pp[1], pp[2],
+                                 acc, pacc[mu][lc]);
+      if (cy == g.ny - 1)
+        face_point<T, LIN, CONV>(m, g, sfac, 3, qy, Xs, Us, mu, lx0, ly0, pp[0], pp[1], pp[2],
+                                 acc, pacc[mu][lc]);
+    }
   }
   __syncthreads();
-  const int color = (cx & 1) | ((cy & 1) << 1);
-  const int lx0 = 2 * (cx - (cx0 - 1)), ly0 = 2 * (cy - (cy0 - 1));
-#pragma unroll 1
-  for (int ph = 0; ph < 4; ++ph) {
-    if (valid && color == ph) {
-#pragma unroll
-      for (int ay = 0; ay < 3; ++ay)
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-          acc[mu * 2 + 0][ly0 + ay][lx0 + ax] += o0[ax + 3 * ay];
-          acc[mu * 2 + 1][ly0 + ay][lx0 + ax] += o1[ax + 3 * ay];
-        }
-    }
-    __syncthreads();
-  }
   // pressure rows of owned cells
-  if (valid && cx >= cx0 && cy >= cy0) {
-    T* ym = y + (int64_t)mu * g.ns + g.nv + 3 * cell;
-    const T* bm = b + (int64_t)mu * g.ns + g.nv + 3 * cell;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) ym[j] = MODE ? bm[j] - op[j] : op[j];
+  for (int i = t; i < 2 * kCells * 3; i += kThreads) {
+    const int pmu = i / (kCells * 3), r = i % (kCells * 3);
+    const int c = r / 3, j = r % 3;
+    const int ccx = cx0 - 1 + c % HX, ccy = cy0 - 1 + c / HX;
+    if (ccx >= cx0 && ccy >= cy0 && ccx < g.nx && ccy < g.ny) {
+      const int64_t idx = (int64_t)pmu * g.ns + g.nv + 3 * ((int64_t)ccy * g.nx + ccx) + j;
+      const double v = pacc[pmu][c][j];
+      y[idx] = MODE ? (T)((double)b[idx] - v) : (T)v;
+    }
   }
   // owned velocity nodes
   const int gx_end = (cx0 + TX >= g.nx) ? 2 * g.nx + 1 : 2 * (cx0 + TX);
-  const int gy_end = (cy0 + TX >= g.ny) ? 2 * g.ny + 1 : 2 * (cy0 + TX);
+  const int gy_end = (cy0 + TY >= g.ny) ? 2 * g.ny + 1 : 2 * (cy0 + TY);
   const int nox = gx_end - 2 * cx0, noy = gy_end - 2 * cy0;
-  for (int i = t; i < nox * noy; i += kThreads) {
-    const int ox = i % nox, oy = i / nox;
+  for (int i = t; i < 4 * nox * noy; i += kThreads) {
+    const int s = i / (nox * noy), r = i % (nox * noy);
+    const int ox = r % nox, oy = r / nox;
     const int64_t gn = (int64_t)(2 * cy0 + oy) * NX + (2 * cx0 + ox);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int64_t idx = (int64_t)(s >> 1) * g.ns + (int64_t)(s & 1) * g.nn + gn;
-      const T v = acc[s][oy + 2][ox + 2];
-      y[idx] = MODE ? b[idx] - v : v;
-    }
+    const int64_t idx = (int64_t)(s >> 1) * g.ns + (int64_t)(s & 1) * g.nn + gn;
+    const double v = acc[s][oy + 2][ox + 2];
+    y[idx] = MODE ? (T)((double)b[idx] - v) : (T)v;
   }
 }
 
 template <typename T, int LIN, bool CONV>
 hipError_t launch3(const Grid& g, const Model& m, double tau, const T* uk, const T* x, const T* b,
                    T* y, int mode, hipStream_t s) {
-  const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TX - 1) / TX;
+  const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY;
   dim3 grid(tx * ty), block(kThreads);
   if (mode == 0)
     hipLaunchKernelGGL((cell_apply_kernel<T, LIN, CONV, 0>), grid, block, 0, s, g, m, tau, uk, x, b,
