@@ -21,8 +21,9 @@ namespace {
 struct Level {
   Grid g;
   double* E64 = nullptr;  // Galerkin element matrices (FP64), levels >= 1 (and 0 if coarsest)
-  void* E = nullptr;      // same in the context precision
+  void* E = nullptr;      // same, transposed per cell, in the context precision
   void* inv = nullptr;    // patch inverses, column-major, context precision
+                          // (level 0: complex 21x21 time-diagonal form)
   void* res = nullptr;    // defect
   void* r = nullptr;      // level right-hand side (levels >= 1)
   void* d = nullptr;      // level correction (levels >= 1)
@@ -100,12 +101,10 @@ size_t layout(pns_ctx* c, bool bind) {
   for (int l = 0; l < c->nlev; ++l) {
     Level& L = c->lev[l];
     const bool coarsest = (l == c->nlev - 1);
-    L.inv = take(L.g.nc * kNst * kNst * es);
+    L.inv = take(L.g.nc * (l == 0 ? 2 * kNs * kNs : kNst * kNst) * es);
     L.res = take(L.g.nst * es);
-    if (l >= 1 || coarsest) {
-      L.E64 = (double*)take(L.g.nc * kNst * kNst * 8);
-      L.E = (es == 8) ? (void*)L.E64 : (void*)take(L.g.nc * kNst * kNst * es);
-    }
+    if (l >= 1 || coarsest) L.E64 = (double*)take(L.g.nc * kNst * kNst * 8);
+    if (l >= 1) L.E = take(L.g.nc * kNst * kNst * es);
     if (l >= 1) {
       L.r = take(L.g.nst * es);
       L.d = take(L.g.nst * es);
@@ -172,7 +171,9 @@ hipError_t smooth(pns_ctx* c, int l, int nsweeps, double omega, const T* r, T* d
       if (e != hipSuccess) return e;
       res = (const T*)L.res;
     }
-    hipError_t e = launch_patch_sweep<T>(L.g, (const T*)L.inv, res, d, omega, c->stream);
+    hipError_t e = l == 0
+                       ? launch_patch_sweep_c<T>(L.g, (const T*)L.inv, res, d, omega, c->stream)
+                       : launch_patch_sweep<T>(L.g, (const T*)L.inv, res, d, omega, c->stream);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -216,7 +217,7 @@ int vanka_setup_impl(pns_ctx* c, const uint16_t* masks) {
   PNS_HIP(c, launch_element_matrices(L0.g, c->model, u1, c->Es1, s));
   PNS_HIP(c, launch_element_matrices(L0.g, c->model, c->urep, c->Esr, s));
   // level 0: surrogate patches, all state-dependent coefficients at t_rep
-  PNS_HIP(c, launch_fine_patches<T>(L0.g, c->disc.tau, c->Esr, c->Esr, masks ? c->masks : nullptr,
+  PNS_HIP(c, launch_fine_patches<T>(L0.g, c->disc.tau, c->Esr, masks ? c->masks : nullptr,
                                     (T*)L0.inv, c->status, s));
   // coarse levels: Galerkin element matrices, exact patches
   for (int l = 1; l < c->nlev; ++l) {
@@ -225,15 +226,13 @@ int vanka_setup_impl(pns_ctx* c, const uint16_t* masks) {
       PNS_HIP(c, launch_galerkin_from_fine(L.g, c->disc.tau, c->Es0, c->Es1, L.E64, s));
     else
       PNS_HIP(c, launch_galerkin(L.g, c->lev[l - 1].E64, L.E64, s));
-    if (c->es == 4) PNS_HIP(c, launch_convert<float>(L.g.nc * kNst * kNst, L.E64, (float*)L.E, s));
+    PNS_HIP(c, launch_transpose_convert<T>(L.g.nc, L.E64, (T*)L.E, s));
     PNS_HIP(c, launch_level_patches<T>(L.g, L.E64, (T*)L.inv, c->status, s));
   }
   // coarsest level: dense operator, pinned, inverted
   Level& Lc = c->lev[c->nlev - 1];
   if (c->nlev == 1) {
     PNS_HIP(c, launch_form_fine_st(Lc.g, c->disc.tau, c->Es0, c->Es1, Lc.E64, s));
-    if (c->es == 4)
-      PNS_HIP(c, launch_convert<float>(Lc.g.nc * kNst * kNst, Lc.E64, (float*)Lc.E, s));
   }
   int st = 0;
   if (!c->has_coarse) {

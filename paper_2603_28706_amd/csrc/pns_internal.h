@@ -39,6 +39,16 @@ constexpr double kWt[2] = {0.75, 0.25};
 // Lagrange basis of the Radau nodes at the slab midpoint t = 1/2.
 constexpr double kXiMid[2] = {0.75, 0.25};
 
+// Time-diagonal form of patches K_t (x) M + tau M_t (x) J (level-0 surrogate
+// patches): M_t^{-1} K_t = V diag(lam, conj(lam)) V^{-1} with lam = 2 + i sqrt2,
+// V = [[1, 1], [1 + 2 sqrt2 i, 1 - 2 sqrt2 i]].  For a real right-hand side
+// (r0, r1) the solution is d0 = 2 Re y, d1 = 2 (Re y - 2 sqrt2 Im y) with
+// (lam M + tau J) y = z, z = (2/3 + i/(3 sqrt2)) r0 - (i/sqrt2) r1.
+constexpr double kSqrt2 = 1.41421356237309504880;
+constexpr double kLamRe = 2.0, kLamIm = kSqrt2;
+constexpr double kZr0 = 2.0 / 3.0, kZi0 = 1.0 / (3.0 * kSqrt2), kZi1 = -1.0 / kSqrt2;
+constexpr double kBackIm = 2.0 * kSqrt2;
+
 // ---------------------------------------------------------------- model
 struct Model {
   double p, delta2, nu, nu_inf, expo;  // expo = (p-2)/2
@@ -79,9 +89,13 @@ hipError_t launch_state_combine(int64_t n, const double* u0, const double* u1, d
                                 double a1, double* out, hipStream_t s);
 template <typename T>
 hipError_t launch_convert(int64_t n, const double* in, T* out, hipStream_t s);
+// level-0 surrogate patches in time-diagonal form: complex 21x21 inverses
+// (interleaved re, im; column-major), from the spatial matrices Es at t_rep
 template <typename T>
-hipError_t launch_fine_patches(const Grid& g, double tau, const double* Es_a, const double* Es_b,
-                               const uint16_t* masks, T* inv, int* status, hipStream_t s);
+hipError_t launch_fine_patches(const Grid& g, double tau, const double* Es, const uint16_t* masks,
+                               T* inv, int* status, hipStream_t s);
+template <typename T>
+hipError_t launch_transpose_convert(int64_t ncells, const double* E, T* Et, hipStream_t s);
 template <typename T>
 hipError_t launch_level_patches(const Grid& g, const double* E, T* inv, int* status,
                                 hipStream_t s);
@@ -100,6 +114,11 @@ hipError_t launch_ebe_apply(const Grid& g, const T* E, const T* x, const T* b, T
 template <typename T>
 hipError_t launch_patch_sweep(const Grid& g, const T* inv, const T* res, T* d, double omega,
                               hipStream_t s);
+template <typename T>
+hipError_t launch_patch_sweep_c(const Grid& g, const T* inv, const T* res, T* d, double omega,
+                                hipStream_t s);
+template <typename T>
+hipError_t launch_copy(int64_t n, const T* x, T* y, hipStream_t s);
 template <typename T>
 hipError_t launch_restrict(const Grid& gf, const Grid& gc, const T* rf, T* rc, hipStream_t s);
 template <typename T>

@@ -329,6 +329,129 @@ __global__ __launch_bounds__(64) void patch_kernel(Grid g, Entry entry,
   }
 }
 
+// Level-0 surrogate patch in time-diagonal form: C = lam M_K + tau J_K with
+// M_K, J_K the spatial mass and surrogate matrix restricted to the patch
+// (neighbour contributions included); one wave inverts C by complex
+// Gauss-Jordan with partial pivoting.
+template <typename T>
+__global__ __launch_bounds__(64) void patch_complex_kernel(Grid g, double tau,
+                                                           const double* __restrict__ Es,
+                                                           const uint16_t* __restrict__ masks,
+                                                           T* __restrict__ inv, int* status) {
+  __shared__ double Ar[kNs][2 * kNs + 1], Ai[kNs][2 * kNs + 1];
+  __shared__ double fr[kNs], fi[kNs];
+  __shared__ double red_v[64];
+  __shared__ int red_i[64];
+  const int64_t K = blockIdx.x;
+  const int cx = (int)(K % g.nx), cy = (int)(K / g.nx);
+  const int t = threadIdx.x;
+  const uint16_t mask = masks ? masks[K] : (uint16_t)0x1ff;
+  for (int e = t; e < kNs * kNs; e += 64) {
+    const int r = e / kNs, c = e % kNs;
+    double cr = 0.0, ci = 0.0;
+    if (dropped(mask, r) || dropped(mask, c)) {
+      cr = (r == c) ? 1.0 : 0.0;
+    } else {
+      double jv = 0.0, mv = 0.0;
+      for (int oy = -1; oy <= 1; ++oy)
+        for (int ox = -1; ox <= 1; ++ox) {
+          const int nx_ = cx + ox, ny_ = cy + oy;
+          if (nx_ < 0 || ny_ < 0 || nx_ >= g.nx || ny_ >= g.ny) continue;
+          const int rr = map_to_neighbour(r, ox, oy), cc = map_to_neighbour(c, ox, oy);
+          if (rr < 0 || cc < 0) continue;
+          const int64_t nb = (int64_t)ny_ * g.nx + nx_;
+          jv += Es[nb * (kNs * kNs) + rr * kNs + cc];
+          if (rr < 18 && cc < 18 && rr / 9 == cc / 9) mv += cell_mass(g, rr % 9, cc % 9);
+        }
+      cr = kLamRe * mv + tau * jv;
+      ci = kLamIm * mv;
+    }
+    Ar[r][c] = cr;
+    Ai[r][c] = ci;
+    Ar[r][kNs + c] = (r == c) ? 1.0 : 0.0;
+    Ai[r][kNs + c] = 0.0;
+  }
+  __syncthreads();
+  bool singular = false;
+  for (int k = 0; k < kNs; ++k) {
+    double bv = -1.0;
+    int bi = k;
+    if (t >= k && t < kNs) {
+      bv = Ar[t][k] * Ar[t][k] + Ai[t][k] * Ai[t][k];
+      bi = t;
+    }
+    red_v[t] = bv;
+    red_i[t] = bi;
+    __syncthreads();
+    for (int off = 32; off > 0; off >>= 1) {
+      if (t < off) {
+        const double ov = red_v[t + off];
+        const int oi = red_i[t + off];
+        if (ov > red_v[t] || (ov == red_v[t] && oi < red_i[t])) {
+          red_v[t] = ov;
+          red_i[t] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const int p = red_i[0];
+    const double pmax = red_v[0];
+    __syncthreads();
+    if (!(pmax > 0.0)) singular = true;
+    for (int c = t; c < 2 * kNs; c += 64) {
+      const double tr = Ar[k][c], ti = Ai[k][c];
+      Ar[k][c] = Ar[p][c];
+      Ai[k][c] = Ai[p][c];
+      Ar[p][c] = tr;
+      Ai[p][c] = ti;
+    }
+    __syncthreads();
+    double pr = Ar[k][k], pi = Ai[k][k];
+    if (singular) { pr = 1.0; pi = 0.0; }
+    const double den = pr * pr + pi * pi;
+    const double qr = pr / den, qi = -pi / den;  // 1 / pivot
+    __syncthreads();
+    for (int c = t; c < 2 * kNs; c += 64) {
+      const double ar = Ar[k][c], ai = Ai[k][c];
+      Ar[k][c] = ar * qr - ai * qi;
+      Ai[k][c] = ar * qi + ai * qr;
+    }
+    if (t < kNs) {
+      fr[t] = (t == k) ? 0.0 : Ar[t][k];
+      fi[t] = (t == k) ? 0.0 : Ai[t][k];
+    }
+    __syncthreads();
+    for (int e = t; e < kNs * 2 * kNs; e += 64) {
+      const int r = e / (2 * kNs), c = e % (2 * kNs);
+      if (r != k) {
+        const double br = Ar[k][c], bi2 = Ai[k][c];
+        Ar[r][c] -= fr[r] * br - fi[r] * bi2;
+        Ai[r][c] -= fr[r] * bi2 + fi[r] * br;
+      }
+    }
+    __syncthreads();
+  }
+  if (singular && t == 0) atomicOr(status, 1);
+  T* out = inv + K * (2 * kNs * kNs);
+  for (int e = t; e < kNs * kNs; e += 64) {
+    const int c = e / kNs, r = e % kNs;
+    const bool z = dropped(mask, r) || dropped(mask, c);
+    out[2 * e] = z ? (T)0 : (T)Ar[r][kNs + c];
+    out[2 * e + 1] = z ? (T)0 : (T)Ai[r][kNs + c];
+  }
+}
+
+template <typename T>
+__global__ void transpose_convert_kernel(int64_t ncells, const double* __restrict__ E,
+                                         T* __restrict__ Et) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ncells * kNst * kNst) return;
+  const int64_t c = i / (kNst * kNst);
+  const int e = (int)(i % (kNst * kNst));
+  const int col = e / kNst, row = e % kNst;  // output index = col*42 + row
+  Et[i] = (T)E[c * (kNst * kNst) + row * kNst + col];
+}
+
 // ---------------------------------------------------------------- Galerkin
 
 // local prolongation of child (ox,oy) of a coarse cell: fine local unknown
@@ -565,11 +688,18 @@ hipError_t launch_convert(int64_t n, const double* in, T* out, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_fine_patches(const Grid& g, double tau, const double* Es_a, const double* Es_b,
-                               const uint16_t* masks, T* inv, int* status, hipStream_t s) {
-  FineEntry e{g, tau, Es_a, Es_b};
-  hipLaunchKernelGGL((patch_kernel<T, FineEntry>), dim3((unsigned)g.nc), dim3(64), 0, s, g, e,
+hipError_t launch_fine_patches(const Grid& g, double tau, const double* Es, const uint16_t* masks,
+                               T* inv, int* status, hipStream_t s) {
+  hipLaunchKernelGGL(patch_complex_kernel<T>, dim3((unsigned)g.nc), dim3(64), 0, s, g, tau, Es,
                      masks, inv, status);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_transpose_convert(int64_t ncells, const double* E, T* Et, hipStream_t s) {
+  const int64_t n = ncells * kNst * kNst;
+  hipLaunchKernelGGL(transpose_convert_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     s, ncells, E, Et);
   return hipGetLastError();
 }
 
@@ -630,10 +760,12 @@ hipError_t coarse_invert(int64_t n, double* A, double* work, int* piv, int* stat
 
 template hipError_t launch_convert<double>(int64_t, const double*, double*, hipStream_t);
 template hipError_t launch_convert<float>(int64_t, const double*, float*, hipStream_t);
-template hipError_t launch_fine_patches<double>(const Grid&, double, const double*, const double*,
-                                                const uint16_t*, double*, int*, hipStream_t);
-template hipError_t launch_fine_patches<float>(const Grid&, double, const double*, const double*,
-                                               const uint16_t*, float*, int*, hipStream_t);
+template hipError_t launch_fine_patches<double>(const Grid&, double, const double*, const uint16_t*,
+                                                double*, int*, hipStream_t);
+template hipError_t launch_fine_patches<float>(const Grid&, double, const double*, const uint16_t*,
+                                               float*, int*, hipStream_t);
+template hipError_t launch_transpose_convert<double>(int64_t, const double*, double*, hipStream_t);
+template hipError_t launch_transpose_convert<float>(int64_t, const double*, float*, hipStream_t);
 template hipError_t launch_level_patches<double>(const Grid&, const double*, double*, int*,
                                                  hipStream_t);
 template hipError_t launch_level_patches<float>(const Grid&, const double*, float*, int*,

@@ -1,11 +1,13 @@
 // Per-iteration smoother and transfer kernels (Sec. 6.3):
-// * coarse-level operator action with Galerkin element matrices (one thread
-//   per output row, gathering the rows of the <= 4 cells that carry it:
-//   every (cell, local row) product is formed exactly once, no atomics);
+// * coarse-level operator action with Galerkin element matrices: one wave per
+//   cell, transposed (column-major) element matrices streamed with coalesced
+//   loads, four colour launches (cells of one parity class share no unknown)
+//   adding into y initialised to 0 or b;
 // * additive Vanka update d += omega sum_K R_K^T A_K^{-1} R_K res,
-//   eq. (stmg-vanka-update): one wave per patch, the stored inverse streamed
-//   column by column, four colour launches so that patches updating d at the
-//   same time share no unknown;
+//   eq. (stmg-vanka-update): the stored patch inverses streamed column by
+//   column (level 0: complex 21x21 time-diagonal form, three patches per wave;
+//   coarse levels: real 42x42, one patch per wave), four colour launches so
+//   that patches updating d at the same time share no unknown;
 // * restriction P^T and prolongation P of the nested Q2 / P1disc spaces;
 // * dense coarsest solve with the stored inverse.
 #include "pns_internal.h"
@@ -24,50 +26,35 @@ __device__ __forceinline__ int64_t gidx(const Grid& g, int cx, int cy, int l) {
   return (int64_t)mu * g.ns + g.nv + 3 * ((int64_t)cy * g.nx + cx) + (i - 18);
 }
 
-template <typename T, int MODE>
-__global__ __launch_bounds__(256) void ebe_apply_kernel(Grid g, const T* __restrict__ E,
+// one wave per cell of the colour class (px, py): lane r < 42 forms row r of
+// E_c x_c from the transposed element matrix (coalesced column loads) and adds
+// sign * row into y; cells of one class share no unknown
+template <typename T>
+__global__ __launch_bounds__(256) void ebe_color_kernel(Grid g, const T* __restrict__ Et,
                                                         const T* __restrict__ x,
-                                                        const T* __restrict__ b,
-                                                        T* __restrict__ y) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= g.nst) return;
-  const int mu = (int)(r / g.ns);
-  const int64_t s = r % g.ns;
-  const int NX = 2 * g.nx + 1;
-  int cxs[2], cys[2], ncx = 0, ncy = 0, lfix = -1, gx = 0, gy = 0, comp = 0;
-  if (s < g.nv) {
-    comp = (int)(s / g.nn);
-    const int64_t node = s % g.nn;
-    gx = (int)(node % NX);
-    gy = (int)(node / NX);
-    if ((gx & 1) == 0) {
-      if (gx / 2 - 1 >= 0) cxs[ncx++] = gx / 2 - 1;
-      if (gx / 2 < g.nx) cxs[ncx++] = gx / 2;
-    } else {
-      cxs[ncx++] = gx >> 1;
+                                                        T* __restrict__ y, T sign, int px, int py,
+                                                        int ncx, int ncy) {
+  __shared__ T xs[4][kNst];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t pid = (int64_t)blockIdx.x * 4 + w;
+  const bool active = pid < (int64_t)ncx * ncy;
+  int cx = 0, cy = 0;
+  int64_t gi = 0;
+  if (active) {
+    cx = px + 2 * (int)(pid % ncx);
+    cy = py + 2 * (int)(pid / ncx);
+    if (lane < kNst) {
+      gi = gidx(g, cx, cy, lane);
+      xs[w][lane] = x[gi];
     }
-    if ((gy & 1) == 0) {
-      if (gy / 2 - 1 >= 0) cys[ncy++] = gy / 2 - 1;
-      if (gy / 2 < g.ny) cys[ncy++] = gy / 2;
-    } else {
-      cys[ncy++] = gy >> 1;
-    }
-  } else {
-    const int64_t cell = (s - g.nv) / 3;
-    cxs[ncx++] = (int)(cell % g.nx);
-    cys[ncy++] = (int)(cell / g.nx);
-    lfix = mu * kNs + 18 + (int)((s - g.nv) % 3);
   }
+  __syncthreads();
+  if (!active || lane >= kNst) return;
+  const T* A = Et + ((int64_t)cy * g.nx + cx) * (kNst * kNst);
   T acc = 0;
-  for (int iy = 0; iy < ncy; ++iy)
-    for (int ix = 0; ix < ncx; ++ix) {
-      const int cx = cxs[ix], cy = cys[iy];
-      const int lr = lfix >= 0 ? lfix : mu * kNs + comp * 9 + (gx - 2 * cx) + 3 * (gy - 2 * cy);
-      const T* Er = E + ((int64_t)cy * g.nx + cx) * (kNst * kNst) + (int64_t)lr * kNst;
 #pragma unroll 6
-      for (int lc = 0; lc < kNst; ++lc) acc += Er[lc] * x[gidx(g, cx, cy, lc)];
-    }
-  y[r] = MODE ? b[r] - acc : acc;
+  for (int j = 0; j < kNst; ++j) acc += A[j * kNst + lane] * xs[w][j];
+  y[gi] += sign * acc;
 }
 
 // one wave per patch of the colour class (px, py)
@@ -97,6 +84,50 @@ __global__ __launch_bounds__(256) void patch_sweep_kernel(Grid g, const T* __res
 #pragma unroll 6
   for (int j = 0; j < kNst; ++j) acc += A[j * kNst + lane] * rhs[w][j];
   d[gi] += omega * acc;
+}
+
+// level-0 patches in time-diagonal form (complex 21x21 inverse): three
+// patches per wave, lane 21 p + i handles spatial unknown i of patch p
+template <typename T>
+__global__ __launch_bounds__(256) void patch_sweep_c_kernel(Grid g, const T* __restrict__ inv,
+                                                            const T* __restrict__ res,
+                                                            T* __restrict__ d, T omega, int px,
+                                                            int py, int ncx, int ncy) {
+  __shared__ T zs[4][3][2][kNs];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int p = lane / kNs, i = lane % kNs;
+  const int64_t pid = ((int64_t)blockIdx.x * 4 + w) * 3 + p;
+  const bool active = lane < 3 * kNs && pid < (int64_t)ncx * ncy;
+  int cx = 0, cy = 0;
+  int64_t g0 = 0, g1 = 0;
+  if (active) {
+    cx = px + 2 * (int)(pid % ncx);
+    cy = py + 2 * (int)(pid / ncx);
+    g0 = gidx(g, cx, cy, i);
+    g1 = gidx(g, cx, cy, kNs + i);
+    const T r0 = res[g0], r1 = res[g1];
+    zs[w][p][0][i] = (T)kZr0 * r0;
+    zs[w][p][1][i] = (T)kZi0 * r0 + (T)kZi1 * r1;
+  }
+  __syncthreads();
+  if (!active) return;
+  const T* C = inv + ((int64_t)cy * g.nx + cx) * (2 * kNs * kNs);
+  T yr = 0, yi = 0;
+#pragma unroll 7
+  for (int j = 0; j < kNs; ++j) {
+    const T cr = C[2 * (j * kNs + i)], ci = C[2 * (j * kNs + i) + 1];
+    const T zr = zs[w][p][0][j], zi = zs[w][p][1][j];
+    yr += cr * zr - ci * zi;
+    yi += cr * zi + ci * zr;
+  }
+  d[g0] += omega * (T)2 * yr;
+  d[g1] += omega * (T)2 * (yr - (T)kBackIm * yi);
+}
+
+template <typename T>
+__global__ void copy_kernel(int64_t n, const T* __restrict__ x, T* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = x[i];
 }
 
 __device__ __forceinline__ double w1d(int I, int i) {
@@ -225,15 +256,44 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
+// E: transposed element matrices (column-major per cell); mode 0: y = A x,
+// mode 1: y = b - A x
 template <typename T>
 hipError_t launch_ebe_apply(const Grid& g, const T* E, const T* x, const T* b, T* y, int mode,
                             hipStream_t s) {
   if (mode == 0)
-    hipLaunchKernelGGL((ebe_apply_kernel<T, 0>), dim3(nblk(g.nst, 256)), dim3(256), 0, s, g, E, x,
-                       b, y);
+    hipLaunchKernelGGL(fill_kernel<T>, dim3(nblk(g.nst, 256)), dim3(256), 0, s, g.nst, (T)0, y);
   else
-    hipLaunchKernelGGL((ebe_apply_kernel<T, 1>), dim3(nblk(g.nst, 256)), dim3(256), 0, s, g, E, x,
-                       b, y);
+    hipLaunchKernelGGL(copy_kernel<T>, dim3(nblk(g.nst, 256)), dim3(256), 0, s, g.nst, b, y);
+  const T sign = mode == 0 ? (T)1 : (T)-1;
+  for (int c = 0; c < 4; ++c) {
+    const int px = c & 1, py = c >> 1;
+    const int ncx = (g.nx - px + 1) / 2, ncy = (g.ny - py + 1) / 2;
+    const int64_t np = (int64_t)ncx * ncy;
+    if (np == 0) continue;
+    hipLaunchKernelGGL(ebe_color_kernel<T>, dim3(nblk(np, 4)), dim3(256), 0, s, g, E, x, y, sign,
+                       px, py, ncx, ncy);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_patch_sweep_c(const Grid& g, const T* inv, const T* res, T* d, double omega,
+                                hipStream_t s) {
+  for (int c = 0; c < 4; ++c) {
+    const int px = c & 1, py = c >> 1;
+    const int ncx = (g.nx - px + 1) / 2, ncy = (g.ny - py + 1) / 2;
+    const int64_t np = (int64_t)ncx * ncy;
+    if (np == 0) continue;
+    hipLaunchKernelGGL(patch_sweep_c_kernel<T>, dim3(nblk(np, 12)), dim3(256), 0, s, g, inv, res,
+                       d, (T)omega, px, py, ncx, ncy);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_copy(int64_t n, const T* x, T* y, hipStream_t s) {
+  hipLaunchKernelGGL(copy_kernel<T>, dim3(nblk(n, 256)), dim3(256), 0, s, n, x, y);
   return hipGetLastError();
 }
 
@@ -289,7 +349,10 @@ hipError_t launch_fill(int64_t n, T v, T* y, hipStream_t s) {
                                             hipStream_t);                                        \
   template hipError_t launch_dense_gemv<T>(int64_t, const double*, const T*, T*, const int64_t*, \
                                            int, hipStream_t);                                    \
-  template hipError_t launch_fill<T>(int64_t, T, T*, hipStream_t);
+  template hipError_t launch_fill<T>(int64_t, T, T*, hipStream_t);                               \
+  template hipError_t launch_patch_sweep_c<T>(const Grid&, const T*, const T*, T*, double,      \
+                                              hipStream_t);                                      \
+  template hipError_t launch_copy<T>(int64_t, const T*, T*, hipStream_t);
 PNS_INST(double)
 PNS_INST(float)
 #undef PNS_INST
