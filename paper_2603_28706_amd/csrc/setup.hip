@@ -575,16 +575,44 @@ __global__ void pin_kernel(int64_t n, double* A, const int64_t* pin, int npin) {
   }
 }
 
-// Gauss-Jordan, in place, partial row pivoting, one column per step.
-__global__ __launch_bounds__(1024) void gj_pivot_kernel(int64_t n, int64_t k, const double* A,
-                                                        int* piv, double* pval, int* status) {
+// Blocked Gauss-Jordan inversion, in place, partial row pivoting.
+// Panels of kGjNb columns K: (1) the panel is copied to a contiguous
+// column-major buffer P (n x kb) and eliminated column by column over all
+// rows (pivot search over the rows not yet used as pivots); (2) its row swaps
+// are applied to every other column; (3) with T = rows K of the other columns,
+// every other column is updated as A[:,C] = [0 on rows K; A[O,C]] + P T, which
+// is the block form of the Gauss-Jordan step; (4) the panel is written back.
+// At the end the columns are permuted back in reverse pivot order.
+constexpr int kGjNb = 64;
+
+__global__ void gj_panel_in_kernel(int64_t n, int64_t k0, int kb, const double* __restrict__ A,
+                                   double* __restrict__ P) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  for (int j = 0; j < kb; ++j) P[(int64_t)j * n + r] = A[r * n + k0 + j];
+}
+
+__global__ void gj_panel_out_kernel(int64_t n, int64_t k0, int kb, double* __restrict__ A,
+                                    const double* __restrict__ P) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  for (int j = 0; j < kb; ++j) A[r * n + k0 + j] = P[(int64_t)j * n + r];
+}
+
+// pivot of panel column jc (global column c = k0 + jc): search, swap the panel
+// rows c and p, scale row c; one workgroup
+__global__ __launch_bounds__(1024) void gj_panel_pivot_kernel(int64_t n, int64_t k0, int kb, int jc,
+                                                              double* __restrict__ P, int* piv,
+                                                              int* status) {
   __shared__ double bv[1024];
   __shared__ int64_t bi[1024];
   const int t = threadIdx.x;
+  const int64_t c = k0 + jc;
+  const double* col = P + (int64_t)jc * n;
   double v = -1.0;
-  int64_t idx = k;
-  for (int64_t r = k + t; r < n; r += 1024) {
-    const double a = fabs(A[r * n + k]);
+  int64_t idx = c;
+  for (int64_t r = c + t; r < n; r += 1024) {
+    const double a = fabs(col[r]);
     if (a > v) {
       v = a;
       idx = r;
@@ -600,56 +628,118 @@ __global__ __launch_bounds__(1024) void gj_pivot_kernel(int64_t n, int64_t k, co
     }
     __syncthreads();
   }
+  const int64_t p = bi[0];
+  const bool sing = !(bv[0] > 0.0);
+  const double pv = sing ? 1.0 : P[(int64_t)jc * n + p];
+  __syncthreads();
   if (t == 0) {
-    piv[k] = (int)bi[0];
-    const double p = A[bi[0] * n + k];
-    if (!(bv[0] > 0.0)) {
-      atomicOr(status, 2);
-      pval[0] = 1.0;
-    } else {
-      pval[0] = p;
+    piv[c] = (int)p;
+    if (sing) atomicOr(status, 2);
+  }
+  if (t < kb) {
+    double a = P[(int64_t)t * n + p];
+    if (p != c) P[(int64_t)t * n + p] = P[(int64_t)t * n + c];
+    P[(int64_t)t * n + c] = (t == jc) ? 1.0 / pv : a / pv;
+  }
+}
+
+// eliminate panel column jc from every other row (thread per row)
+__global__ void gj_panel_elim_kernel(int64_t n, int64_t k0, int kb, int jc, double* __restrict__ P) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = k0 + jc;
+  if (r >= n || r == c) return;
+  const double f = P[(int64_t)jc * n + r];
+  for (int j = 0; j < kb; ++j) {
+    const double pr = P[(int64_t)j * n + c];
+    if (j == jc)
+      P[(int64_t)j * n + r] = -f * pr;
+    else
+      P[(int64_t)j * n + r] -= f * pr;
+  }
+}
+
+// row swaps of the panel applied to column j (outside the panel), in order;
+// then T = rows K of that column
+__global__ void gj_rowswap_copy_kernel(int64_t n, int64_t k0, int kb, double* __restrict__ A,
+                                       const int* __restrict__ piv, double* __restrict__ T) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n || (j >= k0 && j < k0 + kb)) return;
+  for (int q = 0; q < kb; ++q) {
+    const int64_t c = k0 + q, p = piv[c];
+    if (p != c) {
+      const double a = A[c * n + j];
+      A[c * n + j] = A[p * n + j];
+      A[p * n + j] = a;
+    }
+  }
+  for (int q = 0; q < kb; ++q) T[(int64_t)q * n + j] = A[(k0 + q) * n + j];
+}
+
+// A[:,C] = [0 on rows K; A[O,C]] + P T   (64 x 64 output tile per workgroup)
+__global__ __launch_bounds__(256) void gj_update_kernel(int64_t n, int64_t k0, int kb,
+                                                        double* __restrict__ A,
+                                                        const double* __restrict__ P,
+                                                        const double* __restrict__ T) {
+  __shared__ double As[kGjNb][64 + 1];
+  __shared__ double Bs[kGjNb][64 + 1];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int64_t row0 = (int64_t)blockIdx.x * 64;
+  const int64_t m = n - kb;
+  const int64_t ccol0 = (int64_t)blockIdx.y * 64;  // in the compressed column space
+  for (int e = threadIdx.x; e < kb * 64; e += 256) {
+    const int k = e / 64, i = e % 64;
+    const int64_t r = row0 + i;
+    As[k][i] = r < n ? P[(int64_t)k * n + r] : 0.0;
+    const int64_t cc = ccol0 + i;
+    const int64_t col = cc < k0 ? cc : cc + kb;
+    Bs[k][i] = cc < m ? T[(int64_t)k * n + col] : 0.0;
+  }
+  __syncthreads();
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int k = 0; k < kb; ++k) {
+    double a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = As[k][ty * 4 + i];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = Bs[k][tx * 4 + j];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t r = row0 + ty * 4 + i;
+    if (r >= n) continue;
+    const bool inK = r >= k0 && r < k0 + kb;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t cc = ccol0 + tx * 4 + j;
+      if (cc >= m) continue;
+      const int64_t col = cc < k0 ? cc : cc + kb;
+      double* a = A + r * n + col;
+      *a = inK ? acc[i][j] : *a + acc[i][j];
     }
   }
 }
 
-__global__ void gj_swap_scale_kernel(int64_t n, int64_t k, double* A, const int* piv,
-                                     const double* pval) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  const int64_t p = piv[k];
-  const double pv = pval[0];
-  const double a = A[p * n + j];
-  if (p != k) A[p * n + j] = A[k * n + j];
-  // row k after the swap, scaled; the pivot column becomes 1/pv (in-place GJ)
-  A[k * n + j] = (j == k) ? 1.0 / pv : a / pv;
-}
-
-__global__ void gj_column_kernel(int64_t n, int64_t k, const double* A, double* colk) {
+// columns back in reverse pivot order (thread per row)
+__global__ void gj_colperm_kernel(int64_t n, double* __restrict__ A, const int* __restrict__ piv) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
-  colk[r] = (r == k) ? 0.0 : A[r * n + k];
-}
-
-__global__ void gj_eliminate_kernel(int64_t n, int64_t k, double* A, const double* colk) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t r = blockIdx.y;
-  if (j >= n || r == k) return;
-  const double f = colk[r];
-  const double akj = A[k * n + j];
-  if (j == k)
-    A[r * n + j] = -f * akj;
-  else
-    A[r * n + j] -= f * akj;
-}
-
-__global__ void gj_colswap_kernel(int64_t n, int64_t k, double* A, const int* piv) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  const int64_t p = piv[k];
-  if (p == k) return;
-  const double a = A[r * n + k];
-  A[r * n + k] = A[r * n + p];
-  A[r * n + p] = a;
+  double* row = A + r * n;
+  for (int64_t c = n - 1; c >= 0; --c) {
+    const int64_t p = piv[c];
+    if (p != c) {
+      const double a = row[c];
+      row[c] = row[p];
+      row[p] = a;
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void form_fine_st_kernel(Grid g, FineEntry e, double* __restrict__ E) {
@@ -741,20 +831,29 @@ hipError_t launch_pin(int64_t n, double* A, const int64_t* pin, int npin, hipStr
   return hipGetLastError();
 }
 
-// work: n + 1 doubles (pivot column copy, pivot value); piv: n ints
+// work: 2 * kGjNb * n doubles (panel P and row block T); piv: n ints
 hipError_t coarse_invert(int64_t n, double* A, double* work, int* piv, int* status,
                          hipStream_t s) {
-  double* colk = work;
-  double* pval = work + n;
+  double* P = work;
+  double* T = work + (int64_t)kGjNb * n;
   const unsigned nb = (unsigned)((n + 255) / 256);
-  for (int64_t k = 0; k < n; ++k) {
-    hipLaunchKernelGGL(gj_pivot_kernel, dim3(1), dim3(1024), 0, s, n, k, A, piv, pval, status);
-    hipLaunchKernelGGL(gj_swap_scale_kernel, dim3(nb), dim3(256), 0, s, n, k, A, piv, pval);
-    hipLaunchKernelGGL(gj_column_kernel, dim3(nb), dim3(256), 0, s, n, k, A, colk);
-    hipLaunchKernelGGL(gj_eliminate_kernel, dim3(nb, (unsigned)n), dim3(256), 0, s, n, k, A, colk);
+  for (int64_t k0 = 0; k0 < n; k0 += kGjNb) {
+    const int kb = (int)((n - k0) < kGjNb ? (n - k0) : kGjNb);
+    hipLaunchKernelGGL(gj_panel_in_kernel, dim3(nb), dim3(256), 0, s, n, k0, kb, A, P);
+    for (int jc = 0; jc < kb; ++jc) {
+      hipLaunchKernelGGL(gj_panel_pivot_kernel, dim3(1), dim3(1024), 0, s, n, k0, kb, jc, P, piv,
+                         status);
+      hipLaunchKernelGGL(gj_panel_elim_kernel, dim3(nb), dim3(256), 0, s, n, k0, kb, jc, P);
+    }
+    const int64_t m = n - kb;
+    if (m > 0) {
+      hipLaunchKernelGGL(gj_rowswap_copy_kernel, dim3(nb), dim3(256), 0, s, n, k0, kb, A, piv, T);
+      dim3 grid((unsigned)((n + 63) / 64), (unsigned)((m + 63) / 64));
+      hipLaunchKernelGGL(gj_update_kernel, grid, dim3(256), 0, s, n, k0, kb, A, P, T);
+    }
+    hipLaunchKernelGGL(gj_panel_out_kernel, dim3(nb), dim3(256), 0, s, n, k0, kb, A, P);
   }
-  for (int64_t k = n - 1; k >= 0; --k)
-    hipLaunchKernelGGL(gj_colswap_kernel, dim3(nb), dim3(256), 0, s, n, k, A, piv);
+  hipLaunchKernelGGL(gj_colperm_kernel, dim3(nb), dim3(256), 0, s, n, A, piv);
   return hipGetLastError();
 }
 

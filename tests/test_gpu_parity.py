@@ -283,7 +283,9 @@ def test_transfers_and_galerkin_operator():
 
 @pytest.mark.parametrize("n,levels,lin", [((16, 16), 3, pnsmg.MODIFIED_NEWTON),
                                           ((8, 12), 2, pnsmg.PICARD),
-                                          ((8, 8), 1, pnsmg.EXACT_NEWTON)])
+                                          ((8, 8), 1, pnsmg.EXACT_NEWTON),
+                                          ((16, 16), 1, pnsmg.MODIFIED_NEWTON),
+                                          ((32, 32), 2, pnsmg.MODIFIED_NEWTON)])
 def test_vcycle_fp64(n, levels, lin):
     prob = oracle_problem(n, CONFIG1, lin)
     uk = inputs.uniform(71, prob.nt * prob.nv)
