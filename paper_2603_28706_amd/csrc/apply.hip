@@ -18,8 +18,8 @@
 //   a wave never collide) for one row qy (wave-uniform); each thread contracts the nodal values along y at its row (sum
 //   factorisation), evaluates values / gradients / tangent / fluxes at its
 //   three points, and forms its share of the 9 nodal results by the transposed
-//   contractions; the temporal mass coupling is applied to nodal values first
-//   (w = K_t[mu][0] x_0 + K_t[mu][1] x_1);
+//   contractions; the temporal mass coupling K_t[mu][nu] x_nu is formed at the
+//   points from the partner lane's values (DPP lane swap);
 // * the tangent scalars (Delta^2, mu, eta, clip factor, kappa) are evaluated
 //   in FP64 in both precisions; everything else in the storage type T;
 // * shares are summed in LDS with LDS atomics (summation order inside a tile
@@ -55,9 +55,17 @@ __device__ __forceinline__ void tangent_coef(const Model& m, double a00, double 
   }
 }
 
-// value held by the partner lane (lane ^ 1): the other Radau node of the cell
-__device__ __forceinline__ float swap_pair(float v) { return __shfl_xor(v, 1); }
-__device__ __forceinline__ double swap_pair(double v) { return __shfl_xor(v, 1); }
+// value held by the partner lane (lane ^ 1): the other Radau node of the cell;
+// DPP quad permutation [1,0,3,2]
+__device__ __forceinline__ float swap_pair(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double swap_pair(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), 0xB1, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
 // One point of a Dirichlet face of the cell: value / gradient test coefficients,
 // contracted directly against the 9 nodes and added to the LDS sums.
@@ -202,11 +210,11 @@ __global__ __launch_bounds__(kThreads) void cell_apply_kernel(Grid g, Model m, d
     const T area = (T)(g.hx * g.hy);
 
     // contraction along y at row qy: f_y[ax] (values), f_d[ax] (y-derivatives)
-    T u0y[3], u0d[3], u1y[3], u1d[3], x0y[3], x0d[3], x1y[3], x1d[3], w0y[3], w1y[3];
+    T u0y[3], u0d[3], u1y[3], u1d[3], x0y[3], x0d[3], x1y[3], x1d[3];
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       u0y[ax] = u0d[ax] = u1y[ax] = u1d[ax] = (T)0;
-      x0y[ax] = x0d[ax] = x1y[ax] = x1d[ax] = w0y[ax] = w1y[ax] = (T)0;
+      x0y[ax] = x0d[ax] = x1y[ax] = x1d[ax] = (T)0;
     }
 #pragma unroll
     for (int ay = 0; ay < 3; ++ay) {
@@ -219,13 +227,10 @@ __global__ __launch_bounds__(kThreads) void cell_apply_kernel(Grid g, Model m, d
         const int ly = ly0 + ay, lx = lx0 + ax;
         const T u0 = Us[2 * mu][ly][lx], u1 = Us[2 * mu + 1][ly][lx];
         const T x0 = Xs[2 * mu][ly][lx], x1 = Xs[2 * mu + 1][ly][lx];
-        const T w0 = kself * x0 + koth * swap_pair(x0);
-        const T w1 = kself * x1 + koth * swap_pair(x1);
         u0y[ax] += bv * u0; u0d[ax] += bd * u0;
         u1y[ax] += bv * u1; u1d[ax] += bd * u1;
         x0y[ax] += bv * x0; x0d[ax] += bd * x0;
         x1y[ax] += bv * x1; x1d[ax] += bd * x1;
-        w0y[ax] += bv * w0; w1y[ax] += bv * w1;
       }
     }
     const double gyq = qy == 0 ? kGP[0] : (qy == 1 ? kGP[1] : kGP[2]);
@@ -236,7 +241,7 @@ __global__ __launch_bounds__(kThreads) void cell_apply_kernel(Grid g, Model m, d
 #pragma unroll
     for (int qx = 0; qx < 3; ++qx) {
       T U0 = 0, U1 = 0, U0x = 0, U0y = 0, U1x = 0, U1y = 0;
-      T X0 = 0, X1 = 0, X0x = 0, X0y = 0, X1x = 0, X1y = 0, W0 = 0, W1 = 0;
+      T X0 = 0, X1 = 0, X0x = 0, X0y = 0, X1x = 0, X1y = 0;
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) {
         const T bv = (T)q2v(ax, kGP[qx]), bd = (T)q2d(ax, kGP[qx]);
@@ -244,8 +249,10 @@ __global__ __launch_bounds__(kThreads) void cell_apply_kernel(Grid g, Model m, d
         U1 += bv * u1y[ax]; U1x += bd * u1y[ax]; U1y += bv * u1d[ax];
         X0 += bv * x0y[ax]; X0x += bd * x0y[ax]; X0y += bv * x0d[ax];
         X1 += bv * x1y[ax]; X1x += bd * x1y[ax]; X1y += bv * x1d[ax];
-        W0 += bv * w0y[ax]; W1 += bv * w1y[ax];
       }
+      // temporal mass coupling at the point: w = K_t[mu][mu] x_mu + K_t[mu][other] x_other
+      const T W0 = kself * X0 + koth * swap_pair(X0);
+      const T W1 = kself * X1 + koth * swap_pair(X1);
       U0x *= ihx; U1x *= ihx; X0x *= ihx; X1x *= ihx;
       U0y *= ihy; U1y *= ihy; X0y *= ihy; X1y *= ihy;
       const T a00 = U0x, a01 = (T)0.5 * (U0y + U1x), a11 = U1y;

@@ -228,7 +228,9 @@ __global__ void prolong_add_kernel(Grid gf, Grid gc, const T* __restrict__ dc, T
   df[r] = (T)((double)df[r] + acc);
 }
 
-// d = Ainv r~, r~ = r with the pinned entries zeroed; one wave per row
+// d = Ainv r~, r~ = r with the pinned entries zeroed; one wave per row, 16-byte
+// loads of the row (n is even, so every row starts 16-byte aligned), four
+// loads in flight
 template <typename T>
 __global__ __launch_bounds__(256) void dense_gemv_kernel(int64_t n, const double* __restrict__ Ainv,
                                                          const T* __restrict__ r, T* __restrict__ d,
@@ -237,11 +239,31 @@ __global__ __launch_bounds__(256) void dense_gemv_kernel(int64_t n, const double
   const int lane = threadIdx.x & 63;
   if (row >= n) return;
   const double* A = Ainv + row * n;
-  double acc = 0.0;
-  for (int64_t j = lane; j < n; j += 64) {
-    const double rv = (j == pin0 || j == pin1) ? 0.0 : (double)r[j];
-    acc += A[j] * rv;
+  double acc0 = 0.0, acc1 = 0.0;
+  const int64_t npair = n >> 1;
+  int64_t q = lane;
+  for (; q + 192 < npair; q += 256) {
+    double2 a[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] = reinterpret_cast<const double2*>(A)[q + 64 * u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t j = 2 * (q + 64 * u);
+      const double r0 = (j == pin0 || j == pin1) ? 0.0 : (double)r[j];
+      const double r1 = (j + 1 == pin0 || j + 1 == pin1) ? 0.0 : (double)r[j + 1];
+      acc0 += a[u].x * r0;
+      acc1 += a[u].y * r1;
+    }
   }
+  for (; q < npair; q += 64) {
+    const double2 a = reinterpret_cast<const double2*>(A)[q];
+    const int64_t j = 2 * q;
+    const double r0 = (j == pin0 || j == pin1) ? 0.0 : (double)r[j];
+    const double r1 = (j + 1 == pin0 || j + 1 == pin1) ? 0.0 : (double)r[j + 1];
+    acc0 += a.x * r0;
+    acc1 += a.y * r1;
+  }
+  double acc = acc0 + acc1;
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
   if (lane == 0) d[row] = (T)acc;
 }
@@ -327,6 +349,7 @@ hipError_t launch_prolong_add(const Grid& gf, const Grid& gc, const T* dc, T* df
 template <typename T>
 hipError_t launch_dense_gemv(int64_t n, const double* Ainv, const T* r, T* d, const int64_t* pin,
                              int npin, hipStream_t s) {
+  if (n & 1) return hipErrorInvalidValue;  // space-time sizes are 2 * ns: rows 16-byte aligned
   const int64_t p0 = npin > 0 ? pin[0] : -1, p1 = npin > 1 ? pin[1] : -1;
   hipLaunchKernelGGL(dense_gemv_kernel<T>, dim3(nblk(n, 4)), dim3(256), 0, s, n, Ainv, r, d, p0,
                      p1);
