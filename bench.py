@@ -80,7 +80,7 @@ def run(args):
         levels = 1 if args.apply_only else args.levels
         ctx = pnsmg.Context(n, n_levels=levels, precision=prec, tau=0.01, device="cuda:0")
         sz = ctx.sizes(0)
-        ctx.pns_set_state(dict(MODEL, lin=pnsmg.MODIFIED_NEWTON), uk)
+        ctx.pns_set_state(dict(MODEL, lin=args.lin), uk)
         x = torch.tensor(inputs.uniform(202, sz["nst"]), dtype=ctx.dtype, device=dev)
         r = torch.tensor(inputs.uniform(203, sz["nst"]), dtype=ctx.dtype, device=dev)
         y = ctx.vector()
@@ -150,6 +150,7 @@ def main():
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--apply-only", action="store_true")
+    ap.add_argument("--lin", type=int, default=2, help="0 Picard, 1 exact Newton, 2 modified Newton")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
