@@ -116,23 +116,30 @@ def run(args):
         wall = time.perf_counter() - t0
         t_apply = np.array([e[0].elapsed_time(e[1]) for e in evs]) * 1e-3
         t_vc = np.array([e[1].elapsed_time(e[2]) for e in evs]) * 1e-3
-        # a dense run of back-to-back applies for the kernel average
+        # dense runs of back-to-back applies for the kernel average, both apply modes
         n_rep = max(50, args.steps)
-        ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ea.record(stream)
-        for _ in range(n_rep):
+        t_rep = {}
+        for mode in (pnsmg.APPLY_RECOMPUTE, pnsmg.APPLY_CACHED):
+            ctx.pns_set_apply_mode(mode)
             ctx.pns_cell_apply(x, y)
-        eb.record(stream)
-        torch.cuda.synchronize()
-        t_apply_rep = ea.elapsed_time(eb) * 1e-3 / n_rep
+            ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ea.record(stream)
+            for _ in range(n_rep):
+                ctx.pns_cell_apply(x, y)
+            eb.record(stream)
+            torch.cuda.synchronize()
+            t_rep[mode] = ea.elapsed_time(eb) * 1e-3 / n_rep
+        t_apply_rep = t_rep[pnsmg.APPLY_CACHED]
         elem = 8 if prec == pnsmg.FP64 else 4
         results[name] = dict(
             nst=sz["nst"], wall_s=wall, ms_per_step=wall / args.steps * 1e3,
             apply_s_median=float(np.median(t_apply)), apply_s_p10=float(np.percentile(t_apply, 10)),
             apply_s_p90=float(np.percentile(t_apply, 90)), apply_s_backtoback=t_apply_rep,
+            apply_s_recompute=t_rep[pnsmg.APPLY_RECOMPUTE],
             vcycle_s_median=float(np.median(t_vc)) if not args.apply_only else None,
             setup_s=t_setup, bytes=algorithmic_bytes(sz, elem))
-        print(f"[bench] {name}: apply {t_apply_rep * 1e6:.1f} us back-to-back, "
+        print(f"[bench] {name}: apply {t_apply_rep * 1e6:.1f} us back-to-back (recompute "
+              f"{t_rep[pnsmg.APPLY_RECOMPUTE] * 1e6:.1f} us), "
               f"median in step {np.median(t_apply) * 1e6:.1f} us; V-cycle "
               f"{(np.median(t_vc) * 1e3) if not args.apply_only else 0:.3f} ms",
               file=sys.stderr, flush=True)
@@ -187,6 +194,8 @@ def main():
         "apply_us_fp32": round(f32["apply_s_median"] * 1e6, 3),
         "apply_us_back_to_back_fp64_fp32": [round(f64["apply_s_backtoback"] * 1e6, 3),
                                             round(f32["apply_s_backtoback"] * 1e6, 3)],
+        "apply_us_recompute_tangent_fp64_fp32": [round(f64["apply_s_recompute"] * 1e6, 3),
+                                                 round(f32["apply_s_recompute"] * 1e6, 3)],
         "apply_us_in_step_p10_p50_p90_fp64": [round(f64[k] * 1e6, 2) for k in
                                               ("apply_s_p10", "apply_s_median", "apply_s_p90")],
         "vcycle_s_fp64": f64["vcycle_s_median"],

@@ -59,6 +59,15 @@ typedef enum {
 
 typedef enum { PNS_FP64 = 0, PNS_FP32 = 1 } pns_precision;
 
+/* How the level-0 action obtains the constitutive tangent at each quadrature
+ * point (same operator, same FP64 tangent arithmetic; only where it happens):
+ *   RECOMPUTE: from u_k inside every action (nothing stored);
+ *   CACHED: once per pns_set_state, six coefficients per point and Radau node
+ *   (eta, the rank-one direction scaled by sqrt(-kappa), the advecting
+ *   velocity, all times the quadrature weight) stored in the workspace in the
+ *   context precision and read by every action. */
+typedef enum { PNS_APPLY_RECOMPUTE = 0, PNS_APPLY_CACHED = 1 } pns_apply_mode;
+
 /* Box [lo, hi] with n_cells[k] uniform cells per direction; dim must be 2. */
 typedef struct {
   int dim;
@@ -127,6 +136,10 @@ int pns_bind_workspace(pns_ctx* ctx, void* ws_dev, size_t bytes);
  * Radau nodes, 2 blocks of d*(2n_x+1)(2n_y+1) values in the canonical
  * velocity layout.  Copies it into the workspace.  Invalidates the smoother. */
 int pns_set_state(pns_ctx* ctx, const pns_model* model, const double* u_k_dev);
+
+/* Select the apply mode (default PNS_APPLY_CACHED).  Switching to CACHED
+ * after pns_set_state builds the cache from the current state. */
+int pns_set_apply_mode(pns_ctx* ctx, int mode);
 
 /* y = J_n(u_k) x on level 0, eq. (slab-underint-jac): the temporal mass
  * coupling K_t (x) M_x plus tau M_t (x) diag(J_1, J_2), each J_mu the spatial

@@ -61,7 +61,9 @@ struct pns_ctx {
   double* gjwork = nullptr;
   int* gjpiv = nullptr;
   int64_t pin[2] = {-1, -1};
-  bool has_coarse = false;  // the coarsest level is small enough for a dense inverse
+  bool has_coarse = false;
+  int apply_mode = PNS_APPLY_CACHED;
+  void* tcache = nullptr;  // per-point tangent coefficients of level 0  // the coarsest level is small enough for a dense inverse
 };
 
 namespace {
@@ -97,6 +99,7 @@ size_t layout(pns_ctx* c, bool bind) {
   c->Es1 = (double*)take(g0.nc * kNs * kNs * 8);
   c->Esr = (double*)take(g0.nc * kNs * kNs * 8);
   c->masks = (uint16_t*)take(g0.nc * sizeof(uint16_t));
+  c->tcache = take(g0.nc * 18 * 6 * es);
   c->status = (int*)take(sizeof(int) * 4);
   for (int l = 0; l < c->nlev; ++l) {
     Level& L = c->lev[l];
@@ -145,10 +148,16 @@ int ctx_code(pns_ctx* c, bool need_state, bool need_smoother) {
 }
 
 template <typename T>
+const T* tangent_cache(pns_ctx* c) {
+  return c->apply_mode == PNS_APPLY_CACHED ? (const T*)c->tcache : nullptr;
+}
+
+template <typename T>
 hipError_t defect(pns_ctx* c, int l, const T* b, const T* x, T* y) {
   Level& L = c->lev[l];
   if (l == 0)
-    return launch_cell_apply<T>(L.g, c->model, c->disc.tau, (const T*)c->uk, x, b, y, 1, c->stream);
+    return launch_cell_apply<T>(L.g, c->model, c->disc.tau, (const T*)c->uk, tangent_cache<T>(c),
+                                x, b, y, 1, c->stream);
   return launch_ebe_apply<T>(L.g, (const T*)L.E, x, b, y, 1, c->stream);
 }
 
@@ -156,9 +165,18 @@ template <typename T>
 hipError_t apply_level(pns_ctx* c, int l, const T* x, T* y) {
   Level& L = c->lev[l];
   if (l == 0)
-    return launch_cell_apply<T>(L.g, c->model, c->disc.tau, (const T*)c->uk, x, x, y, 0,
-                                c->stream);
+    return launch_cell_apply<T>(L.g, c->model, c->disc.tau, (const T*)c->uk, tangent_cache<T>(c),
+                                x, x, y, 0, c->stream);
   return launch_ebe_apply<T>(L.g, (const T*)L.E, x, x, y, 0, c->stream);
+}
+
+hipError_t build_tangent_cache(pns_ctx* c) {
+  const Grid& g0 = c->lev[0].g;
+  if (c->es == 8)
+    return launch_tangent_cache<double>(g0, c->model, c->disc.tau, c->uk64, (double*)c->tcache,
+                                        c->stream);
+  return launch_tangent_cache<float>(g0, c->model, c->disc.tau, c->uk64, (float*)c->tcache,
+                                     c->stream);
 }
 
 template <typename T>
@@ -366,8 +384,19 @@ int pns_set_state(pns_ctx* ctx, const pns_model* md, const double* u_k) {
     PNS_HIP(ctx, launch_convert<float>(2 * g0.nv, ctx->uk64, (float*)ctx->uk, s));
   PNS_HIP(ctx, launch_state_combine(g0.nv, ctx->uk64, ctx->uk64 + g0.nv, kXiMid[0], kXiMid[1],
                                     ctx->urep, s));
+  if (ctx->apply_mode == PNS_APPLY_CACHED) PNS_HIP(ctx, build_tangent_cache(ctx));
   ctx->has_state = true;
   ctx->has_smoother = false;
+  return PNS_OK;
+}
+
+int pns_set_apply_mode(pns_ctx* ctx, int mode) {
+  if (!ctx) return PNS_EINVAL;
+  if (mode != PNS_APPLY_RECOMPUTE && mode != PNS_APPLY_CACHED)
+    return fail(ctx, PNS_EINVAL, "unknown apply mode");
+  const bool rebuild = mode == PNS_APPLY_CACHED && ctx->apply_mode != mode && ctx->has_state;
+  ctx->apply_mode = mode;
+  if (rebuild) PNS_HIP(ctx, build_tangent_cache(ctx));
   return PNS_OK;
 }
 

@@ -6,24 +6,30 @@
 // Nitsche terms of eq. def-b-gam).
 //
 // Design (gfx950, wave64):
-// * one workgroup per tile of TX x TY owned cells; it also evaluates the
-//   one-cell halo on the low x / low y side, so every node it owns receives all
-//   of its cell contributions inside the workgroup and each output is written
-//   exactly once (no global atomics, no zero fill);
+// * one workgroup of 256 threads per tile of TX x TY owned cells; it also
+//   evaluates the one-cell halo on the low x / low y side, so every node it
+//   owns receives all of its volume contributions inside the workgroup and each
+//   output is written exactly once (no zero fill); tiles are dealt to the XCDs
+//   in contiguous runs;
 // * the tile's nodal values of x and u_k (both Radau nodes) are staged in LDS
 //   with coalesced row loads;
-// * three threads per (cell, Radau node mu), one per row qy of the 3x3 Gauss
-//   points; a wave holds the two Radau nodes of the 32 cells of one parity
-//   class of the tile (cells of one class share no node, so the LDS atomics of
-//   a wave never collide) for one row qy (wave-uniform); each thread contracts the nodal values along y at its row (sum
-//   factorisation), evaluates values / gradients / tangent / fluxes at its
-//   three points, and forms its share of the 9 nodal results by the transposed
-//   contractions; the temporal mass coupling K_t[mu][nu] x_nu is formed at the
-//   points from the partner lane's values (DPP lane swap);
+// * one thread per (cell, Radau node mu); a wave holds the two Radau nodes of
+//   the 32 cells of one parity class of the tile (cells of one class share no
+//   node, so the LDS atomics of a wave never collide); for each row qy of the
+//   3x3 Gauss points a thread contracts the nodal values along y (sum
+//   factorisation), evaluates values / gradients / tangent at the three points
+//   of the row, and forms the row's share of the 9 nodal results by the
+//   transposed contractions; the temporal mass coupling K_t[mu][nu] x_nu is
+//   formed at the points from the partner lane's values (DPP lane swap);
 // * the tangent scalars (Delta^2, mu, eta, clip factor, kappa) are evaluated
 //   in FP64 in both precisions; everything else in the storage type T;
-// * shares are summed in LDS with LDS atomics (summation order inside a tile
-//   is not fixed), then the owned nodes are written coalesced.
+// * velocity shares are summed in LDS with LDS atomics (summation order inside
+//   a tile is not fixed); the pressure rows of a cell are complete in its
+//   thread and stored to LDS;
+// * the boundary-face terms run in a phase of their own after a barrier, one
+//   thread per face point of the tile (only tiles at the boundary), which keeps
+//   their registers out of the volume part: three workgroups share a CU;
+// * the owned nodes and cells are written coalesced from LDS.
 #include "pns_internal.h"
 
 namespace pns {
@@ -31,9 +37,17 @@ namespace {
 
 constexpr int TX = 15, TY = 7;            // owned cells per tile
 constexpr int HX = TX + 1, HY = TY + 1;   // evaluated cells (with low-side halo)
-constexpr int BX = 2 * TX + 4, BY = 2 * TY + 3;  // LDS node box (x padded to 34)
+constexpr int BX = 2 * HX + 1, BY = 2 * HY + 1;  // LDS node box
 constexpr int kCells = HX * HY;           // 128
-constexpr int kThreads = 6 * kCells;      // 768: (cell, mu, qy)
+constexpr int kThreads = 2 * kCells;      // 256: (cell, mu)
+// Waves per SIMD the register allocation must allow: several workgroups share
+// a CU, so the staging, compute and write-out phases of different tiles
+// overlap.  3 (<= 168 VGPRs) fits without spills except for the FP64 variant
+// that recomputes the tangent, which gets 2.
+template <typename T, bool CACHED>
+constexpr int waves_per_simd() {
+  return (sizeof(T) == 8 && !CACHED) ? 2 : 3;
+}
 
 // FP64 elementary functions for the tangent scalars, specialised to the
 // arguments that occur here (finite, positive, normal D2; |exponent argument|
@@ -127,6 +141,20 @@ __device__ __forceinline__ void tangent_coef(const Model& m, double a00, double 
   }
 }
 
+// 1D basis values / derivatives at the Gauss point qy of a wave-uniform row
+template <typename T>
+__device__ __forceinline__ T row_sel(int qy, double a, double b, double c) {
+  return qy == 0 ? (T)a : (qy == 1 ? (T)b : (T)c);
+}
+template <typename T>
+__device__ __forceinline__ T row_v(int qy, int a) {
+  return row_sel<T>(qy, q2v(a, kGP[0]), q2v(a, kGP[1]), q2v(a, kGP[2]));
+}
+template <typename T>
+__device__ __forceinline__ T row_d(int qy, int a) {
+  return row_sel<T>(qy, q2d(a, kGP[0]), q2d(a, kGP[1]), q2d(a, kGP[2]));
+}
+
 // value held by the partner lane (lane ^ 1): the other Radau node of the cell;
 // DPP quad permutation [1,0,3,2]
 __device__ __forceinline__ float swap_pair(float v) {
@@ -139,59 +167,84 @@ __device__ __forceinline__ double swap_pair(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// One point of a Dirichlet face of the cell: value / gradient test coefficients,
-// contracted directly against the 9 nodes and added to the LDS sums.
+// One point q of a Dirichlet boundary face of a cell (the whole boundary of the
+// rectangle is Dirichlet): convective boundary flux, the consistency / symmetry
+// terms with the tangent and the pressure, the lagged inflow term and the two
+// penalties (eq. def-b-gam).  The test coefficients are contracted against the
+// 9 nodes of the cell and added to the tile's LDS sums (velocity: acc, at the
+// cell's node box offset lx0 / ly0; pressure: pa, or nothing for pa == nullptr).
 template <typename T, int LIN, bool CONV>
-__device__ __forceinline__ void face_point(const Model& m, const Grid& g, T sfac, int side, int q,
-                                        const T (*Xs)[BY][BX], const T (*Us)[BY][BX], int mu,
-                                        int lx0, int ly0, T p0, T p1, T p2,
-                                        double (*acc)[BY][BX], double* pacc) {
+__device__ __forceinline__ void face_point(const Model& m, const Grid& g, double tau, int side,
+                                           int q, int mu, int cx, int cy, const T (*Xs)[BY][BX],
+                                           int lx0, int ly0, const T* __restrict__ uk,
+                                           const T* __restrict__ x, double (*acc)[BY][BX],
+                                           double* pa) {
   // side: 0 x=0 (n=-e_x), 1 x=1 (n=+e_x), 2 y=0 (n=-e_y), 3 y=1 (n=+e_y)
   const bool xface = side < 2;
   const double nxv = xface ? (side == 0 ? -1.0 : 1.0) : 0.0;
   const double nyv = xface ? 0.0 : (side == 2 ? -1.0 : 1.0);
-  const double hF = xface ? g.hx : g.hy;
-  const double flen = xface ? g.hy : g.hx;
-  const double xi = xface ? (side == 0 ? 0.0 : 1.0) : kGP[q];
-  const double et = xface ? kGP[q] : (side == 2 ? 0.0 : 1.0);
+  // per-lane q, mu: selects instead of indexed constant tables
+  const double gq = q == 0 ? kGP[0] : (q == 1 ? kGP[1] : kGP[2]);
+  const double wq = q == 0 ? kGW[0] : (q == 1 ? kGW[1] : kGW[2]);
+  const double xi = xface ? (side == 0 ? 0.0 : 1.0) : gq;
+  const double et = xface ? gq : (side == 2 ? 0.0 : 1.0);
+  const double ihF = xface ? g.ihx : g.ihy;  // 1 / h_F, h_F the cell size normal to the face
   const T etaD = (T)m.etaD;
-  const T pen1 = (T)(m.gamma1 * m.etaD / hF);
-  const T pen2 = (T)(m.gamma2 / hF);
+  const T pen1 = (T)(m.gamma1 * m.etaD * ihF);
+  const T pen2 = (T)(m.gamma2 * ihF);
   const T n0 = (T)nxv, n1 = (T)nyv;
+  const int NX = 2 * g.nx + 1;
+  const T* um = uk + (int64_t)mu * g.nv;
+  const int64_t cell = (int64_t)cy * g.nx + cx;
   T vx[3], vy[3], dx[3], dy[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     vx[a] = (T)q2v(a, xi);
     vy[a] = (T)q2v(a, et);
-    dx[a] = (T)(q2d(a, xi) / g.hx);
-    dy[a] = (T)(q2d(a, et) / g.hy);
+    dx[a] = (T)(q2d(a, xi) * g.ihx);
+    dy[a] = (T)(q2d(a, et) * g.ihy);
   }
+  // u_k first and the tangent from it, then x: keeps the loads in flight (and
+  // their registers) to one field at a time
   T U[2] = {0, 0}, GU[2][2] = {{0, 0}, {0, 0}}, X[2] = {0, 0}, GX[2][2] = {{0, 0}, {0, 0}};
 #pragma unroll
   for (int ay = 0; ay < 3; ++ay)
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       const T ph = vx[ax] * vy[ay], px = dx[ax] * vy[ay], py = vx[ax] * dy[ay];
-      const T u0 = Us[2 * mu][ly0 + ay][lx0 + ax], u1 = Us[2 * mu + 1][ly0 + ay][lx0 + ax];
-      const T x0 = Xs[2 * mu][ly0 + ay][lx0 + ax], x1 = Xs[2 * mu + 1][ly0 + ay][lx0 + ax];
+      const int64_t gn = (int64_t)(2 * cy + ay) * NX + (2 * cx + ax);
+      const T u0 = um[gn], u1 = um[g.nn + gn];
       U[0] += u0 * ph; U[1] += u1 * ph;
       GU[0][0] += u0 * px; GU[0][1] += u0 * py;
       GU[1][0] += u1 * px; GU[1][1] += u1 * py;
+    }
+  const T a00 = GU[0][0], a01 = (T)0.5 * (GU[0][1] + GU[1][0]), a11 = GU[1][1];
+  double eta_d, kap_d;
+  tangent_coef<LIN>(m, (double)a00, (double)a01, (double)a11, eta_d, kap_d);
+  const T eta = (T)eta_d, kap = (T)kap_d;
+  // zero offset that the compiler must take as depending on the tangent
+  int lofs = 0;
+  asm volatile("" : "+v"(lofs) : "v"(kap_d));
+#pragma unroll
+  for (int ay = 0; ay < 3; ++ay)
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const T ph = vx[ax] * vy[ay], px = dx[ax] * vy[ay], py = vx[ax] * dy[ay];
+      const T x0 = Xs[2 * mu][ly0 + ay][lx0 + ax + lofs];
+      const T x1 = Xs[2 * mu + 1][ly0 + ay][lx0 + ax + lofs];
       X[0] += x0 * ph; X[1] += x1 * ph;
       GX[0][0] += x0 * px; GX[0][1] += x0 * py;
       GX[1][0] += x1 * px; GX[1][1] += x1 * py;
     }
-  const T xp = p0 + p1 * (T)(xi - 0.5) + p2 * (T)(et - 0.5);
-  const T a00 = GU[0][0], a01 = (T)0.5 * (GU[0][1] + GU[1][0]), a11 = GU[1][1];
+  const T* pv = x + (int64_t)mu * g.ns + g.nv + 3 * cell;
+  const T xp = pv[0] + pv[1] * (T)(xi - 0.5) + pv[2] * (T)(et - 0.5);
   const T b00 = GX[0][0], b01 = (T)0.5 * (GX[0][1] + GX[1][0]), b11 = GX[1][1];
-  double eta_d, kap_d;
-  tangent_coef<LIN>(m, (double)a00, (double)a01, (double)a11, eta_d, kap_d);
-  const T eta = (T)eta_d, kap = (T)kap_d;
   const T ab = a00 * b00 + (T)2 * a01 * b01 + a11 * b11;
   const T T00 = eta * b00 + kap * ab * a00;
   const T T01 = eta * b01 + kap * ab * a01;
   const T T11 = eta * b11 + kap * ab * a11;
-  const T sW = sfac * (T)(kGW[q] * flen);
+  // tau w_mu times the face quadrature weight
+  const T sW = (T)(tau * (mu ? kWt[1] : kWt[0]) * wq * (xface ? g.hy : g.hx));
   const T un = U[0] * n0 + U[1] * n1;
   const T xn = X[0] * n0 + X[1] * n1;
   T F0 = -(T00 * n0 + T01 * n1) + xp * n0 + pen1 * X[0] + pen2 * xn * n0;
@@ -219,30 +272,83 @@ __device__ __forceinline__ void face_point(const Model& m, const Grid& g, T sfac
       atomicAdd(&acc[2 * mu][ly0 + ay][lx0 + ax], (double)(F0 * ph + G00 * px + G01 * py));
       atomicAdd(&acc[2 * mu + 1][ly0 + ay][lx0 + ax], (double)(F1 * ph + G10 * px + G11 * py));
     }
-  const T P = sW * (T)m.qsign * xn;
-  atomicAdd(&pacc[0], (double)P);
-  atomicAdd(&pacc[1], (double)(P * (T)(xi - 0.5)));
-  atomicAdd(&pacc[2], (double)(P * (T)(et - 0.5)));
+  if (pa) {
+    const T P = sW * (T)m.qsign * xn;
+    atomicAdd(&pa[0], (double)P);
+    atomicAdd(&pa[1], (double)(P * (T)(xi - 0.5)));
+    atomicAdd(&pa[2], (double)(P * (T)(et - 0.5)));
+  }
 }
 
-template <typename T, int LIN, bool CONV, int MODE>
-__global__ __launch_bounds__(kThreads) void cell_apply_kernel(Grid g, Model m, double tau,
+// Per-point coefficients of the volume term, cached once per linearisation
+// state (index ((cell*2 + mu)*9 + qy*3 + qx)*6):
+//   c0 = sW eta,  (c1, c2, c3) = sqrt(-sW kappa) (A00, A01, A11),  (c4, c5) = sW u,
+// with sW = tau w_mu W_q, so that sW T(B) = c0 B - (a':B) a' (kappa <= 0 for
+// p <= 2) and the convective flux uses sW u directly.  Tangent scalars in FP64.
+constexpr int kCacheVals = 6;
+
+template <typename T, int LIN>
+__global__ __launch_bounds__(256) void tangent_cache_kernel(Grid g, Model m, double tau,
+                                                            const double* __restrict__ uk,
+                                                            T* __restrict__ cache) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= g.nc * 18) return;
+  const int q = (int)(id % 9);
+  const int mu = (int)((id / 9) % 2);
+  const int64_t cell = id / 18;
+  const int cx = (int)(cell % g.nx), cy = (int)(cell / g.nx);
+  const int qx = q % 3, qy = q / 3;
+  const double* um = uk + (int64_t)mu * g.nv;
+  const int NX = 2 * g.nx + 1;
+  double U0 = 0, U1 = 0, g00 = 0, g01 = 0, g10 = 0, g11 = 0;
+  for (int a = 0; a < 9; ++a) {
+    const int ax = a % 3, ay = a / 3;
+    const int64_t gn = (int64_t)(2 * cy + ay) * NX + (2 * cx + ax);
+    const double u0 = um[gn], u1 = um[g.nn + gn];
+    const double ph = q2v(ax, kGP[qx]) * q2v(ay, kGP[qy]);
+    const double px = q2d(ax, kGP[qx]) / g.hx * q2v(ay, kGP[qy]);
+    const double py = q2v(ax, kGP[qx]) * q2d(ay, kGP[qy]) / g.hy;
+    U0 += u0 * ph; U1 += u1 * ph;
+    g00 += u0 * px; g01 += u0 * py; g10 += u1 * px; g11 += u1 * py;
+  }
+  const double a00 = g00, a01 = 0.5 * (g01 + g10), a11 = g11;
+  double eta, kap;
+  tangent_coef<LIN>(m, a00, a01, a11, eta, kap);
+  const double sW = tau * kWt[mu] * kGW[qx] * kGW[qy] * g.hx * g.hy;
+  const double sk = sqrt(fmax(-sW * kap, 0.0));
+  T* c = cache + id * kCacheVals;
+  c[0] = (T)(sW * eta);
+  c[1] = (T)(sk * a00);
+  c[2] = (T)(sk * a01);
+  c[3] = (T)(sk * a11);
+  c[4] = (T)(sW * U0);
+  c[5] = (T)(sW * U1);
+}
+
+template <typename T, int LIN, bool CONV, int MODE, bool CACHED>
+__global__ __launch_bounds__(kThreads, (waves_per_simd<T, CACHED>())) void cell_apply_kernel(Grid g, Model m, double tau,
                                                               const T* __restrict__ uk,
+                                                              const T* __restrict__ cache,
                                                               const T* __restrict__ x,
                                                               const T* __restrict__ b,
                                                               T* __restrict__ y, int tiles_x) {
-  __shared__ T Xs[4][BY][BX];   // x: [mu*2 + comp]
-  __shared__ T Us[4][BY][BX];   // u_k: [mu*2 + comp]
-  __shared__ double acc[4][BY][BX];  // results: [mu*2 + comp]
-  __shared__ double pacc[2][kCells][3];
-  const int tile = blockIdx.x;
+  __shared__ T Xs[4][BY][BX];                  // x: [mu*2 + comp]
+  __shared__ T Us[CACHED ? 1 : 4][BY][BX];     // u_k: [mu*2 + comp] (recomputing variant)
+  __shared__ double acc[4][BY][BX];            // velocity results: [mu*2 + comp]
+  __shared__ double pacc[2][kCells][3];        // pressure results: [mu][cell][j]
+  // Workgroups are dealt round-robin to the 8 XCDs: give each XCD a contiguous
+  // run of tiles, so that neighbouring tiles (shared halo nodes, shared cache
+  // lines at the tile edges) meet in the same L2.
+  const int nb = gridDim.x, bq = nb >> 3, br = nb & 7;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int tile = xcd * bq + (xcd < br ? xcd : br) + slot;
   const int cx0 = (tile % tiles_x) * TX;
   const int cy0 = (tile / tiles_x) * TY;
   const int t = threadIdx.x;
   const int NX = 2 * g.nx + 1;
   const int gx0 = 2 * (cx0 - 1), gy0 = 2 * (cy0 - 1);
 
-  // stage x and u_k of the node box, zero the sums
+  // stage x (and u_k) of the node box, zero the sums
   for (int i = t; i < 4 * BY * BX; i += kThreads) {
     const int f = i / (BY * BX), r = i % (BY * BX);
     const int ly = r / BX, lx = r % BX;
@@ -251,154 +357,204 @@ __global__ __launch_bounds__(kThreads) void cell_apply_kernel(Grid g, Model m, d
     if (gx >= 0 && gy >= 0 && gx <= 2 * g.nx && gy <= 2 * g.ny) {
       const int64_t gn = (int64_t)gy * NX + gx;
       xv = x[(int64_t)(f >> 1) * g.ns + (int64_t)(f & 1) * g.nn + gn];
-      uv = uk[(int64_t)(f >> 1) * g.nv + (int64_t)(f & 1) * g.nn + gn];
+      if (!CACHED) uv = uk[(int64_t)(f >> 1) * g.nv + (int64_t)(f & 1) * g.nn + gn];
     }
     Xs[f][ly][lx] = xv;
-    Us[f][ly][lx] = uv;
+    if (!CACHED) Us[f][ly][lx] = uv;
     acc[f][ly][lx] = 0.0;
   }
-  for (int i = t; i < 2 * kCells * 3; i += kThreads) (&pacc[0][0][0])[i] = 0.0;
   __syncthreads();
 
-  // wave w: row qy = w / 4, parity class w % 4; lane: (cell of the class, mu)
-  const int qy = __builtin_amdgcn_readfirstlane(t >> 8);
-  const int color = (t >> 6) & 3, lane = t & 63;
+  // wave = parity class (cells of one class share no node); lane = (cell, mu)
+  const int color = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
   const int mu = lane & 1, k = lane >> 1;
   const int hx = 2 * (k % (HX / 2)) + (color & 1), hy = 2 * (k / (HX / 2)) + (color >> 1);
-  const int lc = hy * HX + hx;
   const int cx = cx0 - 1 + hx, cy = cy0 - 1 + hy;
   const bool valid = cx >= 0 && cy >= 0 && cx < g.nx && cy < g.ny;
   const int lx0 = 2 * hx, ly0 = 2 * hy;
 
   // every lane takes part in the pair exchange below, valid or not
   {
-    const int other = 1 - mu;
-    const T kself = (T)kKt[mu][mu], koth = (T)kKt[mu][other];
+    const T kself = (T)(mu ? kKt[1][1] : kKt[0][0]), koth = (T)(mu ? kKt[1][0] : kKt[0][1]);
     const int64_t cell = (int64_t)(valid ? cy : 0) * g.nx + (valid ? cx : 0);
     const T* xm = x + (int64_t)mu * g.ns + g.nv + 3 * cell;
-    T pp[3] = {xm[0], xm[1], xm[2]};
-    const T sfac = (T)(tau * kWt[mu]);
-    const T ihx = (T)(1.0 / g.hx), ihy = (T)(1.0 / g.hy);
+    const T pp[3] = {xm[0], xm[1], xm[2]};
+    const T sfac = (T)(tau * (mu ? kWt[1] : kWt[0]));
+    const T ihx = (T)g.ihx, ihy = (T)g.ihy;
     const T area = (T)(g.hx * g.hy);
+    T op[3] = {0, 0, 0};  // pressure results of this (cell, mu)
 
-    // contraction along y at row qy: f_y[ax] (values), f_d[ax] (y-derivatives)
-    T u0y[3], u0d[3], u1y[3], u1d[3], x0y[3], x0d[3], x1y[3], x1d[3];
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      u0y[ax] = u0d[ax] = u1y[ax] = u1d[ax] = (T)0;
-      x0y[ax] = x0d[ax] = x1y[ax] = x1d[ax] = (T)0;
-    }
-#pragma unroll
-    for (int ay = 0; ay < 3; ++ay) {
-      T bv, bd;
-      // row-dependent 1D basis at the Gauss point qy (select, not a table load)
-      bv = qy == 0 ? (T)q2v(ay, kGP[0]) : (qy == 1 ? (T)q2v(ay, kGP[1]) : (T)q2v(ay, kGP[2]));
-      bd = qy == 0 ? (T)q2d(ay, kGP[0]) : (qy == 1 ? (T)q2d(ay, kGP[1]) : (T)q2d(ay, kGP[2]));
+#pragma unroll 1
+    for (int qy = 0; qy < 3; ++qy) {
+      const T* cq = cache + ((cell * 2 + mu) * 9 + qy * 3) * kCacheVals;
+      // contraction along y at row qy: f_y[ax] (values), f_d[ax] (y-derivatives)
+      T u0y[3], u0d[3], u1y[3], u1d[3], x0y[3], x0d[3], x1y[3], x1d[3];
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) {
-        const int ly = ly0 + ay, lx = lx0 + ax;
-        const T u0 = Us[2 * mu][ly][lx], u1 = Us[2 * mu + 1][ly][lx];
-        const T x0 = Xs[2 * mu][ly][lx], x1 = Xs[2 * mu + 1][ly][lx];
-        u0y[ax] += bv * u0; u0d[ax] += bd * u0;
-        u1y[ax] += bv * u1; u1d[ax] += bd * u1;
-        x0y[ax] += bv * x0; x0d[ax] += bd * x0;
-        x1y[ax] += bv * x1; x1d[ax] += bd * x1;
+        u0y[ax] = u0d[ax] = u1y[ax] = u1d[ax] = (T)0;
+        x0y[ax] = x0d[ax] = x1y[ax] = x1d[ax] = (T)0;
       }
-    }
-    const double gyq = qy == 0 ? kGP[0] : (qy == 1 ? kGP[1] : kGP[2]);
-    const double gwy = qy == 0 ? kGW[0] : (qy == 1 ? kGW[1] : kGW[2]);
-    // per-point coefficients of the tests phi (A*), d/dx phi (B*), d/dy phi (C*)
-    T S1a[3] = {0, 0, 0}, S2a[3] = {0, 0, 0}, S1b[3] = {0, 0, 0}, S2b[3] = {0, 0, 0};
-    T op[3] = {0, 0, 0};
+      // the node values are the same for every row; reloading them from LDS per
+      // row (an opaque zero offset keeps the loads inside the loop) is cheaper
+      // than holding all of them in registers across the rows
+      int lofs = 0;
+      asm volatile("" : "+v"(lofs));
 #pragma unroll
-    for (int qx = 0; qx < 3; ++qx) {
-      T U0 = 0, U1 = 0, U0x = 0, U0y = 0, U1x = 0, U1y = 0;
-      T X0 = 0, X1 = 0, X0x = 0, X0y = 0, X1x = 0, X1y = 0;
+      for (int ay = 0; ay < 3; ++ay) {
+        const T bv = row_v<T>(qy, ay), bd = row_d<T>(qy, ay);
 #pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        const T bv = (T)q2v(ax, kGP[qx]), bd = (T)q2d(ax, kGP[qx]);
-        U0 += bv * u0y[ax]; U0x += bd * u0y[ax]; U0y += bv * u0d[ax];
-        U1 += bv * u1y[ax]; U1x += bd * u1y[ax]; U1y += bv * u1d[ax];
-        X0 += bv * x0y[ax]; X0x += bd * x0y[ax]; X0y += bv * x0d[ax];
-        X1 += bv * x1y[ax]; X1x += bd * x1y[ax]; X1y += bv * x1d[ax];
-      }
-      // temporal mass coupling at the point: w = K_t[mu][mu] x_mu + K_t[mu][other] x_other
-      const T W0 = kself * X0 + koth * swap_pair(X0);
-      const T W1 = kself * X1 + koth * swap_pair(X1);
-      U0x *= ihx; U1x *= ihx; X0x *= ihx; X1x *= ihx;
-      U0y *= ihy; U1y *= ihy; X0y *= ihy; X1y *= ihy;
-      const T a00 = U0x, a01 = (T)0.5 * (U0y + U1x), a11 = U1y;
-      const T b00 = X0x, b01 = (T)0.5 * (X0y + X1x), b11 = X1y;
-      double eta_d, kap_d;
-      tangent_coef<LIN>(m, (double)a00, (double)a01, (double)a11, eta_d, kap_d);
-      const T eta = (T)eta_d, kap = (T)kap_d;
-      const T ab = a00 * b00 + (T)2 * a01 * b01 + a11 * b11;
-      const T xp = pp[0] + pp[1] * (T)(kGP[qx] - 0.5) + pp[2] * (T)(gyq - 0.5);
-      T G00 = eta * b00 + kap * ab * a00 - xp;
-      T G01 = eta * b01 + kap * ab * a01;
-      T G10 = G01;
-      T G11 = eta * b11 + kap * ab * a11 - xp;
-      if (CONV) {
-        G00 -= X0 * U0;
-        G01 -= X0 * U1;
-        G10 -= X1 * U0;
-        G11 -= X1 * U1;
-        if (LIN != PNS_PICARD) {
-          G00 -= U0 * X0;
-          G01 -= U0 * X1;
-          G10 -= U1 * X0;
-          G11 -= U1 * X1;
+        for (int ax = 0; ax < 3; ++ax) {
+          const int ly = ly0 + ay, lx = lx0 + ax + lofs;
+          const T x0 = Xs[2 * mu][ly][lx], x1 = Xs[2 * mu + 1][ly][lx];
+          x0y[ax] += bv * x0; x0d[ax] += bd * x0;
+          x1y[ax] += bv * x1; x1d[ax] += bd * x1;
+          if (!CACHED) {
+            const T u0 = Us[2 * mu][ly][lx], u1 = Us[2 * mu + 1][ly][lx];
+            u0y[ax] += bv * u0; u0d[ax] += bd * u0;
+            u1y[ax] += bv * u1; u1d[ax] += bd * u1;
+          }
         }
       }
-      const T W = area * (T)(kGW[qx] * gwy);
-      const T sW = sfac * W;
-      G00 *= sW * ihx; G10 *= sW * ihx;
-      G01 *= sW * ihy; G11 *= sW * ihy;
-      const T V0 = W * W0, V1 = W * W1;
-      const T P = -sW * (X0x + X1y);
-      op[0] += P;
-      op[1] += P * (T)(kGP[qx] - 0.5);
-      op[2] += P * (T)(gyq - 0.5);
+      const T gyq = row_sel<T>(qy, kGP[0] - 0.5, kGP[1] - 0.5, kGP[2] - 0.5);
+      const T gwy = row_sel<T>(qy, kGW[0], kGW[1], kGW[2]);
+      // per-point coefficients of the tests phi (S1 value / x-derivative, S2 y-derivative)
+      T S1a[3] = {0, 0, 0}, S2a[3] = {0, 0, 0}, S1b[3] = {0, 0, 0}, S2b[3] = {0, 0, 0};
 #pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        const T bv = (T)q2v(ax, kGP[qx]), bd = (T)q2d(ax, kGP[qx]);
-        S1a[ax] += bv * V0 + bd * G00;
-        S2a[ax] += bv * G01;
-        S1b[ax] += bv * V1 + bd * G10;
-        S2b[ax] += bv * G11;
+      for (int qx = 0; qx < 3; ++qx) {
+        T X0 = 0, X1 = 0, X0x = 0, X0y = 0, X1x = 0, X1y = 0;
+        T U0 = 0, U1 = 0, U0x = 0, U0y = 0, U1x = 0, U1y = 0;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          const T bv = (T)q2v(ax, kGP[qx]), bd = (T)q2d(ax, kGP[qx]);
+          X0 += bv * x0y[ax]; X0x += bd * x0y[ax]; X0y += bv * x0d[ax];
+          X1 += bv * x1y[ax]; X1x += bd * x1y[ax]; X1y += bv * x1d[ax];
+          if (!CACHED) {
+            U0 += bv * u0y[ax]; U0x += bd * u0y[ax]; U0y += bv * u0d[ax];
+            U1 += bv * u1y[ax]; U1x += bd * u1y[ax]; U1y += bv * u1d[ax];
+          }
+        }
+        // temporal mass coupling at the point: w = K_t[mu][mu] x_mu + K_t[mu][other] x_other
+        const T W0 = kself * X0 + koth * swap_pair(X0);
+        const T W1 = kself * X1 + koth * swap_pair(X1);
+        X0x *= ihx; X1x *= ihx;
+        X0y *= ihy; X1y *= ihy;
+        const T b00 = X0x, b01 = (T)0.5 * (X0y + X1x), b11 = X1y;
+        const T W = area * (T)kGW[qx] * gwy;
+        const T sW = sfac * W;
+        const T xp = pp[0] + pp[1] * (T)(kGP[qx] - 0.5) + pp[2] * gyq;
+        T G00, G01, G10, G11;  // sW * (T(B) - convective flux - xp I)
+        if (CACHED) {
+          const T c0 = cq[qx * kCacheVals + 0], c1 = cq[qx * kCacheVals + 1];
+          const T c2 = cq[qx * kCacheVals + 2], c3 = cq[qx * kCacheVals + 3];
+          const T c4 = cq[qx * kCacheVals + 4], c5 = cq[qx * kCacheVals + 5];
+          const T ab = c1 * b00 + (T)2 * c2 * b01 + c3 * b11;
+          const T sxp = sW * xp;
+          G00 = c0 * b00 - ab * c1 - sxp;
+          G01 = c0 * b01 - ab * c2;
+          G10 = G01;
+          G11 = c0 * b11 - ab * c3 - sxp;
+          if (CONV) {
+            G00 -= X0 * c4;
+            G01 -= X0 * c5;
+            G10 -= X1 * c4;
+            G11 -= X1 * c5;
+            if (LIN != PNS_PICARD) {
+              G00 -= c4 * X0;
+              G01 -= c4 * X1;
+              G10 -= c5 * X0;
+              G11 -= c5 * X1;
+            }
+          }
+        } else {
+          U0x *= ihx; U1x *= ihx;
+          U0y *= ihy; U1y *= ihy;
+          const T a00 = U0x, a01 = (T)0.5 * (U0y + U1x), a11 = U1y;
+          double eta_d, kap_d;
+          tangent_coef<LIN>(m, (double)a00, (double)a01, (double)a11, eta_d, kap_d);
+          const T eta = (T)eta_d, kap = (T)kap_d;
+          const T ab = a00 * b00 + (T)2 * a01 * b01 + a11 * b11;
+          G00 = eta * b00 + kap * ab * a00 - xp;
+          G01 = eta * b01 + kap * ab * a01;
+          G10 = G01;
+          G11 = eta * b11 + kap * ab * a11 - xp;
+          if (CONV) {
+            G00 -= X0 * U0;
+            G01 -= X0 * U1;
+            G10 -= X1 * U0;
+            G11 -= X1 * U1;
+            if (LIN != PNS_PICARD) {
+              G00 -= U0 * X0;
+              G01 -= U0 * X1;
+              G10 -= U1 * X0;
+              G11 -= U1 * X1;
+            }
+          }
+          G00 *= sW; G01 *= sW; G10 *= sW; G11 *= sW;
+        }
+        G00 *= ihx; G10 *= ihx;
+        G01 *= ihy; G11 *= ihy;
+        const T V0 = W * W0, V1 = W * W1;
+        const T P = -sW * (X0x + X1y);
+        op[0] += P;
+        op[1] += P * (T)(kGP[qx] - 0.5);
+        op[2] += P * gyq;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          const T bv = (T)q2v(ax, kGP[qx]), bd = (T)q2d(ax, kGP[qx]);
+          S1a[ax] += bv * V0 + bd * G00;
+          S2a[ax] += bv * G01;
+          S1b[ax] += bv * V1 + bd * G10;
+          S2b[ax] += bv * G11;
+        }
+      }
+      // this row's share of the nodal results: B[qy][ay] S1[ax] + D[qy][ay] S2[ax]
+      if (valid) {
+#pragma unroll
+        for (int ay = 0; ay < 3; ++ay) {
+          const T bv = row_v<T>(qy, ay), bd = row_d<T>(qy, ay);
+#pragma unroll
+          for (int ax = 0; ax < 3; ++ax) {
+            atomicAdd(&acc[2 * mu][ly0 + ay][lx0 + ax], (double)(bv * S1a[ax] + bd * S2a[ax]));
+            atomicAdd(&acc[2 * mu + 1][ly0 + ay][lx0 + ax], (double)(bv * S1b[ax] + bd * S2b[ax]));
+          }
+        }
       }
     }
     if (valid) {
-      // this row's share of the nodal results: B[qy][ay] S1[ax] + D[qy][ay] S2[ax]
+      // every volume contribution to the pressure rows of the cell is in this thread
+      const int lc = hy * HX + hx;
 #pragma unroll
-      for (int ay = 0; ay < 3; ++ay) {
-        const T bv = qy == 0 ? (T)q2v(ay, kGP[0]) : (qy == 1 ? (T)q2v(ay, kGP[1]) : (T)q2v(ay, kGP[2]));
-        const T bd = qy == 0 ? (T)q2d(ay, kGP[0]) : (qy == 1 ? (T)q2d(ay, kGP[1]) : (T)q2d(ay, kGP[2]));
-#pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-          atomicAdd(&acc[2 * mu][ly0 + ay][lx0 + ax], (double)(bv * S1a[ax] + bd * S2a[ax]));
-          atomicAdd(&acc[2 * mu + 1][ly0 + ay][lx0 + ax], (double)(bv * S1b[ax] + bd * S2b[ax]));
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < 3; ++j) atomicAdd(&pacc[mu][lc][j], (double)op[j]);
-      // Dirichlet faces (the whole boundary): point qy of each boundary face
-      if (cx == 0)
-        face_point<T, LIN, CONV>(m, g, sfac, 0, qy, Xs, Us, mu, lx0, ly0, pp[0], pp[1], pp[2],
-                                 acc, pacc[mu][lc]);
-      if (cx == g.nx - 1)
-        face_point<T, LIN, CONV>(m, g, sfac, 1, qy, Xs, Us, mu, lx0, ly0, pp[0], pp[1], pp[2],
-                                 acc, pacc[mu][lc]);
-      if (cy == 0)
-        face_point<T, LIN, CONV>(m, g, sfac, 2, qy, Xs, Us, mu, lx0, ly0, pp[0], pp[1], pp[2],
-                                 acc, pacc[mu][lc]);
-      if (cy == g.ny - 1)
-        face_point<T, LIN, CONV>(m, g, sfac, 3, qy, Xs, Us, mu, lx0, ly0, pp[0], pp[1], pp[2],
-                                 acc, pacc[mu][lc]);
+      for (int j = 0; j < 3; ++j) pacc[mu][lc][j] = (double)op[j];
     }
   }
   __syncthreads();
-  // pressure rows of owned cells
+
+  // Boundary faces of the evaluated cells, in a phase of their own (one thread
+  // per face point), so that their registers do not add to the volume part's.
+  // Only tiles at the boundary of the rectangle have any.
+  if (cx0 == 0 || cy0 == 0 || cx0 + TX >= g.nx || cy0 + TY >= g.ny) {
+    for (int p = t; p < 4 * HX * 6; p += kThreads) {
+      const int side = p / (HX * 6), r = p % (HX * 6);
+      const int j = r / 6, q = (r >> 1) % 3, fmu = r & 1;
+      int fhx, fhy;
+      if (side < 2) {
+        fhx = (side == 0 ? 0 : g.nx - 1) - cx0 + 1;
+        fhy = j;
+      } else {
+        fhx = j;
+        fhy = (side == 2 ? 0 : g.ny - 1) - cy0 + 1;
+      }
+      const int fcx = cx0 - 1 + fhx, fcy = cy0 - 1 + fhy;
+      if (fhx < 0 || fhx >= HX || fhy < 0 || fhy >= HY || fcx < 0 || fcy < 0 || fcx >= g.nx ||
+          fcy >= g.ny)
+        continue;
+      face_point<T, LIN, CONV>(m, g, tau, side, q, fmu, fcx, fcy, Xs, 2 * fhx, 2 * fhy, uk, x,
+                               acc, (fhx >= 1 && fhy >= 1) ? pacc[fmu][fhy * HX + fhx] : nullptr);
+    }
+    __syncthreads();
+  }
+
+  // pressure rows of the owned cells
   for (int i = t; i < 2 * kCells * 3; i += kThreads) {
     const int pmu = i / (kCells * 3), r = i % (kCells * 3);
     const int c = r / 3, j = r % 3;
@@ -409,57 +565,89 @@ __global__ __launch_bounds__(kThreads) void cell_apply_kernel(Grid g, Model m, d
       y[idx] = MODE ? (T)((double)b[idx] - v) : (T)v;
     }
   }
-  // owned velocity nodes
+  // owned velocity nodes: rows of at most 2 TX + 1 nodes, in a 32-wide frame
   const int gx_end = (cx0 + TX >= g.nx) ? 2 * g.nx + 1 : 2 * (cx0 + TX);
   const int gy_end = (cy0 + TY >= g.ny) ? 2 * g.ny + 1 : 2 * (cy0 + TY);
   const int nox = gx_end - 2 * cx0, noy = gy_end - 2 * cy0;
-  for (int i = t; i < 4 * nox * noy; i += kThreads) {
-    const int s = i / (nox * noy), r = i % (nox * noy);
-    const int ox = r % nox, oy = r / nox;
-    const int64_t gn = (int64_t)(2 * cy0 + oy) * NX + (2 * cx0 + ox);
-    const int64_t idx = (int64_t)(s >> 1) * g.ns + (int64_t)(s & 1) * g.nn + gn;
-    const double v = acc[s][oy + 2][ox + 2];
-    y[idx] = MODE ? (T)((double)b[idx] - v) : (T)v;
+  for (int i = t; i < 4 * (2 * TY + 1) * 32; i += kThreads) {
+    const int s = i / ((2 * TY + 1) * 32), r = i % ((2 * TY + 1) * 32);
+    const int ox = r % 32, oy = r / 32;
+    if (ox < nox && oy < noy) {
+      const int64_t gn = (int64_t)(2 * cy0 + oy) * NX + (2 * cx0 + ox);
+      const int64_t idx = (int64_t)(s >> 1) * g.ns + (int64_t)(s & 1) * g.nn + gn;
+      const double v = acc[s][oy + 2][ox + 2];
+      y[idx] = MODE ? (T)((double)b[idx] - v) : (T)v;
+    }
   }
 }
 
-template <typename T, int LIN, bool CONV>
-hipError_t launch3(const Grid& g, const Model& m, double tau, const T* uk, const T* x, const T* b,
-                   T* y, int mode, hipStream_t s) {
+template <typename T, int LIN, bool CONV, bool CACHED>
+hipError_t launch4(const Grid& g, const Model& m, double tau, const T* uk, const T* cache,
+                   const T* x, const T* b, T* y, int mode, hipStream_t s) {
   const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY;
   dim3 grid(tx * ty), block(kThreads);
   if (mode == 0)
-    hipLaunchKernelGGL((cell_apply_kernel<T, LIN, CONV, 0>), grid, block, 0, s, g, m, tau, uk, x, b,
-                       y, tx);
+    hipLaunchKernelGGL((cell_apply_kernel<T, LIN, CONV, 0, CACHED>), grid, block, 0, s, g, m, tau,
+                       uk, cache, x, b, y, tx);
   else
-    hipLaunchKernelGGL((cell_apply_kernel<T, LIN, CONV, 1>), grid, block, 0, s, g, m, tau, uk, x, b,
-                       y, tx);
+    hipLaunchKernelGGL((cell_apply_kernel<T, LIN, CONV, 1, CACHED>), grid, block, 0, s, g, m, tau,
+                       uk, cache, x, b, y, tx);
   return hipGetLastError();
 }
 
 template <typename T, int LIN>
-hipError_t launch2(const Grid& g, const Model& m, double tau, const T* uk, const T* x, const T* b,
-                   T* y, int mode, hipStream_t s) {
-  return m.convection ? launch3<T, LIN, true>(g, m, tau, uk, x, b, y, mode, s)
-                      : launch3<T, LIN, false>(g, m, tau, uk, x, b, y, mode, s);
+hipError_t launch2(const Grid& g, const Model& m, double tau, const T* uk, const T* cache,
+                   const T* x, const T* b, T* y, int mode, hipStream_t s) {
+  if (cache)
+    return m.convection ? launch4<T, LIN, true, true>(g, m, tau, uk, cache, x, b, y, mode, s)
+                        : launch4<T, LIN, false, true>(g, m, tau, uk, cache, x, b, y, mode, s);
+  return m.convection ? launch4<T, LIN, true, false>(g, m, tau, uk, cache, x, b, y, mode, s)
+                      : launch4<T, LIN, false, false>(g, m, tau, uk, cache, x, b, y, mode, s);
 }
 
 }  // namespace
 
 template <typename T>
-hipError_t launch_cell_apply(const Grid& g, const Model& m, double tau, const T* uk, const T* x,
-                             const T* b, T* y, int mode, hipStream_t s) {
+hipError_t launch_cell_apply(const Grid& g, const Model& m, double tau, const T* uk, const T* cache,
+                             const T* x, const T* b, T* y, int mode, hipStream_t s) {
   switch (m.lin) {
-    case PNS_PICARD: return launch2<T, PNS_PICARD>(g, m, tau, uk, x, b, y, mode, s);
-    case PNS_EXACT_NEWTON: return launch2<T, PNS_EXACT_NEWTON>(g, m, tau, uk, x, b, y, mode, s);
-    default: return launch2<T, PNS_MODIFIED_NEWTON>(g, m, tau, uk, x, b, y, mode, s);
+    case PNS_PICARD: return launch2<T, PNS_PICARD>(g, m, tau, uk, cache, x, b, y, mode, s);
+    case PNS_EXACT_NEWTON:
+      return launch2<T, PNS_EXACT_NEWTON>(g, m, tau, uk, cache, x, b, y, mode, s);
+    default: return launch2<T, PNS_MODIFIED_NEWTON>(g, m, tau, uk, cache, x, b, y, mode, s);
   }
 }
 
+template <typename T>
+hipError_t launch_tangent_cache(const Grid& g, const Model& m, double tau, const double* uk,
+                                T* cache, hipStream_t s) {
+  const int64_t n = g.nc * 18;
+  const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+  switch (m.lin) {
+    case PNS_PICARD:
+      hipLaunchKernelGGL((tangent_cache_kernel<T, PNS_PICARD>), grid, block, 0, s, g, m, tau, uk,
+                         cache);
+      break;
+    case PNS_EXACT_NEWTON:
+      hipLaunchKernelGGL((tangent_cache_kernel<T, PNS_EXACT_NEWTON>), grid, block, 0, s, g, m, tau,
+                         uk, cache);
+      break;
+    default:
+      hipLaunchKernelGGL((tangent_cache_kernel<T, PNS_MODIFIED_NEWTON>), grid, block, 0, s, g, m,
+                         tau, uk, cache);
+  }
+  return hipGetLastError();
+}
+
 template hipError_t launch_cell_apply<double>(const Grid&, const Model&, double, const double*,
-                                              const double*, const double*, double*, int,
-                                              hipStream_t);
+                                              const double*, const double*, const double*, double*,
+                                              int, hipStream_t);
 template hipError_t launch_cell_apply<float>(const Grid&, const Model&, double, const float*,
-                                             const float*, const float*, float*, int, hipStream_t);
+                                             const float*, const float*, const float*, float*, int,
+                                             hipStream_t);
+template hipError_t launch_tangent_cache<double>(const Grid&, const Model&, double, const double*,
+                                                 double*, hipStream_t);
+template hipError_t launch_tangent_cache<float>(const Grid&, const Model&, double, const double*,
+                                                float*, hipStream_t);
 
 }  // namespace pns

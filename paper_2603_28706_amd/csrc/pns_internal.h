@@ -58,7 +58,7 @@ struct Model {
 
 struct Grid {
   int nx, ny;
-  double hx, hy;
+  double hx, hy, ihx, ihy;
   int64_t nn, nc, nv, ns, nst;  // nodes, cells, velocity, spatial, space-time
 };
 
@@ -68,6 +68,8 @@ inline Grid make_grid(int nx, int ny, double lx, double ly) {
   g.ny = ny;
   g.hx = lx / nx;
   g.hy = ly / ny;
+  g.ihx = nx / lx;
+  g.ihy = ny / ly;
   g.nn = (int64_t)(2 * nx + 1) * (2 * ny + 1);
   g.nc = (int64_t)nx * ny;
   g.nv = 2 * g.nn;
@@ -77,10 +79,15 @@ inline Grid make_grid(int nx, int ny, double lx, double ly) {
 }
 
 // ---------------------------------------------------------------- launchers
-// apply.hip: matrix-free level-0 operator; mode 0: y = J x, mode 1: y = b - J x
+// apply.hip: matrix-free level-0 operator; mode 0: y = J x, mode 1: y = b - J x;
+// cache == nullptr: tangent recomputed from u_k at every point, else the
+// per-point coefficients written by launch_tangent_cache are read
 template <typename T>
-hipError_t launch_cell_apply(const Grid& g, const Model& m, double tau, const T* uk, const T* x,
-                             const T* b, T* y, int mode, hipStream_t s);
+hipError_t launch_cell_apply(const Grid& g, const Model& m, double tau, const T* uk, const T* cache,
+                             const T* x, const T* b, T* y, int mode, hipStream_t s);
+template <typename T>
+hipError_t launch_tangent_cache(const Grid& g, const Model& m, double tau, const double* uk,
+                                T* cache, hipStream_t s);
 
 // setup.hip
 hipError_t launch_element_matrices(const Grid& g, const Model& m, const double* u, double* Es,

@@ -21,6 +21,7 @@ PNS_OK, PNS_EINVAL, PNS_EWORKSPACE, PNS_EHIP, PNS_ESTATE, PNS_ESINGULAR, PNS_EUN
     0, -1, -2, -3, -4, -5, -6)
 PICARD, EXACT_NEWTON, MODIFIED_NEWTON = 0, 1, 2
 FP64, FP32 = 0, 1
+APPLY_RECOMPUTE, APPLY_CACHED = 0, 1
 
 
 class PnsError(RuntimeError):
@@ -77,6 +78,7 @@ def lib():
         L.pns_bind_workspace.argtypes = [_vp, _vp, ctypes.c_size_t]
         L.pns_set_state.argtypes = [_vp, pp(pns_model), _vp]
         L.pns_cell_apply.argtypes = [_vp, _vp, _vp]
+        L.pns_set_apply_mode.argtypes = [_vp, i]
         L.pns_cell_defect.argtypes = [_vp, _vp, _vp, _vp]
         L.pns_vanka_setup.argtypes = [_vp, _vp]
         L.pns_vanka_smooth.argtypes = [_vp, i, i, ctypes.c_double, _vp, _vp]
@@ -85,6 +87,7 @@ def lib():
         L.pns_restrict.argtypes = [_vp, i, _vp, _vp]
         L.pns_prolongate_add.argtypes = [_vp, i, _vp, _vp]
         for f in ("pns_ctx_create", "pns_level_sizes", "pns_bind_workspace", "pns_set_state",
+                  "pns_set_apply_mode",
                   "pns_cell_apply", "pns_cell_defect", "pns_vanka_setup", "pns_vanka_smooth",
                   "pns_vcycle", "pns_level_apply", "pns_restrict", "pns_prolongate_add"):
             getattr(L, f).restype = ctypes.c_int
@@ -162,6 +165,9 @@ class Context:
         assert uk.numel() == 2 * self.sizes(0)["nv"]
         self._uk = uk
         self._check(lib().pns_set_state(self.h, ctypes.byref(md), _ptr(uk)))
+
+    def pns_set_apply_mode(self, mode):
+        self._check(lib().pns_set_apply_mode(self.h, int(mode)))
 
     def pns_cell_apply(self, x, y):
         self._check(lib().pns_cell_apply(self.h, self._vec(x), self._vec(y)))

@@ -49,9 +49,14 @@ def rel_blocks(got, ref, prob):
     return out
 
 
-def gpu_apply(n, model, lin, uk, x, precision, tau=0.01, hi=(1.0, 1.0), defect_b=None):
+MODES = [pnsmg.APPLY_CACHED, pnsmg.APPLY_RECOMPUTE]
+
+
+def gpu_apply(n, model, lin, uk, x, precision, tau=0.01, hi=(1.0, 1.0), defect_b=None,
+              mode=pnsmg.APPLY_CACHED):
     ctx = pnsmg.Context(n, n_levels=1, precision=precision, tau=tau, hi=hi)
     dt = ctx.dtype
+    ctx.pns_set_apply_mode(mode)
     ctx.pns_set_state(dict(model, lin=lin), to_dev(uk, torch.float64))
     xd = to_dev(x, dt)
     y = ctx.vector()
@@ -63,29 +68,31 @@ def gpu_apply(n, model, lin, uk, x, precision, tau=0.01, hi=(1.0, 1.0), defect_b
     return y.double().cpu().numpy()
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("lin", KINDS)
-def test_config1_apply_fp64(lin):
+def test_config1_apply_fp64(lin, mode):
     n = (8, 8)
     prob = oracle_problem(n, CONFIG1, lin)
     uk = inputs.uniform(101, prob.nt * prob.nv)
     x = inputs.uniform(102, prob.nst)
     ref = O.apply(prob, uk, x)
-    got = gpu_apply(n, CONFIG1, lin, uk, x, pnsmg.FP64)
+    got = gpu_apply(n, CONFIG1, lin, uk, x, pnsmg.FP64, mode=mode)
     ev, ep = rel_blocks(got, ref, prob)
-    print(f"config1 lin={lin} fp64 rel err vel={ev:.2e} pres={ep:.2e}")
+    print(f"config1 lin={lin} mode={mode} fp64 rel err vel={ev:.2e} pres={ep:.2e}")
     assert ev <= 1e-12 and ep <= 1e-12
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("lin", KINDS)
-def test_config1_apply_fp32(lin):
+def test_config1_apply_fp32(lin, mode):
     n = (8, 8)
     prob = oracle_problem(n, CONFIG1, lin)
     uk = inputs.uniform(101, prob.nt * prob.nv)
     x = inputs.uniform(102, prob.nst)
     ref = O.apply(prob, uk, x)
-    got = gpu_apply(n, CONFIG1, lin, uk, x, pnsmg.FP32)
+    got = gpu_apply(n, CONFIG1, lin, uk, x, pnsmg.FP32, mode=mode)
     ev, ep = rel_blocks(got, ref, prob)
-    print(f"config1 lin={lin} fp32 rel err vel={ev:.2e} pres={ep:.2e}")
+    print(f"config1 lin={lin} mode={mode} fp32 rel err vel={ev:.2e} pres={ep:.2e}")
     assert ev <= 1e-5 and ep <= 1e-5
 
 
@@ -100,9 +107,10 @@ def test_apply_ragged_tiles_fp64(n, hi):
         uk = inputs.uniform(7, prob.nt * prob.nv)
         x = inputs.uniform(8, prob.nst)
         ref = O.apply(prob, uk, x)
-        got = gpu_apply(n, model, lin, uk, x, pnsmg.FP64, hi=hi)
-        ev, ep = rel_blocks(got, ref, prob)
-        assert ev <= 1e-12 and ep <= 1e-12, (n, lin, ev, ep)
+        for mode in MODES:
+            got = gpu_apply(n, model, lin, uk, x, pnsmg.FP64, hi=hi, mode=mode)
+            ev, ep = rel_blocks(got, ref, prob)
+            assert ev <= 1e-12 and ep <= 1e-12, (n, lin, mode, ev, ep)
 
 
 def test_apply_variants_fp64():
@@ -110,17 +118,20 @@ def test_apply_variants_fp64():
     sigma_max = 0 and huge, nu_inf = 0."""
     n = (9, 7)
     variants = [dict(convection=0), dict(qsign=-1), dict(p=2.0), dict(sigma_max=0.0),
-                dict(sigma_max=1e300), dict(nu_inf=0.0, p=1.1, delta=1e-5)]
+                dict(sigma_max=1e300), dict(nu_inf=0.0, p=1.1, delta=1e-5),
+                dict(p=1.05, delta=1e-9, amp=1e-6), dict(p=1.9, delta=0.5, amp=30.0)]
     for v in variants:
+        amp = v.pop("amp", 1.0)
         model = dict(CONFIG1, **v)
         for lin in KINDS:
             prob = oracle_problem(n, model, lin)
-            uk = inputs.uniform(11, prob.nt * prob.nv)
+            uk = amp * inputs.uniform(11, prob.nt * prob.nv)
             x = inputs.uniform(12, prob.nst)
             ref = O.apply(prob, uk, x)
-            got = gpu_apply(n, model, lin, uk, x, pnsmg.FP64)
-            ev, ep = rel_blocks(got, ref, prob)
-            assert ev <= 1e-12 and ep <= 1e-12, (v, lin, ev, ep)
+            for mode in MODES:
+                got = gpu_apply(n, model, lin, uk, x, pnsmg.FP64, mode=mode)
+                ev, ep = rel_blocks(got, ref, prob)
+                assert ev <= 1e-12 and ep <= 1e-12, (v, lin, mode, ev, ep)
 
 
 def test_defect_mode_fp64():
@@ -156,8 +167,10 @@ def test_full_size_apply_sampled_rows():
     prob = oracle_problem(n, model, pnsmg.MODIFIED_NEWTON)
     uk = inputs.sin_series_velocity(n, seed=201, t_nodes=[0.01 / 3, 0.01])
     x = inputs.uniform(202, prob.nst)
-    for prec, tol in ((pnsmg.FP64, 1e-12), (pnsmg.FP32, 1e-5)):
-        got = gpu_apply(n, model, pnsmg.MODIFIED_NEWTON, uk, x, prec)
+    for prec, tol, mode in ((pnsmg.FP64, 1e-12, pnsmg.APPLY_CACHED),
+                            (pnsmg.FP64, 1e-12, pnsmg.APPLY_RECOMPUTE),
+                            (pnsmg.FP32, 1e-5, pnsmg.APPLY_CACHED)):
+        got = gpu_apply(n, model, pnsmg.MODIFIED_NEWTON, uk, x, prec, mode=mode)
         rng = np.random.default_rng(0)
         NX = 2 * n[0] + 1
         special_nodes = [0, NX - 1, NX * NX - 1, 30, 29, 31, 30 * NX + 30, 60 * NX + 61,
