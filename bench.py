@@ -9,19 +9,24 @@ sin-series velocity with 8 random modes plus U[-0.01, 0.01] noise (seed 201),
 input vector U[-1, 1] (seed 202).  All inputs are synthetic and resident in
 HBM before timing.
 
-One step = one Jacobian action + one V-cycle (every row of the hot path).
-Reported value: Jacobian-action throughput in GDoF/s (space-time unknowns per
-second) in FP64; FP32 figures and V-cycle seconds alongside.  Kernel time of
-the action is measured with HIP events on the stream the kernels run on.
+One step = a block of four Jacobian actions + one V-cycle (every row of the
+hot path).  Reported value: Jacobian-action throughput in GDoF/s (space-time
+unknowns per second) in FP64 with the tangent recomputed at every point
+(nothing cached), from the mean in-step duration of the action (HIP events on
+the stream the kernels run on around the block of four); FP32 figures, the cached-tangent variant and the
+V-cycle seconds alongside.  The action's roofline is the FP64 vector ALU
+(its arithmetic intensity, ~14 flop/B, is above the FP64 ridge of ~9.8 flop/B).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256]
-       [--levels 4] [--no-cpu] [--apply-only]
+       [--levels 4] [--no-cpu] [--apply-only] [--lin 2] [--calib-copy]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -30,6 +35,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Jacobian-apply GDoF/s + V-cycle s, FP64 vs FP32; p50/p99 solve latency @1e-8"
 HBM_PEAK_GBS = 8000.0
+FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 FP64 flop / clock
+# Jacobian actions per step, timed as one block: as many level-0 operator
+# evaluations as a 2 + 2 V-cycle makes (one defect per Vanka step); the block
+# also spreads the event overhead so that the per-launch mean is the kernel's
+APPLIES_PER_STEP = 4
 MODEL = dict(p=1.2, delta=1e-4, nu=1.0, nu_inf=1e-4, gamma1=40.0, gamma2=40.0, sigma_max=1.0,
              convection=1, qsign=1)
 
@@ -37,6 +47,65 @@ MODEL = dict(p=1.2, delta=1e-4, nu=1.0, nu_inf=1e-4, gamma1=40.0, gamma2=40.0, s
 def algorithmic_bytes(sizes, elem):
     """x read + y written + u_k (both Radau nodes) read, per Jacobian action."""
     return (2 * sizes["nst"] + 2 * sizes["nv"]) * elem
+
+
+# FETCH_SIZE / WRITE_SIZE of the FP64 action (mean over its in-step launches),
+# each scaled by the counter's reading for a plain streaming kernel of known
+# size, with the hash of the kernel source the counters were taken on
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "cell_apply_256x256_fp64_counters.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2603_28706_amd", "csrc", f)
+                  for f in ("apply.hip", "pns_internal.h")]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the action from the committed counter summary;
+    None if it is missing or the kernel source changed since it was taken."""
+    try:
+        with open(TRAFFIC_SUMMARY) as fh:
+            txt = fh.read()
+    except OSError:
+        return None
+    m = re.search(r"```json\n(.*?)\n```", txt, re.S)
+    if not m:
+        return None
+    d = json.loads(m.group(1))
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def tangent_flops(lin):
+    """FP64 operations of the tangent scalars at one point (FMA = 2; the
+    elementary functions at the operation counts of their evaluation:
+    log 39, exp 33, plus |A|^2 6, Delta^2 1, mu 2, eta 1; exact Newton adds
+    the reciprocal of Delta^2 and kappa (11), modified Newton also the clip
+    sigma_max / |A| and the min (13))."""
+    return {0: 82, 1: 93, 2: 106}[lin]
+
+
+def apply_flops_per_cell(lin):
+    """Algorithmic operations of the sum-factorised volume action per cell
+    (both Radau nodes; the O(N) boundary faces and the halo recomputation of
+    the tiles are not counted).  Per Radau node and Gauss row: contraction of
+    x and u_k along y (9 nodes x 8 FMA = 144), three points, the transposed
+    contraction onto the 9 nodes (2 x 9 x 2 FMA = 72) and its summation (18).
+    Per point: contraction along x (72), temporal mass coupling (6), gradient
+    scalings and symmetric parts (12), weights (3), pressure value (4),
+    tangent, rank-one part and T(B) (18 Newton / 5 Picard), convection
+    (16 Newton / 8 Picard), quadrature scalings (8), mass values (2),
+    divergence and pressure rows (7), test-coefficient sums (36)."""
+    newton = lin != 0
+    point = (72 + 6 + 12 + 3 + 4 + tangent_flops(lin) + (18 if newton else 5)
+             + (16 if newton else 8) + 8 + 2 + 7 + 36)
+    return 2 * 3 * (144 + 3 * point + 72 + 18)
 
 
 def cpu_baseline(n_sample=128, reps=2):
@@ -94,10 +163,20 @@ def run(args):
             t_setup = time.perf_counter() - t0
             print(f"[bench] {name}: smoother setup {t_setup:.2f} s", file=sys.stderr, flush=True)
 
+        if args.calib_copy:
+            # plain streaming kernel of known size (reads and writes nst values)
+            # for the calibration of the memory-traffic counters
+            scratch = torch.empty_like(x)
+            for _ in range(3):
+                torch.neg(x, out=scratch)
+            torch.cuda.synchronize()
+            del scratch
+
         def step(ev=None):
             if ev is not None:
                 ev[0].record(stream)
-            ctx.pns_cell_apply(x, y)
+            for _ in range(APPLIES_PER_STEP):
+                ctx.pns_cell_apply(x, y)
             if ev is not None:
                 ev[1].record(stream)
             if not args.apply_only:
@@ -114,33 +193,31 @@ def run(args):
             step(evs[k])
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        t_apply = np.array([e[0].elapsed_time(e[1]) for e in evs]) * 1e-3
+        t_apply = np.array([e[0].elapsed_time(e[1]) for e in evs]) * 1e-3 / APPLIES_PER_STEP
         t_vc = np.array([e[1].elapsed_time(e[2]) for e in evs]) * 1e-3
-        # dense runs of back-to-back applies for the kernel average, both apply modes
+        # back-to-back applies with the cached-tangent variant (reported alongside)
         n_rep = max(50, args.steps)
-        t_rep = {}
-        for mode in (pnsmg.APPLY_RECOMPUTE, pnsmg.APPLY_CACHED):
-            ctx.pns_set_apply_mode(mode)
+        ctx.pns_set_apply_mode(pnsmg.APPLY_CACHED)
+        ctx.pns_cell_apply(x, y)
+        ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ea.record(stream)
+        for _ in range(n_rep):
             ctx.pns_cell_apply(x, y)
-            ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            ea.record(stream)
-            for _ in range(n_rep):
-                ctx.pns_cell_apply(x, y)
-            eb.record(stream)
-            torch.cuda.synchronize()
-            t_rep[mode] = ea.elapsed_time(eb) * 1e-3 / n_rep
-        t_apply_rep = t_rep[pnsmg.APPLY_CACHED]
+        eb.record(stream)
+        torch.cuda.synchronize()
+        t_cached = ea.elapsed_time(eb) * 1e-3 / n_rep
+        ctx.pns_set_apply_mode(pnsmg.APPLY_RECOMPUTE)
         elem = 8 if prec == pnsmg.FP64 else 4
         results[name] = dict(
-            nst=sz["nst"], wall_s=wall, ms_per_step=wall / args.steps * 1e3,
-            apply_s_median=float(np.median(t_apply)), apply_s_p10=float(np.percentile(t_apply, 10)),
-            apply_s_p90=float(np.percentile(t_apply, 90)), apply_s_backtoback=t_apply_rep,
-            apply_s_recompute=t_rep[pnsmg.APPLY_RECOMPUTE],
+            nst=sz["nst"], cells=sz["cells"], wall_s=wall, ms_per_step=wall / args.steps * 1e3,
+            apply_s_mean=float(np.mean(t_apply)), apply_s_median=float(np.median(t_apply)),
+            apply_s_p10=float(np.percentile(t_apply, 10)),
+            apply_s_p90=float(np.percentile(t_apply, 90)), apply_s_cached=t_cached,
             vcycle_s_median=float(np.median(t_vc)) if not args.apply_only else None,
             setup_s=t_setup, bytes=algorithmic_bytes(sz, elem))
-        print(f"[bench] {name}: apply {t_apply_rep * 1e6:.1f} us back-to-back (recompute "
-              f"{t_rep[pnsmg.APPLY_RECOMPUTE] * 1e6:.1f} us), "
-              f"median in step {np.median(t_apply) * 1e6:.1f} us; V-cycle "
+        print(f"[bench] {name}: apply {np.mean(t_apply) * 1e6:.1f} us mean in step "
+              f"(p50 {np.median(t_apply) * 1e6:.1f}), cached tangent {t_cached * 1e6:.1f} us "
+              f"back-to-back; V-cycle "
               f"{(np.median(t_vc) * 1e3) if not args.apply_only else 0:.3f} ms",
               file=sys.stderr, flush=True)
         del ctx
@@ -157,6 +234,8 @@ def main():
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--apply-only", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run a plain streaming kernel of known size (counter calibration)")
     ap.add_argument("--lin", type=int, default=2, help="0 Picard, 1 exact Newton, 2 modified Newton")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -165,9 +244,10 @@ def main():
         sys.exit(2)
     res = run(args)
     f64, f32 = res["fp64"], res["fp32"]
-    t_ap = f64["apply_s_median"]
+    t_ap = f64["apply_s_mean"]
     value = f64["nst"] / t_ap / 1e9
-    achieved = f64["bytes"] / t_ap / 1e9
+    flops = apply_flops_per_cell(args.lin) * f64["cells"]
+    achieved = flops / t_ap / 1e12
     line = {
         "metric": METRIC,
         "value": round(value, 4),
@@ -189,22 +269,23 @@ def main():
             "levels": args.levels,
         },
         "apply_gdofs_fp64": round(value, 4),
-        "apply_gdofs_fp32": round(f32["nst"] / f32["apply_s_median"] / 1e9, 4),
-        "apply_us_fp64": round(t_ap * 1e6, 3),
-        "apply_us_fp32": round(f32["apply_s_median"] * 1e6, 3),
-        "apply_us_back_to_back_fp64_fp32": [round(f64["apply_s_backtoback"] * 1e6, 3),
-                                            round(f32["apply_s_backtoback"] * 1e6, 3)],
-        "apply_us_recompute_tangent_fp64_fp32": [round(f64["apply_s_recompute"] * 1e6, 3),
-                                                 round(f32["apply_s_recompute"] * 1e6, 3)],
-        "apply_us_in_step_p10_p50_p90_fp64": [round(f64[k] * 1e6, 2) for k in
-                                              ("apply_s_p10", "apply_s_median", "apply_s_p90")],
+        "apply_gdofs_fp32": round(f32["nst"] / f32["apply_s_mean"] / 1e9, 4),
+        "apply_us_mean_fp64_fp32": [round(t_ap * 1e6, 3), round(f32["apply_s_mean"] * 1e6, 3)],
+        "apply_us_p10_p50_p90_fp64": [round(f64[k] * 1e6, 2) for k in
+                                      ("apply_s_p10", "apply_s_median", "apply_s_p90")],
+        "apply_us_cached_tangent_fp64_fp32": [round(f64["apply_s_cached"] * 1e6, 3),
+                                              round(f32["apply_s_cached"] * 1e6, 3)],
+        "apply_hbm_gbs_fp64": round(f64["bytes"] / t_ap / 1e9, 1),
         "vcycle_s_fp64": f64["vcycle_s_median"],
         "vcycle_s_fp32": f32["vcycle_s_median"],
         "setup_s_fp64": f64["setup_s"],
         "setup_s_fp32": f32["setup_s"],
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": "cell_apply_kernel<double, modified Newton>"},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3),
+                     "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4),
+                     "traffic": measured_traffic(),
+                     "kernel": "cell_apply_kernel<double, modified Newton, recompute>",
+                     "flop_per_launch": flops, "algorithmic_bytes": f64["bytes"]},
     }
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()

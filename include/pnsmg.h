@@ -137,8 +137,9 @@ int pns_bind_workspace(pns_ctx* ctx, void* ws_dev, size_t bytes);
  * velocity layout.  Copies it into the workspace.  Invalidates the smoother. */
 int pns_set_state(pns_ctx* ctx, const pns_model* model, const double* u_k_dev);
 
-/* Select the apply mode (default PNS_APPLY_CACHED).  Switching to CACHED
- * after pns_set_state builds the cache from the current state. */
+/* Select the apply mode (default PNS_APPLY_RECOMPUTE).  Switching to CACHED
+ * after pns_set_state builds the cache from the current state; returns
+ * PNS_EINVAL for an unknown mode. */
 int pns_set_apply_mode(pns_ctx* ctx, int mode);
 
 /* y = J_n(u_k) x on level 0, eq. (slab-underint-jac): the temporal mass

@@ -62,7 +62,7 @@ struct pns_ctx {
   int* gjpiv = nullptr;
   int64_t pin[2] = {-1, -1};
   bool has_coarse = false;
-  int apply_mode = PNS_APPLY_CACHED;
+  int apply_mode = PNS_APPLY_RECOMPUTE;
   void* tcache = nullptr;  // per-point tangent coefficients of level 0  // the coarsest level is small enough for a dense inverse
 };
 
