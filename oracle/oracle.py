@@ -16,7 +16,11 @@ module adds the global pieces with numpy / scipy library primitives:
 * one additive Vanka smoothing step, eq. (stmg-vanka-update);
 * the nested Q2 / P1disc prolongation, Galerkin coarse operators
   A_l = P^T A_{l+1} P (Sec. 6.3 "Hierarchy and coarse operators") and the
-  V-cycle with a dense LU on the coarsest level.
+  V-cycle with a dense LU on the coarsest level;
+* the block mass-weighted residual norm and a plain Newton iteration on the
+  slab residual with direct (sparse LU) linear solves and Armijo backtracking
+  (Sec. 5.3 "Krylov solver and preconditioning", "Globalization and stopping
+  criteria"), which defines the solution a slab solve has to reach.
 """
 from __future__ import annotations
 
@@ -698,3 +702,89 @@ def apply_rows(prob: Problem, uk, x, rows, **kw):
                     acc += Kt[mu, nu] * float(M[a] @ x[nu * prob.ns + vidx])
         out[t] = acc
     return out
+
+
+# ------------------------------------------------------------ slab solve
+
+def assemble_pressure_mass(prob: Problem):
+    """P1disc mass in the spatial (ns x ns) layout: on a cell of size
+    h_1 x ... x h_d the basis 1, (x_k - c_k)/h_k is orthogonal, with integrals
+    |K| and |K|/12."""
+    d = prob.dim
+    diag = np.zeros(prob.ns)
+    area = float(np.prod(prob.h))
+    for c in range(prob.num_cells):
+        base = prob.nv + (d + 1) * c
+        diag[base] = area
+        diag[base + 1:base + d + 1] = area / 12.0
+    return sp.diags(diag)
+
+
+def slab_mass(prob: Problem):
+    """Block mass of the time step, velocity and pressure: the spatial masses
+    weighted by tau times the Radau weights, tau M_t (x) M (Sec. 5.3, the norm
+    of the algebraic residuals)."""
+    _, Mt, _, _ = time_matrices(prob.k_time)
+    Ms = assemble_velocity_mass(prob) + assemble_pressure_mass(prob)
+    return sp.block_diag([prob.tau * Mt[m, m] * Ms for m in range(prob.nt)]).tocsr()
+
+
+def mass_norm(prob: Problem, r, M=None):
+    """||(r_v, r_p)||_M = sqrt(r_v^T M_v r_v + r_p^T M_p r_p) (Sec. 5.3)."""
+    r = _f64(r)
+    M = slab_mass(prob) if M is None else M
+    return float(np.sqrt(r @ (M @ r)))
+
+
+def velocity_blocks(prob: Problem, U):
+    """The nt velocity blocks of a space-time vector (the linearisation state)."""
+    U = _f64(U)
+    return [U[m * prob.ns:m * prob.ns + prob.nv].copy() for m in range(prob.nt)]
+
+
+@dataclass
+class NewtonResult:
+    U: np.ndarray
+    residual_norms: list
+    steps: list
+
+
+def newton_solve(prob: Problem, vprev, U0=None, rtol=1e-8, atol=0.0, max_it=30, c_armijo=1e-4,
+                 max_backtrack=30):
+    """Newton iteration on R_n(U) = 0, eq. (nk-newton-lin): J_n(U^m) dU = R_n(U^m)
+    with J_n the slab linearisation of prob.lin, solved directly (sparse LU, with
+    the constant pressure coefficient of cell 0 pinned per time node: with
+    Dirichlet data on the whole boundary the constant pressure of each time
+    node spans the kernel), then U^{m+1} = U^m + lambda dU with Armijo
+    backtracking on phi = ||R||_M^2 / 2 (halving lambda until
+    ||R(U + lambda dU)||_M <= (1 - c lambda) ||R(U)||_M); stops when
+    ||R||_M <= max(atol, rtol ||R(U^0)||_M), eq. (nk-stop).  U0 defaults to
+    the left trace at both time nodes with zero pressure."""
+    import scipy.sparse.linalg as spla
+
+    M = slab_mass(prob)
+    vprev = _f64(vprev)
+    U = state_from_velocity(prob, np.concatenate([vprev] * prob.nt)) if U0 is None else _f64(U0).copy()
+    R = residual(prob, U, vprev)
+    r0 = mass_norm(prob, R, M)
+    norms, steps = [r0], []
+    pin = pressure_pin_indices(prob)
+    keep = np.setdiff1d(np.arange(prob.nst), pin)
+    for _ in range(max_it):
+        if norms[-1] <= max(atol, rtol * r0):
+            break
+        J = assemble_slab(prob, velocity_blocks(prob, U)).tocsc()
+        dU = np.zeros(prob.nst)
+        dU[keep] = spla.splu(J[keep][:, keep].tocsc()).solve(R[keep])
+        lam = 1.0
+        for _ in range(max_backtrack):
+            Rn = residual(prob, U + lam * dU, vprev)
+            nn = mass_norm(prob, Rn, M)
+            if nn <= (1.0 - c_armijo * lam) * norms[-1]:
+                break
+            lam *= 0.5
+        U = U + lam * dU
+        R = Rn
+        norms.append(nn)
+        steps.append(lam)
+    return NewtonResult(U, norms, steps)
