@@ -47,7 +47,8 @@ enum {
   PNS_EHIP = -3,        /* a HIP runtime call failed */
   PNS_ESTATE = -4,      /* call order: no state set / smoother not set up */
   PNS_ESINGULAR = -5,   /* a patch or the coarse matrix had a zero pivot */
-  PNS_EUNSUPPORTED = -6 /* configuration outside what this build implements */
+  PNS_EUNSUPPORTED = -6, /* configuration outside what this build implements */
+  PNS_ENOTCONV = -7     /* a slab solve stopped without reaching its tolerance */
 };
 
 /* Constitutive tangent of the linearisation (Sec. 4.2-4.4). */
@@ -184,6 +185,79 @@ int pns_level_apply(pns_ctx* ctx, int level, const void* x_dev, void* y_dev);
  * df += P dc, P the nested Q2 interpolation / P1disc restriction. */
 int pns_restrict(pns_ctx* ctx, int level, const void* rf_dev, void* rc_dev);
 int pns_prolongate_add(pns_ctx* ctx, int level, const void* dc_dev, void* df_dev);
+
+/* ------------------------------------------------------------- slab solve */
+
+/* R = R_n(U), the slab residual of eq. (slab-underint) with f = 0 and g_D = 0
+ * (Sec. 5.2), in FP64 whatever the context precision:
+ *   R_v,mu = -( sum_nu K_t[mu][nu] M_x u_nu - m_t[mu] M_x v_prev ) - tau w_mu A_gamma(U_mu)_v,
+ *   R_p,mu = - tau w_mu A_gamma(U_mu)_p,
+ * with A_gamma the nonlinear form of eqs. pns-form, def-a-gam, def-b-gam and the
+ * inflow factor (u.n)^- of B^c evaluated at U itself.
+ * U_dev, R_dev: FP64 device vectors, canonical layout of level 0, must not
+ * alias.  v_prev_dev: FP64 device vector of the left-trace velocity
+ * (component 0 over the Q2 nodes, then component 1), or NULL for zero.
+ * Needs a bound workspace, not a state.  Asynchronous on the context stream. */
+int pns_residual(pns_ctx* ctx, const pns_model* model, const double* U_dev,
+                 const double* v_prev_dev, double* R_dev);
+
+/* Parameters of pns_solve. */
+typedef struct {
+  int max_newton;     /* nonlinear iterations */
+  int max_krylov;     /* FGMRES iterations per linear solve */
+  int restart;        /* FGMRES restart length (Krylov vectors kept), 1..200 */
+  double rtol, atol;  /* stop at ||R||_M <= max(atol, rtol ||R(U^0)||_M), eq. (nk-stop) */
+  double eta0;        /* forcing term of the first linear solve */
+  double eta_max;     /* upper bound of the forcing terms */
+  double rho;         /* refresh the smoother when ||R_{m+1}||_M / ||R_m||_M > rho */
+  int nu1, nu2;       /* Vanka steps before / after the coarse correction */
+  double omega;       /* Vanka damping */
+} pns_solve_params;
+
+/* What pns_solve did. */
+typedef struct {
+  int newton_iterations;    /* accepted Newton steps */
+  int krylov_iterations;    /* FGMRES iterations, all steps */
+  int smoother_setups;      /* smoother (re)builds */
+  int backtracks;           /* Armijo halvings, all steps */
+  double residual_initial;  /* ||R(U^0)||_M */
+  double residual_final;    /* ||R(U)||_M on return */
+} pns_solve_info;
+
+/* Device bytes of the pns_solve work buffer for FGMRES restart length `restart`
+ * ((2 restart + 7) vectors of N_st doubles, plus FP32 staging in an FP32
+ * context); 0 for a NULL context or restart outside 1..200. */
+size_t pns_solve_workspace_bytes(const pns_ctx* ctx, int restart);
+
+/* Newton-Krylov solve of R_n(U) = 0 on the slab (Sec. 5.3, eqs. nk-newton-lin,
+ * nk-inexact-newton, nk-stop): at each iterate U^m the linearisation model->lin
+ * acts matrix-free as J_n; FGMRES, right-preconditioned by one V-cycle,
+ * solves J_n dU = R_n(U^m) until ||J_n dU - R_n||_M <= eta_m ||R_n||_M, with
+ * Eisenstat-Walker forcing terms (choice 2, gamma 0.9, exponent 2) and FP64
+ * classical Gram-Schmidt with one reorthogonalisation in the block mass inner
+ * product of the time step (tau M_t (x) blockdiag(M_x, M_p)), whose norm
+ * ||.||_M measures every residual; then U^{m+1} = U^m + lambda dU, lambda
+ * halved until ||R(U^{m+1})||_M <= (1 - 1e-4 lambda (1 - eta_m)) ||R(U^m)||_M
+ * (Armijo on ||R||_M^2 / 2).  The smoother is built at the first step and
+ * rebuilt at the state of a later step when the previous step's residual
+ * ratio exceeded rho or its FGMRES count more than doubled (Sec. 6.3,
+ * "Interpretation and refresh strategy"), and once more, with the linear
+ * solve repeated, when a solve with a smoother from an earlier iterate misses
+ * its forcing term; the Jacobian action always uses the current iterate.  In an FP32 context the Jacobian action and the V-cycle run
+ * in FP32 (coarsest solve in FP64) while the residual, the norms and the
+ * Krylov vectors stay FP64.
+ * U_dev: FP64 device vector, the initial guess on entry, the last iterate on
+ * return.  v_prev_dev as for pns_residual.  work_dev: device buffer, 256-byte
+ * aligned, of at least pns_solve_workspace_bytes(ctx, prm->restart) bytes.
+ * Overwrites the context's state and smoother.  Synchronous: returns when the
+ * solve has finished on the context stream; *info is filled when non-NULL.
+ * Returns PNS_OK on convergence; PNS_ENOTCONV when max_newton is reached, the
+ * line search fails or a linear solve misses its forcing term within
+ * max_krylov iterations; PNS_EUNSUPPORTED when the coarsest level is too large
+ * for the dense coarse solve. */
+int pns_solve(pns_ctx* ctx, const pns_model* model, const double* v_prev_dev, double* U_dev,
+              const pns_solve_params* prm, void* work_dev, size_t work_bytes,
+              pns_solve_info* info);
 
 #ifdef __cplusplus
 }

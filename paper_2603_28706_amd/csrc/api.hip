@@ -6,7 +6,7 @@
 #include <string>
 #include <vector>
 
-#include "pns_internal.h"
+#include "ctx.h"
 
 using namespace pns;
 
@@ -18,68 +18,9 @@ hipError_t launch_form_fine_st(const Grid& g, double tau, const double* Es0, con
 
 namespace {
 
-struct Level {
-  Grid g;
-  double* E64 = nullptr;  // Galerkin element matrices (FP64), levels >= 1 (and 0 if coarsest)
-  void* E = nullptr;      // same, transposed per cell, in the context precision
-  void* inv = nullptr;    // patch inverses, column-major, context precision
-                          // (level 0: complex 21x21 time-diagonal form)
-  void* res = nullptr;    // defect
-  void* r = nullptr;      // level right-hand side (levels >= 1)
-  void* d = nullptr;      // level correction (levels >= 1)
-};
-
-constexpr size_t kAlign = 256;
-constexpr int64_t kMaxCoarse = 40000;  // dense coarsest inverse limit
-
-}  // namespace
-
-struct pns_ctx {
-  pns_mesh mesh{};
-  pns_discretization disc{};
-  int prec = PNS_FP64;
-  size_t es = 8;
-  int nlev = 1;
-  hipStream_t stream = nullptr;
-  std::vector<Level> lev;
-  Model model{};
-  bool has_state = false, has_smoother = false;
-  std::string err;
-  char* ws = nullptr;
-  size_t ws_bytes = 0;
-  // level-0 data
-  void* uk = nullptr;
-  double* uk64 = nullptr;
-  double* urep = nullptr;
-  double* Es0 = nullptr;
-  double* Es1 = nullptr;
-  double* Esr = nullptr;
-  uint16_t* masks = nullptr;
-  int* status = nullptr;
-  // coarsest level
-  double* Adense = nullptr;
-  double* gjwork = nullptr;
-  int* gjpiv = nullptr;
-  int64_t pin[2] = {-1, -1};
-  bool has_coarse = false;
-  int apply_mode = PNS_APPLY_RECOMPUTE;
-  void* tcache = nullptr;  // per-point tangent coefficients of level 0  // the coarsest level is small enough for a dense inverse
-};
-
-namespace {
-
 int fail(pns_ctx* c, int code, const std::string& msg) {
-  if (c) c->err = msg;
-  return code;
+  return fail_msg(c ? &c->err : nullptr, code, msg);
 }
-
-#define PNS_HIP(ctx, call)                                                                  \
-  do {                                                                                      \
-    hipError_t e_ = (call);                                                                 \
-    if (e_ != hipSuccess)                                                                   \
-      return fail(ctx, PNS_EHIP, std::string("HIP error: ") + hipGetErrorString(e_) + " at " + \
-                                     #call);                                                \
-  } while (0)
 
 // Lay out (bind == false: only measure) every buffer of the context.
 size_t layout(pns_ctx* c, bool bind) {
@@ -280,6 +221,32 @@ int vanka_setup_impl(pns_ctx* c, const uint16_t* masks) {
 
 }  // namespace
 
+int pns::make_model(const pns_model* md, Model* m, std::string* err) {
+  if (!(md->p > 1.0 && md->p <= 2.0)) return fail_msg(err, PNS_EINVAL, "p must lie in (1, 2]");
+  if (!(md->delta > 0.0)) return fail_msg(err, PNS_EINVAL, "delta must be > 0");
+  if (!(md->nu > 0.0) || !(md->nu_inf >= 0.0))
+    return fail_msg(err, PNS_EINVAL, "need nu > 0, nu_inf >= 0");
+  if (!(md->gamma1 >= 0.0) || !(md->gamma2 >= 0.0))
+    return fail_msg(err, PNS_EINVAL, "negative penalty");
+  if (!(md->sigma_max >= 0.0)) return fail_msg(err, PNS_EINVAL, "sigma_max must be >= 0");
+  if (md->lin < 0 || md->lin > 2) return fail_msg(err, PNS_EINVAL, "unknown linearisation kind");
+  if (md->nitsche_q_sign != 1 && md->nitsche_q_sign != -1)
+    return fail_msg(err, PNS_EINVAL, "nitsche_q_sign must be +1 or -1");
+  m->p = md->p;
+  m->delta2 = md->delta * md->delta;
+  m->nu = md->nu;
+  m->nu_inf = md->nu_inf;
+  m->expo = 0.5 * (md->p - 2.0);
+  m->sigma_max = md->sigma_max;
+  m->etaD = md->nu_inf + md->nu * std::pow(md->delta, md->p - 2.0);  // eta(D g_D), g_D = 0
+  m->gamma1 = md->gamma1;
+  m->gamma2 = md->gamma2;
+  m->qsign = (double)md->nitsche_q_sign;
+  m->lin = md->lin;
+  m->convection = md->convection ? 1 : 0;
+  return PNS_OK;
+}
+
 extern "C" {
 
 int pns_ctx_create(const pns_mesh* mesh, const pns_discretization* disc, int n_levels,
@@ -353,27 +320,9 @@ int pns_bind_workspace(pns_ctx* ctx, void* ws, size_t bytes) {
 int pns_set_state(pns_ctx* ctx, const pns_model* md, const double* u_k) {
   if (!check_ctx(ctx, false, false)) return ctx_code(ctx, false, false);
   if (!md || !u_k) return fail(ctx, PNS_EINVAL, "NULL model or state");
-  if (!(md->p > 1.0 && md->p <= 2.0)) return fail(ctx, PNS_EINVAL, "p must lie in (1, 2]");
-  if (!(md->delta > 0.0)) return fail(ctx, PNS_EINVAL, "delta must be > 0");
-  if (!(md->nu > 0.0) || !(md->nu_inf >= 0.0)) return fail(ctx, PNS_EINVAL, "need nu > 0, nu_inf >= 0");
-  if (!(md->gamma1 >= 0.0) || !(md->gamma2 >= 0.0)) return fail(ctx, PNS_EINVAL, "negative penalty");
-  if (!(md->sigma_max >= 0.0)) return fail(ctx, PNS_EINVAL, "sigma_max must be >= 0");
-  if (md->lin < 0 || md->lin > 2) return fail(ctx, PNS_EINVAL, "unknown linearisation kind");
-  if (md->nitsche_q_sign != 1 && md->nitsche_q_sign != -1)
-    return fail(ctx, PNS_EINVAL, "nitsche_q_sign must be +1 or -1");
   Model m;
-  m.p = md->p;
-  m.delta2 = md->delta * md->delta;
-  m.nu = md->nu;
-  m.nu_inf = md->nu_inf;
-  m.expo = 0.5 * (md->p - 2.0);
-  m.sigma_max = md->sigma_max;
-  m.etaD = md->nu_inf + md->nu * std::pow(md->delta, md->p - 2.0);  // eta(D g_D), g_D = 0
-  m.gamma1 = md->gamma1;
-  m.gamma2 = md->gamma2;
-  m.qsign = (double)md->nitsche_q_sign;
-  m.lin = md->lin;
-  m.convection = md->convection ? 1 : 0;
+  const int rc = make_model(md, &m, &ctx->err);
+  if (rc != PNS_OK) return rc;
   ctx->model = m;
   const Grid& g0 = ctx->lev[0].g;
   hipStream_t s = ctx->stream;

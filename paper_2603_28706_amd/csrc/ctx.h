@@ -1,0 +1,74 @@
+// Internal: the context behind the opaque pns_ctx handle, shared by the C-ABI
+// entry points (api.hip) and the slab solve (solve.hip).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "pns_internal.h"
+
+namespace pns {
+
+struct Level {
+  Grid g;
+  double* E64 = nullptr;  // Galerkin element matrices (FP64), levels >= 1 (and 0 if coarsest)
+  void* E = nullptr;      // same, transposed per cell, in the context precision
+  void* inv = nullptr;    // patch inverses, column-major, context precision
+                          // (level 0: complex 21x21 time-diagonal form)
+  void* res = nullptr;    // defect
+  void* r = nullptr;      // level right-hand side (levels >= 1)
+  void* d = nullptr;      // level correction (levels >= 1)
+};
+
+constexpr size_t kAlign = 256;
+constexpr int64_t kMaxCoarse = 40000;  // dense coarsest inverse limit
+
+inline int fail_msg(std::string* err, int code, const std::string& msg) {
+  if (err) *err = msg;
+  return code;
+}
+
+// Model of the kernels from the ABI description; PNS_OK or PNS_EINVAL with a message.
+int make_model(const pns_model* md, Model* m, std::string* err);
+
+}  // namespace pns
+
+struct pns_ctx {
+  pns_mesh mesh{};
+  pns_discretization disc{};
+  int prec = PNS_FP64;
+  size_t es = 8;
+  int nlev = 1;
+  hipStream_t stream = nullptr;
+  std::vector<pns::Level> lev;
+  pns::Model model{};
+  bool has_state = false, has_smoother = false;
+  std::string err;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  // level-0 data
+  void* uk = nullptr;
+  double* uk64 = nullptr;
+  double* urep = nullptr;
+  double* Es0 = nullptr;
+  double* Es1 = nullptr;
+  double* Esr = nullptr;
+  uint16_t* masks = nullptr;
+  int* status = nullptr;
+  // coarsest level (dense inverse when it is small enough)
+  double* Adense = nullptr;
+  double* gjwork = nullptr;
+  int* gjpiv = nullptr;
+  int64_t pin[2] = {-1, -1};
+  bool has_coarse = false;
+  int apply_mode = PNS_APPLY_RECOMPUTE;
+  void* tcache = nullptr;  // per-point tangent coefficients of level 0
+};
+
+#define PNS_HIP(ctx, call)                                                                  \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return pns::fail_msg((ctx) ? &(ctx)->err : nullptr, PNS_EHIP,                         \
+                           std::string("HIP error: ") + hipGetErrorString(e_) + " at " + #call); \
+  } while (0)

@@ -137,4 +137,22 @@ hipError_t launch_dense_gemv(int64_t n, const double* Ainv, const T* r, T* d,
 template <typename T>
 hipError_t launch_fill(int64_t n, T v, T* y, hipStream_t s);
 
+// residual.hip: FP64 slab residual R_n(U) (v_prev may be NULL)
+hipError_t launch_residual(const Grid& g, const Model& m, double tau, const double* U,
+                           const double* vprev, double* R, hipStream_t s);
+
+// krylov.hip: vector kernels of the slab solve (FP64)
+int dot_partials();  // partial sums per vector of launch_multi_dot
+hipError_t launch_mass(const Grid& g, double tau, const double* x, double* y, hipStream_t s);
+// out[i] = V_i . u for i < k (V_i = V + i ldv); partial: k * dot_partials() doubles
+hipError_t launch_multi_dot(int64_t n, int k, const double* V, int64_t ldv, const double* u,
+                            double* partial, double* out, hipStream_t s);
+// w = alpha w + sgn sum_{i<k} c[i] V_i, c on the device
+hipError_t launch_combine(int64_t n, int k, const double* V, int64_t ldv, const double* c,
+                          double sgn, double alpha, double* w, hipStream_t s);
+hipError_t launch_axpby(int64_t n, double a, const double* x, double b, const double* y, double* z,
+                        hipStream_t s);
+hipError_t launch_widen(int64_t n, const float* x, double* y, hipStream_t s);
+hipError_t launch_narrow(int64_t n, const double* x, float* y, hipStream_t s);
+
 }  // namespace pns

@@ -17,8 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpnsmg.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "pnsmg.h")
 
-PNS_OK, PNS_EINVAL, PNS_EWORKSPACE, PNS_EHIP, PNS_ESTATE, PNS_ESINGULAR, PNS_EUNSUPPORTED = (
-    0, -1, -2, -3, -4, -5, -6)
+(PNS_OK, PNS_EINVAL, PNS_EWORKSPACE, PNS_EHIP, PNS_ESTATE, PNS_ESINGULAR, PNS_EUNSUPPORTED,
+ PNS_ENOTCONV) = (0, -1, -2, -3, -4, -5, -6, -7)
 PICARD, EXACT_NEWTON, MODIFIED_NEWTON = 0, 1, 2
 FP64, FP32 = 0, 1
 APPLY_RECOMPUTE, APPLY_CACHED = 0, 1
@@ -47,6 +47,22 @@ class pns_model(ctypes.Structure):
                 ("convection", ctypes.c_int), ("nitsche_q_sign", ctypes.c_int),
                 ("lin", ctypes.c_int)]
 
+
+class pns_solve_params(ctypes.Structure):
+    _fields_ = [("max_newton", ctypes.c_int), ("max_krylov", ctypes.c_int),
+                ("restart", ctypes.c_int), ("rtol", ctypes.c_double), ("atol", ctypes.c_double),
+                ("eta0", ctypes.c_double), ("eta_max", ctypes.c_double), ("rho", ctypes.c_double),
+                ("nu1", ctypes.c_int), ("nu2", ctypes.c_int), ("omega", ctypes.c_double)]
+
+
+class pns_solve_info(ctypes.Structure):
+    _fields_ = [("newton_iterations", ctypes.c_int), ("krylov_iterations", ctypes.c_int),
+                ("smoother_setups", ctypes.c_int), ("backtracks", ctypes.c_int),
+                ("residual_initial", ctypes.c_double), ("residual_final", ctypes.c_double)]
+
+
+SOLVE_DEFAULTS = dict(max_newton=30, max_krylov=200, restart=30, rtol=1e-8, atol=0.0, eta0=0.1,
+                      eta_max=0.5, rho=0.5, nu1=2, nu2=2, omega=0.2)
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -86,10 +102,16 @@ def lib():
         L.pns_level_apply.argtypes = [_vp, i, _vp, _vp]
         L.pns_restrict.argtypes = [_vp, i, _vp, _vp]
         L.pns_prolongate_add.argtypes = [_vp, i, _vp, _vp]
+        L.pns_residual.argtypes = [_vp, pp(pns_model), _vp, _vp, _vp]
+        L.pns_solve_workspace_bytes.argtypes = [_vp, i]
+        L.pns_solve_workspace_bytes.restype = ctypes.c_size_t
+        L.pns_solve.argtypes = [_vp, pp(pns_model), _vp, _vp, pp(pns_solve_params), _vp,
+                                ctypes.c_size_t, pp(pns_solve_info)]
         for f in ("pns_ctx_create", "pns_level_sizes", "pns_bind_workspace", "pns_set_state",
                   "pns_set_apply_mode",
                   "pns_cell_apply", "pns_cell_defect", "pns_vanka_setup", "pns_vanka_smooth",
-                  "pns_vcycle", "pns_level_apply", "pns_restrict", "pns_prolongate_add"):
+                  "pns_vcycle", "pns_level_apply", "pns_restrict", "pns_prolongate_add",
+                  "pns_residual", "pns_solve"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -153,14 +175,14 @@ class Context:
         assert t.numel() == self.sizes(level)["nst"]
         return _ptr(t)
 
+    def _f64(self, t, n):
+        assert t.dtype == self.torch.float64 and t.is_contiguous() and t.device.type == "cuda"
+        assert t.numel() == n
+        return _ptr(t)
+
     # -------------------------------------------------------------- C-ABI
     def pns_set_state(self, model: dict, uk):
-        md = pns_model(
-            float(model["p"]), float(model["delta"]), float(model.get("nu", 1.0)),
-            float(model.get("nu_inf", 0.0)), float(model.get("gamma1", 40.0)),
-            float(model.get("gamma2", 40.0)), float(model.get("sigma_max", 1.0)),
-            int(model.get("convection", 1)), int(model.get("qsign", 1)),
-            int(model.get("lin", MODIFIED_NEWTON)))
+        md = model_struct(model)
         assert uk.dtype == self.torch.float64 and uk.is_contiguous()
         assert uk.numel() == 2 * self.sizes(0)["nv"]
         self._uk = uk
@@ -200,6 +222,46 @@ class Context:
     def pns_prolongate_add(self, level, dc, df):
         self._check(lib().pns_prolongate_add(self.h, level, self._vec(dc, level + 1),
                                              self._vec(df, level)))
+
+    def pns_residual(self, model: dict, U, vprev, R):
+        sz = self.sizes(0)
+        vp = None if vprev is None else self._f64(vprev, sz["nv"])
+        self._check(lib().pns_residual(self.h, ctypes.byref(model_struct(model)),
+                                       self._f64(U, sz["nst"]), vp, self._f64(R, sz["nst"])))
+
+    def pns_solve_workspace_bytes(self, restart):
+        return lib().pns_solve_workspace_bytes(self.h, int(restart))
+
+    def pns_solve(self, model: dict, vprev, U, check=True, **params):
+        """Newton-Krylov slab solve; U (FP64) is updated in place.  Returns
+        (return code, info dict); raises on errors other than PNS_ENOTCONV
+        unless check is False."""
+        prm = dict(SOLVE_DEFAULTS, **params)
+        ps = pns_solve_params(*(prm[f] for f, _ in pns_solve_params._fields_))
+        nbytes = self.pns_solve_workspace_bytes(ps.restart)
+        if nbytes == 0:
+            raise PnsError(PNS_EINVAL, "invalid restart length")
+        work = self.torch.empty(nbytes + 256, dtype=self.torch.uint8, device=self.device)
+        base = (work.data_ptr() + 255) // 256 * 256
+        sz = self.sizes(0)
+        vp = None if vprev is None else self._f64(vprev, sz["nv"])
+        info = pns_solve_info()
+        rc = lib().pns_solve(self.h, ctypes.byref(model_struct(model)), vp,
+                             self._f64(U, sz["nst"]), ctypes.byref(ps), _vp(base), nbytes,
+                             ctypes.byref(info))
+        if check and rc not in (PNS_OK, PNS_ENOTCONV):
+            self._check(rc)
+        del work
+        return rc, {f: getattr(info, f) for f, _ in pns_solve_info._fields_}
+
+
+def model_struct(model: dict):
+    return pns_model(
+        float(model["p"]), float(model["delta"]), float(model.get("nu", 1.0)),
+        float(model.get("nu_inf", 0.0)), float(model.get("gamma1", 40.0)),
+        float(model.get("gamma2", 40.0)), float(model.get("sigma_max", 1.0)),
+        int(model.get("convection", 1)), int(model.get("qsign", 1)),
+        int(model.get("lin", MODIFIED_NEWTON)))
 
 
 def masks_to_bits(masks):

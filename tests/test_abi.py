@@ -66,3 +66,35 @@ def test_binding_has_no_fallback(monkeypatch, tmp_path):
     monkeypatch.setattr(pnsmg, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         pnsmg.lib()
+
+
+def test_solve_workspace_query_rejects_bad_arguments():
+    L = pnsmg.lib()
+    assert L.pns_solve_workspace_bytes(None, 30) == 0
+    rc, h = _create((8, 8), 2)
+    assert rc == pnsmg.PNS_OK
+    try:
+        assert L.pns_solve_workspace_bytes(h, 0) == 0
+        assert L.pns_solve_workspace_bytes(h, 201) == 0
+        a = L.pns_solve_workspace_bytes(h, 10)
+        b = L.pns_solve_workspace_bytes(h, 20)
+        nst = 2 * (2 * 17 * 17 + 3 * 64)
+        # ten more Krylov and ten more preconditioned vectors of N_st doubles
+        assert b - a >= 20 * nst * 8
+    finally:
+        L.pns_ctx_destroy(h)
+
+
+def test_solve_and_residual_reject_calls_without_workspace():
+    L = pnsmg.lib()
+    rc, h = _create((8, 8), 2)
+    assert rc == pnsmg.PNS_OK
+    try:
+        md = pnsmg.model_struct(dict(p=1.5, delta=1e-2))
+        assert L.pns_residual(h, ctypes.byref(md), None, None, None) == pnsmg.PNS_EWORKSPACE
+        prm = pnsmg.pns_solve_params(*(pnsmg.SOLVE_DEFAULTS[f] for f, _ in
+                                       pnsmg.pns_solve_params._fields_))
+        rc = L.pns_solve(h, ctypes.byref(md), None, None, ctypes.byref(prm), None, 0, None)
+        assert rc == pnsmg.PNS_EWORKSPACE
+    finally:
+        L.pns_ctx_destroy(h)
