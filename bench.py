@@ -42,6 +42,12 @@ FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 FP64 flop / clock
 APPLIES_PER_STEP = 4
 MODEL = dict(p=1.2, delta=1e-4, nu=1.0, nu_inf=1e-4, gamma1=40.0, gamma2=40.0, sigma_max=1.0,
              convection=1, qsign=1)
+OMEGA = 0.1   # Vanka damping of the V-cycle (its cost does not depend on it)
+# slab solves: a regime in which additive cell-patch Vanka and the clipped
+# tangent converge (see the solve limits in the design notes)
+SOLVE_MODEL = dict(p=1.8, delta=1e-2, nu=0.1, nu_inf=1e-4, gamma1=40.0, gamma2=40.0,
+                   sigma_max=1.0, convection=1, qsign=1, lin=2)
+SOLVE_SEEDS = (201, 202, 203, 204, 205)
 
 
 def algorithmic_bytes(sizes, elem):
@@ -180,7 +186,7 @@ def run(args):
             if ev is not None:
                 ev[1].record(stream)
             if not args.apply_only:
-                ctx.pns_vcycle(2, 2, 0.5, r, d)
+                ctx.pns_vcycle(2, 2, OMEGA, r, d)
             if ev is not None:
                 ev[2].record(stream)
 
@@ -225,6 +231,47 @@ def run(args):
     return results
 
 
+def solve_latency(n, seeds, rtol=1e-8):
+    """Time-to-rtol of independent slab solves (Newton-FGMRES, one V-cycle per
+    Krylov step) at n x n, one per seed of the left-trace velocity, in FP64
+    and mixed precision (FP32 action and V-cycle inside FP64 Newton/FGMRES)."""
+    import numpy as np
+    import torch
+
+    from paper_2603_28706_amd import inputs, pnsmg
+
+    levels = max(1, int(np.log2(n // 16)) + 1)   # coarsest level 16 x 16
+    out = {}
+    for prec, name in ((pnsmg.FP64, "fp64"), (pnsmg.FP32, "mixed")):
+        ctx = pnsmg.Context((n, n), n_levels=levels, precision=prec)
+        sz = ctx.sizes(0)
+        lat, newton, krylov, ok = [], [], [], 0
+        for seed in seeds:
+            vprev = inputs.sin_series_velocity((n, n), seed=seed, t_nodes=[0.0])
+            U0 = np.zeros(sz["nst"])
+            U0[:sz["nv"]] = vprev
+            U0[sz["ns"]:sz["ns"] + sz["nv"]] = vprev
+            U = torch.tensor(U0, device="cuda")
+            vp = torch.tensor(vprev, device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, info = ctx.pns_solve(SOLVE_MODEL, vp, U, rtol=rtol)
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t0)
+            ok += rc == pnsmg.PNS_OK
+            newton.append(info["newton_iterations"])
+            krylov.append(info["krylov_iterations"])
+        out[name] = dict(p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
+                         converged=f"{ok}/{len(seeds)}", newton_mean=float(np.mean(newton)),
+                         krylov_mean=float(np.mean(krylov)))
+        print(f"[bench] solve {name} {n}x{n}: p50 {out[name]['p50_s']:.3f} s, p99 "
+              f"{out[name]['p99_s']:.3f} s, converged {out[name]['converged']}, Newton "
+              f"{np.mean(newton):.1f}, FGMRES {np.mean(krylov):.1f}", file=sys.stderr, flush=True)
+        del ctx
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -234,6 +281,8 @@ def main():
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--apply-only", action="store_true")
+    ap.add_argument("--solve-n", type=int, default=256,
+                    help="mesh of the slab-solve latency measurement (0: skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain streaming kernel of known size (counter calibration)")
     ap.add_argument("--lin", type=int, default=2, help="0 Picard, 1 exact Newton, 2 modified Newton")
@@ -264,7 +313,7 @@ def main():
         "config": {
             "workload": (f"2D {args.n}x{args.n} Q2/P1disc x dG(1) slab, p=1.2 delta=1e-4 "
                          f"nu_inf=1e-4, surrogate-tangent Jacobian action + "
-                         f"{args.levels}-level V-cycle (2+2 Vanka, omega=0.5)"),
+                         f"{args.levels}-level V-cycle (2+2 Vanka, omega={OMEGA})"),
             "space_time_dof": f64["nst"],
             "levels": args.levels,
         },
@@ -287,6 +336,15 @@ def main():
                      "kernel": "cell_apply_kernel<double, modified Newton, recompute>",
                      "flop_per_launch": flops, "algorithmic_bytes": f64["bytes"]},
     }
+    if args.solve_n and not args.apply_only:
+        sl = solve_latency(args.solve_n, SOLVE_SEEDS)
+        line["solve_time_to_1e-8_s"] = {
+            "workload": (f"2D {args.solve_n}x{args.solve_n} slab solve, p=1.8 delta=1e-2 nu0=0.1 "
+                         f"nu_inf=1e-4, modified Newton + FGMRES(30) / V-cycle to ||R||_M <= "
+                         f"1e-8 ||R0||_M, {len(SOLVE_SEEDS)} seeded left traces"),
+            **{k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+               for k, v in sl.items()},
+            "mixed_speedup_p50": round(sl["fp64"]["p50_s"] / sl["mixed"]["p50_s"], 3)}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

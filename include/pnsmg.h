@@ -69,6 +69,15 @@ typedef enum { PNS_FP64 = 0, PNS_FP32 = 1 } pns_precision;
  *   context precision and read by every action. */
 typedef enum { PNS_APPLY_RECOMPUTE = 0, PNS_APPLY_CACHED = 1 } pns_apply_mode;
 
+/* Patch matrices of the finest-level Vanka smoother (Sec. 6.3):
+ *   SURROGATE: every state-dependent coefficient frozen at the slab midpoint,
+ *   eq. (surrogate-diag), solved in time-diagonal form (one complex 21x21
+ *   inverse per cell);
+ *   EXACT: the exact patch matrices R_K A R_K^T of the slab operator with the
+ *   coefficients of each Radau node (real 42x42 inverse per cell), as on the
+ *   coarse levels. */
+typedef enum { PNS_PATCH_SURROGATE = 0, PNS_PATCH_EXACT = 1 } pns_patch_kind;
+
 /* Box [lo, hi] with n_cells[k] uniform cells per direction; dim must be 2. */
 typedef struct {
   int dim;
@@ -142,6 +151,11 @@ int pns_set_state(pns_ctx* ctx, const pns_model* model, const double* u_k_dev);
  * after pns_set_state builds the cache from the current state; returns
  * PNS_EINVAL for an unknown mode. */
 int pns_set_apply_mode(pns_ctx* ctx, int mode);
+
+/* Select the finest-level patch matrices (default PNS_PATCH_SURROGATE); a
+ * change takes effect at the next pns_vanka_setup (until then the context has
+ * no smoother).  PNS_EINVAL for an unknown kind. */
+int pns_set_patch_kind(pns_ctx* ctx, int kind);
 
 /* y = J_n(u_k) x on level 0, eq. (slab-underint-jac): the temporal mass
  * coupling K_t (x) M_x plus tau M_t (x) diag(J_1, J_2), each J_mu the spatial

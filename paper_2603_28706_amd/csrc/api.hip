@@ -45,7 +45,8 @@ size_t layout(pns_ctx* c, bool bind) {
   for (int l = 0; l < c->nlev; ++l) {
     Level& L = c->lev[l];
     const bool coarsest = (l == c->nlev - 1);
-    L.inv = take(L.g.nc * (l == 0 ? 2 * kNs * kNs : kNst * kNst) * es);
+    // level 0 holds either the complex 21x21 or the real 42x42 inverses
+    L.inv = take(L.g.nc * kNst * kNst * es);
     L.res = take(L.g.nst * es);
     if (l >= 1 || coarsest) L.E64 = (double*)take(L.g.nc * kNst * kNst * 8);
     if (l >= 1) L.E = take(L.g.nc * kNst * kNst * es);
@@ -130,7 +131,7 @@ hipError_t smooth(pns_ctx* c, int l, int nsweeps, double omega, const T* r, T* d
       if (e != hipSuccess) return e;
       res = (const T*)L.res;
     }
-    hipError_t e = l == 0
+    hipError_t e = (l == 0 && c->patch_kind == PNS_PATCH_SURROGATE)
                        ? launch_patch_sweep_c<T>(L.g, (const T*)L.inv, res, d, omega, c->stream)
                        : launch_patch_sweep<T>(L.g, (const T*)L.inv, res, d, omega, c->stream);
     if (e != hipSuccess) return e;
@@ -175,9 +176,16 @@ int vanka_setup_impl(pns_ctx* c, const uint16_t* masks) {
   PNS_HIP(c, launch_element_matrices(L0.g, c->model, u0, c->Es0, s));
   PNS_HIP(c, launch_element_matrices(L0.g, c->model, u1, c->Es1, s));
   PNS_HIP(c, launch_element_matrices(L0.g, c->model, c->urep, c->Esr, s));
-  // level 0: surrogate patches, all state-dependent coefficients at t_rep
-  PNS_HIP(c, launch_fine_patches<T>(L0.g, c->disc.tau, c->Esr, masks ? c->masks : nullptr,
-                                    (T*)L0.inv, c->status, s));
+  if (c->patch_kind == PNS_PATCH_SURROGATE) {
+    // level 0: surrogate patches, all state-dependent coefficients at t_rep
+    PNS_HIP(c, launch_fine_patches<T>(L0.g, c->disc.tau, c->Esr, masks ? c->masks : nullptr,
+                                      (T*)L0.inv, c->status, s));
+  } else {
+    // level 0: exact patches, each Radau node with its own spatial matrices
+    PNS_HIP(c, launch_exact_fine_patches<T>(L0.g, c->disc.tau, c->Es0, c->Es1,
+                                            masks ? c->masks : nullptr, (T*)L0.inv, c->status,
+                                            s));
+  }
   // coarse levels: Galerkin element matrices, exact patches
   for (int l = 1; l < c->nlev; ++l) {
     Level& L = c->lev[l];
@@ -346,6 +354,15 @@ int pns_set_apply_mode(pns_ctx* ctx, int mode) {
   const bool rebuild = mode == PNS_APPLY_CACHED && ctx->apply_mode != mode && ctx->has_state;
   ctx->apply_mode = mode;
   if (rebuild) PNS_HIP(ctx, build_tangent_cache(ctx));
+  return PNS_OK;
+}
+
+int pns_set_patch_kind(pns_ctx* ctx, int kind) {
+  if (!ctx) return PNS_EINVAL;
+  if (kind != PNS_PATCH_SURROGATE && kind != PNS_PATCH_EXACT)
+    return fail(ctx, PNS_EINVAL, "unknown patch kind");
+  if (kind != ctx->patch_kind) ctx->has_smoother = false;
+  ctx->patch_kind = kind;
   return PNS_OK;
 }
 

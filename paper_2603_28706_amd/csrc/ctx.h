@@ -13,8 +13,8 @@ struct Level {
   Grid g;
   double* E64 = nullptr;  // Galerkin element matrices (FP64), levels >= 1 (and 0 if coarsest)
   void* E = nullptr;      // same, transposed per cell, in the context precision
-  void* inv = nullptr;    // patch inverses, column-major, context precision
-                          // (level 0: complex 21x21 time-diagonal form)
+  void* inv = nullptr;    // patch inverses, column-major, context precision (level 0
+                          // with surrogate patches: complex 21x21 time-diagonal form)
   void* res = nullptr;    // defect
   void* r = nullptr;      // level right-hand side (levels >= 1)
   void* d = nullptr;      // level correction (levels >= 1)
@@ -62,6 +62,7 @@ struct pns_ctx {
   int64_t pin[2] = {-1, -1};
   bool has_coarse = false;
   int apply_mode = PNS_APPLY_RECOMPUTE;
+  int patch_kind = PNS_PATCH_SURROGATE;  // finest-level patch matrices
   void* tcache = nullptr;  // per-point tangent coefficients of level 0
 };
 

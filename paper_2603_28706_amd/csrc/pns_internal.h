@@ -101,6 +101,12 @@ hipError_t launch_convert(int64_t n, const double* in, T* out, hipStream_t s);
 template <typename T>
 hipError_t launch_fine_patches(const Grid& g, double tau, const double* Es, const uint16_t* masks,
                                T* inv, int* status, hipStream_t s);
+// level-0 exact patches (real 42x42 inverses) from the spatial matrices at the
+// two Radau nodes
+template <typename T>
+hipError_t launch_exact_fine_patches(const Grid& g, double tau, const double* Es0,
+                                     const double* Es1, const uint16_t* masks, T* inv,
+                                     int* status, hipStream_t s);
 template <typename T>
 hipError_t launch_transpose_convert(int64_t ncells, const double* E, T* Et, hipStream_t s);
 template <typename T>

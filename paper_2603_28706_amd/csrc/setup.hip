@@ -786,6 +786,16 @@ hipError_t launch_fine_patches(const Grid& g, double tau, const double* Es, cons
 }
 
 template <typename T>
+hipError_t launch_exact_fine_patches(const Grid& g, double tau, const double* Es0,
+                                     const double* Es1, const uint16_t* masks, T* inv,
+                                     int* status, hipStream_t s) {
+  FineEntry e{g, tau, Es0, Es1};
+  hipLaunchKernelGGL((patch_kernel<T, FineEntry>), dim3((unsigned)g.nc), dim3(64), 0, s, g, e,
+                     masks, inv, status);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_transpose_convert(int64_t ncells, const double* E, T* Et, hipStream_t s) {
   const int64_t n = ncells * kNst * kNst;
   hipLaunchKernelGGL(transpose_convert_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
@@ -863,6 +873,12 @@ template hipError_t launch_fine_patches<double>(const Grid&, double, const doubl
                                                 double*, int*, hipStream_t);
 template hipError_t launch_fine_patches<float>(const Grid&, double, const double*, const uint16_t*,
                                                float*, int*, hipStream_t);
+template hipError_t launch_exact_fine_patches<double>(const Grid&, double, const double*,
+                                                      const double*, const uint16_t*, double*,
+                                                      int*, hipStream_t);
+template hipError_t launch_exact_fine_patches<float>(const Grid&, double, const double*,
+                                                     const double*, const uint16_t*, float*, int*,
+                                                     hipStream_t);
 template hipError_t launch_transpose_convert<double>(int64_t, const double*, double*, hipStream_t);
 template hipError_t launch_transpose_convert<float>(int64_t, const double*, float*, hipStream_t);
 template hipError_t launch_level_patches<double>(const Grid&, const double*, double*, int*,

@@ -22,6 +22,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "pnsmg.h")
 PICARD, EXACT_NEWTON, MODIFIED_NEWTON = 0, 1, 2
 FP64, FP32 = 0, 1
 APPLY_RECOMPUTE, APPLY_CACHED = 0, 1
+PATCH_SURROGATE, PATCH_EXACT = 0, 1
 
 
 class PnsError(RuntimeError):
@@ -62,7 +63,7 @@ class pns_solve_info(ctypes.Structure):
 
 
 SOLVE_DEFAULTS = dict(max_newton=30, max_krylov=200, restart=30, rtol=1e-8, atol=0.0, eta0=0.1,
-                      eta_max=0.5, rho=0.5, nu1=2, nu2=2, omega=0.2)
+                      eta_max=0.5, rho=0.5, nu1=2, nu2=2, omega=0.1)
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -95,6 +96,7 @@ def lib():
         L.pns_set_state.argtypes = [_vp, pp(pns_model), _vp]
         L.pns_cell_apply.argtypes = [_vp, _vp, _vp]
         L.pns_set_apply_mode.argtypes = [_vp, i]
+        L.pns_set_patch_kind.argtypes = [_vp, i]
         L.pns_cell_defect.argtypes = [_vp, _vp, _vp, _vp]
         L.pns_vanka_setup.argtypes = [_vp, _vp]
         L.pns_vanka_smooth.argtypes = [_vp, i, i, ctypes.c_double, _vp, _vp]
@@ -108,7 +110,7 @@ def lib():
         L.pns_solve.argtypes = [_vp, pp(pns_model), _vp, _vp, pp(pns_solve_params), _vp,
                                 ctypes.c_size_t, pp(pns_solve_info)]
         for f in ("pns_ctx_create", "pns_level_sizes", "pns_bind_workspace", "pns_set_state",
-                  "pns_set_apply_mode",
+                  "pns_set_apply_mode", "pns_set_patch_kind",
                   "pns_cell_apply", "pns_cell_defect", "pns_vanka_setup", "pns_vanka_smooth",
                   "pns_vcycle", "pns_level_apply", "pns_restrict", "pns_prolongate_add",
                   "pns_residual", "pns_solve"):
@@ -190,6 +192,9 @@ class Context:
 
     def pns_set_apply_mode(self, mode):
         self._check(lib().pns_set_apply_mode(self.h, int(mode)))
+
+    def pns_set_patch_kind(self, kind):
+        self._check(lib().pns_set_patch_kind(self.h, int(kind)))
 
     def pns_cell_apply(self, x, y):
         self._check(lib().pns_cell_apply(self.h, self._vec(x), self._vec(y)))

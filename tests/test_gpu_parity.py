@@ -191,9 +191,11 @@ def test_full_size_apply_sampled_rows():
 
 # ------------------------------------------------------------------ smoother
 
-def make_ctx(n, levels, model, lin, uk, precision=pnsmg.FP64, masks=None):
+def make_ctx(n, levels, model, lin, uk, precision=pnsmg.FP64, masks=None,
+             patch_kind=pnsmg.PATCH_SURROGATE):
     ctx = pnsmg.Context(n, n_levels=levels, precision=precision, tau=0.01)
     ctx.pns_set_state(dict(model, lin=lin), to_dev(uk, torch.float64))
+    ctx.pns_set_patch_kind(patch_kind)
     ctx.pns_vanka_setup(None if masks is None else pnsmg.masks_to_bits(masks))
     return ctx
 
@@ -329,3 +331,48 @@ def test_vcycle_fp32_close_to_fp64():
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     print(f"vcycle fp32 rel err {err:.2e}")
     assert err <= 1e-4
+
+
+@pytest.mark.parametrize("masked", [False, True])
+def test_exact_fine_patches_vanka_fp64(masked):
+    # exact patch matrices R_K A R_K^T on the finest level (both Radau nodes
+    # with their own coefficients) against the oracle's patches of the
+    # assembled slab operator
+    n = (10, 8)
+    lin = pnsmg.MODIFIED_NEWTON
+    model = dict(CONFIG1, p=1.2, delta=1e-4, nu_inf=1e-4)
+    prob = oracle_problem(n, model, lin)
+    uk = inputs.sin_series_velocity(n, seed=411, t_nodes=[0.01 / 3, 0.01])
+    masks = inputs.truncation_masks(n, seed=412) if masked else None
+    r = inputs.uniform(413, prob.nst)
+    A = O.assemble_slab(prob, O.split_uk(prob, uk))
+    patches = O.all_patches(prob, masks)
+    pm = O.patch_matrices(A, patches)
+    ref = O.vanka_step(A, pm, patches, r, np.zeros(prob.nst), 0.3)
+    ref = O.vanka_step(A, pm, patches, r, ref, 0.3)
+    ctx = make_ctx(n, 1, model, lin, uk, masks=masks, patch_kind=pnsmg.PATCH_EXACT)
+    d = ctx.vector()
+    ctx.pns_vanka_smooth(0, 2, 0.3, to_dev(r, torch.float64), d)
+    got = d.cpu().numpy()
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    print(f"exact fine patches masked={masked}: rel err {err:.2e}")
+    assert err <= 1e-10
+
+
+def test_exact_fine_patches_vcycle_fp64_and_fp32():
+    n = (16, 16)
+    lin = pnsmg.MODIFIED_NEWTON
+    prob = oracle_problem(n, CONFIG1, lin)
+    uk = inputs.uniform(91, prob.nt * prob.nv)
+    r = inputs.uniform(92, prob.nst)
+    H = O.build_hierarchy(prob, uk, n_levels=3, surrogate=False)
+    ref = O.vcycle(H, r, nu1=2, nu2=2, omega=0.3)
+    for precision, tol in ((pnsmg.FP64, 1e-10), (pnsmg.FP32, 1e-4)):
+        ctx = make_ctx(n, 3, CONFIG1, lin, uk, precision=precision, patch_kind=pnsmg.PATCH_EXACT)
+        d = ctx.vector()
+        rr = to_dev(r, ctx.dtype)
+        ctx.pns_vcycle(2, 2, 0.3, rr, d)
+        got = d.double().cpu().numpy()
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        print(f"vcycle exact fine patches prec={precision}: rel err {err:.2e}")
+        assert err <= tol

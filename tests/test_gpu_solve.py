@@ -97,8 +97,9 @@ def test_residual_without_left_trace():
     assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
-def gpu_solve(n, levels, model, vprev, precision, **params):
+def gpu_solve(n, levels, model, vprev, precision, patch_kind=pnsmg.PATCH_SURROGATE, **params):
     ctx = pnsmg.Context(n, n_levels=levels, precision=precision)
+    ctx.pns_set_patch_kind(patch_kind)
     prob = oracle_problem(n, model)
     U0 = O.state_from_velocity(prob, np.concatenate([vprev, vprev]))
     U = dev(U0)
@@ -153,3 +154,21 @@ def test_solve_reports_nonconvergence():
     assert rc == pnsmg.PNS_ENOTCONV
     assert info["newton_iterations"] == 1
     assert info["residual_final"] < info["residual_initial"]
+
+
+def test_solve_with_exact_fine_patches():
+    n = (16, 16)
+    model = dict(CONFIG1, p=1.2, delta=1e-4, nu=1e-2, nu_inf=1e-4)
+    vprev = inputs.sin_series_velocity(n, seed=202, t_nodes=[0.0])
+    rtol = 1e-10
+    rc, info, U, prob = gpu_solve(n, 3, model, vprev, pnsmg.FP64, patch_kind=pnsmg.PATCH_EXACT,
+                                  rtol=rtol, omega=0.3)
+    print(f"solve exact patches: {info}")
+    assert rc == pnsmg.PNS_OK
+    ref = O.newton_solve(prob, vprev, rtol=1e-13)
+    r_gpu = O.mass_norm(prob, O.residual(prob, U, vprev))
+    assert r_gpu <= 1.05 * rtol * ref.residual_norms[0]
+    a = without_pressure_constant(prob, U)
+    b = without_pressure_constant(prob, ref.U)
+    for idx in blocks(prob):
+        assert np.linalg.norm(a[idx] - b[idx]) <= 1e-6 * np.linalg.norm(b[idx])
