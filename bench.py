@@ -240,7 +240,7 @@ def solve_latency(n, seeds, rtol=1e-8):
 
     from paper_2603_28706_amd import inputs, pnsmg
 
-    levels = max(1, int(np.log2(n // 16)) + 1)   # coarsest level 16 x 16
+    levels = max(1, int(np.log2(n // 8)) + 1)   # coarsest level 8 x 8
     out = {}
     for prec, name in ((pnsmg.FP64, "fp64"), (pnsmg.FP32, "mixed")):
         ctx = pnsmg.Context((n, n), n_levels=levels, precision=prec)

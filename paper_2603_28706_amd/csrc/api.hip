@@ -57,7 +57,7 @@ size_t layout(pns_ctx* c, bool bind) {
     if (coarsest && c->has_coarse) {
       const int64_t n = L.g.nst;
       c->Adense = (double*)take((size_t)n * n * 8);
-      c->gjwork = (double*)take((size_t)(2 * 64 * n + 8) * 8);
+      c->gjwork = (double*)take((size_t)(2 * 64 * n + n + 8) * 8);  // panel, rows, factors
       c->gjpiv = (int*)take((size_t)n * sizeof(int));
     }
   }

@@ -603,7 +603,7 @@ __global__ void gj_panel_out_kernel(int64_t n, int64_t k0, int kb, double* __res
 // rows c and p, scale row c; one workgroup
 __global__ __launch_bounds__(1024) void gj_panel_pivot_kernel(int64_t n, int64_t k0, int kb, int jc,
                                                               double* __restrict__ P, int* piv,
-                                                              int* status) {
+                                                              int* status, double* __restrict__ F) {
   __shared__ double bv[1024];
   __shared__ int64_t bi[1024];
   const int t = threadIdx.x;
@@ -636,6 +636,12 @@ __global__ __launch_bounds__(1024) void gj_panel_pivot_kernel(int64_t n, int64_t
     piv[c] = (int)p;
     if (sing) atomicOr(status, 2);
   }
+  // elimination factors: panel column jc after the row swap (F[c] unused)
+  for (int64_t r = t; r < n; r += 1024) {
+    const int64_t src = r == c ? p : (r == p ? c : r);
+    F[r] = col[src];
+  }
+  __syncthreads();
   if (t < kb) {
     double a = P[(int64_t)t * n + p];
     if (p != c) P[(int64_t)t * n + p] = P[(int64_t)t * n + c];
@@ -643,19 +649,23 @@ __global__ __launch_bounds__(1024) void gj_panel_pivot_kernel(int64_t n, int64_t
   }
 }
 
-// eliminate panel column jc from every other row (thread per row)
-__global__ void gj_panel_elim_kernel(int64_t n, int64_t k0, int kb, int jc, double* __restrict__ P) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// eliminate panel column jc from every other row: one thread per (row, panel
+// column); the factors F are a copy of column jc taken before any update
+__global__ __launch_bounds__(256) void gj_panel_elim_kernel(int64_t n, int64_t k0, int kb, int jc,
+                                                            double* __restrict__ P,
+                                                            const double* __restrict__ F) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= n * kb) return;
+  const int j = (int)(id / n);
+  const int64_t r = id - (int64_t)j * n;
   const int64_t c = k0 + jc;
-  if (r >= n || r == c) return;
-  const double f = P[(int64_t)jc * n + r];
-  for (int j = 0; j < kb; ++j) {
-    const double pr = P[(int64_t)j * n + c];
-    if (j == jc)
-      P[(int64_t)j * n + r] = -f * pr;
-    else
-      P[(int64_t)j * n + r] -= f * pr;
-  }
+  if (r == c) return;
+  const double f = F[r];
+  const double pr = P[(int64_t)j * n + c];
+  if (j == jc)
+    P[(int64_t)j * n + r] = -f * pr;
+  else
+    P[(int64_t)j * n + r] -= f * pr;
 }
 
 // row swaps of the panel applied to column j (outside the panel), in order;
@@ -846,14 +856,17 @@ hipError_t coarse_invert(int64_t n, double* A, double* work, int* piv, int* stat
                          hipStream_t s) {
   double* P = work;
   double* T = work + (int64_t)kGjNb * n;
+  double* F = work + (int64_t)2 * kGjNb * n;
   const unsigned nb = (unsigned)((n + 255) / 256);
   for (int64_t k0 = 0; k0 < n; k0 += kGjNb) {
     const int kb = (int)((n - k0) < kGjNb ? (n - k0) : kGjNb);
+    const unsigned ne = (unsigned)((n * kb + 255) / 256);
     hipLaunchKernelGGL(gj_panel_in_kernel, dim3(nb), dim3(256), 0, s, n, k0, kb, A, P);
     for (int jc = 0; jc < kb; ++jc) {
       hipLaunchKernelGGL(gj_panel_pivot_kernel, dim3(1), dim3(1024), 0, s, n, k0, kb, jc, P, piv,
-                         status);
-      hipLaunchKernelGGL(gj_panel_elim_kernel, dim3(nb), dim3(256), 0, s, n, k0, kb, jc, P);
+                         status, F);
+      hipLaunchKernelGGL(gj_panel_elim_kernel, dim3(ne), dim3(256), 0, s, n, k0, kb, jc, P,
+                         (const double*)F);
     }
     const int64_t m = n - kb;
     if (m > 0) {
