@@ -272,6 +272,59 @@ def solve_latency(n, seeds, rtol=1e-8):
     return out
 
 
+def serve_latency(n_req=48, rate=20.0, slots=4, seed=501):
+    """Poisson stream of independent slab-solve requests through the native
+    request server: meshes from {32^2, 64^2, 128^2, 256^2}, p ~ U[1.6, 1.9],
+    delta ~ logU[1e-3, 1e-1], nu_inf ~ logU[1e-4, 1e-2], nu = 0.1, left traces
+    from the sin-series recipe (seed 501 + i), each solved to 1e-8.  Three
+    runs of the same stream: FP64 with one slot (a plain queue), FP64 and
+    mixed precision with `slots` concurrent requests."""
+    import numpy as np
+
+    from paper_2603_28706_amd import inputs, pnsmg
+
+    rng = inputs.rng(seed)
+    sizes = [32, 64, 128, 256]
+    reqs = []
+    for i in range(n_req):
+        n = int(sizes[rng.integers(0, 4)])
+        model = dict(SOLVE_MODEL, p=float(rng.uniform(1.6, 1.9)),
+                     delta=float(10 ** rng.uniform(-3, -1)),
+                     nu_inf=float(10 ** rng.uniform(-4, -2)))
+        reqs.append((n, model, seed + i))
+    gaps = rng.exponential(1.0 / rate, n_req)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    vps = [inputs.sin_series_velocity((n, n), seed=sd, t_nodes=[0.0]) for n, _, sd in reqs]
+    out = {}
+    for name, prec, nslots in (("fp64_queue", pnsmg.FP64, 1), ("fp64", pnsmg.FP64, slots),
+                               ("mixed", pnsmg.FP32, slots)):
+        srv = pnsmg.Server(slots=nslots, arena_bytes=24 << 30)
+        tickets, keep = [], []
+        t0 = time.perf_counter()
+        for (n, model, _), vp, ta in zip(reqs, vps, arrivals):
+            dt = t0 + ta - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            U = np.zeros(2 * (2 * (2 * n + 1) ** 2 + 3 * n * n))
+            levels = max(1, int(np.log2(n // 8)) + 1)
+            q = pnsmg.make_request((n, n), model, vp, U, levels, precision=prec)
+            tickets.append(srv.submit(q, keep=(vp, U)))
+            keep.append(U)
+        res = [srv.wait(t) for t in tickets]
+        srv.close()
+        lat = np.array([r["t_done"] - r["t_submit"] for r in res])
+        span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+        dof = sum(2 * (2 * (2 * n + 1) ** 2 + 3 * n * n) for n, _, _ in reqs)
+        ok = sum(r["status"] == pnsmg.PNS_OK for r in res)
+        out[name] = dict(p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
+                         solves_per_s=n_req / span, mdof_per_s=dof / span / 1e6,
+                         converged=f"{ok}/{n_req}", slots=nslots)
+        print(f"[bench] serve {name}: p50 {out[name]['p50_s']:.3f} s, p99 "
+              f"{out[name]['p99_s']:.3f} s, {out[name]['solves_per_s']:.2f} solves/s, "
+              f"converged {ok}/{n_req}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -283,6 +336,8 @@ def main():
     ap.add_argument("--apply-only", action="store_true")
     ap.add_argument("--solve-n", type=int, default=256,
                     help="mesh of the slab-solve latency measurement (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=48,
+                    help="requests of the serving measurement (0: skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain streaming kernel of known size (counter calibration)")
     ap.add_argument("--lin", type=int, default=2, help="0 Picard, 1 exact Newton, 2 modified Newton")
@@ -345,6 +400,14 @@ def main():
             **{k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                for k, v in sl.items()},
             "mixed_speedup_p50": round(sl["fp64"]["p50_s"] / sl["mixed"]["p50_s"], 3)}
+    if args.serve_requests and not args.apply_only:
+        sv = serve_latency(args.serve_requests)
+        line["serving"] = {
+            "workload": (f"{args.serve_requests} slab solves to 1e-8, Poisson arrivals 20/s (seed "
+                         f"501), meshes U{{32,64,128,256}}^2, p~U[1.6,1.9], delta~logU[1e-3,1e-1], "
+                         f"nu_inf~logU[1e-4,1e-2], nu=0.1; native server, arena-admitted"),
+            **{k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+               for k, v in sv.items()}}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

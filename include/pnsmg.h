@@ -273,6 +273,68 @@ int pns_solve(pns_ctx* ctx, const pns_model* model, const double* v_prev_dev, do
               const pns_solve_params* prm, void* work_dev, size_t work_bytes,
               pns_solve_info* info);
 
+/* ---------------------------------------------------------------- serving */
+
+/* A request server for independent slab solves (each one the Newton-Krylov
+ * solve of pns_solve on its own mesh and model).  `slots` requests run at
+ * once, each on its own HIP stream driven by its own host worker thread, so
+ * the kernels of different requests overlap on the device.  Requests are
+ * admitted in arrival order as a slot and room in the device arena free up;
+ * a request that does not fit yet lets smaller later ones start (backfill).
+ * The server allocates no device memory: every running request takes its
+ * workspace, Krylov vectors and solution vector from the caller's arena and
+ * returns them on completion.  All entry points are thread-safe. */
+typedef struct pns_server pns_server;
+
+typedef struct {
+  int n_cells[2];            /* mesh n_x x n_y of the box [lo, hi] */
+  double lo[2], hi[2];
+  double tau;                /* slab length */
+  int n_levels;              /* multigrid levels; the coarsest must fit the dense solve */
+  int precision;             /* PNS_FP64, or PNS_FP32 for the mixed-precision solve */
+  int patch_kind;            /* pns_patch_kind of the finest level */
+  pns_model model;
+  pns_solve_params params;
+  const double* v_prev_host; /* left-trace velocity, host, 2 (2n_x+1)(2n_y+1) doubles; copied */
+  double* U_host;            /* host buffer of N_st doubles receiving the last iterate */
+} pns_request;
+
+enum { PNS_REQ_QUEUED = 0, PNS_REQ_RUNNING = 1, PNS_REQ_DONE = 2 };
+
+typedef struct {
+  int state;                 /* PNS_REQ_QUEUED / RUNNING / DONE */
+  int status;                /* return code of the solve once DONE */
+  pns_solve_info info;
+  double t_submit, t_start, t_done;  /* seconds on the server's steady clock */
+  size_t footprint;          /* arena bytes the request holds while running */
+} pns_result;
+
+/* Arena bytes one request needs (context workspace, solve work buffer, U and
+ * v_prev, alignment); 0 if the request is invalid. */
+size_t pns_request_footprint(const pns_request* req);
+
+/* Create a server on the current device with `slots` (1..16) concurrent
+ * solves working in [arena_dev, arena_dev + arena_bytes) (device memory,
+ * 256-byte aligned, owned by the caller, untouched outside running requests).
+ * PNS_EINVAL for bad arguments, PNS_EHIP if a stream cannot be created. */
+int pns_server_create(int slots, void* arena_dev, size_t arena_bytes, pns_server** out);
+
+/* Queue a request (Sec. 5.3 slab solve, as pns_solve); the request struct and
+ * v_prev_host are copied, U_host must stay valid until the request is DONE.
+ * *ticket identifies it.  PNS_EINVAL if the request is invalid,
+ * PNS_EWORKSPACE if its footprint exceeds the whole arena. */
+int pns_solve_request(pns_server* srv, const pns_request* req, uint64_t* ticket);
+
+/* State of a request, without blocking; PNS_EINVAL for an unknown ticket. */
+int pns_poll(pns_server* srv, uint64_t ticket, pns_result* out);
+
+/* Block until the request is DONE, then as pns_poll. */
+int pns_wait(pns_server* srv, uint64_t ticket, pns_result* out);
+
+/* Finish every queued and running request, then release the streams and
+ * worker threads. */
+void pns_server_destroy(pns_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -62,6 +62,23 @@ class pns_solve_info(ctypes.Structure):
                 ("residual_initial", ctypes.c_double), ("residual_final", ctypes.c_double)]
 
 
+class pns_request(ctypes.Structure):
+    _fields_ = [("n_cells", ctypes.c_int * 2), ("lo", ctypes.c_double * 2),
+                ("hi", ctypes.c_double * 2), ("tau", ctypes.c_double),
+                ("n_levels", ctypes.c_int), ("precision", ctypes.c_int),
+                ("patch_kind", ctypes.c_int), ("model", pns_model),
+                ("params", pns_solve_params), ("v_prev_host", ctypes.POINTER(ctypes.c_double)),
+                ("U_host", ctypes.POINTER(ctypes.c_double))]
+
+
+class pns_result(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int), ("status", ctypes.c_int), ("info", pns_solve_info),
+                ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("footprint", ctypes.c_size_t)]
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
+
 SOLVE_DEFAULTS = dict(max_newton=30, max_krylov=200, restart=30, rtol=1e-8, atol=0.0, eta0=0.1,
                       eta_max=0.5, rho=0.5, nu1=2, nu2=2, omega=0.1)
 
@@ -109,6 +126,16 @@ def lib():
         L.pns_solve_workspace_bytes.restype = ctypes.c_size_t
         L.pns_solve.argtypes = [_vp, pp(pns_model), _vp, _vp, pp(pns_solve_params), _vp,
                                 ctypes.c_size_t, pp(pns_solve_info)]
+        L.pns_request_footprint.argtypes = [pp(pns_request)]
+        L.pns_request_footprint.restype = ctypes.c_size_t
+        L.pns_server_create.argtypes = [i, _vp, ctypes.c_size_t, pp(_vp)]
+        L.pns_solve_request.argtypes = [_vp, pp(pns_request), pp(ctypes.c_uint64)]
+        L.pns_poll.argtypes = [_vp, ctypes.c_uint64, pp(pns_result)]
+        L.pns_wait.argtypes = [_vp, ctypes.c_uint64, pp(pns_result)]
+        L.pns_server_destroy.argtypes = [_vp]
+        L.pns_server_destroy.restype = None
+        for f in ("pns_server_create", "pns_solve_request", "pns_poll", "pns_wait"):
+            getattr(L, f).restype = ctypes.c_int
         for f in ("pns_ctx_create", "pns_level_sizes", "pns_bind_workspace", "pns_set_state",
                   "pns_set_apply_mode", "pns_set_patch_kind",
                   "pns_cell_apply", "pns_cell_defect", "pns_vanka_setup", "pns_vanka_smooth",
@@ -274,3 +301,79 @@ def masks_to_bits(masks):
     masks = np.asarray(masks)
     return (masks.astype(np.uint16) << np.arange(masks.shape[1], dtype=np.uint16)).sum(
         axis=1).astype(np.uint16)
+
+
+def make_request(n, model: dict, vprev, U_out, levels, precision=FP64, tau=0.01,
+                 patch_kind=PATCH_SURROGATE, lo=(0.0, 0.0), hi=(1.0, 1.0), **params):
+    """pns_request for an n[0] x n[1] slab solve; vprev and U_out are float64
+    numpy arrays that must stay alive until the request is done."""
+    assert vprev.dtype == np.float64 and vprev.flags.c_contiguous
+    assert U_out.dtype == np.float64 and U_out.flags.c_contiguous
+    prm = dict(SOLVE_DEFAULTS, **params)
+    q = pns_request()
+    q.n_cells[0], q.n_cells[1] = int(n[0]), int(n[1])
+    q.lo[0], q.lo[1] = float(lo[0]), float(lo[1])
+    q.hi[0], q.hi[1] = float(hi[0]), float(hi[1])
+    q.tau = float(tau)
+    q.n_levels = int(levels)
+    q.precision = int(precision)
+    q.patch_kind = int(patch_kind)
+    q.model = model_struct(model)
+    q.params = pns_solve_params(*(prm[f] for f, _ in pns_solve_params._fields_))
+    q.v_prev_host = vprev.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    q.U_host = U_out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return q
+
+
+def result_dict(r: pns_result):
+    return dict(state=r.state, status=r.status, t_submit=r.t_submit, t_start=r.t_start,
+                t_done=r.t_done, footprint=r.footprint,
+                **{f: getattr(r.info, f) for f, _ in pns_solve_info._fields_})
+
+
+class Server:
+    """A pns_server over a device arena (a torch uint8 tensor)."""
+
+    def __init__(self, slots, arena_bytes, device="cuda"):
+        import torch
+
+        self.arena = torch.empty(arena_bytes + 256, dtype=torch.uint8, device=device)
+        base = (self.arena.data_ptr() + 255) // 256 * 256
+        h = _vp()
+        rc = lib().pns_server_create(int(slots), _vp(base), int(arena_bytes), ctypes.byref(h))
+        if rc != PNS_OK:
+            raise PnsError(rc, "pns_server_create failed")
+        self.h = h
+        self._keep = {}
+
+    def footprint(self, req):
+        return lib().pns_request_footprint(ctypes.byref(req))
+
+    def submit(self, req, keep=()):
+        t = ctypes.c_uint64()
+        rc = lib().pns_solve_request(self.h, ctypes.byref(req), ctypes.byref(t))
+        if rc != PNS_OK:
+            raise PnsError(rc, "pns_solve_request rejected the request")
+        self._keep[t.value] = (req, keep)
+        return t.value
+
+    def poll(self, ticket):
+        r = pns_result()
+        if lib().pns_poll(self.h, ctypes.c_uint64(ticket), ctypes.byref(r)) != PNS_OK:
+            raise PnsError(PNS_EINVAL, "unknown ticket")
+        return result_dict(r)
+
+    def wait(self, ticket):
+        r = pns_result()
+        if lib().pns_wait(self.h, ctypes.c_uint64(ticket), ctypes.byref(r)) != PNS_OK:
+            raise PnsError(PNS_EINVAL, "unknown ticket")
+        return result_dict(r)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pns_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        if _lib is not None:
+            self.close()

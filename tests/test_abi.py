@@ -98,3 +98,24 @@ def test_solve_and_residual_reject_calls_without_workspace():
         assert rc == pnsmg.PNS_EWORKSPACE
     finally:
         L.pns_ctx_destroy(h)
+
+
+def test_server_entry_points_reject_bad_arguments():
+    import numpy as np
+
+    L = pnsmg.lib()
+    h = ctypes.c_void_p()
+    assert L.pns_server_create(0, None, 0, ctypes.byref(h)) == pnsmg.PNS_EINVAL
+    assert L.pns_server_create(17, ctypes.c_void_p(256), 1 << 20, ctypes.byref(h)) == pnsmg.PNS_EINVAL
+    assert L.pns_server_create(1, ctypes.c_void_p(100), 1 << 20, ctypes.byref(h)) == pnsmg.PNS_EINVAL
+    # request sizes are computed on the host: invalid requests have no footprint
+    vp = np.zeros(2 * 17 * 17)
+    U = np.zeros(2 * (2 * 17 * 17 + 3 * 64))
+    good = pnsmg.make_request((8, 8), dict(p=1.5, delta=1e-2), vp, U, levels=2)
+    assert L.pns_request_footprint(ctypes.byref(good)) > 0
+    bad_p = pnsmg.make_request((8, 8), dict(p=2.5, delta=1e-2), vp, U, levels=2)
+    assert L.pns_request_footprint(ctypes.byref(bad_p)) == 0
+    bad_levels = pnsmg.make_request((8, 8), dict(p=1.5, delta=1e-2), vp, U, levels=5)
+    assert L.pns_request_footprint(ctypes.byref(bad_levels)) == 0
+    too_big_coarse = pnsmg.make_request((256, 256), dict(p=1.5, delta=1e-2), vp, U, levels=1)
+    assert L.pns_request_footprint(ctypes.byref(too_big_coarse)) == 0

@@ -1,0 +1,136 @@
+"""GPU tests of the request server (continuous batching of independent slab
+solves) through the C-ABI.
+
+Each served result is compared with a direct pns_solve of the same request
+and with the same request served inside a mix: both reach the same stopping
+test along the same iteration path, so they agree far below the solve
+tolerance (the only difference is the summation order of LDS sums inside the
+Jacobian action); 1e-9 relative is required.  The oracle's residual of a
+served result must meet the stopping test.
+"""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2603_28706_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2603_28706_amd import pnsmg  # noqa: E402
+
+MODEL = dict(p=1.8, delta=1e-2, nu=0.1, nu_inf=1e-4, gamma1=40.0, gamma2=40.0, sigma_max=1.0,
+             convection=1, qsign=1, lin=pnsmg.MODIFIED_NEWTON)
+
+
+def nst(n):
+    return 2 * (2 * (2 * n[0] + 1) * (2 * n[1] + 1) + 3 * n[0] * n[1])
+
+
+def request(n, seed, levels, precision=pnsmg.FP64, model=MODEL, **params):
+    vprev = inputs.sin_series_velocity(n, seed=seed, t_nodes=[0.0])
+    U = np.zeros(nst(n))
+    q = pnsmg.make_request(n, model, vprev, U, levels, precision=precision, **params)
+    return q, vprev, U
+
+
+def direct_solve(n, seed, levels, precision=pnsmg.FP64, model=MODEL):
+    vprev = inputs.sin_series_velocity(n, seed=seed, t_nodes=[0.0])
+    ctx = pnsmg.Context(n, n_levels=levels, precision=precision)
+    sz = ctx.sizes(0)
+    U0 = np.zeros(sz["nst"])
+    U0[:sz["nv"]] = vprev
+    U0[sz["ns"]:sz["ns"] + sz["nv"]] = vprev
+    U = torch.tensor(U0, device="cuda")
+    rc, info = ctx.pns_solve(model, torch.tensor(vprev, device="cuda"), U)
+    torch.cuda.synchronize()
+    return rc, info, U.cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_served_result_equals_direct_solve_and_oracle_residual():
+    n = (16, 16)
+    srv = pnsmg.Server(slots=2, arena_bytes=256 << 20)
+    q, vprev, U = request(n, 211, 2)
+    t = srv.submit(q, keep=(vprev, U))
+    res = srv.wait(t)
+    srv.close()
+    print("served", res)
+    assert res["state"] == pnsmg.REQ_DONE and res["status"] == pnsmg.PNS_OK
+    rc, info, Ud = direct_solve(n, 211, 2)
+    assert rc == pnsmg.PNS_OK
+    assert res["newton_iterations"] == info["newton_iterations"]
+    assert rel(U, Ud) <= 1e-9
+    prob = O.Problem(n=n, p=MODEL["p"], delta=MODEL["delta"], nu=MODEL["nu"],
+                     nu_inf=MODEL["nu_inf"], lin=O.MODIFIED_NEWTON)
+    r0 = O.mass_norm(prob, O.residual(prob, O.state_from_velocity(
+        prob, np.concatenate([vprev, vprev])), vprev))
+    r = O.mass_norm(prob, O.residual(prob, U, vprev))
+    assert r <= 1.05 * 1e-8 * r0
+
+
+def test_result_is_the_same_alone_and_in_a_mix():
+    target = ((32, 32), 303, 3, pnsmg.FP32)
+    srv = pnsmg.Server(slots=3, arena_bytes=1 << 30)
+    q, vprev, U_alone = request(target[0], target[1], target[2], precision=target[3])
+    srv.wait(srv.submit(q, keep=(vprev, U_alone)))
+    # the same request among others of mixed sizes and precisions
+    mix = [((16, 16), 301, 2, pnsmg.FP64), ((64, 64), 302, 4, pnsmg.FP64), target,
+           ((32, 32), 304, 3, pnsmg.FP64), ((16, 16), 305, 2, pnsmg.FP32),
+           ((64, 64), 306, 4, pnsmg.FP32)]
+    tickets, outs = [], []
+    for (n, seed, lv, prec) in mix:
+        q, vp, U = request(n, seed, lv, precision=prec)
+        tickets.append(srv.submit(q, keep=(vp, U)))
+        outs.append(U)
+    results = [srv.wait(t) for t in tickets]
+    srv.close()
+    for r in results:
+        assert r["status"] == pnsmg.PNS_OK, r
+    err = rel(outs[2], U_alone)
+    print(f"alone vs mix: rel diff {err:.2e}")
+    assert err <= 1e-9
+    # the slots ran concurrently: some running intervals overlap
+    iv = sorted((r["t_start"], r["t_done"]) for r in results)
+    assert any(iv[i + 1][0] < iv[i][1] for i in range(len(iv) - 1))
+
+
+def test_admission_respects_the_arena():
+    reqs = [request((32, 32), 320 + i, 3) for i in range(5)]
+    srv0 = pnsmg.Server(slots=1, arena_bytes=1 << 20)
+    fp = srv0.footprint(reqs[0][0])
+    srv0.close()
+    assert fp > 0
+    # room for two requests at a time although four slots are free
+    arena = int(2.5 * fp)
+    srv = pnsmg.Server(slots=4, arena_bytes=arena)
+    tickets = [srv.submit(q, keep=(v, U)) for (q, v, U) in reqs]
+    results = [srv.wait(t) for t in tickets]
+    srv.close()
+    assert all(r["status"] == pnsmg.PNS_OK for r in results)
+    events = sorted([(r["t_start"], r["footprint"]) for r in results] +
+                    [(r["t_done"], -r["footprint"]) for r in results],
+                    key=lambda e: (e[0], e[1]))
+    held = 0
+    for _, f in events:
+        held += f
+        assert held <= arena
+    assert max(sum(1 for r in results if r["t_start"] <= t < r["t_done"])
+               for t, _ in events) <= 2
+
+
+def test_rejects_requests_larger_than_the_arena():
+    srv = pnsmg.Server(slots=1, arena_bytes=1 << 20)
+    q, vprev, U = request((32, 32), 330, 3)
+    with pytest.raises(pnsmg.PnsError) as e:
+        srv.submit(q, keep=(vprev, U))
+    assert e.value.code == pnsmg.PNS_EWORKSPACE
+    srv.close()
