@@ -10,6 +10,8 @@
 //   that patches updating d at the same time share no unknown;
 // * restriction P^T and prolongation P of the nested Q2 / P1disc spaces;
 // * dense coarsest solve with the stored inverse.
+#include <type_traits>
+
 #include "pns_internal.h"
 
 namespace pns {
@@ -235,37 +237,45 @@ template <typename T>
 __global__ __launch_bounds__(256) void dense_gemv_kernel(int64_t n, const double* __restrict__ Ainv,
                                                          const T* __restrict__ r, T* __restrict__ d,
                                                          int64_t pin0, int64_t pin1) {
+  // one wave per row, 16-byte loads of the row and of r, 8 loads in flight;
+  // the pinned entries of r count as zero: their products are taken out once
+  using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= n) return;
-  const double* A = Ainv + row * n;
+  const double2* A = reinterpret_cast<const double2*>(Ainv + row * n);
+  const T2* r2 = reinterpret_cast<const T2*>(r);
   double acc0 = 0.0, acc1 = 0.0;
   const int64_t npair = n >> 1;
   int64_t q = lane;
-  for (; q + 192 < npair; q += 256) {
-    double2 a[4];
+  for (; q + 448 < npair; q += 512) {
+    double2 a[8];
+    T2 b[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) a[u] = reinterpret_cast<const double2*>(A)[q + 64 * u];
+    for (int u = 0; u < 8; ++u) {
+      a[u] = A[q + 64 * u];
+      b[u] = r2[q + 64 * u];
+    }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t j = 2 * (q + 64 * u);
-      const double r0 = (j == pin0 || j == pin1) ? 0.0 : (double)r[j];
-      const double r1 = (j + 1 == pin0 || j + 1 == pin1) ? 0.0 : (double)r[j + 1];
-      acc0 += a[u].x * r0;
-      acc1 += a[u].y * r1;
+    for (int u = 0; u < 8; ++u) {
+      acc0 += a[u].x * (double)b[u].x;
+      acc1 += a[u].y * (double)b[u].y;
     }
   }
   for (; q < npair; q += 64) {
-    const double2 a = reinterpret_cast<const double2*>(A)[q];
-    const int64_t j = 2 * q;
-    const double r0 = (j == pin0 || j == pin1) ? 0.0 : (double)r[j];
-    const double r1 = (j + 1 == pin0 || j + 1 == pin1) ? 0.0 : (double)r[j + 1];
-    acc0 += a.x * r0;
-    acc1 += a.y * r1;
+    const double2 a = A[q];
+    const T2 b = r2[q];
+    acc0 += a.x * (double)b.x;
+    acc1 += a.y * (double)b.y;
   }
   double acc = acc0 + acc1;
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-  if (lane == 0) d[row] = (T)acc;
+  if (lane == 0) {
+    const double* Ar = Ainv + row * n;
+    if (pin0 >= 0) acc -= Ar[pin0] * (double)r[pin0];
+    if (pin1 >= 0) acc -= Ar[pin1] * (double)r[pin1];
+    d[row] = (T)acc;
+  }
 }
 
 template <typename T>
@@ -349,7 +359,9 @@ hipError_t launch_prolong_add(const Grid& gf, const Grid& gc, const T* dc, T* df
 template <typename T>
 hipError_t launch_dense_gemv(int64_t n, const double* Ainv, const T* r, T* d, const int64_t* pin,
                              int npin, hipStream_t s) {
-  if (n & 1) return hipErrorInvalidValue;  // space-time sizes are 2 * ns: rows 16-byte aligned
+  // space-time sizes are 2 ns: rows are 16-byte aligned; r is read in pairs
+  if ((n & 1) || ((uintptr_t)r % (2 * sizeof(T))) != 0 || ((uintptr_t)Ainv % 16) != 0)
+    return hipErrorInvalidValue;
   const int64_t p0 = npin > 0 ? pin[0] : -1, p1 = npin > 1 ? pin[1] : -1;
   hipLaunchKernelGGL(dense_gemv_kernel<T>, dim3(nblk(n, 4)), dim3(256), 0, s, n, Ainv, r, d, p0,
                      p1);
