@@ -325,6 +325,62 @@ def serve_latency(n_req=48, rate=20.0, slots=4, seed=501):
     return out
 
 
+def batched_vanka(n=512, sweeps=20):
+    """Finest-level smoother alone at n x n in FP32 with boundary-truncated
+    (uneven) patches: patch entries from the surrogate tangent at p = 1.1,
+    delta = 1e-5, nu_inf = 1e-4 (state: sin-series, seed 401; masks seed 402).
+    Setup (element matrices + batched patch factorisation) and one additive
+    Vanka step (global defect + all patch solves), for the midpoint-frozen
+    surrogate patches (complex 21x21 time-diagonal factors) and the exact
+    42x42 patches.  Factor GB/s = factor bytes / (step - defect)."""
+    import numpy as np
+    import torch
+
+    from paper_2603_28706_amd import inputs, pnsmg
+
+    model = dict(MODEL, p=1.1, delta=1e-5, nu_inf=1e-4, lin=2)
+    uk = torch.tensor(inputs.sin_series_velocity((n, n), seed=401, t_nodes=[0.01 / 3, 0.01]),
+                      device="cuda")
+    masks = pnsmg.masks_to_bits(inputs.truncation_masks((n, n), seed=402))
+    out = {}
+    for kind, name, vals in ((pnsmg.PATCH_SURROGATE, "surrogate_complex21", 2 * 21 * 21),
+                             (pnsmg.PATCH_EXACT, "exact_real42", 42 * 42)):
+        ctx = pnsmg.Context((n, n), n_levels=1, precision=pnsmg.FP32)
+        ctx.pns_set_patch_kind(kind)
+        ctx.pns_set_state(model, uk)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.pns_vanka_setup(masks)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        r = torch.tensor(inputs.uniform(403, ctx.sizes()["nst"]), dtype=torch.float32, device="cuda")
+        d = ctx.vector()
+        y = ctx.vector()
+        ctx.pns_vanka_smooth(0, 1, OMEGA, r, d)
+        ea, eb, ec = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        stream = torch.cuda.current_stream()
+        ea.record(stream)
+        for _ in range(sweeps):
+            ctx.pns_vanka_smooth(0, 1, OMEGA, r, d)
+        eb.record(stream)
+        for _ in range(sweeps):
+            ctx.pns_cell_defect(r, d, y)
+        ec.record(stream)
+        torch.cuda.synchronize()
+        t_step = ea.elapsed_time(eb) * 1e-3 / sweeps
+        t_def = eb.elapsed_time(ec) * 1e-3 / sweeps
+        fbytes = n * n * vals * 4
+        out[name] = dict(setup_s=t_setup, step_ms=t_step * 1e3, defect_ms=t_def * 1e3,
+                         factor_mb=fbytes / 1e6, factor_gbs=fbytes / max(t_step - t_def, 1e-9) / 1e9)
+        print(f"[bench] batched Vanka {n}x{n} {name}: setup {t_setup:.3f} s, step "
+              f"{t_step * 1e3:.3f} ms (defect {t_def * 1e3:.3f} ms), factors "
+              f"{fbytes / 1e6:.0f} MB at {out[name]['factor_gbs']:.0f} GB/s", file=sys.stderr,
+              flush=True)
+        del ctx
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -336,6 +392,8 @@ def main():
     ap.add_argument("--apply-only", action="store_true")
     ap.add_argument("--solve-n", type=int, default=256,
                     help="mesh of the slab-solve latency measurement (0: skip)")
+    ap.add_argument("--vanka-n", type=int, default=512,
+                    help="mesh of the batched-Vanka measurement (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests of the serving measurement (0: skip)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -400,6 +458,13 @@ def main():
             **{k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                for k, v in sl.items()},
             "mixed_speedup_p50": round(sl["fp64"]["p50_s"] / sl["mixed"]["p50_s"], 3)}
+    if args.vanka_n and not args.apply_only:
+        bv = batched_vanka(args.vanka_n)
+        line["batched_vanka"] = {
+            "workload": (f"{args.vanka_n}x{args.vanka_n} finest-level additive Vanka, FP32, "
+                         f"boundary-truncated patches (30-42 unknowns), surrogate tangent "
+                         f"p=1.1 delta=1e-5"),
+            **{k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in bv.items()}}
     if args.serve_requests and not args.apply_only:
         sv = serve_latency(args.serve_requests)
         line["serving"] = {
