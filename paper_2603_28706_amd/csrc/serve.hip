@@ -139,7 +139,7 @@ struct pns_server {
 namespace {
 
 // one request on one stream: context, workspace and vectors carved from mem
-int run_request(Req* r, hipStream_t s) {
+int run_request(Req* r, hipStream_t s, pns_solve_info* info) {
   const pns_request& q = r->q;
   pns_mesh m{};
   m.dim = 2;
@@ -174,7 +174,7 @@ int run_request(Req* r, hipStream_t s) {
     if (!ok) {
       rc = PNS_EHIP;
     } else {
-      rc = pns_solve(c, &q.model, vp, U, &q.params, work, r->sz.solve, &r->res.info);
+      rc = pns_solve(c, &q.model, vp, U, &q.params, work, r->sz.solve, info);
       if (rc == PNS_OK || rc == PNS_ENOTCONV) {
         if (hipMemcpyAsync(q.U_host, U, r->sz.nst * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
@@ -211,8 +211,11 @@ void worker_main(pns_server* S, int slot) {
     r->res.state = PNS_REQ_RUNNING;
     r->res.t_start = now_s();
     lk.unlock();
-    const int rc = run_request(r, s);
+    // the request's result is written only under the lock (pns_poll reads it)
+    pns_solve_info info{};
+    const int rc = run_request(r, s, &info);
     lk.lock();
+    r->res.info = info;
     S->arena.give(r->mem, r->footprint);
     r->mem = nullptr;
     r->res.status = rc;
