@@ -78,7 +78,12 @@ typedef enum { PNS_APPLY_RECOMPUTE = 0, PNS_APPLY_CACHED = 1 } pns_apply_mode;
  *   coarse levels. */
 typedef enum { PNS_PATCH_SURROGATE = 0, PNS_PATCH_EXACT = 1 } pns_patch_kind;
 
-/* Box [lo, hi] with n_cells[k] uniform cells per direction; dim must be 2. */
+/* Box [lo, hi] with n_cells[k] uniform cells per direction.  dim = 2
+ * (quadrilaterals; n_cells[2], lo[2], hi[2] unused) or dim = 3 (hexahedra).
+ * Canonical layout of one Radau node's spatial block: velocity component c
+ * at c*nn + node, nodes lexicographic with x fastest over the (2n_k+1) Q2
+ * nodes per direction (nn nodes); then the d+1 P1disc coefficients of each
+ * cell (cells lexicographic, x fastest) in the basis 1, (x_k - xc_k)/h_k. */
 typedef struct {
   int dim;
   int n_cells[3];
@@ -119,7 +124,11 @@ typedef struct pns_ctx pns_ctx;
  * (and so pns_vcycle) is available when the coarsest level has at most 40000
  * space-time unknowns; larger coarsest levels still allow the apply and the
  * smoother.  `stream` is a hipStream_t (NULL =
- * default stream).  Returns PNS_EINVAL / PNS_EUNSUPPORTED on bad input. */
+ * default stream).  A dim = 3 mesh gives an action-only context: n_levels
+ * must be 1; pns_set_state, pns_cell_apply, pns_cell_defect and the size and
+ * workspace queries work, every smoother, V-cycle and solve entry point
+ * returns PNS_EUNSUPPORTED and pns_solve_workspace_bytes returns 0.
+ * Returns PNS_EINVAL / PNS_EUNSUPPORTED on bad input. */
 int pns_ctx_create(const pns_mesh* mesh, const pns_discretization* disc, int n_levels,
                    int precision, void* stream, pns_ctx** out);
 
@@ -143,13 +152,13 @@ size_t pns_workspace_bytes(const pns_ctx* ctx);
 int pns_bind_workspace(pns_ctx* ctx, void* ws_dev, size_t bytes);
 
 /* Set the linearisation point: u_k_dev holds the velocity (FP64) at both
- * Radau nodes, 2 blocks of d*(2n_x+1)(2n_y+1) values in the canonical
- * velocity layout.  Copies it into the workspace.  Invalidates the smoother. */
+ * Radau nodes, 2 blocks of d*nn values in the canonical velocity layout.  Copies it into the workspace.  Invalidates the smoother. */
 int pns_set_state(pns_ctx* ctx, const pns_model* model, const double* u_k_dev);
 
 /* Select the apply mode (default PNS_APPLY_RECOMPUTE).  Switching to CACHED
  * after pns_set_state builds the cache from the current state; returns
- * PNS_EINVAL for an unknown mode. */
+ * PNS_EINVAL for an unknown mode, PNS_EUNSUPPORTED for CACHED on a 3D
+ * context (3D actions always recompute the tangent). */
 int pns_set_apply_mode(pns_ctx* ctx, int mode);
 
 /* Select the finest-level patch matrices (default PNS_PATCH_SURROGATE); a
@@ -162,7 +171,8 @@ int pns_set_patch_kind(pns_ctx* ctx, int kind);
  * linearisation of Sec. 5.2 (viscous volume term with the selected tangent,
  * convection, pressure coupling, boundary flux and Nitsche terms) at u_k of
  * Radau node mu.  Matrix-free; x, y in the context precision, canonical
- * layout, must not alias. */
+ * layout, must not alias.  Contributions are summed with atomics, so the
+ * summation order (and the last bits of y) may vary from call to call. */
 int pns_cell_apply(pns_ctx* ctx, const void* x_dev, void* y_dev);
 
 /* Same operator as pns_cell_apply, y = b - J_n x (the global defect). */

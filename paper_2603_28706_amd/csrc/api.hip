@@ -35,6 +35,7 @@ size_t layout(pns_ctx* c, bool bind) {
   const size_t es = c->es;
   c->uk = take(2 * g0.nv * es);
   c->uk64 = (double*)take(2 * g0.nv * 8);
+  if (c->dim == 3) return (off + kAlign - 1) / kAlign * kAlign;  // action only
   c->urep = (double*)take(g0.nv * 8);
   c->Es0 = (double*)take(g0.nc * kNs * kNs * 8);
   c->Es1 = (double*)take(g0.nc * kNs * kNs * 8);
@@ -97,6 +98,9 @@ const T* tangent_cache(pns_ctx* c) {
 template <typename T>
 hipError_t defect(pns_ctx* c, int l, const T* b, const T* x, T* y) {
   Level& L = c->lev[l];
+  if (c->dim == 3)
+    return launch_cell_apply3d<T>(c->g3, c->model, c->disc.tau, (const T*)c->uk, x, b, y, 1,
+                                  c->stream);
   if (l == 0)
     return launch_cell_apply<T>(L.g, c->model, c->disc.tau, (const T*)c->uk, tangent_cache<T>(c),
                                 x, b, y, 1, c->stream);
@@ -106,6 +110,9 @@ hipError_t defect(pns_ctx* c, int l, const T* b, const T* x, T* y) {
 template <typename T>
 hipError_t apply_level(pns_ctx* c, int l, const T* x, T* y) {
   Level& L = c->lev[l];
+  if (c->dim == 3)
+    return launch_cell_apply3d<T>(c->g3, c->model, c->disc.tau, (const T*)c->uk, x, x, y, 0,
+                                  c->stream);
   if (l == 0)
     return launch_cell_apply<T>(L.g, c->model, c->disc.tau, (const T*)c->uk, tangent_cache<T>(c),
                                 x, x, y, 0, c->stream);
@@ -227,6 +234,49 @@ int vanka_setup_impl(pns_ctx* c, const uint16_t* masks) {
   return PNS_OK;
 }
 
+// 3D context: hexahedra, the level-0 action only
+int create3d(const pns_mesh* mesh, const pns_discretization* disc, int n_levels, int precision,
+             void* stream, pns_ctx** out) {
+  if (disc->k_space != 2 || disc->k_time != 1) return PNS_EUNSUPPORTED;
+  if (precision != PNS_FP64 && precision != PNS_FP32) return PNS_EINVAL;
+  if (!(disc->tau > 0.0) || n_levels < 1) return PNS_EINVAL;
+  if (n_levels != 1) return PNS_EUNSUPPORTED;
+  const int nx = mesh->n_cells[0], ny = mesh->n_cells[1], nz = mesh->n_cells[2];
+  if (nx < 1 || ny < 1 || nz < 1) return PNS_EINVAL;
+  double len[3];
+  for (int k = 0; k < 3; ++k) {
+    len[k] = mesh->hi[k] - mesh->lo[k];
+    if (!(len[k] > 0.0)) return PNS_EINVAL;
+  }
+  // one workgroup per cell in a 1D grid
+  if ((int64_t)nx * ny * nz > ((int64_t)1 << 31) - 1) return PNS_EUNSUPPORTED;
+  pns_ctx* c = new pns_ctx();
+  c->dim = 3;
+  c->mesh = *mesh;
+  c->disc = *disc;
+  c->prec = precision;
+  c->es = precision == PNS_FP64 ? 8 : 4;
+  c->nlev = 1;
+  c->stream = (hipStream_t)stream;
+  c->g3 = make_grid3(nx, ny, nz, len[0], len[1], len[2]);
+  Level L{};
+  L.g.nx = nx;
+  L.g.ny = ny;
+  L.g.hx = c->g3.hx;
+  L.g.hy = c->g3.hy;
+  L.g.ihx = c->g3.ihx;
+  L.g.ihy = c->g3.ihy;
+  L.g.nn = c->g3.nn;
+  L.g.nc = c->g3.nc;
+  L.g.nv = c->g3.nv;
+  L.g.ns = c->g3.ns;
+  L.g.nst = c->g3.nst;
+  c->lev.push_back(L);
+  c->has_coarse = false;
+  *out = c;
+  return PNS_OK;
+}
+
 }  // namespace
 
 int pns::make_model(const pns_model* md, Model* m, std::string* err) {
@@ -262,6 +312,7 @@ int pns_ctx_create(const pns_mesh* mesh, const pns_discretization* disc, int n_l
   if (!out) return PNS_EINVAL;
   *out = nullptr;
   if (!mesh || !disc) return PNS_EINVAL;
+  if (mesh->dim == 3) return create3d(mesh, disc, n_levels, precision, stream, out);
   if (mesh->dim != 2 || disc->k_space != 2 || disc->k_time != 1) return PNS_EUNSUPPORTED;
   if (precision != PNS_FP64 && precision != PNS_FP32) return PNS_EINVAL;
   if (!(disc->tau > 0.0) || n_levels < 1 || n_levels > 12) return PNS_EINVAL;
@@ -339,9 +390,11 @@ int pns_set_state(pns_ctx* ctx, const pns_model* md, const double* u_k) {
     PNS_HIP(ctx, hipMemcpyAsync(ctx->uk, u_k, 2 * g0.nv * 8, hipMemcpyDeviceToDevice, s));
   else
     PNS_HIP(ctx, launch_convert<float>(2 * g0.nv, ctx->uk64, (float*)ctx->uk, s));
-  PNS_HIP(ctx, launch_state_combine(g0.nv, ctx->uk64, ctx->uk64 + g0.nv, kXiMid[0], kXiMid[1],
-                                    ctx->urep, s));
-  if (ctx->apply_mode == PNS_APPLY_CACHED) PNS_HIP(ctx, build_tangent_cache(ctx));
+  if (ctx->dim == 2) {
+    PNS_HIP(ctx, launch_state_combine(g0.nv, ctx->uk64, ctx->uk64 + g0.nv, kXiMid[0], kXiMid[1],
+                                      ctx->urep, s));
+    if (ctx->apply_mode == PNS_APPLY_CACHED) PNS_HIP(ctx, build_tangent_cache(ctx));
+  }
   ctx->has_state = true;
   ctx->has_smoother = false;
   return PNS_OK;
@@ -351,6 +404,8 @@ int pns_set_apply_mode(pns_ctx* ctx, int mode) {
   if (!ctx) return PNS_EINVAL;
   if (mode != PNS_APPLY_RECOMPUTE && mode != PNS_APPLY_CACHED)
     return fail(ctx, PNS_EINVAL, "unknown apply mode");
+  if (ctx->dim == 3 && mode != PNS_APPLY_RECOMPUTE)
+    return fail(ctx, PNS_EUNSUPPORTED, "3D contexts recompute the tangent");
   const bool rebuild = mode == PNS_APPLY_CACHED && ctx->apply_mode != mode && ctx->has_state;
   ctx->apply_mode = mode;
   if (rebuild) PNS_HIP(ctx, build_tangent_cache(ctx));
@@ -359,6 +414,7 @@ int pns_set_apply_mode(pns_ctx* ctx, int mode) {
 
 int pns_set_patch_kind(pns_ctx* ctx, int kind) {
   if (!ctx) return PNS_EINVAL;
+  if (ctx->dim == 3) return fail(ctx, PNS_EUNSUPPORTED, "3D contexts have no smoother");
   if (kind != PNS_PATCH_SURROGATE && kind != PNS_PATCH_EXACT)
     return fail(ctx, PNS_EINVAL, "unknown patch kind");
   if (kind != ctx->patch_kind) ctx->has_smoother = false;
@@ -387,6 +443,7 @@ int pns_cell_defect(pns_ctx* ctx, const void* b, const void* x, void* y) {
 }
 
 int pns_vanka_setup(pns_ctx* ctx, const uint16_t* node_masks) {
+  if (ctx && ctx->dim == 3) return fail(ctx, PNS_EUNSUPPORTED, "3D contexts have no smoother");
   if (!check_ctx(ctx, true, false)) return ctx_code(ctx, true, false);
   ctx->has_smoother = false;
   return ctx->es == 8 ? vanka_setup_impl<double>(ctx, node_masks)
@@ -394,6 +451,7 @@ int pns_vanka_setup(pns_ctx* ctx, const uint16_t* node_masks) {
 }
 
 int pns_vanka_smooth(pns_ctx* ctx, int level, int n_sweeps, double omega, const void* r, void* d) {
+  if (ctx && ctx->dim == 3) return fail(ctx, PNS_EUNSUPPORTED, "3D contexts have no smoother");
   if (!check_ctx(ctx, true, true)) return ctx_code(ctx, true, true);
   if (level < 0 || level >= ctx->nlev || n_sweeps < 0 || !r || !d || r == d)
     return fail(ctx, PNS_EINVAL, "bad level, sweep count or vectors");
@@ -405,6 +463,7 @@ int pns_vanka_smooth(pns_ctx* ctx, int level, int n_sweeps, double omega, const 
 }
 
 int pns_vcycle(pns_ctx* ctx, int nu1, int nu2, double omega, const void* r, void* d) {
+  if (ctx && ctx->dim == 3) return fail(ctx, PNS_EUNSUPPORTED, "3D contexts have no V-cycle");
   if (!check_ctx(ctx, true, true)) return ctx_code(ctx, true, true);
   if (nu1 < 0 || nu2 < 0 || !r || !d || r == d)
     return fail(ctx, PNS_EINVAL, "bad sweep counts or vectors");

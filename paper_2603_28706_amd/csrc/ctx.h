@@ -34,6 +34,8 @@ int make_model(const pns_model* md, Model* m, std::string* err);
 }  // namespace pns
 
 struct pns_ctx {
+  int dim = 2;         // 3: hexahedra, action only (one level, no smoother or solve)
+  pns::Grid3 g3{};     // the 3D mesh (dim == 3)
   pns_mesh mesh{};
   pns_discretization disc{};
   int prec = PNS_FP64;

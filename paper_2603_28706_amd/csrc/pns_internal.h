@@ -78,6 +78,33 @@ inline Grid make_grid(int nx, int ny, double lx, double ly) {
   return g;
 }
 
+// 3D box of hexahedra (x fastest); nodes (2nx+1)(2ny+1)(2nz+1), P1disc pressure
+// with 4 coefficients per cell
+struct Grid3 {
+  int nx, ny, nz;
+  double hx, hy, hz, ihx, ihy, ihz;
+  int64_t nn, nc, nv, ns, nst;
+};
+
+inline Grid3 make_grid3(int nx, int ny, int nz, double lx, double ly, double lz) {
+  Grid3 g;
+  g.nx = nx;
+  g.ny = ny;
+  g.nz = nz;
+  g.hx = lx / nx;
+  g.hy = ly / ny;
+  g.hz = lz / nz;
+  g.ihx = nx / lx;
+  g.ihy = ny / ly;
+  g.ihz = nz / lz;
+  g.nn = (int64_t)(2 * nx + 1) * (2 * ny + 1) * (2 * nz + 1);
+  g.nc = (int64_t)nx * ny * nz;
+  g.nv = 3 * g.nn;
+  g.ns = g.nv + 4 * g.nc;
+  g.nst = 2 * g.ns;
+  return g;
+}
+
 // ---------------------------------------------------------------- launchers
 // apply.hip: matrix-free level-0 operator; mode 0: y = J x, mode 1: y = b - J x;
 // cache == nullptr: tangent recomputed from u_k at every point, else the
@@ -88,6 +115,11 @@ hipError_t launch_cell_apply(const Grid& g, const Model& m, double tau, const T*
 template <typename T>
 hipError_t launch_tangent_cache(const Grid& g, const Model& m, double tau, const double* uk,
                                 T* cache, hipStream_t s);
+
+// apply3d.hip: the same operator on hexahedra; mode 0: y = J x, mode 1: y = b - J x
+template <typename T>
+hipError_t launch_cell_apply3d(const Grid3& g, const Model& m, double tau, const T* uk,
+                               const T* x, const T* b, T* y, int mode, hipStream_t s);
 
 // setup.hip
 hipError_t launch_element_matrices(const Grid& g, const Model& m, const double* u, double* Es,

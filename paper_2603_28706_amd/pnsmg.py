@@ -153,18 +153,23 @@ def _ptr(t):
 class Context:
     """One pns_ctx with its workspace (a torch uint8 tensor on the device)."""
 
-    def __init__(self, n, n_levels=1, precision=FP64, tau=0.01, lo=(0.0, 0.0), hi=(1.0, 1.0),
+    def __init__(self, n, n_levels=1, precision=FP64, tau=0.01, lo=None, hi=None,
                  device="cuda", stream=None):
+        """n: cells per direction, 2 entries (quadrilaterals) or 3 (hexahedra,
+        action only); lo/hi default to the unit square or cube."""
         import torch
 
         self.torch = torch
         self.device = torch.device(device)
         self.precision = precision
         self.dtype = torch.float64 if precision == FP64 else torch.float32
+        dim = len(n)
+        lo = (0.0,) * dim if lo is None else lo
+        hi = (1.0,) * dim if hi is None else hi
         m = pns_mesh()
-        m.dim = 2
-        m.n_cells[0], m.n_cells[1], m.n_cells[2] = int(n[0]), int(n[1]), 1
-        for k in range(2):
+        m.dim = dim
+        m.n_cells[0], m.n_cells[1], m.n_cells[2] = int(n[0]), int(n[1]), int(n[2]) if dim == 3 else 1
+        for k in range(dim):
             m.lo[k], m.hi[k] = float(lo[k]), float(hi[k])
         d = pns_discretization(2, 1, 0.0, float(tau))
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
@@ -174,6 +179,7 @@ class Context:
         if rc != PNS_OK:
             raise PnsError(rc, "pns_ctx_create rejected the configuration")
         self.h = h
+        self.dim = dim
         self.n_levels = n_levels
         nbytes = lib().pns_workspace_bytes(self.h)
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)

@@ -17,11 +17,12 @@ def test_library_exports_every_header_symbol():
         assert hasattr(L, s), s
 
 
-def _create(n=(8, 8), levels=1, prec=pnsmg.FP64, tau=0.01, dim=2, k_space=2, k_time=1):
+def _create(n=(8, 8), levels=1, prec=pnsmg.FP64, tau=0.01, dim=None, k_space=2, k_time=1,
+            hi=1.0):
     m = pnsmg.pns_mesh()
-    m.dim = dim
-    m.n_cells[0], m.n_cells[1], m.n_cells[2] = n[0], n[1], 1
-    m.hi[0] = m.hi[1] = 1.0
+    m.dim = len(n) if dim is None else dim
+    m.n_cells[0], m.n_cells[1], m.n_cells[2] = n[0], n[1], n[2] if len(n) == 3 else 1
+    m.hi[0] = m.hi[1] = m.hi[2] = hi
     d = pnsmg.pns_discretization(k_space, k_time, 0.0, tau)
     h = ctypes.c_void_p()
     rc = pnsmg.lib().pns_ctx_create(ctypes.byref(m), ctypes.byref(d), levels, prec, None,
@@ -30,7 +31,12 @@ def _create(n=(8, 8), levels=1, prec=pnsmg.FP64, tau=0.01, dim=2, k_space=2, k_t
 
 
 def test_create_rejects_bad_configurations():
-    assert _create(dim=3)[0] == pnsmg.PNS_EUNSUPPORTED
+    assert _create(dim=1)[0] == pnsmg.PNS_EUNSUPPORTED
+    assert _create(n=(4, 4, 4), dim=4)[0] == pnsmg.PNS_EUNSUPPORTED
+    assert _create(n=(4, 4, 4), levels=2)[0] == pnsmg.PNS_EUNSUPPORTED  # 3D: action only
+    assert _create(n=(4, 4, 0))[0] == pnsmg.PNS_EINVAL
+    assert _create(n=(4, 4, 4), hi=0.0)[0] == pnsmg.PNS_EINVAL
+    assert _create(n=(4, 4, 4), k_time=2)[0] == pnsmg.PNS_EUNSUPPORTED
     assert _create(k_time=2)[0] == pnsmg.PNS_EUNSUPPORTED
     assert _create(tau=0.0)[0] == pnsmg.PNS_EINVAL
     assert _create(n=(6, 8), levels=3)[0] == pnsmg.PNS_EINVAL     # not divisible by 4
@@ -58,6 +64,38 @@ def test_workspace_query_and_state_errors_without_device():
     assert L.pns_bind_workspace(h, ctypes.c_void_p(1000), nbytes) == pnsmg.PNS_EWORKSPACE
     assert L.pns_bind_workspace(h, ctypes.c_void_p(4096), 16) == pnsmg.PNS_EWORKSPACE
     assert b"workspace" in L.pns_last_error(h)
+    L.pns_ctx_destroy(h)
+
+
+def test_3d_context_is_action_only():
+    """A hexahedral context: unknown counts of Q2^3 / P1disc x dG(1), the
+    workspace holds the state only, every smoother, V-cycle and solve entry
+    point is rejected before any device work."""
+    rc, h = _create(n=(32, 32, 32))
+    assert rc == pnsmg.PNS_OK
+    L = pnsmg.lib()
+    out = (ctypes.c_int64 * 4)()
+    assert L.pns_level_sizes(h, 0, out) == 0
+    assert (out[0], out[1], out[2], out[3]) == (1909894, 32768, 3 * 65 ** 3, 3 * 65 ** 3 + 4 * 32768)
+    assert L.pns_level_sizes(h, 1, out) == pnsmg.PNS_EINVAL
+    nbytes = L.pns_workspace_bytes(h)
+    assert 2 * 3 * 65 ** 3 * (8 + 8) <= nbytes < 2 * 3 * 65 ** 3 * 16 + 4096
+    assert L.pns_solve_workspace_bytes(h, 30) == 0
+    assert L.pns_set_apply_mode(h, pnsmg.APPLY_CACHED) == pnsmg.PNS_EUNSUPPORTED
+    assert L.pns_set_apply_mode(h, pnsmg.APPLY_RECOMPUTE) == pnsmg.PNS_OK
+    assert L.pns_set_patch_kind(h, pnsmg.PATCH_EXACT) == pnsmg.PNS_EUNSUPPORTED
+    v = ctypes.c_void_p(4096)
+    w = ctypes.c_void_p(8192)
+    assert L.pns_vanka_setup(h, None) == pnsmg.PNS_EUNSUPPORTED
+    assert L.pns_vanka_smooth(h, 0, 1, ctypes.c_double(0.1), v, w) == pnsmg.PNS_EUNSUPPORTED
+    assert L.pns_vcycle(h, 1, 1, ctypes.c_double(0.1), v, w) == pnsmg.PNS_EUNSUPPORTED
+    model = pnsmg.model_struct(dict(p=1.3, delta=1e-3, nu=1.0, nu_inf=1e-4, gamma1=40.0,
+                                    gamma2=40.0, sigma_max=1.0, convection=1, qsign=1, lin=2))
+    assert L.pns_residual(h, ctypes.byref(model), v, None, w) == pnsmg.PNS_EUNSUPPORTED
+    info = pnsmg.pns_solve_info()
+    assert L.pns_solve(h, ctypes.byref(model), v, w, None, None, 0,
+                       ctypes.byref(info)) == pnsmg.PNS_EUNSUPPORTED
+    assert L.pns_cell_apply(h, v, w) == pnsmg.PNS_EWORKSPACE
     L.pns_ctx_destroy(h)
 
 
