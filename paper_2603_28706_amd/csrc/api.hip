@@ -35,7 +35,10 @@ size_t layout(pns_ctx* c, bool bind) {
   const size_t es = c->es;
   c->uk = take(2 * g0.nv * es);
   c->uk64 = (double*)take(2 * g0.nv * 8);
-  if (c->dim == 3) return (off + kAlign - 1) / kAlign * kAlign;  // action only
+  if (c->dim == 3) {  // action only
+    c->E3 = take(g0.nc * 170 * es);
+    return (off + kAlign - 1) / kAlign * kAlign;
+  }
   c->urep = (double*)take(g0.nv * 8);
   c->Es0 = (double*)take(g0.nc * kNs * kNs * 8);
   c->Es1 = (double*)take(g0.nc * kNs * kNs * 8);
@@ -99,8 +102,8 @@ template <typename T>
 hipError_t defect(pns_ctx* c, int l, const T* b, const T* x, T* y) {
   Level& L = c->lev[l];
   if (c->dim == 3)
-    return launch_cell_apply3d<T>(c->g3, c->model, c->disc.tau, (const T*)c->uk, x, b, y, 1,
-                                  c->stream);
+    return launch_cell_apply3d<T>(c->g3, c->model, c->disc.tau, (const T*)c->uk, x, b, y,
+                                  (T*)c->E3, 1, c->stream);
   if (l == 0)
     return launch_cell_apply<T>(L.g, c->model, c->disc.tau, (const T*)c->uk, tangent_cache<T>(c),
                                 x, b, y, 1, c->stream);
@@ -111,8 +114,8 @@ template <typename T>
 hipError_t apply_level(pns_ctx* c, int l, const T* x, T* y) {
   Level& L = c->lev[l];
   if (c->dim == 3)
-    return launch_cell_apply3d<T>(c->g3, c->model, c->disc.tau, (const T*)c->uk, x, x, y, 0,
-                                  c->stream);
+    return launch_cell_apply3d<T>(c->g3, c->model, c->disc.tau, (const T*)c->uk, x, x, y,
+                                  (T*)c->E3, 0, c->stream);
   if (l == 0)
     return launch_cell_apply<T>(L.g, c->model, c->disc.tau, (const T*)c->uk, tangent_cache<T>(c),
                                 x, x, y, 0, c->stream);

@@ -3,32 +3,65 @@
 // def-a-gam, Defc, def-b-gam) and the tangents of Sec. 4.2-4.4:
 //   y_mu = sum_nu K_t[mu][nu] M_x x_nu + tau w_mu J_mu x_mu.
 //
-// Design: one workgroup (one wave) per cell.  The 27 nodal values of x and
-// u_k (3 components, both Radau nodes) are staged in LDS and brought to the
-// 3 x 3 x 3 Gauss points by sum factorisation (contractions along x, y, z);
-// one thread per (Gauss point, Radau node) forms the tangent (FP64 scalars),
-// the temporal mass coupling and the test coefficients; the transposed
-// contractions (z, y, x) give the 81 velocity results per Radau node and the
-// 4 pressure rows are summed directly.  Cells on the boundary add their face
-// terms (direct evaluation at the 9 points of each boundary face).  Results are
-// added to y with global atomics (y is zero-filled, or holds b for the defect,
-// before the kernel), so the summation order over cells is not fixed.
+// Three launches, no global atomics, fixed summation order: the volume kernel
+// writes every cell's 170 results (81 velocity + 4 pressure per Radau node)
+// into a per-cell buffer E; the face kernel adds the boundary-face terms of
+// each boundary cell into that cell's slot; the gather kernel sums, for every
+// node, the slots of the (up to 8) cells that share it, in a fixed order, and
+// writes y = J x or y = b - J x.
+//
+// Volume kernel (gfx950, wave64): persistent waves, one cell per wave at a
+// time, kCellsPerWg waves per workgroup working in their own LDS slices.
+// * Each wave prefetches the next cell's nodal lines and pressure
+//   coefficients into registers while it computes the current cell, so the
+//   global-memory latency is hidden behind the arithmetic.
+// * Sum factorisation by lines: each forward stage (x, then y, then z) gives
+//   every lane one line of 3 values of one field and applies the 3x3 basis
+//   value / derivative matrices, whose entries are compile-time constants;
+//   12 fields (x and u_k, 3 components, 2 Radau nodes) x 9 lines = 108 lines.
+// * One lane per (Gauss point, Radau node) forms the tangent (FP64 scalars),
+//   the temporal mass coupling from the partner node's values and the test
+//   coefficients; the 4 pressure rows are summed by a butterfly over the
+//   lanes of one Radau node.
+// * The transposed stages (z, y, x) run one line per lane (2 x 3 components x
+//   9 lines = 54) and end in coalesced stores of the cell's slot of E.
+// * Two LDS buffers per wave are used in turn by the stages (about 18 KB in
+//   FP64); a wave orders its stages with wavefront-scope fences only (the LDS
+//   operations of one wave are performed in order).
+// Face kernel: one wave per boundary cell; the cell's nodal values and its
+// slot of E are staged in LDS, one lane per (boundary side, face Gauss point,
+// Radau node) evaluates the face integrand directly and adds its test
+// coefficients with LDS atomics; the slot is written back.
+#include <type_traits>
+
+#include "devmath.h"
 #include "pns_internal.h"
 
 namespace pns {
 namespace {
 
-constexpr int kF = 12;  // staged fields: x (mu*3 + c), then u_k (6 + mu*3 + c)
-constexpr int kR1 = 2 * 3 * 27 * 3;  // elements of r1 (r2 follows it)
-static_assert(2 * 3 * 4 * 27 <= kF * 9 * 3 * 2, "cf must fit in the s1 buffer");
-static_assert(kR1 + 2 * 3 * 27 * 2 <= kF * 81, "r1 and r2 must fit in the s2 buffer");
+constexpr int kCellsPerWg = 4;   // waves (cells in flight) per workgroup
+constexpr int kF = 12;           // staged fields: x (mu*3 + c), then u_k (6 + mu*3 + c)
+constexpr int kLines = kF * 9;   // forward lines per stage
+constexpr int kP = kF * 27 * 4;  // buffer P: s1 (648), pt (1296), r1 (486)
+constexpr int kQ = kF * 27 * 3;  // buffer Q: s2 (972), cf (648), r2 (324)
+// results per cell in E: velocity of node a, Radau node mu, component c at
+// a*6 + mu*3 + c (the 6 values of a node are contiguous), pressure j of mu at
+// 162 + mu*4 + j
+constexpr int kSlot = 2 * 85;
+static_assert(2 * 3 * 4 * 27 <= kQ, "cf must fit in Q");
 
-__device__ __forceinline__ double gp(int q) { return q == 0 ? kGP[0] : (q == 1 ? kGP[1] : kGP[2]); }
-__device__ __forceinline__ double gw(int q) { return q == 0 ? kGW[0] : (q == 1 ? kGW[1] : kGW[2]); }
-__device__ __forceinline__ double bv(int q, int a) { return q2v(a, gp(q)); }
-__device__ __forceinline__ double bd(int q, int a) { return q2d(a, gp(q)); }
+// 1D Q2 basis at the 3 Gauss points (compile-time constants once unrolled)
+__device__ __forceinline__ constexpr double Bq(int q, int a) { return q2v(a, kGP[q]); }
+__device__ __forceinline__ constexpr double Dq(int q, int a) { return q2d(a, kGP[q]); }
+__device__ __forceinline__ double gp_sel(int q) {
+  return q == 0 ? kGP[0] : (q == 1 ? kGP[1] : kGP[2]);
+}
+__device__ __forceinline__ double gw_sel(int q) {
+  return q == 0 ? kGW[0] : (q == 1 ? kGW[1] : kGW[2]);
+}
 
-// tangent scalars: eta = nu_inf + mu, kappa of the selected linearisation
+// tangent scalars eta, kappa of the selected linearisation at A = D(u_k)
 template <int LIN>
 __device__ __forceinline__ void tangent3(const Model& m, const double A[3][3], double& eta,
                                          double& kappa) {
@@ -38,14 +71,15 @@ __device__ __forceinline__ void tangent3(const Model& m, const double A[3][3], d
 #pragma unroll
     for (int j = 0; j < 3; ++j) a2 += A[i][j] * A[i][j];
   const double D2 = m.delta2 + a2;
-  const double mu = m.nu * pow(D2, m.expo);
+  const double mu = m.nu * exp_small(m.expo * log_pos(D2));
   eta = m.nu_inf + mu;
   if (LIN == PNS_PICARD) {
     kappa = 0.0;
   } else {
-    const double c = (m.p - 2.0) / D2;
+    const double c = (m.p - 2.0) * rcp_nr(D2);
     if (LIN == PNS_MODIFIED_NEWTON) {
-      const double lim = a2 > 0.0 ? m.sigma_max / sqrt(a2) : mu;
+      // a2 = 0 makes the rank-one term vanish whatever kappa is
+      const double lim = a2 > 0.0 ? m.sigma_max * rsqrt_nr(a2) : mu;
       kappa = c * fmin(mu, lim);
     } else {
       kappa = c * mu;
@@ -53,243 +87,398 @@ __device__ __forceinline__ void tangent3(const Model& m, const double A[3][3], d
   }
 }
 
+// Orders the LDS accesses of one wave across a stage boundary: the hardware
+// performs them in order, the fence keeps the compiler from moving them.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename T, int LIN, bool CONV>
-__global__ __launch_bounds__(64) void cell_apply3d_kernel(Grid3 g, Model m, double tau,
-                                                          const T* __restrict__ uk,
-                                                          const T* __restrict__ x,
-                                                          T* __restrict__ y, T sign) {
-  // LDS stages; s1 is dead once s2 is formed and hosts cf, s2 is dead once pt is
-  // formed and hosts r1 and r2
-  __shared__ T nd[kF][27];                 // nodal values, local node a = ax + 3 ay + 9 az
-  __shared__ T bufA[kF * 9 * 3 * 2];       // s1 [f][az*3+ay][qx][B, D along x]; then cf
-  __shared__ T bufB[kF * 81];              // s2 [f][az][qy][qx][val, d/dx, d/dy]; then r1, r2
-  __shared__ T pt[kF][27][4];              // [f][q][val, d/dx, d/dy, d/dz] (reference derivatives)
-  __shared__ T cp[2][27];                  // [mu][q] pressure-test coefficient
-  __shared__ double outv[2][85];           // [mu][81 velocity (c*27 + a), 4 pressure]
-  auto s1 = reinterpret_cast<T(*)[9][3][2]>(bufA);
-  auto cf = reinterpret_cast<T(*)[3][4][27]>(bufA);          // [mu][c][V, Gx, Gy, Gz][q]
-  auto s2 = reinterpret_cast<T(*)[3][3][3][3]>(bufB);
-  auto r1 = reinterpret_cast<T(*)[3][3][3][3][3]>(bufB);     // [mu][c][qy][qx][az][v, x, y]
-  auto r2 = reinterpret_cast<T(*)[3][3][3][3][2]>(bufB + kR1);
-  const int64_t cell = blockIdx.x;
-  const int cx = (int)(cell % g.nx), cy = (int)((cell / g.nx) % g.ny),
-            cz = (int)(cell / ((int64_t)g.nx * g.ny));
-  const int t = threadIdx.x;
-  const int NX = 2 * g.nx + 1, NY = 2 * g.ny + 1;
-  auto gnode = [&](int a) -> int64_t {
-    const int ax = a % 3, ay = (a / 3) % 3, az = a / 9;
-    return ((int64_t)(2 * cz + az) * NY + (2 * cy + ay)) * NX + (2 * cx + ax);
+__global__ __launch_bounds__(64 * kCellsPerWg, 2) void cell_volume3d_kernel(
+    Grid3 g, Model m, double tau, const T* __restrict__ uk, const T* __restrict__ x,
+    T* __restrict__ E, int64_t nwaves) {
+  __shared__ __align__(16) T Pall[kCellsPerWg][kP];
+  __shared__ __align__(16) T Qall[kCellsPerWg][kQ];
+  __shared__ double presall[kCellsPerWg][2][4];
+  const int w = threadIdx.x >> 6;
+  const int t = threadIdx.x & 63;
+  const int64_t wid = (int64_t)blockIdx.x * kCellsPerWg + w;
+  if (wid >= nwaves) return;
+  T* const P = Pall[w];
+  T* const Q = Qall[w];
+  double(*const pres)[4] = presall[w];
+  const int64_t NX = 2 * g.nx + 1, NXY = NX * (2 * g.ny + 1);
+  // Step k of every wave covers the block of nwaves consecutive cells
+  // [k nwaves, (k+1) nwaves), so neighbouring cells run at the same time.
+  // -1: no more cells for this wave.
+  auto cell_of = [&](int64_t k) -> int64_t {
+    const int64_t c = k * nwaves + wid;
+    return c < g.nc ? c : -1;
   };
-
-  // stage the nodal values
-  for (int i = t; i < kF * 27; i += 64) {
-    const int f = i / 27, a = i % 27;
-    const int64_t gn = gnode(a);
-    const int fm = f % 6, mu = fm / 3, c = fm % 3;
-    nd[f][a] = f < 6 ? x[(int64_t)mu * g.ns + (int64_t)c * g.nn + gn]
-                     : uk[(int64_t)mu * g.nv + (int64_t)c * g.nn + gn];
-  }
-  for (int i = t; i < 2 * 85; i += 64) (&outv[0][0])[i] = 0.0;
-  __syncthreads();
-  // contraction along x
-  for (int i = t; i < kF * 9 * 3; i += 64) {
-    const int f = i / 27, r = (i / 3) % 9, qx = i % 3;
-    T v = 0, d = 0;
+  auto node0 = [&](int64_t c) -> int64_t {
+    const int64_t cx = c % g.nx, cy = (c / g.nx) % g.ny, cz = c / ((int64_t)g.nx * g.ny);
+    return 2 * cz * NXY + 2 * cy * NX + 2 * cx;
+  };
+  // the lane's nodal lines l = t, t + 64 (field f, az, ay) and its pressure
+  // coefficients (lanes of the point phase) of cell c, into registers
+  auto load_lines = [&](int64_t c, T (&pre)[2][3]) {
+    const int64_t nd0 = node0(c);
 #pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      const T n = nd[f][r * 3 + ax];
-      v += (T)bv(qx, ax) * n;
-      d += (T)bd(qx, ax) * n;
+    for (int it = 0; it < 2; ++it) {
+      const int l = t + 64 * it;
+      if (l < kLines) {
+        const int f = l / 9, r = l % 9, az = r / 3, ay = r % 3;
+        const int fm = f % 6, mu = fm / 3, comp = fm % 3;
+        const T* src = (f < 6 ? x + (int64_t)mu * g.ns : uk + (int64_t)mu * g.nv) +
+                       (int64_t)comp * g.nn + nd0 + az * NXY + ay * NX;
+        pre[it][0] = src[0];
+        pre[it][1] = src[1];
+        pre[it][2] = src[2];
+      }
     }
-    s1[f][r][qx][0] = v;
-    s1[f][r][qx][1] = d;
-  }
-  __syncthreads();
-  // contraction along y
-  for (int i = t; i < kF * 27; i += 64) {
-    const int f = i / 27, az = (i / 9) % 3, qy = (i / 3) % 3, qx = i % 3;
-    T v = 0, dx = 0, dy = 0;
-#pragma unroll
-    for (int ay = 0; ay < 3; ++ay) {
-      const T b = (T)bv(qy, ay), d = (T)bd(qy, ay);
-      v += b * s1[f][az * 3 + ay][qx][0];
-      dx += b * s1[f][az * 3 + ay][qx][1];
-      dy += d * s1[f][az * 3 + ay][qx][0];
+  };
+  auto load_pres = [&](int64_t c, T (&pp)[4]) {
+    if (t < 54) {
+      const T* pv = x + (int64_t)(t & 1) * g.ns + g.nv + 4 * c;
+      pp[0] = pv[0];
+      pp[1] = pv[1];
+      pp[2] = pv[2];
+      pp[3] = pv[3];
     }
-    s2[f][az][qy][qx][0] = v;
-    s2[f][az][qy][qx][1] = dx;
-    s2[f][az][qy][qx][2] = dy;
-  }
-  __syncthreads();
-  // contraction along z
-  for (int i = t; i < kF * 27; i += 64) {
-    const int f = i / 27, q = i % 27;
-    const int qz = q / 9, qy = (q / 3) % 3, qx = q % 3;
-    T v = 0, dx = 0, dy = 0, dz = 0;
-#pragma unroll
-    for (int az = 0; az < 3; ++az) {
-      const T b = (T)bv(qz, az), d = (T)bd(qz, az);
-      v += b * s2[f][az][qy][qx][0];
-      dx += b * s2[f][az][qy][qx][1];
-      dy += b * s2[f][az][qy][qx][2];
-      dz += d * s2[f][az][qy][qx][0];
-    }
-    pt[f][q][0] = v;
-    pt[f][q][1] = dx;
-    pt[f][q][2] = dy;
-    pt[f][q][3] = dz;
-  }
-  __syncthreads();
-
-  // pointwise: tangent, temporal mass coupling, test coefficients
-  const double ih[3] = {g.ihx, g.ihy, g.ihz};
+  };
+  const T ih[3] = {(T)g.ihx, (T)g.ihy, (T)g.ihz};
   const double vol = g.hx * g.hy * g.hz;
-  if (t < 54) {
-    const int q = t >> 1, mu = t & 1, other = 1 - mu;
-    const int qz = q / 9, qy = (q / 3) % 3, qx = q % 3;
-    const double W = vol * gw(qx) * gw(qy) * gw(qz);
-    const double sW = tau * (mu ? kWt[1] : kWt[0]) * W;
-    const double kself = mu ? kKt[1][1] : kKt[0][0], koth = mu ? kKt[1][0] : kKt[0][1];
-    T X[3], U[3], GX[3][3], GU[3][3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      X[c] = pt[mu * 3 + c][q][0];
-      U[c] = pt[6 + mu * 3 + c][q][0];
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        GX[c][j] = pt[mu * 3 + c][q][1 + j] * (T)ih[j];
-        GU[c][j] = pt[6 + mu * 3 + c][q][1 + j] * (T)ih[j];
-      }
-    }
-    double A[3][3];
-    T B[3][3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        A[i][j] = 0.5 * ((double)GU[i][j] + (double)GU[j][i]);
-        B[i][j] = (T)0.5 * (GX[i][j] + GX[j][i]);
-      }
-    double eta_d, kap_d;
-    tangent3<LIN>(m, A, eta_d, kap_d);
-    const T eta = (T)eta_d, kap = (T)kap_d;
-    T ab = 0;
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) ab += (T)A[i][j] * B[i][j];
-    // pressure of x at the point
-    const T* pv = x + (int64_t)mu * g.ns + g.nv + 4 * cell;
-    const T xp = pv[0] + pv[1] * (T)(gp(qx) - 0.5) + pv[2] * (T)(gp(qy) - 0.5) +
-                 pv[3] * (T)(gp(qz) - 0.5);
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const T w = (T)kself * X[i] + (T)koth * pt[other * 3 + i][q][0];
-      cf[mu][i][0][q] = (T)W * w;
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        // coefficient of d_j w_i: T(B)_ij - convection - xp delta_ij
-        T gij = eta * B[i][j] + kap * ab * (T)A[i][j] - (i == j ? xp : (T)0);
-        if (CONV) {
-          gij -= X[i] * U[j];
-          if (LIN != PNS_PICARD) gij -= U[i] * X[j];
-        }
-        cf[mu][i][1 + j][q] = (T)sW * gij * (T)ih[j];
-      }
-    }
-    cp[mu][q] = -(T)sW * (GX[0][0] + GX[1][1] + GX[2][2]);
-  }
-  __syncthreads();
-  // transposed contraction along z: r1 = sum_qz (Bz V + Dz Gz, Bz Gx, Bz Gy)
-  for (int i = t; i < 6 * 27; i += 64) {
-    const int mc = i / 27, r = i % 27, mu = mc / 3, c = mc % 3;
-    const int qy = r / 9, qx = (r / 3) % 3, az = r % 3;
-    T v = 0, gx = 0, gy = 0;
-#pragma unroll
-    for (int qz = 0; qz < 3; ++qz) {
-      const int q = (qz * 3 + qy) * 3 + qx;
-      const T b = (T)bv(qz, az), d = (T)bd(qz, az);
-      v += b * cf[mu][c][0][q] + d * cf[mu][c][3][q];
-      gx += b * cf[mu][c][1][q];
-      gy += b * cf[mu][c][2][q];
-    }
-    r1[mu][c][qy][qx][az][0] = v;
-    r1[mu][c][qy][qx][az][1] = gx;
-    r1[mu][c][qy][qx][az][2] = gy;
-  }
-  // pressure rows: sum_q P psi_j
-  if (t < 8) {
-    const int mu = t / 4, j = t % 4;
-    double s = 0.0;
-    for (int q = 0; q < 27; ++q) {
-      const int qj = j == 1 ? q % 3 : (j == 2 ? (q / 3) % 3 : q / 9);
-      const double psi = j == 0 ? 1.0 : gp(qj) - 0.5;
-      s += (double)cp[mu][q] * psi;
-    }
-    outv[mu][81 + j] = s;
-  }
-  __syncthreads();
-  // along y: r2 = sum_qy (By v + Dy gy, By gx)
-  for (int i = t; i < 6 * 27; i += 64) {
-    const int mc = i / 27, r = i % 27, mu = mc / 3, c = mc % 3;
-    const int qx = r / 9, az = (r / 3) % 3, ay = r % 3;
-    T v = 0, gx = 0;
-#pragma unroll
-    for (int qy = 0; qy < 3; ++qy) {
-      const T b = (T)bv(qy, ay), d = (T)bd(qy, ay);
-      v += b * r1[mu][c][qy][qx][az][0] + d * r1[mu][c][qy][qx][az][2];
-      gx += b * r1[mu][c][qy][qx][az][1];
-    }
-    r2[mu][c][qx][az][ay][0] = v;
-    r2[mu][c][qx][az][ay][1] = gx;
-  }
-  __syncthreads();
-  // along x: results at the 27 nodes
-  for (int i = t; i < 6 * 27; i += 64) {
-    const int mc = i / 27, a = i % 27, mu = mc / 3, c = mc % 3;
-    const int ax = a % 3, ay = (a / 3) % 3, az = a / 9;
-    T v = 0;
-#pragma unroll
-    for (int qx = 0; qx < 3; ++qx)
-      v += (T)bv(qx, ax) * r2[mu][c][qx][az][ay][0] + (T)bd(qx, ax) * r2[mu][c][qx][az][ay][1];
-    outv[mu][c * 27 + a] = (double)v;
-  }
-  __syncthreads();
+  T pre[2][3] = {}, prep[4] = {};
+  load_lines(wid, pre);
+  load_pres(wid, prep);
+  int64_t next = -1;
+#pragma unroll 1
+  for (int64_t k = 0, cell = wid; cell >= 0; ++k, cell = next) {
+    next = cell_of(k + 1);
 
-  // Dirichlet faces of boundary cells: one task per (side, face point, mu)
-  const bool bx0 = cx == 0, bx1 = cx == g.nx - 1, by0 = cy == 0, by1 = cy == g.ny - 1,
-             bz0 = cz == 0, bz1 = cz == g.nz - 1;
-  if (bx0 || bx1 || by0 || by1 || bz0 || bz1) {
-#pragma unroll 1
-    for (int task = t; task < 6 * 9 * 2; task += 64) {
-      const int side = task / 18, qa = (task / 2) % 9, mu = task & 1;
-      const int k = side / 2, hi = side & 1;  // normal direction and end
-      const bool on = k == 0 ? (hi ? bx1 : bx0) : (k == 1 ? (hi ? by1 : by0) : (hi ? bz1 : bz0));
-      if (!on) continue;
-      // reference coordinates of the point: fixed along k, Gauss in the two others
-      // (taken cyclically after k)
-      const double ga = gp(qa % 3), gb = gp(qa / 3), fix = hi ? 1.0 : 0.0;
-      double xi[3], n[3];
+    // ---- forward x: line (f, az, ay) of nodal values -> s1[f][az][ay][qx][v, d]
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        xi[d] = d == k ? fix : (d == (k + 1) % 3 ? ga : gb);
-        n[d] = d == k ? (hi ? 1.0 : -1.0) : 0.0;
+    for (int it = 0; it < 2; ++it) {
+      const int l = t + 64 * it;
+      if (l < kLines) {
+        const T* n = pre[it];
+        T* dst = P + l * 6;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          dst[2 * q] = (T)Bq(q, 0) * n[0] + (T)Bq(q, 1) * n[1] + (T)Bq(q, 2) * n[2];
+          dst[2 * q + 1] = (T)Dq(q, 0) * n[0] + (T)Dq(q, 1) * n[1] + (T)Dq(q, 2) * n[2];
+        }
       }
-      const double hk = k == 0 ? g.hx : (k == 1 ? g.hy : g.hz);
-      const double ihF = 1.0 / hk;
-      const double sW = tau * (mu ? kWt[1] : kWt[0]) * gw(qa % 3) * gw(qa / 3) * (vol / hk);
-      // values and gradients at the point from the 27 nodes
-      double X[3] = {0, 0, 0}, U[3] = {0, 0, 0}, GX[3][3] = {}, GU[3][3] = {};
-#pragma unroll 1
-      for (int a = 0; a < 27; ++a) {
-        const int ax = a % 3, ay = (a / 3) % 3, az = a / 9;
-        const double px = q2v(ax, xi[0]), py = q2v(ay, xi[1]), pz = q2v(az, xi[2]);
-        const double ph = px * py * pz;
-        const double dph[3] = {q2d(ax, xi[0]) * py * pz * ih[0], px * q2d(ay, xi[1]) * pz * ih[1],
-                               px * py * q2d(az, xi[2]) * ih[2]};
+    }
+    // the next cell's lines load while this one is computed
+    if (next >= 0) load_lines(next, pre);
+    wave_sync();
+    // ---- forward y: line (f, az, qx) -> s2[f][az][qy][qx][v, dx, dy]
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int l = t + 64 * it;
+      if (l < kLines) {
+        const int f = l / 9, r = l % 9, az = r / 3, qx = r % 3;
+        T v[3], d[3];
+#pragma unroll
+        for (int ay = 0; ay < 3; ++ay) {
+          const T* s = P + ((f * 9 + az * 3 + ay) * 3 + qx) * 2;
+          v[ay] = s[0];
+          d[ay] = s[1];
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          T* dst = Q + (((f * 3 + az) * 3 + q) * 3 + qx) * 3;
+          dst[0] = (T)Bq(q, 0) * v[0] + (T)Bq(q, 1) * v[1] + (T)Bq(q, 2) * v[2];
+          dst[1] = (T)Bq(q, 0) * d[0] + (T)Bq(q, 1) * d[1] + (T)Bq(q, 2) * d[2];
+          dst[2] = (T)Dq(q, 0) * v[0] + (T)Dq(q, 1) * v[1] + (T)Dq(q, 2) * v[2];
+        }
+      }
+    }
+    wave_sync();
+    // ---- forward z: line (f, qy, qx) -> pt[f][q][v, dx, dy, dz] (reference derivatives)
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int l = t + 64 * it;
+      if (l < kLines) {
+        const int f = l / 9, r = l % 9;  // r = qy * 3 + qx
+        T v[3], dx[3], dy[3];
+#pragma unroll
+        for (int az = 0; az < 3; ++az) {
+          const T* s = Q + ((f * 3 + az) * 9 + r) * 3;
+          v[az] = s[0];
+          dx[az] = s[1];
+          dy[az] = s[2];
+        }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          T* dst = P + (f * 27 + q * 9 + r) * 4;
+          dst[0] = (T)Bq(q, 0) * v[0] + (T)Bq(q, 1) * v[1] + (T)Bq(q, 2) * v[2];
+          dst[1] = (T)Bq(q, 0) * dx[0] + (T)Bq(q, 1) * dx[1] + (T)Bq(q, 2) * dx[2];
+          dst[2] = (T)Bq(q, 0) * dy[0] + (T)Bq(q, 1) * dy[1] + (T)Bq(q, 2) * dy[2];
+          dst[3] = (T)Dq(q, 0) * v[0] + (T)Dq(q, 1) * v[1] + (T)Dq(q, 2) * v[2];
+        }
+      }
+    }
+    wave_sync();
+
+    // ---- points: lane (q, mu); test coefficients cf[mu][c][V, Gx, Gy, Gz][q] into
+    // Q, pressure rows by butterfly
+    {
+      double p4[4] = {0.0, 0.0, 0.0, 0.0};
+      if (t < 54) {
+        const int q = t >> 1, mu = t & 1, other = 1 - mu;
+        const int qz = q / 9, qy = (q / 3) % 3, qx = q % 3;
+        const double W = vol * gw_sel(qx) * gw_sel(qy) * gw_sel(qz);
+        const double sW = tau * (mu ? kWt[1] : kWt[0]) * W;
+        const double kself = mu ? kKt[1][1] : kKt[0][0], koth = mu ? kKt[1][0] : kKt[0][1];
+        T X[3], U[3], GX[3][3], GU[3][3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const double xv = (double)nd[mu * 3 + c][a], uv = (double)nd[6 + mu * 3 + c][a];
+          const T* px = P + ((mu * 3 + c) * 27 + q) * 4;
+          const T* pu = P + ((6 + mu * 3 + c) * 27 + q) * 4;
+          X[c] = px[0];
+          U[c] = pu[0];
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            GX[c][j] = px[1 + j] * ih[j];
+            GU[c][j] = pu[1 + j] * ih[j];
+          }
+        }
+        double A[3][3];
+        T B[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            A[i][j] = 0.5 * ((double)GU[i][j] + (double)GU[j][i]);
+            B[i][j] = (T)0.5 * (GX[i][j] + GX[j][i]);
+          }
+        double eta_d, kap_d;
+        tangent3<LIN>(m, A, eta_d, kap_d);
+        const T eta = (T)eta_d, kap = (T)kap_d;
+        T ab = 0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) ab += (T)A[i][j] * B[i][j];
+        const T kab = kap * ab;
+        // pressure of x at the point
+        const T xp = prep[0] + prep[1] * (T)(gp_sel(qx) - 0.5) +
+                     prep[2] * (T)(gp_sel(qy) - 0.5) + prep[3] * (T)(gp_sel(qz) - 0.5);
+        T xo[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) xo[i] = P[((other * 3 + i) * 27 + q) * 4];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          Q[((mu * 3 + i) * 4 + 0) * 27 + q] = (T)W * ((T)kself * X[i] + (T)koth * xo[i]);
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            // coefficient of d_j w_i: T(B)_ij - convection - xp delta_ij
+            T gij = eta * B[i][j] + kab * (T)A[i][j] - (i == j ? xp : (T)0);
+            if (CONV) {
+              gij -= X[i] * U[j];
+              if (LIN != PNS_PICARD) gij -= U[i] * X[j];
+            }
+            Q[((mu * 3 + i) * 4 + 1 + j) * 27 + q] = (T)sW * gij * ih[j];
+          }
+        }
+        const double cpv = -sW * (double)(GX[0][0] + GX[1][1] + GX[2][2]);
+        p4[0] = cpv;
+        p4[1] = cpv * (gp_sel(qx) - 0.5);
+        p4[2] = cpv * (gp_sel(qy) - 0.5);
+        p4[3] = cpv * (gp_sel(qz) - 0.5);
+      }
+      // sum over the lanes of one Radau node (xor with even masks keeps the parity)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+#pragma unroll
+        for (int msk = 2; msk < 64; msk <<= 1) p4[j] += __shfl_xor(p4[j], msk, 64);
+      }
+      if (t < 2) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) pres[t][j] = p4[j];
+      }
+    }
+    if (next >= 0) load_pres(next, prep);
+    wave_sync();
+    // ---- backward z: line (mu, c, qy, qx) -> r1[mu][c][qy][qx][az][v, gx, gy]
+    if (t < 54) {
+      const int mc = t / 9, r = t % 9;  // mc = mu * 3 + c, r = qy * 3 + qx
+      T V[3], GXv[3], GYv[3], GZv[3];
+#pragma unroll
+      for (int qz = 0; qz < 3; ++qz) {
+        const int q = qz * 9 + r;
+        V[qz] = Q[(mc * 4 + 0) * 27 + q];
+        GXv[qz] = Q[(mc * 4 + 1) * 27 + q];
+        GYv[qz] = Q[(mc * 4 + 2) * 27 + q];
+        GZv[qz] = Q[(mc * 4 + 3) * 27 + q];
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        T* dst = P + ((mc * 9 + r) * 3 + a) * 3;
+        dst[0] = (T)Bq(0, a) * V[0] + (T)Bq(1, a) * V[1] + (T)Bq(2, a) * V[2] +
+                 (T)Dq(0, a) * GZv[0] + (T)Dq(1, a) * GZv[1] + (T)Dq(2, a) * GZv[2];
+        dst[1] = (T)Bq(0, a) * GXv[0] + (T)Bq(1, a) * GXv[1] + (T)Bq(2, a) * GXv[2];
+        dst[2] = (T)Bq(0, a) * GYv[0] + (T)Bq(1, a) * GYv[1] + (T)Bq(2, a) * GYv[2];
+      }
+    }
+    wave_sync();
+    // ---- backward y: line (mu, c, qx, az) -> r2[mu][c][qx][az][ay][v, gx]
+    if (t < 54) {
+      const int mc = t / 9, qx = (t % 9) / 3, az = t % 3;
+      T v[3], gx[3], gy[3];
+#pragma unroll
+      for (int qy = 0; qy < 3; ++qy) {
+        const T* s = P + ((mc * 9 + qy * 3 + qx) * 3 + az) * 3;
+        v[qy] = s[0];
+        gx[qy] = s[1];
+        gy[qy] = s[2];
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        T* dst = Q + (((mc * 3 + qx) * 3 + az) * 3 + a) * 2;
+        dst[0] = (T)Bq(0, a) * v[0] + (T)Bq(1, a) * v[1] + (T)Bq(2, a) * v[2] +
+                 (T)Dq(0, a) * gy[0] + (T)Dq(1, a) * gy[1] + (T)Dq(2, a) * gy[2];
+        dst[1] = (T)Bq(0, a) * gx[0] + (T)Bq(1, a) * gx[1] + (T)Bq(2, a) * gx[2];
+      }
+    }
+    wave_sync();
+    // ---- backward x: line (mu, c, az, ay) -> results at its 3 nodes, into E
+    T* slot = E + cell * kSlot;
+    if (t < 54) {
+      const int mc = t / 9, az = (t % 9) / 3, ay = t % 3;
+      const int mu = mc / 3, c = mc % 3;
+      T v[3], gx[3];
+#pragma unroll
+      for (int qx = 0; qx < 3; ++qx) {
+        const T* s = Q + (((mc * 3 + qx) * 3 + az) * 3 + ay) * 2;
+        v[qx] = s[0];
+        gx[qx] = s[1];
+      }
+      T* dst = slot + (az * 9 + ay * 3) * 6 + mu * 3 + c;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        dst[6 * a] = (T)Bq(0, a) * v[0] + (T)Bq(1, a) * v[1] + (T)Bq(2, a) * v[2] +
+                 (T)Dq(0, a) * gx[0] + (T)Dq(1, a) * gx[1] + (T)Dq(2, a) * gx[2];
+    } else if (t < 62) {
+      const int mu = (t - 54) / 4, j = (t - 54) % 4;
+      slot[162 + mu * 4 + j] = (T)pres[mu][j];
+    }
+    wave_sync();  // the buffers and pres are rewritten by the next cell
+  }
+}
+
+// Face point qa (two tangential Gauss indices) of boundary side sd (normal
+// direction k = sd / 2, end sd % 2) of a cell: reference coordinates (fixed
+// along k, Gauss in the two other directions taken cyclically after k),
+// outward normal, quadrature weight times tau w_mu times the face measure, and
+// 1 / h_F with h_F the cell size normal to the face.
+__device__ __forceinline__ void face_point_geometry(const Grid3& g, double tau, int sd, int qa,
+                                                    int mu, double xi[3], double n[3],
+                                                    double& sW, double& ihF) {
+  const int k = sd >> 1, hi = sd & 1, k1 = (k + 1) % 3;
+  const double ga = gp_sel(qa % 3), gb = gp_sel(qa / 3), fix = hi ? 1.0 : 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    xi[d] = d == k ? fix : (d == k1 ? ga : gb);
+    n[d] = d == k ? (hi ? 1.0 : -1.0) : 0.0;
+  }
+  const double hk = k == 0 ? g.hx : (k == 1 ? g.hy : g.hz);
+  ihF = 1.0 / hk;
+  sW = tau * (mu ? kWt[1] : kWt[0]) * gw_sel(qa % 3) * gw_sel(qa / 3) * (g.hx * g.hy * g.hz / hk);
+}
+
+// Boundary cells: one wave per cell of the six boundary layers.  Workgroup b
+// takes face b of the boundary (faces numbered side by side, side s: normal
+// direction k = s / 2, low / high end s % 2, within a side lexicographically
+// over the tangential cell indices taken cyclically after k) and processes
+// that face's cell if s is the cell's first boundary side, with all of the
+// cell's boundary sides; otherwise it exits.
+template <typename T, int LIN, bool CONV>
+__global__ __launch_bounds__(64) void face3d_kernel(Grid3 g, Model m, double tau,
+                                                    const T* __restrict__ uk,
+                                                    const T* __restrict__ x, T* __restrict__ E) {
+  __shared__ T nd[kF * 27];            // nd[f * 27 + a], local node a = ax + 3 ay + 9 az
+  __shared__ double coef[6 * 18][13];  // per task: F (3), G (3x3), pressure coefficient
+  const int n3[3] = {g.nx, g.ny, g.nz};
+  int64_t f = blockIdx.x;
+  int side = 0;
+  for (; side < 5; ++side) {
+    const int kk = side >> 1;
+    const int64_t nf = (int64_t)n3[(kk + 1) % 3] * n3[(kk + 2) % 3];
+    if (f < nf) break;
+    f -= nf;
+  }
+  int cc[3];
+  {
+    const int k = side >> 1, k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+    cc[k] = (side & 1) ? n3[k] - 1 : 0;
+    cc[k1] = (int)(f % n3[k1]);
+    cc[k2] = (int)(f / n3[k1]);
+  }
+  const int sides = (cc[0] == 0 ? 1 : 0) | (cc[0] == g.nx - 1 ? 2 : 0) | (cc[1] == 0 ? 4 : 0) |
+                    (cc[1] == g.ny - 1 ? 8 : 0) | (cc[2] == 0 ? 16 : 0) |
+                    (cc[2] == g.nz - 1 ? 32 : 0);
+  if (__builtin_ctz(sides) != side) return;  // the cell belongs to an earlier side
+  const int nsides = __builtin_popcount(sides);
+  const int64_t cell = ((int64_t)cc[2] * g.ny + cc[1]) * g.nx + cc[0];
+  const int64_t NX = 2 * g.nx + 1, NXY = NX * (2 * g.ny + 1);
+  const int64_t n0 = 2 * (int64_t)cc[2] * NXY + 2 * (int64_t)cc[1] * NX + 2 * (int64_t)cc[0];
+  T* slot = E + cell * kSlot;
+  const int t = threadIdx.x;
+  for (int l = t; l < kLines; l += 64) {
+    const int fl = l / 9, r = l % 9, lz = r / 3, ly = r % 3;
+    const int fm = fl % 6, mu = fm / 3, comp = fm % 3;
+    const T* src = (fl < 6 ? x + (int64_t)mu * g.ns : uk + (int64_t)mu * g.nv) +
+                   (int64_t)comp * g.nn + n0 + lz * NXY + ly * NX;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) nd[fl * 27 + r * 3 + a] = src[a];
+  }
+  __syncthreads();
+  // phase 1: one task per (boundary side, face point, Radau node) forms the
+  // test coefficients of the face integrand at its point
+#pragma unroll 1
+  for (int task = t; task < nsides * 18; task += 64) {
+    // the (task / 18)-th boundary side of the cell
+    int sd = 0;
+    for (int rem = task / 18, bits = sides;; bits &= bits - 1) {
+      if (rem-- == 0) {
+        sd = __builtin_ctz(bits);
+        break;
+      }
+    }
+    const int qa = (task % 18) >> 1, mu = task & 1;
+    double xi[3], n[3], sW, ihF;
+    face_point_geometry(g, tau, sd, qa, mu, xi, n, sW, ihF);
+    // 1D basis values / physical derivatives at the point, per direction
+    double bv[3][3], bd[3][3];
+    const double ihd[3] = {g.ihx, g.ihy, g.ihz};
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        bv[d][a] = q2v(a, xi[d]);
+        bd[d][a] = q2d(a, xi[d]) * ihd[d];
+      }
+    // values and gradients at the point from the 27 nodes
+    double X[3] = {0, 0, 0}, U[3] = {0, 0, 0}, GX[3][3] = {}, GU[3][3] = {};
+#pragma unroll 1
+    for (int az = 0; az < 3; ++az) {
+      const double vz = az == 0 ? bv[2][0] : (az == 1 ? bv[2][1] : bv[2][2]);
+      const double dz = az == 0 ? bd[2][0] : (az == 1 ? bd[2][1] : bd[2][2]);
+#pragma unroll
+      for (int r = 0; r < 9; ++r) {
+        const int ax = r % 3, ay = r / 3, a = az * 9 + r;
+        const double ph = bv[0][ax] * bv[1][ay] * vz;
+        const double dph[3] = {bd[0][ax] * bv[1][ay] * vz, bv[0][ax] * bd[1][ay] * vz,
+                               bv[0][ax] * bv[1][ay] * dz};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double xv = (double)nd[(mu * 3 + c) * 27 + a];
+          const double uv = (double)nd[(6 + mu * 3 + c) * 27 + a];
           X[c] += xv * ph;
           U[c] += uv * ph;
 #pragma unroll
@@ -299,115 +488,222 @@ __global__ __launch_bounds__(64) void cell_apply3d_kernel(Grid3 g, Model m, doub
           }
         }
       }
-      double A[3][3], B[3][3];
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          A[i][j] = 0.5 * (GU[i][j] + GU[j][i]);
-          B[i][j] = 0.5 * (GX[i][j] + GX[j][i]);
-        }
-      double eta, kap;
-      tangent3<LIN>(m, A, eta, kap);
-      double ab = 0.0;
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) ab += A[i][j] * B[i][j];
-      const T* pv = x + (int64_t)mu * g.ns + g.nv + 4 * cell;
-      const double xp = (double)pv[0] + (double)pv[1] * (xi[0] - 0.5) +
-                        (double)pv[2] * (xi[1] - 0.5) + (double)pv[3] * (xi[2] - 0.5);
-      const double un = U[0] * n[0] + U[1] * n[1] + U[2] * n[2];
-      const double xn = X[0] * n[0] + X[1] * n[1] + X[2] * n[2];
-      const double pen1 = m.gamma1 * m.etaD * ihF, pen2 = m.gamma2 * ihF;
-      double F[3], G[3][3];
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        double Tn = 0.0;
-#pragma unroll
-        for (int j = 0; j < 3; ++j) Tn += (eta * B[i][j] + kap * ab * A[i][j]) * n[j];
-        F[i] = -Tn + xp * n[i] + pen1 * X[i] + pen2 * xn * n[i];
-        if (CONV) {
-          const double neg = 0.5 * (fabs(un) - un);
-          F[i] += (un - neg) * X[i];
-          if (LIN != PNS_PICARD) F[i] += xn * U[i];
-        }
-        F[i] *= sW;
-#pragma unroll
-        for (int j = 0; j < 3; ++j) G[i][j] = -sW * m.etaD * 0.5 * (X[i] * n[j] + X[j] * n[i]);
-      }
-#pragma unroll 1
-      for (int a = 0; a < 27; ++a) {
-        const int ax = a % 3, ay = (a / 3) % 3, az = a / 9;
-        const double px = q2v(ax, xi[0]), py = q2v(ay, xi[1]), pz = q2v(az, xi[2]);
-        const double ph = px * py * pz;
-        const double dph[3] = {q2d(ax, xi[0]) * py * pz * ih[0], px * q2d(ay, xi[1]) * pz * ih[1],
-                               px * py * q2d(az, xi[2]) * ih[2]};
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-          atomicAdd(&outv[mu][c * 27 + a],
-                    F[c] * ph + G[c][0] * dph[0] + G[c][1] * dph[1] + G[c][2] * dph[2]);
-      }
-      const double P = sW * m.qsign * xn;
-      atomicAdd(&outv[mu][81], P);
-#pragma unroll
-      for (int j = 0; j < 3; ++j) atomicAdd(&outv[mu][82 + j], P * (xi[j] - 0.5));
     }
-    __syncthreads();
+    double A[3][3], B[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        A[i][j] = 0.5 * (GU[i][j] + GU[j][i]);
+        B[i][j] = 0.5 * (GX[i][j] + GX[j][i]);
+      }
+    double eta, kap;
+    tangent3<LIN>(m, A, eta, kap);
+    double ab = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) ab += A[i][j] * B[i][j];
+    const T* pv = x + (int64_t)mu * g.ns + g.nv + 4 * cell;
+    const double xp = (double)pv[0] + (double)pv[1] * (xi[0] - 0.5) +
+                      (double)pv[2] * (xi[1] - 0.5) + (double)pv[3] * (xi[2] - 0.5);
+    const double un = U[0] * n[0] + U[1] * n[1] + U[2] * n[2];
+    const double xn = X[0] * n[0] + X[1] * n[1] + X[2] * n[2];
+    const double pen1 = m.gamma1 * m.etaD * ihF, pen2 = m.gamma2 * ihF;
+    double* cf = coef[task];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      double Tn = 0.0;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) Tn += (eta * B[i][j] + kap * ab * A[i][j]) * n[j];
+      // -(T(B) n).w + x_pi n.w, penalties, convective flux with the inflow correction
+      double F = -Tn + xp * n[i] + pen1 * X[i] + pen2 * xn * n[i];
+      if (CONV) {
+        const double neg = 0.5 * (fabs(un) - un);
+        F += (un - neg) * X[i];
+        if (LIN != PNS_PICARD) F += xn * U[i];
+      }
+      cf[i] = sW * F;
+      // symmetry term -eta_D (D(w) n).x as a coefficient of d_j w_i
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        cf[3 + 3 * i + j] = -sW * m.etaD * 0.5 * (X[i] * n[j] + X[j] * n[i]);
+    }
+    cf[12] = sW * m.qsign * xn;  // coefficient of the pressure test
   }
-
-  // add the cell's results to y
-  for (int i = t; i < 2 * 85; i += 64) {
-    const int mu = i / 85, l = i % 85;
-    int64_t idx;
-    if (l < 81)
-      idx = (int64_t)mu * g.ns + (int64_t)(l / 27) * g.nn + gnode(l % 27);
-    else
-      idx = (int64_t)mu * g.ns + g.nv + 4 * cell + (l - 81);
-    atomicAdd(y + idx, sign * (T)outv[mu][l]);
+  __syncthreads();
+  // phase 2: one lane per unknown of the cell sums the face points of its
+  // Radau node (sides in increasing order) and adds the sum to the slot
+#pragma unroll 1
+  for (int o = t; o < kSlot; o += 64) {
+    int mu, c = 0, a = 0, j = 0;
+    const bool vel = o < 162;
+    if (vel) {
+      a = o / 6;
+      mu = (o % 6) / 3;
+      c = o % 3;
+    } else {
+      mu = (o - 162) / 4;
+      j = (o - 162) % 4;
+    }
+    const int ax = a % 3, ay = (a / 3) % 3, az = a / 9;
+    double acc = 0.0;
+    int si = 0;
+#pragma unroll 1
+    for (int bits = sides; bits; bits &= bits - 1, ++si) {
+      const int sd = __builtin_ctz(bits);
+#pragma unroll 1
+      for (int qa = 0; qa < 9; ++qa) {
+        double xi[3], n[3], sW, ihF;
+        face_point_geometry(g, tau, sd, qa, mu, xi, n, sW, ihF);
+        const double* cf = coef[si * 18 + qa * 2 + mu];
+        if (vel) {
+          const double px = q2v(ax, xi[0]), py = q2v(ay, xi[1]), pz = q2v(az, xi[2]);
+          const double d0 = q2d(ax, xi[0]) * py * pz * g.ihx;
+          const double d1 = px * q2d(ay, xi[1]) * pz * g.ihy;
+          const double d2 = px * py * q2d(az, xi[2]) * g.ihz;
+          acc += cf[c] * (px * py * pz) + cf[3 + 3 * c] * d0 + cf[4 + 3 * c] * d1 +
+                 cf[5 + 3 * c] * d2;
+        } else {
+          acc += cf[12] * (j == 0 ? 1.0 : xi[j - 1] - 0.5);
+        }
+      }
+    }
+    slot[o] = (T)((double)slot[o] + acc);
   }
 }
 
+// y = s or y = b - s, s the sum over the cells sharing each unknown of their
+// slots of E: thread i < nn takes node i (6 velocity unknowns), thread
+// nn + c takes the 8 pressure unknowns of cell c.  Cells are visited in the
+// order of increasing index, so the result does not depend on scheduling.
 template <typename T>
-__global__ void fill3_kernel(int64_t n, const T* __restrict__ b, T* __restrict__ y) {
+__global__ void gather3_kernel(Grid3 g, const T* __restrict__ E, const T* __restrict__ b,
+                               T* __restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) y[i] = b ? b[i] : (T)0;
+  if (i >= g.nn + g.nc) return;
+  if (i >= g.nn) {
+    const int64_t cell = i - g.nn;
+#pragma unroll
+    for (int mu = 0; mu < 2; ++mu)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t idx = (int64_t)mu * g.ns + g.nv + 4 * cell + j;
+        const T v = E[cell * kSlot + 162 + mu * 4 + j];
+        y[idx] = b ? b[idx] - v : v;
+      }
+    return;
+  }
+  const int64_t NX = 2 * g.nx + 1, NY = 2 * g.ny + 1;
+  const int ix = (int)(i % NX), iy = (int)((i / NX) % NY), iz = (int)(i / (NX * NY));
+  // per direction: the cells that contain the node and its local index there
+  int cs[3][2], as[3][2], ncnt[3];
+  const int ii[3] = {ix, iy, iz}, nn3[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int v = ii[d];
+    int cnt = 0;
+    if (v & 1) {
+      cs[d][0] = v >> 1;
+      as[d][0] = 1;
+      cnt = 1;
+    } else {
+      if (v > 0) {
+        cs[d][cnt] = (v >> 1) - 1;
+        as[d][cnt] = 2;
+        ++cnt;
+      }
+      if ((v >> 1) < nn3[d]) {
+        cs[d][cnt] = v >> 1;
+        as[d][cnt] = 0;
+        ++cnt;
+      }
+    }
+    ncnt[d] = cnt;
+  }
+  T acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int a2 = 0; a2 < ncnt[2]; ++a2)
+    for (int a1 = 0; a1 < ncnt[1]; ++a1)
+      for (int a0 = 0; a0 < ncnt[0]; ++a0) {
+        const int64_t cell = ((int64_t)cs[2][a2] * g.ny + cs[1][a1]) * g.nx + cs[0][a0];
+        const int a = as[0][a0] + 3 * as[1][a1] + 9 * as[2][a2];
+        // the node's 6 values are contiguous (16-byte aligned in FP64, 8 in FP32)
+        using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
+        const T2* sl = reinterpret_cast<const T2*>(E + cell * kSlot + a * 6);
+#pragma unroll
+        for (int h = 0; h < 3; ++h) {
+          const T2 v = sl[h];
+          acc[2 * h] += v.x;
+          acc[2 * h + 1] += v.y;
+        }
+      }
+#pragma unroll
+  for (int mu = 0; mu < 2; ++mu)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t idx = (int64_t)mu * g.ns + (int64_t)c * g.nn + i;
+      y[idx] = b ? b[idx] - acc[mu * 3 + c] : acc[mu * 3 + c];
+    }
+}
+
+// waves of the kernel that are resident at once on the device (0 on error)
+template <typename K>
+int64_t resident_waves(K kernel) {
+  int dev = 0, cus = 0, nb = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, 64 * kCellsPerWg, 0) != hipSuccess)
+    return 0;
+  return (int64_t)nb * cus * kCellsPerWg;
+}
+
+template <typename T, int LIN, bool CONV>
+hipError_t launch3_kernels(const Grid3& g, const Model& m, double tau, const T* uk, const T* x,
+                           T* E, hipStream_t s) {
+  auto vkern = cell_volume3d_kernel<T, LIN, CONV>;
+  static const int64_t resident = resident_waves(vkern);
+  if (resident <= 0) return hipErrorInvalidDeviceFunction;
+  const int64_t nwaves = g.nc < resident ? g.nc : resident;
+  hipLaunchKernelGGL(vkern, dim3((unsigned)((nwaves + kCellsPerWg - 1) / kCellsPerWg)),
+                     dim3(64 * kCellsPerWg), 0, s, g, m, tau, uk, x, E, nwaves);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t nfaces = 2 * ((int64_t)g.ny * g.nz + (int64_t)g.nz * g.nx + (int64_t)g.nx * g.ny);
+  hipLaunchKernelGGL((face3d_kernel<T, LIN, CONV>), dim3((unsigned)nfaces), dim3(64), 0, s, g, m,
+                     tau, uk, x, E);
+  return hipGetLastError();
 }
 
 template <typename T, int LIN>
-hipError_t launch3_lin(const Grid3& g, const Model& m, double tau, const T* uk, const T* x,
-                       T* y, T sign, hipStream_t s) {
-  const dim3 grid((unsigned)g.nc), block(64);
-  if (m.convection)
-    hipLaunchKernelGGL((cell_apply3d_kernel<T, LIN, true>), grid, block, 0, s, g, m, tau, uk, x, y,
-                       sign);
-  else
-    hipLaunchKernelGGL((cell_apply3d_kernel<T, LIN, false>), grid, block, 0, s, g, m, tau, uk, x,
-                       y, sign);
-  return hipGetLastError();
+hipError_t launch3_lin(const Grid3& g, const Model& m, double tau, const T* uk, const T* x, T* E,
+                       hipStream_t s) {
+  return m.convection ? launch3_kernels<T, LIN, true>(g, m, tau, uk, x, E, s)
+                      : launch3_kernels<T, LIN, false>(g, m, tau, uk, x, E, s);
 }
 
 }  // namespace
 
 template <typename T>
 hipError_t launch_cell_apply3d(const Grid3& g, const Model& m, double tau, const T* uk,
-                               const T* x, const T* b, T* y, int mode, hipStream_t s) {
-  // y = 0 (action) or y = b (defect), then the cells add +J x or -J x
-  hipLaunchKernelGGL(fill3_kernel<T>, dim3((unsigned)((g.nst + 255) / 256)), dim3(256), 0, s,
-                     g.nst, mode ? b : (const T*)nullptr, y);
-  const T sign = mode ? (T)-1 : (T)1;
+                               const T* x, const T* b, T* y, T* E, int mode, hipStream_t s) {
+  hipError_t e;
   switch (m.lin) {
-    case PNS_PICARD: return launch3_lin<T, PNS_PICARD>(g, m, tau, uk, x, y, sign, s);
-    case PNS_EXACT_NEWTON: return launch3_lin<T, PNS_EXACT_NEWTON>(g, m, tau, uk, x, y, sign, s);
-    default: return launch3_lin<T, PNS_MODIFIED_NEWTON>(g, m, tau, uk, x, y, sign, s);
+    case PNS_PICARD: e = launch3_lin<T, PNS_PICARD>(g, m, tau, uk, x, E, s); break;
+    case PNS_EXACT_NEWTON: e = launch3_lin<T, PNS_EXACT_NEWTON>(g, m, tau, uk, x, E, s); break;
+    default: e = launch3_lin<T, PNS_MODIFIED_NEWTON>(g, m, tau, uk, x, E, s); break;
   }
+  if (e != hipSuccess) return e;
+  const int64_t nt = g.nn + g.nc;
+  hipLaunchKernelGGL(gather3_kernel<T>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, g,
+                     (const T*)E, mode ? b : (const T*)nullptr, y);
+  return hipGetLastError();
 }
 
 template hipError_t launch_cell_apply3d<double>(const Grid3&, const Model&, double, const double*,
-                                                const double*, const double*, double*, int,
-                                                hipStream_t);
+                                                const double*, const double*, double*, double*,
+                                                int, hipStream_t);
 template hipError_t launch_cell_apply3d<float>(const Grid3&, const Model&, double, const float*,
-                                               const float*, const float*, float*, int,
+                                               const float*, const float*, float*, float*, int,
                                                hipStream_t);
 
 }  // namespace pns

@@ -66,6 +66,7 @@ struct pns_ctx {
   int apply_mode = PNS_APPLY_RECOMPUTE;
   int patch_kind = PNS_PATCH_SURROGATE;  // finest-level patch matrices
   void* tcache = nullptr;  // per-point tangent coefficients of level 0
+  void* E3 = nullptr;      // 3D: per-cell results of the action (170 per cell)
 };
 
 #define PNS_HIP(ctx, call)                                                                  \

@@ -116,10 +116,11 @@ template <typename T>
 hipError_t launch_tangent_cache(const Grid& g, const Model& m, double tau, const double* uk,
                                 T* cache, hipStream_t s);
 
-// apply3d.hip: the same operator on hexahedra; mode 0: y = J x, mode 1: y = b - J x
+// apply3d.hip: the same operator on hexahedra; mode 0: y = J x, mode 1: y = b - J x;
+// E: per-cell results, nc * 170 values of scratch
 template <typename T>
 hipError_t launch_cell_apply3d(const Grid3& g, const Model& m, double tau, const T* uk,
-                               const T* x, const T* b, T* y, int mode, hipStream_t s);
+                               const T* x, const T* b, T* y, T* E, int mode, hipStream_t s);
 
 // setup.hip
 hipError_t launch_element_matrices(const Grid& g, const Model& m, const double* u, double* Es,
