@@ -396,13 +396,20 @@ __device__ __forceinline__ void face_point_geometry(const Grid3& g, double tau, 
 // direction k = s / 2, low / high end s % 2, within a side lexicographically
 // over the tangential cell indices taken cyclically after k) and processes
 // that face's cell if s is the cell's first boundary side, with all of the
-// cell's boundary sides; otherwise it exits.
+// cell's boundary sides in turn; otherwise it exits.  Per side, sum
+// factorisation on the face: the nodal values are contracted along the normal
+// (face-layer value and normal derivative) and along the two tangential
+// directions to the 3 x 3 face Gauss points; after the pointwise integrand
+// the transposed contractions give the 81 velocity and 4 pressure results of
+// each Radau node, one output line per lane, added to the cell's slot of E.
 template <typename T, int LIN, bool CONV>
 __global__ __launch_bounds__(64) void face3d_kernel(Grid3 g, Model m, double tau,
                                                     const T* __restrict__ uk,
                                                     const T* __restrict__ x, T* __restrict__ E) {
   __shared__ T nd[kF * 27];            // nd[f * 27 + a], local node a = ax + 3 ay + 9 az
-  __shared__ double coef[6 * 18][13];  // per task: F (3), G (3x3), pressure coefficient
+  __shared__ double pf[kF][9][4];      // per field, face point: value, d/dx, d/dy, d/dz
+  __shared__ double coef[2][9][13];    // per Radau node, face point: F (3), G (3x3), P
+  __shared__ double outv[kSlot];       // the cell's slot of E, FP64
   const int n3[3] = {g.nx, g.ny, g.nz};
   int64_t f = blockIdx.x;
   int side = 0;
@@ -423,7 +430,6 @@ __global__ __launch_bounds__(64) void face3d_kernel(Grid3 g, Model m, double tau
                     (cc[1] == g.ny - 1 ? 8 : 0) | (cc[2] == 0 ? 16 : 0) |
                     (cc[2] == g.nz - 1 ? 32 : 0);
   if (__builtin_ctz(sides) != side) return;  // the cell belongs to an earlier side
-  const int nsides = __builtin_popcount(sides);
   const int64_t cell = ((int64_t)cc[2] * g.ny + cc[1]) * g.nx + cc[0];
   const int64_t NX = 2 * g.nx + 1, NXY = NX * (2 * g.ny + 1);
   const int64_t n0 = 2 * (int64_t)cc[2] * NXY + 2 * (int64_t)cc[1] * NX + 2 * (int64_t)cc[0];
@@ -437,140 +443,153 @@ __global__ __launch_bounds__(64) void face3d_kernel(Grid3 g, Model m, double tau
 #pragma unroll
     for (int a = 0; a < 3; ++a) nd[fl * 27 + r * 3 + a] = src[a];
   }
+  for (int i = t; i < kSlot; i += 64) outv[i] = (double)slot[i];
+  const double ihd[3] = {g.ihx, g.ihy, g.ihz};
   __syncthreads();
-  // phase 1: one task per (boundary side, face point, Radau node) forms the
-  // test coefficients of the face integrand at its point
 #pragma unroll 1
-  for (int task = t; task < nsides * 18; task += 64) {
-    // the (task / 18)-th boundary side of the cell
-    int sd = 0;
-    for (int rem = task / 18, bits = sides;; bits &= bits - 1) {
-      if (rem-- == 0) {
-        sd = __builtin_ctz(bits);
-        break;
-      }
-    }
-    const int qa = (task % 18) >> 1, mu = task & 1;
-    double xi[3], n[3], sW, ihF;
-    face_point_geometry(g, tau, sd, qa, mu, xi, n, sW, ihF);
-    // 1D basis values / physical derivatives at the point, per direction
-    double bv[3][3], bd[3][3];
-    const double ihd[3] = {g.ihx, g.ihy, g.ihz};
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        bv[d][a] = q2v(a, xi[d]);
-        bd[d][a] = q2d(a, xi[d]) * ihd[d];
-      }
-    // values and gradients at the point from the 27 nodes
-    double X[3] = {0, 0, 0}, U[3] = {0, 0, 0}, GX[3][3] = {}, GU[3][3] = {};
+  for (int bits = sides; bits; bits &= bits - 1) {
+    const int sd = __builtin_ctz(bits);
+    const int k = sd >> 1, hi = sd & 1, k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+    // strides of the local node index along k, k1, k2; the face layer along k
+    const int sk = k == 0 ? 1 : (k == 1 ? 3 : 9);
+    const int s1 = k1 == 0 ? 1 : (k1 == 1 ? 3 : 9);
+    const int s2 = k2 == 0 ? 1 : (k2 == 1 ? 3 : 9);
+    const int lay = hi ? 2 : 0;
+    // derivative of the 1D basis along k at the face (reference): q2d(a, 0 or 1)
+    const double dn0 = hi ? 1.0 : -3.0, dn1 = hi ? -4.0 : 4.0, dn2 = hi ? 3.0 : -1.0;
+    const double ihk = k == 0 ? g.ihx : (k == 1 ? g.ihy : g.ihz);
+    const double ih1 = k1 == 0 ? g.ihx : (k1 == 1 ? g.ihy : g.ihz);
+    const double ih2 = k2 == 0 ? g.ihx : (k2 == 1 ? g.ihy : g.ihz);
+    // ---- (1) fields at the face points: lane (field, point q1 + 3 q2)
 #pragma unroll 1
-    for (int az = 0; az < 3; ++az) {
-      const double vz = az == 0 ? bv[2][0] : (az == 1 ? bv[2][1] : bv[2][2]);
-      const double dz = az == 0 ? bd[2][0] : (az == 1 ? bd[2][1] : bd[2][2]);
+    for (int l = t; l < kF * 9; l += 64) {
+      const int fl = l / 9, q = l % 9, q1 = q % 3, q2 = q / 3;
+      const T* nf = nd + fl * 27;
+      double v = 0.0, d1 = 0.0, d2 = 0.0, dk = 0.0;
 #pragma unroll
-      for (int r = 0; r < 9; ++r) {
-        const int ax = r % 3, ay = r / 3, a = az * 9 + r;
-        const double ph = bv[0][ax] * bv[1][ay] * vz;
-        const double dph[3] = {bd[0][ax] * bv[1][ay] * vz, bv[0][ax] * bd[1][ay] * vz,
-                               bv[0][ax] * bv[1][ay] * dz};
+      for (int b2 = 0; b2 < 3; ++b2) {
+        const double B2 = q2 == 0 ? Bq(0, b2) : (q2 == 1 ? Bq(1, b2) : Bq(2, b2));
+        const double D2 = q2 == 0 ? Dq(0, b2) : (q2 == 1 ? Dq(1, b2) : Dq(2, b2));
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const double xv = (double)nd[(mu * 3 + c) * 27 + a];
-          const double uv = (double)nd[(6 + mu * 3 + c) * 27 + a];
-          X[c] += xv * ph;
-          U[c] += uv * ph;
-#pragma unroll
-          for (int j = 0; j < 3; ++j) {
-            GX[c][j] += xv * dph[j];
-            GU[c][j] += uv * dph[j];
-          }
+        for (int b1 = 0; b1 < 3; ++b1) {
+          const double B1 = q1 == 0 ? Bq(0, b1) : (q1 == 1 ? Bq(1, b1) : Bq(2, b1));
+          const double D1 = q1 == 0 ? Dq(0, b1) : (q1 == 1 ? Dq(1, b1) : Dq(2, b1));
+          const int ab = b1 * s1 + b2 * s2;
+          const double val = (double)nf[ab + lay * sk];
+          const double dnv = dn0 * (double)nf[ab] + dn1 * (double)nf[ab + sk] +
+                             dn2 * (double)nf[ab + 2 * sk];
+          v += B1 * B2 * val;
+          d1 += D1 * B2 * val;
+          d2 += B1 * D2 * val;
+          dk += B1 * B2 * dnv;
         }
       }
+      d1 *= ih1;
+      d2 *= ih2;
+      dk *= ihk;
+      pf[fl][q][0] = v;
+      pf[fl][q][1] = k == 0 ? dk : (k1 == 0 ? d1 : d2);
+      pf[fl][q][2] = k == 1 ? dk : (k1 == 1 ? d1 : d2);
+      pf[fl][q][3] = k == 2 ? dk : (k1 == 2 ? d1 : d2);
     }
-    double A[3][3], B[3][3];
+    __syncthreads();
+    // ---- (2) integrand: lane (point, Radau node)
+    if (t < 18) {
+      const int qa = t >> 1, mu = t & 1;
+      double xi[3], n[3], sW, ihF;
+      face_point_geometry(g, tau, sd, qa, mu, xi, n, sW, ihF);
+      double X[3], U[3], A[3][3], B[3][3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        A[i][j] = 0.5 * (GU[i][j] + GU[j][i]);
-        B[i][j] = 0.5 * (GX[i][j] + GX[j][i]);
+      for (int i = 0; i < 3; ++i) {
+        X[i] = pf[mu * 3 + i][qa][0];
+        U[i] = pf[6 + mu * 3 + i][qa][0];
       }
-    double eta, kap;
-    tangent3<LIN>(m, A, eta, kap);
-    double ab = 0.0;
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
+      for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) ab += A[i][j] * B[i][j];
-    const T* pv = x + (int64_t)mu * g.ns + g.nv + 4 * cell;
-    const double xp = (double)pv[0] + (double)pv[1] * (xi[0] - 0.5) +
-                      (double)pv[2] * (xi[1] - 0.5) + (double)pv[3] * (xi[2] - 0.5);
-    const double un = U[0] * n[0] + U[1] * n[1] + U[2] * n[2];
-    const double xn = X[0] * n[0] + X[1] * n[1] + X[2] * n[2];
-    const double pen1 = m.gamma1 * m.etaD * ihF, pen2 = m.gamma2 * ihF;
-    double* cf = coef[task];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      double Tn = 0.0;
-#pragma unroll
-      for (int j = 0; j < 3; ++j) Tn += (eta * B[i][j] + kap * ab * A[i][j]) * n[j];
-      // -(T(B) n).w + x_pi n.w, penalties, convective flux with the inflow correction
-      double F = -Tn + xp * n[i] + pen1 * X[i] + pen2 * xn * n[i];
-      if (CONV) {
-        const double neg = 0.5 * (fabs(un) - un);
-        F += (un - neg) * X[i];
-        if (LIN != PNS_PICARD) F += xn * U[i];
-      }
-      cf[i] = sW * F;
-      // symmetry term -eta_D (D(w) n).x as a coefficient of d_j w_i
-#pragma unroll
-      for (int j = 0; j < 3; ++j)
-        cf[3 + 3 * i + j] = -sW * m.etaD * 0.5 * (X[i] * n[j] + X[j] * n[i]);
-    }
-    cf[12] = sW * m.qsign * xn;  // coefficient of the pressure test
-  }
-  __syncthreads();
-  // phase 2: one lane per unknown of the cell sums the face points of its
-  // Radau node (sides in increasing order) and adds the sum to the slot
-#pragma unroll 1
-  for (int o = t; o < kSlot; o += 64) {
-    int mu, c = 0, a = 0, j = 0;
-    const bool vel = o < 162;
-    if (vel) {
-      a = o / 6;
-      mu = (o % 6) / 3;
-      c = o % 3;
-    } else {
-      mu = (o - 162) / 4;
-      j = (o - 162) % 4;
-    }
-    const int ax = a % 3, ay = (a / 3) % 3, az = a / 9;
-    double acc = 0.0;
-    int si = 0;
-#pragma unroll 1
-    for (int bits = sides; bits; bits &= bits - 1, ++si) {
-      const int sd = __builtin_ctz(bits);
-#pragma unroll 1
-      for (int qa = 0; qa < 9; ++qa) {
-        double xi[3], n[3], sW, ihF;
-        face_point_geometry(g, tau, sd, qa, mu, xi, n, sW, ihF);
-        const double* cf = coef[si * 18 + qa * 2 + mu];
-        if (vel) {
-          const double px = q2v(ax, xi[0]), py = q2v(ay, xi[1]), pz = q2v(az, xi[2]);
-          const double d0 = q2d(ax, xi[0]) * py * pz * g.ihx;
-          const double d1 = px * q2d(ay, xi[1]) * pz * g.ihy;
-          const double d2 = px * py * q2d(az, xi[2]) * g.ihz;
-          acc += cf[c] * (px * py * pz) + cf[3 + 3 * c] * d0 + cf[4 + 3 * c] * d1 +
-                 cf[5 + 3 * c] * d2;
-        } else {
-          acc += cf[12] * (j == 0 ? 1.0 : xi[j - 1] - 0.5);
+        for (int j = 0; j < 3; ++j) {
+          A[i][j] = 0.5 * (pf[6 + mu * 3 + i][qa][1 + j] + pf[6 + mu * 3 + j][qa][1 + i]);
+          B[i][j] = 0.5 * (pf[mu * 3 + i][qa][1 + j] + pf[mu * 3 + j][qa][1 + i]);
         }
+      double eta, kap;
+      tangent3<LIN>(m, A, eta, kap);
+      double ab = 0.0;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) ab += A[i][j] * B[i][j];
+      const T* pv = x + (int64_t)mu * g.ns + g.nv + 4 * cell;
+      const double xp = (double)pv[0] + (double)pv[1] * (xi[0] - 0.5) +
+                        (double)pv[2] * (xi[1] - 0.5) + (double)pv[3] * (xi[2] - 0.5);
+      const double un = U[0] * n[0] + U[1] * n[1] + U[2] * n[2];
+      const double xn = X[0] * n[0] + X[1] * n[1] + X[2] * n[2];
+      const double pen1 = m.gamma1 * m.etaD * ihF, pen2 = m.gamma2 * ihF;
+      double* cf = coef[mu][qa];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        double Tn = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Tn += (eta * B[i][j] + kap * ab * A[i][j]) * n[j];
+        // -(T(B) n).w + x_pi n.w, penalties, convective flux with the inflow correction
+        double F = -Tn + xp * n[i] + pen1 * X[i] + pen2 * xn * n[i];
+        if (CONV) {
+          const double neg = 0.5 * (fabs(un) - un);
+          F += (un - neg) * X[i];
+          if (LIN != PNS_PICARD) F += xn * U[i];
+        }
+        cf[i] = sW * F;
+        // symmetry term -eta_D (D(w) n).x as a coefficient of d_j w_i
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          cf[3 + 3 * i + j] = -sW * m.etaD * 0.5 * (X[i] * n[j] + X[j] * n[i]);
       }
+      cf[12] = sW * m.qsign * xn;  // coefficient of the pressure test
     }
-    slot[o] = (T)((double)slot[o] + acc);
+    __syncthreads();
+    // ---- (3) transposed: lane (mu, c, face node b1 + 3 b2) -> its 3 nodes along k;
+    // lanes 54..61 the pressure rows
+    if (t < 54) {
+      const int mu = t / 27, c = (t / 9) % 3, b = t % 9, b1 = b % 3, b2 = b / 3;
+      // component of the gradient coefficient along k, k1, k2
+      const int gk = 3 + 3 * c + k, g1 = 3 + 3 * c + k1, g2 = 3 + 3 * c + k2;
+      double sface = 0.0, snorm = 0.0;
+#pragma unroll
+      for (int q2 = 0; q2 < 3; ++q2)
+#pragma unroll
+        for (int q1 = 0; q1 < 3; ++q1) {
+          const double* cf = coef[mu][q1 + 3 * q2];
+          const double BB = Bq(q1, b1 == 0 ? 0 : (b1 == 1 ? 1 : 2)) *
+                            Bq(q2, b2 == 0 ? 0 : (b2 == 1 ? 1 : 2));
+          const double DB = Dq(q1, b1 == 0 ? 0 : (b1 == 1 ? 1 : 2)) *
+                            Bq(q2, b2 == 0 ? 0 : (b2 == 1 ? 1 : 2));
+          const double BD = Bq(q1, b1 == 0 ? 0 : (b1 == 1 ? 1 : 2)) *
+                            Dq(q2, b2 == 0 ? 0 : (b2 == 1 ? 1 : 2));
+          sface += cf[c] * BB + cf[g1] * ih1 * DB + cf[g2] * ih2 * BD;
+          snorm += cf[gk] * ihk * BB;
+        }
+      const int ab = b1 * s1 + b2 * s2;
+      double* o = outv + mu * 3 + c;
+      // node index a in the slot: velocity at a*6 + mu*3 + c
+      o[(ab + 0 * sk) * 6] += dn0 * snorm + (lay == 0 ? sface : 0.0);
+      o[(ab + 1 * sk) * 6] += dn1 * snorm;
+      o[(ab + 2 * sk) * 6] += dn2 * snorm + (lay == 2 ? sface : 0.0);
+    } else if (t < 62) {
+      const int mu = (t - 54) / 4, j = (t - 54) % 4;
+      double sp = 0.0;
+#pragma unroll
+      for (int q2 = 0; q2 < 3; ++q2)
+#pragma unroll
+        for (int q1 = 0; q1 < 3; ++q1) {
+          // psi_j at the point: 1 or (xi_d - 1/2), d = j - 1
+          const int d = j - 1;
+          const double xd = d == k ? (hi ? 1.0 : 0.0) : (d == k1 ? kGP[q1] : kGP[q2]);
+          sp += coef[mu][q1 + 3 * q2][12] * (j == 0 ? 1.0 : xd - 0.5);
+        }
+      outv[162 + mu * 4 + j] += sp;
+    }
+    __syncthreads();
   }
+  for (int i = t; i < kSlot; i += 64) slot[i] = (T)outv[i];
 }
 
 // y = s or y = b - s, s the sum over the cells sharing each unknown of their
@@ -595,48 +614,49 @@ __global__ void gather3_kernel(Grid3 g, const T* __restrict__ E, const T* __rest
     return;
   }
   const int64_t NX = 2 * g.nx + 1, NY = 2 * g.ny + 1;
-  const int ix = (int)(i % NX), iy = (int)((i / NX) % NY), iz = (int)(i / (NX * NY));
-  // per direction: the cells that contain the node and its local index there
-  int cs[3][2], as[3][2], ncnt[3];
-  const int ii[3] = {ix, iy, iz}, nn3[3] = {g.nx, g.ny, g.nz};
+  const int ii[3] = {(int)(i % NX), (int)((i / NX) % NY), (int)(i / (NX * NY))};
+  const int nn3[3] = {g.nx, g.ny, g.nz};
+  // per direction, candidates h = 0, 1: the cell below the node (local index
+  // 2) and the cell above it (local index 0); an odd node index lies inside
+  // one cell (local index 1, candidate 1 only)
+  int cs[3][2], as[3][2];
+  bool ok[3][2];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int v = ii[d];
-    int cnt = 0;
-    if (v & 1) {
-      cs[d][0] = v >> 1;
-      as[d][0] = 1;
-      cnt = 1;
-    } else {
-      if (v > 0) {
-        cs[d][cnt] = (v >> 1) - 1;
-        as[d][cnt] = 2;
-        ++cnt;
-      }
-      if ((v >> 1) < nn3[d]) {
-        cs[d][cnt] = v >> 1;
-        as[d][cnt] = 0;
-        ++cnt;
-      }
+    const bool odd = v & 1;
+    cs[d][0] = (v >> 1) - 1;
+    as[d][0] = 2;
+    ok[d][0] = !odd && v > 0;
+    cs[d][1] = v >> 1;
+    as[d][1] = odd ? 1 : 0;
+    ok[d][1] = (v >> 1) < nn3[d];
+  }
+  // all loads first (fixed trip count), then the sum in a fixed order
+  using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
+  T2 v[8][3];
+#pragma unroll
+  for (int h = 0; h < 8; ++h) {
+    const int h0 = h & 1, h1 = (h >> 1) & 1, h2 = h >> 2;
+    const bool use = ok[0][h0] && ok[1][h1] && ok[2][h2];
+    const int64_t cell =
+        use ? ((int64_t)cs[2][h2] * g.ny + cs[1][h1]) * g.nx + cs[0][h0] : 0;
+    const int a = as[0][h0] + 3 * as[1][h1] + 9 * as[2][h2];
+    // the node's 6 values are contiguous (16-byte aligned in FP64, 8 in FP32)
+    const T2* sl = reinterpret_cast<const T2*>(E + cell * kSlot + a * 6);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      v[h][q] = use ? sl[q] : T2{(T)0, (T)0};
     }
-    ncnt[d] = cnt;
   }
   T acc[6] = {0, 0, 0, 0, 0, 0};
-  for (int a2 = 0; a2 < ncnt[2]; ++a2)
-    for (int a1 = 0; a1 < ncnt[1]; ++a1)
-      for (int a0 = 0; a0 < ncnt[0]; ++a0) {
-        const int64_t cell = ((int64_t)cs[2][a2] * g.ny + cs[1][a1]) * g.nx + cs[0][a0];
-        const int a = as[0][a0] + 3 * as[1][a1] + 9 * as[2][a2];
-        // the node's 6 values are contiguous (16-byte aligned in FP64, 8 in FP32)
-        using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
-        const T2* sl = reinterpret_cast<const T2*>(E + cell * kSlot + a * 6);
 #pragma unroll
-        for (int h = 0; h < 3; ++h) {
-          const T2 v = sl[h];
-          acc[2 * h] += v.x;
-          acc[2 * h + 1] += v.y;
-        }
-      }
+  for (int h = 0; h < 8; ++h)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      acc[2 * q] += v[h][q].x;
+      acc[2 * q + 1] += v[h][q].y;
+    }
 #pragma unroll
   for (int mu = 0; mu < 2; ++mu)
 #pragma unroll
