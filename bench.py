@@ -17,8 +17,13 @@ the stream the kernels run on around the block of four); FP32 figures, the cache
 V-cycle seconds alongside.  The action's roofline is the FP64 vector ALU
 (its arithmetic intensity, ~14 flop/B, is above the FP64 ridge of ~9.8 flop/B).
 
+Beside the step: the 3D action on 32^3 hexahedra (FP64 and FP32), the slab
+solve's time to 1e-8, the batched finest-level Vanka at 512^2 and the request
+server's latencies, each as a field of its own in the JSON line.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256]
        [--levels 4] [--no-cpu] [--apply-only] [--lin 2] [--calib-copy]
+       [--apply3d-n 32] [--solve-n 256] [--vanka-n 512] [--serve-requests 48]
 """
 from __future__ import annotations
 
@@ -59,9 +64,10 @@ def algorithmic_bytes(sizes, elem):
 # each scaled by the counter's reading for a plain streaming kernel of known
 # size, with the hash of the kernel source the counters were taken on
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "cell_apply_256x256_fp64_counters.md")
-# the action kernel's own source (the element constants it includes are fixed
-# by the discretisation)
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2603_28706_amd", "csrc", "apply.hip")]
+# the action kernel's own source and its elementary functions (the element
+# constants it includes are fixed by the discretisation)
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2603_28706_amd", "csrc", f)
+                  for f in ("apply.hip", "devmath.h")]
 
 
 def kernel_source_hash():
@@ -113,6 +119,72 @@ def apply_flops_per_cell(lin):
     point = (72 + 6 + 12 + 3 + 4 + tangent_flops(lin) + (18 if newton else 5)
              + (16 if newton else 8) + 8 + 2 + 7 + 36)
     return 2 * 3 * (144 + 3 * point + 72 + 18)
+
+
+def apply3d_flops_per_cell(lin):
+    """Algorithmic operations of the sum-factorised 3D volume action per
+    hexahedron (both Radau nodes; the boundary faces and the gather over cells
+    are not counted).  Forward contractions of 12 fields (x and u_k, 3
+    components, 2 Radau nodes) on 9 lines each: along x 2 outputs, along y 3,
+    along z 4, at 3 points with 3 FMA each (3888 + 5832 + 7776).  Per point
+    and Radau node (54): gradient scalings (18), symmetric parts (36), tangent
+    scalars (those of the 2D count plus 12 for the longer |A|^2), A:B (18),
+    kappa A:B (1), pressure value (6), temporal mass coupling (12), test
+    coefficients of the 9 gradient entries (84 Newton / 66 Picard), divergence
+    and pressure-row terms (7), weights (4); pressure-row sums over the 27
+    points (216).  Transposed contractions onto the 81 velocity tests per
+    Radau node: along z 12 FMA, along y 9, along x 6 per line and node
+    (3888 + 2916 + 1944)."""
+    newton = lin != 0
+    point = 18 + 36 + tangent_flops(lin) + 12 + 18 + 1 + 6 + 12 + (84 if newton else 66) + 7 + 4
+    return 3888 + 5832 + 7776 + 54 * point + 216 + 3888 + 2916 + 1944
+
+
+MODEL3D = dict(p=1.3, delta=1e-3, nu=1.0, nu_inf=1e-3, gamma1=40.0, gamma2=40.0, sigma_max=1.0,
+               convection=1, qsign=1)
+
+
+def apply3d(n=32, reps=50, lin=2):
+    """3D action on n^3 hexahedra (Q2 / P1disc x dG(1), tau = 0.01) with
+    p = 1.3, delta = 1e-3, nu = 1, nu_inf = 1e-3; state: 3D sin-series
+    velocity (8 modes, seed 301, O(tau) time variation), input U[-1, 1]
+    (seed 302).  Mean duration of `reps` back-to-back actions (HIP events on
+    the stream the kernels run on), FP64 and FP32."""
+    import torch
+
+    from paper_2603_28706_amd import inputs, pnsmg
+
+    uk = torch.tensor(inputs.sin_series_velocity((n, n, n), seed=301, t_nodes=[0.01 / 3, 0.01]),
+                      device="cuda")
+    out = {}
+    for prec, name in ((pnsmg.FP64, "fp64"), (pnsmg.FP32, "fp32")):
+        ctx = pnsmg.Context((n, n, n), precision=prec)
+        ctx.pns_set_state(dict(MODEL3D, lin=lin), uk)
+        sz = ctx.sizes()
+        x = torch.tensor(inputs.uniform(302, sz["nst"]), dtype=ctx.dtype, device="cuda")
+        y = ctx.vector()
+        for _ in range(3):
+            ctx.pns_cell_apply(x, y)
+        stream = torch.cuda.current_stream()
+        ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ea.record(stream)
+        for _ in range(reps):
+            ctx.pns_cell_apply(x, y)
+        eb.record(stream)
+        torch.cuda.synchronize()
+        t = ea.elapsed_time(eb) * 1e-3 / reps
+        flops = apply3d_flops_per_cell(lin) * sz["cells"]
+        out[name] = dict(us_mean=t * 1e6, gdofs=sz["nst"] / t / 1e9,
+                         volume_tflops=flops / t / 1e12,
+                         hbm_gbs=algorithmic_bytes(sz, 8 if prec == pnsmg.FP64 else 4) / t / 1e9)
+        out["space_time_dof"] = sz["nst"]
+        out["flop_per_apply"] = flops
+        print(f"[bench] 3D action {n}^3 {name}: {t * 1e6:.1f} us, {sz['nst'] / t / 1e9:.2f} GDoF/s",
+              file=sys.stderr, flush=True)
+        del ctx
+        torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(n_sample=128, reps=2):
@@ -397,6 +469,8 @@ def main():
                     help="mesh of the batched-Vanka measurement (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests of the serving measurement (0: skip)")
+    ap.add_argument("--apply3d-n", type=int, default=32,
+                    help="mesh of the 3D action measurement, n^3 hexahedra (0: skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain streaming kernel of known size (counter calibration)")
     ap.add_argument("--lin", type=int, default=2, help="0 Picard, 1 exact Newton, 2 modified Newton")
@@ -450,6 +524,13 @@ def main():
                      "kernel": "cell_apply_kernel<double, modified Newton, recompute>",
                      "flop_per_launch": flops, "algorithmic_bytes": f64["bytes"]},
     }
+    if args.apply3d_n and not args.apply_only:
+        a3 = apply3d(args.apply3d_n, lin=args.lin)
+        line["apply3d"] = {
+            "workload": (f"3D {args.apply3d_n}^3 hexahedra Q2/P1disc x dG(1), p=1.3 delta=1e-3 "
+                         f"nu_inf=1e-3, modified-Newton Jacobian action, 3D sin-series state"),
+            **{k: ({kk: round(vv, 4) for kk, vv in v.items()} if isinstance(v, dict) else v)
+               for k, v in a3.items()}}
     if args.solve_n and not args.apply_only:
         sl = solve_latency(args.solve_n, SOLVE_SEEDS)
         line["solve_time_to_1e-8_s"] = {
