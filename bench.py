@@ -286,6 +286,22 @@ def run(args):
         torch.cuda.synchronize()
         t_cached = ea.elapsed_time(eb) * 1e-3 / n_rep
         ctx.pns_set_apply_mode(pnsmg.APPLY_RECOMPUTE)
+        # the same V-cycle replayed from one captured HIP graph (reported alongside)
+        t_vc_graph = None
+        if not args.apply_only:
+            ctx.pns_set_vcycle_graph(1)
+            ctx.pns_vcycle(2, 2, OMEGA, r, d)   # capture
+            torch.cuda.synchronize()
+            tg = []
+            for _ in range(max(20, args.steps // 2)):
+                ga, gb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                ga.record(stream)
+                ctx.pns_vcycle(2, 2, OMEGA, r, d)
+                gb.record(stream)
+                tg.append((ga, gb))
+            torch.cuda.synchronize()
+            t_vc_graph = float(np.median([a.elapsed_time(b) for a, b in tg])) * 1e-3
+            ctx.pns_set_vcycle_graph(0)
         elem = 8 if prec == pnsmg.FP64 else 4
         results[name] = dict(
             nst=sz["nst"], cells=sz["cells"], wall_s=wall, ms_per_step=wall / args.steps * 1e3,
@@ -293,12 +309,12 @@ def run(args):
             apply_s_p10=float(np.percentile(t_apply, 10)),
             apply_s_p90=float(np.percentile(t_apply, 90)), apply_s_cached=t_cached,
             vcycle_s_median=float(np.median(t_vc)) if not args.apply_only else None,
-            setup_s=t_setup, bytes=algorithmic_bytes(sz, elem))
+            vcycle_s_graph=t_vc_graph, setup_s=t_setup, bytes=algorithmic_bytes(sz, elem))
         print(f"[bench] {name}: apply {np.mean(t_apply) * 1e6:.1f} us mean in step "
               f"(p50 {np.median(t_apply) * 1e6:.1f}), cached tangent {t_cached * 1e6:.1f} us "
               f"back-to-back; V-cycle "
-              f"{(np.median(t_vc) * 1e3) if not args.apply_only else 0:.3f} ms",
-              file=sys.stderr, flush=True)
+              f"{(np.median(t_vc) * 1e3) if not args.apply_only else 0:.3f} ms (graph-replayed "
+              f"{(t_vc_graph or 0) * 1e3:.3f} ms)", file=sys.stderr, flush=True)
         del ctx
         torch.cuda.empty_cache()
     return results
@@ -515,6 +531,7 @@ def main():
         "apply_hbm_gbs_fp64": round(f64["bytes"] / t_ap / 1e9, 1),
         "vcycle_s_fp64": f64["vcycle_s_median"],
         "vcycle_s_fp32": f32["vcycle_s_median"],
+        "vcycle_s_graph_fp64_fp32": [f64["vcycle_s_graph"], f32["vcycle_s_graph"]],
         "setup_s_fp64": f64["setup_s"],
         "setup_s_fp32": f32["setup_s"],
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),

@@ -200,6 +200,18 @@ int pns_vanka_smooth(pns_ctx* ctx, int level, int n_sweeps, double omega, const 
  * PNS_EUNSUPPORTED if the coarsest level exceeds the dense-solve limit. */
 int pns_vcycle(pns_ctx* ctx, int nu1, int nu2, double omega, const void* r_dev, void* d_dev);
 
+/* enable = 1: pns_vcycle (and so the preconditioner of pns_solve) replays one
+ * HIP graph holding the whole V-cycle of the operator sequence above, instead
+ * of launching its ~100 kernels one by one; the launch overhead of the small
+ * coarse-level grids goes away, the arithmetic is the same.  The graph is
+ * captured at the first V-cycle on a stream the library creates (default
+ * priority), is keyed on (nu1, nu2, omega) and is dropped by pns_set_state,
+ * pns_vanka_setup, pns_set_apply_mode, pns_set_patch_kind and
+ * pns_bind_workspace; r and d pass through two workspace vectors (two copies
+ * per V-cycle).  enable = 0 returns to eager launches.  PNS_EINVAL for other
+ * values, PNS_EUNSUPPORTED on 3D contexts. */
+int pns_set_vcycle_graph(pns_ctx* ctx, int enable);
+
 /* y = A_l x with the level-l operator (level 0: pns_cell_apply; coarser:
  * the Galerkin operator applied element by element).  Needs pns_vanka_setup
  * for level > 0. */

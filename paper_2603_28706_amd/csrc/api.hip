@@ -45,6 +45,8 @@ size_t layout(pns_ctx* c, bool bind) {
   c->Esr = (double*)take(g0.nc * kNs * kNs * 8);
   c->masks = (uint16_t*)take(g0.nc * sizeof(uint16_t));
   c->tcache = take(g0.nc * 18 * 6 * es);
+  c->gr = take(g0.nst * es);
+  c->gd = take(g0.nst * es);
   c->status = (int*)take(sizeof(int) * 4);
   for (int l = 0; l < c->nlev; ++l) {
     Level& L = c->lev[l];
@@ -237,6 +239,42 @@ int vanka_setup_impl(pns_ctx* c, const uint16_t* masks) {
   return PNS_OK;
 }
 
+// One V-cycle d = V(r) replayed from a graph captured on the library's own
+// stream (the context stream may be the legacy default stream, which cannot
+// capture): r is copied into c->gr, the graph runs vcycle_level on
+// (c->gr, c->gd), c->gd is copied out.  Captured on first use and again when
+// nu1, nu2 or omega change; dropped by everything that changes the data the
+// kernels read or their arguments.
+template <typename T>
+int vcycle_graph(pns_ctx* c, int nu1, int nu2, double omega, const T* r, T* d) {
+  const int64_t n = c->lev[0].g.nst;
+  if (c->vgraph && (c->g_nu1 != nu1 || c->g_nu2 != nu2 || c->g_omega != omega)) c->drop_graph();
+  if (!c->vgraph) {
+    if (!c->cap_stream)
+      PNS_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+    PNS_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipStream_t saved = c->stream;
+    c->stream = c->cap_stream;
+    const hipError_t e = vcycle_level<T>(c, 0, nu1, nu2, omega, (const T*)c->gr, (T*)c->gd);
+    c->stream = saved;
+    hipGraph_t graph = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &graph);
+    PNS_HIP(c, e);
+    PNS_HIP(c, e2);
+    const hipError_t e3 = hipGraphInstantiate(&c->vgraph, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) c->vgraph = nullptr;
+    PNS_HIP(c, e3);
+    c->g_nu1 = nu1;
+    c->g_nu2 = nu2;
+    c->g_omega = omega;
+  }
+  PNS_HIP(c, launch_copy<T>(n, r, (T*)c->gr, c->stream));
+  PNS_HIP(c, hipGraphLaunch(c->vgraph, c->stream));
+  PNS_HIP(c, launch_copy<T>(n, (const T*)c->gd, d, c->stream));
+  return PNS_OK;
+}
+
 // 3D context: hexahedra, the level-0 action only
 int create3d(const pns_mesh* mesh, const pns_discretization* disc, int n_levels, int precision,
              void* stream, pns_ctx** out) {
@@ -346,6 +384,15 @@ int pns_ctx_create(const pns_mesh* mesh, const pns_discretization* disc, int n_l
 
 void pns_ctx_destroy(pns_ctx* ctx) { delete ctx; }
 
+int pns_set_vcycle_graph(pns_ctx* ctx, int enable) {
+  if (!ctx) return PNS_EINVAL;
+  if (enable != 0 && enable != 1) return fail(ctx, PNS_EINVAL, "enable must be 0 or 1");
+  if (enable && ctx->dim == 3) return fail(ctx, PNS_EUNSUPPORTED, "3D contexts have no V-cycle");
+  ctx->graph_mode = enable == 1;
+  if (!enable) ctx->drop_graph();
+  return PNS_OK;
+}
+
 const char* pns_last_error(const pns_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
 int pns_level_sizes(const pns_ctx* ctx, int level, int64_t out[4]) {
@@ -361,6 +408,9 @@ int pns_level_sizes(const pns_ctx* ctx, int level, int64_t out[4]) {
 size_t pns_workspace_bytes(const pns_ctx* ctx) {
   if (!ctx) return 0;
   pns_ctx tmp = *ctx;
+  // the copy measures the layout only; it does not own the graph or its stream
+  tmp.vgraph = nullptr;
+  tmp.cap_stream = nullptr;
   return layout(&tmp, false);
 }
 
@@ -374,6 +424,7 @@ int pns_bind_workspace(pns_ctx* ctx, void* ws, size_t bytes) {
                 "workspace too small: need " + std::to_string(need) + " bytes");
   ctx->ws = (char*)ws;
   ctx->ws_bytes = bytes;
+  ctx->drop_graph();
   layout(ctx, true);
   ctx->has_state = ctx->has_smoother = false;
   return PNS_OK;
@@ -386,6 +437,7 @@ int pns_set_state(pns_ctx* ctx, const pns_model* md, const double* u_k) {
   const int rc = make_model(md, &m, &ctx->err);
   if (rc != PNS_OK) return rc;
   ctx->model = m;
+  ctx->drop_graph();
   const Grid& g0 = ctx->lev[0].g;
   hipStream_t s = ctx->stream;
   PNS_HIP(ctx, hipMemcpyAsync(ctx->uk64, u_k, 2 * g0.nv * 8, hipMemcpyDeviceToDevice, s));
@@ -410,6 +462,7 @@ int pns_set_apply_mode(pns_ctx* ctx, int mode) {
   if (ctx->dim == 3 && mode != PNS_APPLY_RECOMPUTE)
     return fail(ctx, PNS_EUNSUPPORTED, "3D contexts recompute the tangent");
   const bool rebuild = mode == PNS_APPLY_CACHED && ctx->apply_mode != mode && ctx->has_state;
+  if (mode != ctx->apply_mode) ctx->drop_graph();
   ctx->apply_mode = mode;
   if (rebuild) PNS_HIP(ctx, build_tangent_cache(ctx));
   return PNS_OK;
@@ -420,7 +473,10 @@ int pns_set_patch_kind(pns_ctx* ctx, int kind) {
   if (ctx->dim == 3) return fail(ctx, PNS_EUNSUPPORTED, "3D contexts have no smoother");
   if (kind != PNS_PATCH_SURROGATE && kind != PNS_PATCH_EXACT)
     return fail(ctx, PNS_EINVAL, "unknown patch kind");
-  if (kind != ctx->patch_kind) ctx->has_smoother = false;
+  if (kind != ctx->patch_kind) {
+    ctx->has_smoother = false;
+    ctx->drop_graph();
+  }
   ctx->patch_kind = kind;
   return PNS_OK;
 }
@@ -449,6 +505,7 @@ int pns_vanka_setup(pns_ctx* ctx, const uint16_t* node_masks) {
   if (ctx && ctx->dim == 3) return fail(ctx, PNS_EUNSUPPORTED, "3D contexts have no smoother");
   if (!check_ctx(ctx, true, false)) return ctx_code(ctx, true, false);
   ctx->has_smoother = false;
+  ctx->drop_graph();
   return ctx->es == 8 ? vanka_setup_impl<double>(ctx, node_masks)
                       : vanka_setup_impl<float>(ctx, node_masks);
 }
@@ -472,6 +529,9 @@ int pns_vcycle(pns_ctx* ctx, int nu1, int nu2, double omega, const void* r, void
     return fail(ctx, PNS_EINVAL, "bad sweep counts or vectors");
   if (!ctx->has_coarse)
     return fail(ctx, PNS_EUNSUPPORTED, "coarsest level too large for the dense coarse solve");
+  if (ctx->graph_mode)
+    return ctx->es == 8 ? vcycle_graph<double>(ctx, nu1, nu2, omega, (const double*)r, (double*)d)
+                        : vcycle_graph<float>(ctx, nu1, nu2, omega, (const float*)r, (float*)d);
   if (ctx->es == 8)
     PNS_HIP(ctx, vcycle_level<double>(ctx, 0, nu1, nu2, omega, (const double*)r, (double*)d));
   else

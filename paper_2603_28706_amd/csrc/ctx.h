@@ -67,6 +67,22 @@ struct pns_ctx {
   int patch_kind = PNS_PATCH_SURROGATE;  // finest-level patch matrices
   void* tcache = nullptr;  // per-point tangent coefficients of level 0
   void* E3 = nullptr;      // 3D: per-cell results of the action (170 per cell)
+  // V-cycles replayed from a captured HIP graph (pns_set_vcycle_graph)
+  bool graph_mode = false;
+  void* gr = nullptr;  // level-0 right-hand side and correction read / written by the graph
+  void* gd = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t vgraph = nullptr;
+  int g_nu1 = -1, g_nu2 = -1;
+  double g_omega = 0.0;
+  void drop_graph() {
+    if (vgraph) (void)hipGraphExecDestroy(vgraph);
+    vgraph = nullptr;
+  }
+  ~pns_ctx() {
+    drop_graph();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
 };
 
 #define PNS_HIP(ctx, call)                                                                  \

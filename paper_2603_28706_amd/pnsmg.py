@@ -118,6 +118,7 @@ def lib():
         L.pns_vanka_setup.argtypes = [_vp, _vp]
         L.pns_vanka_smooth.argtypes = [_vp, i, i, ctypes.c_double, _vp, _vp]
         L.pns_vcycle.argtypes = [_vp, i, i, ctypes.c_double, _vp, _vp]
+        L.pns_set_vcycle_graph.argtypes = [_vp, i]
         L.pns_level_apply.argtypes = [_vp, i, _vp, _vp]
         L.pns_restrict.argtypes = [_vp, i, _vp, _vp]
         L.pns_prolongate_add.argtypes = [_vp, i, _vp, _vp]
@@ -249,6 +250,9 @@ class Context:
 
     def pns_vcycle(self, nu1, nu2, omega, r, d):
         self._check(lib().pns_vcycle(self.h, nu1, nu2, float(omega), self._vec(r), self._vec(d)))
+
+    def pns_set_vcycle_graph(self, enable):
+        self._check(lib().pns_set_vcycle_graph(self.h, int(enable)))
 
     def pns_level_apply(self, level, x, y):
         self._check(lib().pns_level_apply(self.h, level, self._vec(x, level), self._vec(y, level)))

@@ -98,6 +98,22 @@ def test_3d_context_is_action_only():
     assert L.pns_solve(h, ctypes.byref(model), v, w, None, None, 0,
                        ctypes.byref(info)) == pnsmg.PNS_EUNSUPPORTED
     assert L.pns_cell_apply(h, v, w) == pnsmg.PNS_EWORKSPACE
+    assert L.pns_set_vcycle_graph(h, 1) == pnsmg.PNS_EUNSUPPORTED
+    L.pns_ctx_destroy(h)
+
+
+def test_vcycle_graph_switch_rejects_bad_arguments():
+    L = pnsmg.lib()
+    assert L.pns_set_vcycle_graph(None, 1) == pnsmg.PNS_EINVAL
+    rc, h = _create((8, 8), 2)
+    assert rc == pnsmg.PNS_OK
+    assert L.pns_set_vcycle_graph(h, 2) == pnsmg.PNS_EINVAL
+    assert L.pns_set_vcycle_graph(h, 1) == pnsmg.PNS_OK
+    assert L.pns_set_vcycle_graph(h, 0) == pnsmg.PNS_OK
+    # without a workspace the V-cycle is rejected in either mode
+    assert L.pns_set_vcycle_graph(h, 1) == pnsmg.PNS_OK
+    assert L.pns_vcycle(h, 2, 2, ctypes.c_double(0.1), ctypes.c_void_p(4096),
+                        ctypes.c_void_p(8192)) == pnsmg.PNS_EWORKSPACE
     L.pns_ctx_destroy(h)
 
 
