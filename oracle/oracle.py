@@ -333,14 +333,16 @@ def assemble_velocity_mass(prob: Problem):
     """Velocity mass M_x embedded in the spatial (ns x ns) layout."""
     nb = 3 ** prob.dim
     dofs = local_dofs(prob)
-    rows, cols, vals = [], [], []
+    cs = _cs(prob)
+    Me = np.zeros((prob.num_cells, nb, nb))
     for c in range(prob.num_cells):
-        Mc = element_mass(prob, c)
-        for comp in range(prob.dim):
-            idx = dofs[c, comp * nb:(comp + 1) * nb]
-            rows.append(np.repeat(idx, nb))
-            cols.append(np.tile(idx, nb))
-            vals.append(Mc.ravel())
+        lib().orc_element_mass(cs, int(c), _dp(Me[c]))
+    rows, cols, vals = [], [], []
+    for comp in range(prob.dim):
+        idx = dofs[:, comp * nb:(comp + 1) * nb]          # (cells, nb)
+        rows.append(np.repeat(idx, nb, axis=1).ravel())   # row a repeated for every column b
+        cols.append(np.tile(idx, (1, nb)).ravel())
+        vals.append(Me.reshape(prob.num_cells, nb * nb).ravel())
     return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                          shape=(prob.ns, prob.ns))
 
@@ -430,6 +432,62 @@ def all_patches(prob: Problem, node_masks=None):
             idx.extend(base + ld[c, prob.dim * nb:])
         out.append(np.asarray(idx, dtype=np.int64))
     return out
+
+
+def local_patch_matrix(prob: Problem, uk_blocks, cell: int, node_mask=None, **kw):
+    """R_K A R_K^T of the slab operator J_n = [K_t (x) M_x, 0; 0, 0] +
+    (tau M_t (x) I) diag(J_1..J_{k+1}) (eq. slab-underint-jac) for the patch
+    of one cell (Sec. 6.3), summed from the element matrices of the cells
+    that share an unknown with the patch only, so that single patches of a
+    large mesh can be formed without the global matrix.  uk_blocks: nt
+    velocity states (the surrogate operator passes u_rep for every node).
+    Returns (matrix, space-time index set in the order of cell_patch)."""
+    idx = cell_patch(prob, cell, node_mask)
+    pos = {int(g): k for k, g in enumerate(idx)}
+    _, Mt, Kt, _ = time_matrices(prob.k_time)
+    nb = 3 ** prob.dim
+    nloc = prob.nloc
+    cs = _cs(prob, **kw)
+    # multi-index of the cell, x fastest
+    ci, r = [], cell
+    for k in range(prob.dim):
+        ci.append(r % prob.n[k])
+        r //= prob.n[k]
+    A = np.zeros((idx.size, idx.size))
+    ld = np.zeros(nloc, dtype=np.int32)
+    import itertools
+    for off in itertools.product((-1, 0, 1), repeat=prob.dim):
+        cc = [ci[k] + off[k] for k in range(prob.dim)]
+        if any(c < 0 or c >= prob.n[k] for k, c in enumerate(cc)):
+            continue
+        c, stride = 0, 1
+        for k in range(prob.dim):
+            c += cc[k] * stride
+            stride *= prob.n[k]
+        lib().orc_local_dofs(cs, int(c), ld.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
+        dofs = ld.copy()
+        M = np.zeros((nb, nb))
+        lib().orc_element_mass(cs, int(c), _dp(M))
+        for m in range(prob.nt):
+            uloc = _f64(uk_blocks[m][dofs[:prob.dim * nb]])
+            E = np.zeros((nloc, nloc))
+            lib().orc_element_matrix(cs, int(c), _dp(uloc), _dp(E))
+            rows = [(i, pos.get(m * prob.ns + int(dofs[i]))) for i in range(nloc)]
+            rows = [(i, p) for i, p in rows if p is not None]
+            for i, pi in rows:
+                for j, pj in rows:
+                    A[pi, pj] += prob.tau * Mt[m, m] * E[i, j]
+            for n in range(prob.nt):
+                for comp in range(prob.dim):
+                    for a in range(nb):
+                        pi = pos.get(m * prob.ns + int(dofs[comp * nb + a]))
+                        if pi is None:
+                            continue
+                        for b in range(nb):
+                            pj = pos.get(n * prob.ns + int(dofs[comp * nb + b]))
+                            if pj is not None:
+                                A[pi, pj] += Kt[m, n] * M[a, b]
+    return A, idx
 
 
 def representative_velocity(prob: Problem, uk, t_rep: float = 0.5):
@@ -713,10 +771,10 @@ def assemble_pressure_mass(prob: Problem):
     d = prob.dim
     diag = np.zeros(prob.ns)
     area = float(np.prod(prob.h))
-    for c in range(prob.num_cells):
-        base = prob.nv + (d + 1) * c
-        diag[base] = area
-        diag[base + 1:base + d + 1] = area / 12.0
+    base = prob.nv + (d + 1) * np.arange(prob.num_cells)
+    diag[base] = area
+    for k in range(1, d + 1):
+        diag[base + k] = area / 12.0
     return sp.diags(diag)
 
 

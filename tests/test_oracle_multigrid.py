@@ -195,3 +195,22 @@ def test_coarse_solve_with_pinned_pressure():
     r = H.A[0] @ x
     d = O.coarse_solve(H, r)
     assert np.abs(H.A[0] @ d - r).max() < 1e-10 * np.abs(r).max()
+
+
+@pytest.mark.parametrize("n", [(4, 3), (2, 2, 2)])
+def test_local_patch_matrix_equals_restriction_of_the_assembled_operator(n):
+    """Patches formed from the neighbouring element matrices only are the
+    restriction R_K A R_K^T of the globally assembled slab operator (exact
+    and surrogate states, full and truncated patches)."""
+    prob = O.Problem(n=n, p=1.3, delta=1e-3, lin=O.MODIFIED_NEWTON)
+    uk = inputs.uniform(61, prob.nt * prob.nv)
+    masks = inputs.truncation_masks(n, seed=62)
+    A = O.assemble_slab(prob, O.split_uk(prob, uk))
+    ur = O.representative_velocity(prob, uk)
+    As = O.assemble_surrogate(prob, uk)
+    for cell in range(prob.num_cells):
+        for mask in (None, masks[cell]):
+            for Ag, blocks in ((A, O.split_uk(prob, uk)), (As, [ur] * prob.nt)):
+                AK, idx = O.local_patch_matrix(prob, blocks, cell, mask)
+                ref = Ag.tocsr()[idx][:, idx].toarray()
+                assert np.abs(AK - ref).max() <= 1e-14 * np.abs(ref).max(), (cell, mask)
