@@ -418,10 +418,13 @@ def batched_vanka(n=512, sweeps=20):
     """Finest-level smoother alone at n x n in FP32 with boundary-truncated
     (uneven) patches: patch entries from the surrogate tangent at p = 1.1,
     delta = 1e-5, nu_inf = 1e-4 (state: sin-series, seed 401; masks seed 402).
-    Setup (element matrices + batched patch factorisation) and one additive
-    Vanka step (global defect + all patch solves), for the midpoint-frozen
-    surrogate patches (complex 21x21 time-diagonal factors) and the exact
-    42x42 patches.  Factor GB/s = factor bytes / (step - defect)."""
+    Setup (element matrices + batched patch factorisation + sweep autotuning)
+    and one additive Vanka step (global defect + all patch solves), for the
+    midpoint-frozen surrogate patches (complex 21x21 time-diagonal factors)
+    and the exact 42x42 patches.  Factor GB/s = factor bytes / (step -
+    defect).  The step is timed with the autotuned sweep shape and again with
+    variant 0 (the fixed shape: three complex patches or one real patch per
+    wave, four waves per workgroup)."""
     import numpy as np
     import torch
 
@@ -458,13 +461,28 @@ def batched_vanka(n=512, sweeps=20):
         torch.cuda.synchronize()
         t_step = ea.elapsed_time(eb) * 1e-3 / sweeps
         t_def = eb.elapsed_time(ec) * 1e-3 / sweeps
+        # the autotuned sweep shape against variant 0 (the fixed shape it replaces)
+        tuned = ctx.pns_sweep_variant(0)
+        times = [ctx.pns_sweep_variant_time(0, v) for v in range(tuned["count"])]
+        ctx.pns_set_sweep_variant(0, 0)
+        ctx.pns_vanka_smooth(0, 1, OMEGA, r, d)
+        ea.record(stream)
+        for _ in range(sweeps):
+            ctx.pns_vanka_smooth(0, 1, OMEGA, r, d)
+        eb.record(stream)
+        torch.cuda.synchronize()
+        t_step0 = ea.elapsed_time(eb) * 1e-3 / sweeps
         fbytes = n * n * vals * 4
         out[name] = dict(setup_s=t_setup, step_ms=t_step * 1e3, defect_ms=t_def * 1e3,
-                         factor_mb=fbytes / 1e6, factor_gbs=fbytes / max(t_step - t_def, 1e-9) / 1e9)
+                         factor_mb=fbytes / 1e6, factor_gbs=fbytes / max(t_step - t_def, 1e-9) / 1e9,
+                         step_ms_variant0=t_step0 * 1e3,
+                         autotuned_variant=tuned["variant"], waves_per_workgroup=tuned["waves"],
+                         loads_in_flight=tuned["unroll"], rows_per_lane=tuned["rows"],
+                         variant_step_ms=[round(t, 4) for t in times])
         print(f"[bench] batched Vanka {n}x{n} {name}: setup {t_setup:.3f} s, step "
               f"{t_step * 1e3:.3f} ms (defect {t_def * 1e3:.3f} ms), factors "
-              f"{fbytes / 1e6:.0f} MB at {out[name]['factor_gbs']:.0f} GB/s", file=sys.stderr,
-              flush=True)
+              f"{fbytes / 1e6:.0f} MB at {out[name]['factor_gbs']:.0f} GB/s; autotuned {tuned}, "
+              f"variant 0 step {t_step0 * 1e3:.3f} ms", file=sys.stderr, flush=True)
         del ctx
         torch.cuda.empty_cache()
     return out
@@ -563,7 +581,8 @@ def main():
             "workload": (f"{args.vanka_n}x{args.vanka_n} finest-level additive Vanka, FP32, "
                          f"boundary-truncated patches (30-42 unknowns), surrogate tangent "
                          f"p=1.1 delta=1e-5"),
-            **{k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in bv.items()}}
+            **{k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+               for k, v in bv.items()}}
     if args.serve_requests and not args.apply_only:
         sv = serve_latency(args.serve_requests)
         line["serving"] = {

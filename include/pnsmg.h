@@ -195,6 +195,26 @@ int pns_vanka_setup(pns_ctx* ctx, const uint16_t* node_masks);
 int pns_vanka_smooth(pns_ctx* ctx, int level, int n_sweeps, double omega, const void* r_dev,
                      void* d_dev);
 
+/* Tile shapes of the batched patch sweeps (Sec. 6.3 additive Vanka step),
+ * chosen on the device by an autotuner.  Each patch form has several kernel
+ * variants that compute
+ * the same additive step with different workgroup sizes (waves per
+ * workgroup), column loads in flight and rows per lane; pns_vanka_setup runs
+ * every variant of every level once on zero vectors, times three further
+ * runs with events on the context stream and keeps the fastest.  Variants
+ * differ only in time and in the summation order inside a patch.
+ *   pns_sweep_variant: out = {chosen variant, number of variants of the
+ *     level's form, waves per workgroup, column loads in flight, rows per
+ *     lane};
+ *   pns_sweep_variant_time: the autotuner's mean time (ms) of one step of
+ *     `variant` on `level` (0 before the first setup);
+ *   pns_set_sweep_variant: use `variant` on `level` until the next
+ *     pns_vanka_setup (drops a captured V-cycle graph).
+ * PNS_EINVAL for a bad level or variant and on 3D contexts. */
+int pns_sweep_variant(const pns_ctx* ctx, int level, int out[5]);
+int pns_sweep_variant_time(const pns_ctx* ctx, int level, int variant, double* ms);
+int pns_set_sweep_variant(pns_ctx* ctx, int level, int variant);
+
 /* d = V(r): one V-cycle over all levels (nu1 pre- and nu2 post-smoothing steps
  * from d = 0, restriction P^T, coarsest dense solve, prolongation).
  * PNS_EUNSUPPORTED if the coarsest level exceeds the dense-solve limit. */

@@ -133,6 +133,11 @@ hipError_t build_tangent_cache(pns_ctx* c) {
                                      c->stream);
 }
 
+// level l holds complex 21x21 time-diagonal patch inverses (else real 42x42)
+bool complex_patches(const pns_ctx* c, int l) {
+  return l == 0 && c->patch_kind == PNS_PATCH_SURROGATE;
+}
+
 template <typename T>
 hipError_t smooth(pns_ctx* c, int l, int nsweeps, double omega, const T* r, T* d, bool d_is_zero) {
   Level& L = c->lev[l];
@@ -143,9 +148,11 @@ hipError_t smooth(pns_ctx* c, int l, int nsweeps, double omega, const T* r, T* d
       if (e != hipSuccess) return e;
       res = (const T*)L.res;
     }
-    hipError_t e = (l == 0 && c->patch_kind == PNS_PATCH_SURROGATE)
-                       ? launch_patch_sweep_c<T>(L.g, (const T*)L.inv, res, d, omega, c->stream)
-                       : launch_patch_sweep<T>(L.g, (const T*)L.inv, res, d, omega, c->stream);
+    hipError_t e = complex_patches(c, l)
+                       ? launch_patch_sweep_c<T>(L.g, (const T*)L.inv, res, d, omega,
+                                                 c->sweep_var[l], c->stream)
+                       : launch_patch_sweep<T>(L.g, (const T*)L.inv, res, d, omega,
+                                               c->sweep_var[l], c->stream);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -172,6 +179,58 @@ hipError_t vcycle_level(pns_ctx* c, int l, int nu1, int nu2, double omega, const
     return e;
   if ((e = launch_prolong_add<T>(L.g, C.g, (const T*)C.d, d, c->stream)) != hipSuccess) return e;
   return smooth<T>(c, l, nu2, omega, r, d, false);
+}
+
+// Autotuner of the patch sweeps: on every level, each variant of that level's
+// patch form runs one additive step (4 colour launches) on zero vectors, once
+// to warm up and three times timed with events on the context stream; the
+// fastest is kept.  The variants compute the same step, so the choice changes
+// the time and the summation order within a patch only.
+template <typename T>
+int autotune_sweeps(pns_ctx* c) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  PNS_HIP(c, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(c, PNS_EHIP, "hipEventCreate failed");
+  }
+  int rc = PNS_OK;
+  for (int l = 0; l < c->nlev && rc == PNS_OK; ++l) {
+    Level& L = c->lev[l];
+    const bool cx = complex_patches(c, l);
+    const int nv = sweep_variant_count(cx);
+    T* res = (T*)L.res;
+    T* d = l == 0 ? (T*)c->gd : (T*)L.d;
+    float best = 0.0f;
+    if (launch_fill<T>(L.g.nst, (T)0, res, c->stream) != hipSuccess ||
+        launch_fill<T>(L.g.nst, (T)0, d, c->stream) != hipSuccess) {
+      rc = fail(c, PNS_EHIP, "fill failed in the sweep autotuner");
+      break;
+    }
+    for (int v = 0; v < nv && rc == PNS_OK; ++v) {
+      auto run = [&]() {
+        return cx ? launch_patch_sweep_c<T>(L.g, (const T*)L.inv, res, d, 1.0, v, c->stream)
+                  : launch_patch_sweep<T>(L.g, (const T*)L.inv, res, d, 1.0, v, c->stream);
+      };
+      float ms = 0.0f;
+      if (run() != hipSuccess || hipEventRecord(e0, c->stream) != hipSuccess ||
+          run() != hipSuccess || run() != hipSuccess || run() != hipSuccess ||
+          hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        rc = fail(c, PNS_EHIP, "sweep autotuner launch failed");
+        break;
+      }
+      ms /= 3.0f;
+      c->sweep_ms[l][v] = ms;
+      if (v == 0 || ms < best) {
+        best = ms;
+        c->sweep_var[l] = v;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
 }
 
 template <typename T>
@@ -218,6 +277,8 @@ int vanka_setup_impl(pns_ctx* c, const uint16_t* masks) {
     PNS_HIP(c, hipMemcpyAsync(&st, c->status, sizeof(int), hipMemcpyDeviceToHost, s));
     PNS_HIP(c, hipStreamSynchronize(s));
     if (st & 1) return fail(c, PNS_ESINGULAR, "a patch matrix has a zero pivot");
+    const int rc = autotune_sweeps<T>(c);
+    if (rc != PNS_OK) return rc;
     c->has_smoother = true;
     return PNS_OK;
   }
@@ -235,6 +296,8 @@ int vanka_setup_impl(pns_ctx* c, const uint16_t* masks) {
   PNS_HIP(c, hipStreamSynchronize(s));
   if (st & 1) return fail(c, PNS_ESINGULAR, "a patch matrix has a zero pivot");
   if (st & 2) return fail(c, PNS_ESINGULAR, "the coarsest matrix has a zero pivot");
+  const int rc = autotune_sweeps<T>(c);
+  if (rc != PNS_OK) return rc;
   c->has_smoother = true;
   return PNS_OK;
 }
@@ -383,6 +446,34 @@ int pns_ctx_create(const pns_mesh* mesh, const pns_discretization* disc, int n_l
 }
 
 void pns_ctx_destroy(pns_ctx* ctx) { delete ctx; }
+
+int pns_sweep_variant(const pns_ctx* ctx, int level, int out[5]) {
+  if (!ctx || !out || level < 0 || level >= ctx->nlev || ctx->dim == 3) return PNS_EINVAL;
+  const bool cx = complex_patches(ctx, level);
+  out[0] = ctx->sweep_var[level];
+  out[1] = sweep_variant_count(cx);
+  sweep_variant_shape(cx, out[0], out + 2);
+  return PNS_OK;
+}
+
+int pns_sweep_variant_time(const pns_ctx* ctx, int level, int variant, double* ms) {
+  if (!ctx || !ms || level < 0 || level >= ctx->nlev || ctx->dim == 3) return PNS_EINVAL;
+  if (variant < 0 || variant >= sweep_variant_count(complex_patches(ctx, level)))
+    return PNS_EINVAL;
+  *ms = ctx->sweep_ms[level][variant];
+  return PNS_OK;
+}
+
+int pns_set_sweep_variant(pns_ctx* ctx, int level, int variant) {
+  if (!ctx) return PNS_EINVAL;
+  if (level < 0 || level >= ctx->nlev || ctx->dim == 3)
+    return fail(ctx, PNS_EINVAL, "bad level");
+  if (variant < 0 || variant >= sweep_variant_count(complex_patches(ctx, level)))
+    return fail(ctx, PNS_EINVAL, "bad sweep variant");
+  ctx->sweep_var[level] = variant;
+  ctx->drop_graph();
+  return PNS_OK;
+}
 
 int pns_set_vcycle_graph(pns_ctx* ctx, int enable) {
   if (!ctx) return PNS_EINVAL;

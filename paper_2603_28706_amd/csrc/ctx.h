@@ -67,6 +67,10 @@ struct pns_ctx {
   int patch_kind = PNS_PATCH_SURROGATE;  // finest-level patch matrices
   void* tcache = nullptr;  // per-point tangent coefficients of level 0
   void* E3 = nullptr;      // 3D: per-cell results of the action (170 per cell)
+  // patch-sweep variant per level (chosen by timing at pns_vanka_setup) and the
+  // measured time of every variant of that level's form
+  int sweep_var[16] = {};
+  float sweep_ms[16][16] = {};
   // V-cycles replayed from a captured HIP graph (pns_set_vcycle_graph)
   bool graph_mode = false;
   void* gr = nullptr;  // level-0 right-hand side and correction read / written by the graph

@@ -157,12 +157,18 @@ hipError_t coarse_invert(int64_t n, double* A, double* work, int* piv, int* stat
 template <typename T>
 hipError_t launch_ebe_apply(const Grid& g, const T* E, const T* x, const T* b, T* y, int mode,
                             hipStream_t s);
+// additive Vanka step with sweep variant `variant` (real 42x42 or complex 21x21
+// patches); variants differ in workgroup size, loads in flight and rows per
+// lane, not in what they compute
 template <typename T>
 hipError_t launch_patch_sweep(const Grid& g, const T* inv, const T* res, T* d, double omega,
-                              hipStream_t s);
+                              int variant, hipStream_t s);
 template <typename T>
 hipError_t launch_patch_sweep_c(const Grid& g, const T* inv, const T* res, T* d, double omega,
-                                hipStream_t s);
+                                int variant, hipStream_t s);
+int sweep_variant_count(bool complex_form);
+// {waves per workgroup, column loads in flight, rows per lane}
+void sweep_variant_shape(bool complex_form, int variant, int out[3]);
 template <typename T>
 hipError_t launch_copy(int64_t n, const T* x, T* y, hipStream_t s);
 template <typename T>

@@ -6,8 +6,10 @@
 // * additive Vanka update d += omega sum_K R_K^T A_K^{-1} R_K res,
 //   eq. (stmg-vanka-update): the stored patch inverses streamed column by
 //   column (level 0: complex 21x21 time-diagonal form, three patches per wave;
-//   coarse levels: real 42x42, one patch per wave), four colour launches so
-//   that patches updating d at the same time share no unknown;
+//   real 42x42: one patch per wave, or three with two rows per lane), four
+//   colour launches so that patches updating d at the same time share no
+//   unknown; each form comes in variants of workgroup size and loads in
+//   flight, among which the smoother setup picks the fastest on the device;
 // * restriction P^T and prolongation P of the nested Q2 / P1disc spaces;
 // * dense coarsest solve with the stored inverse.
 #include <type_traits>
@@ -59,15 +61,17 @@ __global__ __launch_bounds__(256) void ebe_color_kernel(Grid g, const T* __restr
   y[gi] += sign * acc;
 }
 
-// one wave per patch of the colour class (px, py)
-template <typename T>
-__global__ __launch_bounds__(256) void patch_sweep_kernel(Grid g, const T* __restrict__ inv,
-                                                          const T* __restrict__ res,
-                                                          T* __restrict__ d, T omega, int px,
-                                                          int py, int ncx, int ncy) {
-  __shared__ T rhs[4][kNst];
+// Real 42x42 patches, one wave per patch of the colour class (px, py), lane r
+// < 42 forms row r; WAVES patches per workgroup, UNROLL column loads in flight.
+template <typename T, int WAVES, int UNROLL>
+__global__ __launch_bounds__(64 * WAVES) void patch_sweep_kernel(Grid g, const T* __restrict__ inv,
+                                                                 const T* __restrict__ res,
+                                                                 T* __restrict__ d, T omega,
+                                                                 int px, int py, int ncx,
+                                                                 int ncy) {
+  __shared__ T rhs[WAVES][kNst];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t pid = (int64_t)blockIdx.x * 4 + w;
+  const int64_t pid = (int64_t)blockIdx.x * WAVES + w;
   const bool active = pid < (int64_t)ncx * ncy;
   int cx = 0, cy = 0;
   int64_t gi = 0;
@@ -83,22 +87,64 @@ __global__ __launch_bounds__(256) void patch_sweep_kernel(Grid g, const T* __res
   if (!active || lane >= kNst) return;
   const T* A = inv + ((int64_t)cy * g.nx + cx) * (kNst * kNst);
   T acc = 0;
-#pragma unroll 6
+#pragma unroll UNROLL
   for (int j = 0; j < kNst; ++j) acc += A[j * kNst + lane] * rhs[w][j];
   d[gi] += omega * acc;
 }
 
+// Real 42x42 patches, three patches per wave, lane 21 p + i forms rows 2i and
+// 2i + 1 of patch p from paired loads (63 of 64 lanes busy); WAVES waves per
+// workgroup, UNROLL column loads in flight.
+template <typename T, int WAVES, int UNROLL>
+__global__ __launch_bounds__(64 * WAVES) void patch_sweep2_kernel(Grid g, const T* __restrict__ inv,
+                                                                  const T* __restrict__ res,
+                                                                  T* __restrict__ d, T omega,
+                                                                  int px, int py, int ncx,
+                                                                  int ncy) {
+  using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
+  __shared__ T rhs[WAVES][3][kNst];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int p = lane / 21, i = lane % 21;
+  const int64_t pid = ((int64_t)blockIdx.x * WAVES + w) * 3 + p;
+  const bool active = lane < 63 && pid < (int64_t)ncx * ncy;
+  int cx = 0, cy = 0;
+  int64_t g0 = 0, g1 = 0;
+  if (active) {
+    cx = px + 2 * (int)(pid % ncx);
+    cy = py + 2 * (int)(pid / ncx);
+    g0 = gidx(g, cx, cy, 2 * i);
+    g1 = gidx(g, cx, cy, 2 * i + 1);
+    rhs[w][p][2 * i] = res[g0];
+    rhs[w][p][2 * i + 1] = res[g1];
+  }
+  __syncthreads();
+  if (!active) return;
+  // column j starts at an even offset, so the pair (2i, 2i+1) is aligned
+  const T2* A = reinterpret_cast<const T2*>(inv + ((int64_t)cy * g.nx + cx) * (kNst * kNst));
+  T a0 = 0, a1 = 0;
+#pragma unroll UNROLL
+  for (int j = 0; j < kNst; ++j) {
+    const T2 c = A[j * (kNst / 2) + i];
+    const T r = rhs[w][p][j];
+    a0 += c.x * r;
+    a1 += c.y * r;
+  }
+  d[g0] += omega * a0;
+  d[g1] += omega * a1;
+}
+
 // level-0 patches in time-diagonal form (complex 21x21 inverse): three
 // patches per wave, lane 21 p + i handles spatial unknown i of patch p
-template <typename T>
-__global__ __launch_bounds__(256) void patch_sweep_c_kernel(Grid g, const T* __restrict__ inv,
-                                                            const T* __restrict__ res,
-                                                            T* __restrict__ d, T omega, int px,
-                                                            int py, int ncx, int ncy) {
-  __shared__ T zs[4][3][2][kNs];
+template <typename T, int WAVES, int UNROLL>
+__global__ __launch_bounds__(64 * WAVES) void patch_sweep_c_kernel(Grid g, const T* __restrict__ inv,
+                                                                   const T* __restrict__ res,
+                                                                   T* __restrict__ d, T omega,
+                                                                   int px, int py, int ncx,
+                                                                   int ncy) {
+  __shared__ T zs[WAVES][3][2][kNs];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int p = lane / kNs, i = lane % kNs;
-  const int64_t pid = ((int64_t)blockIdx.x * 4 + w) * 3 + p;
+  const int64_t pid = ((int64_t)blockIdx.x * WAVES + w) * 3 + p;
   const bool active = lane < 3 * kNs && pid < (int64_t)ncx * ncy;
   int cx = 0, cy = 0;
   int64_t g0 = 0, g1 = 0;
@@ -115,7 +161,7 @@ __global__ __launch_bounds__(256) void patch_sweep_c_kernel(Grid g, const T* __r
   if (!active) return;
   const T* C = inv + ((int64_t)cy * g.nx + cx) * (2 * kNs * kNs);
   T yr = 0, yi = 0;
-#pragma unroll 7
+#pragma unroll UNROLL
   for (int j = 0; j < kNs; ++j) {
     const T cr = C[2 * (j * kNs + i)], ci = C[2 * (j * kNs + i) + 1];
     const T zr = zs[w][p][0][j], zi = zs[w][p][1][j];
@@ -310,37 +356,91 @@ hipError_t launch_ebe_apply(const Grid& g, const T* E, const T* x, const T* b, T
 }
 
 template <typename T>
-hipError_t launch_patch_sweep_c(const Grid& g, const T* inv, const T* res, T* d, double omega,
-                                hipStream_t s) {
-  for (int c = 0; c < 4; ++c) {
-    const int px = c & 1, py = c >> 1;
-    const int ncx = (g.nx - px + 1) / 2, ncy = (g.ny - py + 1) / 2;
-    const int64_t np = (int64_t)ncx * ncy;
-    if (np == 0) continue;
-    hipLaunchKernelGGL(patch_sweep_c_kernel<T>, dim3(nblk(np, 12)), dim3(256), 0, s, g, inv, res,
-                       d, (T)omega, px, py, ncx, ncy);
-  }
-  return hipGetLastError();
-}
-
-template <typename T>
 hipError_t launch_copy(int64_t n, const T* x, T* y, hipStream_t s) {
   hipLaunchKernelGGL(copy_kernel<T>, dim3(nblk(n, 256)), dim3(256), 0, s, n, x, y);
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_patch_sweep(const Grid& g, const T* inv, const T* res, T* d, double omega,
-                              hipStream_t s) {
+namespace {
+
+// The four colour launches of one additive step with one kernel variant;
+// PPB patches per workgroup.
+template <typename T, typename K>
+hipError_t sweep_colours(K kern, int threads, int ppb, const Grid& g, const T* inv, const T* res,
+                         T* d, double omega, hipStream_t s) {
   for (int c = 0; c < 4; ++c) {
     const int px = c & 1, py = c >> 1;
     const int ncx = (g.nx - px + 1) / 2, ncy = (g.ny - py + 1) / 2;
     const int64_t np = (int64_t)ncx * ncy;
     if (np == 0) continue;
-    hipLaunchKernelGGL(patch_sweep_kernel<T>, dim3(nblk(np, 4)), dim3(256), 0, s, g, inv, res, d,
-                       (T)omega, px, py, ncx, ncy);
+    hipLaunchKernelGGL(kern, dim3(nblk(np, ppb)), dim3(threads), 0, s, g, inv, res, d, (T)omega,
+                       px, py, ncx, ncy);
   }
   return hipGetLastError();
+}
+
+template <typename T, int W, int U>
+hipError_t sweep_r1(const Grid& g, const T* inv, const T* res, T* d, double omega, hipStream_t s) {
+  return sweep_colours<T>(patch_sweep_kernel<T, W, U>, 64 * W, W, g, inv, res, d, omega, s);
+}
+template <typename T, int W, int U>
+hipError_t sweep_r2(const Grid& g, const T* inv, const T* res, T* d, double omega, hipStream_t s) {
+  return sweep_colours<T>(patch_sweep2_kernel<T, W, U>, 64 * W, 3 * W, g, inv, res, d, omega, s);
+}
+template <typename T, int W, int U>
+hipError_t sweep_c(const Grid& g, const T* inv, const T* res, T* d, double omega, hipStream_t s) {
+  return sweep_colours<T>(patch_sweep_c_kernel<T, W, U>, 64 * W, 3 * W, g, inv, res, d, omega, s);
+}
+
+template <typename T>
+using SweepFn = hipError_t (*)(const Grid&, const T*, const T*, T*, double, hipStream_t);
+
+// variant tables: {launcher, waves per workgroup, column loads in flight, rows per lane}
+template <typename T>
+struct SweepVariant {
+  SweepFn<T> fn;
+  int waves, unroll, rows;
+};
+
+template <typename T>
+const SweepVariant<T>* real_variants() {
+  static const SweepVariant<T> v[] = {
+      {sweep_r1<T, 4, 6>, 4, 6, 1},   {sweep_r1<T, 1, 6>, 1, 6, 1},   {sweep_r1<T, 2, 6>, 2, 6, 1},
+      {sweep_r1<T, 1, 42>, 1, 42, 1}, {sweep_r1<T, 2, 42>, 2, 42, 1}, {sweep_r1<T, 4, 42>, 4, 42, 1},
+      {sweep_r2<T, 1, 7>, 1, 7, 2},   {sweep_r2<T, 2, 7>, 2, 7, 2},   {sweep_r2<T, 4, 7>, 4, 7, 2},
+      {sweep_r2<T, 1, 42>, 1, 42, 2}, {sweep_r2<T, 2, 42>, 2, 42, 2}, {sweep_r2<T, 4, 42>, 4, 42, 2}};
+  return v;
+}
+template <typename T>
+const SweepVariant<T>* complex_variants() {
+  static const SweepVariant<T> v[] = {
+      {sweep_c<T, 4, 7>, 4, 7, 1},  {sweep_c<T, 1, 7>, 1, 7, 1},  {sweep_c<T, 2, 7>, 2, 7, 1},
+      {sweep_c<T, 1, 21>, 1, 21, 1}, {sweep_c<T, 2, 21>, 2, 21, 1}, {sweep_c<T, 4, 21>, 4, 21, 1}};
+  return v;
+}
+
+}  // namespace
+
+int sweep_variant_count(bool complex_form) { return complex_form ? 6 : 12; }
+
+void sweep_variant_shape(bool complex_form, int v, int out[3]) {
+  const SweepVariant<double>& e = complex_form ? complex_variants<double>()[v]
+                                               : real_variants<double>()[v];
+  out[0] = e.waves;
+  out[1] = e.unroll;
+  out[2] = e.rows;
+}
+
+template <typename T>
+hipError_t launch_patch_sweep(const Grid& g, const T* inv, const T* res, T* d, double omega,
+                              int variant, hipStream_t s) {
+  return real_variants<T>()[variant].fn(g, inv, res, d, omega, s);
+}
+
+template <typename T>
+hipError_t launch_patch_sweep_c(const Grid& g, const T* inv, const T* res, T* d, double omega,
+                                int variant, hipStream_t s) {
+  return complex_variants<T>()[variant].fn(g, inv, res, d, omega, s);
 }
 
 template <typename T>
@@ -377,7 +477,7 @@ hipError_t launch_fill(int64_t n, T v, T* y, hipStream_t s) {
 #define PNS_INST(T)                                                                              \
   template hipError_t launch_ebe_apply<T>(const Grid&, const T*, const T*, const T*, T*, int,   \
                                           hipStream_t);                                          \
-  template hipError_t launch_patch_sweep<T>(const Grid&, const T*, const T*, T*, double,        \
+  template hipError_t launch_patch_sweep<T>(const Grid&, const T*, const T*, T*, double, int,   \
                                             hipStream_t);                                        \
   template hipError_t launch_restrict<T>(const Grid&, const Grid&, const T*, T*, hipStream_t);  \
   template hipError_t launch_prolong_add<T>(const Grid&, const Grid&, const T*, T*,             \
@@ -385,7 +485,7 @@ hipError_t launch_fill(int64_t n, T v, T* y, hipStream_t s) {
   template hipError_t launch_dense_gemv<T>(int64_t, const double*, const T*, T*, const int64_t*, \
                                            int, hipStream_t);                                    \
   template hipError_t launch_fill<T>(int64_t, T, T*, hipStream_t);                               \
-  template hipError_t launch_patch_sweep_c<T>(const Grid&, const T*, const T*, T*, double,      \
+  template hipError_t launch_patch_sweep_c<T>(const Grid&, const T*, const T*, T*, double, int, \
                                               hipStream_t);                                      \
   template hipError_t launch_copy<T>(int64_t, const T*, T*, hipStream_t);
 PNS_INST(double)

@@ -119,6 +119,9 @@ def lib():
         L.pns_vanka_smooth.argtypes = [_vp, i, i, ctypes.c_double, _vp, _vp]
         L.pns_vcycle.argtypes = [_vp, i, i, ctypes.c_double, _vp, _vp]
         L.pns_set_vcycle_graph.argtypes = [_vp, i]
+        L.pns_sweep_variant.argtypes = [_vp, i, pp(ctypes.c_int)]
+        L.pns_sweep_variant_time.argtypes = [_vp, i, i, pp(ctypes.c_double)]
+        L.pns_set_sweep_variant.argtypes = [_vp, i, i]
         L.pns_level_apply.argtypes = [_vp, i, _vp, _vp]
         L.pns_restrict.argtypes = [_vp, i, _vp, _vp]
         L.pns_prolongate_add.argtypes = [_vp, i, _vp, _vp]
@@ -250,6 +253,19 @@ class Context:
 
     def pns_vcycle(self, nu1, nu2, omega, r, d):
         self._check(lib().pns_vcycle(self.h, nu1, nu2, float(omega), self._vec(r), self._vec(d)))
+
+    def pns_sweep_variant(self, level=0):
+        out = (ctypes.c_int * 5)()
+        self._check(lib().pns_sweep_variant(self.h, level, out))
+        return dict(variant=out[0], count=out[1], waves=out[2], unroll=out[3], rows=out[4])
+
+    def pns_sweep_variant_time(self, level, variant):
+        ms = ctypes.c_double()
+        self._check(lib().pns_sweep_variant_time(self.h, level, variant, ctypes.byref(ms)))
+        return ms.value
+
+    def pns_set_sweep_variant(self, level, variant):
+        self._check(lib().pns_set_sweep_variant(self.h, level, variant))
 
     def pns_set_vcycle_graph(self, enable):
         self._check(lib().pns_set_vcycle_graph(self.h, int(enable)))

@@ -102,6 +102,27 @@ def test_3d_context_is_action_only():
     L.pns_ctx_destroy(h)
 
 
+def test_sweep_variant_entry_points_reject_bad_arguments():
+    L = pnsmg.lib()
+    rc, h = _create((8, 8), 2)
+    assert rc == pnsmg.PNS_OK
+    out = (ctypes.c_int * 5)()
+    assert L.pns_sweep_variant(h, 0, out) == pnsmg.PNS_OK
+    assert out[0] == 0 and out[1] == 6            # complex level-0 patches: 6 variants
+    assert L.pns_sweep_variant(h, 1, out) == pnsmg.PNS_OK and out[1] == 12
+    assert L.pns_sweep_variant(h, 2, out) == pnsmg.PNS_EINVAL
+    assert L.pns_set_sweep_variant(h, 0, 6) == pnsmg.PNS_EINVAL
+    assert L.pns_set_sweep_variant(h, 1, 11) == pnsmg.PNS_OK
+    assert L.pns_set_sweep_variant(h, -1, 0) == pnsmg.PNS_EINVAL
+    ms = ctypes.c_double(-1.0)
+    assert L.pns_sweep_variant_time(h, 1, 3, ctypes.byref(ms)) == pnsmg.PNS_OK and ms.value == 0.0
+    assert L.pns_sweep_variant_time(h, 1, 12, ctypes.byref(ms)) == pnsmg.PNS_EINVAL
+    L.pns_ctx_destroy(h)
+    rc, h = _create((2, 2, 2))
+    assert L.pns_sweep_variant(h, 0, out) == pnsmg.PNS_EINVAL
+    L.pns_ctx_destroy(h)
+
+
 def test_vcycle_graph_switch_rejects_bad_arguments():
     L = pnsmg.lib()
     assert L.pns_set_vcycle_graph(None, 1) == pnsmg.PNS_EINVAL
