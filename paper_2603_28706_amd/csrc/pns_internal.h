@@ -78,6 +78,20 @@ inline Grid make_grid(int nx, int ny, double lx, double ly) {
   return g;
 }
 
+// Storage position of the patch inverse of cell (cx, cy): colour-major (colour
+// = parity class of (cx, cy), in the order (0,0), (1,0), (0,1), (1,1)), within a
+// colour the cells of that class row by row, so that each of the four colour
+// passes of a sweep streams one contiguous block of inverses.
+__host__ __device__ inline int64_t patch_slot(const Grid& g, int cx, int cy) {
+  const int px = cx & 1, py = cy & 1, c = px + 2 * py;
+  const int64_t ncx0 = (g.nx + 1) / 2, ncx1 = g.nx / 2, ncy0 = (g.ny + 1) / 2;
+  int64_t off = 0;
+  if (c >= 1) off += ncx0 * ncy0;
+  if (c >= 2) off += ncx1 * ncy0;
+  if (c >= 3) off += ncx0 * (g.ny / 2);
+  return off + (int64_t)(cy >> 1) * (px ? ncx1 : ncx0) + (cx >> 1);
+}
+
 // 3D box of hexahedra (x fastest); nodes (2nx+1)(2ny+1)(2nz+1), P1disc pressure
 // with 4 coefficients per cell
 struct Grid3 {

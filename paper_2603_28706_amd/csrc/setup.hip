@@ -321,7 +321,7 @@ __global__ __launch_bounds__(64) void patch_kernel(Grid g, Entry entry,
   }
   if (singular && t == 0) atomicOr(status, 1);
   // store the inverse column-major, dropped rows/columns zeroed
-  T* out = inv + K * (kNst * kNst);
+  T* out = inv + patch_slot(g, cx, cy) * (kNst * kNst);
   for (int e = t; e < kNst * kNst; e += 64) {
     const int c = e / kNst, r = e % kNst;
     const bool z = dropped(mask, r) || dropped(mask, c);
@@ -432,7 +432,7 @@ __global__ __launch_bounds__(64) void patch_complex_kernel(Grid g, double tau,
     __syncthreads();
   }
   if (singular && t == 0) atomicOr(status, 1);
-  T* out = inv + K * (2 * kNs * kNs);
+  T* out = inv + patch_slot(g, cx, cy) * (2 * kNs * kNs);
   for (int e = t; e < kNs * kNs; e += 64) {
     const int c = e / kNs, r = e % kNs;
     const bool z = dropped(mask, r) || dropped(mask, c);

@@ -85,7 +85,7 @@ __global__ __launch_bounds__(64 * WAVES) void patch_sweep_kernel(Grid g, const T
   }
   __syncthreads();
   if (!active || lane >= kNst) return;
-  const T* A = inv + ((int64_t)cy * g.nx + cx) * (kNst * kNst);
+  const T* A = inv + patch_slot(g, cx, cy) * (kNst * kNst);
   T acc = 0;
 #pragma unroll UNROLL
   for (int j = 0; j < kNst; ++j) acc += A[j * kNst + lane] * rhs[w][j];
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(64 * WAVES) void patch_sweep2_kernel(Grid g, const 
   __syncthreads();
   if (!active) return;
   // column j starts at an even offset, so the pair (2i, 2i+1) is aligned
-  const T2* A = reinterpret_cast<const T2*>(inv + ((int64_t)cy * g.nx + cx) * (kNst * kNst));
+  const T2* A = reinterpret_cast<const T2*>(inv + patch_slot(g, cx, cy) * (kNst * kNst));
   T a0 = 0, a1 = 0;
 #pragma unroll UNROLL
   for (int j = 0; j < kNst; ++j) {
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(64 * WAVES) void patch_sweep_c_kernel(Grid g, const
   }
   __syncthreads();
   if (!active) return;
-  const T* C = inv + ((int64_t)cy * g.nx + cx) * (2 * kNs * kNs);
+  const T* C = inv + patch_slot(g, cx, cy) * (2 * kNs * kNs);
   T yr = 0, yi = 0;
 #pragma unroll UNROLL
   for (int j = 0; j < kNs; ++j) {
