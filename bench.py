@@ -23,7 +23,7 @@ server's latencies, each as a field of its own in the JSON line.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256]
        [--levels 4] [--no-cpu] [--apply-only] [--lin 2] [--calib-copy]
-       [--apply3d-n 32] [--solve-n 256] [--vanka-n 512] [--serve-requests 48]
+       [--apply3d-n 32] [--solve-n 256] [--vanka-n 512] [--serve-requests 256]
 """
 from __future__ import annotations
 
@@ -361,7 +361,7 @@ def solve_latency(n, seeds, rtol=1e-8):
     return out
 
 
-def serve_latency(n_req=48, rate=20.0, slots=4, seed=501):
+def serve_latency(n_req=256, rate=20.0, slots=4, seed=501):
     """Poisson stream of independent slab-solve requests through the native
     request server: meshes from {32^2, 64^2, 128^2, 256^2}, p ~ U[1.6, 1.9],
     delta ~ logU[1e-3, 1e-1], nu_inf ~ logU[1e-4, 1e-2], nu = 0.1, left traces
@@ -501,7 +501,7 @@ def main():
                     help="mesh of the slab-solve latency measurement (0: skip)")
     ap.add_argument("--vanka-n", type=int, default=512,
                     help="mesh of the batched-Vanka measurement (0: skip)")
-    ap.add_argument("--serve-requests", type=int, default=48,
+    ap.add_argument("--serve-requests", type=int, default=256,
                     help="requests of the serving measurement (0: skip)")
     ap.add_argument("--apply3d-n", type=int, default=32,
                     help="mesh of the 3D action measurement, n^3 hexahedra (0: skip)")
