@@ -315,6 +315,22 @@ int pns_solve(pns_ctx* ctx, const pns_model* model, const double* v_prev_dev, do
               const pns_solve_params* prm, void* work_dev, size_t work_bytes,
               pns_solve_info* info);
 
+/* Time marching over n_slabs consecutive slabs of length tau (Sec. 3.1: the
+ * dG(1) slabs are coupled only through the left trace v^-): for each slab,
+ * U starts from v at both Radau nodes with zero pressure, pns_solve runs with
+ * v as v^-, and the velocity at the second Radau node (the slab's end point,
+ * which the right Radau rule contains) becomes v for the next slab.
+ * v_dev (FP64, n_v values): in, the velocity at the start; out, at the end of
+ * the last solved slab.  U_dev (FP64, N_st): out, the last slab's solution.
+ * work as for pns_solve.  info: the sums of the iteration counts over the
+ * slabs, residual_initial of the first and residual_final of the last slab
+ * solved.  Returns the first failing pns_solve code (PNS_ENOTCONV: the
+ * slab that did not converge is left in U_dev and v_dev holds the start of
+ * that slab); n_slabs = 0 leaves v_dev unchanged. */
+int pns_march(pns_ctx* ctx, const pns_model* model, double* v_dev, int n_slabs, double* U_dev,
+              const pns_solve_params* prm, void* work_dev, size_t work_bytes,
+              pns_solve_info* info);
+
 /* ---------------------------------------------------------------- serving */
 
 /* A request server for independent slab solves (each one the Newton-Krylov

@@ -338,4 +338,39 @@ int pns_solve(pns_ctx* ctx, const pns_model* md, const double* vprev, double* U,
   return fail(ctx, PNS_ENOTCONV, why);
 }
 
+int pns_march(pns_ctx* ctx, const pns_model* md, double* v, int n_slabs, double* U,
+              const pns_solve_params* prm, void* work, size_t work_bytes, pns_solve_info* info) {
+  if (!ctx) return PNS_EINVAL;
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (ctx->dim == 3) return fail(ctx, PNS_EUNSUPPORTED, "3D contexts have the action only");
+  if (!md || !v || !U || !prm || n_slabs < 0 || (const void*)v == (const void*)U)
+    return fail(ctx, PNS_EINVAL, "NULL model, vectors or parameters, or n_slabs < 0");
+  if (!ctx->ws) return fail(ctx, PNS_EWORKSPACE, "no workspace bound");
+  const Grid& g = ctx->lev[0].g;
+  hipStream_t s = ctx->stream;
+  pns_solve_info tot{};
+  for (int k = 0; k < n_slabs; ++k) {
+    // initial guess of the slab: the left trace at both Radau nodes, zero pressure
+    PNS_HIP(ctx, launch_fill<double>(g.nst, 0.0, U, s));
+    PNS_HIP(ctx, launch_copy<double>(g.nv, v, U, s));
+    PNS_HIP(ctx, launch_copy<double>(g.nv, v, U + g.ns, s));
+    pns_solve_info si{};
+    const int rc = pns_solve(ctx, md, v, U, prm, work, work_bytes, &si);
+    tot.newton_iterations += si.newton_iterations;
+    tot.krylov_iterations += si.krylov_iterations;
+    tot.smoother_setups += si.smoother_setups;
+    tot.backtracks += si.backtracks;
+    if (k == 0) tot.residual_initial = si.residual_initial;
+    tot.residual_final = si.residual_final;
+    if (info) *info = tot;
+    if (rc != PNS_OK) return rc;
+    // the right Radau rule ends at the slab's end: its second node's velocity
+    // is the left trace of the next slab
+    PNS_HIP(ctx, launch_copy<double>(g.nv, U + g.ns, v, s));
+  }
+  PNS_HIP(ctx, hipStreamSynchronize(s));
+  if (info) *info = tot;
+  return PNS_OK;
+}
+
 }  // extern "C"

@@ -130,6 +130,8 @@ def lib():
         L.pns_solve_workspace_bytes.restype = ctypes.c_size_t
         L.pns_solve.argtypes = [_vp, pp(pns_model), _vp, _vp, pp(pns_solve_params), _vp,
                                 ctypes.c_size_t, pp(pns_solve_info)]
+        L.pns_march.argtypes = [_vp, pp(pns_model), _vp, i, _vp, pp(pns_solve_params), _vp,
+                                ctypes.c_size_t, pp(pns_solve_info)]
         L.pns_request_footprint.argtypes = [pp(pns_request)]
         L.pns_request_footprint.restype = ctypes.c_size_t
         L.pns_server_create.argtypes = [i, _vp, ctypes.c_size_t, pp(_vp)]
@@ -307,6 +309,27 @@ class Context:
         rc = lib().pns_solve(self.h, ctypes.byref(model_struct(model)), vp,
                              self._f64(U, sz["nst"]), ctypes.byref(ps), _vp(base), nbytes,
                              ctypes.byref(info))
+        if check and rc not in (PNS_OK, PNS_ENOTCONV):
+            self._check(rc)
+        del work
+        return rc, {f: getattr(info, f) for f, _ in pns_solve_info._fields_}
+
+    def pns_march(self, model: dict, v, n_slabs, U, check=True, **params):
+        """Time marching over n_slabs slabs: v (FP64, velocity) is advanced in
+        place, U (FP64) holds the last slab's solution.  Returns (return code,
+        info dict with the summed iteration counts)."""
+        prm = dict(SOLVE_DEFAULTS, **params)
+        ps = pns_solve_params(*(prm[f] for f, _ in pns_solve_params._fields_))
+        nbytes = self.pns_solve_workspace_bytes(ps.restart)
+        if nbytes == 0:
+            raise PnsError(PNS_EINVAL, "invalid restart length")
+        work = self.torch.empty(nbytes + 256, dtype=self.torch.uint8, device=self.device)
+        base = (work.data_ptr() + 255) // 256 * 256
+        sz = self.sizes(0)
+        info = pns_solve_info()
+        rc = lib().pns_march(self.h, ctypes.byref(model_struct(model)), self._f64(v, sz["nv"]),
+                             int(n_slabs), self._f64(U, sz["nst"]), ctypes.byref(ps), _vp(base),
+                             nbytes, ctypes.byref(info))
         if check and rc not in (PNS_OK, PNS_ENOTCONV):
             self._check(rc)
         del work

@@ -123,6 +123,29 @@ def test_sweep_variant_entry_points_reject_bad_arguments():
     L.pns_ctx_destroy(h)
 
 
+def test_march_rejects_bad_arguments():
+    L = pnsmg.lib()
+    model = pnsmg.model_struct(dict(p=1.8, delta=1e-2, nu=0.1, nu_inf=1e-4))
+    prm = pnsmg.pns_solve_params(*(pnsmg.SOLVE_DEFAULTS[f] for f, _ in
+                                   pnsmg.pns_solve_params._fields_))
+    info = pnsmg.pns_solve_info()
+    assert L.pns_march(None, ctypes.byref(model), None, 1, None, ctypes.byref(prm), None, 0,
+                       ctypes.byref(info)) == pnsmg.PNS_EINVAL
+    rc, h = _create((8, 8), 2)
+    v, U = ctypes.c_void_p(4096), ctypes.c_void_p(8192)
+    assert L.pns_march(h, ctypes.byref(model), v, -1, U, ctypes.byref(prm), None, 0,
+                       ctypes.byref(info)) == pnsmg.PNS_EINVAL
+    assert L.pns_march(h, ctypes.byref(model), v, 1, v, ctypes.byref(prm), None, 0,
+                       ctypes.byref(info)) == pnsmg.PNS_EINVAL
+    assert L.pns_march(h, ctypes.byref(model), v, 1, U, ctypes.byref(prm), None, 0,
+                       ctypes.byref(info)) == pnsmg.PNS_EWORKSPACE
+    L.pns_ctx_destroy(h)
+    rc, h = _create((2, 2, 2))
+    assert L.pns_march(h, ctypes.byref(model), v, 1, U, ctypes.byref(prm), None, 0,
+                       ctypes.byref(info)) == pnsmg.PNS_EUNSUPPORTED
+    L.pns_ctx_destroy(h)
+
+
 def test_vcycle_graph_switch_rejects_bad_arguments():
     L = pnsmg.lib()
     assert L.pns_set_vcycle_graph(None, 1) == pnsmg.PNS_EINVAL
