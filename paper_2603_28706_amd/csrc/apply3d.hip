@@ -21,8 +21,9 @@
 //   12 fields (x and u_k, 3 components, 2 Radau nodes) x 9 lines = 108 lines.
 // * One lane per (Gauss point, Radau node) forms the tangent (FP64 scalars),
 //   the temporal mass coupling from the partner node's values and the test
-//   coefficients; the 4 pressure rows are summed by a butterfly over the
-//   lanes of one Radau node.
+//   coefficients; the Radau nodes take the two half-waves and the point values
+//   are stored point-index fastest, so these LDS accesses are unit-stride; the
+//   4 pressure rows are summed by a butterfly within each half-wave.
 // * The transposed stages (z, y, x) run one line per lane (2 x 3 components x
 //   9 lines = 54) and end in coalesced stores of the cell's slot of E.
 // * Two LDS buffers per wave are used in turn by the stages (about 18 KB in
@@ -43,7 +44,7 @@ namespace {
 constexpr int kCellsPerWg = 4;   // waves (cells in flight) per workgroup
 constexpr int kF = 12;           // staged fields: x (mu*3 + c), then u_k (6 + mu*3 + c)
 constexpr int kLines = kF * 9;   // forward lines per stage
-constexpr int kP = kF * 27 * 4;  // buffer P: s1 (648), pt (1296), r1 (486)
+constexpr int kP = kF * 27 * 4;  // buffer P: s1 (648), pt [f][4][27] (1296), r1 (486)
 constexpr int kQ = kF * 27 * 3;  // buffer Q: s2 (972), cf (648), r2 (324)
 // results per cell in E: velocity of node a, Radau node mu, component c at
 // a*6 + mu*3 + c (the 6 values of a node are contiguous), pressure j of mu at
@@ -140,8 +141,8 @@ __global__ __launch_bounds__(64 * kCellsPerWg, 2) void cell_volume3d_kernel(
     }
   };
   auto load_pres = [&](int64_t c, T (&pp)[4]) {
-    if (t < 54) {
-      const T* pv = x + (int64_t)(t & 1) * g.ns + g.nv + 4 * c;
+    if ((t & 31) < 27) {  // the lanes of the point phase: Radau node t / 32
+      const T* pv = x + (int64_t)(t >> 5) * g.ns + g.nv + 4 * c;
       pp[0] = pv[0];
       pp[1] = pv[1];
       pp[2] = pv[2];
@@ -198,7 +199,8 @@ __global__ __launch_bounds__(64 * kCellsPerWg, 2) void cell_volume3d_kernel(
       }
     }
     wave_sync();
-    // ---- forward z: line (f, qy, qx) -> pt[f][q][v, dx, dy, dz] (reference derivatives)
+    // ---- forward z: line (f, qy, qx) -> pt[f][v, dx, dy, dz][q] (reference
+    // derivatives; point index fastest so that the point phase reads unit stride)
 #pragma unroll
     for (int it = 0; it < 2; ++it) {
       const int l = t + 64 * it;
@@ -214,22 +216,23 @@ __global__ __launch_bounds__(64 * kCellsPerWg, 2) void cell_volume3d_kernel(
         }
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          T* dst = P + (f * 27 + q * 9 + r) * 4;
+          T* dst = P + f * 108 + q * 9 + r;
           dst[0] = (T)Bq(q, 0) * v[0] + (T)Bq(q, 1) * v[1] + (T)Bq(q, 2) * v[2];
-          dst[1] = (T)Bq(q, 0) * dx[0] + (T)Bq(q, 1) * dx[1] + (T)Bq(q, 2) * dx[2];
-          dst[2] = (T)Bq(q, 0) * dy[0] + (T)Bq(q, 1) * dy[1] + (T)Bq(q, 2) * dy[2];
-          dst[3] = (T)Dq(q, 0) * v[0] + (T)Dq(q, 1) * v[1] + (T)Dq(q, 2) * v[2];
+          dst[27] = (T)Bq(q, 0) * dx[0] + (T)Bq(q, 1) * dx[1] + (T)Bq(q, 2) * dx[2];
+          dst[54] = (T)Bq(q, 0) * dy[0] + (T)Bq(q, 1) * dy[1] + (T)Bq(q, 2) * dy[2];
+          dst[81] = (T)Dq(q, 0) * v[0] + (T)Dq(q, 1) * v[1] + (T)Dq(q, 2) * v[2];
         }
       }
     }
     wave_sync();
 
-    // ---- points: lane (q, mu); test coefficients cf[mu][c][V, Gx, Gy, Gz][q] into
-    // Q, pressure rows by butterfly
+    // ---- points: Radau node mu = half-wave, point q = lane within the half (27 of
+    // 32 busy); test coefficients cf[mu][c][V, Gx, Gy, Gz][q] into Q, pressure
+    // rows by a butterfly within each half
     {
       double p4[4] = {0.0, 0.0, 0.0, 0.0};
-      if (t < 54) {
-        const int q = t >> 1, mu = t & 1, other = 1 - mu;
+      const int q = t & 31, mu = t >> 5, other = 1 - mu;
+      if (q < 27) {
         const int qz = q / 9, qy = (q / 3) % 3, qx = q % 3;
         const double W = vol * gw_sel(qx) * gw_sel(qy) * gw_sel(qz);
         const double sW = tau * (mu ? kWt[1] : kWt[0]) * W;
@@ -237,14 +240,14 @@ __global__ __launch_bounds__(64 * kCellsPerWg, 2) void cell_volume3d_kernel(
         T X[3], U[3], GX[3][3], GU[3][3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const T* px = P + ((mu * 3 + c) * 27 + q) * 4;
-          const T* pu = P + ((6 + mu * 3 + c) * 27 + q) * 4;
+          const T* px = P + (mu * 3 + c) * 108 + q;
+          const T* pu = P + (6 + mu * 3 + c) * 108 + q;
           X[c] = px[0];
           U[c] = pu[0];
 #pragma unroll
           for (int j = 0; j < 3; ++j) {
-            GX[c][j] = px[1 + j] * ih[j];
-            GU[c][j] = pu[1 + j] * ih[j];
+            GX[c][j] = px[27 * (1 + j)] * ih[j];
+            GU[c][j] = pu[27 * (1 + j)] * ih[j];
           }
         }
         double A[3][3];
@@ -270,7 +273,7 @@ __global__ __launch_bounds__(64 * kCellsPerWg, 2) void cell_volume3d_kernel(
                      prep[2] * (T)(gp_sel(qy) - 0.5) + prep[3] * (T)(gp_sel(qz) - 0.5);
         T xo[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) xo[i] = P[((other * 3 + i) * 27 + q) * 4];
+        for (int i = 0; i < 3; ++i) xo[i] = P[(other * 3 + i) * 108 + q];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
           Q[((mu * 3 + i) * 4 + 0) * 27 + q] = (T)W * ((T)kself * X[i] + (T)koth * xo[i]);
@@ -291,15 +294,15 @@ __global__ __launch_bounds__(64 * kCellsPerWg, 2) void cell_volume3d_kernel(
         p4[2] = cpv * (gp_sel(qy) - 0.5);
         p4[3] = cpv * (gp_sel(qz) - 0.5);
       }
-      // sum over the lanes of one Radau node (xor with even masks keeps the parity)
+      // sum over the lanes of one Radau node (xor masks below 32 stay in the half)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
 #pragma unroll
-        for (int msk = 2; msk < 64; msk <<= 1) p4[j] += __shfl_xor(p4[j], msk, 64);
+        for (int msk = 1; msk < 32; msk <<= 1) p4[j] += __shfl_xor(p4[j], msk, 64);
       }
-      if (t < 2) {
+      if (q == 0) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) pres[t][j] = p4[j];
+        for (int j = 0; j < 4; ++j) pres[mu][j] = p4[j];
       }
     }
     if (next >= 0) load_pres(next, prep);
