@@ -199,15 +199,19 @@ int pns_vanka_smooth(pns_ctx* ctx, int level, int n_sweeps, double omega, const 
  * chosen on the device by an autotuner.  Each patch form has several kernel
  * variants that compute
  * the same additive step with different workgroup sizes (waves per
- * workgroup), column loads in flight and rows per lane; pns_vanka_setup runs
- * every variant of every level once on zero vectors, times three further
- * runs with events on the context stream and keeps the fastest.  Variants
- * differ only in time and in the summation order inside a patch.
+ * workgroup), column loads in flight and rows per lane; the first
+ * pns_vanka_setup in a process that meets a level shape (cells in x and y,
+ * patch form, precision) runs every variant of every level once on zero
+ * vectors, times three further runs with events on the context stream and
+ * keeps the fastest; later setups and contexts with the same shapes reuse
+ * the choices without timing.  Variants differ only in time and in the
+ * summation order inside a patch.
  *   pns_sweep_variant: out = {chosen variant, number of variants of the
  *     level's form, waves per workgroup, column loads in flight, rows per
  *     lane};
  *   pns_sweep_variant_time: the autotuner's mean time (ms) of one step of
- *     `variant` on `level` (0 before the first setup);
+ *     `variant` on `level` in this context (0 if the context reused an
+ *     earlier choice or has not been set up);
  *   pns_set_sweep_variant: use `variant` on `level` until the next
  *     pns_vanka_setup (drops a captured V-cycle graph).
  * PNS_EINVAL for a bad level or variant and on 3D contexts. */

@@ -3,7 +3,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "ctx.h"
@@ -185,9 +188,39 @@ hipError_t vcycle_level(pns_ctx* c, int l, int nu1, int nu2, double omega, const
 // patch form runs one additive step (4 colour launches) on zero vectors, once
 // to warm up and three times timed with events on the context stream; the
 // fastest is kept.  The variants compute the same step, so the choice changes
-// the time and the summation order within a patch only.
+// the time and the summation order within a patch only.  The choice depends on
+// the level's shape, not on its data: it is made once per (cells in x, cells
+// in y, patch form, precision) in a process and reused by later setups and
+// contexts (smoother refreshes inside a solve, served requests).
+struct TunedShapes {
+  std::mutex mu;
+  std::map<std::tuple<int, int, int, int>, int> best;
+};
+TunedShapes& tuned_shapes() {
+  static TunedShapes t;
+  return t;
+}
+
 template <typename T>
 int autotune_sweeps(pns_ctx* c) {
+  {
+    // every level already tuned in this process: reuse the choices
+    TunedShapes& ts = tuned_shapes();
+    std::lock_guard<std::mutex> lk(ts.mu);
+    bool all = true;
+    for (int l = 0; l < c->nlev && all; ++l) {
+      const Grid& g = c->lev[l].g;
+      auto it = ts.best.find({g.nx, g.ny, complex_patches(c, l) ? 1 : 0, (int)c->es});
+      if (it == ts.best.end()) all = false;
+    }
+    if (all) {
+      for (int l = 0; l < c->nlev; ++l) {
+        const Grid& g = c->lev[l].g;
+        c->sweep_var[l] = ts.best[{g.nx, g.ny, complex_patches(c, l) ? 1 : 0, (int)c->es}];
+      }
+      return PNS_OK;
+    }
+  }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   PNS_HIP(c, hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -230,6 +263,14 @@ int autotune_sweeps(pns_ctx* c) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (rc == PNS_OK) {
+    TunedShapes& ts = tuned_shapes();
+    std::lock_guard<std::mutex> lk(ts.mu);
+    for (int l = 0; l < c->nlev; ++l) {
+      const Grid& g = c->lev[l].g;
+      ts.best[{g.nx, g.ny, complex_patches(c, l) ? 1 : 0, (int)c->es}] = c->sweep_var[l];
+    }
+  }
   return rc;
 }
 
