@@ -175,8 +175,9 @@ def apply3d(n=32, reps=50, lin=2):
         torch.cuda.synchronize()
         t = ea.elapsed_time(eb) * 1e-3 / reps
         flops = apply3d_flops_per_cell(lin) * sz["cells"]
+        # tflops: the volume-term operation count over the whole action's time
         out[name] = dict(us_mean=t * 1e6, gdofs=sz["nst"] / t / 1e9,
-                         volume_tflops=flops / t / 1e12,
+                         tflops=flops / t / 1e12,
                          hbm_gbs=algorithmic_bytes(sz, 8 if prec == pnsmg.FP64 else 4) / t / 1e9)
         out["space_time_dof"] = sz["nst"]
         out["flop_per_apply"] = flops
