@@ -144,12 +144,14 @@ MODEL3D = dict(p=1.3, delta=1e-3, nu=1.0, nu_inf=1e-3, gamma1=40.0, gamma2=40.0,
                convection=1, qsign=1)
 
 
-def apply3d(n=32, reps=50, lin=2):
+def apply3d(n=32, reps=50, lin=2, smoother=True, sweeps=20):
     """3D action on n^3 hexahedra (Q2 / P1disc x dG(1), tau = 0.01) with
     p = 1.3, delta = 1e-3, nu = 1, nu_inf = 1e-3; state: 3D sin-series
     velocity (8 modes, seed 301, O(tau) time variation), input U[-1, 1]
     (seed 302).  Mean duration of `reps` back-to-back actions (HIP events on
-    the stream the kernels run on), FP64 and FP32."""
+    the stream the kernels run on), FP64 and FP32; then the finest-level
+    Vanka smoother: setup wall time and the mean of `sweeps` sweeps (residual
+    U[-1, 1], seed 303, omega = 0.5)."""
     import torch
 
     from paper_2603_28706_amd import inputs, pnsmg
@@ -183,6 +185,35 @@ def apply3d(n=32, reps=50, lin=2):
         out["flop_per_apply"] = flops
         print(f"[bench] 3D action {n}^3 {name}: {t * 1e6:.1f} us, {sz['nst'] / t / 1e9:.2f} GDoF/s",
               file=sys.stderr, flush=True)
+        if smoother:
+            # finest-level Vanka smoother: setup (cell matrices at the midpoint
+            # state + batched complex 85 x 85 inversions), then sweeps
+            # (defect by the action + 8 colour launches of patch solves)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.pns_vanka_setup()
+            torch.cuda.synchronize()
+            setup_s = time.perf_counter() - t0
+            r = torch.tensor(inputs.uniform(303, sz["nst"]), dtype=ctx.dtype, device="cuda")
+            d = ctx.vector()
+            for _ in range(2):
+                ctx.pns_vanka_smooth(0, 1, 0.5, r, d)
+            torch.cuda.synchronize()
+            ea.record(stream)
+            for _ in range(sweeps):
+                ctx.pns_vanka_smooth(0, 1, 0.5, r, d)
+            eb.record(stream)
+            torch.cuda.synchronize()
+            ts = ea.elapsed_time(eb) * 1e-3 / sweeps
+            es = 8 if prec == pnsmg.FP64 else 4
+            factor_bytes = sz["cells"] * 2 * 85 * 85 * es
+            # the patch part: sweep time less one action (the defect)
+            tp = max(ts - t, 1e-9)
+            out[name].update(vanka_setup_s=setup_s, sweep_us=ts * 1e6, patch_part_us=tp * 1e6,
+                             factor_bytes=factor_bytes, factor_gbs=factor_bytes / tp / 1e9)
+            print(f"[bench] 3D Vanka {n}^3 {name}: setup {setup_s:.3f} s, sweep {ts * 1e6:.1f} us "
+                  f"(patch part {tp * 1e6:.1f} us, {factor_bytes / tp / 1e9:.0f} GB/s on factors)",
+                  file=sys.stderr, flush=True)
         del ctx
         torch.cuda.empty_cache()
     return out

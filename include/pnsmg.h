@@ -124,10 +124,12 @@ typedef struct pns_ctx pns_ctx;
  * (and so pns_vcycle) is available when the coarsest level has at most 40000
  * space-time unknowns; larger coarsest levels still allow the apply and the
  * smoother.  `stream` is a hipStream_t (NULL =
- * default stream).  A dim = 3 mesh gives an action-only context: n_levels
- * must be 1; pns_set_state, pns_cell_apply, pns_cell_defect and the size and
- * workspace queries work, every smoother, V-cycle and solve entry point
- * returns PNS_EUNSUPPORTED and pns_solve_workspace_bytes returns 0.
+ * default stream).  A dim = 3 mesh gives a one-level context: n_levels must
+ * be 1; pns_set_state, pns_cell_apply, pns_cell_defect, the size and
+ * workspace queries and the finest-level smoother (pns_vanka_setup without
+ * node masks, pns_vanka_smooth on level 0, surrogate patches) work; the
+ * V-cycle, residual and solve entry points return PNS_EUNSUPPORTED and
+ * pns_solve_workspace_bytes returns 0.
  * Returns PNS_EINVAL / PNS_EUNSUPPORTED on bad input. */
 int pns_ctx_create(const pns_mesh* mesh, const pns_discretization* disc, int n_levels,
                    int precision, void* stream, pns_ctx** out);
@@ -163,7 +165,8 @@ int pns_set_apply_mode(pns_ctx* ctx, int mode);
 
 /* Select the finest-level patch matrices (default PNS_PATCH_SURROGATE); a
  * change takes effect at the next pns_vanka_setup (until then the context has
- * no smoother).  PNS_EINVAL for an unknown kind. */
+ * no smoother).  PNS_EINVAL for an unknown kind; PNS_EUNSUPPORTED for
+ * PNS_PATCH_EXACT on a 3D context. */
 int pns_set_patch_kind(pns_ctx* ctx, int kind);
 
 /* y = J_n(u_k) x on level 0, eq. (slab-underint-jac): the temporal mass
@@ -187,7 +190,13 @@ int pns_cell_defect(pns_ctx* ctx, const void* b_dev, const void* x_dev, void* y_
  * node_masks (host, may be NULL): one uint16 per level-0 cell, bit a set if
  * local Q2 node a (a = ax + 3 ay) belongs to that cell's patch; dropped nodes
  * are removed from the patch (uneven patches).  Returns PNS_ESINGULAR if a
- * patch has a zero pivot. */
+ * patch has a zero pivot.
+ * 3D contexts (one level): the 85 x 85 spatial cell matrices at the midpoint
+ * state are formed in FP64, each cell patch (27 nodes x 3 components + 4
+ * pressure coefficients per Radau node, 170 unknowns) is summed from the 27
+ * cells around it and inverted in time-diagonal form (one complex 85 x 85
+ * Gauss-Jordan inversion with partial pivoting, FP64, stored in the context
+ * precision); node_masks must be NULL (PNS_EUNSUPPORTED otherwise). */
 int pns_vanka_setup(pns_ctx* ctx, const uint16_t* node_masks);
 
 /* n_sweeps additive Vanka steps on level `level`, eq. (stmg-vanka-update):

@@ -38,8 +38,14 @@ size_t layout(pns_ctx* c, bool bind) {
   const size_t es = c->es;
   c->uk = take(2 * g0.nv * es);
   c->uk64 = (double*)take(2 * g0.nv * 8);
-  if (c->dim == 3) {  // action only
+  if (c->dim == 3) {  // action and the finest-level smoother
     c->E3 = take(g0.nc * 170 * es);
+    c->urep = (double*)take(g0.nv * 8);
+    c->Esr = (double*)take(g0.nc * 85 * 85 * 8);
+    c->status = (int*)take(sizeof(int) * 4);
+    Level& L = c->lev[0];
+    L.inv = take(g0.nc * 2 * 85 * 85 * es);
+    L.res = take(g0.nst * es);
     return (off + kAlign - 1) / kAlign * kAlign;
   }
   c->urep = (double*)take(g0.nv * 8);
@@ -150,6 +156,11 @@ hipError_t smooth(pns_ctx* c, int l, int nsweeps, double omega, const T* r, T* d
       hipError_t e = defect<T>(c, l, r, d, (T*)L.res);
       if (e != hipSuccess) return e;
       res = (const T*)L.res;
+    }
+    if (c->dim == 3) {
+      hipError_t e = launch_patch_sweep3<T>(c->g3, (const T*)L.inv, res, d, omega, c->stream);
+      if (e != hipSuccess) return e;
+      continue;
     }
     hipError_t e = complex_patches(c, l)
                        ? launch_patch_sweep_c<T>(L.g, (const T*)L.inv, res, d, omega,
@@ -272,6 +283,21 @@ int autotune_sweeps(pns_ctx* c) {
     }
   }
   return rc;
+}
+
+// 3D: surrogate patches of the finest level only (time-diagonal form)
+template <typename T>
+int vanka_setup3d(pns_ctx* c) {
+  hipStream_t s = c->stream;
+  PNS_HIP(c, hipMemsetAsync(c->status, 0, sizeof(int), s));
+  PNS_HIP(c, launch_element_matrices3d(c->g3, c->model, c->urep, c->Esr, s));
+  PNS_HIP(c, launch_patches3d<T>(c->g3, c->disc.tau, c->Esr, (T*)c->lev[0].inv, c->status, s));
+  int st = 0;
+  PNS_HIP(c, hipMemcpyAsync(&st, c->status, sizeof(int), hipMemcpyDeviceToHost, s));
+  PNS_HIP(c, hipStreamSynchronize(s));
+  if (st & 1) return fail(c, PNS_ESINGULAR, "a patch matrix has a zero pivot");
+  c->has_smoother = true;
+  return PNS_OK;
 }
 
 template <typename T>
@@ -577,11 +603,9 @@ int pns_set_state(pns_ctx* ctx, const pns_model* md, const double* u_k) {
     PNS_HIP(ctx, hipMemcpyAsync(ctx->uk, u_k, 2 * g0.nv * 8, hipMemcpyDeviceToDevice, s));
   else
     PNS_HIP(ctx, launch_convert<float>(2 * g0.nv, ctx->uk64, (float*)ctx->uk, s));
-  if (ctx->dim == 2) {
-    PNS_HIP(ctx, launch_state_combine(g0.nv, ctx->uk64, ctx->uk64 + g0.nv, kXiMid[0], kXiMid[1],
-                                      ctx->urep, s));
-    if (ctx->apply_mode == PNS_APPLY_CACHED) PNS_HIP(ctx, build_tangent_cache(ctx));
-  }
+  PNS_HIP(ctx, launch_state_combine(g0.nv, ctx->uk64, ctx->uk64 + g0.nv, kXiMid[0], kXiMid[1],
+                                    ctx->urep, s));
+  if (ctx->dim == 2 && ctx->apply_mode == PNS_APPLY_CACHED) PNS_HIP(ctx, build_tangent_cache(ctx));
   ctx->has_state = true;
   ctx->has_smoother = false;
   return PNS_OK;
@@ -602,9 +626,10 @@ int pns_set_apply_mode(pns_ctx* ctx, int mode) {
 
 int pns_set_patch_kind(pns_ctx* ctx, int kind) {
   if (!ctx) return PNS_EINVAL;
-  if (ctx->dim == 3) return fail(ctx, PNS_EUNSUPPORTED, "3D contexts have no smoother");
   if (kind != PNS_PATCH_SURROGATE && kind != PNS_PATCH_EXACT)
     return fail(ctx, PNS_EINVAL, "unknown patch kind");
+  if (ctx->dim == 3 && kind != PNS_PATCH_SURROGATE)
+    return fail(ctx, PNS_EUNSUPPORTED, "3D contexts have surrogate patches only");
   if (kind != ctx->patch_kind) {
     ctx->has_smoother = false;
     ctx->drop_graph();
@@ -634,16 +659,18 @@ int pns_cell_defect(pns_ctx* ctx, const void* b, const void* x, void* y) {
 }
 
 int pns_vanka_setup(pns_ctx* ctx, const uint16_t* node_masks) {
-  if (ctx && ctx->dim == 3) return fail(ctx, PNS_EUNSUPPORTED, "3D contexts have no smoother");
   if (!check_ctx(ctx, true, false)) return ctx_code(ctx, true, false);
   ctx->has_smoother = false;
   ctx->drop_graph();
+  if (ctx->dim == 3) {
+    if (node_masks) return fail(ctx, PNS_EUNSUPPORTED, "3D patches are not truncated");
+    return ctx->es == 8 ? vanka_setup3d<double>(ctx) : vanka_setup3d<float>(ctx);
+  }
   return ctx->es == 8 ? vanka_setup_impl<double>(ctx, node_masks)
                       : vanka_setup_impl<float>(ctx, node_masks);
 }
 
 int pns_vanka_smooth(pns_ctx* ctx, int level, int n_sweeps, double omega, const void* r, void* d) {
-  if (ctx && ctx->dim == 3) return fail(ctx, PNS_EUNSUPPORTED, "3D contexts have no smoother");
   if (!check_ctx(ctx, true, true)) return ctx_code(ctx, true, true);
   if (level < 0 || level >= ctx->nlev || n_sweeps < 0 || !r || !d || r == d)
     return fail(ctx, PNS_EINVAL, "bad level, sweep count or vectors");

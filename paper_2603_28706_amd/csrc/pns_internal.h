@@ -136,6 +136,20 @@ template <typename T>
 hipError_t launch_cell_apply3d(const Grid3& g, const Model& m, double tau, const T* uk,
                                const T* x, const T* b, T* y, T* E, int mode, hipStream_t s);
 
+// smooth3d.hip: finest-level Vanka smoother on hexahedra (surrogate patches in
+// time-diagonal form).  Es: nc * 85 * 85 FP64 spatial cell matrices at the
+// state u; inv: nc complex 85 x 85 inverses (2 * 85 * 85 values per patch,
+// colour-major patch order); status bit 0 set on a zero pivot.
+hipError_t launch_element_matrices3d(const Grid3& g, const Model& m, const double* u, double* Es,
+                                     hipStream_t s);
+template <typename T>
+hipError_t launch_patches3d(const Grid3& g, double tau, const double* Es, T* inv, int* status,
+                            hipStream_t s);
+// one additive Vanka step d += omega sum_K R_K^T A_K^{-1} R_K res (8 colour launches)
+template <typename T>
+hipError_t launch_patch_sweep3(const Grid3& g, const T* inv, const T* res, T* d, double omega,
+                               hipStream_t s);
+
 // setup.hip
 hipError_t launch_element_matrices(const Grid& g, const Model& m, const double* u, double* Es,
                                    hipStream_t s);

@@ -33,7 +33,7 @@ def _create(n=(8, 8), levels=1, prec=pnsmg.FP64, tau=0.01, dim=None, k_space=2, 
 def test_create_rejects_bad_configurations():
     assert _create(dim=1)[0] == pnsmg.PNS_EUNSUPPORTED
     assert _create(n=(4, 4, 4), dim=4)[0] == pnsmg.PNS_EUNSUPPORTED
-    assert _create(n=(4, 4, 4), levels=2)[0] == pnsmg.PNS_EUNSUPPORTED  # 3D: action only
+    assert _create(n=(4, 4, 4), levels=2)[0] == pnsmg.PNS_EUNSUPPORTED  # 3D: one level
     assert _create(n=(4, 4, 0))[0] == pnsmg.PNS_EINVAL
     assert _create(n=(4, 4, 4), hi=0.0)[0] == pnsmg.PNS_EINVAL
     assert _create(n=(4, 4, 4), k_time=2)[0] == pnsmg.PNS_EUNSUPPORTED
@@ -67,29 +67,35 @@ def test_workspace_query_and_state_errors_without_device():
     L.pns_ctx_destroy(h)
 
 
-def test_3d_context_is_action_only():
-    """A hexahedral context: unknown counts of Q2^3 / P1disc x dG(1), the
-    workspace holds the state only, every smoother, V-cycle and solve entry
-    point is rejected before any device work."""
+def test_3d_context_layout_and_rejections():
+    """A hexahedral context: unknown counts of Q2^3 / P1disc x dG(1); the
+    workspace holds the state, the per-cell results of the action and the
+    finest-level smoother (midpoint state, FP64 cell matrices, complex 85 x 85
+    patch inverses, defect); V-cycle, residual and solve entry points and
+    exact or truncated patches are rejected before any device work."""
     rc, h = _create(n=(32, 32, 32))
     assert rc == pnsmg.PNS_OK
     L = pnsmg.lib()
     out = (ctypes.c_int64 * 4)()
     assert L.pns_level_sizes(h, 0, out) == 0
-    assert (out[0], out[1], out[2], out[3]) == (1909894, 32768, 3 * 65 ** 3, 3 * 65 ** 3 + 4 * 32768)
+    nv = 3 * 65 ** 3
+    nst = 1909894
+    assert (out[0], out[1], out[2], out[3]) == (nst, 32768, nv, nv + 4 * 32768)
     assert L.pns_level_sizes(h, 1, out) == pnsmg.PNS_EINVAL
     nbytes = L.pns_workspace_bytes(h)
-    # state (context precision and FP64) and the per-cell results of the action
-    need = 2 * 3 * 65 ** 3 * (8 + 8) + 32768 * 170 * 8
+    es = 8
+    need = (2 * nv * (es + 8) + 32768 * 170 * es + nv * 8 + 32768 * 85 * 85 * 8 + 16
+            + 32768 * 2 * 85 * 85 * es + nst * es)
     assert need <= nbytes < need + 4096
     assert L.pns_solve_workspace_bytes(h, 30) == 0
     assert L.pns_set_apply_mode(h, pnsmg.APPLY_CACHED) == pnsmg.PNS_EUNSUPPORTED
     assert L.pns_set_apply_mode(h, pnsmg.APPLY_RECOMPUTE) == pnsmg.PNS_OK
     assert L.pns_set_patch_kind(h, pnsmg.PATCH_EXACT) == pnsmg.PNS_EUNSUPPORTED
+    assert L.pns_set_patch_kind(h, pnsmg.PATCH_SURROGATE) == pnsmg.PNS_OK
     v = ctypes.c_void_p(4096)
     w = ctypes.c_void_p(8192)
-    assert L.pns_vanka_setup(h, None) == pnsmg.PNS_EUNSUPPORTED
-    assert L.pns_vanka_smooth(h, 0, 1, ctypes.c_double(0.1), v, w) == pnsmg.PNS_EUNSUPPORTED
+    assert L.pns_vanka_setup(h, None) == pnsmg.PNS_EWORKSPACE
+    assert L.pns_vanka_smooth(h, 0, 1, ctypes.c_double(0.1), v, w) == pnsmg.PNS_EWORKSPACE
     assert L.pns_vcycle(h, 1, 1, ctypes.c_double(0.1), v, w) == pnsmg.PNS_EUNSUPPORTED
     model = pnsmg.model_struct(dict(p=1.3, delta=1e-3, nu=1.0, nu_inf=1e-4, gamma1=40.0,
                                     gamma2=40.0, sigma_max=1.0, convection=1, qsign=1, lin=2))
@@ -99,6 +105,16 @@ def test_3d_context_is_action_only():
                        ctypes.byref(info)) == pnsmg.PNS_EUNSUPPORTED
     assert L.pns_cell_apply(h, v, w) == pnsmg.PNS_EWORKSPACE
     assert L.pns_set_vcycle_graph(h, 1) == pnsmg.PNS_EUNSUPPORTED
+    L.pns_ctx_destroy(h)
+    # FP32: inverses and defect in single precision
+    rc, h = _create(n=(4, 2, 3), prec=pnsmg.FP32)
+    assert rc == pnsmg.PNS_OK
+    nn = 9 * 5 * 7
+    nc = 24
+    nst = 2 * (3 * nn + 4 * nc)
+    need = (2 * 3 * nn * (4 + 8) + nc * 170 * 4 + 3 * nn * 8 + nc * 85 * 85 * 8 + 16
+            + nc * 2 * 85 * 85 * 4 + nst * 4)
+    assert need <= L.pns_workspace_bytes(h) < need + 4096
     L.pns_ctx_destroy(h)
 
 

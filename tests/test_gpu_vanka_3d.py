@@ -1,0 +1,186 @@
+"""GPU parity of the finest-level Vanka smoother on hexahedra (Q2 / P1disc x
+dG(1), surrogate patches frozen at the slab midpoint) through the C-ABI
+against the FP64 oracle.
+
+The GPU inverts each surrogate patch in time-diagonal form (one complex
+85 x 85 system); the oracle solves the real 170 x 170 patch matrix restricted
+from the globally assembled surrogate operator by LU with partial pivoting.
+Both are the same linear map evaluated with different rounding.  Tolerances
+as in 2D: FP64 1e-10 relative (patch condition numbers of these inputs are
+far below 1e4), FP32 1e-4 (inverses stored in FP32).  Small meshes are
+compared on every row; the 32^3 mesh (the 3D workload) on sampled rows, each
+formed by the oracle from the patches that contain it.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2603_28706_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2603_28706_amd import pnsmg  # noqa: E402
+
+MODEL3 = dict(p=1.3, delta=1e-3, nu=1.0, nu_inf=1e-3, gamma1=40.0, gamma2=40.0, sigma_max=1.0,
+              convection=1, qsign=1)
+KINDS = [pnsmg.PICARD, pnsmg.EXACT_NEWTON, pnsmg.MODIFIED_NEWTON]
+
+
+def oracle_problem(n, model, lin, tau=0.01, hi=(1.0, 1.0, 1.0)):
+    return O.Problem(n=tuple(n), hi=tuple(hi), tau=tau, p=model["p"], delta=model["delta"],
+                     nu=model["nu"], nu_inf=model["nu_inf"], gamma1=model["gamma1"],
+                     gamma2=model["gamma2"], sigma_max=model["sigma_max"],
+                     convection=model["convection"], qsign=model["qsign"], lin=lin)
+
+
+def to_dev(a, dtype):
+    return torch.as_tensor(np.asarray(a), dtype=dtype, device="cuda").contiguous()
+
+
+def gpu_context(n, model, lin, uk, precision, tau=0.01, hi=(1.0, 1.0, 1.0)):
+    ctx = pnsmg.Context(n, n_levels=1, precision=precision, tau=tau, hi=hi)
+    ctx.pns_set_state(dict(model, lin=lin), to_dev(uk, torch.float64))
+    ctx.pns_vanka_setup()
+    return ctx
+
+
+def oracle_steps(prob, uk, r, omega, nsteps):
+    A = O.assemble_slab(prob, O.split_uk(prob, uk))
+    patches = O.all_patches(prob)
+    pm = O.patch_matrices(O.assemble_surrogate(prob, uk), patches)
+    out = []
+    d = np.zeros(prob.nst)
+    for _ in range(nsteps):
+        d = O.vanka_step(A, pm, patches, r, d, omega)
+        out.append(d.copy())
+    return out
+
+
+@pytest.mark.parametrize("n,hi", [((2, 2, 2), (1.0, 1.0, 1.0)), ((3, 2, 4), (1.0, 2.0, 0.5))])
+def test_vanka3d_two_steps_fp64_and_fp32(n, hi):
+    lin = pnsmg.MODIFIED_NEWTON
+    prob = oracle_problem(n, MODEL3, lin, hi=hi)
+    uk = inputs.sin_series_velocity(n, seed=501, t_nodes=[0.01 / 3, 0.01], hi=hi)
+    r = inputs.uniform(502, prob.nst)
+    ref1, ref2 = oracle_steps(prob, uk, r, 0.5, 2)
+    for prec, dt, tol in ((pnsmg.FP64, torch.float64, 1e-10), (pnsmg.FP32, torch.float32, 1e-4)):
+        ctx = gpu_context(n, MODEL3, lin, uk, prec, hi=hi)
+        d = ctx.vector()
+        rd = to_dev(r, dt)
+        ctx.pns_vanka_smooth(0, 1, 0.5, rd, d)
+        torch.cuda.synchronize()
+        e1 = np.linalg.norm(d.double().cpu().numpy() - ref1) / np.linalg.norm(ref1)
+        ctx.pns_vanka_smooth(0, 1, 0.5, rd, d)
+        torch.cuda.synchronize()
+        e2 = np.linalg.norm(d.double().cpu().numpy() - ref2) / np.linalg.norm(ref2)
+        print(f"3D vanka n={n} prec={prec}: step 1 {e1:.2e}, step 2 {e2:.2e}")
+        assert e1 <= tol and e2 <= tol, (prec, e1, e2)
+
+
+@pytest.mark.parametrize("lin", KINDS)
+def test_vanka3d_tangents_and_model_variants(lin):
+    """All three tangents; p-Stokes; the literal pressure sign; random state
+    (the two Radau nodes differ, so the surrogate differs from the exact
+    patches); one sweep count of two through a single call."""
+    n = (2, 3, 2)
+    for v in ({}, dict(convection=0), dict(qsign=-1), dict(p=2.0)):
+        model = dict(MODEL3, **v)
+        prob = oracle_problem(n, model, lin)
+        uk = inputs.uniform(511, prob.nt * prob.nv)
+        r = inputs.uniform(512, prob.nst)
+        ref = oracle_steps(prob, uk, r, 0.7, 2)[1]
+        ctx = gpu_context(n, model, lin, uk, pnsmg.FP64)
+        d = ctx.vector()
+        ctx.pns_vanka_smooth(0, 2, 0.7, to_dev(r, torch.float64), d)
+        torch.cuda.synchronize()
+        err = np.linalg.norm(d.cpu().numpy() - ref) / np.linalg.norm(ref)
+        assert err <= 1e-10, (v, lin, err)
+
+
+def test_vanka3d_two_cells_and_zero_residual():
+    """Two cells (every patch touches the whole boundary; a single cell would
+    be the whole operator, singular in the constant pressure), omega = 1; a
+    zero residual gives a zero correction."""
+    n = (2, 1, 1)
+    prob = oracle_problem(n, MODEL3, pnsmg.MODIFIED_NEWTON)
+    uk = inputs.uniform(521, prob.nt * prob.nv)
+    r = inputs.uniform(522, prob.nst)
+    ref = oracle_steps(prob, uk, r, 1.0, 1)[0]
+    ctx = gpu_context(n, MODEL3, pnsmg.MODIFIED_NEWTON, uk, pnsmg.FP64)
+    d = ctx.vector()
+    ctx.pns_vanka_smooth(0, 1, 1.0, to_dev(r, torch.float64), d)
+    torch.cuda.synchronize()
+    assert np.linalg.norm(d.cpu().numpy() - ref) <= 1e-10 * np.linalg.norm(ref)
+    d2 = ctx.vector()
+    ctx.pns_vanka_smooth(0, 3, 0.5, ctx.vector(), d2)
+    torch.cuda.synchronize()
+    assert torch.all(d2 == 0)
+
+
+def test_vanka3d_32cubed_sampled_rows():
+    """32^3 with the sin-series state (the 3D workload): one step from d = 0,
+    d = omega sum_K R_K^T A_K^{-1} R_K r, on sampled rows; the oracle forms
+    each patch that holds a sampled row from the element matrices around it."""
+    n = (32, 32, 32)
+    prob = oracle_problem(n, MODEL3, pnsmg.MODIFIED_NEWTON)
+    uk = inputs.sin_series_velocity(n, seed=301, t_nodes=[0.01 / 3, 0.01])
+    r = inputs.uniform(302, prob.nst)
+    ur = O.representative_velocity(prob, uk)
+    N = 2 * n[0] + 1
+    nn = prob.num_nodes
+    # (node grid coordinates) corners, edges, faces, interior; pressure cells
+    nodes = [(0, 0, 0), (N - 1, 5, 0), (32, 32, 32), (7, 12, 40), (1, 1, 1), (64, 63, 17)]
+    cells_p = [0, 5 + 32 * (7 + 32 * 9), 32 ** 3 - 1]
+    rows = []
+    for mu in range(2):
+        for c, (ix, iy, iz) in enumerate(nodes):
+            rows.append(mu * prob.ns + (c % 3) * nn + ix + N * (iy + N * iz))
+        for k, cell in enumerate(cells_p):
+            rows.append(mu * prob.ns + prob.nv + 4 * cell + k)
+
+    def cells_of(row):
+        s = row % prob.ns
+        if s >= prob.nv:
+            return [(s - prob.nv) // 4]
+        node = s % nn
+        ijk = (node % N, (node // N) % N, node // (N * N))
+        lists = []
+        for i in ijk:
+            lists.append([i // 2 - 1, i // 2] if i % 2 == 0 else [(i - 1) // 2])
+        out = []
+        for cz in lists[2]:
+            for cy in lists[1]:
+                for cx in lists[0]:
+                    if 0 <= cx < 32 and 0 <= cy < 32 and 0 <= cz < 32:
+                        out.append(cx + 32 * (cy + 32 * cz))
+        return out
+
+    omega = 0.5
+    cache = {}
+    ref = []
+    for row in rows:
+        v = 0.0
+        for cell in cells_of(row):
+            if cell not in cache:
+                AK, idx = O.local_patch_matrix(prob, [ur, ur], cell)
+                cache[cell] = (idx, np.linalg.solve(AK, r[idx]))
+            idx, y = cache[cell]
+            v += omega * y[int(np.flatnonzero(idx == row)[0])]
+        ref.append(v)
+    ref = np.array(ref)
+    scale = np.abs(ref).max()
+    for prec, dt, tol in ((pnsmg.FP64, torch.float64, 1e-10), (pnsmg.FP32, torch.float32, 1e-4)):
+        ctx = gpu_context(n, MODEL3, pnsmg.MODIFIED_NEWTON, uk, prec)
+        d = ctx.vector()
+        ctx.pns_vanka_smooth(0, 1, omega, to_dev(r, dt), d)
+        torch.cuda.synchronize()
+        got = d.double().cpu().numpy()[rows]
+        err = np.abs(got - ref).max()
+        print(f"32^3 vanka sampled rows prec={prec}: max abs err {err:.3e} / {scale:.3e}")
+        assert err <= tol * scale
+        del ctx
+        torch.cuda.empty_cache()
