@@ -214,3 +214,66 @@ def test_local_patch_matrix_equals_restriction_of_the_assembled_operator(n):
                 AK, idx = O.local_patch_matrix(prob, blocks, cell, mask)
                 ref = Ag.tocsr()[idx][:, idx].toarray()
                 assert np.abs(AK - ref).max() <= 1e-14 * np.abs(ref).max(), (cell, mask)
+
+
+def test_prolongation_reproduces_coarse_fields_3d():
+    """3D nested interpolation: a global triquadratic velocity field and a
+    piecewise-linear (per coarse cell, discontinuous) pressure are reproduced
+    exactly on the refined mesh."""
+    coarse = O.Problem(n=(2, 1, 2), hi=(1.0, 0.5, 2.0))
+    fine = O.Problem(n=(4, 2, 4), hi=(1.0, 0.5, 2.0))
+    Ps = O.prolongation_spatial(coarse, fine)
+    fs = [lambda x, y, z: 1 + x * y * z - 2 * x ** 2 * y ** 2 * z ** 2 + z ** 2,
+          lambda x, y, z: x ** 2 - 3 * y + x * y ** 2 * z,
+          lambda x, y, z: y * z ** 2 - x ** 2 * z + 0.5]
+    vc = np.concatenate([q2_field(coarse, f) for f in fs])
+    vf = np.concatenate([q2_field(fine, f) for f in fs])
+
+    def pressure(prob, parent):
+        h = prob.h
+        out = np.zeros(4 * prob.num_cells)
+        for c in range(prob.num_cells):
+            i, j, k = c % prob.n[0], (c // prob.n[0]) % prob.n[1], c // (prob.n[0] * prob.n[1])
+            ctr = [(i + .5) * h[0], (j + .5) * h[1], (k + .5) * h[2]]
+            pc = parent(i, j, k)
+            q = lambda x, y, z: 0.3 + pc - 2 * x + 5 * y - 1.5 * z
+            out[4 * c:4 * c + 4] = [q(*ctr), -2 * h[0], 5 * h[1], -1.5 * h[2]]
+        return out
+
+    pcoarse = pressure(coarse, lambda i, j, k: i + 2 * j + 3 * k)
+    pfine = pressure(fine, lambda i, j, k: i // 2 + 2 * (j // 2) + 3 * (k // 2))
+    got = Ps @ np.concatenate([vc, pcoarse])
+    assert np.allclose(got, np.concatenate([vf, pfine]), atol=1e-13)
+
+
+def test_two_level_vcycle_matches_closed_form_3d():
+    """The recursive 3D V-cycle (2^3 -> 1^3) equals the explicit composition
+    of smoother, restriction, pinned coarse inverse and prolongation."""
+    fine = O.Problem(n=(2, 2, 2), p=1.5, delta=1e-2)
+    rng = np.random.default_rng(7)
+    uk = rng.uniform(-1, 1, fine.nt * fine.nv)
+    H = O.build_hierarchy(fine, uk, n_levels=2)
+    A = H.A[1].toarray()
+    n = A.shape[0]
+    omega, nu1, nu2 = 0.5, 1, 2
+    B = np.zeros_like(A)
+    for AK, idx in zip(H.patch_mats[1], H.patches[1]):
+        B[np.ix_(idx, idx)] += np.linalg.inv(AK)
+    P = H.P[0].toarray()
+    nc = P.shape[1]
+    Ac = H.A[0].toarray()
+    for i in H.pin:
+        Ac[i, :] = 0
+        Ac[:, i] = 0
+        Ac[i, i] = 1
+    Z = np.eye(nc)
+    Z[H.pin, H.pin] = 0
+    C = np.linalg.inv(Ac) @ Z
+    S = np.eye(n) - omega * B @ A
+    pre = sum(np.linalg.matrix_power(S, i) for i in range(nu1)) @ (omega * B)
+    post = sum(np.linalg.matrix_power(S, i) for i in range(nu2)) @ (omega * B)
+    V = pre + P @ C @ P.T @ (np.eye(n) - A @ pre)
+    V = np.linalg.matrix_power(S, nu2) @ V + post
+    r = rng.uniform(-1, 1, n)
+    got = O.vcycle(H, r, nu1=nu1, nu2=nu2, omega=omega)
+    assert np.allclose(got, V @ r, rtol=0, atol=1e-9 * np.abs(V @ r).max())
