@@ -38,14 +38,37 @@ size_t layout(pns_ctx* c, bool bind) {
   const size_t es = c->es;
   c->uk = take(2 * g0.nv * es);
   c->uk64 = (double*)take(2 * g0.nv * 8);
-  if (c->dim == 3) {  // action and the finest-level smoother
+  if (c->dim == 3) {  // action, smoother of every level, dense coarsest inverse
+    constexpr int64_t kE = 170 * 170;
     c->E3 = take(g0.nc * 170 * es);
     c->urep = (double*)take(g0.nv * 8);
     c->Esr = (double*)take(g0.nc * 85 * 85 * 8);
     c->status = (int*)take(sizeof(int) * 4);
-    Level& L = c->lev[0];
-    L.inv = take(g0.nc * 2 * 85 * 85 * es);
-    L.res = take(g0.nst * es);
+    if (c->nlev >= 2) {
+      c->Es0 = (double*)take(g0.nc * 85 * 85 * 8);
+      c->Es1 = (double*)take(g0.nc * 85 * 85 * 8);
+    }
+    for (int l = 0; l < c->nlev; ++l) {
+      Level& L = c->lev[l];
+      const bool coarsest = l == c->nlev - 1;
+      L.res = take(L.g.nst * es);
+      if (l == 0) {
+        L.inv = take(L.g.nc * 2 * 85 * 85 * es);  // complex time-diagonal surrogate inverses
+        continue;
+      }
+      L.E64 = (double*)take(L.g.nc * kE * 8);
+      L.E = take(L.g.nc * kE * es);
+      L.r = take(L.g.nst * es);
+      L.d = take(L.g.nst * es);
+      if (!coarsest) L.inv = take(L.g.nc * kE * es);
+    }
+    if (c->nlev >= 3) c->gjscratch3 = (double*)take(c->lev[1].g.nc * kE * 8);
+    if (c->has_coarse) {
+      const int64_t n = c->lev.back().g.nst;
+      c->Adense = (double*)take((size_t)n * n * 8);
+      c->gjwork = (double*)take((size_t)(2 * 64 * n + n + 8) * 8);
+      c->gjpiv = (int*)take((size_t)n * sizeof(int));
+    }
     return (off + kAlign - 1) / kAlign * kAlign;
   }
   c->urep = (double*)take(g0.nv * 8);
@@ -112,9 +135,11 @@ const T* tangent_cache(pns_ctx* c) {
 template <typename T>
 hipError_t defect(pns_ctx* c, int l, const T* b, const T* x, T* y) {
   Level& L = c->lev[l];
-  if (c->dim == 3)
+  if (c->dim == 3 && l == 0)
     return launch_cell_apply3d<T>(c->g3, c->model, c->disc.tau, (const T*)c->uk, x, b, y,
                                   (T*)c->E3, 1, c->stream);
+  if (c->dim == 3)
+    return launch_ebe_apply3d<T>(L.g3, (const T*)L.E, x, b, y, (T*)c->E3, c->stream);
   if (l == 0)
     return launch_cell_apply<T>(L.g, c->model, c->disc.tau, (const T*)c->uk, tangent_cache<T>(c),
                                 x, b, y, 1, c->stream);
@@ -124,9 +149,12 @@ hipError_t defect(pns_ctx* c, int l, const T* b, const T* x, T* y) {
 template <typename T>
 hipError_t apply_level(pns_ctx* c, int l, const T* x, T* y) {
   Level& L = c->lev[l];
-  if (c->dim == 3)
+  if (c->dim == 3 && l == 0)
     return launch_cell_apply3d<T>(c->g3, c->model, c->disc.tau, (const T*)c->uk, x, x, y,
                                   (T*)c->E3, 0, c->stream);
+  if (c->dim == 3)
+    return launch_ebe_apply3d<T>(L.g3, (const T*)L.E, x, (const T*)nullptr, y, (T*)c->E3,
+                                 c->stream);
   if (l == 0)
     return launch_cell_apply<T>(L.g, c->model, c->disc.tau, (const T*)c->uk, tangent_cache<T>(c),
                                 x, x, y, 0, c->stream);
@@ -158,7 +186,9 @@ hipError_t smooth(pns_ctx* c, int l, int nsweeps, double omega, const T* r, T* d
       res = (const T*)L.res;
     }
     if (c->dim == 3) {
-      hipError_t e = launch_patch_sweep3<T>(c->g3, (const T*)L.inv, res, d, omega, c->stream);
+      hipError_t e = l == 0
+                         ? launch_patch_sweep3<T>(L.g3, (const T*)L.inv, res, d, omega, c->stream)
+                         : launch_patch_sweep3r<T>(L.g3, (const T*)L.inv, res, d, omega, c->stream);
       if (e != hipSuccess) return e;
       continue;
     }
@@ -188,10 +218,14 @@ hipError_t vcycle_level(pns_ctx* c, int l, int nu1, int nu2, double omega, const
     res = (const T*)L.res;
   }
   Level& C = c->lev[l + 1];
-  if ((e = launch_restrict<T>(L.g, C.g, res, (T*)C.r, c->stream)) != hipSuccess) return e;
+  e = c->dim == 3 ? launch_restrict3<T>(L.g3, C.g3, res, (T*)C.r, c->stream)
+                  : launch_restrict<T>(L.g, C.g, res, (T*)C.r, c->stream);
+  if (e != hipSuccess) return e;
   if ((e = vcycle_level<T>(c, l + 1, nu1, nu2, omega, (const T*)C.r, (T*)C.d)) != hipSuccess)
     return e;
-  if ((e = launch_prolong_add<T>(L.g, C.g, (const T*)C.d, d, c->stream)) != hipSuccess) return e;
+  e = c->dim == 3 ? launch_prolong_add3<T>(L.g3, C.g3, (const T*)C.d, d, c->stream)
+                  : launch_prolong_add<T>(L.g, C.g, (const T*)C.d, d, c->stream);
+  if (e != hipSuccess) return e;
   return smooth<T>(c, l, nu2, omega, r, d, false);
 }
 
@@ -286,16 +320,47 @@ int autotune_sweeps(pns_ctx* c) {
 }
 
 // 3D: surrogate patches of the finest level only (time-diagonal form)
+// 3D: level 0 surrogate patches in time-diagonal form; coarse levels: Galerkin
+// element matrices (from the exact level-0 element matrices of both Radau
+// nodes), exact real patches (all but the coarsest), dense coarsest inverse
 template <typename T>
 int vanka_setup3d(pns_ctx* c) {
   hipStream_t s = c->stream;
+  const Grid3& g0 = c->lev[0].g3;
   PNS_HIP(c, hipMemsetAsync(c->status, 0, sizeof(int), s));
-  PNS_HIP(c, launch_element_matrices3d(c->g3, c->model, c->urep, c->Esr, s));
-  PNS_HIP(c, launch_patches3d<T>(c->g3, c->disc.tau, c->Esr, (T*)c->lev[0].inv, c->status, s));
+  PNS_HIP(c, launch_element_matrices3d(g0, c->model, c->urep, c->Esr, s));
+  PNS_HIP(c, launch_patches3d<T>(g0, c->disc.tau, c->Esr, (T*)c->lev[0].inv, c->status, s));
+  if (c->nlev >= 2) {
+    PNS_HIP(c, launch_element_matrices3d(g0, c->model, c->uk64, c->Es0, s));
+    PNS_HIP(c, launch_element_matrices3d(g0, c->model, c->uk64 + g0.nv, c->Es1, s));
+  }
+  for (int l = 1; l < c->nlev; ++l) {
+    Level& L = c->lev[l];
+    if (l == 1)
+      PNS_HIP(c, launch_galerkin3d_from_fine(L.g3, g0, c->disc.tau, c->Es0, c->Es1, L.E64, s));
+    else
+      PNS_HIP(c, launch_galerkin3d(L.g3, c->lev[l - 1].g3, c->lev[l - 1].E64, L.E64, s));
+    PNS_HIP(c, launch_transpose_convert3<T>(L.g.nc, L.E64, (T*)L.E, s));
+    if (l < c->nlev - 1)
+      PNS_HIP(c, launch_level_patches3d<T>(L.g3, L.E64, c->gjscratch3, (T*)L.inv, c->status, s));
+  }
   int st = 0;
+  if (c->has_coarse) {
+    Level& Lc = c->lev[c->nlev - 1];
+    const int64_t n = Lc.g.nst;
+    PNS_HIP(c, hipMemsetAsync(c->Adense, 0, (size_t)n * n * 8, s));
+    PNS_HIP(c, launch_coarse_assemble3(Lc.g3, Lc.E64, c->Adense, s));
+    c->pin[0] = Lc.g.nv;
+    c->pin[1] = Lc.g.ns + Lc.g.nv;
+    PNS_HIP(c, hipMemcpyAsync(c->gjwork, c->pin, sizeof(c->pin), hipMemcpyHostToDevice, s));
+    PNS_HIP(c, hipStreamSynchronize(s));
+    PNS_HIP(c, launch_pin(n, c->Adense, (const int64_t*)c->gjwork, 2, s));
+    PNS_HIP(c, coarse_invert(n, c->Adense, c->gjwork, c->gjpiv, c->status, s));
+  }
   PNS_HIP(c, hipMemcpyAsync(&st, c->status, sizeof(int), hipMemcpyDeviceToHost, s));
   PNS_HIP(c, hipStreamSynchronize(s));
   if (st & 1) return fail(c, PNS_ESINGULAR, "a patch matrix has a zero pivot");
+  if (st & 2) return fail(c, PNS_ESINGULAR, "the coarsest matrix has a zero pivot");
   c->has_smoother = true;
   return PNS_OK;
 }
@@ -405,15 +470,16 @@ int vcycle_graph(pns_ctx* c, int nu1, int nu2, double omega, const T* r, T* d) {
   return PNS_OK;
 }
 
-// 3D context: hexahedra, the level-0 action only
+// 3D context: hexahedra (action, smoother, V-cycle over n_levels nested meshes)
 int create3d(const pns_mesh* mesh, const pns_discretization* disc, int n_levels, int precision,
              void* stream, pns_ctx** out) {
   if (disc->k_space != 2 || disc->k_time != 1) return PNS_EUNSUPPORTED;
   if (precision != PNS_FP64 && precision != PNS_FP32) return PNS_EINVAL;
-  if (!(disc->tau > 0.0) || n_levels < 1) return PNS_EINVAL;
-  if (n_levels != 1) return PNS_EUNSUPPORTED;
+  if (!(disc->tau > 0.0) || n_levels < 1 || n_levels > 10) return PNS_EINVAL;
   const int nx = mesh->n_cells[0], ny = mesh->n_cells[1], nz = mesh->n_cells[2];
   if (nx < 1 || ny < 1 || nz < 1) return PNS_EINVAL;
+  const int f = 1 << (n_levels - 1);
+  if (nx % f || ny % f || nz % f) return PNS_EINVAL;
   double len[3];
   for (int k = 0; k < 3; ++k) {
     len[k] = mesh->hi[k] - mesh->lo[k];
@@ -427,23 +493,27 @@ int create3d(const pns_mesh* mesh, const pns_discretization* disc, int n_levels,
   c->disc = *disc;
   c->prec = precision;
   c->es = precision == PNS_FP64 ? 8 : 4;
-  c->nlev = 1;
+  c->nlev = n_levels;
   c->stream = (hipStream_t)stream;
   c->g3 = make_grid3(nx, ny, nz, len[0], len[1], len[2]);
-  Level L{};
-  L.g.nx = nx;
-  L.g.ny = ny;
-  L.g.hx = c->g3.hx;
-  L.g.hy = c->g3.hy;
-  L.g.ihx = c->g3.ihx;
-  L.g.ihy = c->g3.ihy;
-  L.g.nn = c->g3.nn;
-  L.g.nc = c->g3.nc;
-  L.g.nv = c->g3.nv;
-  L.g.ns = c->g3.ns;
-  L.g.nst = c->g3.nst;
-  c->lev.push_back(L);
-  c->has_coarse = false;
+  for (int l = 0; l < n_levels; ++l) {
+    Level L{};
+    L.g3 = make_grid3(nx >> l, ny >> l, nz >> l, len[0], len[1], len[2]);
+    L.g.nx = L.g3.nx;
+    L.g.ny = L.g3.ny;
+    L.g.hx = L.g3.hx;
+    L.g.hy = L.g3.hy;
+    L.g.ihx = L.g3.ihx;
+    L.g.ihy = L.g3.ihy;
+    L.g.nn = L.g3.nn;
+    L.g.nc = L.g3.nc;
+    L.g.nv = L.g3.nv;
+    L.g.ns = L.g3.ns;
+    L.g.nst = L.g3.nst;
+    c->lev.push_back(L);
+  }
+  // dense coarsest inverse (and so the V-cycle) with at least two levels
+  c->has_coarse = n_levels >= 2 && c->lev.back().g.nst <= kMaxCoarse;
   *out = c;
   return PNS_OK;
 }
@@ -674,6 +744,8 @@ int pns_vanka_smooth(pns_ctx* ctx, int level, int n_sweeps, double omega, const 
   if (!check_ctx(ctx, true, true)) return ctx_code(ctx, true, true);
   if (level < 0 || level >= ctx->nlev || n_sweeps < 0 || !r || !d || r == d)
     return fail(ctx, PNS_EINVAL, "bad level, sweep count or vectors");
+  if (ctx->dim == 3 && level >= 1 && level == ctx->nlev - 1)
+    return fail(ctx, PNS_EINVAL, "the coarsest 3D level has no patches (dense solve)");
   if (ctx->es == 8)
     PNS_HIP(ctx, smooth<double>(ctx, level, n_sweeps, omega, (const double*)r, (double*)d, false));
   else
@@ -682,7 +754,8 @@ int pns_vanka_smooth(pns_ctx* ctx, int level, int n_sweeps, double omega, const 
 }
 
 int pns_vcycle(pns_ctx* ctx, int nu1, int nu2, double omega, const void* r, void* d) {
-  if (ctx && ctx->dim == 3) return fail(ctx, PNS_EUNSUPPORTED, "3D contexts have no V-cycle");
+  if (ctx && ctx->dim == 3 && ctx->nlev < 2)
+    return fail(ctx, PNS_EUNSUPPORTED, "3D V-cycles need at least two levels");
   if (!check_ctx(ctx, true, true)) return ctx_code(ctx, true, true);
   if (nu1 < 0 || nu2 < 0 || !r || !d || r == d)
     return fail(ctx, PNS_EINVAL, "bad sweep counts or vectors");
@@ -716,7 +789,13 @@ int pns_restrict(pns_ctx* ctx, int level, const void* rf, void* rc) {
     return fail(ctx, PNS_EINVAL, "bad level or vectors");
   const Grid& gf = ctx->lev[level].g;
   const Grid& gc = ctx->lev[level + 1].g;
-  if (ctx->es == 8)
+  if (ctx->dim == 3 && ctx->es == 8)
+    PNS_HIP(ctx, launch_restrict3<double>(ctx->lev[level].g3, ctx->lev[level + 1].g3,
+                                          (const double*)rf, (double*)rc, ctx->stream));
+  else if (ctx->dim == 3)
+    PNS_HIP(ctx, launch_restrict3<float>(ctx->lev[level].g3, ctx->lev[level + 1].g3,
+                                         (const float*)rf, (float*)rc, ctx->stream));
+  else if (ctx->es == 8)
     PNS_HIP(ctx, launch_restrict<double>(gf, gc, (const double*)rf, (double*)rc, ctx->stream));
   else
     PNS_HIP(ctx, launch_restrict<float>(gf, gc, (const float*)rf, (float*)rc, ctx->stream));
@@ -729,7 +808,13 @@ int pns_prolongate_add(pns_ctx* ctx, int level, const void* dc, void* df) {
     return fail(ctx, PNS_EINVAL, "bad level or vectors");
   const Grid& gf = ctx->lev[level].g;
   const Grid& gc = ctx->lev[level + 1].g;
-  if (ctx->es == 8)
+  if (ctx->dim == 3 && ctx->es == 8)
+    PNS_HIP(ctx, launch_prolong_add3<double>(ctx->lev[level].g3, ctx->lev[level + 1].g3,
+                                             (const double*)dc, (double*)df, ctx->stream));
+  else if (ctx->dim == 3)
+    PNS_HIP(ctx, launch_prolong_add3<float>(ctx->lev[level].g3, ctx->lev[level + 1].g3,
+                                            (const float*)dc, (float*)df, ctx->stream));
+  else if (ctx->es == 8)
     PNS_HIP(ctx, launch_prolong_add<double>(gf, gc, (const double*)dc, (double*)df, ctx->stream));
   else
     PNS_HIP(ctx, launch_prolong_add<float>(gf, gc, (const float*)dc, (float*)df, ctx->stream));

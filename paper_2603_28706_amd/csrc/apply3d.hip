@@ -722,6 +722,18 @@ hipError_t launch_cell_apply3d(const Grid3& g, const Model& m, double tau, const
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_gather3(const Grid3& g, const T* E, const T* b, T* y, hipStream_t s) {
+  const int64_t nt = g.nn + g.nc;
+  hipLaunchKernelGGL(gather3_kernel<T>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, g, E,
+                     b, y);
+  return hipGetLastError();
+}
+
+template hipError_t launch_gather3<double>(const Grid3&, const double*, const double*, double*,
+                                           hipStream_t);
+template hipError_t launch_gather3<float>(const Grid3&, const float*, const float*, float*,
+                                          hipStream_t);
 template hipError_t launch_cell_apply3d<double>(const Grid3&, const Model&, double, const double*,
                                                 const double*, const double*, double*, double*,
                                                 int, hipStream_t);

@@ -10,7 +10,8 @@
 namespace pns {
 
 struct Level {
-  Grid g;
+  Grid g;                 // sizes (both dimensions); the quadrilateral mesh in 2D
+  Grid3 g3{};             // the hexahedral mesh of the level (3D contexts)
   double* E64 = nullptr;  // Galerkin element matrices (FP64), levels >= 1 (and 0 if coarsest)
   void* E = nullptr;      // same, transposed per cell, in the context precision
   void* inv = nullptr;    // patch inverses, column-major, context precision (level 0
@@ -34,7 +35,7 @@ int make_model(const pns_model* md, Model* m, std::string* err);
 }  // namespace pns
 
 struct pns_ctx {
-  int dim = 2;         // 3: hexahedra, action only (one level, no smoother or solve)
+  int dim = 2;         // 3: hexahedra (action, smoother and V-cycle; no residual or solve)
   pns::Grid3 g3{};     // the 3D mesh (dim == 3)
   pns_mesh mesh{};
   pns_discretization disc{};
@@ -67,6 +68,7 @@ struct pns_ctx {
   int patch_kind = PNS_PATCH_SURROGATE;  // finest-level patch matrices
   void* tcache = nullptr;  // per-point tangent coefficients of level 0
   void* E3 = nullptr;      // 3D: per-cell results of the action (170 per cell)
+  double* gjscratch3 = nullptr;  // 3D: FP64 elimination copies of the coarse patches
   // patch-sweep variant per level (chosen by timing at pns_vanka_setup) and the
   // measured time of every variant of that level's form
   int sweep_var[16] = {};

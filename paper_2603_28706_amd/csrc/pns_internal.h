@@ -136,6 +136,12 @@ template <typename T>
 hipError_t launch_cell_apply3d(const Grid3& g, const Model& m, double tau, const T* uk,
                                const T* x, const T* b, T* y, T* E, int mode, hipStream_t s);
 
+// y[node, cell rows] = sum of the per-cell slots (170 per cell, layout of the
+// 3D action) of the cells sharing each unknown, fixed order; b != nullptr:
+// y = b - sum
+template <typename T>
+hipError_t launch_gather3(const Grid3& g, const T* E, const T* b, T* y, hipStream_t s);
+
 // smooth3d.hip: finest-level Vanka smoother on hexahedra (surrogate patches in
 // time-diagonal form).  Es: nc * 85 * 85 FP64 spatial cell matrices at the
 // state u; inv: nc complex 85 x 85 inverses (2 * 85 * 85 values per patch,
@@ -149,6 +155,35 @@ hipError_t launch_patches3d(const Grid3& g, double tau, const double* Es, T* inv
 template <typename T>
 hipError_t launch_patch_sweep3(const Grid3& g, const T* inv, const T* res, T* d, double omega,
                                hipStream_t s);
+
+// mg3d.hip: coarse levels on hexahedra.  Space-time cell matrices are 170 x 170
+// (local unknown mu * 85 + spatial), row-major in FP64; Et: transposed per cell
+// in the context precision; scratch: nc * 170 * 170 FP64 for the elimination;
+// inv: nc real 170 x 170 inverses, column-major, colour-major patch order.
+hipError_t launch_galerkin3d_from_fine(const Grid3& gc, const Grid3& gf, double tau,
+                                       const double* Es0, const double* Es1, double* Ec,
+                                       hipStream_t s);
+hipError_t launch_galerkin3d(const Grid3& gc, const Grid3& gf, const double* Ef, double* Ec,
+                             hipStream_t s);
+template <typename T>
+hipError_t launch_transpose_convert3(int64_t ncells, const double* E, T* Et, hipStream_t s);
+template <typename T>
+hipError_t launch_level_patches3d(const Grid3& g, const double* E, double* scratch, T* inv,
+                                  int* status, hipStream_t s);
+// y = A x (b == nullptr) or y = b - A x with the element matrices; S: nc * 170 slots
+template <typename T>
+hipError_t launch_ebe_apply3d(const Grid3& g, const T* Et, const T* x, const T* b, T* y, T* S,
+                              hipStream_t s);
+template <typename T>
+hipError_t launch_patch_sweep3r(const Grid3& g, const T* inv, const T* res, T* d, double omega,
+                                hipStream_t s);
+template <typename T>
+hipError_t launch_restrict3(const Grid3& gf, const Grid3& gc, const T* rf, T* rc, hipStream_t s);
+template <typename T>
+hipError_t launch_prolong_add3(const Grid3& gf, const Grid3& gc, const T* dc, T* df,
+                               hipStream_t s);
+// A (n x n, zeroed by the caller) += the cell matrices E, colour by colour
+hipError_t launch_coarse_assemble3(const Grid3& g, const double* E, double* A, hipStream_t s);
 
 // setup.hip
 hipError_t launch_element_matrices(const Grid& g, const Model& m, const double* u, double* Es,

@@ -27,58 +27,12 @@
 //   colour share no node, so their corrections are added without atomics.
 #include <type_traits>
 
-#include "pns_internal.h"
+#include "hex3.h"
 
 namespace pns {
 namespace {
 
-constexpr int kNb3 = 27;             // Q2 nodes of a hexahedron
-constexpr int kNv3 = 3 * kNb3;       // velocity unknowns of a cell
-constexpr int kNs3 = kNv3 + 4;       // spatial unknowns of a cell (85)
-constexpr int kEs3 = kNs3 * kNs3;    // entries of a spatial cell matrix
 constexpr int kMaxPts = 27 + 6 * 9;  // volume points + face points of a cell
-
-__host__ __device__ inline int64_t cell_index3(const Grid3& g, int cx, int cy, int cz) {
-  return ((int64_t)cz * g.ny + cy) * g.nx + cx;
-}
-
-__device__ __forceinline__ int64_t node_index3(const Grid3& g, int cx, int cy, int cz, int a) {
-  const int64_t NX = 2 * g.nx + 1, NY = 2 * g.ny + 1;
-  return (int64_t)(2 * cx + a % 3) + NX * ((int64_t)(2 * cy + (a / 3) % 3) + NY * (2 * cz + a / 9));
-}
-
-// canonical index of spatial local unknown l of cell (cx,cy,cz) at Radau node mu
-__device__ __forceinline__ int64_t gidx3(const Grid3& g, int cx, int cy, int cz, int l, int mu) {
-  if (l < kNv3) return (int64_t)mu * g.ns + (int64_t)(l / kNb3) * g.nn + node_index3(g, cx, cy, cz, l % kNb3);
-  return (int64_t)mu * g.ns + g.nv + 4 * cell_index3(g, cx, cy, cz) + (l - kNv3);
-}
-
-// Patches of one colour (parity px, py, pz) are stored contiguously, colours
-// in the order c = px + 2 py + 4 pz, lexicographically (x fastest) within.
-__host__ __device__ inline int64_t colour_count3(const Grid3& g, int c) {
-  const int px = c & 1, py = (c >> 1) & 1, pz = c >> 2;
-  return (int64_t)((g.nx - px + 1) / 2) * ((g.ny - py + 1) / 2) * ((g.nz - pz + 1) / 2);
-}
-
-__host__ __device__ inline int64_t patch_slot3(const Grid3& g, int cx, int cy, int cz) {
-  const int c = (cx & 1) + 2 * (cy & 1) + 4 * (cz & 1);
-  int64_t off = 0;
-  for (int k = 0; k < c; ++k) off += colour_count3(g, k);
-  const int64_t ncx = (g.nx - (cx & 1) + 1) / 2, ncy = (g.ny - (cy & 1) + 1) / 2;
-  return off + ((int64_t)(cz >> 1) * ncy + (cy >> 1)) * ncx + (cx >> 1);
-}
-
-// 1D Q2 mass of a cell of unit length (nodes 0, 1/2, 1): [[4,2,-1],[2,16,2],[-1,2,4]] / 30
-__device__ __forceinline__ double mass1(int a, int b) {
-  if (a == 1 && b == 1) return 16.0 / 30.0;
-  if (a == 1 || b == 1) return 2.0 / 30.0;
-  return a == b ? 4.0 / 30.0 : -1.0 / 30.0;
-}
-
-__device__ __forceinline__ double cell_mass3(const Grid3& g, int a, int b) {
-  return mass1(a % 3, b % 3) * g.hx * mass1((a / 3) % 3, (b / 3) % 3) * g.hy *
-         mass1(a / 9, b / 9) * g.hz;
-}
 
 // ------------------------------------------------------------ cell matrices
 

@@ -161,8 +161,8 @@ class Context:
 
     def __init__(self, n, n_levels=1, precision=FP64, tau=0.01, lo=None, hi=None,
                  device="cuda", stream=None):
-        """n: cells per direction, 2 entries (quadrilaterals) or 3 (hexahedra,
-        action only); lo/hi default to the unit square or cube."""
+        """n: cells per direction, 2 entries (quadrilaterals) or 3 (hexahedra:
+        action, smoother and V-cycle); lo/hi default to the unit square or cube."""
         import torch
 
         self.torch = torch

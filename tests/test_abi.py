@@ -33,7 +33,8 @@ def _create(n=(8, 8), levels=1, prec=pnsmg.FP64, tau=0.01, dim=None, k_space=2, 
 def test_create_rejects_bad_configurations():
     assert _create(dim=1)[0] == pnsmg.PNS_EUNSUPPORTED
     assert _create(n=(4, 4, 4), dim=4)[0] == pnsmg.PNS_EUNSUPPORTED
-    assert _create(n=(4, 4, 4), levels=2)[0] == pnsmg.PNS_EUNSUPPORTED  # 3D: one level
+    assert _create(n=(6, 4, 4), levels=3)[0] == pnsmg.PNS_EINVAL  # 6 not divisible by 4
+    assert _create(n=(4, 4, 4), levels=11)[0] == pnsmg.PNS_EINVAL
     assert _create(n=(4, 4, 0))[0] == pnsmg.PNS_EINVAL
     assert _create(n=(4, 4, 4), hi=0.0)[0] == pnsmg.PNS_EINVAL
     assert _create(n=(4, 4, 4), k_time=2)[0] == pnsmg.PNS_EUNSUPPORTED
@@ -105,6 +106,24 @@ def test_3d_context_layout_and_rejections():
                        ctypes.byref(info)) == pnsmg.PNS_EUNSUPPORTED
     assert L.pns_cell_apply(h, v, w) == pnsmg.PNS_EWORKSPACE
     assert L.pns_set_vcycle_graph(h, 1) == pnsmg.PNS_EUNSUPPORTED
+    L.pns_ctx_destroy(h)
+    # three levels 8^3 -> 4^3 -> 2^3: level-0 matrices of both Radau nodes,
+    # Galerkin matrices (FP64 and transposed copies), real inverses of level 1,
+    # one elimination scratch, the dense coarsest inverse
+    rc, h = _create(n=(8, 8, 8), levels=3)
+    assert rc == pnsmg.PNS_OK
+    sizes = []
+    for lev in range(3):
+        assert L.pns_level_sizes(h, lev, out) == 0
+        sizes.append((out[0], out[1]))
+    assert sizes == [(33574, 512), (4886, 64), (814, 8)]
+    kE = 170 * 170
+    need = (2 * 3 * 17 ** 3 * 16 + 512 * 170 * 8 + 3 * 17 ** 3 * 8 + 3 * 512 * 85 * 85 * 8 + 16
+            + 33574 * 8 + 512 * 2 * 85 * 85 * 8
+            + 4886 * 8 * 3 + 64 * kE * 16 + 64 * kE * 8
+            + 814 * 8 * 3 + 8 * kE * 16 + 64 * kE * 8
+            + 814 * 814 * 8 + (2 * 64 * 814 + 814 + 8) * 8 + 814 * 4)
+    assert need <= L.pns_workspace_bytes(h) < need + 8192
     L.pns_ctx_destroy(h)
     # FP32: inverses and defect in single precision
     rc, h = _create(n=(4, 2, 3), prec=pnsmg.FP32)

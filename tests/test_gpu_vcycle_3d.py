@@ -1,0 +1,203 @@
+"""GPU parity of the 3D multigrid hierarchy (hexahedra, Q2 / P1disc x dG(1))
+through the C-ABI against the FP64 oracle: transfers P and P^T, Galerkin
+level operators (element by element on the GPU, sparse triple products in
+the oracle), exact coarse-level Vanka steps, and whole V-cycles (surrogate
+finest patches, exact coarse patches, dense pinned coarsest solve).
+
+Tolerances: transfers and level operators are sums of a few products
+(1e-13 relative); smoother and V-cycle are linear maps through patch and
+coarse solves whose condition numbers on these inputs stay below 1e4, so FP64
+uses 1e-10 and FP32 1e-4, as in 2D.  At 32^3 (the 3D workload, 4 levels) the
+oracle hierarchy is out of reach, so the V-cycle is checked there by
+linearity and as the preconditioner of a GMRES iteration.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2603_28706_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2603_28706_amd import pnsmg  # noqa: E402
+
+MODEL3 = dict(p=1.3, delta=1e-3, nu=1.0, nu_inf=1e-3, gamma1=40.0, gamma2=40.0, sigma_max=1.0,
+              convection=1, qsign=1)
+LIN = pnsmg.MODIFIED_NEWTON
+
+
+def oracle_problem(n, model, lin, tau=0.01, hi=(1.0, 1.0, 1.0)):
+    return O.Problem(n=tuple(n), hi=tuple(hi), tau=tau, p=model["p"], delta=model["delta"],
+                     nu=model["nu"], nu_inf=model["nu_inf"], gamma1=model["gamma1"],
+                     gamma2=model["gamma2"], sigma_max=model["sigma_max"],
+                     convection=model["convection"], qsign=model["qsign"], lin=lin)
+
+
+def to_dev(a, dtype):
+    return torch.as_tensor(np.asarray(a), dtype=dtype, device="cuda").contiguous()
+
+
+def setup(n, levels, precision, uk, hi=(1.0, 1.0, 1.0), model=MODEL3, lin=LIN):
+    ctx = pnsmg.Context(n, n_levels=levels, precision=precision, tau=0.01, hi=hi)
+    ctx.pns_set_state(dict(model, lin=lin), to_dev(uk, torch.float64))
+    ctx.pns_vanka_setup()
+    return ctx
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_transfers_3d():
+    n, hi = (4, 2, 6), (1.0, 0.5, 1.5)
+    fine = oracle_problem(n, MODEL3, LIN, hi=hi)
+    coarse = oracle_problem((2, 1, 3), MODEL3, LIN, hi=hi)
+    P = O.prolongation(coarse, fine)
+    rf = inputs.uniform(601, fine.nst)
+    dc = inputs.uniform(602, coarse.nst)
+    df0 = inputs.uniform(603, fine.nst)
+    ctx = pnsmg.Context(n, n_levels=2, precision=pnsmg.FP64, tau=0.01, hi=hi)
+    rc = ctx.vector(1)
+    ctx.pns_restrict(0, to_dev(rf, torch.float64), rc)
+    df = to_dev(df0, torch.float64)
+    ctx.pns_prolongate_add(0, to_dev(dc, torch.float64), df)
+    torch.cuda.synchronize()
+    assert rel(rc.cpu().numpy(), P.T @ rf) <= 1e-13
+    assert rel(df.cpu().numpy(), df0 + P @ dc) <= 1e-13
+
+
+@pytest.mark.parametrize("n,levels,hi", [((4, 4, 4), 3, (1.0, 1.0, 1.0)),
+                                         ((4, 2, 6), 2, (1.0, 0.5, 1.5))])
+def test_level_operators_and_coarse_sweeps_3d(n, levels, hi):
+    prob = oracle_problem(n, MODEL3, LIN, hi=hi)
+    uk = inputs.sin_series_velocity(n, seed=611, t_nodes=[0.01 / 3, 0.01], hi=hi)
+    H = O.build_hierarchy(prob, uk, n_levels=levels)
+    for prec, dt, tol_op, tol in ((pnsmg.FP64, torch.float64, 1e-13, 1e-10),
+                                  (pnsmg.FP32, torch.float32, 1e-5, 1e-4)):
+        ctx = setup(n, levels, prec, uk, hi=hi)
+        for lev in range(1, levels):
+            k = levels - 1 - lev  # oracle levels run from the coarsest
+            nl = H.probs[k].nst
+            x = inputs.uniform(620 + lev, nl)
+            y = ctx.vector(lev)
+            ctx.pns_level_apply(lev, to_dev(x, dt), y)
+            torch.cuda.synchronize()
+            e_op = rel(y.double().cpu().numpy(), H.A[k] @ x)
+            print(f"3D level {lev} operator prec={prec}: {e_op:.2e}")
+            assert e_op <= tol_op
+            if lev == levels - 1:
+                continue  # the coarsest level has no patches
+            r = inputs.uniform(630 + lev, nl)
+            ref = O.vanka_step(H.A[k], H.patch_mats[k], H.patches[k], r, np.zeros(nl), 0.5)
+            ref = O.vanka_step(H.A[k], H.patch_mats[k], H.patches[k], r, ref, 0.5)
+            d = ctx.vector(lev)
+            ctx.pns_vanka_smooth(lev, 2, 0.5, to_dev(r, dt), d)
+            torch.cuda.synchronize()
+            e_sw = rel(d.double().cpu().numpy(), ref)
+            print(f"3D level {lev} Vanka x2 prec={prec}: {e_sw:.2e}")
+            assert e_sw <= tol
+
+
+@pytest.mark.parametrize("n,levels,hi", [((4, 4, 4), 2, (1.0, 1.0, 1.0)),
+                                         ((4, 4, 4), 3, (1.0, 1.0, 1.0)),
+                                         ((4, 2, 6), 2, (1.0, 0.5, 1.5))])
+def test_vcycle_3d_fp64_and_fp32(n, levels, hi):
+    prob = oracle_problem(n, MODEL3, LIN, hi=hi)
+    uk = inputs.sin_series_velocity(n, seed=641, t_nodes=[0.01 / 3, 0.01], hi=hi)
+    r = inputs.uniform(642, prob.nst)
+    H = O.build_hierarchy(prob, uk, n_levels=levels)
+    ref = O.vcycle(H, r, nu1=2, nu2=2, omega=0.5)
+    for prec, dt, tol in ((pnsmg.FP64, torch.float64, 1e-10), (pnsmg.FP32, torch.float32, 1e-4)):
+        ctx = setup(n, levels, prec, uk, hi=hi)
+        d = ctx.vector()
+        ctx.pns_vcycle(2, 2, 0.5, to_dev(r, dt), d)
+        torch.cuda.synchronize()
+        err = rel(d.double().cpu().numpy(), ref)
+        print(f"3D V-cycle n={n} levels={levels} prec={prec}: {err:.2e}")
+        assert err <= tol
+
+
+def test_vcycle_3d_tangents_and_variants():
+    n = (4, 4, 4)
+    for lin in (pnsmg.PICARD, pnsmg.EXACT_NEWTON):
+        for v in ({}, dict(convection=0, qsign=-1)):
+            model = dict(MODEL3, **v)
+            prob = oracle_problem(n, model, lin)
+            uk = inputs.uniform(651, prob.nt * prob.nv)
+            r = inputs.uniform(652, prob.nst)
+            H = O.build_hierarchy(prob, uk, n_levels=2)
+            ref = O.vcycle(H, r, nu1=1, nu2=2, omega=0.6)
+            ctx = setup(n, 2, pnsmg.FP64, uk, model=model, lin=lin)
+            d = ctx.vector()
+            ctx.pns_vcycle(1, 2, 0.6, to_dev(r, torch.float64), d)
+            torch.cuda.synchronize()
+            err = rel(d.cpu().numpy(), ref)
+            assert err <= 1e-10, (lin, v, err)
+
+
+def gmres_right(apply, precond, b, m):
+    """Right-preconditioned GMRES (FP64, test side): relative residual history."""
+    beta = torch.linalg.norm(b)
+    V = [b / beta]
+    Hh = torch.zeros(m + 1, m, dtype=torch.float64)
+    hist = [1.0]
+    for j in range(m):
+        w = apply(precond(V[j]))
+        for i in range(j + 1):
+            Hh[i, j] = torch.dot(w, V[i]).cpu()
+            w = w - Hh[i, j].item() * V[i]
+        Hh[j + 1, j] = torch.linalg.norm(w).cpu()
+        V.append(w / Hh[j + 1, j].item())
+        e = torch.zeros(j + 2, dtype=torch.float64)
+        e[0] = beta.item()
+        y = torch.linalg.lstsq(Hh[:j + 2, :j + 1], e.unsqueeze(1)).solution
+        hist.append(float(torch.linalg.norm(Hh[:j + 2, :j + 1] @ y - e.unsqueeze(1))) / beta.item())
+    return hist
+
+
+def test_vcycle_3d_32cubed_linear_and_preconditions_gmres():
+    """The 3D workload (32^3, 4 levels, coarsest 4^3): the V-cycle is a linear
+    map (FP64 1e-12, FP32 1e-5) with V(0) = 0; as the right preconditioner of
+    GMRES on J x = J x_true it reaches 1e-6 within 25 iterations (FP64).  The
+    damping is 0.15: each vertex lies in 8 cell patches, and the additive step
+    with 0.5 over-corrects (the oracle's own GMRES stalls near 0.2 on 8^3)."""
+    n = (32, 32, 32)
+    omega = 0.15
+    uk = inputs.sin_series_velocity(n, seed=301, t_nodes=[0.01 / 3, 0.01])
+    for prec, dt, tol in ((pnsmg.FP64, torch.float64, 1e-12), (pnsmg.FP32, torch.float32, 1e-5)):
+        ctx = setup(n, 4, prec, uk)
+        nst = ctx.sizes()["nst"]
+        r1 = to_dev(inputs.uniform(661, nst), dt)
+        r2 = to_dev(inputs.uniform(662, nst), dt)
+        outs = []
+        for r in (r1, r2, 2 * r1 - 3 * r2, torch.zeros_like(r1)):
+            d = ctx.vector()
+            ctx.pns_vcycle(2, 2, omega, r, d)
+            outs.append(d.double())
+        torch.cuda.synchronize()
+        comb = 2 * outs[0] - 3 * outs[1]
+        err = float(torch.linalg.norm(outs[2] - comb) / torch.linalg.norm(comb))
+        print(f"32^3 V-cycle prec={prec}: linearity {err:.2e}")
+        assert err <= tol
+        assert bool(torch.all(outs[3] == 0))
+        if prec == pnsmg.FP64:
+            def apply(x):
+                y = ctx.vector()
+                ctx.pns_cell_apply(x, y)
+                return y
+
+            def precond(r):
+                d = ctx.vector()
+                ctx.pns_vcycle(2, 2, omega, r, d)
+                return d
+
+            b = apply(to_dev(inputs.uniform(663, nst), torch.float64))
+            hist = gmres_right(apply, precond, b, 25)
+            print("32^3 GMRES + V-cycle residuals:", " ".join(f"{h:.1e}" for h in hist[::3]))
+            assert hist[-1] <= 1e-6
+        del ctx
+        torch.cuda.empty_cache()
