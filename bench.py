@@ -17,9 +17,10 @@ the stream the kernels run on around the block of four); FP32 figures, the cache
 V-cycle seconds alongside.  The action's roofline is the FP64 vector ALU
 (its arithmetic intensity, ~14 flop/B, is above the FP64 ridge of ~9.8 flop/B).
 
-Beside the step: the 3D action on 32^3 hexahedra (FP64 and FP32), the slab
-solve's time to 1e-8, the batched finest-level Vanka at 512^2 and the request
-server's latencies, each as a field of its own in the JSON line.
+Beside the step: on 32^3 hexahedra the 3D action, Vanka setup and sweep and
+a 4-level V-cycle (FP64 and FP32); the slab solve's time to 1e-8, the batched
+finest-level Vanka at 512^2 and the request server's latencies, each as a
+field of its own in the JSON line.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256]
        [--levels 4] [--no-cpu] [--apply-only] [--lin 2] [--calib-copy]
@@ -144,14 +145,19 @@ MODEL3D = dict(p=1.3, delta=1e-3, nu=1.0, nu_inf=1e-3, gamma1=40.0, gamma2=40.0,
                convection=1, qsign=1)
 
 
-def apply3d(n=32, reps=50, lin=2, smoother=True, sweeps=20):
+OMEGA3D = 0.15
+
+
+def apply3d(n=32, reps=50, lin=2, smoother=True, sweeps=20, vcycles=10, levels3d=4):
     """3D action on n^3 hexahedra (Q2 / P1disc x dG(1), tau = 0.01) with
     p = 1.3, delta = 1e-3, nu = 1, nu_inf = 1e-3; state: 3D sin-series
     velocity (8 modes, seed 301, O(tau) time variation), input U[-1, 1]
     (seed 302).  Mean duration of `reps` back-to-back actions (HIP events on
     the stream the kernels run on), FP64 and FP32; then the finest-level
-    Vanka smoother: setup wall time and the mean of `sweeps` sweeps (residual
-    U[-1, 1], seed 303, omega = 0.5)."""
+    Vanka smoother: setup wall time (all levels of the `levels3d`-level
+    hierarchy) and the mean of `sweeps` sweeps (residual U[-1, 1], seed 303,
+    omega = 0.5); then the mean of `vcycles` V-cycles (2 + 2 sweeps, omega
+    0.15)."""
     import torch
 
     from paper_2603_28706_amd import inputs, pnsmg
@@ -160,7 +166,7 @@ def apply3d(n=32, reps=50, lin=2, smoother=True, sweeps=20):
                       device="cuda")
     out = {}
     for prec, name in ((pnsmg.FP64, "fp64"), (pnsmg.FP32, "fp32")):
-        ctx = pnsmg.Context((n, n, n), precision=prec)
+        ctx = pnsmg.Context((n, n, n), precision=prec, n_levels=levels3d if smoother else 1)
         ctx.pns_set_state(dict(MODEL3D, lin=lin), uk)
         sz = ctx.sizes()
         x = torch.tensor(inputs.uniform(302, sz["nst"]), dtype=ctx.dtype, device="cuda")
@@ -211,9 +217,24 @@ def apply3d(n=32, reps=50, lin=2, smoother=True, sweeps=20):
             tp = max(ts - t, 1e-9)
             out[name].update(vanka_setup_s=setup_s, sweep_us=ts * 1e6, patch_part_us=tp * 1e6,
                              factor_bytes=factor_bytes, factor_gbs=factor_bytes / tp / 1e9)
-            print(f"[bench] 3D Vanka {n}^3 {name}: setup {setup_s:.3f} s, sweep {ts * 1e6:.1f} us "
-                  f"(patch part {tp * 1e6:.1f} us, {factor_bytes / tp / 1e9:.0f} GB/s on factors)",
-                  file=sys.stderr, flush=True)
+            print(f"[bench] 3D Vanka {n}^3 {name}: setup {setup_s:.3f} s (all {levels3d} levels), "
+                  f"sweep {ts * 1e6:.1f} us (patch part {tp * 1e6:.1f} us, "
+                  f"{factor_bytes / tp / 1e9:.0f} GB/s on factors)", file=sys.stderr, flush=True)
+            # V-cycle over the hierarchy (2 + 2 sweeps, damping 0.15: a vertex lies
+            # in 8 cell patches)
+            for _ in range(2):
+                ctx.pns_vcycle(2, 2, OMEGA3D, r, d)
+            torch.cuda.synchronize()
+            ea.record(stream)
+            for _ in range(vcycles):
+                ctx.pns_vcycle(2, 2, OMEGA3D, r, d)
+            eb.record(stream)
+            torch.cuda.synchronize()
+            tv = ea.elapsed_time(eb) * 1e-3 / vcycles
+            out[name].update(vcycle_ms=tv * 1e3)
+            out["levels"] = levels3d
+            out["omega"] = OMEGA3D
+            print(f"[bench] 3D V-cycle {n}^3 {name}: {tv * 1e3:.3f} ms", file=sys.stderr, flush=True)
         del ctx
         torch.cuda.empty_cache()
     return out

@@ -191,16 +191,20 @@ int pns_cell_defect(pns_ctx* ctx, const void* b_dev, const void* x_dev, void* y_
  * local Q2 node a (a = ax + 3 ay) belongs to that cell's patch; dropped nodes
  * are removed from the patch (uneven patches).  Returns PNS_ESINGULAR if a
  * patch has a zero pivot.
- * 3D contexts (one level): the 85 x 85 spatial cell matrices at the midpoint
+ * 3D contexts: the 85 x 85 spatial cell matrices at the midpoint
  * state are formed in FP64, each cell patch (27 nodes x 3 components + 4
  * pressure coefficients per Radau node, 170 unknowns) is summed from the 27
  * cells around it and inverted in time-diagonal form (one complex 85 x 85
  * Gauss-Jordan inversion with partial pivoting, FP64, stored in the context
- * precision); node_masks must be NULL (PNS_EUNSUPPORTED otherwise). */
+ * precision); coarse levels as above with real 170 x 170 patches (FP64
+ * Gauss-Jordan), the coarsest level without patches; node_masks must be NULL
+ * (PNS_EUNSUPPORTED otherwise). */
 int pns_vanka_setup(pns_ctx* ctx, const uint16_t* node_masks);
 
 /* n_sweeps additive Vanka steps on level `level`, eq. (stmg-vanka-update):
- * d <- d + omega sum_K R_K^T A_K^{-1} R_K (r - A_l d), in place on d. */
+ * d <- d + omega sum_K R_K^T A_K^{-1} R_K (r - A_l d), in place on d.
+ * PNS_EINVAL for the coarsest level of a 3D context with two or more levels
+ * (it holds the dense inverse, no patches). */
 int pns_vanka_smooth(pns_ctx* ctx, int level, int n_sweeps, double omega, const void* r_dev,
                      void* d_dev);
 
@@ -230,7 +234,10 @@ int pns_set_sweep_variant(pns_ctx* ctx, int level, int variant);
 
 /* d = V(r): one V-cycle over all levels (nu1 pre- and nu2 post-smoothing steps
  * from d = 0, restriction P^T, coarsest dense solve, prolongation).
- * PNS_EUNSUPPORTED if the coarsest level exceeds the dense-solve limit. */
+ * PNS_EUNSUPPORTED if the coarsest level exceeds the dense-solve limit, and
+ * on 3D contexts with one level.  On hexahedra each vertex lies in 8 cell
+ * patches; the additive step needs a smaller omega there (about 0.15) than on
+ * quadrilaterals for the V-cycle to precondition well. */
 int pns_vcycle(pns_ctx* ctx, int nu1, int nu2, double omega, const void* r_dev, void* d_dev);
 
 /* enable = 1: pns_vcycle (and so the preconditioner of pns_solve) replays one
