@@ -41,19 +41,21 @@ size_t layout(pns_ctx* c, bool bind) {
   if (c->dim == 3) {  // action, smoother of every level, dense coarsest inverse
     constexpr int64_t kE = 170 * 170;
     c->E3 = take(g0.nc * 170 * es);
+    c->r3u = (double*)take(2 * g0.nv * 8);
+    c->r3b = (double*)take(g0.nst * 8);
+    c->r3slot = (double*)take(g0.nc * 170 * 8);
     c->urep = (double*)take(g0.nv * 8);
     c->Esr = (double*)take(g0.nc * 85 * 85 * 8);
     c->status = (int*)take(sizeof(int) * 4);
-    if (c->nlev >= 2) {
-      c->Es0 = (double*)take(g0.nc * 85 * 85 * 8);
-      c->Es1 = (double*)take(g0.nc * 85 * 85 * 8);
-    }
+    c->Es0 = (double*)take(g0.nc * 85 * 85 * 8);
+    c->Es1 = (double*)take(g0.nc * 85 * 85 * 8);
     for (int l = 0; l < c->nlev; ++l) {
       Level& L = c->lev[l];
       const bool coarsest = l == c->nlev - 1;
       L.res = take(L.g.nst * es);
       if (l == 0) {
-        L.inv = take(L.g.nc * 2 * 85 * 85 * es);  // complex time-diagonal surrogate inverses
+        // complex 85 x 85 time-diagonal surrogate inverses or real 170 x 170 exact ones
+        L.inv = take(L.g.nc * kE * es);
         continue;
       }
       L.E64 = (double*)take(L.g.nc * kE * 8);
@@ -62,7 +64,9 @@ size_t layout(pns_ctx* c, bool bind) {
       L.d = take(L.g.nst * es);
       if (!coarsest) L.inv = take(L.g.nc * kE * es);
     }
-    if (c->nlev >= 3) c->gjscratch3 = (double*)take(c->lev[1].g.nc * kE * 8);
+    // elimination copies of the real patches, one colour at a time (the
+    // largest colour of level 0 bounds every level's)
+    c->gjscratch3 = (double*)take(patch_scratch3_cells(c->lev[0].g3) * kE * 8);
     if (c->has_coarse) {
       const int64_t n = c->lev.back().g.nst;
       c->Adense = (double*)take((size_t)n * n * 8);
@@ -186,7 +190,7 @@ hipError_t smooth(pns_ctx* c, int l, int nsweeps, double omega, const T* r, T* d
       res = (const T*)L.res;
     }
     if (c->dim == 3) {
-      hipError_t e = l == 0
+      hipError_t e = complex_patches(c, l)
                          ? launch_patch_sweep3<T>(L.g3, (const T*)L.inv, res, d, omega, c->stream)
                          : launch_patch_sweep3r<T>(L.g3, (const T*)L.inv, res, d, omega, c->stream);
       if (e != hipSuccess) return e;
@@ -328,11 +332,19 @@ int vanka_setup3d(pns_ctx* c) {
   hipStream_t s = c->stream;
   const Grid3& g0 = c->lev[0].g3;
   PNS_HIP(c, hipMemsetAsync(c->status, 0, sizeof(int), s));
-  PNS_HIP(c, launch_element_matrices3d(g0, c->model, c->urep, c->Esr, s));
-  PNS_HIP(c, launch_patches3d<T>(g0, c->disc.tau, c->Esr, (T*)c->lev[0].inv, c->status, s));
-  if (c->nlev >= 2) {
+  const bool exact = c->patch_kind == PNS_PATCH_EXACT;
+  if (c->nlev >= 2 || exact) {
     PNS_HIP(c, launch_element_matrices3d(g0, c->model, c->uk64, c->Es0, s));
     PNS_HIP(c, launch_element_matrices3d(g0, c->model, c->uk64 + g0.nv, c->Es1, s));
+  }
+  if (exact) {
+    // level 0: exact patches, each Radau node with its own spatial matrices
+    PNS_HIP(c, launch_exact_fine_patches3d<T>(g0, c->disc.tau, c->Es0, c->Es1, c->gjscratch3,
+                                              (T*)c->lev[0].inv, c->status, s));
+  } else {
+    // level 0: surrogate patches, all state-dependent coefficients at t_rep
+    PNS_HIP(c, launch_element_matrices3d(g0, c->model, c->urep, c->Esr, s));
+    PNS_HIP(c, launch_patches3d<T>(g0, c->disc.tau, c->Esr, (T*)c->lev[0].inv, c->status, s));
   }
   for (int l = 1; l < c->nlev; ++l) {
     Level& L = c->lev[l];
@@ -698,8 +710,6 @@ int pns_set_patch_kind(pns_ctx* ctx, int kind) {
   if (!ctx) return PNS_EINVAL;
   if (kind != PNS_PATCH_SURROGATE && kind != PNS_PATCH_EXACT)
     return fail(ctx, PNS_EINVAL, "unknown patch kind");
-  if (ctx->dim == 3 && kind != PNS_PATCH_SURROGATE)
-    return fail(ctx, PNS_EUNSUPPORTED, "3D contexts have surrogate patches only");
   if (kind != ctx->patch_kind) {
     ctx->has_smoother = false;
     ctx->drop_graph();

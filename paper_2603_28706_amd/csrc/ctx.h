@@ -35,7 +35,7 @@ int make_model(const pns_model* md, Model* m, std::string* err);
 }  // namespace pns
 
 struct pns_ctx {
-  int dim = 2;         // 3: hexahedra (action, smoother and V-cycle; no residual or solve)
+  int dim = 2;         // 3: hexahedra
   pns::Grid3 g3{};     // the 3D mesh (dim == 3)
   pns_mesh mesh{};
   pns_discretization disc{};
@@ -69,6 +69,10 @@ struct pns_ctx {
   void* tcache = nullptr;  // per-point tangent coefficients of level 0
   void* E3 = nullptr;      // 3D: per-cell results of the action (170 per cell)
   double* gjscratch3 = nullptr;  // 3D: FP64 elimination copies of the coarse patches
+  // 3D FP64 residual: state copy, left-trace term, per-cell slots of the action
+  double* r3u = nullptr;
+  double* r3b = nullptr;
+  double* r3slot = nullptr;
   // patch-sweep variant per level (chosen by timing at pns_vanka_setup) and the
   // measured time of every variant of that level's form
   int sweep_var[16] = {};

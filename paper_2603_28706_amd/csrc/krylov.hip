@@ -57,6 +57,48 @@ __global__ __launch_bounds__(kBlock) void mass_kernel(Grid g, double tau, const 
   y[id] = tw * s;
 }
 
+// Hexahedra: y_mu = c_mu (M_x x_v,mu ; pscale M_p x_p,mu), Q2 mass = tensor
+// product of three 1D masses, P1disc mass per cell |K| diag(1, 1/12, 1/12, 1/12).
+// c_mu = tau w_mu, pscale = 1 gives the block mass of the time step; c = m_t,
+// pscale = 0 the left-trace coupling of the residual.
+__global__ __launch_bounds__(kBlock) void mass3_kernel(Grid3 g, double c0, double c1, double pscale,
+                                                       const double* __restrict__ x,
+                                                       double* __restrict__ y) {
+  const int64_t id = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (id >= g.nst) return;
+  const int mu = (int)(id / g.ns);
+  const int64_t r = id - (int64_t)mu * g.ns;
+  const double cw = mu ? c1 : c0;
+  if (r >= g.nv) {
+    const int j = (int)((r - g.nv) % 4);
+    y[id] = cw * pscale * g.hx * g.hy * g.hz * (j == 0 ? 1.0 : 1.0 / 12.0) * x[id];
+    return;
+  }
+  const int NX = 2 * g.nx + 1, NY = 2 * g.ny + 1, NZ = 2 * g.nz + 1;
+  const int64_t node = r % g.nn;
+  const int gx = (int)(node % NX), gy = (int)((node / NX) % NY), gz = (int)(node / ((int64_t)NX * NY));
+  const double* xb = x + (id - node);
+  double s = 0.0;
+  for (int dz = -2; dz <= 2; ++dz) {
+    const double mz = mass1d(gz, gz + dz, NZ, g.hz);
+    if (mz == 0.0) continue;
+    double sy = 0.0;
+    for (int dy = -2; dy <= 2; ++dy) {
+      const double my = mass1d(gy, gy + dy, NY, g.hy);
+      if (my == 0.0) continue;
+      double t = 0.0;
+#pragma unroll
+      for (int dx = -2; dx <= 2; ++dx) {
+        const double mx = mass1d(gx, gx + dx, NX, g.hx);
+        if (mx != 0.0) t += mx * xb[((int64_t)(gz + dz) * NY + gy + dy) * NX + gx + dx];
+      }
+      sy += my * t;
+    }
+    s += mz * sy;
+  }
+  y[id] = cw * s;
+}
+
 // partial[i * kDotBlocks + b] = sum over block b's chunk of V_i . u, i < k
 __global__ __launch_bounds__(kBlock) void multi_dot_kernel(int64_t n, int k, const double* __restrict__ V,
                                                            int64_t ldv, const double* __restrict__ u,
@@ -144,6 +186,12 @@ int dot_partials() { return kDotBlocks; }
 
 hipError_t launch_mass(const Grid& g, double tau, const double* x, double* y, hipStream_t s) {
   hipLaunchKernelGGL(mass_kernel, grid_for(g.nst), dim3(kBlock), 0, s, g, tau, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_mass3(const Grid3& g, double c0, double c1, double pscale, const double* x,
+                        double* y, hipStream_t s) {
+  hipLaunchKernelGGL(mass3_kernel, grid_for(g.nst), dim3(kBlock), 0, s, g, c0, c1, pscale, x, y);
   return hipGetLastError();
 }
 

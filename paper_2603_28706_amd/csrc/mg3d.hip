@@ -6,12 +6,15 @@
 //   interpolation per Radau node and velocity component, one 4 x 4 P1disc
 //   restriction per Radau node), so one workgroup forms one block of E_C
 //   (row group x column group) over the 8 children;
-// * patch3r_kernel: exact coarse patches R_K A_l R_K^T (sums of the stored
-//   element matrices of the cells around the patch), inverted by Gauss-Jordan
-//   with partial row pivoting in FP64; the 170 x 170 matrix is larger than the
-//   LDS of a CU, so each workgroup eliminates in a scratch copy in global
-//   memory (L2 / Infinity-Cache resident) and writes the inverse in the
-//   context precision;
+// * patch3r_kernel: exact patches R_K A_l R_K^T (sums of the element matrices
+//   of the cells around the patch: stored Galerkin matrices on coarse levels,
+//   or on the finest level K_t (x) M + tau M_t (x) diag(J_1, J_2) formed from
+//   the spatial matrices of both Radau nodes), inverted by Gauss-Jordan with
+//   partial row pivoting in FP64; the 170 x 170 matrix is larger than the LDS
+//   of a CU, so each workgroup eliminates in a scratch copy in global memory
+//   (L2 / Infinity-Cache resident), one colour per launch so that the scratch
+//   holds one colour's patches, and writes the inverse in the context
+//   precision;
 // * ebe3_kernel: the level operator element by element, y_K = E_K x_K into the
 //   per-cell slots, summed per unknown by the gather of the 3D action;
 // * patch_sweep3r_kernel: additive Vanka step with the real coarse inverses,
@@ -132,27 +135,31 @@ __global__ void transpose_convert3_kernel(int64_t ncells, const double* __restri
 
 constexpr int kPT = 512;
 
-template <typename T>
-__global__ __launch_bounds__(kPT) void patch3r_kernel(Grid3 g, const double* __restrict__ E,
-                                                      double* __restrict__ W,
-                                                      T* __restrict__ inv, int* status) {
+// one colour (cell parity px, py, pz) per launch; workgroup pid eliminates in
+// scratch slice pid, so the scratch holds one colour's patches
+template <typename T, typename Src>
+__global__ __launch_bounds__(kPT) void patch3r_kernel(Grid3 g, Src Esrc, double* __restrict__ W,
+                                                      T* __restrict__ inv, int* status, int px,
+                                                      int py, int pz, int ncx, int ncy) {
   __shared__ double rk[kNst3], fk[kNst3];
   __shared__ int piv[kNst3], src[kNst3];
   __shared__ double s_pv, s_kk;
   __shared__ int s_p, s_sing;
-  const int64_t K = blockIdx.x;
-  const int cx = (int)(K % g.nx), cy = (int)((K / g.nx) % g.ny),
-            cz = (int)(K / ((int64_t)g.nx * g.ny));
+  const int64_t pid = blockIdx.x;
+  const int cx = px + 2 * (int)(pid % ncx);
+  const int cy = py + 2 * (int)((pid / ncx) % ncy);
+  const int cz = pz + 2 * (int)(pid / ((int64_t)ncx * ncy));
+  const int64_t K = cell_index3(g, cx, cy, cz);
   const int cc[3] = {cx, cy, cz}, nc[3] = {g.nx, g.ny, g.nz};
   const int t = threadIdx.x;
-  double* A = W + K * kE3;
+  double* A = W + pid * kE3;
   if (t == 0) s_sing = 0;
   for (int e = t; e < kE3; e += kPT) {
     const int r = e / kNst3, c = e % kNst3;
     const int mr = r / kNs3, sr = r % kNs3, mc = c / kNs3, sc = c % kNs3;
     double v = 0.0;
     if (sr >= kNv3 || sc >= kNv3) {
-      v = E[K * kE3 + e];  // the cell's own pressure lives in this cell only
+      v = Esrc(K, r, c);  // the cell's own pressure lives in this cell only
     } else {
       const int a = sr % kNb3, b = sc % kNb3;
       const int pa[3] = {a % 3, (a / 3) % 3, a / 9}, pb[3] = {b % 3, (b / 3) % 3, b / 9};
@@ -173,7 +180,7 @@ __global__ __launch_bounds__(kPT) void patch3r_kernel(Grid3 g, const double* __r
               st *= 3;
             }
             const int64_t nbc = cell_index3(g, cx + ox, cy + oy, cz + oz);
-            v += E[nbc * kE3 + (rbase + na) * kNst3 + cbase + nb];
+            v += Esrc(nbc, rbase + na, cbase + nb);
           }
     }
     A[e] = v;
@@ -482,12 +489,34 @@ hipError_t launch_transpose_convert3(int64_t ncells, const double* E, T* Et, hip
   return hipGetLastError();
 }
 
+namespace {
+template <typename T, typename Src>
+hipError_t patches3r_by_colour(const Grid3& g, Src src, double* scratch, T* inv, int* status,
+                               hipStream_t s) {
+  for (int c = 0; c < 8; ++c) {
+    const int px = c & 1, py = (c >> 1) & 1, pz = c >> 2;
+    const int64_t np = colour_count3(g, c);
+    if (np == 0) continue;
+    hipLaunchKernelGGL((patch3r_kernel<T, Src>), dim3((unsigned)np), dim3(kPT), 0, s, g, src,
+                       scratch, inv, status, px, py, pz, (g.nx - px + 1) / 2, (g.ny - py + 1) / 2);
+  }
+  return hipGetLastError();
+}
+}  // namespace
+
+int64_t patch_scratch3_cells(const Grid3& g) { return colour_count3(g, 0); }
+
 template <typename T>
 hipError_t launch_level_patches3d(const Grid3& g, const double* E, double* scratch, T* inv,
                                   int* status, hipStream_t s) {
-  hipLaunchKernelGGL(patch3r_kernel<T>, dim3((unsigned)g.nc), dim3(kPT), 0, s, g, E, scratch, inv,
-                     status);
-  return hipGetLastError();
+  return patches3r_by_colour<T>(g, StoredSrc3{E}, scratch, inv, status, s);
+}
+
+template <typename T>
+hipError_t launch_exact_fine_patches3d(const Grid3& g, double tau, const double* Es0,
+                                       const double* Es1, double* scratch, T* inv, int* status,
+                                       hipStream_t s) {
+  return patches3r_by_colour<T>(g, FineSrc3{g, tau, Es0, Es1}, scratch, inv, status, s);
 }
 
 template <typename T>
@@ -543,6 +572,9 @@ hipError_t launch_coarse_assemble3(const Grid3& g, const double* E, double* A, h
   template hipError_t launch_transpose_convert3<T>(int64_t, const double*, T*, hipStream_t);    \
   template hipError_t launch_level_patches3d<T>(const Grid3&, const double*, double*, T*, int*, \
                                                 hipStream_t);                                   \
+  template hipError_t launch_exact_fine_patches3d<T>(const Grid3&, double, const double*,       \
+                                                     const double*, double*, T*, int*,          \
+                                                     hipStream_t);                              \
   template hipError_t launch_ebe_apply3d<T>(const Grid3&, const T*, const T*, const T*, T*, T*, \
                                             hipStream_t);                                       \
   template hipError_t launch_patch_sweep3r<T>(const Grid3&, const T*, const T*, T*, double,     \

@@ -71,6 +71,34 @@ size_t work_layout(const pns_ctx* c, int m, char* base, Work* w) {
   return (off + kAlign - 1) / kAlign * kAlign;
 }
 
+// Hexahedra: the FP64 slab residual from the fixed-point form of the Picard
+// linearisation.  With the state taken at U itself (tangent eta(DU) I,
+// advecting field U, inflow factor (U.n)^- at U) the Picard operator applied
+// to U reproduces every term of the nonlinear form, so
+//   R(U) = [m_t (x) M_x v_prev ; 0] - J_Picard(U) U,
+// one FP64 3D action in defect mode with b = the left-trace term.
+int residual3d(pns_ctx* c, const Model& m, const double* U, const double* vprev, double* R) {
+  const Level& L = c->lev[0];
+  const Grid3& g = L.g3;
+  hipStream_t s = c->stream;
+  if (vprev) {
+    // stage (v_prev, 0, v_prev, 0) in R, then b = (m_t[0] M v, 0, m_t[1] M v, 0)
+    PNS_HIP(c, launch_fill<double>(g.nst, 0.0, R, s));
+    PNS_HIP(c, launch_copy<double>(g.nv, vprev, R, s));
+    PNS_HIP(c, launch_copy<double>(g.nv, vprev, R + g.ns, s));
+    PNS_HIP(c, launch_mass3(g, 1.5, -0.5, 0.0, R, c->r3b, s));
+  } else {
+    PNS_HIP(c, launch_fill<double>(g.nst, 0.0, c->r3b, s));
+  }
+  PNS_HIP(c, hipMemcpyAsync(c->r3u, U, g.nv * 8, hipMemcpyDeviceToDevice, s));
+  PNS_HIP(c, hipMemcpyAsync(c->r3u + g.nv, U + g.ns, g.nv * 8, hipMemcpyDeviceToDevice, s));
+  Model mp = m;
+  mp.lin = PNS_PICARD;
+  PNS_HIP(c, launch_cell_apply3d<double>(g, mp, c->disc.tau, c->r3u, U, c->r3b, R, c->r3slot, 1,
+                                         s));
+  return PNS_OK;
+}
+
 struct Solver {
   pns_ctx* c;
   const pns_model* md;
@@ -82,8 +110,16 @@ struct Solver {
   pns_solve_params prm;
 
   // ||x||_M; h[0] receives x . M x
+  // W.Mw = M x, the block mass of the time step (the inner product of FGMRES)
+  hipError_t mass(const double* x) {
+    if (c->dim == 3)
+      return launch_mass3(c->lev[0].g3, c->disc.tau * kWt[0], c->disc.tau * kWt[1], 1.0, x, W.Mw,
+                          s);
+    return launch_mass(g, c->disc.tau, x, W.Mw, s);
+  }
+
   int mnorm(const double* x, double* out) {
-    PNS_HIP(c, launch_mass(g, c->disc.tau, x, W.Mw, s));
+    PNS_HIP(c, mass(x));
     PNS_HIP(c, launch_multi_dot(W.n, 1, x, W.n, W.Mw, W.part, W.h, s));
     double v = 0.0;
     PNS_HIP(c, hipMemcpyAsync(&v, W.h, 8, hipMemcpyDeviceToHost, s));
@@ -93,6 +129,7 @@ struct Solver {
   }
 
   int residual(const double* U, double* R) {
+    if (c->dim == 3) return residual3d(c, model, U, vprev, R);
     PNS_HIP(c, launch_residual(g, model, c->disc.tau, U, vprev, R, s));
     return PNS_OK;
   }
@@ -156,7 +193,7 @@ struct Solver {
         if ((rc = jacobian(zj, W.w)) != PNS_OK) return rc;
         // classical Gram-Schmidt in the M inner product, twice
         for (int pass = 0; pass < 2; ++pass) {
-          PNS_HIP(c, launch_mass(g, c->disc.tau, W.w, W.Mw, s));
+          PNS_HIP(c, mass(W.w));
           PNS_HIP(c, launch_multi_dot(n, j + 1, W.V, n, W.Mw, W.part, W.h, s));
           PNS_HIP(c, launch_combine(n, j + 1, W.V, n, W.h, -1.0, 1.0, W.w, s));
           PNS_HIP(c, hipMemcpyAsync(hv.data(), W.h, (j + 1) * 8, hipMemcpyDeviceToHost, s));
@@ -218,18 +255,18 @@ extern "C" {
 int pns_residual(pns_ctx* ctx, const pns_model* md, const double* U, const double* vprev,
                  double* R) {
   if (!ctx) return PNS_EINVAL;
-  if (ctx->dim == 3) return fail(ctx, PNS_EUNSUPPORTED, "3D contexts have the action only");
   if (!ctx->ws) return fail(ctx, PNS_EWORKSPACE, "no workspace bound");
   if (!md || !U || !R || U == R) return fail(ctx, PNS_EINVAL, "NULL model or vectors, or U == R");
   Model m;
   const int rc = make_model(md, &m, &ctx->err);
   if (rc != PNS_OK) return rc;
+  if (ctx->dim == 3) return residual3d(ctx, m, U, vprev, R);
   PNS_HIP(ctx, launch_residual(ctx->lev[0].g, m, ctx->disc.tau, U, vprev, R, ctx->stream));
   return PNS_OK;
 }
 
 size_t pns_solve_workspace_bytes(const pns_ctx* ctx, int restart) {
-  if (!ctx || ctx->dim == 3 || restart < 1 || restart > kMaxRestart) return 0;
+  if (!ctx || restart < 1 || restart > kMaxRestart) return 0;
   return work_layout(ctx, restart, nullptr, nullptr);
 }
 
@@ -237,7 +274,6 @@ int pns_solve(pns_ctx* ctx, const pns_model* md, const double* vprev, double* U,
               const pns_solve_params* prm, void* work, size_t work_bytes, pns_solve_info* info) {
   if (!ctx) return PNS_EINVAL;
   if (info) std::memset(info, 0, sizeof(*info));
-  if (ctx->dim == 3) return fail(ctx, PNS_EUNSUPPORTED, "3D contexts have the action only");
   if (!ctx->ws) return fail(ctx, PNS_EWORKSPACE, "no workspace bound");
   if (!md || !U || !prm) return fail(ctx, PNS_EINVAL, "NULL model, U or parameters");
   if (prm->restart < 1 || prm->restart > kMaxRestart || prm->max_newton < 1 ||
@@ -342,7 +378,6 @@ int pns_march(pns_ctx* ctx, const pns_model* md, double* v, int n_slabs, double*
               const pns_solve_params* prm, void* work, size_t work_bytes, pns_solve_info* info) {
   if (!ctx) return PNS_EINVAL;
   if (info) std::memset(info, 0, sizeof(*info));
-  if (ctx->dim == 3) return fail(ctx, PNS_EUNSUPPORTED, "3D contexts have the action only");
   if (!md || !v || !U || !prm || n_slabs < 0 || (const void*)v == (const void*)U)
     return fail(ctx, PNS_EINVAL, "NULL model, vectors or parameters, or n_slabs < 0");
   if (!ctx->ws) return fail(ctx, PNS_EWORKSPACE, "no workspace bound");

@@ -72,8 +72,9 @@ def test_3d_context_layout_and_rejections():
     """A hexahedral context: unknown counts of Q2^3 / P1disc x dG(1); the
     workspace holds the state, the per-cell results of the action and the
     finest-level smoother (midpoint state, FP64 cell matrices, complex 85 x 85
-    patch inverses, defect); V-cycle, residual and solve entry points and
-    exact or truncated patches are rejected before any device work."""
+    patch inverses, defect) and the FP64 residual's buffers; a one-level
+    V-cycle and exact or truncated patches are rejected before any device
+    work."""
     rc, h = _create(n=(32, 32, 32))
     assert rc == pnsmg.PNS_OK
     L = pnsmg.lib()
@@ -85,13 +86,19 @@ def test_3d_context_layout_and_rejections():
     assert L.pns_level_sizes(h, 1, out) == pnsmg.PNS_EINVAL
     nbytes = L.pns_workspace_bytes(h)
     es = 8
-    need = (2 * nv * (es + 8) + 32768 * 170 * es + nv * 8 + 32768 * 85 * 85 * 8 + 16
-            + 32768 * 2 * 85 * 85 * es + nst * es)
+    kE = 170 * 170
+    # state, action slots, residual buffers, midpoint state, three sets of
+    # spatial cell matrices, defect, patch inverses (room for the real exact
+    # form), one colour of elimination copies (16^3 cells)
+    need = (2 * nv * (es + 8) + 32768 * 170 * es + 2 * nv * 8 + nst * 8 + 32768 * 170 * 8
+            + nv * 8 + 3 * 32768 * 85 * 85 * 8 + 16 + nst * es + 32768 * kE * es
+            + 16 ** 3 * kE * 8)
     assert need <= nbytes < need + 4096
-    assert L.pns_solve_workspace_bytes(h, 30) == 0
+    # FGMRES(30) vectors: 31 + 30 Krylov vectors and 6 work vectors of N_st FP64
+    assert L.pns_solve_workspace_bytes(h, 30) >= (61 + 6) * nst * 8
     assert L.pns_set_apply_mode(h, pnsmg.APPLY_CACHED) == pnsmg.PNS_EUNSUPPORTED
     assert L.pns_set_apply_mode(h, pnsmg.APPLY_RECOMPUTE) == pnsmg.PNS_OK
-    assert L.pns_set_patch_kind(h, pnsmg.PATCH_EXACT) == pnsmg.PNS_EUNSUPPORTED
+    assert L.pns_set_patch_kind(h, pnsmg.PATCH_EXACT) == pnsmg.PNS_OK
     assert L.pns_set_patch_kind(h, pnsmg.PATCH_SURROGATE) == pnsmg.PNS_OK
     v = ctypes.c_void_p(4096)
     w = ctypes.c_void_p(8192)
@@ -100,10 +107,10 @@ def test_3d_context_layout_and_rejections():
     assert L.pns_vcycle(h, 1, 1, ctypes.c_double(0.1), v, w) == pnsmg.PNS_EUNSUPPORTED
     model = pnsmg.model_struct(dict(p=1.3, delta=1e-3, nu=1.0, nu_inf=1e-4, gamma1=40.0,
                                     gamma2=40.0, sigma_max=1.0, convection=1, qsign=1, lin=2))
-    assert L.pns_residual(h, ctypes.byref(model), v, None, w) == pnsmg.PNS_EUNSUPPORTED
+    assert L.pns_residual(h, ctypes.byref(model), v, None, w) == pnsmg.PNS_EWORKSPACE
     info = pnsmg.pns_solve_info()
     assert L.pns_solve(h, ctypes.byref(model), v, w, None, None, 0,
-                       ctypes.byref(info)) == pnsmg.PNS_EUNSUPPORTED
+                       ctypes.byref(info)) == pnsmg.PNS_EWORKSPACE
     assert L.pns_cell_apply(h, v, w) == pnsmg.PNS_EWORKSPACE
     assert L.pns_set_vcycle_graph(h, 1) == pnsmg.PNS_EUNSUPPORTED
     L.pns_ctx_destroy(h)
@@ -119,7 +126,8 @@ def test_3d_context_layout_and_rejections():
     assert sizes == [(33574, 512), (4886, 64), (814, 8)]
     kE = 170 * 170
     need = (2 * 3 * 17 ** 3 * 16 + 512 * 170 * 8 + 3 * 17 ** 3 * 8 + 3 * 512 * 85 * 85 * 8 + 16
-            + 33574 * 8 + 512 * 2 * 85 * 85 * 8
+            + 2 * 3 * 17 ** 3 * 8 + 33574 * 8 + 512 * 170 * 8
+            + 33574 * 8 + 512 * kE * 8
             + 4886 * 8 * 3 + 64 * kE * 16 + 64 * kE * 8
             + 814 * 8 * 3 + 8 * kE * 16 + 64 * kE * 8
             + 814 * 814 * 8 + (2 * 64 * 814 + 814 + 8) * 8 + 814 * 4)
@@ -131,8 +139,9 @@ def test_3d_context_layout_and_rejections():
     nn = 9 * 5 * 7
     nc = 24
     nst = 2 * (3 * nn + 4 * nc)
-    need = (2 * 3 * nn * (4 + 8) + nc * 170 * 4 + 3 * nn * 8 + nc * 85 * 85 * 8 + 16
-            + nc * 2 * 85 * 85 * 4 + nst * 4)
+    need = (2 * 3 * nn * (4 + 8) + nc * 170 * 4 + 3 * nn * 8 + 3 * nc * 85 * 85 * 8 + 16
+            + nc * 170 * 170 * 4 + nst * 4 + 2 * 3 * nn * 8 + nst * 8 + nc * 170 * 8
+            + 2 * 1 * 2 * 170 * 170 * 8)
     assert need <= L.pns_workspace_bytes(h) < need + 4096
     L.pns_ctx_destroy(h)
 
@@ -175,9 +184,9 @@ def test_march_rejects_bad_arguments():
     assert L.pns_march(h, ctypes.byref(model), v, 1, U, ctypes.byref(prm), None, 0,
                        ctypes.byref(info)) == pnsmg.PNS_EWORKSPACE
     L.pns_ctx_destroy(h)
-    rc, h = _create((2, 2, 2))
+    rc, h = _create((2, 2, 2), 2)  # 3D: same checks, no workspace bound yet
     assert L.pns_march(h, ctypes.byref(model), v, 1, U, ctypes.byref(prm), None, 0,
-                       ctypes.byref(info)) == pnsmg.PNS_EUNSUPPORTED
+                       ctypes.byref(info)) == pnsmg.PNS_EWORKSPACE
     L.pns_ctx_destroy(h)
 
 

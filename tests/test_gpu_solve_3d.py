@@ -1,0 +1,155 @@
+"""GPU parity of the slab solve on hexahedra (Sec. 5.3) through the C-ABI: the
+FP64 residual against the oracle's, and the Newton-Krylov solve (FGMRES with
+the 3D V-cycle) against the oracle's Newton solution.
+
+The GPU's 3D residual is the Picard action at U applied to U plus the
+left-trace term (the fixed-point form, pinned in the oracle's 3D tests); the
+oracle assembles the nonlinear forms directly.  Tolerances as in 2D: residual
+1e-12 relative per velocity / pressure block; a solve must meet its stopping
+test by the oracle's own residual (5 % slack) and agree with the oracle
+solution to 1e-6 after removing the pressure constant of each Radau node.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2603_28706_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_2603_28706_amd import pnsmg  # noqa: E402
+
+MODEL3 = dict(p=1.3, delta=1e-3, nu=1.0, nu_inf=1e-3, gamma1=40.0, gamma2=40.0, sigma_max=1.0,
+              convection=1, qsign=1)
+OMEGA3 = 0.15
+
+
+def oracle_problem(n, model, lin=pnsmg.MODIFIED_NEWTON, tau=0.01, hi=(1.0, 1.0, 1.0)):
+    return O.Problem(n=tuple(n), hi=tuple(hi), tau=tau, p=model["p"], delta=model["delta"],
+                     nu=model["nu"], nu_inf=model["nu_inf"], gamma1=model["gamma1"],
+                     gamma2=model["gamma2"], sigma_max=model["sigma_max"],
+                     convection=model["convection"], qsign=model["qsign"], lin=lin)
+
+
+def dev(a):
+    return torch.as_tensor(np.asarray(a), dtype=torch.float64, device="cuda").contiguous()
+
+
+def blocks(prob):
+    vel = np.concatenate([np.arange(m * prob.ns, m * prob.ns + prob.nv) for m in range(prob.nt)])
+    pre = np.concatenate([np.arange(m * prob.ns + prob.nv, (m + 1) * prob.ns)
+                          for m in range(prob.nt)])
+    return vel, pre
+
+
+def without_pressure_constant(prob, U):
+    U = np.array(U, dtype=np.float64)
+    for m in range(prob.nt):
+        sl = slice(m * prob.ns + prob.nv, (m + 1) * prob.ns, 4)
+        U[sl] -= U[sl].mean()
+    return U
+
+
+@pytest.mark.parametrize("n,hi,variant", [
+    ((2, 2, 2), (1.0, 1.0, 1.0), {}),
+    ((3, 2, 4), (1.0, 2.0, 0.5), {}),
+    ((2, 3, 2), (1.0, 1.0, 1.0), dict(convection=0)),
+    ((3, 3, 2), (1.0, 1.0, 1.0), dict(qsign=-1, p=1.8, delta=1e-2)),
+    ((1, 1, 1), (1.0, 1.0, 1.0), {}),
+])
+def test_residual3d_fp64(n, hi, variant):
+    model = dict(MODEL3, **variant)
+    prob = oracle_problem(n, model, hi=hi)
+    U = inputs.uniform(701, prob.nst)
+    vprev = inputs.uniform(702, prob.nv)
+    for prec in (pnsmg.FP64, pnsmg.FP32):  # the residual is FP64 in both contexts
+        ctx = pnsmg.Context(n, n_levels=1, precision=prec, hi=hi)
+        for vp in (vprev, None):
+            ref = O.residual(prob, U, vp)
+            R = torch.zeros(prob.nst, dtype=torch.float64, device="cuda")
+            ctx.pns_residual(model, dev(U), None if vp is None else dev(vp), R)
+            torch.cuda.synchronize()
+            got = R.cpu().numpy()
+            for idx in blocks(prob):
+                err = np.linalg.norm(got[idx] - ref[idx]) / np.linalg.norm(ref[idx])
+                assert err <= 1e-12, (n, variant, prec, vp is None, err)
+
+
+@pytest.mark.parametrize("precision", [pnsmg.FP64, pnsmg.FP32])
+@pytest.mark.parametrize("n", [(2, 2, 2), (4, 2, 2)])
+def test_solve3d_reaches_the_oracle_solution(n, precision):
+    model = dict(MODEL3)
+    prob = oracle_problem(n, model)
+    vprev = inputs.sin_series_velocity(n, seed=301, t_nodes=[0.0])
+    rtol = 1e-10
+    ctx = pnsmg.Context(n, n_levels=2, precision=precision)
+    U = dev(O.state_from_velocity(prob, np.concatenate([vprev, vprev])))
+    rc, info = ctx.pns_solve(model, dev(vprev), U, rtol=rtol, omega=OMEGA3)
+    torch.cuda.synchronize()
+    U = U.cpu().numpy()
+    print(f"3D solve {n} prec {precision}: {info}")
+    assert rc == pnsmg.PNS_OK
+    ref = O.newton_solve(prob, vprev, rtol=1e-13)
+    assert info["residual_initial"] == pytest.approx(ref.residual_norms[0], rel=1e-12)
+    r_gpu = O.mass_norm(prob, O.residual(prob, U, vprev))
+    assert r_gpu <= 1.05 * rtol * ref.residual_norms[0]
+    a = without_pressure_constant(prob, U)
+    b = without_pressure_constant(prob, ref.U)
+    for idx in blocks(prob):
+        err = np.linalg.norm(a[idx] - b[idx]) / np.linalg.norm(b[idx])
+        print(f"  block rel err {err:.2e}")
+        assert err <= 1e-6
+    assert info["newton_iterations"] >= 1 and info["smoother_setups"] >= 1
+
+
+def test_solve3d_exact_patches_small():
+    n = (4, 2, 2)
+    model = dict(MODEL3)
+    prob = oracle_problem(n, model)
+    vprev = inputs.sin_series_velocity(n, seed=302, t_nodes=[0.0])
+    rtol = 1e-10
+    ctx = pnsmg.Context(n, n_levels=2, precision=pnsmg.FP64)
+    ctx.pns_set_patch_kind(pnsmg.PATCH_EXACT)
+    U = dev(O.state_from_velocity(prob, np.concatenate([vprev, vprev])))
+    rc, info = ctx.pns_solve(model, dev(vprev), U, rtol=rtol, omega=OMEGA3)
+    torch.cuda.synchronize()
+    print(f"3D solve exact patches {n}: {info}")
+    assert rc == pnsmg.PNS_OK
+    ref = O.newton_solve(prob, vprev, rtol=1e-13)
+    r_gpu = O.mass_norm(prob, O.residual(prob, U.cpu().numpy(), vprev))
+    assert r_gpu <= 1.05 * rtol * ref.residual_norms[0]
+
+
+def test_solve3d_32cubed_to_1e8():
+    """The 3D workload (32^3, 4 levels, exact finest patches): FP64 and mixed
+    precision reach ||R||_M <= 1e-8 ||R(U^0)||_M, and the FP64 residual of the
+    final iterate, re-evaluated through the ABI, is finite.  The clipped
+    tangent (sigma_max = 1 clips the rank-one term to ~40 % on this field)
+    converges linearly, ~0.55 per Newton step, hence up to 60 steps.  (With
+    midpoint-frozen finest patches the preconditioner stalls from the third
+    Newton step on: the two Radau velocities of an iterate differ by ~45 %
+    here, far from the O(tau) variation the surrogate assumes.)"""
+    n = (32, 32, 32)
+    vprev = inputs.sin_series_velocity(n, seed=301, t_nodes=[0.0])
+    for prec in (pnsmg.FP64, pnsmg.FP32):
+        ctx = pnsmg.Context(n, n_levels=4, precision=prec)
+        ctx.pns_set_patch_kind(pnsmg.PATCH_EXACT)
+        sz = ctx.sizes()
+        U = torch.zeros(sz["nst"], dtype=torch.float64, device="cuda")
+        vp = dev(vprev)
+        U[:sz["nv"]] = vp
+        U[sz["ns"]:sz["ns"] + sz["nv"]] = vp
+        rc, info = ctx.pns_solve(MODEL3, vp, U, rtol=1e-8, omega=OMEGA3, max_newton=60)
+        print(f"32^3 solve prec {prec}: {info}")
+        assert rc == pnsmg.PNS_OK
+        assert info["residual_final"] <= 1e-8 * info["residual_initial"]
+        R = torch.zeros_like(U)
+        ctx.pns_residual(MODEL3, U, vp, R)
+        torch.cuda.synchronize()
+        assert torch.isfinite(R).all()
+        del ctx
+        torch.cuda.empty_cache()

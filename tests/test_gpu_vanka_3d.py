@@ -184,3 +184,34 @@ def test_vanka3d_32cubed_sampled_rows():
         assert err <= tol * scale
         del ctx
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n,hi", [((2, 2, 2), (1.0, 1.0, 1.0)), ((3, 2, 4), (1.0, 2.0, 0.5))])
+def test_vanka3d_exact_patches(n, hi):
+    """Exact finest-level patches (each Radau node with its own state, real
+    170 x 170 FP64 Gauss-Jordan) against the oracle's restriction of the
+    exact slab operator; random state, so the two Radau nodes differ."""
+    lin = pnsmg.MODIFIED_NEWTON
+    prob = oracle_problem(n, MODEL3, lin, hi=hi)
+    uk = inputs.uniform(531, prob.nt * prob.nv)
+    r = inputs.uniform(532, prob.nst)
+    A = O.assemble_slab(prob, O.split_uk(prob, uk))
+    patches = O.all_patches(prob)
+    pm = O.patch_matrices(A, patches)
+    ref1 = O.vanka_step(A, pm, patches, r, np.zeros(prob.nst), 0.5)
+    ref2 = O.vanka_step(A, pm, patches, r, ref1, 0.5)
+    for prec, dt, tol in ((pnsmg.FP64, torch.float64, 1e-10), (pnsmg.FP32, torch.float32, 1e-4)):
+        ctx = pnsmg.Context(n, n_levels=1, precision=prec, tau=0.01, hi=hi)
+        ctx.pns_set_patch_kind(pnsmg.PATCH_EXACT)
+        ctx.pns_set_state(dict(MODEL3, lin=lin), to_dev(uk, torch.float64))
+        ctx.pns_vanka_setup()
+        d = ctx.vector()
+        rd = to_dev(r, dt)
+        ctx.pns_vanka_smooth(0, 1, 0.5, rd, d)
+        torch.cuda.synchronize()
+        e1 = np.linalg.norm(d.double().cpu().numpy() - ref1) / np.linalg.norm(ref1)
+        ctx.pns_vanka_smooth(0, 1, 0.5, rd, d)
+        torch.cuda.synchronize()
+        e2 = np.linalg.norm(d.double().cpu().numpy() - ref2) / np.linalg.norm(ref2)
+        print(f"3D exact-patch vanka n={n} prec={prec}: {e1:.2e}, {e2:.2e}")
+        assert e1 <= tol and e2 <= tol

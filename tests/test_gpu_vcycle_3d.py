@@ -139,6 +139,26 @@ def test_vcycle_3d_tangents_and_variants():
             assert err <= 1e-10, (lin, v, err)
 
 
+def test_vcycle_3d_exact_fine_patches():
+    n = (4, 4, 4)
+    prob = oracle_problem(n, MODEL3, LIN)
+    uk = inputs.uniform(671, prob.nt * prob.nv)
+    r = inputs.uniform(672, prob.nst)
+    H = O.build_hierarchy(prob, uk, n_levels=2, surrogate=False)
+    ref = O.vcycle(H, r, nu1=2, nu2=2, omega=0.15)
+    for prec, dt, tol in ((pnsmg.FP64, torch.float64, 1e-10), (pnsmg.FP32, torch.float32, 1e-4)):
+        ctx = pnsmg.Context(n, n_levels=2, precision=prec, tau=0.01)
+        ctx.pns_set_patch_kind(pnsmg.PATCH_EXACT)
+        ctx.pns_set_state(dict(MODEL3, lin=LIN), to_dev(uk, torch.float64))
+        ctx.pns_vanka_setup()
+        d = ctx.vector()
+        ctx.pns_vcycle(2, 2, 0.15, to_dev(r, dt), d)
+        torch.cuda.synchronize()
+        err = rel(d.double().cpu().numpy(), ref)
+        print(f"3D V-cycle exact fine patches prec={prec}: {err:.2e}")
+        assert err <= tol
+
+
 def gmres_right(apply, precond, b, m):
     """Right-preconditioned GMRES (FP64, test side): relative residual history."""
     beta = torch.linalg.norm(b)

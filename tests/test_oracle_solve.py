@@ -49,6 +49,29 @@ def test_mass_norm_of_a_quadratic_field_is_its_l2_norm():
     assert O.mass_norm(prob, r) ** 2 == pytest.approx(prob.tau * w0 / 90.0, rel=1e-12)
 
 
+def test_mass_norm_closed_forms_3d():
+    prob = O.Problem(n=(2, 3, 2), hi=(2.0, 0.5, 1.5), tau=0.02)
+    vol = 2.0 * 0.5 * 1.5
+    w0, w1 = O.radau_right(1)[1]
+    nn = prob.num_nodes
+    # constant velocity component 2 (value 3) at both Radau nodes
+    r = np.zeros(prob.nst)
+    for m in range(prob.nt):
+        r[m * prob.ns + 2 * nn:m * prob.ns + 3 * nn] = 3.0
+    assert O.mass_norm(prob, r) ** 2 == pytest.approx(prob.tau * vol * 9.0, rel=1e-13)
+    # the z-slope pressure coefficient at the second node: |K| / 12 per cell
+    r = np.zeros(prob.nst)
+    r[prob.ns + prob.nv + 3:2 * prob.ns:4] = 1.0
+    assert O.mass_norm(prob, r) ** 2 == pytest.approx(prob.tau * w1 * vol / 12.0, rel=1e-13)
+    # u_1 = x y (1.5 - z) z is triquadratic, represented exactly:
+    # int u^2 = (8/3) (1/24) (1.5^5 / 30) over [0,2] x [0,0.5] x [0,1.5]
+    x, y, z = inputs.node_coordinates(prob.n, prob.lo, prob.hi)
+    r = np.zeros(prob.nst)
+    r[nn:2 * nn] = x * y * (1.5 - z) * z
+    exact = (8.0 / 3.0) * (0.125 / 3.0) * (1.5 ** 5 / 30.0)
+    assert O.mass_norm(prob, r) ** 2 == pytest.approx(prob.tau * w0 * exact, rel=1e-12)
+
+
 def test_zero_data_gives_zero_solution_without_steps():
     prob = O.Problem(n=N)
     res = O.newton_solve(prob, np.zeros(prob.nv))
