@@ -17,8 +17,9 @@ the stream the kernels run on around the block of four); FP32 figures, the cache
 V-cycle seconds alongside.  The action's roofline is the FP64 vector ALU
 (its arithmetic intensity, ~14 flop/B, is above the FP64 ridge of ~9.8 flop/B).
 
-Beside the step: on 32^3 hexahedra the 3D action, Vanka setup and sweep and
-a 4-level V-cycle (FP64 and FP32); the slab solve's time to 1e-8, the batched
+Beside the step: on 32^3 hexahedra the 3D action, Vanka setup and sweep, a
+4-level V-cycle and the 3D slab solve's time to 1e-8 (FP64 and FP32 / mixed);
+the 2D slab solve's time to 1e-8, the batched
 finest-level Vanka at 512^2 and the request server's latencies, each as a
 field of its own in the JSON line.
 
@@ -414,6 +415,41 @@ def solve_latency(n, seeds, rtol=1e-8):
     return out
 
 
+def solve3d_latency(n=32, rtol=1e-8, max_newton=60):
+    """Time to rtol of the 3D slab solve on n^3 hexahedra (the 3D workload:
+    p = 1.3, delta = 1e-3, nu = 1, nu_inf = 1e-3, modified Newton, left trace
+    = 3D sin-series velocity, seed 301), 4-level V-cycle (coarsest n/8 cubed)
+    with exact finest-level patches (the two Radau velocities of the iterates
+    differ by O(1) in this regime, where midpoint-frozen patches stall the
+    Krylov solves) and damping 0.15; FP64 and mixed precision."""
+    import torch
+
+    from paper_2603_28706_amd import inputs, pnsmg
+
+    model = dict(MODEL3D, lin=2)
+    vprev = torch.tensor(inputs.sin_series_velocity((n, n, n), seed=301, t_nodes=[0.0]),
+                         device="cuda")
+    out = {}
+    for prec, name in ((pnsmg.FP64, "fp64"), (pnsmg.FP32, "mixed")):
+        ctx = pnsmg.Context((n, n, n), n_levels=4, precision=prec)
+        ctx.pns_set_patch_kind(pnsmg.PATCH_EXACT)
+        sz = ctx.sizes()
+        U = torch.zeros(sz["nst"], dtype=torch.float64, device="cuda")
+        U[:sz["nv"]] = vprev
+        U[sz["ns"]:sz["ns"] + sz["nv"]] = vprev
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, info = ctx.pns_solve(model, vprev, U, rtol=rtol, omega=OMEGA3D, max_newton=max_newton)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out[name] = dict(time_s=t, converged=bool(rc == pnsmg.PNS_OK), **info)
+        print(f"[bench] 3D solve {n}^3 {name}: {t:.2f} s, rc {rc}, {info}", file=sys.stderr,
+              flush=True)
+        del ctx
+        torch.cuda.empty_cache()
+    return out
+
+
 def serve_latency(n_req=256, rate=20.0, slots=4, seed=501):
     """Poisson stream of independent slab-solve requests through the native
     request server: meshes from {32^2, 64^2, 128^2, 256^2}, p ~ U[1.6, 1.9],
@@ -619,6 +655,15 @@ def main():
                          f"nu_inf=1e-3, modified-Newton Jacobian action, 3D sin-series state"),
             **{k: ({kk: round(vv, 4) for kk, vv in v.items()} if isinstance(v, dict) else v)
                for k, v in a3.items()}}
+    if args.apply3d_n and not args.apply_only:
+        s3 = solve3d_latency(args.apply3d_n)
+        line["solve3d_time_to_1e-8_s"] = {
+            "workload": (f"3D {args.apply3d_n}^3 slab solve, p=1.3 delta=1e-3 nu0=1 nu_inf=1e-3, "
+                         f"modified Newton + FGMRES(30) / 4-level V-cycle (exact finest "
+                         f"patches, omega 0.15) to ||R||_M <= 1e-8 ||R0||_M"),
+            **{k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+               for k, v in s3.items()},
+            "mixed_speedup": round(s3["fp64"]["time_s"] / s3["mixed"]["time_s"], 3)}
     if args.solve_n and not args.apply_only:
         sl = solve_latency(args.solve_n, SOLVE_SEEDS)
         line["solve_time_to_1e-8_s"] = {

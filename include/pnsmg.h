@@ -124,12 +124,11 @@ typedef struct pns_ctx pns_ctx;
  * (and so pns_vcycle) is available when the coarsest level has at most 40000
  * space-time unknowns; larger coarsest levels still allow the apply and the
  * smoother.  `stream` is a hipStream_t (NULL =
- * default stream).  A dim = 3 mesh gives a one-level context: n_levels must
- * be 1; pns_set_state, pns_cell_apply, pns_cell_defect, the size and
- * workspace queries and the finest-level smoother (pns_vanka_setup without
- * node masks, pns_vanka_smooth on level 0, surrogate patches) work; the
- * V-cycle, residual and solve entry points return PNS_EUNSUPPORTED and
- * pns_solve_workspace_bytes returns 0.
+ * default stream).  A dim = 3 mesh (hexahedra, n_cells divisible by
+ * 2^(n_levels-1) in every direction) supports every entry point below except
+ * node masks in pns_vanka_setup and graph replay (pns_set_vcycle_graph);
+ * pns_vcycle and pns_solve need at least two levels (the dense coarsest
+ * inverse is formed only then).
  * Returns PNS_EINVAL / PNS_EUNSUPPORTED on bad input. */
 int pns_ctx_create(const pns_mesh* mesh, const pns_discretization* disc, int n_levels,
                    int precision, void* stream, pns_ctx** out);
@@ -165,8 +164,10 @@ int pns_set_apply_mode(pns_ctx* ctx, int mode);
 
 /* Select the finest-level patch matrices (default PNS_PATCH_SURROGATE); a
  * change takes effect at the next pns_vanka_setup (until then the context has
- * no smoother).  PNS_EINVAL for an unknown kind; PNS_EUNSUPPORTED for
- * PNS_PATCH_EXACT on a 3D context. */
+ * no smoother).  PNS_EINVAL for an unknown kind.  PNS_PATCH_EXACT restricts
+ * the exact slab operator (each Radau node with its own state); on hexahedra
+ * it is needed when the velocity varies by O(1) across the slab, where the
+ * midpoint-frozen surrogate stops preconditioning. */
 int pns_set_patch_kind(pns_ctx* ctx, int kind);
 
 /* y = J_n(u_k) x on level 0, eq. (slab-underint-jac): the temporal mass
@@ -196,8 +197,9 @@ int pns_cell_defect(pns_ctx* ctx, const void* b_dev, const void* x_dev, void* y_
  * pressure coefficients per Radau node, 170 unknowns) is summed from the 27
  * cells around it and inverted in time-diagonal form (one complex 85 x 85
  * Gauss-Jordan inversion with partial pivoting, FP64, stored in the context
- * precision); coarse levels as above with real 170 x 170 patches (FP64
- * Gauss-Jordan), the coarsest level without patches; node_masks must be NULL
+ * precision), or with PNS_PATCH_EXACT real 170 x 170 patches of the exact
+ * operator (FP64 Gauss-Jordan); coarse levels as above with real 170 x 170
+ * patches, the coarsest level without patches; node_masks must be NULL
  * (PNS_EUNSUPPORTED otherwise). */
 int pns_vanka_setup(pns_ctx* ctx, const uint16_t* node_masks);
 
@@ -273,7 +275,10 @@ int pns_prolongate_add(pns_ctx* ctx, int level, const void* dc_dev, void* df_dev
  * U_dev, R_dev: FP64 device vectors, canonical layout of level 0, must not
  * alias.  v_prev_dev: FP64 device vector of the left-trace velocity
  * (component 0 over the Q2 nodes, then component 1), or NULL for zero.
- * Needs a bound workspace, not a state.  Asynchronous on the context stream. */
+ * Needs a bound workspace, not a state.  Asynchronous on the context stream.
+ * Hexahedra: v_prev holds 3 components; R is evaluated as the Picard
+ * linearisation at U applied to U (which reproduces every nonlinear term of
+ * A_gamma, the inflow factor included) plus the left-trace term, in FP64. */
 int pns_residual(pns_ctx* ctx, const pns_model* model, const double* U_dev,
                  const double* v_prev_dev, double* R_dev);
 
