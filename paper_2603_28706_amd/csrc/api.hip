@@ -64,9 +64,6 @@ size_t layout(pns_ctx* c, bool bind) {
       L.d = take(L.g.nst * es);
       if (!coarsest) L.inv = take(L.g.nc * kE * es);
     }
-    // elimination copies of the real patches, one colour at a time (the
-    // largest colour of level 0 bounds every level's)
-    c->gjscratch3 = (double*)take(patch_scratch3_cells(c->lev[0].g3) * kE * 8);
     if (c->has_coarse) {
       const int64_t n = c->lev.back().g.nst;
       c->Adense = (double*)take((size_t)n * n * 8);
@@ -339,7 +336,7 @@ int vanka_setup3d(pns_ctx* c) {
   }
   if (exact) {
     // level 0: exact patches, each Radau node with its own spatial matrices
-    PNS_HIP(c, launch_exact_fine_patches3d<T>(g0, c->disc.tau, c->Es0, c->Es1, c->gjscratch3,
+    PNS_HIP(c, launch_exact_fine_patches3d<T>(g0, c->disc.tau, c->Es0, c->Es1,
                                               (T*)c->lev[0].inv, c->status, s));
   } else {
     // level 0: surrogate patches, all state-dependent coefficients at t_rep
@@ -354,7 +351,7 @@ int vanka_setup3d(pns_ctx* c) {
       PNS_HIP(c, launch_galerkin3d(L.g3, c->lev[l - 1].g3, c->lev[l - 1].E64, L.E64, s));
     PNS_HIP(c, launch_transpose_convert3<T>(L.g.nc, L.E64, (T*)L.E, s));
     if (l < c->nlev - 1)
-      PNS_HIP(c, launch_level_patches3d<T>(L.g3, L.E64, c->gjscratch3, (T*)L.inv, c->status, s));
+      PNS_HIP(c, launch_level_patches3d<T>(L.g3, L.E64, (T*)L.inv, c->status, s));
   }
   int st = 0;
   if (c->has_coarse) {

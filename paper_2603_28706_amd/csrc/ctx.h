@@ -68,7 +68,6 @@ struct pns_ctx {
   int patch_kind = PNS_PATCH_SURROGATE;  // finest-level patch matrices
   void* tcache = nullptr;  // per-point tangent coefficients of level 0
   void* E3 = nullptr;      // 3D: per-cell results of the action (170 per cell)
-  double* gjscratch3 = nullptr;  // 3D: FP64 elimination copies of the coarse patches
   // 3D FP64 residual: state copy, left-trace term, per-cell slots of the action
   double* r3u = nullptr;
   double* r3b = nullptr;

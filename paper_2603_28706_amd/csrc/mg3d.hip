@@ -10,11 +10,10 @@
 //   of the cells around the patch: stored Galerkin matrices on coarse levels,
 //   or on the finest level K_t (x) M + tau M_t (x) diag(J_1, J_2) formed from
 //   the spatial matrices of both Radau nodes), inverted by Gauss-Jordan with
-//   partial row pivoting in FP64; the 170 x 170 matrix is larger than the LDS
-//   of a CU, so each workgroup eliminates in a scratch copy in global memory
-//   (L2 / Infinity-Cache resident), one colour per launch so that the scratch
-//   holds one colour's patches, and writes the inverse in the context
-//   precision;
+//   partial row pivoting in FP64; the 170 x 170 matrix (231 KB) is larger than
+//   the LDS of a CU but fits in the registers of a 1024-thread workgroup, which
+//   holds it there (29 entries per thread) and exchanges only the pivot row and
+//   column through LDS; the inverse is written in the context precision;
 // * ebe3_kernel: the level operator element by element, y_K = E_K x_K into the
 //   per-cell slots, summed per unknown by the gather of the 3D action;
 // * patch_sweep3r_kernel: additive Vanka step with the real coarse inverses,
@@ -134,16 +133,23 @@ __global__ void transpose_convert3_kernel(int64_t ncells, const double* __restri
 // ------------------------------------------------------------- patches
 
 constexpr int kPT = 512;
+// register-resident Gauss-Jordan: 6 threads per row, each holding 29 entries
+// (columns part, part + 6, ...) of one row of the 170 x 170 FP64 matrix
+constexpr int kRP = 6;
+constexpr int kRS = (kNst3 + kRP - 1) / kRP;  // 29
+constexpr int kRT = kNst3 * kRP;               // 1020 working threads
 
-// one colour (cell parity px, py, pz) per launch; workgroup pid eliminates in
-// scratch slice pid, so the scratch holds one colour's patches
+// One workgroup of 1024 threads per patch (one colour per launch).  The matrix
+// lives in registers (58 VGPRs per thread); each pivot step exchanges only
+// column k, rows k and p and the new pivot row through LDS, so a step costs
+// five barriers and O(170) LDS traffic.
 template <typename T, typename Src>
-__global__ __launch_bounds__(kPT) void patch3r_kernel(Grid3 g, Src Esrc, double* __restrict__ W,
-                                                      T* __restrict__ inv, int* status, int px,
-                                                      int py, int pz, int ncx, int ncy) {
-  __shared__ double rk[kNst3], fk[kNst3];
-  __shared__ int piv[kNst3], src[kNst3];
-  __shared__ double s_pv, s_kk;
+__global__ __launch_bounds__(1024) void patch3r_kernel(Grid3 g, Src Esrc, T* __restrict__ inv,
+                                                       int* status, int px, int py, int pz,
+                                                       int ncx, int ncy) {
+  __shared__ double colv[kNst3], rowk[kNst3], rowp[kNst3], rowb[kNst3], fk[kNst3];
+  __shared__ int piv[kNst3], dst[kNst3], srcc[kNst3];
+  __shared__ double s_pv;
   __shared__ int s_p, s_sing;
   const int64_t pid = blockIdx.x;
   const int cx = px + 2 * (int)(pid % ncx);
@@ -152,49 +158,65 @@ __global__ __launch_bounds__(kPT) void patch3r_kernel(Grid3 g, Src Esrc, double*
   const int64_t K = cell_index3(g, cx, cy, cz);
   const int cc[3] = {cx, cy, cz}, nc[3] = {g.nx, g.ny, g.nz};
   const int t = threadIdx.x;
-  double* A = W + pid * kE3;
+  const bool active = t < kRT;
+  const int i = t % kNst3, part = t / kNst3;  // row i, columns part + 6 s
   if (t == 0) s_sing = 0;
-  for (int e = t; e < kE3; e += kPT) {
-    const int r = e / kNst3, c = e % kNst3;
-    const int mr = r / kNs3, sr = r % kNs3, mc = c / kNs3, sc = c % kNs3;
+  double a[kRS];
+#pragma unroll
+  for (int s = 0; s < kRS; ++s) a[s] = 0.0;
+  // assembly: entry (i, j) sums the cells that hold both unknowns (a rolled
+  // loop; each value is moved into its register by a select chain)
+  const int mr = i / kNs3, sr = i % kNs3;
+#pragma unroll 1
+  for (int s = 0; s < kRS; ++s) {
+    const int j = part + kRP * s;
     double v = 0.0;
-    if (sr >= kNv3 || sc >= kNv3) {
-      v = Esrc(K, r, c);  // the cell's own pressure lives in this cell only
-    } else {
-      const int a = sr % kNb3, b = sc % kNb3;
-      const int pa[3] = {a % 3, (a / 3) % 3, a / 9}, pb[3] = {b % 3, (b / 3) % 3, b / 9};
-      int lo[3], hi[3];
-      for (int k = 0; k < 3; ++k) {
-        lo[k] = (pa[k] == 0 && pb[k] == 0 && cc[k] > 0) ? -1 : 0;
-        hi[k] = (pa[k] == 2 && pb[k] == 2 && cc[k] < nc[k] - 1) ? 1 : 0;
-      }
-      const int rbase = mr * kNs3 + (sr / kNb3) * kNb3, cbase = mc * kNs3 + (sc / kNb3) * kNb3;
-      for (int oz = lo[2]; oz <= hi[2]; ++oz)
-        for (int oy = lo[1]; oy <= hi[1]; ++oy)
-          for (int ox = lo[0]; ox <= hi[0]; ++ox) {
-            const int o[3] = {ox, oy, oz};
-            int na = 0, nb = 0, st = 1;
-            for (int k = 0; k < 3; ++k) {
-              na += (pa[k] - 2 * o[k]) * st;
-              nb += (pb[k] - 2 * o[k]) * st;
-              st *= 3;
+    if (active && j < kNst3) {
+      const int mc = j / kNs3, sc = j % kNs3;
+      if (sr >= kNv3 || sc >= kNv3) {
+        v = Esrc(K, i, j);  // the cell's own pressure lives in this cell only
+      } else {
+        const int ea = sr % kNb3, eb = sc % kNb3;
+        const int pa[3] = {ea % 3, (ea / 3) % 3, ea / 9}, pb[3] = {eb % 3, (eb / 3) % 3, eb / 9};
+        int lo[3], hi[3];
+        for (int k = 0; k < 3; ++k) {
+          lo[k] = (pa[k] == 0 && pb[k] == 0 && cc[k] > 0) ? -1 : 0;
+          hi[k] = (pa[k] == 2 && pb[k] == 2 && cc[k] < nc[k] - 1) ? 1 : 0;
+        }
+        const int rbase = mr * kNs3 + (sr / kNb3) * kNb3, cbase = mc * kNs3 + (sc / kNb3) * kNb3;
+        for (int oz = lo[2]; oz <= hi[2]; ++oz)
+          for (int oy = lo[1]; oy <= hi[1]; ++oy)
+            for (int ox = lo[0]; ox <= hi[0]; ++ox) {
+              const int na = (pa[0] - 2 * ox) + 3 * (pa[1] - 2 * oy) + 9 * (pa[2] - 2 * oz);
+              const int nb = (pb[0] - 2 * ox) + 3 * (pb[1] - 2 * oy) + 9 * (pb[2] - 2 * oz);
+              v += Esrc(cell_index3(g, cx + ox, cy + oy, cz + oz), rbase + na, cbase + nb);
             }
-            const int64_t nbc = cell_index3(g, cx + ox, cy + oy, cz + oz);
-            v += Esrc(nbc, rbase + na, cbase + nb);
-          }
+      }
     }
-    A[e] = v;
+#pragma unroll
+    for (int q = 0; q < kRS; ++q)
+      if (q == s) a[q] = v;
   }
-  __syncthreads();
   for (int k = 0; k < kNst3; ++k) {
+    const int ks = k / kRP, kp = k % kRP;
+    // column k to LDS
+    if (active && part == kp) {
+      double v = 0.0;
+#pragma unroll
+      for (int s = 0; s < kRS; ++s)
+        if (s == ks) v = a[s];
+      colv[i] = v;
+    }
+    __syncthreads();
+    // pivot: largest |a_ik| over i >= k (ties to the smaller row)
     if (t < 64) {
       double bv = -1.0;
       int bi = k;
-      for (int i = k + t; i < kNst3; i += 64) {
-        const double v = fabs(A[i * kNst3 + k]);
+      for (int r = k + t; r < kNst3; r += 64) {
+        const double v = fabs(colv[r]);
         if (v > bv) {
           bv = v;
-          bi = i;
+          bi = r;
         }
       }
       for (int off = 32; off > 0; off >>= 1) {
@@ -212,57 +234,76 @@ __global__ __launch_bounds__(kPT) void patch3r_kernel(Grid3 g, Src Esrc, double*
           s_sing = 1;
           s_pv = 1.0;
         } else {
-          s_pv = A[bi * kNst3 + k];
+          s_pv = colv[bi];
         }
-        s_kk = A[k * kNst3 + k];
       }
     }
     __syncthreads();
     const int p = s_p;
     const double dinv = 1.0 / s_pv;
+    // rows k and p as they are
+    if (active && (i == k || i == p)) {
+#pragma unroll
+      for (int s = 0; s < kRS; ++s) {
+        const int j = part + kRP * s;
+        if (j < kNst3) {
+          if (i == k) rowk[j] = a[s];
+          if (i == p) rowp[j] = a[s];
+        }
+      }
+    }
+    __syncthreads();
+    // new row k (old row p scaled, its pivot entry becomes 1 / pivot) and the
+    // elimination factors (column k after the interchange, zero on row k)
     if (t < kNst3) {
-      // swap rows k and p; scale the new row k (its pivot entry becomes 1 / pivot)
-      const int j = t;
-      const double kv = A[k * kNst3 + j];
-      double xv = A[p * kNst3 + j];
-      if (p != k) A[p * kNst3 + j] = kv;
-      if (j == k) xv = 1.0;
-      const double y = xv * dinv;
-      A[k * kNst3 + j] = y;
-      rk[j] = y;
+      rowb[t] = (t == k ? 1.0 : rowp[t]) * dinv;
     } else if (t >= 256 && t < 256 + kNst3) {
-      // elimination factors: column k after the row swap, zero on row k
-      const int i = t - 256;
-      double f = 0.0;
-      if (i == p && p != k)
-        f = s_kk;
-      else if (i != k)
-        f = A[i * kNst3 + k];
-      fk[i] = f;
+      const int r = t - 256;
+      fk[r] = r == k ? 0.0 : (r == p ? rowk[k] : colv[r]);
     }
     __syncthreads();
-    for (int e = t; e < kE3; e += kPT) {
-      const int i = e / kNst3, j = e % kNst3;
-      if (i == k) continue;
-      const double a = j == k ? 0.0 : A[e];
-      A[e] = a - fk[i] * rk[j];
+    if (active) {
+      if (i == k) {
+#pragma unroll
+        for (int s = 0; s < kRS; ++s) {
+          const int j = part + kRP * s;
+          if (j < kNst3) a[s] = rowb[j];
+        }
+      } else {
+        const double f = fk[i];
+        const bool isp = i == p;
+#pragma unroll
+        for (int s = 0; s < kRS; ++s) {
+          const int j = part + kRP * s;
+          if (j < kNst3) {
+            double v = isp ? rowk[j] : a[s];
+            if (j == k) v = 0.0;
+            a[s] = v - f * rowb[j];
+          }
+        }
+      }
     }
-    __syncthreads();
   }
+  // the row interchanges become column interchanges of the inverse, applied
+  // in reverse order: column dst[j] of the inverse is column j of the result
   if (t == 0) {
-    for (int j = 0; j < kNst3; ++j) src[j] = j;
+    for (int j = 0; j < kNst3; ++j) srcc[j] = j;
     for (int k = kNst3 - 1; k >= 0; --k) {
-      const int tmp = src[k];
-      src[k] = src[piv[k]];
-      src[piv[k]] = tmp;
+      const int tmp = srcc[k];
+      srcc[k] = srcc[piv[k]];
+      srcc[piv[k]] = tmp;
     }
+    for (int c = 0; c < kNst3; ++c) dst[srcc[c]] = c;
     if (s_sing) atomicOr(status, 1);
   }
   __syncthreads();
   T* out = inv + patch_slot3(g, cx, cy, cz) * kE3;
-  for (int e = t; e < kE3; e += kPT) {
-    const int c = e / kNst3, r = e % kNst3;
-    out[e] = (T)A[r * kNst3 + src[c]];
+  if (active) {
+#pragma unroll
+    for (int s = 0; s < kRS; ++s) {
+      const int j = part + kRP * s;
+      if (j < kNst3) out[dst[j] * kNst3 + i] = (T)a[s];
+    }
   }
 }
 
@@ -491,32 +532,28 @@ hipError_t launch_transpose_convert3(int64_t ncells, const double* E, T* Et, hip
 
 namespace {
 template <typename T, typename Src>
-hipError_t patches3r_by_colour(const Grid3& g, Src src, double* scratch, T* inv, int* status,
-                               hipStream_t s) {
+hipError_t patches3r_by_colour(const Grid3& g, Src src, T* inv, int* status, hipStream_t s) {
   for (int c = 0; c < 8; ++c) {
     const int px = c & 1, py = (c >> 1) & 1, pz = c >> 2;
     const int64_t np = colour_count3(g, c);
     if (np == 0) continue;
-    hipLaunchKernelGGL((patch3r_kernel<T, Src>), dim3((unsigned)np), dim3(kPT), 0, s, g, src,
-                       scratch, inv, status, px, py, pz, (g.nx - px + 1) / 2, (g.ny - py + 1) / 2);
+    hipLaunchKernelGGL((patch3r_kernel<T, Src>), dim3((unsigned)np), dim3(1024), 0, s, g, src, inv,
+                       status, px, py, pz, (g.nx - px + 1) / 2, (g.ny - py + 1) / 2);
   }
   return hipGetLastError();
 }
 }  // namespace
 
-int64_t patch_scratch3_cells(const Grid3& g) { return colour_count3(g, 0); }
-
 template <typename T>
-hipError_t launch_level_patches3d(const Grid3& g, const double* E, double* scratch, T* inv,
-                                  int* status, hipStream_t s) {
-  return patches3r_by_colour<T>(g, StoredSrc3{E}, scratch, inv, status, s);
+hipError_t launch_level_patches3d(const Grid3& g, const double* E, T* inv, int* status,
+                                  hipStream_t s) {
+  return patches3r_by_colour<T>(g, StoredSrc3{E}, inv, status, s);
 }
 
 template <typename T>
 hipError_t launch_exact_fine_patches3d(const Grid3& g, double tau, const double* Es0,
-                                       const double* Es1, double* scratch, T* inv, int* status,
-                                       hipStream_t s) {
-  return patches3r_by_colour<T>(g, FineSrc3{g, tau, Es0, Es1}, scratch, inv, status, s);
+                                       const double* Es1, T* inv, int* status, hipStream_t s) {
+  return patches3r_by_colour<T>(g, FineSrc3{g, tau, Es0, Es1}, inv, status, s);
 }
 
 template <typename T>
@@ -570,11 +607,10 @@ hipError_t launch_coarse_assemble3(const Grid3& g, const double* E, double* A, h
 
 #define PNS_MG3D_INST(T)                                                                         \
   template hipError_t launch_transpose_convert3<T>(int64_t, const double*, T*, hipStream_t);    \
-  template hipError_t launch_level_patches3d<T>(const Grid3&, const double*, double*, T*, int*, \
+  template hipError_t launch_level_patches3d<T>(const Grid3&, const double*, T*, int*,          \
                                                 hipStream_t);                                   \
   template hipError_t launch_exact_fine_patches3d<T>(const Grid3&, double, const double*,       \
-                                                     const double*, double*, T*, int*,          \
-                                                     hipStream_t);                              \
+                                                     const double*, T*, int*, hipStream_t);     \
   template hipError_t launch_ebe_apply3d<T>(const Grid3&, const T*, const T*, const T*, T*, T*, \
                                             hipStream_t);                                       \
   template hipError_t launch_patch_sweep3r<T>(const Grid3&, const T*, const T*, T*, double,     \

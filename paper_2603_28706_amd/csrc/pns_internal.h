@@ -158,8 +158,7 @@ hipError_t launch_patch_sweep3(const Grid3& g, const T* inv, const T* res, T* d,
 
 // mg3d.hip: coarse levels on hexahedra.  Space-time cell matrices are 170 x 170
 // (local unknown mu * 85 + spatial), row-major in FP64; Et: transposed per cell
-// in the context precision; scratch: patch_scratch3_cells * 170 * 170 FP64 for
-// the elimination;
+// in the context precision;
 // inv: nc real 170 x 170 inverses, column-major, colour-major patch order.
 hipError_t launch_galerkin3d_from_fine(const Grid3& gc, const Grid3& gf, double tau,
                                        const double* Es0, const double* Es1, double* Ec,
@@ -169,16 +168,12 @@ hipError_t launch_galerkin3d(const Grid3& gc, const Grid3& gf, const double* Ef,
 template <typename T>
 hipError_t launch_transpose_convert3(int64_t ncells, const double* E, T* Et, hipStream_t s);
 template <typename T>
-hipError_t launch_level_patches3d(const Grid3& g, const double* E, double* scratch, T* inv,
-                                  int* status, hipStream_t s);
+hipError_t launch_level_patches3d(const Grid3& g, const double* E, T* inv, int* status,
+                                  hipStream_t s);
 // exact finest-level patches from the spatial cell matrices of both Radau nodes
 template <typename T>
 hipError_t launch_exact_fine_patches3d(const Grid3& g, double tau, const double* Es0,
-                                       const double* Es1, double* scratch, T* inv, int* status,
-                                       hipStream_t s);
-// cells per colour of the largest colour: the patch scratch holds this many
-// 170 x 170 FP64 matrices
-int64_t patch_scratch3_cells(const Grid3& g);
+                                       const double* Es1, T* inv, int* status, hipStream_t s);
 // y = A x (b == nullptr) or y = b - A x with the element matrices; S: nc * 170 slots
 template <typename T>
 hipError_t launch_ebe_apply3d(const Grid3& g, const T* Et, const T* x, const T* b, T* y, T* S,
