@@ -25,7 +25,8 @@ field of its own in the JSON line.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 256]
        [--levels 4] [--no-cpu] [--apply-only] [--lin 2] [--calib-copy]
-       [--apply3d-n 32] [--solve-n 256] [--vanka-n 512] [--serve-requests 256]
+       [--apply3d-n 32] [--solve3d-n 32] [--solve-n 256] [--vanka-n 512]
+       [--serve-requests 256]
 """
 from __future__ import annotations
 
@@ -592,6 +593,8 @@ def main():
                     help="mesh of the batched-Vanka measurement (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=256,
                     help="requests of the serving measurement (0: skip)")
+    ap.add_argument("--solve3d-n", type=int, default=32,
+                    help="3D slab solve to 1e-8 on n^3 (0 skips it)")
     ap.add_argument("--apply3d-n", type=int, default=32,
                     help="mesh of the 3D action measurement, n^3 hexahedra (0: skip)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -655,10 +658,10 @@ def main():
                          f"nu_inf=1e-3, modified-Newton Jacobian action, 3D sin-series state"),
             **{k: ({kk: round(vv, 4) for kk, vv in v.items()} if isinstance(v, dict) else v)
                for k, v in a3.items()}}
-    if args.apply3d_n and not args.apply_only:
-        s3 = solve3d_latency(args.apply3d_n)
+    if args.solve3d_n and not args.apply_only:
+        s3 = solve3d_latency(args.solve3d_n)
         line["solve3d_time_to_1e-8_s"] = {
-            "workload": (f"3D {args.apply3d_n}^3 slab solve, p=1.3 delta=1e-3 nu0=1 nu_inf=1e-3, "
+            "workload": (f"3D {args.solve3d_n}^3 slab solve, p=1.3 delta=1e-3 nu0=1 nu_inf=1e-3, "
                          f"modified Newton + FGMRES(30) / 4-level V-cycle (exact finest "
                          f"patches, omega 0.15) to ||R||_M <= 1e-8 ||R0||_M"),
             **{k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}

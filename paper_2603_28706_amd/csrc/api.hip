@@ -67,7 +67,7 @@ size_t layout(pns_ctx* c, bool bind) {
     if (c->has_coarse) {
       const int64_t n = c->lev.back().g.nst;
       c->Adense = (double*)take((size_t)n * n * 8);
-      c->gjwork = (double*)take((size_t)(2 * 64 * n + n + 8) * 8);
+      c->gjwork = (double*)take((size_t)coarse_invert_work_doubles(n) * 8);
       c->gjpiv = (int*)take((size_t)n * sizeof(int));
     }
     return (off + kAlign - 1) / kAlign * kAlign;
@@ -96,7 +96,7 @@ size_t layout(pns_ctx* c, bool bind) {
     if (coarsest && c->has_coarse) {
       const int64_t n = L.g.nst;
       c->Adense = (double*)take((size_t)n * n * 8);
-      c->gjwork = (double*)take((size_t)(2 * 64 * n + n + 8) * 8);  // panel, rows, factors
+      c->gjwork = (double*)take((size_t)coarse_invert_work_doubles(n) * 8);
       c->gjpiv = (int*)take((size_t)n * sizeof(int));
     }
   }

@@ -578,7 +578,7 @@ __global__ void pin_kernel(int64_t n, double* A, const int64_t* pin, int npin) {
 // Blocked Gauss-Jordan inversion, in place, partial row pivoting.
 // Panels of kGjNb columns K: (1) the panel is copied to a contiguous
 // column-major buffer P (n x kb) and eliminated column by column over all
-// rows (pivot search over the rows not yet used as pivots); (2) its row swaps
+// rows (one launch per column, below); (2) its row swaps
 // are applied to every other column; (3) with T = rows K of the other columns,
 // every other column is updated as A[:,C] = [0 on rows K; A[O,C]] + P T, which
 // is the block form of the Gauss-Jordan step; (4) the panel is written back.
@@ -599,73 +599,112 @@ __global__ void gj_panel_out_kernel(int64_t n, int64_t k0, int kb, double* __res
   for (int j = 0; j < kb; ++j) A[r * n + k0 + j] = P[(int64_t)j * n + r];
 }
 
-// pivot of panel column jc (global column c = k0 + jc): search, swap the panel
-// rows c and p, scale row c; one workgroup
-__global__ __launch_bounds__(1024) void gj_panel_pivot_kernel(int64_t n, int64_t k0, int kb, int jc,
-                                                              double* __restrict__ P, int* piv,
-                                                              int* status, double* __restrict__ F) {
-  __shared__ double bv[1024];
-  __shared__ int64_t bi[1024];
-  const int t = threadIdx.x;
-  const int64_t c = k0 + jc;
-  const double* col = P + (int64_t)jc * n;
-  double v = -1.0;
-  int64_t idx = c;
-  for (int64_t r = c + t; r < n; r += 1024) {
-    const double a = fabs(col[r]);
-    if (a > v) {
-      v = a;
-      idx = r;
+// Panel elimination, one launch per column.  Workgroup b owns rows
+// 64 b .. 64 b + 63 of the panel (one row per lane, the four waves take a
+// quarter of the panel's columns each).  Step jc reads the panel from Pin and
+// writes it whole to Pout (two copies, so no workgroup reads what another one
+// is writing): the pivot row p of column jc comes from the per-block maxima
+// left by the previous step (largest |P[jc][r]| over the rows r >= c not yet
+// used as pivots, ties to the smaller row); the new row c is old row p scaled
+// by 1 / pivot (its pivot entry becomes 1 / pivot), row p takes old row c, and
+// every other row subtracts its column-jc entry times the new row c (its
+// column-jc entry becomes -entry / pivot): the Gauss-Jordan step with the
+// interchange folded in.  The wave holding column jc + 1 leaves its block's
+// maximum for the next step.
+constexpr int kGjQ = kGjNb / 4;  // panel columns per wave
+
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(v, off);
+    const int oi = __shfl_xor(i, off);
+    if (ov > v || (ov == v && oi < i)) {
+      v = ov;
+      i = oi;
     }
-  }
-  bv[t] = v;
-  bi[t] = idx;
-  __syncthreads();
-  for (int off = 512; off > 0; off >>= 1) {
-    if (t < off && (bv[t + off] > bv[t] || (bv[t + off] == bv[t] && bi[t + off] < bi[t]))) {
-      bv[t] = bv[t + off];
-      bi[t] = bi[t + off];
-    }
-    __syncthreads();
-  }
-  const int64_t p = bi[0];
-  const bool sing = !(bv[0] > 0.0);
-  const double pv = sing ? 1.0 : P[(int64_t)jc * n + p];
-  __syncthreads();
-  if (t == 0) {
-    piv[c] = (int)p;
-    if (sing) atomicOr(status, 2);
-  }
-  // elimination factors: panel column jc after the row swap (F[c] unused)
-  for (int64_t r = t; r < n; r += 1024) {
-    const int64_t src = r == c ? p : (r == p ? c : r);
-    F[r] = col[src];
-  }
-  __syncthreads();
-  if (t < kb) {
-    double a = P[(int64_t)t * n + p];
-    if (p != c) P[(int64_t)t * n + p] = P[(int64_t)t * n + c];
-    P[(int64_t)t * n + c] = (t == jc) ? 1.0 / pv : a / pv;
   }
 }
 
-// eliminate panel column jc from every other row: one thread per (row, panel
-// column); the factors F are a copy of column jc taken before any update
-__global__ __launch_bounds__(256) void gj_panel_elim_kernel(int64_t n, int64_t k0, int kb, int jc,
-                                                            double* __restrict__ P,
-                                                            const double* __restrict__ F) {
-  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (id >= n * kb) return;
-  const int j = (int)(id / n);
-  const int64_t r = id - (int64_t)j * n;
+// block maxima of column 0 of the panel over the rows r >= k0
+__global__ __launch_bounds__(64) void gj_partials0_kernel(int64_t n, int64_t k0,
+                                                          const double* __restrict__ P,
+                                                          double* __restrict__ bv,
+                                                          int* __restrict__ bi) {
+  const int64_t r = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  double v = (r < n && r >= k0) ? fabs(P[r]) : -1.0;
+  int i = (int)r;
+  wave_argmax(v, i);
+  if (threadIdx.x == 0) {
+    bv[blockIdx.x] = v;
+    bi[blockIdx.x] = i;
+  }
+}
+
+__global__ __launch_bounds__(256) void gj_panel_step_kernel(
+    int64_t n, int64_t k0, int kb, int jc, const double* __restrict__ Pin, double* __restrict__ Pout,
+    const double* __restrict__ bv_in, const int* __restrict__ bi_in, double* __restrict__ bv_out,
+    int* __restrict__ bi_out, int nblk, int* piv, int* status) {
+  __shared__ double oc[kGjNb], op[kGjNb];
+  __shared__ double s_pv;
+  __shared__ int s_p;
   const int64_t c = k0 + jc;
-  if (r == c) return;
-  const double f = F[r];
-  const double pr = P[(int64_t)j * n + c];
-  if (j == jc)
-    P[(int64_t)j * n + r] = -f * pr;
-  else
-    P[(int64_t)j * n + r] -= f * pr;
+  const int t = threadIdx.x, lane = t & 63, q = t >> 6;
+  if (t < 64) {
+    double v = -1.0;
+    int i = (int)c;
+    for (int b = lane; b < nblk; b += 64) {
+      const double w = bv_in[b];
+      const int wi = bi_in[b];
+      if (w > v || (w == v && wi < i)) {
+        v = w;
+        i = wi;
+      }
+    }
+    wave_argmax(v, i);
+    if (lane == 0) {
+      const bool sing = !(v > 0.0);
+      s_p = sing ? (int)c : i;
+      s_pv = sing ? 1.0 : Pin[(int64_t)jc * n + i];
+      if (blockIdx.x == 0) {
+        piv[c] = s_p;
+        if (sing) atomicOr(status, 2);
+      }
+    }
+  }
+  __syncthreads();
+  const int64_t p = s_p;
+  if (t < kb) {
+    oc[t] = Pin[(int64_t)t * n + c];
+    op[t] = Pin[(int64_t)t * n + p];
+  }
+  __syncthreads();
+  const double dinv = 1.0 / s_pv;
+  const int64_t r = (int64_t)blockIdx.x * 64 + lane;
+  double mine = -1.0;
+  if (r < n) {
+    const double f = r == p ? oc[jc] : Pin[(int64_t)jc * n + r];
+    const int j1 = min(kb, (q + 1) * kGjQ);
+    for (int j = q * kGjQ; j < j1; ++j) {
+      const double nc = (j == jc ? 1.0 : op[j]) * dinv;
+      double out;
+      if (r == c) {
+        out = nc;
+      } else {
+        double base = r == p ? oc[j] : Pin[(int64_t)j * n + r];
+        if (j == jc) base = 0.0;
+        out = base - f * nc;
+      }
+      Pout[(int64_t)j * n + r] = out;
+      if (j == jc + 1 && r > c) mine = fabs(out);
+    }
+  }
+  if (jc + 1 < kb && q == (jc + 1) / kGjQ) {
+    int i = (int)r;
+    wave_argmax(mine, i);
+    if (lane == 0) {
+      bv_out[blockIdx.x] = mine;
+      bi_out[blockIdx.x] = i;
+    }
+  }
 }
 
 // row swaps of the panel applied to column j (outside the panel), in order;
@@ -851,30 +890,38 @@ hipError_t launch_pin(int64_t n, double* A, const int64_t* pin, int npin, hipStr
   return hipGetLastError();
 }
 
-// work: 2 * kGjNb * n doubles (panel P and row block T); piv: n ints
+// work: coarse_invert_work_doubles(n) doubles (two panel copies, the row block
+// T, the per-block pivot candidates); piv: n ints
 hipError_t coarse_invert(int64_t n, double* A, double* work, int* piv, int* status,
                          hipStream_t s) {
-  double* P = work;
+  double* P[2] = {work, work + (int64_t)2 * kGjNb * n};
   double* T = work + (int64_t)kGjNb * n;
-  double* F = work + (int64_t)2 * kGjNb * n;
+  const int nblk = (int)((n + 63) / 64);
+  double* bv[2] = {work + (int64_t)3 * kGjNb * n, work + (int64_t)3 * kGjNb * n + nblk};
+  int* bi[2] = {(int*)(work + (int64_t)3 * kGjNb * n + 2 * nblk),
+                (int*)(work + (int64_t)3 * kGjNb * n + 2 * nblk) + nblk};
   const unsigned nb = (unsigned)((n + 255) / 256);
   for (int64_t k0 = 0; k0 < n; k0 += kGjNb) {
     const int kb = (int)((n - k0) < kGjNb ? (n - k0) : kGjNb);
-    const unsigned ne = (unsigned)((n * kb + 255) / 256);
-    hipLaunchKernelGGL(gj_panel_in_kernel, dim3(nb), dim3(256), 0, s, n, k0, kb, A, P);
+    hipLaunchKernelGGL(gj_panel_in_kernel, dim3(nb), dim3(256), 0, s, n, k0, kb, A, P[0]);
+    hipLaunchKernelGGL(gj_partials0_kernel, dim3((unsigned)nblk), dim3(64), 0, s, n, k0,
+                       (const double*)P[0], bv[0], bi[0]);
     for (int jc = 0; jc < kb; ++jc) {
-      hipLaunchKernelGGL(gj_panel_pivot_kernel, dim3(1), dim3(1024), 0, s, n, k0, kb, jc, P, piv,
-                         status, F);
-      hipLaunchKernelGGL(gj_panel_elim_kernel, dim3(ne), dim3(256), 0, s, n, k0, kb, jc, P,
-                         (const double*)F);
+      const int a = jc & 1, b = a ^ 1;
+      hipLaunchKernelGGL(gj_panel_step_kernel, dim3((unsigned)nblk), dim3(256), 0, s, n, k0, kb, jc,
+                         (const double*)P[a], P[b], (const double*)bv[a], (const int*)bi[a], bv[b],
+                         bi[b], nblk, piv, status);
     }
+    double* Pf = P[kb & 1];
     const int64_t m = n - kb;
     if (m > 0) {
       hipLaunchKernelGGL(gj_rowswap_copy_kernel, dim3(nb), dim3(256), 0, s, n, k0, kb, A, piv, T);
       dim3 grid((unsigned)((n + 63) / 64), (unsigned)((m + 63) / 64));
-      hipLaunchKernelGGL(gj_update_kernel, grid, dim3(256), 0, s, n, k0, kb, A, P, T);
+      hipLaunchKernelGGL(gj_update_kernel, grid, dim3(256), 0, s, n, k0, kb, A, (const double*)Pf,
+                         (const double*)T);
     }
-    hipLaunchKernelGGL(gj_panel_out_kernel, dim3(nb), dim3(256), 0, s, n, k0, kb, A, P);
+    hipLaunchKernelGGL(gj_panel_out_kernel, dim3(nb), dim3(256), 0, s, n, k0, kb, A,
+                       (const double*)Pf);
   }
   hipLaunchKernelGGL(gj_colperm_kernel, dim3(nb), dim3(256), 0, s, n, A, piv);
   return hipGetLastError();

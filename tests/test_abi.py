@@ -129,7 +129,7 @@ def test_3d_context_layout_and_rejections():
             + 33574 * 8 + 512 * kE * 8
             + 4886 * 8 * 3 + 64 * kE * 16 + 64 * kE * 8
             + 814 * 8 * 3 + 8 * kE * 16
-            + 814 * 814 * 8 + (2 * 64 * 814 + 814 + 8) * 8 + 814 * 4)
+            + 814 * 814 * 8 + (3 * 64 * 814 + 4 * 13 + 8) * 8 + 814 * 4)
     assert need <= L.pns_workspace_bytes(h) < need + 8192
     L.pns_ctx_destroy(h)
     # FP32: inverses and defect in single precision
