@@ -664,7 +664,8 @@ def main():
             "workload": (f"3D {args.solve3d_n}^3 slab solve, p=1.3 delta=1e-3 nu0=1 nu_inf=1e-3, "
                          f"modified Newton + FGMRES(30) / 4-level V-cycle (exact finest "
                          f"patches, omega 0.15) to ||R||_M <= 1e-8 ||R0||_M"),
-            **{k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+            **{k: {kk: (float(f"{vv:.5g}") if isinstance(vv, float) else vv)
+                   for kk, vv in v.items()}
                for k, v in s3.items()},
             "mixed_speedup": round(s3["fp64"]["time_s"] / s3["mixed"]["time_s"], 3)}
     if args.solve_n and not args.apply_only:

@@ -681,15 +681,23 @@ __global__ __launch_bounds__(256) void gj_panel_step_kernel(
   const int64_t r = (int64_t)blockIdx.x * 64 + lane;
   double mine = -1.0;
   if (r < n) {
+    // all of this thread's loads first, then the update and the stores
+    const int j0 = q * kGjQ;
+    double v[kGjQ];
+#pragma unroll
+    for (int u = 0; u < kGjQ; ++u)
+      v[u] = (j0 + u < kb && r != p) ? Pin[(int64_t)(j0 + u) * n + r] : 0.0;
     const double f = r == p ? oc[jc] : Pin[(int64_t)jc * n + r];
-    const int j1 = min(kb, (q + 1) * kGjQ);
-    for (int j = q * kGjQ; j < j1; ++j) {
+#pragma unroll
+    for (int u = 0; u < kGjQ; ++u) {
+      const int j = j0 + u;
+      if (j >= kb) break;
       const double nc = (j == jc ? 1.0 : op[j]) * dinv;
       double out;
       if (r == c) {
         out = nc;
       } else {
-        double base = r == p ? oc[j] : Pin[(int64_t)j * n + r];
+        double base = r == p ? oc[j] : v[u];
         if (j == jc) base = 0.0;
         out = base - f * nc;
       }
