@@ -155,7 +155,8 @@ def apply3d(n=32, reps=50, lin=2, smoother=True, sweeps=20, vcycles=10, levels3d
     p = 1.3, delta = 1e-3, nu = 1, nu_inf = 1e-3; state: 3D sin-series
     velocity (8 modes, seed 301, O(tau) time variation), input U[-1, 1]
     (seed 302).  Mean duration of `reps` back-to-back actions (HIP events on
-    the stream the kernels run on), FP64 and FP32; then the finest-level
+    the stream the kernels run on), BF16 storage (x and u_k, FP32 arithmetic,
+    FP32 y), FP64 and FP32; then the finest-level
     Vanka smoother: setup wall time (all levels of the `levels3d`-level
     hierarchy) and the mean of `sweeps` sweeps (residual U[-1, 1], seed 303,
     omega = 0.5); then the mean of `vcycles` V-cycles (2 + 2 sweeps, omega
@@ -167,6 +168,30 @@ def apply3d(n=32, reps=50, lin=2, smoother=True, sweeps=20, vcycles=10, levels3d
     uk = torch.tensor(inputs.sin_series_velocity((n, n, n), seed=301, t_nodes=[0.01 / 3, 0.01]),
                       device="cuda")
     out = {}
+    # BF16 storage of x and u_k, FP32 arithmetic: the action only
+    ctx = pnsmg.Context((n, n, n), precision=pnsmg.BF16)
+    ctx.pns_set_state(dict(MODEL3D, lin=lin), uk)
+    sz = ctx.sizes()
+    xb = torch.tensor(inputs.uniform(302, sz["nst"]), device="cuda").to(torch.bfloat16)
+    y = ctx.vector()
+    for _ in range(3):
+        ctx.pns_cell_apply(xb, y)
+    stream = torch.cuda.current_stream()
+    ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ea.record(stream)
+    for _ in range(reps):
+        ctx.pns_cell_apply(xb, y)
+    eb.record(stream)
+    torch.cuda.synchronize()
+    t = ea.elapsed_time(eb) * 1e-3 / reps
+    bytes_bf16 = 2 * sz["nst"] + 4 * sz["nst"] + 2 * 2 * sz["nv"]
+    out["bf16"] = dict(us_mean=t * 1e6, gdofs=sz["nst"] / t / 1e9,
+                       tflops=apply3d_flops_per_cell(lin) * sz["cells"] / t / 1e12,
+                       hbm_gbs=bytes_bf16 / t / 1e9)
+    print(f"[bench] 3D action {n}^3 bf16 storage: {t * 1e6:.1f} us, {sz['nst'] / t / 1e9:.2f} GDoF/s",
+          file=sys.stderr, flush=True)
+    del ctx
     for prec, name in ((pnsmg.FP64, "fp64"), (pnsmg.FP32, "fp32")):
         ctx = pnsmg.Context((n, n, n), precision=prec, n_levels=levels3d if smoother else 1)
         ctx.pns_set_state(dict(MODEL3D, lin=lin), uk)
@@ -659,7 +684,8 @@ def main():
         a3 = apply3d(args.apply3d_n, lin=args.lin)
         line["apply3d"] = {
             "workload": (f"3D {args.apply3d_n}^3 hexahedra Q2/P1disc x dG(1), p=1.3 delta=1e-3 "
-                         f"nu_inf=1e-3, modified-Newton Jacobian action, 3D sin-series state"),
+                         f"nu_inf=1e-3, modified-Newton Jacobian action (bf16: x and u_k stored "
+                         f"in BF16, FP32 arithmetic), 3D sin-series state"),
             **{k: ({kk: round(vv, 4) for kk, vv in v.items()} if isinstance(v, dict) else v)
                for k, v in a3.items()}}
     if args.solve3d_n and not args.apply_only:

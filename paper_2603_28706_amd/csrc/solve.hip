@@ -255,6 +255,7 @@ extern "C" {
 int pns_residual(pns_ctx* ctx, const pns_model* md, const double* U, const double* vprev,
                  double* R) {
   if (!ctx) return PNS_EINVAL;
+  if (ctx->prec == PNS_BF16) return fail(ctx, PNS_EUNSUPPORTED, "BF16 contexts have the action only");
   if (!ctx->ws) return fail(ctx, PNS_EWORKSPACE, "no workspace bound");
   if (!md || !U || !R || U == R) return fail(ctx, PNS_EINVAL, "NULL model or vectors, or U == R");
   Model m;
@@ -266,7 +267,7 @@ int pns_residual(pns_ctx* ctx, const pns_model* md, const double* U, const doubl
 }
 
 size_t pns_solve_workspace_bytes(const pns_ctx* ctx, int restart) {
-  if (!ctx || restart < 1 || restart > kMaxRestart) return 0;
+  if (!ctx || ctx->prec == PNS_BF16 || restart < 1 || restart > kMaxRestart) return 0;
   return work_layout(ctx, restart, nullptr, nullptr);
 }
 
@@ -274,6 +275,7 @@ int pns_solve(pns_ctx* ctx, const pns_model* md, const double* vprev, double* U,
               const pns_solve_params* prm, void* work, size_t work_bytes, pns_solve_info* info) {
   if (!ctx) return PNS_EINVAL;
   if (info) std::memset(info, 0, sizeof(*info));
+  if (ctx->prec == PNS_BF16) return fail(ctx, PNS_EUNSUPPORTED, "BF16 contexts have the action only");
   if (!ctx->ws) return fail(ctx, PNS_EWORKSPACE, "no workspace bound");
   if (!md || !U || !prm) return fail(ctx, PNS_EINVAL, "NULL model, U or parameters");
   if (prm->restart < 1 || prm->restart > kMaxRestart || prm->max_newton < 1 ||

@@ -20,7 +20,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "pnsmg.h")
 (PNS_OK, PNS_EINVAL, PNS_EWORKSPACE, PNS_EHIP, PNS_ESTATE, PNS_ESINGULAR, PNS_EUNSUPPORTED,
  PNS_ENOTCONV) = (0, -1, -2, -3, -4, -5, -6, -7)
 PICARD, EXACT_NEWTON, MODIFIED_NEWTON = 0, 1, 2
-FP64, FP32 = 0, 1
+FP64, FP32, BF16 = 0, 1, 2
 APPLY_RECOMPUTE, APPLY_CACHED = 0, 1
 PATCH_SURROGATE, PATCH_EXACT = 0, 1
 
@@ -168,7 +168,9 @@ class Context:
         self.torch = torch
         self.device = torch.device(device)
         self.precision = precision
+        # element type of y, b, r, d; x of the action is BF16 in a BF16 context
         self.dtype = torch.float64 if precision == FP64 else torch.float32
+        self.in_dtype = torch.bfloat16 if precision == BF16 else self.dtype
         dim = len(n)
         lo = (0.0,) * dim if lo is None else lo
         hi = (1.0,) * dim if hi is None else hi
@@ -211,8 +213,8 @@ class Context:
     def vector(self, level=0):
         return self.torch.zeros(self.sizes(level)["nst"], dtype=self.dtype, device=self.device)
 
-    def _vec(self, t, level=0):
-        assert t.dtype == self.dtype and t.is_contiguous() and t.device.type == "cuda"
+    def _vec(self, t, level=0, dtype=None):
+        assert t.dtype == (dtype or self.dtype) and t.is_contiguous() and t.device.type == "cuda"
         assert t.numel() == self.sizes(level)["nst"]
         return _ptr(t)
 
@@ -236,10 +238,11 @@ class Context:
         self._check(lib().pns_set_patch_kind(self.h, int(kind)))
 
     def pns_cell_apply(self, x, y):
-        self._check(lib().pns_cell_apply(self.h, self._vec(x), self._vec(y)))
+        self._check(lib().pns_cell_apply(self.h, self._vec(x, dtype=self.in_dtype), self._vec(y)))
 
     def pns_cell_defect(self, b, x, y):
-        self._check(lib().pns_cell_defect(self.h, self._vec(b), self._vec(x), self._vec(y)))
+        self._check(lib().pns_cell_defect(self.h, self._vec(b), self._vec(x, dtype=self.in_dtype),
+                                          self._vec(y)))
 
     def pns_vanka_setup(self, node_masks=None):
         if node_masks is None:

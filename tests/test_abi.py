@@ -132,6 +132,20 @@ def test_3d_context_layout_and_rejections():
             + 814 * 814 * 8 + (3 * 64 * 814 + 4 * 13 + 8) * 8 + 814 * 4)
     assert need <= L.pns_workspace_bytes(h) < need + 8192
     L.pns_ctx_destroy(h)
+    # BF16: hexahedral action only (state in BF16, action slots in FP32)
+    rc, h = _create(n=(4, 2, 3), prec=pnsmg.BF16)
+    assert rc == pnsmg.PNS_OK
+    nn3, nc3 = 9 * 5 * 7, 24
+    need = 2 * 3 * nn3 * (2 + 8) + nc3 * 170 * 4
+    assert need <= L.pns_workspace_bytes(h) < need + 1024
+    assert L.pns_vanka_setup(h, None) == pnsmg.PNS_EUNSUPPORTED
+    assert L.pns_vanka_smooth(h, 0, 1, ctypes.c_double(0.1), v, w) == pnsmg.PNS_EUNSUPPORTED
+    assert L.pns_vcycle(h, 1, 1, ctypes.c_double(0.1), v, w) == pnsmg.PNS_EUNSUPPORTED
+    assert L.pns_residual(h, ctypes.byref(model), v, None, w) == pnsmg.PNS_EUNSUPPORTED
+    assert L.pns_solve_workspace_bytes(h, 30) == 0
+    L.pns_ctx_destroy(h)
+    assert _create(n=(4, 4, 4), levels=2, prec=pnsmg.BF16)[0] == pnsmg.PNS_EUNSUPPORTED
+    assert _create(n=(8, 8), prec=pnsmg.BF16)[0] == pnsmg.PNS_EINVAL
     # FP32: inverses and defect in single precision
     rc, h = _create(n=(4, 2, 3), prec=pnsmg.FP32)
     assert rc == pnsmg.PNS_OK

@@ -129,3 +129,53 @@ def test_apply3d_32cubed_sampled_rows():
         err = np.abs(got[rows] - ref).max()
         print(f"32^3 sampled rows prec={prec}: max abs err {err:.3e} / max |y| {scale:.3e}")
         assert err <= tol * scale
+
+
+def bf16_round(a):
+    """Values exactly representable in BF16 (as FP64) and their BF16 tensor."""
+    t = torch.as_tensor(np.asarray(a), dtype=torch.float64).to(torch.bfloat16)
+    return t.double().numpy(), t
+
+
+@pytest.mark.parametrize("lin", KINDS)
+def test_apply3d_bf16_storage(lin):
+    """BF16 context: x and the state stored in BF16, arithmetic in FP32.  On
+    BF16-representable inputs the only differences to the FP64 oracle are the
+    FP32 operations, so the FP32 bound (1e-5 relative) applies; also y = b - Jx
+    with FP32 b, and a mesh with a different box."""
+    for n, hi in (((2, 2, 2), (1.0, 1.0, 1.0)), ((3, 2, 4), (1.0, 2.0, 0.5))):
+        prob = oracle_problem(n, MODEL3, lin, hi=hi)
+        uk, _ = bf16_round(inputs.uniform(441, prob.nt * prob.nv))
+        x, xb = bf16_round(inputs.uniform(442, prob.nst))
+        ref = O.apply(prob, uk, x)
+        ctx = pnsmg.Context(n, n_levels=1, precision=pnsmg.BF16, tau=0.01, hi=hi)
+        ctx.pns_set_state(dict(MODEL3, lin=lin), to_dev(uk, torch.float64))
+        y = ctx.vector()
+        assert y.dtype == torch.float32
+        ctx.pns_cell_apply(xb.cuda(), y)
+        b = inputs.uniform(443, prob.nst)
+        yd = ctx.vector()
+        ctx.pns_cell_defect(to_dev(b, torch.float32), xb.cuda(), yd)
+        torch.cuda.synchronize()
+        ev, ep = rel_blocks(y.double().cpu().numpy(), ref, prob)
+        print(f"3D BF16 n={n} lin={lin}: rel err vel={ev:.2e} pres={ep:.2e}")
+        assert ev <= 1e-5 and ep <= 1e-5
+        refd = np.float32(b).astype(np.float64) - ref
+        assert np.linalg.norm(yd.double().cpu().numpy() - refd) <= 1e-5 * np.linalg.norm(refd)
+
+
+def test_apply3d_bf16_32cubed_sampled_rows():
+    n = (32, 32, 32)
+    prob = oracle_problem(n, MODEL3, pnsmg.MODIFIED_NEWTON)
+    uk, _ = bf16_round(inputs.sin_series_velocity(n, seed=431, t_nodes=[0.01 / 3, 0.01]))
+    x, xb = bf16_round(inputs.uniform(432, prob.nst))
+    rows = np.array(sorted(set(int(r) for r in np.random.default_rng(1).integers(0, prob.nst, 60))))
+    ref = O.apply_rows(prob, uk, x, rows)
+    ctx = pnsmg.Context(n, n_levels=1, precision=pnsmg.BF16)
+    ctx.pns_set_state(dict(MODEL3, lin=pnsmg.MODIFIED_NEWTON), to_dev(uk, torch.float64))
+    y = ctx.vector()
+    ctx.pns_cell_apply(xb.cuda(), y)
+    torch.cuda.synchronize()
+    err = np.abs(y.double().cpu().numpy()[rows] - ref).max()
+    print(f"32^3 BF16 sampled rows: max abs err {err:.3e} / {np.abs(ref).max():.3e}")
+    assert err <= 1e-5 * np.abs(ref).max()
