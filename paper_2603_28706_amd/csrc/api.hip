@@ -84,6 +84,7 @@ size_t layout(pns_ctx* c, bool bind) {
   c->Esr = (double*)take(g0.nc * kNs * kNs * 8);
   c->masks = (uint16_t*)take(g0.nc * sizeof(uint16_t));
   c->tcache = take(g0.nc * 18 * 6 * es);
+  c->edge2 = (double*)take(cell_apply_edge_doubles(g0) * 8);
   c->gr = take(g0.nst * es);
   c->gd = take(g0.nst * es);
   c->status = (int*)take(sizeof(int) * 4);
@@ -149,7 +150,7 @@ hipError_t defect(pns_ctx* c, int l, const T* b, const T* x, T* y) {
     return launch_ebe_apply3d<T>(L.g3, (const T*)L.E, x, b, y, (T*)c->E3, c->stream);
   if (l == 0)
     return launch_cell_apply<T>(L.g, c->model, c->disc.tau, (const T*)c->uk, tangent_cache<T>(c),
-                                x, b, y, 1, c->stream);
+                                x, b, y, c->edge2, 1, c->stream);
   return launch_ebe_apply<T>(L.g, (const T*)L.E, x, b, y, 1, c->stream);
 }
 
@@ -164,7 +165,7 @@ hipError_t apply_level(pns_ctx* c, int l, const T* x, T* y) {
                                  c->stream);
   if (l == 0)
     return launch_cell_apply<T>(L.g, c->model, c->disc.tau, (const T*)c->uk, tangent_cache<T>(c),
-                                x, x, y, 0, c->stream);
+                                x, x, y, c->edge2, 0, c->stream);
   return launch_ebe_apply<T>(L.g, (const T*)L.E, x, x, y, 0, c->stream);
 }
 

@@ -6,11 +6,14 @@
 // Nitsche terms of eq. def-b-gam).
 //
 // Design (gfx950, wave64):
-// * one workgroup of 256 threads per tile of TX x TY owned cells; it also
-//   evaluates the one-cell halo on the low x / low y side, so every node it
-//   owns receives all of its volume contributions inside the workgroup and each
-//   output is written exactly once (no zero fill); tiles are dealt to the XCDs
-//   in contiguous runs;
+// * one workgroup of 256 threads per tile of 16 x 8 evaluated cells; tiles
+//   are dealt to the XCDs in contiguous runs.  Two tilings (chosen per variant
+//   by how many workgroups share a CU): 15 x 7 owned cells plus a one-cell
+//   halo on the low x / low y side, so every owned node is complete in its
+//   tile and written once; or 16 x 8 owned cells without halo, each cell
+//   evaluated once (at 256 x 256: 512 tiles, one per slot of two workgroups
+//   per CU), nodes of shared tile edges written as per-tile partial sums and
+//   completed by a second kernel in a fixed order;
 // * the tile's nodal values of x and u_k (both Radau nodes) are staged in LDS
 //   with coalesced row loads;
 // * one thread per (cell, Radau node mu); a wave holds the two Radau nodes of
@@ -29,18 +32,29 @@
 // * the boundary-face terms run in a phase of their own after a barrier, one
 //   thread per face point of the tile (only tiles at the boundary), which keeps
 //   their registers out of the volume part: three workgroups share a CU;
-// * the owned nodes and cells are written coalesced from LDS.
+// * the owned cells' pressure rows and the tile's complete nodes are written
+//   coalesced from LDS (without halo: the partial sums of shared edge nodes to
+//   the edge buffer).
 #include "devmath.h"
 #include "pns_internal.h"
 
 namespace pns {
 namespace {
 
-constexpr int TX = 15, TY = 7;            // owned cells per tile
-constexpr int HX = TX + 1, HY = TY + 1;   // evaluated cells (with low-side halo)
-constexpr int BX = 2 * HX + 1, BY = 2 * HY + 1;  // LDS node box
+constexpr int HX = 16, HY = 8;            // evaluated cells per tile
+constexpr int BX = 2 * HX + 1, BY = 2 * HY + 1;  // LDS node box (33 x 17)
 constexpr int kCells = HX * HY;           // 128
 constexpr int kThreads = 2 * kCells;      // 256: (cell, mu)
+// perimeter of the node box: bottom row (33), top row (33), left and right
+// columns without the corners (15 each)
+constexpr int kPerim = 2 * BX + 2 * (BY - 2);  // 96
+
+__host__ __device__ inline int perim_index(int lx, int ly) {
+  if (ly == 0) return lx;
+  if (ly == BY - 1) return BX + lx;
+  if (lx == 0) return 2 * BX + ly - 1;
+  return 2 * BX + (BY - 2) + ly - 1;  // lx == BX - 1
+}
 // Waves per SIMD the register allocation must allow: several workgroups share
 // a CU, so the staging, compute and write-out phases of different tiles
 // overlap.  3 (<= 168 VGPRs) fits without spills except for the FP64 variant
@@ -48,6 +62,17 @@ constexpr int kThreads = 2 * kCells;      // 256: (cell, mu)
 template <typename T, bool CACHED>
 constexpr int waves_per_simd() {
   return (sizeof(T) == 8 && !CACHED) ? 2 : 3;
+}
+// Tiling of a variant.  With three workgroups per CU (768 slots) the tiles of
+// 15 x 7 owned cells plus a one-cell halo on the low x / low y side (666 tiles
+// at 256 x 256) fit in one round and every node is complete inside its tile.
+// With two per CU (512 slots) those tiles would take two rounds, so the tile
+// is 16 x 8 owned cells without halo (512 tiles at 256 x 256, 22 % less
+// arithmetic) and the nodes of shared tile edges are completed by a second
+// kernel from per-tile partial sums.
+template <typename T, bool CACHED>
+constexpr bool halo_tiles() {
+  return waves_per_simd<T, CACHED>() == 3;
 }
 
 // Tangent scalars at a point, A = D(u_k):  eta = nu_inf + mu,
@@ -265,7 +290,9 @@ __global__ __launch_bounds__(kThreads, (waves_per_simd<T, CACHED>())) void cell_
                                                               const T* __restrict__ cache,
                                                               const T* __restrict__ x,
                                                               const T* __restrict__ b,
-                                                              T* __restrict__ y, int tiles_x) {
+                                                              T* __restrict__ y,
+                                                              double* __restrict__ edge,
+                                                              int tiles_x) {
   __shared__ T Xs[4][BY][BX];                  // x: [mu*2 + comp]
   __shared__ T Us[CACHED ? 1 : 4][BY][BX];     // u_k: [mu*2 + comp] (recomputing variant)
   __shared__ double acc[4][BY][BX];            // velocity results: [mu*2 + comp]
@@ -276,11 +303,13 @@ __global__ __launch_bounds__(kThreads, (waves_per_simd<T, CACHED>())) void cell_
   const int nb = gridDim.x, bq = nb >> 3, br = nb & 7;
   const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
   const int tile = xcd * bq + (xcd < br ? xcd : br) + slot;
-  const int cx0 = (tile % tiles_x) * TX;
-  const int cy0 = (tile / tiles_x) * TY;
+  constexpr bool HALO = halo_tiles<T, CACHED>();
+  constexpr int OFF = HALO ? 1 : 0;  // halo cells on the low side
+  const int cx0 = (tile % tiles_x) * (HX - OFF);  // first owned cell
+  const int cy0 = (tile / tiles_x) * (HY - OFF);
   const int t = threadIdx.x;
   const int NX = 2 * g.nx + 1;
-  const int gx0 = 2 * (cx0 - 1), gy0 = 2 * (cy0 - 1);
+  const int gx0 = 2 * (cx0 - OFF), gy0 = 2 * (cy0 - OFF);  // node box origin
 
   // stage x (and u_k) of the node box, zero the sums
   for (int i = t; i < 4 * BY * BX; i += kThreads) {
@@ -303,7 +332,7 @@ __global__ __launch_bounds__(kThreads, (waves_per_simd<T, CACHED>())) void cell_
   const int color = __builtin_amdgcn_readfirstlane(t >> 6), lane = t & 63;
   const int mu = lane & 1, k = lane >> 1;
   const int hx = 2 * (k % (HX / 2)) + (color & 1), hy = 2 * (k / (HX / 2)) + (color >> 1);
-  const int cx = cx0 - 1 + hx, cy = cy0 - 1 + hy;
+  const int cx = cx0 - OFF + hx, cy = cy0 - OFF + hy;
   const bool valid = cx >= 0 && cy >= 0 && cx < g.nx && cy < g.ny;
   const int lx0 = 2 * hx, ly0 = 2 * hy;
 
@@ -463,27 +492,30 @@ __global__ __launch_bounds__(kThreads, (waves_per_simd<T, CACHED>())) void cell_
   }
   __syncthreads();
 
-  // Boundary faces of the evaluated cells, in a phase of their own (one thread
-  // per face point), so that their registers do not add to the volume part's.
-  // Only tiles at the boundary of the rectangle have any.
-  if (cx0 == 0 || cy0 == 0 || cx0 + TX >= g.nx || cy0 + TY >= g.ny) {
+  // Boundary faces of the evaluated cells, in a phase of their own (one
+  // thread per face point), so that their registers do not add to the volume
+  // part's.  Only tiles at the boundary of the rectangle have any.
+  const int hxe = min(HX - OFF, g.nx - cx0), hye = min(HY - OFF, g.ny - cy0);  // owned cells
+  if (cx0 == 0 || cy0 == 0 || cx0 + hxe == g.nx || cy0 + hye == g.ny) {
     for (int p = t; p < 4 * HX * 6; p += kThreads) {
       const int side = p / (HX * 6), r = p % (HX * 6);
       const int j = r / 6, q = (r >> 1) % 3, fmu = r & 1;
-      int fhx, fhy;
+      int fhx, fhy;  // evaluated-cell coordinates in the tile
       if (side < 2) {
-        fhx = (side == 0 ? 0 : g.nx - 1) - cx0 + 1;
+        fhx = (side == 0 ? 0 : g.nx - 1) - cx0 + OFF;
         fhy = j;
       } else {
         fhx = j;
-        fhy = (side == 2 ? 0 : g.ny - 1) - cy0 + 1;
+        fhy = (side == 2 ? 0 : g.ny - 1) - cy0 + OFF;
       }
-      const int fcx = cx0 - 1 + fhx, fcy = cy0 - 1 + fhy;
+      const int fcx = cx0 - OFF + fhx, fcy = cy0 - OFF + fhy;
       if (fhx < 0 || fhx >= HX || fhy < 0 || fhy >= HY || fcx < 0 || fcy < 0 || fcx >= g.nx ||
           fcy >= g.ny)
         continue;
+      // a halo cell contributes to the tile's nodes but not to its pressure rows
+      const bool own = fhx >= OFF && fhy >= OFF;
       face_point<T, LIN, CONV>(m, g, tau, side, q, fmu, fcx, fcy, Xs, 2 * fhx, 2 * fhy, uk, x,
-                               acc, (fhx >= 1 && fhy >= 1) ? pacc[fmu][fhy * HX + fhx] : nullptr);
+                               acc, own ? pacc[fmu][fhy * HX + fhx] : nullptr);
     }
     __syncthreads();
   }
@@ -492,64 +524,166 @@ __global__ __launch_bounds__(kThreads, (waves_per_simd<T, CACHED>())) void cell_
   for (int i = t; i < 2 * kCells * 3; i += kThreads) {
     const int pmu = i / (kCells * 3), r = i % (kCells * 3);
     const int c = r / 3, j = r % 3;
-    const int ccx = cx0 - 1 + c % HX, ccy = cy0 - 1 + c / HX;
+    const int ccx = cx0 - OFF + c % HX, ccy = cy0 - OFF + c / HX;
     if (ccx >= cx0 && ccy >= cy0 && ccx < g.nx && ccy < g.ny) {
       const int64_t idx = (int64_t)pmu * g.ns + g.nv + 3 * ((int64_t)ccy * g.nx + ccx) + j;
       const double v = pacc[pmu][c][j];
       y[idx] = MODE ? (T)((double)b[idx] - v) : (T)v;
     }
   }
-  // owned velocity nodes: rows of at most 2 TX + 1 nodes, in a 32-wide frame
-  const int gx_end = (cx0 + TX >= g.nx) ? 2 * g.nx + 1 : 2 * (cx0 + TX);
-  const int gy_end = (cy0 + TY >= g.ny) ? 2 * g.ny + 1 : 2 * (cy0 + TY);
-  const int nox = gx_end - 2 * cx0, noy = gy_end - 2 * cy0;
-  for (int i = t; i < 4 * (2 * TY + 1) * 32; i += kThreads) {
-    const int s = i / ((2 * TY + 1) * 32), r = i % ((2 * TY + 1) * 32);
-    const int ox = r % 32, oy = r / 32;
-    if (ox < nox && oy < noy) {
-      const int64_t gn = (int64_t)(2 * cy0 + oy) * NX + (2 * cx0 + ox);
-      const int64_t idx = (int64_t)(s >> 1) * g.ns + (int64_t)(s & 1) * g.nn + gn;
-      const double v = acc[s][oy + 2][ox + 2];
-      y[idx] = MODE ? (T)((double)b[idx] - v) : (T)v;
+  if constexpr (HALO) {
+    // owned velocity nodes, complete: rows of at most 31 nodes in a 32-wide
+    // frame starting at the first owned cell's low corner
+    const int gx_end = (cx0 + hxe >= g.nx) ? 2 * g.nx + 1 : 2 * (cx0 + hxe);
+    const int gy_end = (cy0 + hye >= g.ny) ? 2 * g.ny + 1 : 2 * (cy0 + hye);
+    const int nox = gx_end - 2 * cx0, noy = gy_end - 2 * cy0;
+    for (int i = t; i < 4 * (2 * HY - 1) * 32; i += kThreads) {
+      const int s = i / ((2 * HY - 1) * 32), r = i % ((2 * HY - 1) * 32);
+      const int ox = r % 32, oy = r / 32;
+      if (ox < nox && oy < noy) {
+        const int64_t gn = (int64_t)(2 * cy0 + oy) * NX + (2 * cx0 + ox);
+        const int64_t idx = (int64_t)(s >> 1) * g.ns + (int64_t)(s & 1) * g.nn + gn;
+        const double v = acc[s][oy + 2][ox + 2];
+        y[idx] = MODE ? (T)((double)b[idx] - v) : (T)v;
+      }
+    }
+  } else {
+    // velocity nodes: unshared ones complete, to y; those on an edge shared
+    // with another tile as partial sums, to the tile's slice of the edge buffer
+    double* te = edge + (int64_t)tile * 4 * kPerim;
+    const bool shl = cx0 > 0, shr = cx0 + hxe < g.nx, shb = cy0 > 0, sht = cy0 + hye < g.ny;
+    for (int i = t; i < 4 * BY * BX; i += kThreads) {
+      const int s = i / (BY * BX), r = i % (BY * BX);
+      const int ly = r / BX, lx = r % BX;
+      if (lx > 2 * hxe || ly > 2 * hye) continue;
+      const double v = acc[s][ly][lx];
+      const bool shared = (lx == 0 && shl) || (lx == 2 * hxe && shr) || (ly == 0 && shb) ||
+                          (ly == 2 * hye && sht);
+      if (shared) {
+        te[s * kPerim + perim_index(lx, ly)] = v;
+      } else {
+        const int64_t gn = (int64_t)(gy0 + ly) * NX + (gx0 + lx);
+        const int64_t idx = (int64_t)(s >> 1) * g.ns + (int64_t)(s & 1) * g.nn + gn;
+        y[idx] = MODE ? (T)((double)b[idx] - v) : (T)v;
+      }
     }
   }
 }
 
+// Tiles without halo: nodes on tile edges shared by 2 or 4 tiles get
+// y = the sum of the tiles' partial sums (tiles in increasing order), or
+// b - sum.  One thread per node of a shared tile boundary and velocity field:
+// the vertical boundaries first, then the horizontal ones, whose nodes on a
+// vertical boundary were done there.
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void edge_sum_kernel(Grid g, const double* __restrict__ edge,
+                                                       const T* __restrict__ b,
+                                                       T* __restrict__ y, int tiles_x,
+                                                       int tiles_y) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int NX = 2 * g.nx + 1, NY = 2 * g.ny + 1;
+  const int nvl = tiles_x - 1, nhl = tiles_y - 1;  // shared boundaries
+  const int64_t nvert = (int64_t)nvl * NY;
+  const int64_t nhor = (int64_t)nhl * NX;
+  const int s = (int)(id & 3);
+  const int64_t nid = id >> 2;
+  if (nid >= nvert + nhor) return;
+  int gx, gy;
+  const bool onv_line = nid < nvert;
+  if (onv_line) {
+    gx = 2 * HX * (int)(nid / NY + 1);
+    gy = (int)(nid % NY);
+  } else {
+    const int64_t h = nid - nvert;
+    gy = 2 * HY * (int)(h / NX + 1);
+    gx = (int)(h % NX);
+  }
+  const bool onv = gx % (2 * HX) == 0 && gx > 0 && gx / (2 * HX) <= nvl;
+  if (!onv_line && onv) return;  // done by the vertical pass
+  int txs[2], lxs[2], nxt = 0, tys[2], lys[2], nyt = 0;
+  if (onv) {
+    txs[0] = gx / (2 * HX) - 1; lxs[0] = 2 * HX;
+    txs[1] = gx / (2 * HX);     lxs[1] = 0;
+    nxt = 2;
+  } else {
+    txs[0] = min(gx / (2 * HX), tiles_x - 1); lxs[0] = gx - 2 * HX * txs[0];
+    nxt = 1;
+  }
+  if (gy % (2 * HY) == 0 && gy > 0 && gy / (2 * HY) <= nhl) {
+    tys[0] = gy / (2 * HY) - 1; lys[0] = 2 * HY;
+    tys[1] = gy / (2 * HY);     lys[1] = 0;
+    nyt = 2;
+  } else {
+    tys[0] = min(gy / (2 * HY), tiles_y - 1); lys[0] = gy - 2 * HY * tys[0];
+    nyt = 1;
+  }
+  double v = 0.0;
+  for (int a = 0; a < nyt; ++a)
+    for (int c = 0; c < nxt; ++c) {
+      const int64_t tl = (int64_t)tys[a] * tiles_x + txs[c];
+      v += edge[(tl * 4 + s) * kPerim + perim_index(lxs[c], lys[a])];
+    }
+  const int64_t idx = (int64_t)(s >> 1) * g.ns + (int64_t)(s & 1) * g.nn + (int64_t)gy * NX + gx;
+  y[idx] = MODE ? (T)((double)b[idx] - v) : (T)v;
+}
+
 template <typename T, int LIN, bool CONV, bool CACHED>
 hipError_t launch4(const Grid& g, const Model& m, double tau, const T* uk, const T* cache,
-                   const T* x, const T* b, T* y, int mode, hipStream_t s) {
-  const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY;
+                   const T* x, const T* b, T* y, double* edge, int mode, hipStream_t s) {
+  constexpr int OFF = halo_tiles<T, CACHED>() ? 1 : 0;
+  const int tx = (g.nx + HX - OFF - 1) / (HX - OFF), ty = (g.ny + HY - OFF - 1) / (HY - OFF);
   dim3 grid(tx * ty), block(kThreads);
   if (mode == 0)
     hipLaunchKernelGGL((cell_apply_kernel<T, LIN, CONV, 0, CACHED>), grid, block, 0, s, g, m, tau,
-                       uk, cache, x, b, y, tx);
+                       uk, cache, x, b, y, edge, tx);
   else
     hipLaunchKernelGGL((cell_apply_kernel<T, LIN, CONV, 1, CACHED>), grid, block, 0, s, g, m, tau,
-                       uk, cache, x, b, y, tx);
+                       uk, cache, x, b, y, edge, tx);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || OFF) return e;
+  const int nvl = tx - 1, nhl = ty - 1;
+  const int64_t nshared = (int64_t)nvl * (2 * g.ny + 1) + (int64_t)nhl * (2 * g.nx + 1);
+  if (nshared == 0) return hipSuccess;
+  const dim3 eg((unsigned)((4 * nshared + 255) / 256));
+  if (mode == 0)
+    hipLaunchKernelGGL((edge_sum_kernel<T, 0>), eg, dim3(256), 0, s, g, (const double*)edge, b, y,
+                       tx, ty);
+  else
+    hipLaunchKernelGGL((edge_sum_kernel<T, 1>), eg, dim3(256), 0, s, g, (const double*)edge, b, y,
+                       tx, ty);
   return hipGetLastError();
 }
 
 template <typename T, int LIN>
 hipError_t launch2(const Grid& g, const Model& m, double tau, const T* uk, const T* cache,
-                   const T* x, const T* b, T* y, int mode, hipStream_t s) {
+                   const T* x, const T* b, T* y, double* edge, int mode, hipStream_t s) {
   if (cache)
-    return m.convection ? launch4<T, LIN, true, true>(g, m, tau, uk, cache, x, b, y, mode, s)
-                        : launch4<T, LIN, false, true>(g, m, tau, uk, cache, x, b, y, mode, s);
-  return m.convection ? launch4<T, LIN, true, false>(g, m, tau, uk, cache, x, b, y, mode, s)
-                      : launch4<T, LIN, false, false>(g, m, tau, uk, cache, x, b, y, mode, s);
+    return m.convection
+               ? launch4<T, LIN, true, true>(g, m, tau, uk, cache, x, b, y, edge, mode, s)
+               : launch4<T, LIN, false, true>(g, m, tau, uk, cache, x, b, y, edge, mode, s);
+  return m.convection
+             ? launch4<T, LIN, true, false>(g, m, tau, uk, cache, x, b, y, edge, mode, s)
+             : launch4<T, LIN, false, false>(g, m, tau, uk, cache, x, b, y, edge, mode, s);
 }
 
 }  // namespace
 
 template <typename T>
 hipError_t launch_cell_apply(const Grid& g, const Model& m, double tau, const T* uk, const T* cache,
-                             const T* x, const T* b, T* y, int mode, hipStream_t s) {
+                             const T* x, const T* b, T* y, double* edge, int mode,
+                             hipStream_t s) {
   switch (m.lin) {
-    case PNS_PICARD: return launch2<T, PNS_PICARD>(g, m, tau, uk, cache, x, b, y, mode, s);
+    case PNS_PICARD: return launch2<T, PNS_PICARD>(g, m, tau, uk, cache, x, b, y, edge, mode, s);
     case PNS_EXACT_NEWTON:
-      return launch2<T, PNS_EXACT_NEWTON>(g, m, tau, uk, cache, x, b, y, mode, s);
-    default: return launch2<T, PNS_MODIFIED_NEWTON>(g, m, tau, uk, cache, x, b, y, mode, s);
+      return launch2<T, PNS_EXACT_NEWTON>(g, m, tau, uk, cache, x, b, y, edge, mode, s);
+    default:
+      return launch2<T, PNS_MODIFIED_NEWTON>(g, m, tau, uk, cache, x, b, y, edge, mode, s);
   }
+}
+
+int64_t cell_apply_edge_doubles(const Grid& g) {
+  const int64_t tx = (g.nx + HX - 1) / HX, ty = (g.ny + HY - 1) / HY;
+  return tx * ty * 4 * kPerim;
 }
 
 template <typename T>
@@ -575,10 +709,10 @@ hipError_t launch_tangent_cache(const Grid& g, const Model& m, double tau, const
 
 template hipError_t launch_cell_apply<double>(const Grid&, const Model&, double, const double*,
                                               const double*, const double*, const double*, double*,
-                                              int, hipStream_t);
+                                              double*, int, hipStream_t);
 template hipError_t launch_cell_apply<float>(const Grid&, const Model&, double, const float*,
-                                             const float*, const float*, const float*, float*, int,
-                                             hipStream_t);
+                                             const float*, const float*, const float*, float*,
+                                             double*, int, hipStream_t);
 template hipError_t launch_tangent_cache<double>(const Grid&, const Model&, double, const double*,
                                                  double*, hipStream_t);
 template hipError_t launch_tangent_cache<float>(const Grid&, const Model&, double, const double*,

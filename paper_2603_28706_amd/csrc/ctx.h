@@ -67,6 +67,7 @@ struct pns_ctx {
   int apply_mode = PNS_APPLY_RECOMPUTE;
   int patch_kind = PNS_PATCH_SURROGATE;  // finest-level patch matrices
   void* tcache = nullptr;  // per-point tangent coefficients of level 0
+  double* edge2 = nullptr;  // 2D action: per-tile partial sums on shared tile edges
   void* E3 = nullptr;      // 3D: per-cell results of the action (170 per cell)
   // 3D FP64 residual: state copy, left-trace term, per-cell slots of the action
   double* r3u = nullptr;

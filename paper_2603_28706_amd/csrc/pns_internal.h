@@ -125,7 +125,11 @@ inline Grid3 make_grid3(int nx, int ny, int nz, double lx, double ly, double lz)
 // per-point coefficients written by launch_tangent_cache are read
 template <typename T>
 hipError_t launch_cell_apply(const Grid& g, const Model& m, double tau, const T* uk, const T* cache,
-                             const T* x, const T* b, T* y, int mode, hipStream_t s);
+                             const T* x, const T* b, T* y, double* edge, int mode,
+                             hipStream_t s);
+// doubles of the edge buffer of launch_cell_apply (per tile without halo:
+// 4 fields x 96 perimeter nodes of partial sums)
+int64_t cell_apply_edge_doubles(const Grid& g);
 template <typename T>
 hipError_t launch_tangent_cache(const Grid& g, const Model& m, double tau, const double* uk,
                                 T* cache, hipStream_t s);
