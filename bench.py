@@ -460,8 +460,7 @@ def solve3d_latency(n=32, rtol=1e-8, max_newton=60, rho=0.9):
                          device="cuda")
     out = {}
     for prec, name in ((pnsmg.FP64, "fp64"), (pnsmg.FP32, "mixed")):
-        ctx = pnsmg.Context((n, n, n), n_levels=4, precision=prec)
-        ctx.pns_set_patch_kind(pnsmg.PATCH_EXACT)
+        ctx = pnsmg.Context((n, n, n), n_levels=4, precision=prec, patch_kind=pnsmg.PATCH_EXACT)
         sz = ctx.sizes()
         U = torch.zeros(sz["nst"], dtype=torch.float64, device="cuda")
         U[:sz["nv"]] = vprev

@@ -149,7 +149,11 @@ const char* pns_last_error(const pns_ctx* ctx);
 int pns_level_sizes(const pns_ctx* ctx, int level, int64_t out[4]);
 
 /* Bytes of device workspace the context needs (all levels, smoother data,
- * coarse inverse) and its required alignment (256). */
+ * coarse inverse) and its required alignment (256).  On hexahedra the
+ * level-0 smoother storage follows the patch kind selected at the time of
+ * the query (FP64 per cell: ~173 KB surrogate, ~347 KB exact, plus 58 KB of
+ * second-node cell matrices with two or more levels), so select the kind
+ * first. */
 size_t pns_workspace_bytes(const pns_ctx* ctx);
 
 /* Bind a caller-owned device buffer of at least pns_workspace_bytes bytes,
@@ -169,7 +173,10 @@ int pns_set_apply_mode(pns_ctx* ctx, int mode);
 
 /* Select the finest-level patch matrices (default PNS_PATCH_SURROGATE); a
  * change takes effect at the next pns_vanka_setup (until then the context has
- * no smoother).  PNS_EINVAL for an unknown kind.  PNS_PATCH_EXACT restricts
+ * no smoother).  PNS_EINVAL for an unknown kind.  On a hexahedral context
+ * with a workspace bound that is too small for the new kind's level-0
+ * storage: PNS_EWORKSPACE, kind unchanged (state and action data are kept
+ * either way).  PNS_PATCH_EXACT restricts
  * the exact slab operator (each Radau node with its own state); on hexahedra
  * it is needed when the velocity varies by O(1) across the slab, where the
  * midpoint-frozen surrogate stops preconditioning. */

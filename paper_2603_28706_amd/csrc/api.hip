@@ -50,18 +50,24 @@ size_t layout(pns_ctx* c, bool bind) {
     c->r3u = (double*)take(2 * g0.nv * 8);
     c->r3b = (double*)take(g0.nst * 8);
     c->r3slot = (double*)take(g0.nc * 170 * 8);
+    // Level-0 smoother storage follows the patch kind current at sizing time
+    // (it dominates the footprint): the surrogate's midpoint cell matrices
+    // share the buffer of the Radau-node-1 matrices (they are consumed before
+    // those are formed), the Radau-node-2 matrices exist only for exact
+    // patches or for the Galerkin product of a second level.
+    const bool exact = c->patch_kind == PNS_PATCH_EXACT;
     c->urep = (double*)take(g0.nv * 8);
-    c->Esr = (double*)take(g0.nc * 85 * 85 * 8);
     c->status = (int*)take(sizeof(int) * 4);
     c->Es0 = (double*)take(g0.nc * 85 * 85 * 8);
-    c->Es1 = (double*)take(g0.nc * 85 * 85 * 8);
+    c->Esr = c->Es0;
+    c->Es1 = (exact || c->nlev >= 2) ? (double*)take(g0.nc * 85 * 85 * 8) : nullptr;
     for (int l = 0; l < c->nlev; ++l) {
       Level& L = c->lev[l];
       const bool coarsest = l == c->nlev - 1;
       L.res = take(L.g.nst * es);
       if (l == 0) {
-        // complex 85 x 85 time-diagonal surrogate inverses or real 170 x 170 exact ones
-        L.inv = take(L.g.nc * kE * es);
+        // real 170 x 170 exact inverses or complex 85 x 85 time-diagonal ones
+        L.inv = take(L.g.nc * (exact ? kE : 2 * 85 * 85) * es);
         continue;
       }
       L.E64 = (double*)take(L.g.nc * kE * 8);
@@ -337,6 +343,12 @@ int vanka_setup3d(pns_ctx* c) {
   const Grid3& g0 = c->lev[0].g3;
   PNS_HIP(c, hipMemsetAsync(c->status, 0, sizeof(int), s));
   const bool exact = c->patch_kind == PNS_PATCH_EXACT;
+  if (!exact) {
+    // level 0: surrogate patches, all state-dependent coefficients at t_rep;
+    // Esr is the buffer of Es0, so this comes first (stream order)
+    PNS_HIP(c, launch_element_matrices3d(g0, c->model, c->urep, c->Esr, s));
+    PNS_HIP(c, launch_patches3d<T>(g0, c->disc.tau, c->Esr, (T*)c->lev[0].inv, c->status, s));
+  }
   if (c->nlev >= 2 || exact) {
     PNS_HIP(c, launch_element_matrices3d(g0, c->model, c->uk64, c->Es0, s));
     PNS_HIP(c, launch_element_matrices3d(g0, c->model, c->uk64 + g0.nv, c->Es1, s));
@@ -345,10 +357,6 @@ int vanka_setup3d(pns_ctx* c) {
     // level 0: exact patches, each Radau node with its own spatial matrices
     PNS_HIP(c, launch_exact_fine_patches3d<T>(g0, c->disc.tau, c->Es0, c->Es1,
                                               (T*)c->lev[0].inv, c->status, s));
-  } else {
-    // level 0: surrogate patches, all state-dependent coefficients at t_rep
-    PNS_HIP(c, launch_element_matrices3d(g0, c->model, c->urep, c->Esr, s));
-    PNS_HIP(c, launch_patches3d<T>(g0, c->disc.tau, c->Esr, (T*)c->lev[0].inv, c->status, s));
   }
   for (int l = 1; l < c->nlev; ++l) {
     Level& L = c->lev[l];
@@ -721,10 +729,23 @@ int pns_set_patch_kind(pns_ctx* ctx, int kind) {
   if (!ctx) return PNS_EINVAL;
   if (kind != PNS_PATCH_SURROGATE && kind != PNS_PATCH_EXACT)
     return fail(ctx, PNS_EINVAL, "unknown patch kind");
-  if (kind != ctx->patch_kind) {
-    ctx->has_smoother = false;
-    ctx->drop_graph();
+  if (kind == ctx->patch_kind) return PNS_OK;
+  if (ctx->dim == 3 && ctx->ws) {
+    // the level-0 smoother storage depends on the kind; everything laid out
+    // before it (state, action buffers) keeps its place
+    const int old = ctx->patch_kind;
+    ctx->patch_kind = kind;
+    const size_t need = layout(ctx, false);
+    if (need > ctx->ws_bytes) {
+      ctx->patch_kind = old;
+      return fail(ctx, PNS_EWORKSPACE,
+                  "bound workspace too small for this patch kind: need " + std::to_string(need) +
+                      " bytes (select the kind before pns_workspace_bytes)");
+    }
+    layout(ctx, true);
   }
+  ctx->has_smoother = false;
+  ctx->drop_graph();
   ctx->patch_kind = kind;
   return PNS_OK;
 }

@@ -160,9 +160,11 @@ class Context:
     """One pns_ctx with its workspace (a torch uint8 tensor on the device)."""
 
     def __init__(self, n, n_levels=1, precision=FP64, tau=0.01, lo=None, hi=None,
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, patch_kind=None):
         """n: cells per direction, 2 entries (quadrilaterals) or 3 (hexahedra:
-        action, smoother and V-cycle); lo/hi default to the unit square or cube."""
+        action, smoother and V-cycle); lo/hi default to the unit square or cube.
+        patch_kind is selected before the workspace is sized (on hexahedra the
+        exact kind needs about twice the level-0 smoother storage)."""
         import torch
 
         self.torch = torch
@@ -189,6 +191,8 @@ class Context:
         self.h = h
         self.dim = dim
         self.n_levels = n_levels
+        if patch_kind is not None:
+            self._check(lib().pns_set_patch_kind(self.h, int(patch_kind)))
         nbytes = lib().pns_workspace_bytes(self.h)
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
         base = self.ws.data_ptr()

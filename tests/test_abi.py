@@ -72,8 +72,10 @@ def test_3d_context_layout_and_rejections():
     """A hexahedral context: unknown counts of Q2^3 / P1disc x dG(1); the
     workspace holds the state, the per-cell results of the action and the
     finest-level smoother (midpoint state, FP64 cell matrices, complex 85 x 85
-    patch inverses, defect) and the FP64 residual's buffers; a one-level
-    V-cycle and exact or truncated patches are rejected before any device
+    patch inverses, defect) and the FP64 residual's buffers; the exact patch
+    kind adds the second Radau node's cell matrices and doubles the inverse
+    storage, and a bound workspace too small for it rejects the switch; a
+    one-level V-cycle and truncated patches are rejected before any device
     work."""
     rc, h = _create(n=(32, 32, 32))
     assert rc == pnsmg.PNS_OK
@@ -87,12 +89,30 @@ def test_3d_context_layout_and_rejections():
     nbytes = L.pns_workspace_bytes(h)
     es = 8
     kE = 170 * 170
-    # state, action slots, residual buffers, midpoint state, three sets of
-    # spatial cell matrices, defect, patch inverses (room for the real exact
-    # form)
-    need = (2 * nv * (es + 8) + 32768 * 170 * es + 2 * nv * 8 + nst * 8 + 32768 * 170 * 8
-            + nv * 8 + 3 * 32768 * 85 * 85 * 8 + 16 + nst * es + 32768 * kE * es)
+    # state, action slots, residual buffers, midpoint state, one set of
+    # spatial cell matrices, defect, complex 85 x 85 patch inverses
+    base = 2 * nv * (es + 8) + 32768 * 170 * es + 2 * nv * 8 + nst * 8 + 32768 * 170 * 8
+    need = base + nv * 8 + 16 + 32768 * 85 * 85 * 8 + nst * es + 32768 * 2 * 85 * 85 * es
     assert need <= nbytes < need + 4096
+    # exact patches: both Radau nodes' cell matrices, real 170 x 170 inverses
+    assert L.pns_set_patch_kind(h, pnsmg.PATCH_EXACT) == pnsmg.PNS_OK
+    need_x = base + nv * 8 + 16 + 2 * 32768 * 85 * 85 * 8 + nst * es + 32768 * kE * es
+    nbytes_x = L.pns_workspace_bytes(h)
+    assert need_x <= nbytes_x < need_x + 4096
+    assert L.pns_set_patch_kind(h, pnsmg.PATCH_SURROGATE) == pnsmg.PNS_OK
+    assert L.pns_workspace_bytes(h) == nbytes
+    # binding does no device work: a surrogate-sized buffer refuses the switch
+    fake = ctypes.c_void_p(1 << 40)
+    assert L.pns_bind_workspace(h, fake, ctypes.c_size_t(nbytes)) == pnsmg.PNS_OK
+    assert L.pns_set_patch_kind(h, pnsmg.PATCH_EXACT) == pnsmg.PNS_EWORKSPACE
+    assert b"too small" in L.pns_last_error(h)
+    assert L.pns_set_patch_kind(h, pnsmg.PATCH_SURROGATE) == pnsmg.PNS_OK
+    assert L.pns_bind_workspace(h, fake, ctypes.c_size_t(nbytes_x)) == pnsmg.PNS_OK
+    assert L.pns_set_patch_kind(h, pnsmg.PATCH_EXACT) == pnsmg.PNS_OK
+    assert L.pns_workspace_bytes(h) == nbytes_x
+    L.pns_ctx_destroy(h)
+    rc, h = _create(n=(32, 32, 32))
+    assert rc == pnsmg.PNS_OK
     # FGMRES(30) vectors: 31 + 30 Krylov vectors and 6 work vectors of N_st FP64
     assert L.pns_solve_workspace_bytes(h, 30) >= (61 + 6) * nst * 8
     assert L.pns_set_apply_mode(h, pnsmg.APPLY_CACHED) == pnsmg.PNS_EUNSUPPORTED
@@ -124,9 +144,9 @@ def test_3d_context_layout_and_rejections():
         sizes.append((out[0], out[1]))
     assert sizes == [(33574, 512), (4886, 64), (814, 8)]
     kE = 170 * 170
-    need = (2 * 3 * 17 ** 3 * 16 + 512 * 170 * 8 + 3 * 17 ** 3 * 8 + 3 * 512 * 85 * 85 * 8 + 16
+    need = (2 * 3 * 17 ** 3 * 16 + 512 * 170 * 8 + 3 * 17 ** 3 * 8 + 2 * 512 * 85 * 85 * 8 + 16
             + 2 * 3 * 17 ** 3 * 8 + 33574 * 8 + 512 * 170 * 8
-            + 33574 * 8 + 512 * kE * 8
+            + 33574 * 8 + 512 * 2 * 85 * 85 * 8
             + 4886 * 8 * 3 + 64 * kE * 16 + 64 * kE * 8
             + 814 * 8 * 3 + 8 * kE * 16
             + 814 * 814 * 8 + (3 * 64 * 814 + 4 * 13 + 8) * 8 + 814 * 4)
@@ -152,8 +172,8 @@ def test_3d_context_layout_and_rejections():
     nn = 9 * 5 * 7
     nc = 24
     nst = 2 * (3 * nn + 4 * nc)
-    need = (2 * 3 * nn * (4 + 8) + nc * 170 * 4 + 3 * nn * 8 + 3 * nc * 85 * 85 * 8 + 16
-            + nc * 170 * 170 * 4 + nst * 4 + 2 * 3 * nn * 8 + nst * 8 + nc * 170 * 8)
+    need = (2 * 3 * nn * (4 + 8) + nc * 170 * 4 + 3 * nn * 8 + nc * 85 * 85 * 8 + 16
+            + nc * 2 * 85 * 85 * 4 + nst * 4 + 2 * 3 * nn * 8 + nst * 8 + nc * 170 * 8)
     assert need <= L.pns_workspace_bytes(h) < need + 4096
     L.pns_ctx_destroy(h)
 

@@ -112,8 +112,7 @@ def test_solve3d_exact_patches_small():
     prob = oracle_problem(n, model)
     vprev = inputs.sin_series_velocity(n, seed=302, t_nodes=[0.0])
     rtol = 1e-10
-    ctx = pnsmg.Context(n, n_levels=2, precision=pnsmg.FP64)
-    ctx.pns_set_patch_kind(pnsmg.PATCH_EXACT)
+    ctx = pnsmg.Context(n, n_levels=2, precision=pnsmg.FP64, patch_kind=pnsmg.PATCH_EXACT)
     U = dev(O.state_from_velocity(prob, np.concatenate([vprev, vprev])))
     rc, info = ctx.pns_solve(model, dev(vprev), U, rtol=rtol, omega=OMEGA3)
     torch.cuda.synchronize()
@@ -136,8 +135,7 @@ def test_solve3d_32cubed_to_1e8():
     n = (32, 32, 32)
     vprev = inputs.sin_series_velocity(n, seed=301, t_nodes=[0.0])
     for prec in (pnsmg.FP64, pnsmg.FP32):
-        ctx = pnsmg.Context(n, n_levels=4, precision=prec)
-        ctx.pns_set_patch_kind(pnsmg.PATCH_EXACT)
+        ctx = pnsmg.Context(n, n_levels=4, precision=prec, patch_kind=pnsmg.PATCH_EXACT)
         sz = ctx.sizes()
         U = torch.zeros(sz["nst"], dtype=torch.float64, device="cuda")
         vp = dev(vprev)

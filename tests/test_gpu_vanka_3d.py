@@ -201,8 +201,8 @@ def test_vanka3d_exact_patches(n, hi):
     ref1 = O.vanka_step(A, pm, patches, r, np.zeros(prob.nst), 0.5)
     ref2 = O.vanka_step(A, pm, patches, r, ref1, 0.5)
     for prec, dt, tol in ((pnsmg.FP64, torch.float64, 1e-10), (pnsmg.FP32, torch.float32, 1e-4)):
-        ctx = pnsmg.Context(n, n_levels=1, precision=prec, tau=0.01, hi=hi)
-        ctx.pns_set_patch_kind(pnsmg.PATCH_EXACT)
+        ctx = pnsmg.Context(n, n_levels=1, precision=prec, tau=0.01, hi=hi,
+                            patch_kind=pnsmg.PATCH_EXACT)
         ctx.pns_set_state(dict(MODEL3, lin=lin), to_dev(uk, torch.float64))
         ctx.pns_vanka_setup()
         d = ctx.vector()

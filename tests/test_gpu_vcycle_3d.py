@@ -147,8 +147,7 @@ def test_vcycle_3d_exact_fine_patches():
     H = O.build_hierarchy(prob, uk, n_levels=2, surrogate=False)
     ref = O.vcycle(H, r, nu1=2, nu2=2, omega=0.15)
     for prec, dt, tol in ((pnsmg.FP64, torch.float64, 1e-10), (pnsmg.FP32, torch.float32, 1e-4)):
-        ctx = pnsmg.Context(n, n_levels=2, precision=prec, tau=0.01)
-        ctx.pns_set_patch_kind(pnsmg.PATCH_EXACT)
+        ctx = pnsmg.Context(n, n_levels=2, precision=prec, tau=0.01, patch_kind=pnsmg.PATCH_EXACT)
         ctx.pns_set_state(dict(MODEL3, lin=LIN), to_dev(uk, torch.float64))
         ctx.pns_vanka_setup()
         d = ctx.vector()
