@@ -735,7 +735,7 @@ int pns_set_patch_kind(pns_ctx* ctx, int kind) {
     // before it (state, action buffers) keeps its place
     const int old = ctx->patch_kind;
     ctx->patch_kind = kind;
-    const size_t need = layout(ctx, false);
+    const size_t need = pns_workspace_bytes(ctx);  // measures on a copy
     if (need > ctx->ws_bytes) {
       ctx->patch_kind = old;
       return fail(ctx, PNS_EWORKSPACE,

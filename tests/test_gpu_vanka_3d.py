@@ -110,7 +110,14 @@ def test_vanka3d_two_cells_and_zero_residual():
     uk = inputs.uniform(521, prob.nt * prob.nv)
     r = inputs.uniform(522, prob.nst)
     ref = oracle_steps(prob, uk, r, 1.0, 1)[0]
-    ctx = gpu_context(n, MODEL3, pnsmg.MODIFIED_NEWTON, uk, pnsmg.FP64)
+    ctx = pnsmg.Context(n, n_levels=1, precision=pnsmg.FP64, tau=0.01)
+    ctx.pns_set_state(dict(MODEL3, lin=pnsmg.MODIFIED_NEWTON), to_dev(uk, torch.float64))
+    # the workspace was sized for surrogate patches: the switch is refused and
+    # the context keeps its state and kind
+    with pytest.raises(pnsmg.PnsError) as e:
+        ctx.pns_set_patch_kind(pnsmg.PATCH_EXACT)
+    assert e.value.code == pnsmg.PNS_EWORKSPACE
+    ctx.pns_vanka_setup()
     d = ctx.vector()
     ctx.pns_vanka_smooth(0, 1, 1.0, to_dev(r, torch.float64), d)
     torch.cuda.synchronize()
