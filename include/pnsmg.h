@@ -131,9 +131,8 @@ typedef struct pns_ctx pns_ctx;
  * smoother.  `stream` is a hipStream_t (NULL =
  * default stream).  A dim = 3 mesh (hexahedra, n_cells divisible by
  * 2^(n_levels-1) in every direction) supports every entry point below except
- * node masks in pns_vanka_setup and graph replay (pns_set_vcycle_graph);
- * pns_vcycle and pns_solve need at least two levels (the dense coarsest
- * inverse is formed only then).
+ * node masks in pns_vanka_setup; pns_vcycle and pns_solve need at least two
+ * levels (the dense coarsest inverse is formed only then).
  * Returns PNS_EINVAL / PNS_EUNSUPPORTED on bad input. */
 int pns_ctx_create(const pns_mesh* mesh, const pns_discretization* disc, int n_levels,
                    int precision, void* stream, pns_ctx** out);
@@ -263,7 +262,7 @@ int pns_vcycle(pns_ctx* ctx, int nu1, int nu2, double omega, const void* r_dev, 
  * pns_vanka_setup, pns_set_apply_mode, pns_set_patch_kind and
  * pns_bind_workspace; r and d pass through two workspace vectors (two copies
  * per V-cycle).  enable = 0 returns to eager launches.  PNS_EINVAL for other
- * values, PNS_EUNSUPPORTED on 3D contexts. */
+ * values, PNS_EUNSUPPORTED on BF16 contexts (no V-cycle). */
 int pns_set_vcycle_graph(pns_ctx* ctx, int enable);
 
 /* y = A_l x with the level-l operator (level 0: pns_cell_apply; coarser:

@@ -50,6 +50,10 @@ size_t layout(pns_ctx* c, bool bind) {
     c->r3u = (double*)take(2 * g0.nv * 8);
     c->r3b = (double*)take(g0.nst * 8);
     c->r3slot = (double*)take(g0.nc * 170 * 8);
+    if (c->nlev >= 2) {  // right-hand side and correction of graph-replayed V-cycles
+      c->gr = take(g0.nst * es);
+      c->gd = take(g0.nst * es);
+    }
     // Level-0 smoother storage follows the patch kind current at sizing time
     // (it dominates the footprint): the surrogate's midpoint cell matrices
     // share the buffer of the Radau-node-1 matrices (they are consumed before
@@ -640,7 +644,8 @@ int pns_set_sweep_variant(pns_ctx* ctx, int level, int variant) {
 int pns_set_vcycle_graph(pns_ctx* ctx, int enable) {
   if (!ctx) return PNS_EINVAL;
   if (enable != 0 && enable != 1) return fail(ctx, PNS_EINVAL, "enable must be 0 or 1");
-  if (enable && ctx->dim == 3) return fail(ctx, PNS_EUNSUPPORTED, "3D contexts have no V-cycle");
+  if (enable && ctx->prec == PNS_BF16)
+    return fail(ctx, PNS_EUNSUPPORTED, "BF16 contexts have the action only");
   ctx->graph_mode = enable == 1;
   if (!enable) ctx->drop_graph();
   return PNS_OK;

@@ -131,11 +131,15 @@ def test_3d_context_layout_and_rejections():
     assert L.pns_solve(h, ctypes.byref(model), v, w, None, None, 0,
                        ctypes.byref(info)) == pnsmg.PNS_EWORKSPACE
     assert L.pns_cell_apply(h, v, w) == pnsmg.PNS_EWORKSPACE
-    assert L.pns_set_vcycle_graph(h, 1) == pnsmg.PNS_EUNSUPPORTED
+    # graph mode may be switched on; the one-level V-cycle itself is refused
+    assert L.pns_set_vcycle_graph(h, 1) == pnsmg.PNS_OK
+    assert L.pns_vcycle(h, 1, 1, ctypes.c_double(0.1), v, w) == pnsmg.PNS_EUNSUPPORTED
+    assert L.pns_set_vcycle_graph(h, 0) == pnsmg.PNS_OK
     L.pns_ctx_destroy(h)
-    # three levels 8^3 -> 4^3 -> 2^3: level-0 matrices of both Radau nodes,
-    # Galerkin matrices (FP64 and transposed copies), real inverses of level 1,
-    # the dense coarsest inverse
+    # three levels 8^3 -> 4^3 -> 2^3: the two vectors of graph-replayed
+    # V-cycles, level-0 matrices of both Radau nodes, Galerkin matrices (FP64
+    # and transposed copies), real inverses of level 1, the dense coarsest
+    # inverse
     rc, h = _create(n=(8, 8, 8), levels=3)
     assert rc == pnsmg.PNS_OK
     sizes = []
@@ -145,7 +149,7 @@ def test_3d_context_layout_and_rejections():
     assert sizes == [(33574, 512), (4886, 64), (814, 8)]
     kE = 170 * 170
     need = (2 * 3 * 17 ** 3 * 16 + 512 * 170 * 8 + 3 * 17 ** 3 * 8 + 2 * 512 * 85 * 85 * 8 + 16
-            + 2 * 3 * 17 ** 3 * 8 + 33574 * 8 + 512 * 170 * 8
+            + 2 * 3 * 17 ** 3 * 8 + 33574 * 8 + 512 * 170 * 8 + 2 * 33574 * 8
             + 33574 * 8 + 512 * 2 * 85 * 85 * 8
             + 4886 * 8 * 3 + 64 * kE * 16 + 64 * kE * 8
             + 814 * 8 * 3 + 8 * kE * 16
@@ -163,6 +167,7 @@ def test_3d_context_layout_and_rejections():
     assert L.pns_vcycle(h, 1, 1, ctypes.c_double(0.1), v, w) == pnsmg.PNS_EUNSUPPORTED
     assert L.pns_residual(h, ctypes.byref(model), v, None, w) == pnsmg.PNS_EUNSUPPORTED
     assert L.pns_solve_workspace_bytes(h, 30) == 0
+    assert L.pns_set_vcycle_graph(h, 1) == pnsmg.PNS_EUNSUPPORTED
     L.pns_ctx_destroy(h)
     assert _create(n=(4, 4, 4), levels=2, prec=pnsmg.BF16)[0] == pnsmg.PNS_EUNSUPPORTED
     assert _create(n=(8, 8), prec=pnsmg.BF16)[0] == pnsmg.PNS_EINVAL

@@ -220,3 +220,78 @@ def test_vcycle_3d_32cubed_linear_and_preconditions_gmres():
             assert hist[-1] <= 1e-6
         del ctx
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("precision,tol", [(pnsmg.FP64, 1e-13), (pnsmg.FP32, 1e-6)])
+def test_vcycle_3d_graph_replays_equal_eager_vcycles(precision, tol):
+    """Graph-replayed 3D V-cycles (8^3, 3 levels) equal the eager ones on every
+    replay, with the program's own eager work between replays; a new omega is
+    recaptured; a new state drops the graph."""
+    n = (8, 8, 8)
+    omega = 0.15
+    uk = inputs.sin_series_velocity(n, seed=681, t_nodes=[0.01 / 3, 0.01])
+    ctx = setup(n, 3, precision, uk)
+    dt = ctx.dtype
+    nst = ctx.sizes()["nst"]
+    rs = [to_dev(inputs.uniform(682 + i, nst), dt) for i in range(3)]
+    eager = []
+    for r in rs:
+        d = ctx.vector()
+        ctx.pns_vcycle(2, 2, omega, r, d)
+        eager.append(d.clone())
+    ctx.pns_set_vcycle_graph(1)
+    y = ctx.vector()
+    for rep in range(6):
+        r = rs[rep % 3]
+        d = ctx.vector()
+        ctx.pns_vcycle(2, 2, omega, r, d)
+        ctx.pns_cell_apply(r, y)
+        y.mul_(0.5)
+        torch.cuda.synchronize()
+        err = float(torch.linalg.norm((d - eager[rep % 3]).double())
+                    / torch.linalg.norm(eager[rep % 3].double()))
+        print(f"3D replay {rep}: rel diff {err:.2e} bitwise {bool(torch.equal(d, eager[rep % 3]))}")
+        assert err <= tol, (rep, err)
+    ctx.pns_set_vcycle_graph(0)
+    d_e = ctx.vector()
+    ctx.pns_vcycle(1, 1, 0.1, rs[0], d_e)
+    ctx.pns_set_vcycle_graph(1)
+    for _ in range(2):
+        d_g = ctx.vector()
+        ctx.pns_vcycle(1, 1, 0.1, rs[0], d_g)
+        torch.cuda.synchronize()
+        assert rel(d_g.double().cpu().numpy(), d_e.double().cpu().numpy()) <= tol
+    # a new linearisation state and smoother: the replay follows the new operator
+    uk2 = inputs.uniform(685, 2 * ctx.sizes()["nv"])
+    ctx.pns_set_state(dict(MODEL3, lin=LIN), to_dev(uk2, torch.float64))
+    ctx.pns_vanka_setup()
+    d1 = ctx.vector()
+    ctx.pns_vcycle(2, 2, omega, rs[0], d1)
+    ctx.pns_set_vcycle_graph(0)
+    d2 = ctx.vector()
+    ctx.pns_vcycle(2, 2, omega, rs[0], d2)
+    torch.cuda.synchronize()
+    assert rel(d1.double().cpu().numpy(), d2.double().cpu().numpy()) <= tol
+    assert rel(d1.double().cpu().numpy(), eager[0].double().cpu().numpy()) > 1e-3
+
+
+def test_solve3d_with_graph_vcycles_matches_eager_solve():
+    n = (4, 4, 4)
+    vprev = inputs.sin_series_velocity(n, seed=690, t_nodes=[0.0])
+    out = {}
+    for graph in (0, 1):
+        ctx = pnsmg.Context(n, n_levels=2, precision=pnsmg.FP64)
+        ctx.pns_set_vcycle_graph(graph)
+        sz = ctx.sizes()
+        U = torch.zeros(sz["nst"], dtype=torch.float64, device="cuda")
+        vp = to_dev(vprev, torch.float64)
+        U[:sz["nv"]] = vp
+        U[sz["ns"]:sz["ns"] + sz["nv"]] = vp
+        rc, info = ctx.pns_solve(MODEL3, vp, U, rtol=1e-10, omega=0.15)
+        torch.cuda.synchronize()
+        assert rc == pnsmg.PNS_OK, info
+        out[graph] = (info, U.cpu().numpy())
+    assert out[0][0]["newton_iterations"] == out[1][0]["newton_iterations"]
+    diff = np.linalg.norm(out[0][1] - out[1][1]) / np.linalg.norm(out[0][1])
+    print("3D graph vs eager solve:", out[1][0], f"rel diff {diff:.2e}")
+    assert diff <= 1e-9
