@@ -63,10 +63,11 @@ def algorithmic_bytes(sizes, elem):
     return (2 * sizes["nst"] + 2 * sizes["nv"]) * elem
 
 
-# FETCH_SIZE / WRITE_SIZE of the FP64 action (mean over its in-step launches),
-# each scaled by the counter's reading for a plain streaming kernel of known
-# size, with the hash of the kernel source the counters were taken on
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "cell_apply_256x256_fp64_counters.md")
+# FETCH_SIZE / WRITE_SIZE of the FP64 action (mean over its launches), each
+# scaled by the counter's reading for a plain streaming kernel of known size,
+# with the hash of the kernel source the counters were taken on; one summary
+# per mesh size
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "cell_apply_{n}x{n}_fp64_counters.md")
 # the action kernel's own source and its elementary functions (the element
 # constants it includes are fixed by the discretisation)
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2603_28706_amd", "csrc", f)
@@ -81,11 +82,12 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the action from the committed counter summary;
-    None if it is missing or the kernel source changed since it was taken."""
+def measured_traffic(n):
+    """HBM bytes per launch of the action on the n x n mesh from the committed
+    counter summary; None if there is none for that size or the kernel source
+    changed since it was taken."""
     try:
-        with open(TRAFFIC_SUMMARY) as fh:
+        with open(TRAFFIC_SUMMARY.format(n=n)) as fh:
             txt = fh.read()
     except OSError:
         return None
@@ -258,10 +260,23 @@ def apply3d(n=32, reps=50, lin=2, smoother=True, sweeps=20, vcycles=10, levels3d
             eb.record(stream)
             torch.cuda.synchronize()
             tv = ea.elapsed_time(eb) * 1e-3 / vcycles
-            out[name].update(vcycle_ms=tv * 1e3)
+            # the same V-cycle replayed from one captured HIP graph
+            ctx.pns_set_vcycle_graph(1)
+            for _ in range(2):
+                ctx.pns_vcycle(2, 2, OMEGA3D, r, d)  # capture, then one replay
+            torch.cuda.synchronize()
+            ea.record(stream)
+            for _ in range(vcycles):
+                ctx.pns_vcycle(2, 2, OMEGA3D, r, d)
+            eb.record(stream)
+            torch.cuda.synchronize()
+            tg = ea.elapsed_time(eb) * 1e-3 / vcycles
+            ctx.pns_set_vcycle_graph(0)
+            out[name].update(vcycle_ms=tv * 1e3, vcycle_graph_ms=tg * 1e3)
             out["levels"] = levels3d
             out["omega"] = OMEGA3D
-            print(f"[bench] 3D V-cycle {n}^3 {name}: {tv * 1e3:.3f} ms", file=sys.stderr, flush=True)
+            print(f"[bench] 3D V-cycle {n}^3 {name}: {tv * 1e3:.3f} ms (graph-replayed "
+                  f"{tg * 1e3:.3f} ms)", file=sys.stderr, flush=True)
         del ctx
         torch.cuda.empty_cache()
     return out
@@ -675,7 +690,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4),
-                     "traffic": measured_traffic(),
+                     "traffic": measured_traffic(args.n),
                      "kernel": "cell_apply_kernel<double, modified Newton, recompute>",
                      "flop_per_launch": flops, "algorithmic_bytes": f64["bytes"]},
     }
