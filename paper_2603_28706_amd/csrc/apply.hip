@@ -574,19 +574,22 @@ __global__ __launch_bounds__(kThreads, (waves_per_simd<T, CACHED>())) void cell_
 // y = the sum of the tiles' partial sums (tiles in increasing order), or
 // b - sum.  One thread per node of a shared tile boundary and velocity field:
 // the vertical boundaries first, then the horizontal ones, whose nodes on a
-// vertical boundary were done there.
+// vertical boundary were done there.  Index arithmetic in 32 bits (the node
+// count of the shared boundaries is far below 2^31); the up to four partial
+// sums and b are loaded before the first of them is used, so their latencies
+// overlap.
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void edge_sum_kernel(Grid g, const double* __restrict__ edge,
                                                        const T* __restrict__ b,
                                                        T* __restrict__ y, int tiles_x,
                                                        int tiles_y) {
-  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int NX = 2 * g.nx + 1, NY = 2 * g.ny + 1;
-  const int nvl = tiles_x - 1, nhl = tiles_y - 1;  // shared boundaries
-  const int64_t nvert = (int64_t)nvl * NY;
-  const int64_t nhor = (int64_t)nhl * NX;
+  const unsigned id = blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned NX = 2 * g.nx + 1, NY = 2 * g.ny + 1;
+  const unsigned nvl = tiles_x - 1, nhl = tiles_y - 1;  // shared boundaries
+  const unsigned nvert = nvl * NY;
+  const unsigned nhor = nhl * NX;
   const int s = (int)(id & 3);
-  const int64_t nid = id >> 2;
+  const unsigned nid = id >> 2;
   if (nid >= nvert + nhor) return;
   int gx, gy;
   const bool onv_line = nid < nvert;
@@ -594,37 +597,42 @@ __global__ __launch_bounds__(256) void edge_sum_kernel(Grid g, const double* __r
     gx = 2 * HX * (int)(nid / NY + 1);
     gy = (int)(nid % NY);
   } else {
-    const int64_t h = nid - nvert;
+    const unsigned h = nid - nvert;
     gy = 2 * HY * (int)(h / NX + 1);
     gx = (int)(h % NX);
   }
-  const bool onv = gx % (2 * HX) == 0 && gx > 0 && gx / (2 * HX) <= nvl;
+  const bool onv = gx % (2 * HX) == 0 && gx > 0 && gx / (2 * HX) <= (int)nvl;
   if (!onv_line && onv) return;  // done by the vertical pass
-  int txs[2], lxs[2], nxt = 0, tys[2], lys[2], nyt = 0;
+  const bool onh = gy % (2 * HY) == 0 && gy > 0 && gy / (2 * HY) <= (int)nhl;
+  // tiles (and local node coordinates) left / right of the node, below / above
+  int tx0, lx0, tx1 = 0, lx1 = 0;
   if (onv) {
-    txs[0] = gx / (2 * HX) - 1; lxs[0] = 2 * HX;
-    txs[1] = gx / (2 * HX);     lxs[1] = 0;
-    nxt = 2;
+    tx0 = gx / (2 * HX) - 1; lx0 = 2 * HX;
+    tx1 = gx / (2 * HX);     lx1 = 0;
   } else {
-    txs[0] = min(gx / (2 * HX), tiles_x - 1); lxs[0] = gx - 2 * HX * txs[0];
-    nxt = 1;
+    tx0 = min(gx / (2 * HX), tiles_x - 1); lx0 = gx - 2 * HX * tx0;
   }
-  if (gy % (2 * HY) == 0 && gy > 0 && gy / (2 * HY) <= nhl) {
-    tys[0] = gy / (2 * HY) - 1; lys[0] = 2 * HY;
-    tys[1] = gy / (2 * HY);     lys[1] = 0;
-    nyt = 2;
+  int ty0, ly0, ty1 = 0, ly1 = 0;
+  if (onh) {
+    ty0 = gy / (2 * HY) - 1; ly0 = 2 * HY;
+    ty1 = gy / (2 * HY);     ly1 = 0;
   } else {
-    tys[0] = min(gy / (2 * HY), tiles_y - 1); lys[0] = gy - 2 * HY * tys[0];
-    nyt = 1;
+    ty0 = min(gy / (2 * HY), tiles_y - 1); ly0 = gy - 2 * HY * ty0;
   }
-  double v = 0.0;
-  for (int a = 0; a < nyt; ++a)
-    for (int c = 0; c < nxt; ++c) {
-      const int64_t tl = (int64_t)tys[a] * tiles_x + txs[c];
-      v += edge[(tl * 4 + s) * kPerim + perim_index(lxs[c], lys[a])];
-    }
-  const int64_t idx = (int64_t)(s >> 1) * g.ns + (int64_t)(s & 1) * g.nn + (int64_t)gy * NX + gx;
-  y[idx] = MODE ? (T)((double)b[idx] - v) : (T)v;
+  const double* es = edge + (size_t)s * kPerim;
+  auto part = [&](int ty, int tx, int lx, int ly) {
+    return es[((size_t)ty * tiles_x + tx) * (4 * kPerim) + perim_index(lx, ly)];
+  };
+  const size_t idx = (size_t)(s >> 1) * g.ns + (size_t)(s & 1) * g.nn + (size_t)gy * NX + gx;
+  const double e00 = part(ty0, tx0, lx0, ly0);
+  const double e01 = onv ? part(ty0, tx1, lx1, ly0) : 0.0;
+  const double e10 = onh ? part(ty1, tx0, lx0, ly1) : 0.0;
+  const double e11 = (onv && onh) ? part(ty1, tx1, lx1, ly1) : 0.0;
+  const double bv = MODE ? (double)b[idx] : 0.0;
+  // tile order (0,0), (0,1), (1,0), (1,1); an absent tile adds +0, which
+  // leaves every partial sum unchanged
+  const double v = ((e00 + e01) + e10) + e11;
+  y[idx] = MODE ? (T)(bv - v) : (T)v;
 }
 
 template <typename T, int LIN, bool CONV, bool CACHED>
