@@ -186,8 +186,10 @@ int pns_set_patch_kind(pns_ctx* ctx, int kind);
  * linearisation of Sec. 5.2 (viscous volume term with the selected tangent,
  * convection, pressure coupling, boundary flux and Nitsche terms) at u_k of
  * Radau node mu.  Matrix-free; x, y in the context precision, canonical
- * layout, must not alias.  Contributions are summed with atomics, so the
- * summation order (and the last bits of y) may vary from call to call. */
+ * layout, must not alias.  On quadrilaterals the cell contributions inside
+ * a tile are summed with LDS atomics, so the last bits of y may vary from
+ * call to call; on hexahedra every sum has a fixed order (bitwise
+ * reproducible). */
 int pns_cell_apply(pns_ctx* ctx, const void* x_dev, void* y_dev);
 
 /* Same operator as pns_cell_apply, y = b - J_n x (the global defect). */

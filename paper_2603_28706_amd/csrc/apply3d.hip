@@ -30,9 +30,11 @@
 //   FP64); a wave orders its stages with wavefront-scope fences only (the LDS
 //   operations of one wave are performed in order).
 // Face kernel: one wave per boundary cell; the cell's nodal values and its
-// slot of E are staged in LDS, one lane per (boundary side, face Gauss point,
-// Radau node) evaluates the face integrand directly and adds its test
-// coefficients with LDS atomics; the slot is written back.
+// slot of E are staged in LDS; its boundary sides are taken in turn, each by
+// sum factorisation on the face (fields at the 3 x 3 face points, one lane per
+// (face point, Radau node) for the integrand, transposed contractions in
+// which every lane adds to its own entries of the slot); the slot is written
+// back.
 #include <type_traits>
 
 #include "devmath.h"
