@@ -269,14 +269,24 @@ __global__ __launch_bounds__(1024) void patch3r_kernel(Grid3 g, Src Esrc, T* __r
           const int j = part + kRP * s;
           if (j < kNst3) a[s] = rowb[j];
         }
-      } else {
+      } else if (i == p) {  // old row k moves to row p (6 threads)
         const double f = fk[i];
-        const bool isp = i == p;
 #pragma unroll
         for (int s = 0; s < kRS; ++s) {
           const int j = part + kRP * s;
           if (j < kNst3) {
-            double v = isp ? rowk[j] : a[s];
+            double v = rowk[j];
+            if (j == k) v = 0.0;
+            a[s] = v - f * rowb[j];
+          }
+        }
+      } else {  // every other row: only the new pivot row is read from LDS
+        const double f = fk[i];
+#pragma unroll
+        for (int s = 0; s < kRS; ++s) {
+          const int j = part + kRP * s;
+          if (j < kNst3) {
+            double v = a[s];
             if (j == k) v = 0.0;
             a[s] = v - f * rowb[j];
           }
