@@ -295,3 +295,36 @@ def test_solve3d_with_graph_vcycles_matches_eager_solve():
     diff = np.linalg.norm(out[0][1] - out[1][1]) / np.linalg.norm(out[0][1])
     print("3D graph vs eager solve:", out[1][0], f"rel diff {diff:.2e}")
     assert diff <= 1e-9
+
+
+def test_patch_kind_switch_keeps_the_state_of_a_bound_context():
+    """A context sized for exact patches switched to surrogate patches and back
+    re-lays out its level-0 smoother storage only: without a new
+    pns_set_state its V-cycles equal those of fresh contexts of each kind."""
+    n = (4, 4, 4)
+    prob = oracle_problem(n, MODEL3, LIN)
+    uk = inputs.uniform(695, prob.nt * prob.nv)
+    r = to_dev(inputs.uniform(696, prob.nst), torch.float64)
+
+    def vcycle(ctx):
+        d = ctx.vector()
+        ctx.pns_vcycle(2, 2, 0.15, r, d)
+        torch.cuda.synchronize()
+        return d.cpu().numpy()
+
+    refs = {}
+    for kind in (pnsmg.PATCH_EXACT, pnsmg.PATCH_SURROGATE):
+        fresh = pnsmg.Context(n, n_levels=2, precision=pnsmg.FP64, tau=0.01, patch_kind=kind)
+        fresh.pns_set_state(dict(MODEL3, lin=LIN), to_dev(uk, torch.float64))
+        fresh.pns_vanka_setup()
+        refs[kind] = vcycle(fresh)
+        del fresh
+    assert rel(refs[pnsmg.PATCH_SURROGATE], refs[pnsmg.PATCH_EXACT]) > 1e-6  # the kinds differ
+    ctx = pnsmg.Context(n, n_levels=2, precision=pnsmg.FP64, tau=0.01, patch_kind=pnsmg.PATCH_EXACT)
+    ctx.pns_set_state(dict(MODEL3, lin=LIN), to_dev(uk, torch.float64))
+    for kind in (pnsmg.PATCH_EXACT, pnsmg.PATCH_SURROGATE, pnsmg.PATCH_EXACT):
+        ctx.pns_set_patch_kind(kind)
+        ctx.pns_vanka_setup()
+        err = rel(vcycle(ctx), refs[kind])
+        print(f"patch kind {kind} after switch: rel diff {err:.2e}")
+        assert err <= 1e-13
