@@ -4,7 +4,7 @@ Workload (2D, 256 x 256 quadrilaterals, Q2 / P1disc x dG(1), one slab with
 tau = 0.01; p = 1.2, delta = 1e-4, nu = 1, nu_inf = 1e-4, Nitsche
 gamma1 = gamma2 = 40, sigma_max = 1): the surrogate-tangent (modified Newton)
 Jacobian action and one 4-level V-cycle (256^2 -> 32^2, 2 pre + 2 post Vanka
-steps, omega = 0.5, dense FP64 coarsest solve).  Linearisation state: smooth
+steps, omega = 0.1, dense FP64 coarsest solve).  Linearisation state: smooth
 sin-series velocity with 8 random modes plus U[-0.01, 0.01] noise (seed 201),
 input vector U[-1, 1] (seed 202).  All inputs are synthetic and resident in
 HBM before timing.
