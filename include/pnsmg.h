@@ -53,7 +53,8 @@ enum {
   PNS_ESTATE = -4,      /* call order: no state set / smoother not set up */
   PNS_ESINGULAR = -5,   /* a patch or the coarse matrix had a zero pivot */
   PNS_EUNSUPPORTED = -6, /* configuration outside what this build implements */
-  PNS_ENOTCONV = -7     /* a slab solve stopped without reaching its tolerance */
+  PNS_ENOTCONV = -7,    /* a slab solve stopped without reaching its tolerance */
+  PNS_ENONFINITE = -8   /* a slab solve met a NaN or infinite residual or Krylov value */
 };
 
 /* Constitutive tangent of the linearisation (Sec. 4.2-4.4). */
@@ -247,8 +248,13 @@ int pns_sweep_variant(const pns_ctx* ctx, int level, int out[5]);
 int pns_sweep_variant_time(const pns_ctx* ctx, int level, int variant, double* ms);
 int pns_set_sweep_variant(pns_ctx* ctx, int level, int variant);
 
-/* d = V(r): one V-cycle over all levels (nu1 pre- and nu2 post-smoothing steps
- * from d = 0, restriction P^T, coarsest dense solve, prolongation).
+/* d = V(r): one V-cycle over all levels (Sec. 6.3 "Hierarchy and coarse
+ * operators": levels l = 0 .. L-1 with A_{l+1} = P^T A_l P; Sec. 6.3 "Vanka
+ * smoothing": nu1 pre- and nu2 post-smoothing steps of eq. stmg-vanka-update
+ * on every level but the coarsest).  From d = 0: nu1 steps, restriction
+ * P^T of the defect, recursion, coarsest dense solve, prolongation-add,
+ * nu2 steps.  r_dev, d_dev: level-0 vectors in the context precision,
+ * canonical layout, caller-owned, must not alias; d is overwritten.
  * PNS_EUNSUPPORTED if the coarsest level exceeds the dense-solve limit, and
  * on 3D contexts with one level.  On hexahedra each vertex lies in 8 cell
  * patches; the additive step needs a smaller omega there (about 0.15) than on
@@ -323,8 +329,8 @@ typedef struct {
  * context); 0 for a NULL context or restart outside 1..200. */
 size_t pns_solve_workspace_bytes(const pns_ctx* ctx, int restart);
 
-/* Newton-Krylov solve of R_n(U) = 0 on the slab (Sec. 5.3, eqs. nk-newton-lin,
- * nk-inexact-newton, nk-stop): at each iterate U^m the linearisation model->lin
+/* Newton-Krylov solve of R_n(U) = 0 on the slab (Sec. 6 eq. nk-newton-lin; Sec. 6.1
+ * eq. nk-inexact-newton; Sec. 6.2 eq. nk-stop): at each iterate U^m the linearisation model->lin
  * acts matrix-free as J_n; FGMRES, right-preconditioned by one V-cycle,
  * solves J_n dU = R_n(U^m) until ||J_n dU - R_n||_M <= eta_m ||R_n||_M, with
  * Eisenstat-Walker forcing terms (choice 2, gamma 0.9, exponent 2) and FP64
@@ -347,8 +353,11 @@ size_t pns_solve_workspace_bytes(const pns_ctx* ctx, int restart);
  * solve has finished on the context stream; *info is filled when non-NULL.
  * Returns PNS_OK on convergence; PNS_ENOTCONV when max_newton is reached, the
  * line search fails or a linear solve misses its forcing term within
- * max_krylov iterations; PNS_EUNSUPPORTED when the coarsest level is too large
- * for the dense coarse solve. */
+ * max_krylov iterations; PNS_ENONFINITE when the initial residual, a trial
+ * residual of every backtracking step or the FGMRES residual estimate is not
+ * finite (a NaN or infinity in U, v_prev or the model's output): U is then
+ * left at the last finite iterate; PNS_EUNSUPPORTED when the coarsest level
+ * is too large for the dense coarse solve. */
 int pns_solve(pns_ctx* ctx, const pns_model* model, const double* v_prev_dev, double* U_dev,
               const pns_solve_params* prm, void* work_dev, size_t work_bytes,
               pns_solve_info* info);
@@ -391,8 +400,11 @@ typedef struct {
   int patch_kind;            /* pns_patch_kind of the finest level */
   pns_model model;
   pns_solve_params params;
-  const double* v_prev_host; /* left-trace velocity, host, 2 (2n_x+1)(2n_y+1) doubles; copied */
+  const double* v_prev_host; /* left-trace velocity, host, 2 (2n_x+1)(2n_y+1) doubles; copied
+                                at submission, the copy released once it is on the device */
   double* U_host;            /* host buffer of N_st doubles receiving the last iterate */
+  int vcycle_graph;          /* 1: the request's V-cycles replay a captured HIP graph
+                                (pns_set_vcycle_graph), 0: eager launches */
 } pns_request;
 
 enum { PNS_REQ_QUEUED = 0, PNS_REQ_RUNNING = 1, PNS_REQ_DONE = 2 };
@@ -415,7 +427,7 @@ size_t pns_request_footprint(const pns_request* req);
  * PNS_EINVAL for bad arguments, PNS_EHIP if a stream cannot be created. */
 int pns_server_create(int slots, void* arena_dev, size_t arena_bytes, pns_server** out);
 
-/* Queue a request (Sec. 5.3 slab solve, as pns_solve); the request struct and
+/* Queue a request (Sec. 6-6.2 slab solve, as pns_solve); the request struct and
  * v_prev_host are copied, U_host must stay valid until the request is DONE.
  * *ticket identifies it.  PNS_EINVAL if the request is invalid,
  * PNS_EWORKSPACE if its footprint exceeds the whole arena. */
@@ -426,6 +438,12 @@ int pns_poll(pns_server* srv, uint64_t ticket, pns_result* out);
 
 /* Block until the request is DONE, then as pns_poll. */
 int pns_wait(pns_server* srv, uint64_t ticket, pns_result* out);
+
+/* Forget a finished request: its result can no longer be polled and the
+ * server's host memory for it is freed (a long-running server calls this
+ * for every ticket it has waited for).  PNS_EINVAL for an unknown ticket,
+ * PNS_ESTATE if the request is not DONE yet (nothing changes then). */
+int pns_release(pns_server* srv, uint64_t ticket);
 
 /* Finish every queued and running request, then release the streams and
  * worker threads. */

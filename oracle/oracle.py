@@ -19,8 +19,8 @@ module adds the global pieces with numpy / scipy library primitives:
   V-cycle with a dense LU on the coarsest level;
 * the block mass-weighted residual norm and a plain Newton iteration on the
   slab residual with direct (sparse LU) linear solves and Armijo backtracking
-  (Sec. 5.3 "Krylov solver and preconditioning", "Globalization and stopping
-  criteria"), which defines the solution a slab solve has to reach.
+  (Sec. 6.1 "Krylov solver and preconditioning", Sec. 6.2 "Globalization and
+  stopping criteria"), which defines the solution a slab solve has to reach.
 """
 from __future__ import annotations
 
@@ -780,7 +780,7 @@ def assemble_pressure_mass(prob: Problem):
 
 def slab_mass(prob: Problem):
     """Block mass of the time step, velocity and pressure: the spatial masses
-    weighted by tau times the Radau weights, tau M_t (x) M (Sec. 5.3, the norm
+    weighted by tau times the Radau weights, tau M_t (x) M (Sec. 6.1, the norm
     of the algebraic residuals)."""
     _, Mt, _, _ = time_matrices(prob.k_time)
     Ms = assemble_velocity_mass(prob) + assemble_pressure_mass(prob)
@@ -788,7 +788,7 @@ def slab_mass(prob: Problem):
 
 
 def mass_norm(prob: Problem, r, M=None):
-    """||(r_v, r_p)||_M = sqrt(r_v^T M_v r_v + r_p^T M_p r_p) (Sec. 5.3)."""
+    """||(r_v, r_p)||_M = sqrt(r_v^T M_v r_v + r_p^T M_p r_p) (Sec. 6.1)."""
     r = _f64(r)
     M = slab_mass(prob) if M is None else M
     return float(np.sqrt(r @ (M @ r)))

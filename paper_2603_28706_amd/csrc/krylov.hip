@@ -1,4 +1,4 @@
-// Vector kernels of the slab solve (Sec. 5.3): the block mass of the time step
+// Vector kernels of the slab solve (Sec. 6.1): the block mass of the time step
 // (the inner product in which residuals are measured), deterministic multi-dot
 // products and combinations of Krylov vectors, precision conversions.  All
 // reductions use a fixed partition and a fixed summation tree, so results do

@@ -1,4 +1,4 @@
-// Coarse levels of the space-time multigrid on hexahedra (Sec. 6.2-6.3), the
+// Coarse levels of the space-time multigrid on hexahedra (Sec. 6.3), the
 // 3D counterparts of the quadrilateral setup and V-cycle kernels:
 // * galerkin3d_kernel: coarse space-time element matrices
 //   E_C = sum_children P_f^T E_f P_f (A_{l+1} = P^T A_l P restricted cell by

@@ -1,7 +1,7 @@
 // Request server for independent slab solves: a queue with admission by slot
 // and arena room, host worker threads each driving one HIP stream, first-fit
 // sub-allocation of the caller's device arena.  Each request runs the
-// Newton-Krylov solve of solve.hip (Sec. 5.3) on its own context.
+// Newton-Krylov solve of solve.hip (Sec. 6-6.2) on its own context.
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -96,6 +96,7 @@ int request_sizes(const pns_request* q, Sizes* out) {
   if (rc == PNS_OK && !c->has_coarse) rc = PNS_EUNSUPPORTED;
   if (rc == PNS_OK && q->patch_kind != PNS_PATCH_SURROGATE && q->patch_kind != PNS_PATCH_EXACT)
     rc = PNS_EINVAL;
+  if (rc == PNS_OK && q->vcycle_graph != 0 && q->vcycle_graph != 1) rc = PNS_EINVAL;
   if (rc == PNS_OK) {
     out->ws = pns_workspace_bytes(c);
     out->solve = pns_solve_workspace_bytes(c, q->params.restart);
@@ -165,30 +166,35 @@ int run_request(Req* r, hipStream_t s, pns_solve_info* info) {
   double* vp = (double*)p;
   const int64_t ns = c->lev[0].g.ns, nv = c->lev[0].g.nv;
   if ((rc = pns_bind_workspace(c, ws, r->sz.ws)) == PNS_OK &&
-      (rc = pns_set_patch_kind(c, q.patch_kind)) == PNS_OK) {
-    // initial guess: the left trace at both Radau nodes, zero pressure
+      (rc = pns_set_patch_kind(c, q.patch_kind)) == PNS_OK &&
+      (rc = pns_set_vcycle_graph(c, q.vcycle_graph ? 1 : 0)) == PNS_OK) {
+    // initial guess: the left trace at both Radau nodes, zero pressure; the
+    // host copy of the left trace is released once it is on the device
     bool ok = hipMemcpyAsync(vp, r->vprev.data(), nv * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
-              hipMemsetAsync(U, 0, r->sz.nst * 8, s) == hipSuccess &&
-              hipMemcpyAsync(U, vp, nv * 8, hipMemcpyDeviceToDevice, s) == hipSuccess &&
-              hipMemcpyAsync(U + ns, vp, nv * 8, hipMemcpyDeviceToDevice, s) == hipSuccess;
+              hipStreamSynchronize(s) == hipSuccess;
+    std::vector<double>().swap(r->vprev);
+    r->q.v_prev_host = nullptr;
+    ok = ok && hipMemsetAsync(U, 0, r->sz.nst * 8, s) == hipSuccess &&
+         hipMemcpyAsync(U, vp, nv * 8, hipMemcpyDeviceToDevice, s) == hipSuccess &&
+         hipMemcpyAsync(U + ns, vp, nv * 8, hipMemcpyDeviceToDevice, s) == hipSuccess;
     if (!ok) {
       rc = PNS_EHIP;
     } else {
       rc = pns_solve(c, &q.model, vp, U, &q.params, work, r->sz.solve, info);
-      if (rc == PNS_OK || rc == PNS_ENOTCONV) {
+      if (rc == PNS_OK || rc == PNS_ENOTCONV || rc == PNS_ENONFINITE) {
         if (hipMemcpyAsync(q.U_host, U, r->sz.nst * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
           rc = PNS_EHIP;
       }
     }
   }
-  hipStreamSynchronize(s);
+  (void)hipStreamSynchronize(s);
   pns_ctx_destroy(c);
   return rc;
 }
 
 void worker_main(pns_server* S, int slot) {
-  hipSetDevice(S->device);
+  (void)hipSetDevice(S->device);
   hipStream_t s = S->streams[slot];
   std::unique_lock<std::mutex> lk(S->mu);
   while (true) {
@@ -250,7 +256,7 @@ int pns_server_create(int slots, void* arena, size_t bytes, pns_server** out) {
   for (int i = 0; i < slots; ++i) {
     hipStream_t st;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-      for (hipStream_t x : S->streams) hipStreamDestroy(x);
+      for (hipStream_t x : S->streams) (void)hipStreamDestroy(x);
       delete S;
       return PNS_EHIP;
     }
@@ -303,6 +309,16 @@ int pns_wait(pns_server* S, uint64_t ticket, pns_result* out) {
   return PNS_OK;
 }
 
+int pns_release(pns_server* S, uint64_t ticket) {
+  if (!S) return PNS_EINVAL;
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->all.find(ticket);
+  if (it == S->all.end()) return PNS_EINVAL;
+  if (it->second->res.state != PNS_REQ_DONE) return PNS_ESTATE;
+  S->all.erase(it);
+  return PNS_OK;
+}
+
 void pns_server_destroy(pns_server* S) {
   if (!S) return;
   {
@@ -311,7 +327,7 @@ void pns_server_destroy(pns_server* S) {
   }
   S->cv_work.notify_all();
   for (auto& t : S->workers) t.join();
-  for (hipStream_t s : S->streams) hipStreamDestroy(s);
+  for (hipStream_t s : S->streams) (void)hipStreamDestroy(s);
   delete S;
 }
 

@@ -1,4 +1,5 @@
-// Newton-Krylov slab solve (Sec. 5.3): FP64 residual and norms, FGMRES with a
+// Newton-Krylov slab solve (Sec. 6, eq. nk-newton-lin; Sec. 6.1 Krylov solver,
+// Sec. 6.2 globalisation and stopping): FP64 residual and norms, FGMRES with a
 // V-cycle preconditioner, Eisenstat-Walker forcing, Armijo backtracking,
 // smoother refresh on deterioration (Sec. 6.3).  Host-side sequencing of
 // device kernels on the context stream; the small Hessenberg least-squares
@@ -305,6 +306,11 @@ int pns_solve(pns_ctx* ctx, const pns_model* md, const double* vprev, double* U,
   if ((rc = S.residual(U, S.W.R)) != PNS_OK) return rc;
   double rnorm;
   if ((rc = S.mnorm(S.W.R, &rnorm)) != PNS_OK) return rc;
+  if (!std::isfinite(rnorm)) {
+    inf.residual_initial = inf.residual_final = rnorm;
+    if (info) *info = inf;
+    return fail(ctx, PNS_ENONFINITE, "initial residual is not finite (NaN or Inf in U or v_prev)");
+  }
   const double r0 = rnorm;
   const double stop = std::max(prm->atol, prm->rtol * r0);
   inf.residual_initial = inf.residual_final = r0;
@@ -330,6 +336,11 @@ int pns_solve(pns_ctx* ctx, const pns_model* md, const double* vprev, double* U,
     double achieved = 0.0;
     if ((rc = S.fgmres(S.W.R, rnorm, eta * rnorm, &its, &achieved)) != PNS_OK) return rc;
     inf.krylov_iterations += its;
+    if (!std::isfinite(achieved)) {
+      PNS_HIP(ctx, hipStreamSynchronize(s));
+      if (info) *info = inf;
+      return fail(ctx, PNS_ENONFINITE, "FGMRES residual estimate is not finite");
+    }
     if (achieved > eta * rnorm && !refresh) {
       // the smoother was built at an earlier iterate: rebuild it here and
       // solve again before declaring the linear solve failed
@@ -338,6 +349,11 @@ int pns_solve(pns_ctx* ctx, const pns_model* md, const double* vprev, double* U,
       ++inf.smoother_setups;
       if ((rc = S.fgmres(S.W.R, rnorm, eta * rnorm, &its, &achieved)) != PNS_OK) return rc;
       inf.krylov_iterations += its;
+      if (!std::isfinite(achieved)) {
+        PNS_HIP(ctx, hipStreamSynchronize(s));
+        if (info) *info = inf;
+        return fail(ctx, PNS_ENONFINITE, "FGMRES residual estimate is not finite");
+      }
     }
     if (achieved > eta * rnorm) {
       why = "FGMRES missed its forcing term within max_krylov iterations";
@@ -345,17 +361,23 @@ int pns_solve(pns_ctx* ctx, const pns_model* md, const double* vprev, double* U,
     }
     // Armijo backtracking on ||R||_M^2 / 2
     double lam = 1.0, rt = 0.0;
-    bool ok = false;
+    bool ok = false, finite = false;
     for (int bt = 0; bt <= kMaxBacktrack; ++bt) {
       PNS_HIP(ctx, launch_axpby(n, 1.0, U, lam, S.W.dU, S.W.Ut, s));
       if ((rc = S.residual(S.W.Ut, S.W.Rt)) != PNS_OK) return rc;
       if ((rc = S.mnorm(S.W.Rt, &rt)) != PNS_OK) return rc;
+      finite = finite || std::isfinite(rt);
       if (rt <= (1.0 - kArmijo * lam * (1.0 - eta)) * rnorm) {
         ok = true;
         break;
       }
       lam *= 0.5;
       ++inf.backtracks;
+    }
+    if (!ok && !finite) {
+      PNS_HIP(ctx, hipStreamSynchronize(s));
+      if (info) *info = inf;
+      return fail(ctx, PNS_ENONFINITE, "every trial residual of the line search is not finite");
     }
     if (!ok) {
       why = "line search failed";

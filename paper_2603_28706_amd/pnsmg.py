@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libpnsmg.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "pnsmg.h")
 
 (PNS_OK, PNS_EINVAL, PNS_EWORKSPACE, PNS_EHIP, PNS_ESTATE, PNS_ESINGULAR, PNS_EUNSUPPORTED,
- PNS_ENOTCONV) = (0, -1, -2, -3, -4, -5, -6, -7)
+ PNS_ENOTCONV, PNS_ENONFINITE) = (0, -1, -2, -3, -4, -5, -6, -7, -8)
 PICARD, EXACT_NEWTON, MODIFIED_NEWTON = 0, 1, 2
 FP64, FP32, BF16 = 0, 1, 2
 APPLY_RECOMPUTE, APPLY_CACHED = 0, 1
@@ -68,7 +68,7 @@ class pns_request(ctypes.Structure):
                 ("n_levels", ctypes.c_int), ("precision", ctypes.c_int),
                 ("patch_kind", ctypes.c_int), ("model", pns_model),
                 ("params", pns_solve_params), ("v_prev_host", ctypes.POINTER(ctypes.c_double)),
-                ("U_host", ctypes.POINTER(ctypes.c_double))]
+                ("U_host", ctypes.POINTER(ctypes.c_double)), ("vcycle_graph", ctypes.c_int)]
 
 
 class pns_result(ctypes.Structure):
@@ -138,9 +138,11 @@ def lib():
         L.pns_solve_request.argtypes = [_vp, pp(pns_request), pp(ctypes.c_uint64)]
         L.pns_poll.argtypes = [_vp, ctypes.c_uint64, pp(pns_result)]
         L.pns_wait.argtypes = [_vp, ctypes.c_uint64, pp(pns_result)]
+        L.pns_release.argtypes = [_vp, ctypes.c_uint64]
         L.pns_server_destroy.argtypes = [_vp]
         L.pns_server_destroy.restype = None
-        for f in ("pns_server_create", "pns_solve_request", "pns_poll", "pns_wait"):
+        for f in ("pns_server_create", "pns_solve_request", "pns_poll", "pns_wait",
+                  "pns_release"):
             getattr(L, f).restype = ctypes.c_int
         for f in ("pns_ctx_create", "pns_level_sizes", "pns_bind_workspace", "pns_set_state",
                   "pns_set_apply_mode", "pns_set_patch_kind",
@@ -301,8 +303,8 @@ class Context:
 
     def pns_solve(self, model: dict, vprev, U, check=True, **params):
         """Newton-Krylov slab solve; U (FP64) is updated in place.  Returns
-        (return code, info dict); raises on errors other than PNS_ENOTCONV
-        unless check is False."""
+        (return code, info dict); raises on errors other than PNS_ENOTCONV and
+        PNS_ENONFINITE unless check is False."""
         prm = dict(SOLVE_DEFAULTS, **params)
         ps = pns_solve_params(*(prm[f] for f, _ in pns_solve_params._fields_))
         nbytes = self.pns_solve_workspace_bytes(ps.restart)
@@ -316,7 +318,7 @@ class Context:
         rc = lib().pns_solve(self.h, ctypes.byref(model_struct(model)), vp,
                              self._f64(U, sz["nst"]), ctypes.byref(ps), _vp(base), nbytes,
                              ctypes.byref(info))
-        if check and rc not in (PNS_OK, PNS_ENOTCONV):
+        if check and rc not in (PNS_OK, PNS_ENOTCONV, PNS_ENONFINITE):
             self._check(rc)
         del work
         return rc, {f: getattr(info, f) for f, _ in pns_solve_info._fields_}
@@ -337,7 +339,7 @@ class Context:
         rc = lib().pns_march(self.h, ctypes.byref(model_struct(model)), self._f64(v, sz["nv"]),
                              int(n_slabs), self._f64(U, sz["nst"]), ctypes.byref(ps), _vp(base),
                              nbytes, ctypes.byref(info))
-        if check and rc not in (PNS_OK, PNS_ENOTCONV):
+        if check and rc not in (PNS_OK, PNS_ENOTCONV, PNS_ENONFINITE):
             self._check(rc)
         del work
         return rc, {f: getattr(info, f) for f, _ in pns_solve_info._fields_}
@@ -360,7 +362,8 @@ def masks_to_bits(masks):
 
 
 def make_request(n, model: dict, vprev, U_out, levels, precision=FP64, tau=0.01,
-                 patch_kind=PATCH_SURROGATE, lo=(0.0, 0.0), hi=(1.0, 1.0), **params):
+                 patch_kind=PATCH_SURROGATE, lo=(0.0, 0.0), hi=(1.0, 1.0), vcycle_graph=0,
+                 **params):
     """pns_request for an n[0] x n[1] slab solve; vprev and U_out are float64
     numpy arrays that must stay alive until the request is done."""
     assert vprev.dtype == np.float64 and vprev.flags.c_contiguous
@@ -378,6 +381,7 @@ def make_request(n, model: dict, vprev, U_out, levels, precision=FP64, tau=0.01,
     q.params = pns_solve_params(*(prm[f] for f, _ in pns_solve_params._fields_))
     q.v_prev_host = vprev.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     q.U_host = U_out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    q.vcycle_graph = int(vcycle_graph)
     return q
 
 
@@ -424,6 +428,12 @@ class Server:
         if lib().pns_wait(self.h, ctypes.c_uint64(ticket), ctypes.byref(r)) != PNS_OK:
             raise PnsError(PNS_EINVAL, "unknown ticket")
         return result_dict(r)
+
+    def release(self, ticket):
+        rc = lib().pns_release(self.h, ctypes.c_uint64(ticket))
+        if rc != PNS_OK:
+            raise PnsError(rc, "pns_release: unknown ticket or request not done")
+        self._keep.pop(ticket, None)
 
     def close(self):
         if getattr(self, "h", None):

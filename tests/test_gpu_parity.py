@@ -3,15 +3,19 @@
 Tolerances: FP64 apply <= 1e-12 relative (2-norm, velocity and pressure rows
 separately); FP32 apply <= 1e-5 relative.  Smoother, transfers and V-cycle
 are linear maps evaluated with different rounding order on both sides; their
-FP64 tolerance is derived from the conditioning of the patch / coarse solves
-(patch condition numbers of these workloads are below 1e4, so the forward
-error stays below ~1e-16 * kappa * (a few) and a 1e-10 bound is used).
+FP64 tolerance is derived per test from the conditioning of the patch and
+coarse matrices solved: max(1e-12, kappa_eq * 1e-16) with kappa_eq the largest
+condition number of those matrices after row and column equilibration
+(tests/tolerances.py).  On the parity workloads kappa_eq stays below 1e4, so
+the bound is 1e-12; the benchmark model (p = 1.2, delta = 1e-4) reaches
+kappa_eq ~ 1e5.
 """
 import numpy as np
 import pytest
 
 from oracle import oracle as O
 from paper_2603_28706_amd import inputs
+from tolerances import fp64_tol, hierarchy_kappa, kappa_eq
 
 pytestmark = pytest.mark.gpu
 
@@ -210,18 +214,19 @@ def test_config1_vanka_sweep_fp64(lin):
     patches = O.all_patches(prob)
     pm = O.patch_matrices(O.assemble_surrogate(prob, uk), patches)
     ref = O.vanka_step(A, pm, patches, r, np.zeros(prob.nst), 0.5)
+    tol = fp64_tol(kappa_eq(pm))
     ctx = make_ctx(n, 1, CONFIG1, lin, uk)
     d = ctx.vector()
     ctx.pns_vanka_smooth(0, 1, 0.5, to_dev(r, torch.float64), d)
     got = d.cpu().numpy()
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-    print(f"config1 vanka lin={lin}: rel err {err:.2e}")
-    assert err <= 1e-10
+    print(f"config1 vanka lin={lin}: rel err {err:.2e} (bound {tol:.1e})")
+    assert err <= tol
     # a second sweep (exercises the defect path)
     ref2 = O.vanka_step(A, pm, patches, r, ref, 0.5)
     ctx.pns_vanka_smooth(0, 1, 0.5, to_dev(r, torch.float64), d)
     got2 = d.cpu().numpy()
-    assert np.linalg.norm(got2 - ref2) <= 1e-10 * np.linalg.norm(ref2)
+    assert np.linalg.norm(got2 - ref2) <= tol * np.linalg.norm(ref2)
 
 
 def test_vanka_sweep_fp32():
@@ -257,13 +262,14 @@ def test_truncated_patches_fp64():
     assert len({len(p) for p in patches}) > 1
     pm = O.patch_matrices(O.assemble_surrogate(prob, uk), patches)
     ref = O.vanka_step(A, pm, patches, r, np.zeros(prob.nst), 0.5)
+    tol = fp64_tol(kappa_eq(pm))
     ctx = make_ctx(n, 1, model, lin, uk, masks=masks)
     d = ctx.vector()
     ctx.pns_vanka_smooth(0, 1, 0.5, to_dev(r, torch.float64), d)
     got = d.cpu().numpy()
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-    print(f"truncated patches rel err {err:.2e}")
-    assert err <= 1e-10
+    print(f"truncated patches rel err {err:.2e} (bound {tol:.1e})")
+    assert err <= tol
 
 
 def test_transfers_and_galerkin_operator():
@@ -307,13 +313,14 @@ def test_vcycle_fp64(n, levels, lin):
     r = inputs.uniform(72, prob.nst)
     H = O.build_hierarchy(prob, uk, n_levels=levels)
     ref = O.vcycle(H, r, nu1=2, nu2=2, omega=0.5)
+    tol = fp64_tol(hierarchy_kappa(H))
     ctx = make_ctx(n, levels, CONFIG1, lin, uk)
     d = ctx.vector()
     ctx.pns_vcycle(2, 2, 0.5, to_dev(r, torch.float64), d)
     got = d.cpu().numpy()
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-    print(f"vcycle n={n} levels={levels} lin={lin}: rel err {err:.2e}")
-    assert err <= 1e-10
+    print(f"vcycle n={n} levels={levels} lin={lin}: rel err {err:.2e} (bound {tol:.1e})")
+    assert err <= tol
 
 
 def test_vcycle_fp32_close_to_fp64():
@@ -350,13 +357,14 @@ def test_exact_fine_patches_vanka_fp64(masked):
     pm = O.patch_matrices(A, patches)
     ref = O.vanka_step(A, pm, patches, r, np.zeros(prob.nst), 0.3)
     ref = O.vanka_step(A, pm, patches, r, ref, 0.3)
+    tol = fp64_tol(kappa_eq(pm))
     ctx = make_ctx(n, 1, model, lin, uk, masks=masks, patch_kind=pnsmg.PATCH_EXACT)
     d = ctx.vector()
     ctx.pns_vanka_smooth(0, 2, 0.3, to_dev(r, torch.float64), d)
     got = d.cpu().numpy()
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-    print(f"exact fine patches masked={masked}: rel err {err:.2e}")
-    assert err <= 1e-10
+    print(f"exact fine patches masked={masked}: rel err {err:.2e} (bound {tol:.1e})")
+    assert err <= tol
 
 
 def test_exact_fine_patches_vcycle_fp64_and_fp32():
@@ -367,7 +375,7 @@ def test_exact_fine_patches_vcycle_fp64_and_fp32():
     r = inputs.uniform(92, prob.nst)
     H = O.build_hierarchy(prob, uk, n_levels=3, surrogate=False)
     ref = O.vcycle(H, r, nu1=2, nu2=2, omega=0.3)
-    for precision, tol in ((pnsmg.FP64, 1e-10), (pnsmg.FP32, 1e-4)):
+    for precision, tol in ((pnsmg.FP64, fp64_tol(hierarchy_kappa(H))), (pnsmg.FP32, 1e-4)):
         ctx = make_ctx(n, 3, CONFIG1, lin, uk, precision=precision, patch_kind=pnsmg.PATCH_EXACT)
         d = ctx.vector()
         rr = to_dev(r, ctx.dtype)
@@ -376,3 +384,39 @@ def test_exact_fine_patches_vcycle_fp64_and_fp32():
         err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
         print(f"vcycle exact fine patches prec={precision}: rel err {err:.2e}")
         assert err <= tol
+
+
+# ----------------------------------------------- the benchmarked V-cycle shape
+
+BENCH_MODEL = dict(CONFIG1, p=1.2, delta=1e-4, nu_inf=1e-4)
+
+
+@pytest.mark.parametrize("n,precisions", [((64, 64), (pnsmg.FP64, pnsmg.FP32)),
+                                          ((128, 128), (pnsmg.FP64,))])
+def test_vcycle_benchmark_model_four_levels(n, precisions):
+    """The V-cycle as benchmarked at 256^2: four levels (here 64^2 -> 8^2 and
+    128^2 -> 16^2), surrogate finest patches, 2 + 2 steps, omega = 0.1, the
+    modified-Newton tangent at p = 1.2, delta = 1e-4, nu_inf = 1e-4 and the
+    sin-series state of the 256^2 workload (seed 201), against the oracle's
+    V-cycle (sparse Galerkin triple products, dense LU patch solves, dense LU
+    coarsest solve).  FP64 bound from the conditioning (kappa_eq ~ 1e5 here);
+    FP32 (coarsest solve in FP64) within kappa_eq times the FP32 unit
+    roundoff."""
+    lin = pnsmg.MODIFIED_NEWTON
+    prob = oracle_problem(n, BENCH_MODEL, lin)
+    uk = inputs.sin_series_velocity(n, seed=201, t_nodes=[0.01 / 3, 0.01])
+    r = inputs.uniform(203, prob.nst)
+    H = O.build_hierarchy(prob, uk, n_levels=4)
+    ref = O.vcycle(H, r, nu1=2, nu2=2, omega=0.1)
+    kappa = hierarchy_kappa(H)
+    for precision in precisions:
+        tol = fp64_tol(kappa) if precision == pnsmg.FP64 else max(1e-4, kappa * 2.0 ** -24)
+        ctx = make_ctx(n, 4, BENCH_MODEL, lin, uk, precision=precision)
+        d = ctx.vector()
+        ctx.pns_vcycle(2, 2, 0.1, to_dev(r, ctx.dtype), d)
+        got = d.double().cpu().numpy()
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        print(f"benchmark-model V-cycle n={n} prec={precision}: rel err {err:.2e} "
+              f"(kappa_eq {kappa:.1e}, bound {tol:.1e})")
+        assert err <= tol
+        del ctx

@@ -134,3 +134,43 @@ def test_rejects_requests_larger_than_the_arena():
         srv.submit(q, keep=(vprev, U))
     assert e.value.code == pnsmg.PNS_EWORKSPACE
     srv.close()
+
+
+def test_graph_replayed_request_and_release():
+    """A request whose V-cycles replay a captured HIP graph takes the same
+    iterations and reaches the same iterate as the eager one; a finished
+    ticket can be released once, after which it is unknown."""
+    n = (32, 32)
+    srv = pnsmg.Server(slots=2, arena_bytes=512 << 20)
+    q0, v0, U0 = request(n, 341, 3)
+    q1, v1, U1 = request(n, 341, 3, vcycle_graph=1)
+    t0 = srv.submit(q0, keep=(v0, U0))
+    t1 = srv.submit(q1, keep=(v1, U1))
+    r0, r1 = srv.wait(t0), srv.wait(t1)
+    assert r0["status"] == pnsmg.PNS_OK and r1["status"] == pnsmg.PNS_OK
+    assert r0["newton_iterations"] == r1["newton_iterations"]
+    assert r0["krylov_iterations"] == r1["krylov_iterations"]
+    err = rel(U1, U0)
+    print(f"graph-replayed request vs eager: rel diff {err:.2e}")
+    assert err <= 1e-9
+    srv.release(t0)
+    with pytest.raises(pnsmg.PnsError) as e:
+        srv.release(t0)
+    assert e.value.code == pnsmg.PNS_EINVAL
+    with pytest.raises(pnsmg.PnsError):
+        srv.poll(t0)
+    assert srv.poll(t1)["state"] == pnsmg.REQ_DONE
+    srv.release(t1)
+    srv.close()
+
+
+def test_served_nonfinite_request_is_reported():
+    n = (16, 16)
+    srv = pnsmg.Server(slots=1, arena_bytes=256 << 20)
+    q, vprev, U = request(n, 351, 2)
+    vprev[5] = np.inf
+    q = pnsmg.make_request(n, MODEL, vprev, U, 2)
+    t = srv.submit(q, keep=(vprev, U))
+    res = srv.wait(t)
+    srv.close()
+    assert res["state"] == pnsmg.REQ_DONE and res["status"] == pnsmg.PNS_ENONFINITE

@@ -1,4 +1,4 @@
-"""GPU parity of the slab solve rows (Sec. 5.3) through the C-ABI: the FP64
+"""GPU parity of the slab solve rows (Sec. 6-6.2) through the C-ABI: the FP64
 residual against the oracle's, and the Newton-Krylov solve against the
 oracle's Newton solution.
 
@@ -172,3 +172,26 @@ def test_solve_with_exact_fine_patches():
     b = without_pressure_constant(prob, ref.U)
     for idx in blocks(prob):
         assert np.linalg.norm(a[idx] - b[idx]) <= 1e-6 * np.linalg.norm(b[idx])
+
+
+def test_solve_reports_nonfinite_input():
+    # a NaN in the left trace makes the initial residual NaN: the solve stops
+    # at once with PNS_ENONFINITE and leaves U untouched
+    n = (8, 8)
+    vprev = inputs.sin_series_velocity(n, seed=203, t_nodes=[0.0])
+    vprev[17] = np.nan
+    ctx = pnsmg.Context(n, n_levels=2, precision=pnsmg.FP64)
+    prob = oracle_problem(n, CONFIG1)
+    U0 = O.state_from_velocity(prob, np.concatenate([vprev, vprev]))
+    U0[np.isnan(U0)] = 0.0
+    U = dev(U0)
+    rc, info = ctx.pns_solve(CONFIG1, dev(vprev), U)
+    torch.cuda.synchronize()
+    assert rc == pnsmg.PNS_ENONFINITE
+    assert info["newton_iterations"] == 0 and not np.isfinite(info["residual_initial"])
+    assert np.array_equal(U.cpu().numpy(), U0)
+    # a NaN in the initial iterate itself
+    U0b = O.state_from_velocity(prob, np.concatenate([vprev, vprev]))
+    vprev[17] = 0.0
+    rc, info = ctx.pns_solve(CONFIG1, dev(vprev), dev(U0b))
+    assert rc == pnsmg.PNS_ENONFINITE

@@ -1,4 +1,4 @@
-"""GPU parity of the slab solve on hexahedra (Sec. 5.3) through the C-ABI: the
+"""GPU parity of the slab solve on hexahedra (Sec. 6-6.2) through the C-ABI: the
 FP64 residual against the oracle's, and the Newton-Krylov solve (FGMRES with
 the 3D V-cycle) against the oracle's Newton solution.
 

@@ -6,8 +6,10 @@ The GPU inverts each surrogate patch in time-diagonal form (one complex
 85 x 85 system); the oracle solves the real 170 x 170 patch matrix restricted
 from the globally assembled surrogate operator by LU with partial pivoting.
 Both are the same linear map evaluated with different rounding.  Tolerances
-as in 2D: FP64 1e-10 relative (patch condition numbers of these inputs are
-far below 1e4), FP32 1e-4 (inverses stored in FP32).  Small meshes are
+as in 2D: FP64 max(1e-12, kappa_eq * 1e-16) with kappa_eq the largest
+equilibrated condition number of the patch matrices solved
+(tests/tolerances.py; below 1e4 on these inputs, so 1e-12), FP32 1e-4
+(inverses stored in FP32).  Small meshes are
 compared on every row; the 32^3 mesh (the 3D workload) on sampled rows, each
 formed by the oracle from the patches that contain it.
 """
@@ -16,6 +18,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2603_28706_amd import inputs
+from tolerances import fp64_tol, kappa_eq
 
 pytestmark = pytest.mark.gpu
 
@@ -57,7 +60,7 @@ def oracle_steps(prob, uk, r, omega, nsteps):
     for _ in range(nsteps):
         d = O.vanka_step(A, pm, patches, r, d, omega)
         out.append(d.copy())
-    return out
+    return out, fp64_tol(kappa_eq(pm))
 
 
 @pytest.mark.parametrize("n,hi", [((2, 2, 2), (1.0, 1.0, 1.0)), ((3, 2, 4), (1.0, 2.0, 0.5))])
@@ -66,8 +69,8 @@ def test_vanka3d_two_steps_fp64_and_fp32(n, hi):
     prob = oracle_problem(n, MODEL3, lin, hi=hi)
     uk = inputs.sin_series_velocity(n, seed=501, t_nodes=[0.01 / 3, 0.01], hi=hi)
     r = inputs.uniform(502, prob.nst)
-    ref1, ref2 = oracle_steps(prob, uk, r, 0.5, 2)
-    for prec, dt, tol in ((pnsmg.FP64, torch.float64, 1e-10), (pnsmg.FP32, torch.float32, 1e-4)):
+    (ref1, ref2), tol64 = oracle_steps(prob, uk, r, 0.5, 2)
+    for prec, dt, tol in ((pnsmg.FP64, torch.float64, tol64), (pnsmg.FP32, torch.float32, 1e-4)):
         ctx = gpu_context(n, MODEL3, lin, uk, prec, hi=hi)
         d = ctx.vector()
         rd = to_dev(r, dt)
@@ -92,13 +95,15 @@ def test_vanka3d_tangents_and_model_variants(lin):
         prob = oracle_problem(n, model, lin)
         uk = inputs.uniform(511, prob.nt * prob.nv)
         r = inputs.uniform(512, prob.nst)
-        ref = oracle_steps(prob, uk, r, 0.7, 2)[1]
+        refs, tol = oracle_steps(prob, uk, r, 0.7, 2)
+        ref = refs[1]
         ctx = gpu_context(n, model, lin, uk, pnsmg.FP64)
         d = ctx.vector()
         ctx.pns_vanka_smooth(0, 2, 0.7, to_dev(r, torch.float64), d)
         torch.cuda.synchronize()
         err = np.linalg.norm(d.cpu().numpy() - ref) / np.linalg.norm(ref)
-        assert err <= 1e-10, (v, lin, err)
+        print(f"3D vanka lin={lin} {v}: {err:.2e} (bound {tol:.1e})")
+        assert err <= tol, (v, lin, err)
 
 
 def test_vanka3d_two_cells_and_zero_residual():
@@ -109,7 +114,8 @@ def test_vanka3d_two_cells_and_zero_residual():
     prob = oracle_problem(n, MODEL3, pnsmg.MODIFIED_NEWTON)
     uk = inputs.uniform(521, prob.nt * prob.nv)
     r = inputs.uniform(522, prob.nst)
-    ref = oracle_steps(prob, uk, r, 1.0, 1)[0]
+    refs, tol = oracle_steps(prob, uk, r, 1.0, 1)
+    ref = refs[0]
     ctx = pnsmg.Context(n, n_levels=1, precision=pnsmg.FP64, tau=0.01)
     ctx.pns_set_state(dict(MODEL3, lin=pnsmg.MODIFIED_NEWTON), to_dev(uk, torch.float64))
     # the workspace was sized for surrogate patches: the switch is refused and
@@ -121,7 +127,7 @@ def test_vanka3d_two_cells_and_zero_residual():
     d = ctx.vector()
     ctx.pns_vanka_smooth(0, 1, 1.0, to_dev(r, torch.float64), d)
     torch.cuda.synchronize()
-    assert np.linalg.norm(d.cpu().numpy() - ref) <= 1e-10 * np.linalg.norm(ref)
+    assert np.linalg.norm(d.cpu().numpy() - ref) <= tol * np.linalg.norm(ref)
     d2 = ctx.vector()
     ctx.pns_vanka_smooth(0, 3, 0.5, ctx.vector(), d2)
     torch.cuda.synchronize()
@@ -180,7 +186,10 @@ def test_vanka3d_32cubed_sampled_rows():
         ref.append(v)
     ref = np.array(ref)
     scale = np.abs(ref).max()
-    for prec, dt, tol in ((pnsmg.FP64, torch.float64, 1e-10), (pnsmg.FP32, torch.float32, 1e-4)):
+    kappa = kappa_eq([O.local_patch_matrix(prob, [ur, ur], cell)[0] for cell in cache])
+    tol64 = fp64_tol(kappa)
+    print(f"32^3 sampled patches: kappa_eq {kappa:.1e}")
+    for prec, dt, tol in ((pnsmg.FP64, torch.float64, tol64), (pnsmg.FP32, torch.float32, 1e-4)):
         ctx = gpu_context(n, MODEL3, pnsmg.MODIFIED_NEWTON, uk, prec)
         d = ctx.vector()
         ctx.pns_vanka_smooth(0, 1, omega, to_dev(r, dt), d)
@@ -207,7 +216,8 @@ def test_vanka3d_exact_patches(n, hi):
     pm = O.patch_matrices(A, patches)
     ref1 = O.vanka_step(A, pm, patches, r, np.zeros(prob.nst), 0.5)
     ref2 = O.vanka_step(A, pm, patches, r, ref1, 0.5)
-    for prec, dt, tol in ((pnsmg.FP64, torch.float64, 1e-10), (pnsmg.FP32, torch.float32, 1e-4)):
+    tol64 = fp64_tol(kappa_eq(pm))
+    for prec, dt, tol in ((pnsmg.FP64, torch.float64, tol64), (pnsmg.FP32, torch.float32, 1e-4)):
         ctx = pnsmg.Context(n, n_levels=1, precision=prec, tau=0.01, hi=hi,
                             patch_kind=pnsmg.PATCH_EXACT)
         ctx.pns_set_state(dict(MODEL3, lin=lin), to_dev(uk, torch.float64))

@@ -6,8 +6,10 @@ finest patches, exact coarse patches, dense pinned coarsest solve).
 
 Tolerances: transfers and level operators are sums of a few products
 (1e-13 relative); smoother and V-cycle are linear maps through patch and
-coarse solves whose condition numbers on these inputs stay below 1e4, so FP64
-uses 1e-10 and FP32 1e-4, as in 2D.  At 32^3 (the 3D workload, 4 levels) the
+coarse solves; FP64 uses max(1e-12, kappa_eq * 1e-16) with kappa_eq the
+largest equilibrated condition number of the patch and pinned coarsest
+matrices (tests/tolerances.py; below 1e4 on these inputs, so 1e-12), FP32
+1e-4, as in 2D.  At 32^3 (the 3D workload, 4 levels) the
 oracle hierarchy is out of reach, so the V-cycle is checked there by
 linearity and as the preconditioner of a GMRES iteration.
 """
@@ -16,6 +18,7 @@ import pytest
 
 from oracle import oracle as O
 from paper_2603_28706_amd import inputs
+from tolerances import fp64_tol, hierarchy_kappa
 
 pytestmark = pytest.mark.gpu
 
@@ -76,7 +79,7 @@ def test_level_operators_and_coarse_sweeps_3d(n, levels, hi):
     prob = oracle_problem(n, MODEL3, LIN, hi=hi)
     uk = inputs.sin_series_velocity(n, seed=611, t_nodes=[0.01 / 3, 0.01], hi=hi)
     H = O.build_hierarchy(prob, uk, n_levels=levels)
-    for prec, dt, tol_op, tol in ((pnsmg.FP64, torch.float64, 1e-13, 1e-10),
+    for prec, dt, tol_op, tol in ((pnsmg.FP64, torch.float64, 1e-13, fp64_tol(hierarchy_kappa(H))),
                                   (pnsmg.FP32, torch.float32, 1e-5, 1e-4)):
         ctx = setup(n, levels, prec, uk, hi=hi)
         for lev in range(1, levels):
@@ -111,7 +114,8 @@ def test_vcycle_3d_fp64_and_fp32(n, levels, hi):
     r = inputs.uniform(642, prob.nst)
     H = O.build_hierarchy(prob, uk, n_levels=levels)
     ref = O.vcycle(H, r, nu1=2, nu2=2, omega=0.5)
-    for prec, dt, tol in ((pnsmg.FP64, torch.float64, 1e-10), (pnsmg.FP32, torch.float32, 1e-4)):
+    tol64 = fp64_tol(hierarchy_kappa(H))
+    for prec, dt, tol in ((pnsmg.FP64, torch.float64, tol64), (pnsmg.FP32, torch.float32, 1e-4)):
         ctx = setup(n, levels, prec, uk, hi=hi)
         d = ctx.vector()
         ctx.pns_vcycle(2, 2, 0.5, to_dev(r, dt), d)
@@ -136,7 +140,9 @@ def test_vcycle_3d_tangents_and_variants():
             ctx.pns_vcycle(1, 2, 0.6, to_dev(r, torch.float64), d)
             torch.cuda.synchronize()
             err = rel(d.cpu().numpy(), ref)
-            assert err <= 1e-10, (lin, v, err)
+            tol = fp64_tol(hierarchy_kappa(H))
+            print(f"3D V-cycle lin={lin} {v}: {err:.2e} (bound {tol:.1e})")
+            assert err <= tol, (lin, v, err)
 
 
 def test_vcycle_3d_exact_fine_patches():
@@ -146,7 +152,8 @@ def test_vcycle_3d_exact_fine_patches():
     r = inputs.uniform(672, prob.nst)
     H = O.build_hierarchy(prob, uk, n_levels=2, surrogate=False)
     ref = O.vcycle(H, r, nu1=2, nu2=2, omega=0.15)
-    for prec, dt, tol in ((pnsmg.FP64, torch.float64, 1e-10), (pnsmg.FP32, torch.float32, 1e-4)):
+    tol64 = fp64_tol(hierarchy_kappa(H))
+    for prec, dt, tol in ((pnsmg.FP64, torch.float64, tol64), (pnsmg.FP32, torch.float32, 1e-4)):
         ctx = pnsmg.Context(n, n_levels=2, precision=prec, tau=0.01, patch_kind=pnsmg.PATCH_EXACT)
         ctx.pns_set_state(dict(MODEL3, lin=LIN), to_dev(uk, torch.float64))
         ctx.pns_vanka_setup()

@@ -1,5 +1,5 @@
 """CPU pins of the oracle's slab solve: the block mass-weighted residual norm and
-the Newton iteration on R_n(U) = 0 (Sec. 5.3).  They check the oracle against
+the Newton iteration on R_n(U) = 0 (Sec. 6, Sec. 6.2).  They check the oracle against
 closed forms and against properties that any correct solver has, not against
 itself."""
 import numpy as np
