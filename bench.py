@@ -282,9 +282,23 @@ def apply3d(n=32, reps=50, lin=2, smoother=True, sweeps=20, vcycles=10, levels3d
     return out
 
 
-def cpu_baseline(n_sample=128, reps=2):
-    """The oracle (plain per-cell quadrature C code, one thread) on the same
-    parameters and input recipe, on an n_sample^2 mesh."""
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n_sample=256, reps_all=3):
+    """The oracle (plain per-cell quadrature C code, no sum factorisation) on the
+    benchmark's own parameters, input recipe and mesh: one action on one thread,
+    and the median of `reps_all` actions on every core this process may run on
+    (the same per-cell code over the cells in parity classes).  A correctness
+    baseline, not a tuned CPU code."""
     import numpy as np
 
     from oracle import oracle as O
@@ -295,16 +309,49 @@ def cpu_baseline(n_sample=128, reps=2):
                                                                 if k not in ("qsign",)})
     uk = inputs.sin_series_velocity(n, seed=201, t_nodes=[0.01 / 3, 0.01])
     x = inputs.uniform(202, prob.nst)
+    cores = len(os.sched_getaffinity(0))
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp and omp.isdigit():
+        cores = min(cores, int(omp))
+    t0 = time.perf_counter()
+    O.apply(prob, uk, x)
+    t1 = time.perf_counter() - t0
     times = []
-    for _ in range(reps):
+    for _ in range(reps_all):
         t0 = time.perf_counter()
-        O.apply(prob, uk, x)
+        O.apply_threads(prob, uk, x, cores)
         times.append(time.perf_counter() - t0)
-    t = float(np.median(times))
-    return {"value": prob.nst / t / 1e9, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
-            "sample": f"one surrogate-tangent Jacobian action on a {n_sample}x{n_sample} mesh "
-                      f"({prob.nst} space-time DoF), same parameters and input recipe, median of "
-                      f"{reps}, {t:.2f} s each"}
+    tn = float(np.median(times))
+    print(f"[bench] oracle action {n_sample}^2: 1 thread {t1:.2f} s, {cores} threads {tn:.2f} s",
+          file=sys.stderr, flush=True)
+    return {"value": prob.nst / tn / 1e9, "unit": "GDoF/s", "cores": cores, "kind": "oracle",
+            "sample": f"one surrogate-tangent Jacobian action on the benchmark's {n_sample}x"
+                      f"{n_sample} mesh ({prob.nst} space-time DoF), same parameters and input "
+                      f"recipe; {cores} threads: median of {reps_all}, {tn:.2f} s each",
+            "single_core": {"value": prob.nst / t1 / 1e9, "cores": 1, "seconds": round(t1, 3)},
+            "cpu_model": host_cpu_model()}
+
+
+def measured_copy_gbs(nbytes=2 << 30, reps=10):
+    """HBM bandwidth of a plain device-to-device copy (read + write bytes per
+    second), the measured counterpart of the nominal 8 TB/s."""
+    import torch
+
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    stream = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record(stream)
+    torch.cuda.synchronize()
+    t = a.elapsed_time(b) * 1e-3 / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / t / 1e9
 
 
 def run(args):
@@ -692,7 +739,9 @@ def main():
                      "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4),
                      "traffic": measured_traffic(args.n),
                      "kernel": "cell_apply_kernel<double, modified Newton, recompute>",
-                     "flop_per_launch": flops, "algorithmic_bytes": f64["bytes"]},
+                     "flop_per_launch": flops, "algorithmic_bytes": f64["bytes"],
+                     "hbm_copy_measured_gbs": round(measured_copy_gbs(), 1),
+                     "hbm_nominal_gbs": HBM_PEAK_GBS},
     }
     if args.apply3d_n and not args.apply_only:
         a3 = apply3d(args.apply3d_n, lin=args.lin)
@@ -738,7 +787,7 @@ def main():
             **{k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                for k, v in sv.items()}}
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline()
+        line["cpu_baseline"] = cpu_baseline(args.n)
     print(json.dumps(line), flush=True)
 
 

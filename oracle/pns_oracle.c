@@ -461,47 +461,79 @@ void orc_all_element_matrices(const orc_problem* P, const double* u, double* E) 
 
 /* ---------------------------------------------------------- slab apply */
 
-/* y = J_n x, eq. (slab-underint-jac):
- *   y_v,mu = sum_nu Kt[mu][nu] (M_x x_v,nu) + tau wt[mu] (J_mu x_mu)_v
- *   y_p,mu = tau wt[mu] (J_mu x_mu)_p
- * uk holds the velocity state at every Radau node (nt blocks of d*num_nodes),
- * x and y hold nt blocks of spatial_size.  Element by element. */
-void orc_apply(const orc_problem* P, const double* uk, const double* x, double* y) {
+/* Contributions of cell c to y = J_n x, eq. (slab-underint-jac):
+ *   y_v,mu += sum_nu Kt[mu][nu] (M_x x_v,nu) + tau wt[mu] (J_mu x_mu)_v
+ *   y_p,mu += tau wt[mu] (J_mu x_mu)_p
+ * restricted to the cell (its element matrices times its local values).
+ * E: scratch of nloc^2 doubles. */
+static void apply_cell(const orc_problem* P, int c, const double* uk, const double* x,
+                       double* y, double* E) {
   int d = P->dim, nb = ipow3(d), nloc = orc_local_size(P);
-  int nc = orc_num_cells(P), nn = orc_num_nodes(P), ns = orc_spatial_size(P);
-  memset(y, 0, sizeof(double) * (size_t)ns * P->nt);
-  double* E = (double*)malloc(sizeof(double) * nloc * nloc);
+  int nn = orc_num_nodes(P), ns = orc_spatial_size(P);
   double M[729];
   int dofs[85];
   double uloc[81];
-  for (int c = 0; c < nc; ++c) {
-    orc_local_dofs(P, c, dofs);
-    orc_element_mass(P, c, M);
-    for (int mu = 0; mu < P->nt; ++mu) {
-      gather_velocity(P, dofs, uk + (size_t)mu * d * nn, uloc);
-      orc_element_matrix(P, c, uloc, E);
-      const double* xm = x + (size_t)mu * ns;
-      double* ym = y + (size_t)mu * ns;
-      double scale = P->tau * P->wt[mu];
-      for (int i = 0; i < nloc; ++i) {
-        double s = 0.0;
-        for (int j = 0; j < nloc; ++j) s += E[i * nloc + j] * xm[dofs[j]];
-        ym[dofs[i]] += scale * s;
-      }
-      /* temporal mass coupling, velocity only */
-      for (int nu = 0; nu < P->nt; ++nu) {
-        double kmn = P->kt[mu * P->nt + nu];
-        const double* xn = x + (size_t)nu * ns;
-        for (int cc = 0; cc < d; ++cc)
-          for (int a = 0; a < nb; ++a) {
-            double s = 0.0;
-            for (int b = 0; b < nb; ++b) s += M[a * nb + b] * xn[dofs[cc * nb + b]];
-            ym[dofs[cc * nb + a]] += kmn * s;
-          }
-      }
+  orc_local_dofs(P, c, dofs);
+  orc_element_mass(P, c, M);
+  for (int mu = 0; mu < P->nt; ++mu) {
+    gather_velocity(P, dofs, uk + (size_t)mu * d * nn, uloc);
+    orc_element_matrix(P, c, uloc, E);
+    const double* xm = x + (size_t)mu * ns;
+    double* ym = y + (size_t)mu * ns;
+    double scale = P->tau * P->wt[mu];
+    for (int i = 0; i < nloc; ++i) {
+      double s = 0.0;
+      for (int j = 0; j < nloc; ++j) s += E[i * nloc + j] * xm[dofs[j]];
+      ym[dofs[i]] += scale * s;
+    }
+    /* temporal mass coupling, velocity only */
+    for (int nu = 0; nu < P->nt; ++nu) {
+      double kmn = P->kt[mu * P->nt + nu];
+      const double* xn = x + (size_t)nu * ns;
+      for (int cc = 0; cc < d; ++cc)
+        for (int a = 0; a < nb; ++a) {
+          double s = 0.0;
+          for (int b = 0; b < nb; ++b) s += M[a * nb + b] * xn[dofs[cc * nb + b]];
+          ym[dofs[cc * nb + a]] += kmn * s;
+        }
     }
   }
+}
+
+/* y = J_n x, eq. (slab-underint-jac), element by element.
+ * uk holds the velocity state at every Radau node (nt blocks of d*num_nodes),
+ * x and y hold nt blocks of spatial_size. */
+void orc_apply(const orc_problem* P, const double* uk, const double* x, double* y) {
+  int nloc = orc_local_size(P), nc = orc_num_cells(P), ns = orc_spatial_size(P);
+  memset(y, 0, sizeof(double) * (size_t)ns * P->nt);
+  double* E = (double*)malloc(sizeof(double) * nloc * nloc);
+  for (int c = 0; c < nc; ++c) apply_cell(P, c, uk, x, y, E);
   free(E);
+}
+
+/* The same action on `nthreads` host threads (CPU timing only): the cells are
+ * visited in 2^d parity classes (cells of one class share no node and no
+ * pressure coefficient), each class split over the threads.  Per cell the
+ * arithmetic is that of orc_apply; only the order in which the cells add to a
+ * shared node differs. */
+void orc_apply_threads(const orc_problem* P, const double* uk, const double* x, double* y,
+                       int nthreads) {
+  int d = P->dim, nloc = orc_local_size(P), nc = orc_num_cells(P), ns = orc_spatial_size(P);
+  memset(y, 0, sizeof(double) * (size_t)ns * P->nt);
+  for (int color = 0; color < (1 << d); ++color) {
+#pragma omp parallel num_threads(nthreads)
+    {
+      double* E = (double*)malloc(sizeof(double) * nloc * nloc);
+#pragma omp for schedule(static)
+      for (int c = 0; c < nc; ++c) {
+        int cx = c % P->n[0], cy = (c / P->n[0]) % P->n[1];
+        int cz = d == 3 ? c / (P->n[0] * P->n[1]) : 0;
+        int cl = (cx & 1) | ((cy & 1) << 1) | ((cz & 1) << 2);
+        if (cl == color) apply_cell(P, c, uk, x, y, E);
+      }
+      free(E);
+    }
+  }
 }
 
 /* --------------------------------------------------------- slab residual */

@@ -39,3 +39,14 @@ def test_traffic_is_read_per_mesh_size():
         want = d["traffic_bytes_per_launch"] if d["kernel_source_sha256_16"] == \
             bench.kernel_source_hash() else None
         assert bench.measured_traffic(n) == want
+
+
+def test_cpu_baseline_reports_cores_and_model():
+    bench = load_bench()
+    cb = bench.cpu_baseline(8, reps_all=1)
+    assert cb["kind"] == "oracle" and cb["unit"] == "GDoF/s"
+    assert 1 <= cb["cores"] <= len(os.sched_getaffinity(0))
+    assert cb["value"] > 0 and cb["single_core"]["value"] > 0
+    assert cb["single_core"]["cores"] == 1
+    assert isinstance(cb["cpu_model"], str) and cb["cpu_model"]
+    assert "8x8" in cb["sample"]

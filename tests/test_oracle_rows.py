@@ -99,3 +99,17 @@ def test_apply_rows_detects_a_dropped_cell():
         i = int(np.flatnonzero(dofs[c] == node)[0])
         part = prob.tau * w[0] * (E[c][i] @ x[dofs[c]])
         assert abs(part) > 1e-9 * max(1.0, abs(full))
+
+
+@pytest.mark.parametrize("n", [(5, 4), (6, 7), (3, 3, 2), (2, 3, 4)])
+def test_threaded_action_equals_serial(n):
+    """The multi-threaded oracle action (cells in parity classes, used only to
+    time the oracle on every host core) is the serial action up to the order in
+    which cells add to shared nodes."""
+    prob = problem(n)
+    uk = inputs.uniform(11, prob.nt * prob.nv)
+    x = inputs.uniform(12, prob.nst)
+    a = O.apply(prob, uk, x)
+    for th in (1, 3):
+        b = O.apply_threads(prob, uk, x, th)
+        assert np.abs(a - b).max() <= 1e-14 * np.abs(a).max()
