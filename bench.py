@@ -512,7 +512,8 @@ def solve3d_latency(n=32, rtol=1e-8, max_newton=60, rho=0.9):
     Krylov solves), damping 0.15, smoother rebuilt when a Newton step reduces
     the residual by less than rho = 0.9 (the clipped tangent contracts by
     ~0.55 per step, so rho = 0.5 would rebuild at every step); FP64 and mixed
-    precision."""
+    precision, and mixed precision whose FGMRES applies the Jacobian with x and
+    u_k stored in BF16 (FP32 arithmetic)."""
     import torch
 
     from paper_2603_28706_amd import inputs, pnsmg
@@ -521,8 +522,11 @@ def solve3d_latency(n=32, rtol=1e-8, max_newton=60, rho=0.9):
     vprev = torch.tensor(inputs.sin_series_velocity((n, n, n), seed=301, t_nodes=[0.0]),
                          device="cuda")
     out = {}
-    for prec, name in ((pnsmg.FP64, "fp64"), (pnsmg.FP32, "mixed")):
+    for prec, name, jac in ((pnsmg.FP64, "fp64", None), (pnsmg.FP32, "mixed", None),
+                            (pnsmg.FP32, "mixed_bf16_jacobian", pnsmg.BF16)):
         ctx = pnsmg.Context((n, n, n), n_levels=4, precision=prec, patch_kind=pnsmg.PATCH_EXACT)
+        if jac is not None:
+            ctx.pns_set_jacobian_precision(jac)
         sz = ctx.sizes()
         U = torch.zeros(sz["nst"], dtype=torch.float64, device="cuda")
         U[:sz["nv"]] = vprev
@@ -756,11 +760,15 @@ def main():
         line["solve3d_time_to_1e-8_s"] = {
             "workload": (f"3D {args.solve3d_n}^3 slab solve, p=1.3 delta=1e-3 nu0=1 nu_inf=1e-3, "
                          f"modified Newton + FGMRES(30) / 4-level V-cycle (exact finest "
-                         f"patches, omega 0.15, refresh rho 0.9) to ||R||_M <= 1e-8 ||R0||_M"),
+                         f"patches, omega 0.15, refresh rho 0.9) to ||R||_M <= 1e-8 ||R0||_M; "
+                         f"FP64, mixed (FP32 action and V-cycle), mixed with the BF16-storage "
+                         f"Jacobian in FGMRES"),
             **{k: {kk: (float(f"{vv:.5g}") if isinstance(vv, float) else vv)
                    for kk, vv in v.items()}
                for k, v in s3.items()},
-            "mixed_speedup": round(s3["fp64"]["time_s"] / s3["mixed"]["time_s"], 3)}
+            "mixed_speedup": round(s3["fp64"]["time_s"] / s3["mixed"]["time_s"], 3),
+            "mixed_bf16_jacobian_speedup": round(s3["fp64"]["time_s"] /
+                                                 s3["mixed_bf16_jacobian"]["time_s"], 3)}
     if args.solve_n and not args.apply_only:
         sl = solve_latency(args.solve_n, SOLVE_SEEDS)
         line["solve_time_to_1e-8_s"] = {

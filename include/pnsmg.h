@@ -182,6 +182,19 @@ int pns_set_apply_mode(pns_ctx* ctx, int mode);
  * midpoint-frozen surrogate stops preconditioning. */
 int pns_set_patch_kind(pns_ctx* ctx, int kind);
 
+/* Storage precision of the Jacobian action that pns_solve's FGMRES applies
+ * (Sec. 6.1; the mixed-precision pattern of iterative refinement): PNS_BF16 on
+ * a hexahedral PNS_FP32 context stores the Krylov vector and the state u_k in
+ * BF16 (rounded to nearest even from FP64) for that action, with FP32
+ * arithmetic (power law in FP64) and an FP32 result widened to FP64; the
+ * V-cycle preconditioner stays FP32 with its FP64 coarsest solve, the
+ * residual, norms and Krylov vectors FP64.  The context precision (the
+ * default) switches it back.  Query pns_solve_workspace_bytes after setting
+ * it (the BF16 staging adds 2 N_st + 4 n_v bytes).  PNS_EINVAL for an unknown
+ * precision; PNS_EUNSUPPORTED for BF16 on other contexts or for a precision
+ * other than the context's. */
+int pns_set_jacobian_precision(pns_ctx* ctx, int precision);
+
 /* y = J_n(u_k) x on level 0, eq. (slab-underint-jac): the temporal mass
  * coupling K_t (x) M_x plus tau M_t (x) diag(J_1, J_2), each J_mu the spatial
  * linearisation of Sec. 5.2 (viscous volume term with the selected tangent,

@@ -755,6 +755,23 @@ int pns_set_patch_kind(pns_ctx* ctx, int kind) {
   return PNS_OK;
 }
 
+int pns_set_jacobian_precision(pns_ctx* ctx, int precision) {
+  if (!ctx) return PNS_EINVAL;
+  if (precision != PNS_FP64 && precision != PNS_FP32 && precision != PNS_BF16)
+    return fail(ctx, PNS_EINVAL, "unknown precision");
+  if (precision == PNS_BF16) {
+    if (ctx->dim != 3 || ctx->prec != PNS_FP32)
+      return fail(ctx, PNS_EUNSUPPORTED,
+                  "a BF16 Jacobian action needs a hexahedral FP32 context");
+    ctx->jac_bf16 = true;
+    return PNS_OK;
+  }
+  if (precision != ctx->prec)
+    return fail(ctx, PNS_EUNSUPPORTED, "the Jacobian action runs in the context precision or BF16");
+  ctx->jac_bf16 = false;
+  return PNS_OK;
+}
+
 int pns_cell_apply(pns_ctx* ctx, const void* x, void* y) {
   if (!check_ctx(ctx, true, false)) return ctx_code(ctx, true, false);
   if (!x || !y || x == y) return fail(ctx, PNS_EINVAL, "x, y must be distinct non-NULL");

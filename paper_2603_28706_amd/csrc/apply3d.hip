@@ -733,12 +733,18 @@ hipError_t apply3d_any(const Grid3& g, const Model& m, double tau, const S* uk, 
   return hipGetLastError();
 }
 
-// FP64 -> BF16 with round to nearest even (through FP32: the inputs that the
-// tests use are BF16-representable, so the two roundings never both act)
+// FP64 -> BF16 with round to nearest even, correctly rounded for finite
+// values in the FP32 range: the value is first rounded to FP32 by round to
+// odd (truncate, then set the last bit when the truncation was inexact), which
+// keeps every bit the final rounding to 8 significant bits needs, then rounded
+// to nearest even on its upper 16 bits.
 __global__ void to_bf16_kernel(int64_t n, const double* __restrict__ in, uint16_t* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  uint32_t u = __float_as_uint((float)in[i]);
+  const double v = in[i];
+  const float f = __double2float_rz(v);
+  uint32_t u = __float_as_uint(f);
+  if ((double)f != v) u |= 1u;
   u += 0x7fffu + ((u >> 16) & 1u);
   out[i] = (uint16_t)(u >> 16);
 }

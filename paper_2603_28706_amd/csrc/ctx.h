@@ -77,6 +77,9 @@ struct pns_ctx {
   // measured time of every variant of that level's form
   int sweep_var[16] = {};
   float sweep_ms[16][16] = {};
+  // pns_solve's Jacobian action with x and u_k stored in BF16 (3D FP32
+  // contexts, pns_set_jacobian_precision)
+  bool jac_bf16 = false;
   // V-cycles replayed from a captured HIP graph (pns_set_vcycle_graph)
   bool graph_mode = false;
   void* gr = nullptr;  // level-0 right-hand side and correction read / written by the graph

@@ -38,6 +38,8 @@ struct Work {
   double* h = nullptr;   // device scalars
   float* x32 = nullptr;  // FP32 staging (FP32 context)
   float* y32 = nullptr;
+  uint16_t* x16 = nullptr;   // BF16 Jacobian action: the Krylov vector and the state in BF16
+  uint16_t* uk16 = nullptr;
 };
 
 size_t work_layout(const pns_ctx* c, int m, char* base, Work* w) {
@@ -67,6 +69,10 @@ size_t work_layout(const pns_ctx* c, int m, char* base, Work* w) {
   if (c->es == 4) {
     t.x32 = (float*)take(n * 4);
     t.y32 = (float*)take(n * 4);
+  }
+  if (c->jac_bf16) {
+    t.x16 = (uint16_t*)take(n * 2);
+    t.uk16 = (uint16_t*)take(2 * g.nv * 2);
   }
   if (w) *w = t;
   return (off + kAlign - 1) / kAlign * kAlign;
@@ -145,10 +151,18 @@ struct Solver {
     return PNS_OK;
   }
 
-  // y = J_n x in the context precision
+  // y = J_n x in the context precision (x and u_k in BF16 with FP32
+  // arithmetic when the context asks for it)
   int jacobian(const double* x, double* y) {
     int rc;
     if (c->es == 8) return pns_cell_apply(c, x, y);
+    if (c->jac_bf16) {
+      PNS_HIP(c, launch_to_bf16(W.n, x, W.x16, s));
+      PNS_HIP(c, launch_cell_apply3d_bf16(c->g3, c->model, c->disc.tau, W.uk16, W.x16, nullptr,
+                                          W.y32, (float*)c->E3, 0, s));
+      PNS_HIP(c, launch_widen(W.n, W.y32, y, s));
+      return PNS_OK;
+    }
     PNS_HIP(c, launch_narrow(W.n, x, W.x32, s));
     if ((rc = pns_cell_apply(c, W.x32, W.y32)) != PNS_OK) return rc;
     PNS_HIP(c, launch_widen(W.n, W.y32, y, s));
@@ -162,6 +176,7 @@ struct Solver {
     PNS_HIP(c, hipMemcpyAsync(W.uk + g.nv, U + g.ns, g.nv * 8, hipMemcpyDeviceToDevice, s));
     int rc = pns_set_state(c, md, W.uk);
     if (rc != PNS_OK) return rc;
+    if (c->jac_bf16) PNS_HIP(c, launch_to_bf16(2 * g.nv, W.uk, W.uk16, s));
     // the smoother's patch inverses and coarse operators are untouched by a
     // new state; keep them when no refresh is due
     if (keep_smoother) c->has_smoother = had;

@@ -114,6 +114,7 @@ def lib():
         L.pns_cell_apply.argtypes = [_vp, _vp, _vp]
         L.pns_set_apply_mode.argtypes = [_vp, i]
         L.pns_set_patch_kind.argtypes = [_vp, i]
+        L.pns_set_jacobian_precision.argtypes = [_vp, i]
         L.pns_cell_defect.argtypes = [_vp, _vp, _vp, _vp]
         L.pns_vanka_setup.argtypes = [_vp, _vp]
         L.pns_vanka_smooth.argtypes = [_vp, i, i, ctypes.c_double, _vp, _vp]
@@ -145,7 +146,7 @@ def lib():
                   "pns_release"):
             getattr(L, f).restype = ctypes.c_int
         for f in ("pns_ctx_create", "pns_level_sizes", "pns_bind_workspace", "pns_set_state",
-                  "pns_set_apply_mode", "pns_set_patch_kind",
+                  "pns_set_apply_mode", "pns_set_patch_kind", "pns_set_jacobian_precision",
                   "pns_cell_apply", "pns_cell_defect", "pns_vanka_setup", "pns_vanka_smooth",
                   "pns_vcycle", "pns_level_apply", "pns_restrict", "pns_prolongate_add",
                   "pns_residual", "pns_solve"):
@@ -242,6 +243,9 @@ class Context:
 
     def pns_set_patch_kind(self, kind):
         self._check(lib().pns_set_patch_kind(self.h, int(kind)))
+
+    def pns_set_jacobian_precision(self, precision):
+        self._check(lib().pns_set_jacobian_precision(self.h, int(precision)))
 
     def pns_cell_apply(self, x, y):
         self._check(lib().pns_cell_apply(self.h, self._vec(x, dtype=self.in_dtype), self._vec(y)))

@@ -300,3 +300,25 @@ def test_server_entry_points_reject_bad_arguments():
     assert L.pns_request_footprint(ctypes.byref(bad_levels)) == 0
     too_big_coarse = pnsmg.make_request((256, 256), dict(p=1.5, delta=1e-2), vp, U, levels=1)
     assert L.pns_request_footprint(ctypes.byref(too_big_coarse)) == 0
+
+
+def test_jacobian_precision_selection_without_device():
+    """BF16 Jacobian storage is offered on hexahedral FP32 contexts only; it
+    enlarges the solve work buffer by its BF16 staging."""
+    L = pnsmg.lib()
+    rc, h = _create(n=(4, 4, 4), levels=2, prec=pnsmg.FP32)
+    assert rc == pnsmg.PNS_OK
+    before = L.pns_solve_workspace_bytes(h, 30)
+    assert L.pns_set_jacobian_precision(h, 7) == pnsmg.PNS_EINVAL
+    assert L.pns_set_jacobian_precision(h, pnsmg.FP64) == pnsmg.PNS_EUNSUPPORTED
+    assert L.pns_set_jacobian_precision(h, pnsmg.BF16) == pnsmg.PNS_OK
+    after = L.pns_solve_workspace_bytes(h, 30)
+    assert after >= before + 2 * (2 * (3 * 9 ** 3 + 4 * 64)) + 4 * 3 * 9 ** 3
+    assert L.pns_set_jacobian_precision(h, pnsmg.FP32) == pnsmg.PNS_OK
+    assert L.pns_solve_workspace_bytes(h, 30) == before
+    L.pns_ctx_destroy(h)
+    for n, prec in (((8, 8), pnsmg.FP32), ((4, 4, 4), pnsmg.FP64)):
+        rc, h = _create(n=n, levels=1, prec=prec)
+        assert rc == pnsmg.PNS_OK
+        assert L.pns_set_jacobian_precision(h, pnsmg.BF16) == pnsmg.PNS_EUNSUPPORTED
+        L.pns_ctx_destroy(h)

@@ -179,3 +179,57 @@ def test_apply3d_bf16_32cubed_sampled_rows():
     err = np.abs(y.double().cpu().numpy()[rows] - ref).max()
     print(f"32^3 BF16 sampled rows: max abs err {err:.3e} / {np.abs(ref).max():.3e}")
     assert err <= 1e-5 * np.abs(ref).max()
+
+
+def bf16_rne_exact(a):
+    """FP64 -> nearest BF16 (ties to even) by integer arithmetic on the FP64
+    bits, as FP64 values; finite values in the BF16 normal range."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = a.view(np.uint64)
+    drop = np.uint64(45)  # 52 - 7 fraction bits
+    keep = b >> drop
+    rem = b & np.uint64((1 << 45) - 1)
+    half = np.uint64(1 << 44)
+    up = (rem > half) | ((rem == half) & ((keep & np.uint64(1)) == np.uint64(1)))
+    keep = keep + up.astype(np.uint64)  # a carry into the exponent is the right result
+    return (keep << drop).view(np.float64)
+
+
+def test_bf16_rne_exact_reference():
+    one = 1.0
+    cases = [(one + 3 * 2.0 ** -8 - 2.0 ** -40, one + 2.0 ** -7),   # below a tie: down
+             (one + 3 * 2.0 ** -8, one + 2.0 ** -6),                # tie: to even
+             (one + 2.0 ** -8, one),                                # tie: to even
+             (one + 2.0 ** -8 + 2.0 ** -40, one + 2.0 ** -7),       # above a tie: up
+             (2.0 - 2.0 ** -9, 2.0),                                # carry into the exponent
+             (-(one + 3 * 2.0 ** -8 - 2.0 ** -40), -(one + 2.0 ** -7))]
+    got = bf16_rne_exact([c for c, _ in cases])
+    assert np.array_equal(got, np.array([w for _, w in cases]))
+
+
+def test_apply3d_bf16_state_rounding_at_ties():
+    """The FP64 state is rounded to BF16 on the device correctly (nearest,
+    ties to even), also for values within 2^-40 of a tie, where rounding to
+    FP32 first and then to BF16 would round the wrong way half of the time:
+    the action matches the oracle on the correctly rounded state to the FP32
+    bound."""
+    n = (2, 2, 2)
+    prob = oracle_problem(n, MODEL3, pnsmg.MODIFIED_NEWTON)
+    rng = np.random.default_rng(451)
+    m = prob.nt * prob.nv
+    k = rng.integers(0, 128, m)
+    e = rng.integers(-2, 2, m).astype(np.float64)
+    side = rng.choice([-1.0, 1.0], m)
+    sign = rng.choice([-1.0, 1.0], m)
+    uk = sign * 2.0 ** e * (1.0 + k * 2.0 ** -7 + 2.0 ** -8 + side * 2.0 ** -40)
+    ukr = bf16_rne_exact(uk)
+    x, xb = bf16_round(inputs.uniform(452, prob.nst))
+    ref = O.apply(prob, ukr, x)
+    ctx = pnsmg.Context(n, n_levels=1, precision=pnsmg.BF16, tau=0.01)
+    ctx.pns_set_state(dict(MODEL3, lin=pnsmg.MODIFIED_NEWTON), to_dev(uk, torch.float64))
+    y = ctx.vector()
+    ctx.pns_cell_apply(xb.cuda(), y)
+    torch.cuda.synchronize()
+    ev, ep = rel_blocks(y.double().cpu().numpy(), ref, prob)
+    print(f"3D BF16 state at ties: rel err vel={ev:.2e} pres={ep:.2e}")
+    assert ev <= 1e-5 and ep <= 1e-5
