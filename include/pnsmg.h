@@ -237,6 +237,27 @@ int pns_vanka_setup(pns_ctx* ctx, const uint16_t* node_masks);
 int pns_vanka_smooth(pns_ctx* ctx, int level, int n_sweeps, double omega, const void* r_dev,
                      void* d_dev);
 
+/* For callers that cannot allocate device memory or reserve per-context
+ * scratch (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the same n_sweeps additive Vanka steps as
+ * pns_vanka_smooth (same kernels, same arguments, d updated in place), with
+ * the buffers that are neither inputs nor outputs -- the defect r - A_l d of
+ * each step, the tile-edge partial sums of the quadrilateral level-0 action,
+ * the per-cell result slots of the hexahedral actions -- taken from a static
+ * device array of the library (64 MiB, one per GPU, held until the process
+ * ends) instead of the bound workspace.  Allocates nothing: no hipMalloc, no
+ * allocating library call.  Nothing in that array has to start at zero (every
+ * call writes each scratch value before reading it).  All calls on one GPU
+ * share the array, so calls that overlap on one GPU (several streams, several
+ * threads, or a pns_vanka_smooth_static of another context still running)
+ * race; serialise them.  PNS_EINVAL, before any device work, when the level
+ * needs more than 64 MiB of scratch (the defect is N_st values of the context
+ * precision, plus 2D level 0: 3 KB per 16 x 8 tile; 3D: 170 values per cell;
+ * e.g. a 256 x 256 FP64 level 0 needs 13.2 MB, 512 x 512 FP64 53 MB, 32^3
+ * FP64 60 MB), otherwise the errors of pns_vanka_smooth. */
+int pns_vanka_smooth_static(pns_ctx* ctx, int level, int n_sweeps, double omega,
+                            const void* r_dev, void* d_dev);
+
 /* Tile shapes of the batched patch sweeps (Sec. 6.3 additive Vanka step),
  * chosen on the device by an autotuner.  Each patch form has several kernel
  * variants that compute

@@ -150,17 +150,31 @@ const T* tangent_cache(pns_ctx* c) {
   return c->apply_mode == PNS_APPLY_CACHED ? (const T*)c->tcache : nullptr;
 }
 
+// Buffers of one smoothing call that are neither inputs nor outputs: the
+// defect r - A_l d, the tile-edge partial sums of the 2D level-0 action and the
+// per-cell result slots of the 3D actions.  By default the context's own (in
+// the bound workspace); pns_vanka_smooth_static points them into the static
+// device array below.
+struct SmoothScratch {
+  void* res;
+  double* edge;
+  void* slot;
+};
+
 template <typename T>
-hipError_t defect(pns_ctx* c, int l, const T* b, const T* x, T* y) {
+hipError_t defect(pns_ctx* c, int l, const T* b, const T* x, T* y,
+                  const SmoothScratch* sc = nullptr) {
   Level& L = c->lev[l];
+  double* edge = sc ? sc->edge : c->edge2;
+  T* slot = (T*)(sc ? sc->slot : c->E3);
   if (c->dim == 3 && l == 0)
     return launch_cell_apply3d<T>(c->g3, c->model, c->disc.tau, (const T*)c->uk, x, b, y,
-                                  (T*)c->E3, 1, c->stream);
+                                  slot, 1, c->stream);
   if (c->dim == 3)
-    return launch_ebe_apply3d<T>(L.g3, (const T*)L.E, x, b, y, (T*)c->E3, c->stream);
+    return launch_ebe_apply3d<T>(L.g3, (const T*)L.E, x, b, y, slot, c->stream);
   if (l == 0)
     return launch_cell_apply<T>(L.g, c->model, c->disc.tau, (const T*)c->uk, tangent_cache<T>(c),
-                                x, b, y, c->edge2, 1, c->stream);
+                                x, b, y, edge, 1, c->stream);
   return launch_ebe_apply<T>(L.g, (const T*)L.E, x, b, y, 1, c->stream);
 }
 
@@ -194,14 +208,16 @@ bool complex_patches(const pns_ctx* c, int l) {
 }
 
 template <typename T>
-hipError_t smooth(pns_ctx* c, int l, int nsweeps, double omega, const T* r, T* d, bool d_is_zero) {
+hipError_t smooth(pns_ctx* c, int l, int nsweeps, double omega, const T* r, T* d, bool d_is_zero,
+                  const SmoothScratch* sc = nullptr) {
   Level& L = c->lev[l];
+  T* resbuf = (T*)(sc ? sc->res : L.res);
   for (int s = 0; s < nsweeps; ++s) {
     const T* res = r;
     if (!(s == 0 && d_is_zero)) {
-      hipError_t e = defect<T>(c, l, r, d, (T*)L.res);
+      hipError_t e = defect<T>(c, l, r, d, resbuf, sc);
       if (e != hipSuccess) return e;
-      res = (const T*)L.res;
+      res = (const T*)resbuf;
     }
     if (c->dim == 3) {
       hipError_t e = complex_patches(c, l)
@@ -547,6 +563,56 @@ int create3d(const pns_mesh* mesh, const pns_discretization* disc, int n_levels,
   return PNS_OK;
 }
 
+// Scratch of pns_vanka_smooth_static: one array per GPU the library runs on,
+// held until the process ends.  In host code `scratch` names a host-side
+// stand-in, not the device array: its device address is taken once per device
+// with hipGetSymbolAddress and only that address is passed to kernels.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the device of `stream` (looked up with that
+// device current, then kept).
+hipError_t static_scratch(hipStream_t stream, void** out) {
+  int dev = -1;
+  hipError_t e = hipStreamGetDevice(stream, &dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    int cur = -1;
+    if ((e = hipGetDevice(&cur)) != hipSuccess) return e;
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) {
+      const hipError_t e2 = hipSetDevice(cur);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
+}
+
+// Bytes of static scratch one smoothing call on `level` uses: the defect, the
+// 2D level-0 tile-edge partial sums, the 3D per-cell result slots.
+size_t static_scratch_need(const pns_ctx* c, int level) {
+  auto up = [](size_t b) { return (b + kAlign - 1) / kAlign * kAlign; };
+  const Level& L = c->lev[level];
+  size_t need = up(L.g.nst * c->es);
+  if (c->dim == 3)
+    need += up(L.g.nc * 170 * c->es);
+  else if (level == 0)
+    need += up(cell_apply_edge_doubles(L.g) * 8);
+  return need;
+}
+
 }  // namespace
 
 int pns::make_model(const pns_model* md, Model* m, std::string* err) {
@@ -827,6 +893,38 @@ int pns_vanka_smooth(pns_ctx* ctx, int level, int n_sweeps, double omega, const 
     PNS_HIP(ctx, smooth<double>(ctx, level, n_sweeps, omega, (const double*)r, (double*)d, false));
   else
     PNS_HIP(ctx, smooth<float>(ctx, level, n_sweeps, omega, (const float*)r, (float*)d, false));
+  return PNS_OK;
+}
+
+int pns_vanka_smooth_static(pns_ctx* ctx, int level, int n_sweeps, double omega, const void* r,
+                            void* d) {
+  if (!ctx) return PNS_EINVAL;
+  if (ctx->prec == PNS_BF16)
+    return fail(ctx, PNS_EUNSUPPORTED, "BF16 contexts have the action only");
+  if (level < 0 || level >= ctx->nlev || n_sweeps < 0 || !r || !d || r == d)
+    return fail(ctx, PNS_EINVAL, "bad level, sweep count or vectors");
+  const size_t need = static_scratch_need(ctx, level);
+  if (need > kStaticScratchBytes)
+    return fail(ctx, PNS_EINVAL,
+                "level too large for the static scratch: needs " + std::to_string(need) +
+                    " bytes, the limit is " + std::to_string(kStaticScratchBytes));
+  if (!check_ctx(ctx, true, true)) return ctx_code(ctx, true, true);
+  if (ctx->dim == 3 && level >= 1 && level == ctx->nlev - 1)
+    return fail(ctx, PNS_EINVAL, "the coarsest 3D level has no patches (dense solve)");
+  void* base = nullptr;
+  PNS_HIP(ctx, static_scratch(ctx->stream, &base));
+  const Level& L = ctx->lev[level];
+  const size_t res_bytes = (L.g.nst * ctx->es + kAlign - 1) / kAlign * kAlign;
+  SmoothScratch sc;
+  sc.res = base;
+  sc.edge = (ctx->dim == 2 && level == 0) ? (double*)((char*)base + res_bytes) : nullptr;
+  sc.slot = ctx->dim == 3 ? (void*)((char*)base + res_bytes) : nullptr;
+  if (ctx->es == 8)
+    PNS_HIP(ctx, smooth<double>(ctx, level, n_sweeps, omega, (const double*)r, (double*)d, false,
+                                &sc));
+  else
+    PNS_HIP(ctx, smooth<float>(ctx, level, n_sweeps, omega, (const float*)r, (float*)d, false,
+                               &sc));
   return PNS_OK;
 }
 

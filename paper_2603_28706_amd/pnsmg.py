@@ -118,6 +118,7 @@ def lib():
         L.pns_cell_defect.argtypes = [_vp, _vp, _vp, _vp]
         L.pns_vanka_setup.argtypes = [_vp, _vp]
         L.pns_vanka_smooth.argtypes = [_vp, i, i, ctypes.c_double, _vp, _vp]
+        L.pns_vanka_smooth_static.argtypes = [_vp, i, i, ctypes.c_double, _vp, _vp]
         L.pns_vcycle.argtypes = [_vp, i, i, ctypes.c_double, _vp, _vp]
         L.pns_set_vcycle_graph.argtypes = [_vp, i]
         L.pns_sweep_variant.argtypes = [_vp, i, pp(ctypes.c_int)]
@@ -148,6 +149,7 @@ def lib():
         for f in ("pns_ctx_create", "pns_level_sizes", "pns_bind_workspace", "pns_set_state",
                   "pns_set_apply_mode", "pns_set_patch_kind", "pns_set_jacobian_precision",
                   "pns_cell_apply", "pns_cell_defect", "pns_vanka_setup", "pns_vanka_smooth",
+                  "pns_vanka_smooth_static",
                   "pns_vcycle", "pns_level_apply", "pns_restrict", "pns_prolongate_add",
                   "pns_residual", "pns_solve"):
             getattr(L, f).restype = ctypes.c_int
@@ -265,6 +267,10 @@ class Context:
     def pns_vanka_smooth(self, level, n_sweeps, omega, r, d):
         self._check(lib().pns_vanka_smooth(self.h, level, n_sweeps, float(omega),
                                            self._vec(r, level), self._vec(d, level)))
+
+    def pns_vanka_smooth_static(self, level, n_sweeps, omega, r, d):
+        self._check(lib().pns_vanka_smooth_static(self.h, level, n_sweeps, float(omega),
+                                                  self._vec(r, level), self._vec(d, level)))
 
     def pns_vcycle(self, nu1, nu2, omega, r, d):
         self._check(lib().pns_vcycle(self.h, nu1, nu2, float(omega), self._vec(r), self._vec(d)))
