@@ -335,6 +335,23 @@ int pns_prolongate_add(pns_ctx* ctx, int level, const void* dc_dev, void* df_dev
 int pns_residual(pns_ctx* ctx, const pns_model* model, const double* U_dev,
                  const double* v_prev_dev, double* R_dev);
 
+/* Volume force (the f-term of eq. disc-residual on one slab, with the Radau
+ * rule of eq. slab-underint): F_v,mu = tau w_mu (f(t_mu), phi)_Omega, each
+ * cell integrated with its 3^d-point Gauss rule; F_p = 0.  f_qp_dev (FP64,
+ * device): f at the Gauss points of every cell at both Radau nodes,
+ * f_qp[((mu * cells + cell) * 3^d + q) * d + comp], cells lexicographic
+ * (x fastest), q = qx + 3 qy (+ 9 qz) over the points x_c + h (g_qx, g_qy
+ * [, g_qz]) - x_c the cell's low corner, g = 1/2 - sqrt(3/5)/2, 1/2,
+ * 1/2 + sqrt(3/5)/2 -, t_mu = t0 + tau (1/3, 1).  F_dev: FP64 device vector
+ * of N_st values (canonical layout), overwritten.  Needs no workspace. */
+int pns_load_vector(pns_ctx* ctx, const double* f_qp_dev, double* F_dev);
+
+/* Register a load vector F (FP64 device vector of N_st values, e.g. from
+ * pns_load_vector; caller-owned, read at every use) that pns_residual,
+ * pns_solve and pns_march add to every slab residual, R_n(U) + F; NULL (the
+ * default) for f = 0.  pns_march adds the same F to each of its slabs. */
+int pns_set_load(pns_ctx* ctx, const double* F_dev);
+
 /* Parameters of pns_solve. */
 typedef struct {
   int max_newton;     /* nonlinear iterations */

@@ -94,9 +94,10 @@ def lib():
         L.orc_apply_threads.argtypes = [P, dp, dp, dp, ctypes.c_int]
         L.orc_element_form.argtypes = [P, ctypes.c_int, dp, dp, dp, dp]
         L.orc_residual.argtypes = [P, dp, dp, dp, dp]
+        L.orc_load.argtypes = [P, dp, dp]
         for f in ("orc_stress", "orc_tangent", "orc_local_dofs", "orc_element_matrix",
                   "orc_element_mass", "orc_all_element_matrices", "orc_apply",
-                  "orc_apply_threads", "orc_element_form", "orc_residual"):
+                  "orc_apply_threads", "orc_element_form", "orc_residual", "orc_load"):
             getattr(L, f).restype = None
         _lib = L
     return _lib
@@ -393,14 +394,50 @@ def apply_threads(prob: Problem, uk, x, nthreads, **kw):
     return y
 
 
-def residual(prob: Problem, U, vprev=None, ulag=None, **kw):
-    """Slab residual R_n(U), eq. (slab-underint), f = 0, g_D = 0."""
+def quadrature_points(prob: Problem):
+    """Physical coordinates of the volume Gauss points (3 per direction) of
+    every cell: array [cells, 3^d, d], cells lexicographic (x fastest), points
+    q = qx + 3 qy (+ 9 qz)."""
+    d = prob.dim
+    g = 0.5 - np.sqrt(3.0 / 5.0) / 2.0
+    gp = np.array([g, 0.5, 1.0 - g])
+    h = [(prob.hi[k] - prob.lo[k]) / prob.n[k] for k in range(d)]
+    cells = np.indices(prob.n[::-1]).reshape(d, -1)[::-1].T      # (cx, cy[, cz]), x fastest
+    qs = np.indices((3,) * d).reshape(d, -1)[::-1].T                # (qx, qy[, qz]), qx fastest
+    out = np.zeros((cells.shape[0], 3 ** d, d))
+    for k in range(d):
+        out[:, :, k] = prob.lo[k] + h[k] * (cells[:, k][:, None] + gp[qs[:, k]][None, :])
+    return out
+
+
+def radau_times(prob: Problem, t0: float):
+    """Times of the Gauss-Radau nodes of the slab (t0, t0 + tau]."""
+    t, _ = radau_right(prob.k_time)
+    return t0 + prob.tau * np.asarray(t)
+
+
+def load_vector(prob: Problem, f_qp):
+    """F_v,mu = tau w_mu (f(t_mu), phi)_Omega (Gauss rule per cell), F_p = 0:
+    the volume-force term of eq. (disc-residual) on one slab.  f_qp: f at the
+    points of `quadrature_points` for every Radau node, [nt, cells, 3^d, d]."""
+    f_qp = _f64(f_qp)
+    assert f_qp.size == prob.nt * prob.num_cells * 3 ** prob.dim * prob.dim
+    F = np.zeros(prob.nst)
+    lib().orc_load(_cs(prob), _dp(f_qp), _dp(F))
+    return F
+
+
+def residual(prob: Problem, U, vprev=None, ulag=None, load=None, **kw):
+    """Slab residual R_n(U), eq. (slab-underint), g_D = 0; `load` is the
+    volume-force vector of `load_vector` (None: f = 0)."""
     U = _f64(U)
     R = np.zeros(prob.nst)
     vp = _f64(vprev) if vprev is not None else None
     ul = _f64(ulag) if ulag is not None else None
     lib().orc_residual(_cs(prob, **kw), _dp(U), _dp(vp) if vp is not None else None,
                        _dp(ul) if ul is not None else None, _dp(R))
+    if load is not None:
+        R += _f64(load)
     return R
 
 
@@ -821,7 +858,7 @@ class NewtonResult:
 
 
 def newton_solve(prob: Problem, vprev, U0=None, rtol=1e-8, atol=0.0, max_it=30, c_armijo=1e-4,
-                 max_backtrack=30):
+                 max_backtrack=30, load=None):
     """Newton iteration on R_n(U) = 0, eq. (nk-newton-lin): J_n(U^m) dU = R_n(U^m)
     with J_n the slab linearisation of prob.lin, solved directly (sparse LU, with
     the constant pressure coefficient of cell 0 pinned per time node: with
@@ -830,13 +867,14 @@ def newton_solve(prob: Problem, vprev, U0=None, rtol=1e-8, atol=0.0, max_it=30, 
     backtracking on phi = ||R||_M^2 / 2 (halving lambda until
     ||R(U + lambda dU)||_M <= (1 - c lambda) ||R(U)||_M); stops when
     ||R||_M <= max(atol, rtol ||R(U^0)||_M), eq. (nk-stop).  U0 defaults to
-    the left trace at both time nodes with zero pressure."""
+    the left trace at both time nodes with zero pressure; `load` a
+    volume-force vector (`load_vector`), None for f = 0."""
     import scipy.sparse.linalg as spla
 
     M = slab_mass(prob)
     vprev = _f64(vprev)
     U = state_from_velocity(prob, np.concatenate([vprev] * prob.nt)) if U0 is None else _f64(U0).copy()
-    R = residual(prob, U, vprev)
+    R = residual(prob, U, vprev, load=load)
     r0 = mass_norm(prob, R, M)
     norms, steps = [r0], []
     pin = pressure_pin_indices(prob)
@@ -849,7 +887,7 @@ def newton_solve(prob: Problem, vprev, U0=None, rtol=1e-8, atol=0.0, max_it=30, 
         dU[keep] = spla.splu(J[keep][:, keep].tocsc()).solve(R[keep])
         lam = 1.0
         for _ in range(max_backtrack):
-            Rn = residual(prob, U + lam * dU, vprev)
+            Rn = residual(prob, U + lam * dU, vprev, load=load)
             nn = mass_norm(prob, Rn, M)
             if nn <= (1.0 - c_armijo * lam) * norms[-1]:
                 break

@@ -536,6 +536,38 @@ void orc_apply_threads(const orc_problem* P, const double* uk, const double* x, 
   }
 }
 
+/* ------------------------------------------------------------ load vector */
+
+/* Right-hand side of the volume force on the slab, the f-term of eq.
+ * (disc-residual) under the Radau rule of eq. (slab-underint):
+ *   F_v,mu[i] = tau wt[mu] (f(t_mu), phi_i)_Omega,   F_p = 0,
+ * each cell integrated with its 3^d-point Gauss rule.  f_qp holds f at those
+ * points: f_qp[((mu * cells + cell) * 3^d + q) * d + comp], q = qx + 3 qy
+ * (+ 9 qz), the points ordered as in volume_rule. */
+void orc_load(const orc_problem* P, const double* f_qp, double* F) {
+  int d = P->dim, nb = ipow3(d), nc = orc_num_cells(P), ns = orc_spatial_size(P);
+  memset(F, 0, sizeof(double) * (size_t)ns * P->nt);
+  int dofs[85];
+  double xi[27][3], w[27];
+  for (int c = 0; c < nc; ++c) {
+    cellgeo g;
+    cell_setup(P, c, &g);
+    orc_local_dofs(P, c, dofs);
+    int nq = volume_rule(&g, xi, w);
+    for (int mu = 0; mu < P->nt; ++mu) {
+      double* Fm = F + (size_t)mu * ns;
+      double scale = P->tau * P->wt[mu];
+      for (int q = 0; q < nq; ++q) {
+        basis_at B;
+        eval_basis(&g, xi[q], &B);
+        const double* f = f_qp + (((size_t)mu * nc + c) * nq + q) * d;
+        for (int cc = 0; cc < d; ++cc)
+          for (int a = 0; a < nb; ++a) Fm[dofs[cc * nb + a]] += scale * w[q] * f[cc] * B.phi[a];
+      }
+    }
+  }
+}
+
 /* --------------------------------------------------------- slab residual */
 
 /* Nonlinear left-hand-side form A_gamma(u,pi)(w) at one point (volume part):

@@ -838,6 +838,22 @@ int pns_set_jacobian_precision(pns_ctx* ctx, int precision) {
   return PNS_OK;
 }
 
+int pns_load_vector(pns_ctx* ctx, const double* f_qp, double* F) {
+  if (!ctx) return PNS_EINVAL;
+  if (!f_qp || !F) return fail(ctx, PNS_EINVAL, "NULL f or F");
+  if (ctx->dim == 3)
+    PNS_HIP(ctx, launch_load3(ctx->g3, ctx->disc.tau, f_qp, F, ctx->stream));
+  else
+    PNS_HIP(ctx, launch_load2(ctx->lev[0].g, ctx->disc.tau, f_qp, F, ctx->stream));
+  return PNS_OK;
+}
+
+int pns_set_load(pns_ctx* ctx, const double* F) {
+  if (!ctx) return PNS_EINVAL;
+  ctx->load = F;
+  return PNS_OK;
+}
+
 int pns_cell_apply(pns_ctx* ctx, const void* x, void* y) {
   if (!check_ctx(ctx, true, false)) return ctx_code(ctx, true, false);
   if (!x || !y || x == y) return fail(ctx, PNS_EINVAL, "x, y must be distinct non-NULL");

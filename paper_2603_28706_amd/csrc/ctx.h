@@ -77,6 +77,8 @@ struct pns_ctx {
   // measured time of every variant of that level's form
   int sweep_var[16] = {};
   float sweep_ms[16][16] = {};
+  // volume-force vector added to every slab residual (pns_set_load), or NULL
+  const double* load = nullptr;
   // pns_solve's Jacobian action with x and u_k stored in BF16 (3D FP32
   // contexts, pns_set_jacobian_precision)
   bool jac_bf16 = false;

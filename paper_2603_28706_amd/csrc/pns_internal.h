@@ -270,6 +270,12 @@ hipError_t launch_fill(int64_t n, T v, T* y, hipStream_t s);
 hipError_t launch_residual(const Grid& g, const Model& m, double tau, const double* U,
                            const double* vprev, double* R, hipStream_t s);
 
+// load.hip: volume-force right-hand side from f at the Gauss points of every
+// cell (f_qp[((mu * cells + cell) * 3^d + q) * d + comp]), FP64; y += x
+hipError_t launch_load2(const Grid& g, double tau, const double* f_qp, double* F, hipStream_t s);
+hipError_t launch_load3(const Grid3& g, double tau, const double* f_qp, double* F, hipStream_t s);
+hipError_t launch_add(int64_t n, const double* x, double* y, hipStream_t s);
+
 // krylov.hip: vector kernels of the slab solve (FP64)
 int dot_partials();  // partial sums per vector of launch_multi_dot
 hipError_t launch_mass(const Grid& g, double tau, const double* x, double* y, hipStream_t s);

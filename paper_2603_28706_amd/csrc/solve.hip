@@ -136,8 +136,13 @@ struct Solver {
   }
 
   int residual(const double* U, double* R) {
-    if (c->dim == 3) return residual3d(c, model, U, vprev, R);
-    PNS_HIP(c, launch_residual(g, model, c->disc.tau, U, vprev, R, s));
+    if (c->dim == 3) {
+      const int rc = residual3d(c, model, U, vprev, R);
+      if (rc != PNS_OK) return rc;
+    } else {
+      PNS_HIP(c, launch_residual(g, model, c->disc.tau, U, vprev, R, s));
+    }
+    if (c->load) PNS_HIP(c, launch_add(W.n, c->load, R, s));
     return PNS_OK;
   }
 
@@ -273,12 +278,18 @@ int pns_residual(pns_ctx* ctx, const pns_model* md, const double* U, const doubl
   if (!ctx) return PNS_EINVAL;
   if (ctx->prec == PNS_BF16) return fail(ctx, PNS_EUNSUPPORTED, "BF16 contexts have the action only");
   if (!ctx->ws) return fail(ctx, PNS_EWORKSPACE, "no workspace bound");
-  if (!md || !U || !R || U == R) return fail(ctx, PNS_EINVAL, "NULL model or vectors, or U == R");
+  if (!md || !U || !R || U == R || R == ctx->load)
+    return fail(ctx, PNS_EINVAL, "NULL model or vectors, U == R, or R is the load vector");
   Model m;
   const int rc = make_model(md, &m, &ctx->err);
   if (rc != PNS_OK) return rc;
-  if (ctx->dim == 3) return residual3d(ctx, m, U, vprev, R);
-  PNS_HIP(ctx, launch_residual(ctx->lev[0].g, m, ctx->disc.tau, U, vprev, R, ctx->stream));
+  if (ctx->dim == 3) {
+    const int rc = residual3d(ctx, m, U, vprev, R);
+    if (rc != PNS_OK) return rc;
+  } else {
+    PNS_HIP(ctx, launch_residual(ctx->lev[0].g, m, ctx->disc.tau, U, vprev, R, ctx->stream));
+  }
+  if (ctx->load) PNS_HIP(ctx, launch_add(ctx->lev[0].g.nst, ctx->load, R, ctx->stream));
   return PNS_OK;
 }
 

@@ -128,6 +128,8 @@ def lib():
         L.pns_restrict.argtypes = [_vp, i, _vp, _vp]
         L.pns_prolongate_add.argtypes = [_vp, i, _vp, _vp]
         L.pns_residual.argtypes = [_vp, pp(pns_model), _vp, _vp, _vp]
+        L.pns_load_vector.argtypes = [_vp, _vp, _vp]
+        L.pns_set_load.argtypes = [_vp, _vp]
         L.pns_solve_workspace_bytes.argtypes = [_vp, i]
         L.pns_solve_workspace_bytes.restype = ctypes.c_size_t
         L.pns_solve.argtypes = [_vp, pp(pns_model), _vp, _vp, pp(pns_solve_params), _vp,
@@ -151,7 +153,7 @@ def lib():
                   "pns_cell_apply", "pns_cell_defect", "pns_vanka_setup", "pns_vanka_smooth",
                   "pns_vanka_smooth_static",
                   "pns_vcycle", "pns_level_apply", "pns_restrict", "pns_prolongate_add",
-                  "pns_residual", "pns_solve"):
+                  "pns_residual", "pns_solve", "pns_load_vector", "pns_set_load"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -307,6 +309,24 @@ class Context:
         vp = None if vprev is None else self._f64(vprev, sz["nv"])
         self._check(lib().pns_residual(self.h, ctypes.byref(model_struct(model)),
                                        self._f64(U, sz["nst"]), vp, self._f64(R, sz["nst"])))
+
+    def pns_load_vector(self, f_qp, F):
+        """F (FP64, N_st) = the volume-force vector of f at the Gauss points
+        (FP64 device tensor [2, cells, 3^d, d])."""
+        sz = self.sizes(0)
+        d = self.dim
+        self._f64(f_qp, 2 * sz["cells"] * 3 ** d * d)
+        self._check(lib().pns_load_vector(self.h, _ptr(f_qp), self._f64(F, sz["nst"])))
+
+    def pns_set_load(self, F):
+        """Add F (FP64 device tensor of N_st values, kept alive by the caller)
+        to every slab residual; None clears it."""
+        if F is None:
+            self._load = None
+            self._check(lib().pns_set_load(self.h, None))
+            return
+        self._load = F
+        self._check(lib().pns_set_load(self.h, self._f64(F, self.sizes(0)["nst"])))
 
     def pns_solve_workspace_bytes(self, restart):
         return lib().pns_solve_workspace_bytes(self.h, int(restart))
