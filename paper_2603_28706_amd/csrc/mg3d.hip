@@ -6,14 +6,14 @@
 //   interpolation per Radau node and velocity component, one 4 x 4 P1disc
 //   restriction per Radau node), so one workgroup forms one block of E_C
 //   (row group x column group) over the 8 children;
-// * patch3r_kernel: exact patches R_K A_l R_K^T (sums of the element matrices
+// * patch3m_kernel: exact patches R_K A_l R_K^T (sums of the element matrices
 //   of the cells around the patch: stored Galerkin matrices on coarse levels,
 //   or on the finest level K_t (x) M + tau M_t (x) diag(J_1, J_2) formed from
-//   the spatial matrices of both Radau nodes), inverted by Gauss-Jordan with
-//   partial row pivoting in FP64; the 170 x 170 matrix (231 KB) is larger than
-//   the LDS of a CU but fits in the registers of a 1024-thread workgroup, which
-//   holds it there (29 entries per thread) and exchanges only the pivot row and
-//   column through LDS; the inverse is written in the context precision;
+//   the spatial matrices of both Radau nodes), inverted by blocked
+//   Gauss-Jordan with partial pivoting in FP64 on the matrix cores; the
+//   170 x 170 matrix (231 KB) is larger than the LDS of a CU but fits in the
+//   registers of a 512-thread workgroup as 16 x 16 accumulator tiles; the
+//   inverse is written in the context precision;
 // * ebe3_kernel: the level operator element by element, y_K = E_K x_K into the
 //   per-cell slots, summed per unknown by the gather of the 3D action;
 // * patch_sweep3r_kernel: additive Vanka step with the real coarse inverses,
@@ -42,8 +42,11 @@ struct FineSrc3 {
   __device__ double operator()(int64_t cell, int r, int c) const {
     const int mu = r / kNs3, i = r % kNs3, nu = c / kNs3, j = c % kNs3;
     double v = 0.0;
-    if (i < kNv3 && j < kNv3 && i / kNb3 == j / kNb3)
-      v = kKt[mu][nu] * cell_mass3(g, i % kNb3, j % kNb3);
+    if (i < kNv3 && j < kNv3 && i / kNb3 == j / kNb3) {
+      const double kt = mu == 0 ? (nu == 0 ? kKt[0][0] : kKt[0][1])
+                                : (nu == 0 ? kKt[1][0] : kKt[1][1]);
+      v = kt * cell_mass3(g, i % kNb3, j % kNb3);
+    }
     if (mu == nu) v += tau * kWt[mu] * (mu == 0 ? Es_a : Es_b)[cell * kEs3 + i * kNs3 + j];
     return v;
   }
@@ -133,187 +136,268 @@ __global__ void transpose_convert3_kernel(int64_t ncells, const double* __restri
 // ------------------------------------------------------------- patches
 
 constexpr int kPT = 512;
-// register-resident Gauss-Jordan: 6 threads per row, each holding 29 entries
-// (columns part, part + 6, ...) of one row of the 170 x 170 FP64 matrix
-constexpr int kRP = 6;
-constexpr int kRS = (kNst3 + kRP - 1) / kRP;  // 29
-constexpr int kRT = kNst3 * kRP;               // 1020 working threads
 
-// One workgroup of 1024 threads per patch (one colour per launch).  The matrix
-// lives in registers (58 VGPRs per thread); each pivot step exchanges only
-// column k, rows k and p and the new pivot row through LDS, so a step costs
-// five barriers and O(170) LDS traffic.
+// Entry (i, j) of the exact patch R_K A R_K^T of cell (cx, cy, cz): the sum of
+// the element matrices of the cells that hold both unknowns (the cell's own
+// pressure lives in that cell only).
+template <typename Src>
+__device__ double patch3_entry(const Grid3& g, const Src& Esrc, int cx, int cy, int cz, int i,
+                               int j) {
+  const int64_t K = cell_index3(g, cx, cy, cz);
+  const int mr = i / kNs3, sr = i % kNs3, mc = j / kNs3, sc = j % kNs3;
+  if (sr >= kNv3 || sc >= kNv3) return Esrc(K, i, j);
+  const int ea = sr % kNb3, eb = sc % kNb3;
+  const int ax = ea % 3, ay = (ea / 3) % 3, az = ea / 9;
+  const int bx = eb % 3, by = (eb / 3) % 3, bz = eb / 9;
+  // neighbours that share both nodes: a step -1 (+1) along a direction when
+  // both nodes lie on the low (high) face of the cell in that direction
+  const int lox = (ax == 0 && bx == 0 && cx > 0) ? -1 : 0;
+  const int hix = (ax == 2 && bx == 2 && cx < g.nx - 1) ? 1 : 0;
+  const int loy = (ay == 0 && by == 0 && cy > 0) ? -1 : 0;
+  const int hiy = (ay == 2 && by == 2 && cy < g.ny - 1) ? 1 : 0;
+  const int loz = (az == 0 && bz == 0 && cz > 0) ? -1 : 0;
+  const int hiz = (az == 2 && bz == 2 && cz < g.nz - 1) ? 1 : 0;
+  const int rbase = mr * kNs3 + (sr / kNb3) * kNb3, cbase = mc * kNs3 + (sc / kNb3) * kNb3;
+  double v = 0.0;
+  for (int oz = loz; oz <= hiz; ++oz)
+    for (int oy = loy; oy <= hiy; ++oy)
+      for (int ox = lox; ox <= hix; ++ox) {
+        const int na = (ax - 2 * ox) + 3 * (ay - 2 * oy) + 9 * (az - 2 * oz);
+        const int nb = (bx - 2 * ox) + 3 * (by - 2 * oy) + 9 * (bz - 2 * oz);
+        v += Esrc(cell_index3(g, cx + ox, cy + oy, cz + oz), rbase + na, cbase + nb);
+      }
+  return v;
+}
+
+// Blocked Gauss-Jordan inversion of the 170 x 170 patches on the FP64 matrix
+// cores.  The patch, padded to 176 x 176 with an identity block (whose inverse
+// is the identity again), is held in the registers of a 512-thread workgroup
+// as 121 tiles of 16 x 16 in the accumulator layout of v_mfma_f64_16x16x4f64
+// (lane l holds rows l/16 + 4r, r = 0..3, of column l%16 of a tile); wave w
+// holds tiles t = 8 s + w.  Per block column K of 16 columns:
+// * the panel (all rows, the 16 columns of K) goes through LDS into the
+//   registers of the workgroup, one panel row per lane (22 per wave), and the
+//   workgroup performs its 16 exchange steps (pivot = largest |entry| among
+//   the rows not yet pivoted, reduced within each wave and then across the
+//   waves; the pivot row is scaled and broadcast through LDS, the column
+//   eliminated from every other row, the pivot column replaced by its
+//   elementary-transform column; two barriers per step), so the panel ends
+//   as the columns E[:, r_m] of the product E of the 16 transforms, r_m the
+//   pivot rows;
+// * every other column is multiplied by E: W[:, J] += (E[:, R] - I[:, R])
+//   W[R, J], a rank-16 update whose left factor is the panel with 1
+//   subtracted at (r_m, m) and whose right factor the 16 pivot rows gathered
+//   before the update: 4 MFMA per 16 x 16 tile.
+// Rows are never interchanged (the pivot rows are recorded): the final array
+// holds the inverse with permuted rows and columns, A^{-1}[i][j] =
+// W[r_i][c] with r_c = j, which the write-out undoes.  Same arithmetic as
+// Gauss-Jordan with partial pivoting, in another summation order.
+constexpr int kMB = 16;                       // block = MFMA tile
+constexpr int kMN = 176;                      // padded order
+constexpr int kMT = kMN / kMB;                // 11 tile rows / columns
+constexpr int kMWaves = 8;                    // 2 waves per SIMD: room for 16 tiles each
+constexpr int kMThreads = 64 * kMWaves;
+constexpr int kMSlots = (kMT * kMT + kMWaves - 1) / kMWaves;  // 16 tiles per wave
+constexpr int kPS = kMB + 1;                  // panel row stride (odd: spreads the banks)
+constexpr int kMR = (kMN + kMWaves - 1) / kMWaves;  // panel rows per wave (22)
+constexpr int kOS = kMN + 1;                  // output staging row stride
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
 template <typename T, typename Src>
-__global__ __launch_bounds__(1024) void patch3r_kernel(Grid3 g, Src Esrc, T* __restrict__ inv,
+__global__ __launch_bounds__(kMThreads) void patch3m_kernel(Grid3 g, Src Esrc, T* __restrict__ inv,
                                                        int* status, int px, int py, int pz,
                                                        int ncx, int ncy) {
-  __shared__ double colv[kNst3], rowk[kNst3], rowp[kNst3], rowb[kNst3], fk[kNst3];
-  __shared__ int piv[kNst3], dst[kNst3], srcc[kNst3];
-  __shared__ double s_pv;
-  __shared__ int s_p, s_sing;
+  __shared__ double P[kMN * kPS];      // panel
+  __shared__ double Bm[kMB * kOS];     // pivot rows (right factor); output staging at the end
+  __shared__ int rowpiv[kMN];          // pivot row of each column
+  __shared__ int rinv[kMN];            // column of each pivot row (-1: not yet pivoted)
+  __shared__ double prow[kMB];         // scaled pivot row of the current exchange step
+  __shared__ double cand_v[2][kMWaves];  // per-wave pivot candidates (two steps in turn)
+  __shared__ int cand_i[2][kMWaves];
+  __shared__ int s_sing;
   const int64_t pid = blockIdx.x;
   const int cx = px + 2 * (int)(pid % ncx);
   const int cy = py + 2 * (int)((pid / ncx) % ncy);
   const int cz = pz + 2 * (int)(pid / ((int64_t)ncx * ncy));
-  const int64_t K = cell_index3(g, cx, cy, cz);
-  const int cc[3] = {cx, cy, cz}, nc[3] = {g.nx, g.ny, g.nz};
-  const int t = threadIdx.x;
-  const bool active = t < kRT;
-  const int i = t % kNst3, part = t / kNst3;  // row i, columns part + 6 s
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int lr = l >> 4, lc = l & 15;  // row quarter and column of the lane in a tile
+  if (t < kMN) rinv[t] = -1;
   if (t == 0) s_sing = 0;
-  double a[kRS];
+  // assembly, one block column at a time through LDS (rolled loops: the
+  // tile registers are only ever indexed by compile-time slot numbers)
+  mfma_d4 C[kMSlots];
+  for (int Jb = 0; Jb < kMT; ++Jb) {
+    for (int e = t; e < kMN * kMB; e += kMThreads) {
+      const int row = e / kMB, col = kMB * Jb + e % kMB;
+      double v;
+      if (row < kNst3 && col < kNst3)
+        v = patch3_entry(g, Esrc, cx, cy, cz, row, col);
+      else
+        v = row == col ? 1.0 : 0.0;
+      P[row * kPS + e % kMB] = v;
+    }
+    __syncthreads();
 #pragma unroll
-  for (int s = 0; s < kRS; ++s) a[s] = 0.0;
-  // assembly: entry (i, j) sums the cells that hold both unknowns (a rolled
-  // loop; each value is moved into its register by a select chain)
-  const int mr = i / kNs3, sr = i % kNs3;
+    for (int s = 0; s < kMSlots; ++s) {
+      const int tile = s * kMWaves + w;
+      if (tile < kMT * kMT && tile % kMT == Jb) {
+        const int I = tile / kMT;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) C[s][r] = P[(kMB * I + lr + 4 * r) * kPS + lc];
+      }
+    }
+    __syncthreads();
+  }
+  for (int K = 0; K < kMT; ++K) {
+    // the panel to LDS
+#pragma unroll
+    for (int s = 0; s < kMSlots; ++s) {
+      const int tile = s * kMWaves + w;
+      if (tile < kMT * kMT && tile % kMT == K) {
+        const int I = tile / kMT;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) P[(kMB * I + lr + 4 * r) * kPS + lc] = C[s][r];
+      }
+    }
+    __syncthreads();
+    // 16 exchange steps on the panel, its rows held one per lane (lanes
+    // 0 .. kMR-1 of each wave), the pivot found by a wave reduction and one
+    // across the waves
+    {
+      const int prow_i = w * kMR + l;  // panel row of this lane
+      const bool has = l < kMR && prow_i < kMN;
+      double rv[kMB];
+#pragma unroll
+      for (int j = 0; j < kMB; ++j) rv[j] = has ? P[prow_i * kPS + j] : 0.0;
+      bool used = has ? rinv[prow_i] >= 0 : true;
 #pragma unroll 1
-  for (int s = 0; s < kRS; ++s) {
-    const int j = part + kRP * s;
-    double v = 0.0;
-    if (active && j < kNst3) {
-      const int mc = j / kNs3, sc = j % kNs3;
-      if (sr >= kNv3 || sc >= kNv3) {
-        v = Esrc(K, i, j);  // the cell's own pressure lives in this cell only
-      } else {
-        const int ea = sr % kNb3, eb = sc % kNb3;
-        const int pa[3] = {ea % 3, (ea / 3) % 3, ea / 9}, pb[3] = {eb % 3, (eb / 3) % 3, eb / 9};
-        int lo[3], hi[3];
-        for (int k = 0; k < 3; ++k) {
-          lo[k] = (pa[k] == 0 && pb[k] == 0 && cc[k] > 0) ? -1 : 0;
-          hi[k] = (pa[k] == 2 && pb[k] == 2 && cc[k] < nc[k] - 1) ? 1 : 0;
+      for (int m = 0; m < kMB; ++m) {
+        double vm = 0.0;  // rv[m] (a select chain keeps rv in registers)
+#pragma unroll
+        for (int j = 0; j < kMB; ++j) vm = j == m ? rv[j] : vm;
+        double bv = used ? -1.0 : fabs(vm);
+        int bi = used ? kMN : prow_i;
+        for (int off = 32; off > 0; off >>= 1) {
+          const double ov = __shfl_xor(bv, off);
+          const int oi = __shfl_xor(bi, off);
+          if (ov > bv || (ov == bv && oi < bi)) {
+            bv = ov;
+            bi = oi;
+          }
         }
-        const int rbase = mr * kNs3 + (sr / kNb3) * kNb3, cbase = mc * kNs3 + (sc / kNb3) * kNb3;
-        for (int oz = lo[2]; oz <= hi[2]; ++oz)
-          for (int oy = lo[1]; oy <= hi[1]; ++oy)
-            for (int ox = lo[0]; ox <= hi[0]; ++ox) {
-              const int na = (pa[0] - 2 * ox) + 3 * (pa[1] - 2 * oy) + 9 * (pa[2] - 2 * oz);
-              const int nb = (pb[0] - 2 * ox) + 3 * (pb[1] - 2 * oy) + 9 * (pb[2] - 2 * oz);
-              v += Esrc(cell_index3(g, cx + ox, cy + oy, cz + oz), rbase + na, cbase + nb);
-            }
+        if (l == 0) {
+          cand_v[m & 1][w] = bv;
+          cand_i[m & 1][w] = bi;
+        }
+        __syncthreads();
+        bv = cand_v[m & 1][0];
+        bi = cand_i[m & 1][0];
+        for (int q = 1; q < kMWaves; ++q) {
+          const double ov = cand_v[m & 1][q];
+          const int oi = cand_i[m & 1][q];
+          if (ov > bv || (ov == bv && oi < bi)) {
+            bv = ov;
+            bi = oi;
+          }
+        }
+        const int rp = bi;  // uniform over the workgroup
+        if (has && prow_i == rp) {
+          double pv = vm;
+          if (!(bv > 0.0)) {
+            pv = 1.0;
+            s_sing = 1;
+          }
+          const double dinv = 1.0 / pv;
+#pragma unroll
+          for (int j = 0; j < kMB; ++j) prow[j] = (j == m ? 1.0 : rv[j]) * dinv;
+          rinv[rp] = kMB * K + m;
+          rowpiv[kMB * K + m] = rp;
+        }
+        __syncthreads();
+        if (has) {
+          const bool piv = prow_i == rp;
+          const double f = piv ? -1.0 : vm;
+#pragma unroll
+          for (int j = 0; j < kMB; ++j) {
+            const double keep = (piv || j == m) ? 0.0 : rv[j];
+            rv[j] = keep - f * prow[j];
+          }
+          used = used || piv;
+        }
       }
-    }
+      if (has) {
 #pragma unroll
-    for (int q = 0; q < kRS; ++q)
-      if (q == s) a[q] = v;
-  }
-  for (int k = 0; k < kNst3; ++k) {
-    const int ks = k / kRP, kp = k % kRP;
-    // column k to LDS
-    if (active && part == kp) {
-      double v = 0.0;
-#pragma unroll
-      for (int s = 0; s < kRS; ++s)
-        if (s == ks) v = a[s];
-      colv[i] = v;
+        for (int j = 0; j < kMB; ++j) P[prow_i * kPS + j] = rv[j];
+      }
     }
     __syncthreads();
-    // pivot: largest |a_ik| over i >= k (ties to the smaller row)
-    if (t < 64) {
-      double bv = -1.0;
-      int bi = k;
-      for (int r = k + t; r < kNst3; r += 64) {
-        const double v = fabs(colv[r]);
-        if (v > bv) {
-          bv = v;
-          bi = r;
-        }
-      }
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(bv, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ov > bv || (ov == bv && oi < bi)) {
-          bv = ov;
-          bi = oi;
-        }
-      }
-      if (t == 0) {
-        s_p = bi;
-        piv[k] = bi;
-        if (!(bv > 0.0)) {
-          s_sing = 1;
-          s_pv = 1.0;
+    // the panel back into its tiles; the pivot rows of the other columns to Bm
+#pragma unroll
+    for (int s = 0; s < kMSlots; ++s) {
+      const int tile = s * kMWaves + w;
+      if (tile >= kMT * kMT) continue;
+      const int I = tile / kMT, J = tile % kMT;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = kMB * I + lr + 4 * r;
+        if (J == K) {
+          C[s][r] = P[row * kPS + lc];
         } else {
-          s_pv = colv[bi];
+          const int m = rinv[row] - kMB * K;
+          if (m >= 0 && m < kMB) Bm[m * kOS + kMB * J + lc] = C[s][r];
         }
       }
     }
     __syncthreads();
-    const int p = s_p;
-    const double dinv = 1.0 / s_pv;
-    // rows k and p as they are
-    if (active && (i == k || i == p)) {
+    // left factor: the panel minus the selection of its pivot rows
+    if (t < kMB) P[rowpiv[kMB * K + t] * kPS + t] -= 1.0;
+    __syncthreads();
+    // rank-16 update of every other block column
 #pragma unroll
-      for (int s = 0; s < kRS; ++s) {
-        const int j = part + kRP * s;
-        if (j < kNst3) {
-          if (i == k) rowk[j] = a[s];
-          if (i == p) rowp[j] = a[s];
-        }
+    for (int s = 0; s < kMSlots; ++s) {
+      const int tile = s * kMWaves + w;
+      if (tile >= kMT * kMT) continue;
+      const int I = tile / kMT, J = tile % kMT;
+      if (J == K) continue;
+      double a[4], b[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        a[c] = P[(kMB * I + lc) * kPS + 4 * c + lr];
+        b[c] = Bm[(4 * c + lr) * kOS + kMB * J + lc];
       }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) C[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c], b[c], C[s], 0, 0, 0);
+      // the operands of one tile at a time
+      asm volatile("" ::: "memory");
     }
     __syncthreads();
-    // new row k (old row p scaled, its pivot entry becomes 1 / pivot) and the
-    // elimination factors (column k after the interchange, zero on row k)
-    if (t < kNst3) {
-      rowb[t] = (t == k ? 1.0 : rowp[t]) * dinv;
-    } else if (t >= 256 && t < 256 + kNst3) {
-      const int r = t - 256;
-      fk[r] = r == k ? 0.0 : (r == p ? rowk[k] : colv[r]);
-    }
-    __syncthreads();
-    if (active) {
-      if (i == k) {
-#pragma unroll
-        for (int s = 0; s < kRS; ++s) {
-          const int j = part + kRP * s;
-          if (j < kNst3) a[s] = rowb[j];
-        }
-      } else if (i == p) {  // old row k moves to row p (6 threads)
-        const double f = fk[i];
-#pragma unroll
-        for (int s = 0; s < kRS; ++s) {
-          const int j = part + kRP * s;
-          if (j < kNst3) {
-            double v = rowk[j];
-            if (j == k) v = 0.0;
-            a[s] = v - f * rowb[j];
-          }
-        }
-      } else {  // every other row: only the new pivot row is read from LDS
-        const double f = fk[i];
-#pragma unroll
-        for (int s = 0; s < kRS; ++s) {
-          const int j = part + kRP * s;
-          if (j < kNst3) {
-            double v = a[s];
-            if (j == k) v = 0.0;
-            a[s] = v - f * rowb[j];
-          }
-        }
-      }
-    }
   }
-  // the row interchanges become column interchanges of the inverse, applied
-  // in reverse order: column dst[j] of the inverse is column j of the result
-  if (t == 0) {
-    for (int j = 0; j < kNst3; ++j) srcc[j] = j;
-    for (int k = kNst3 - 1; k >= 0; --k) {
-      const int tmp = srcc[k];
-      srcc[k] = srcc[piv[k]];
-      srcc[piv[k]] = tmp;
-    }
-    for (int c = 0; c < kNst3; ++c) dst[srcc[c]] = c;
-    if (s_sing) atomicOr(status, 1);
-  }
-  __syncthreads();
+  if (t == 0 && s_sing) atomicOr(status, 1);
+  // A^{-1}[i][j] = W[a][b] with i = rinv[a], j = rowpiv[b]; column-major, one
+  // block column of W at a time staged so that each output column is written
+  // contiguously
   T* out = inv + patch_slot3(g, cx, cy, cz) * kE3;
-  if (active) {
+  double* O = Bm;
+  for (int Jb = 0; Jb < kMT; ++Jb) {
 #pragma unroll
-    for (int s = 0; s < kRS; ++s) {
-      const int j = part + kRP * s;
-      if (j < kNst3) out[dst[j] * kNst3 + i] = (T)a[s];
+    for (int s = 0; s < kMSlots; ++s) {
+      const int tile = s * kMWaves + w;
+      if (tile >= kMT * kMT || tile % kMT != Jb) continue;
+      const int I = tile / kMT;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = kMB * I + lr + 4 * r;
+        const int i = rinv[row];
+        if (i < kNst3) O[lc * kOS + i] = C[s][r];
+      }
     }
+    __syncthreads();
+    for (int e = t; e < kMB * kNst3; e += kMThreads) {
+      const int m = e / kNst3, i = e % kNst3;
+      const int b = kMB * Jb + m;
+      if (b < kNst3) out[(int64_t)rowpiv[b] * kNst3 + i] = (T)O[m * kOS + i];
+    }
+    __syncthreads();
   }
 }
 
@@ -547,7 +631,7 @@ hipError_t patches3r_by_colour(const Grid3& g, Src src, T* inv, int* status, hip
     const int px = c & 1, py = (c >> 1) & 1, pz = c >> 2;
     const int64_t np = colour_count3(g, c);
     if (np == 0) continue;
-    hipLaunchKernelGGL((patch3r_kernel<T, Src>), dim3((unsigned)np), dim3(1024), 0, s, g, src, inv,
+    hipLaunchKernelGGL((patch3m_kernel<T, Src>), dim3((unsigned)np), dim3(kMThreads), 0, s, g, src, inv,
                        status, px, py, pz, (g.nx - px + 1) / 2, (g.ny - py + 1) / 2);
   }
   return hipGetLastError();
