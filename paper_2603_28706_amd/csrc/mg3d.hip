@@ -201,14 +201,21 @@ constexpr int kMSlots = (kMT * kMT + kMWaves - 1) / kMWaves;  // 16 tiles per wa
 constexpr int kPS = kMB + 1;                  // panel row stride (odd: spreads the banks)
 constexpr int kMR = (kMN + kMWaves - 1) / kMWaves;  // panel rows per wave (22)
 constexpr int kOS = kMN + 1;                  // output staging row stride
+constexpr int kAB = 4;                        // block columns assembled per round
+constexpr int kAS = kAB * kMB + 1;            // assembly staging row stride
+constexpr int kPool = (kMN * kAS > kMN * kPS + kMB * kOS) ? kMN * kAS : kMN * kPS + kMB * kOS;
 typedef double mfma_d4 __attribute__((ext_vector_type(4)));
 
 template <typename T, typename Src>
 __global__ __launch_bounds__(kMThreads) void patch3m_kernel(Grid3 g, Src Esrc, T* __restrict__ inv,
                                                        int* status, int px, int py, int pz,
                                                        int ncx, int ncy) {
-  __shared__ double P[kMN * kPS];      // panel
-  __shared__ double Bm[kMB * kOS];     // pivot rows (right factor); output staging at the end
+  // one LDS pool: the assembly staging first, then the panel and the pivot
+  // rows (right factor; output staging at the end)
+  __shared__ double pool[kPool];
+  double* const P = pool;
+  double* const Bm = pool + kMN * kPS;
+  double* const S = pool;
   __shared__ int rowpiv[kMN];          // pivot row of each column
   __shared__ int rinv[kMN];            // column of each pivot row (-1: not yet pivoted)
   __shared__ double prow[kMB];         // scaled pivot row of the current exchange step
@@ -223,27 +230,31 @@ __global__ __launch_bounds__(kMThreads) void patch3m_kernel(Grid3 g, Src Esrc, T
   const int lr = l >> 4, lc = l & 15;  // row quarter and column of the lane in a tile
   if (t < kMN) rinv[t] = -1;
   if (t == 0) s_sing = 0;
-  // assembly, one block column at a time through LDS (rolled loops: the
+  // assembly, kAB block columns at a time through LDS (rolled loops: the
   // tile registers are only ever indexed by compile-time slot numbers)
   mfma_d4 C[kMSlots];
-  for (int Jb = 0; Jb < kMT; ++Jb) {
-    for (int e = t; e < kMN * kMB; e += kMThreads) {
-      const int row = e / kMB, col = kMB * Jb + e % kMB;
+  for (int J0 = 0; J0 < kMT; J0 += kAB) {
+    const int ncol = kMB * min(kAB, kMT - J0);
+#pragma unroll 2
+    for (int e = t; e < kMN * ncol; e += kMThreads) {
+      const int row = e / ncol, cl = e % ncol, col = kMB * J0 + cl;
       double v;
       if (row < kNst3 && col < kNst3)
         v = patch3_entry(g, Esrc, cx, cy, cz, row, col);
       else
         v = row == col ? 1.0 : 0.0;
-      P[row * kPS + e % kMB] = v;
+      S[row * kAS + cl] = v;
     }
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < kMSlots; ++s) {
       const int tile = s * kMWaves + w;
-      if (tile < kMT * kMT && tile % kMT == Jb) {
+      const int J = tile % kMT;
+      if (tile < kMT * kMT && J >= J0 && J < J0 + kAB) {
         const int I = tile / kMT;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) C[s][r] = P[(kMB * I + lr + 4 * r) * kPS + lc];
+        for (int r = 0; r < 4; ++r)
+          C[s][r] = S[(kMB * I + lr + 4 * r) * kAS + kMB * (J - J0) + lc];
       }
     }
     __syncthreads();
