@@ -63,6 +63,7 @@ class _CProblem(ctypes.Structure):
         ("gamma1", ctypes.c_double), ("gamma2", ctypes.c_double),
         ("sigma_max", ctypes.c_double),
         ("convection", ctypes.c_int), ("qsign", ctypes.c_int), ("lin", ctypes.c_int),
+        ("gamma_cip", ctypes.c_double),
     ]
 
 
@@ -95,6 +96,10 @@ def lib():
         L.orc_element_form.argtypes = [P, ctypes.c_int, dp, dp, dp, dp]
         L.orc_residual.argtypes = [P, dp, dp, dp, dp]
         L.orc_load.argtypes = [P, dp, dp]
+        L.orc_cip_count.argtypes = [P]
+        L.orc_cip_count.restype = ctypes.c_int
+        L.orc_cip_face.argtypes = [P, dp, ctypes.c_int, ip, dp]
+        L.orc_cip_face.restype = None
         for f in ("orc_stress", "orc_tangent", "orc_local_dofs", "orc_element_matrix",
                   "orc_element_mass", "orc_all_element_matrices", "orc_apply",
                   "orc_apply_threads", "orc_element_form", "orc_residual", "orc_load"):
@@ -202,6 +207,7 @@ class Problem:
     convection: int = 1
     qsign: int = 1
     lin: int = MODIFIED_NEWTON
+    gamma_cip: float = 0.0
     _c: object = dcfield(default=None, repr=False, compare=False)
 
     @property
@@ -227,7 +233,7 @@ class Problem:
             for j in range(nt):
                 s.kt[i * nt + j] = K[i, j]
         s.tau = fields["tau"]
-        for name in ("p", "delta", "nu", "nu_inf", "gamma1", "gamma2", "sigma_max"):
+        for name in ("p", "delta", "nu", "nu_inf", "gamma1", "gamma2", "sigma_max", "gamma_cip"):
             setattr(s, name, float(fields[name]))
         s.convection = int(fields["convection"])
         s.qsign = int(fields["qsign"])
@@ -322,13 +328,42 @@ def element_mass(prob: Problem, cell: int = 0):
     return M
 
 
+def cip_matrix(prob: Problem, u_weight):
+    """Assembled CIP form of eq. (scip-def) on the interior faces, s_CIP(uw; x, v)
+    (ns x ns, CSR, zero outside the velocity block), with the weight field
+    uw (one time node's velocity, d * num_nodes values) and gamma_CIP of prob."""
+    u_weight = _f64(u_weight)
+    cs = _cs(prob)
+    nf = lib().orc_cip_count(cs)
+    nl = 2 * prob.dim * 3 ** prob.dim
+    dofs = np.zeros(nl, dtype=np.int32)
+    M = np.zeros((nl, nl))
+    rows, cols, vals = [], [], []
+    for f in range(nf):
+        lib().orc_cip_face(cs, _dp(u_weight), f, dofs.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                           _dp(M))
+        rows.append(np.repeat(dofs, nl))
+        cols.append(np.tile(dofs, nl))
+        vals.append(M.ravel().copy())
+    if not rows:
+        return sp.csr_matrix((prob.ns, prob.ns))
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(prob.ns, prob.ns))
+
+
 def assemble_spatial(prob: Problem, u_spatial, **kw):
-    """Assembled spatial block J_mu (ns x ns, CSR) at velocity state u."""
+    """Assembled spatial block J_mu (ns x ns, CSR) at velocity state u: the
+    element matrices plus, with gamma_CIP > 0, the CIP form with its weight
+    lagged at u (eq. Amu-decomp)."""
     E = element_matrices(prob, u_spatial, **kw)
     dofs = local_dofs(prob)
     rows = np.repeat(dofs, prob.nloc, axis=1).ravel()
     cols = np.tile(dofs, (1, prob.nloc)).ravel()
-    return sp.csr_matrix((E.ravel(), (rows, cols)), shape=(prob.ns, prob.ns))
+    J = sp.csr_matrix((E.ravel(), (rows, cols)), shape=(prob.ns, prob.ns))
+    pk = prob.with_(**kw) if kw else prob
+    if pk.gamma_cip > 0.0:
+        J = J + cip_matrix(pk, u_spatial)
+    return J
 
 
 def assemble_velocity_mass(prob: Problem):

@@ -58,6 +58,7 @@ typedef struct {
   int convection;     /* 1: p-Navier-Stokes, 0: p-Stokes */
   int qsign;          /* +1 or -1, see header */
   int lin;            /* ORC_PICARD / ORC_EXACT_NEWTON / ORC_MODIFIED_NEWTON */
+  double gamma_cip;   /* CIP weight gamma_CIP of eq. (scip-def); 0 = off */
 } orc_problem;
 
 /* ---------------------------------------------------------------- sizes */
@@ -459,6 +460,128 @@ void orc_all_element_matrices(const orc_problem* P, const double* u, double* E) 
   }
 }
 
+/* ------------------------------------------------------ CIP stabilisation */
+
+/* Interior faces: direction k (normal e_k), between cell L = c - e_k and cell
+ * R = c (c_k >= 1).  Faces are numbered direction by direction, within a
+ * direction by the index of cell R in the mesh with n_k - 1 cells along k. */
+int orc_cip_count(const orc_problem* P) {
+  int total = 0;
+  for (int k = 0; k < P->dim; ++k) {
+    int m = 1;
+    for (int j = 0; j < P->dim; ++j) m *= (j == k ? P->n[j] - 1 : P->n[j]);
+    total += m;
+  }
+  return total;
+}
+
+/* Local matrix of the CIP form of eq. (scip-def) on interior face f,
+ *   s_F(uw; x, v) = gamma_CIP h_F^2 int_F |uw . n_F| [grad x n_F] . [grad v n_F] ds,
+ * [g] = g|_L - g|_R, the weight field uw (d*num_nodes velocity values of one
+ * time node) evaluated on the face, h_F the cell size normal to the face,
+ * 3^(d-1) Gauss points.  Local unknowns: velocity (component c, node a) of L
+ * at c*nb + a, of R at d*nb + c*nb + a; dofs[] receives their global spatial
+ * indices, M the (2 d nb)^2 matrix, row = test. */
+void orc_cip_face(const orc_problem* P, const double* uw, int f, int* dofs, double* M) {
+  int d = P->dim, nb = ipow3(d), nl = 2 * d * nb;
+  int k = 0;
+  for (; k < d; ++k) {
+    int m = 1;
+    for (int j = 0; j < d; ++j) m *= (j == k ? P->n[j] - 1 : P->n[j]);
+    if (f < m) break;
+    f -= m;
+  }
+  /* cell R from f over the mesh with n_k - 1 cells along k, shifted by one */
+  int idx[3] = {0, 0, 0}, r = f;
+  for (int j = 0; j < d; ++j) {
+    int nj = (j == k ? P->n[j] - 1 : P->n[j]);
+    idx[j] = r % nj + (j == k ? 1 : 0);
+    r /= nj;
+  }
+  int cR = 0, cL = 0, stride = 1;
+  for (int j = 0; j < d; ++j) {
+    cR += idx[j] * stride;
+    cL += (idx[j] - (j == k ? 1 : 0)) * stride;
+    stride *= P->n[j];
+  }
+  int dl[85], dr[85];
+  orc_local_dofs(P, cL, dl);
+  orc_local_dofs(P, cR, dr);
+  for (int i = 0; i < d * nb; ++i) {
+    dofs[i] = dl[i];
+    dofs[d * nb + i] = dr[i];
+  }
+  memset(M, 0, sizeof(double) * nl * nl);
+  cellgeo gL, gR;
+  cell_setup(P, cL, &gL);
+  cell_setup(P, cR, &gR);
+  double gx[3], gw[3];
+  gauss3(gx, gw);
+  double hF = gL.h[k];
+  double area = gL.vol / gL.h[k];
+  int nq = ipow3(d - 1);
+  double uwl[81];
+  for (int i = 0; i < d * nb; ++i) uwl[i] = uw[dl[i]];
+  double* jn = (double*)malloc(sizeof(double) * nl);
+  for (int q = 0; q < nq; ++q) {
+    int qt[2] = {q % 3, (q / 3) % 3};
+    double xiL[3] = {0, 0, 0}, xiR[3] = {0, 0, 0}, w = area;
+    int t = 0;
+    for (int m = 0; m < d; ++m) {
+      if (m == k) {
+        xiL[m] = 1.0;
+        xiR[m] = 0.0;
+      } else {
+        xiL[m] = xiR[m] = gx[qt[t]];
+        w *= gw[qt[t]];
+        ++t;
+      }
+    }
+    basis_at BL, BR;
+    eval_basis(&gL, xiL, &BL);
+    eval_basis(&gR, xiR, &BR);
+    field uf;
+    state_field(&gL, &BL, uwl, &uf);
+    double un = fabs(uf.v[k]);   /* n_F = e_k */
+    double wq = P->gamma_cip * hF * hF * un * w;
+    /* normal derivative of each local unknown, with the sign of the jump */
+    for (int c = 0; c < d; ++c)
+      for (int a = 0; a < nb; ++a) {
+        jn[c * nb + a] = BL.dphi[a][k];
+        jn[d * nb + c * nb + a] = -BR.dphi[a][k];
+      }
+    for (int i = 0; i < nl; ++i)
+      for (int j = 0; j < nl; ++j) {
+        int ci = (i % (d * nb)) / nb, cj = (j % (d * nb)) / nb;
+        if (ci == cj) M[i * nl + j] += wq * jn[i] * jn[j];
+      }
+  }
+  free(jn);
+}
+
+/* y_mu += tau wt[mu] s_CIP(uw_mu; x_mu, .) over every interior face, the
+ * weight fields uw given per time node (nt blocks of d*num_nodes). */
+static void cip_add(const orc_problem* P, const double* uw, const double* x, double* y,
+                    double sign) {
+  int d = P->dim, nb = ipow3(d), nl = 2 * d * nb, nn = orc_num_nodes(P);
+  int ns = orc_spatial_size(P), nf = orc_cip_count(P);
+  int dofs[162];
+  double* M = (double*)malloc(sizeof(double) * nl * nl);
+  for (int mu = 0; mu < P->nt; ++mu)
+    for (int f = 0; f < nf; ++f) {
+      orc_cip_face(P, uw + (size_t)mu * d * nn, f, dofs, M);
+      const double* xm = x + (size_t)mu * ns;
+      double* ym = y + (size_t)mu * ns;
+      double scale = sign * P->tau * P->wt[mu];
+      for (int i = 0; i < nl; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < nl; ++j) s += M[i * nl + j] * xm[dofs[j]];
+        ym[dofs[i]] += scale * s;
+      }
+    }
+  free(M);
+}
+
 /* ---------------------------------------------------------- slab apply */
 
 /* Contributions of cell c to y = J_n x, eq. (slab-underint-jac):
@@ -509,6 +632,8 @@ void orc_apply(const orc_problem* P, const double* uk, const double* x, double* 
   double* E = (double*)malloc(sizeof(double) * nloc * nloc);
   for (int c = 0; c < nc; ++c) apply_cell(P, c, uk, x, y, E);
   free(E);
+  /* CIP with the weight lagged at u_k (every linearisation) */
+  if (P->gamma_cip > 0.0) cip_add(P, uk, x, y, 1.0);
 }
 
 /* The same action on `nthreads` host threads (CPU timing only): the cells are
@@ -534,6 +659,7 @@ void orc_apply_threads(const orc_problem* P, const double* uk, const double* x, 
       free(E);
     }
   }
+  if (P->gamma_cip > 0.0) cip_add(P, uk, x, y, 1.0);
 }
 
 /* ------------------------------------------------------------ load vector */
@@ -706,5 +832,15 @@ void orc_residual(const orc_problem* P, const double* U, const double* vprev, co
           Rm[dofs[cc * nb + a]] -= s;
         }
     }
+  }
+  /* CIP, eq. (scip-def): s_CIP(u; u, v) with the weight at the state itself,
+   * or at ulag (the lagged weight of the linearisations) when given */
+  if (P->gamma_cip > 0.0) {
+    double* uw = (double*)malloc(sizeof(double) * (size_t)P->nt * d * nn);
+    for (int mu = 0; mu < P->nt; ++mu)
+      for (int i = 0; i < d * nn; ++i)
+        uw[(size_t)mu * d * nn + i] = ulag ? ulag[(size_t)mu * d * nn + i] : U[(size_t)mu * ns + i];
+    cip_add(P, uw, U, R, -1.0);
+    free(uw);
   }
 }
