@@ -112,7 +112,17 @@ typedef struct {
  *   (Sec. 4.4); convection = 1 for p-Navier-Stokes, 0 for p-Stokes;
  *   nitsche_q_sign = +1 makes the Nitsche pressure coupling the transpose of
  *   the momentum one (-q I in B^s), -1 keeps the printed +q I;
- *   lin = pns_lin_kind of the Jacobian action. */
+ *   lin = pns_lin_kind of the Jacobian action;
+ *   gamma_cip > 0 adds the convection-aligned CIP stabilisation of Sec. 3.2,
+ *   eq. (scip-def): on every interior face F, gamma_cip h_F^2 int_F
+ *   |u^ . n_F| [grad u n_F] . [grad v n_F], h_F the cell size normal to F; in
+ *   the residual the weight u^ is the state itself, in the Jacobian action of
+ *   every linearisation it is lagged at u_k (eq. Amu-decomp), which keeps the
+ *   term symmetric positive semidefinite.  The Vanka patches and the coarse
+ *   Galerkin operators are formed from the cell terms only (the CIP face
+ *   coupling enters the action and the residual, so the solve converges to
+ *   the stabilised solution; the V-cycle preconditions it without the face
+ *   term).  Hexahedral contexts return PNS_EUNSUPPORTED for gamma_cip > 0. */
 typedef struct {
   double p, delta, nu, nu_inf;
   double gamma1, gamma2;
@@ -120,6 +130,7 @@ typedef struct {
   int convection;
   int nitsche_q_sign;
   int lin;
+  double gamma_cip;  /* CIP weight of eq. (scip-def), >= 0; 0 = off (quadrilaterals only) */
 } pns_model;
 
 typedef struct pns_ctx pns_ctx;

@@ -95,6 +95,8 @@ size_t layout(pns_ctx* c, bool bind) {
   c->masks = (uint16_t*)take(g0.nc * sizeof(uint16_t));
   c->tcache = take(g0.nc * 18 * 6 * es);
   c->edge2 = (double*)take(cell_apply_edge_doubles(g0) * 8);
+  c->cipG = (double*)take(cip_face_doubles(g0) * 8);
+  c->Sr = (double*)take(cip_face_count(g0) * 9 * 8);
   c->gr = take(g0.nst * es);
   c->gd = take(g0.nst * es);
   c->status = (int*)take(sizeof(int) * 4);
@@ -104,6 +106,7 @@ size_t layout(pns_ctx* c, bool bind) {
     // level 0 holds either the complex 21x21 or the real 42x42 inverses
     L.inv = take(L.g.nc * kNst * kNst * es);
     L.res = take(L.g.nst * es);
+    L.S = (double*)take(cip_face_count(L.g) * 18 * 8);
     if (l >= 1 || coarsest) L.E64 = (double*)take(L.g.nc * kNst * kNst * 8);
     if (l >= 1) L.E = take(L.g.nc * kNst * kNst * es);
     if (l >= 1) {
@@ -159,6 +162,7 @@ struct SmoothScratch {
   void* res;
   double* edge;
   void* slot;
+  double* cip;
 };
 
 template <typename T>
@@ -172,10 +176,16 @@ hipError_t defect(pns_ctx* c, int l, const T* b, const T* x, T* y,
                                   slot, 1, c->stream);
   if (c->dim == 3)
     return launch_ebe_apply3d<T>(L.g3, (const T*)L.E, x, b, y, slot, c->stream);
-  if (l == 0)
-    return launch_cell_apply<T>(L.g, c->model, c->disc.tau, (const T*)c->uk, tangent_cache<T>(c),
-                                x, b, y, edge, 1, c->stream);
-  return launch_ebe_apply<T>(L.g, (const T*)L.E, x, b, y, 1, c->stream);
+  if (l == 0) {
+    hipError_t e = launch_cell_apply<T>(L.g, c->model, c->disc.tau, (const T*)c->uk,
+                                        tangent_cache<T>(c), x, b, y, edge, 1, c->stream);
+    if (e != hipSuccess || !(c->model.gamma_cip > 0.0)) return e;
+    return launch_cip<T>(L.g, c->model, c->disc.tau, (const T*)c->uk, L.g.nv, x, y, -1.0,
+                         sc ? sc->cip : c->cipG, c->stream);
+  }
+  hipError_t e = launch_ebe_apply<T>(L.g, (const T*)L.E, x, b, y, 1, c->stream);
+  if (e != hipSuccess || !(c->model.gamma_cip > 0.0)) return e;
+  return launch_cip_level<T>(L.g, L.S, x, y, -1.0, sc ? sc->cip : c->cipG, c->stream);
 }
 
 template <typename T>
@@ -187,10 +197,16 @@ hipError_t apply_level(pns_ctx* c, int l, const T* x, T* y) {
   if (c->dim == 3)
     return launch_ebe_apply3d<T>(L.g3, (const T*)L.E, x, (const T*)nullptr, y, (T*)c->E3,
                                  c->stream);
-  if (l == 0)
-    return launch_cell_apply<T>(L.g, c->model, c->disc.tau, (const T*)c->uk, tangent_cache<T>(c),
-                                x, x, y, c->edge2, 0, c->stream);
-  return launch_ebe_apply<T>(L.g, (const T*)L.E, x, x, y, 0, c->stream);
+  if (l == 0) {
+    hipError_t e = launch_cell_apply<T>(L.g, c->model, c->disc.tau, (const T*)c->uk,
+                                        tangent_cache<T>(c), x, x, y, c->edge2, 0, c->stream);
+    if (e != hipSuccess || !(c->model.gamma_cip > 0.0)) return e;
+    return launch_cip<T>(L.g, c->model, c->disc.tau, (const T*)c->uk, L.g.nv, x, y, 1.0, c->cipG,
+                         c->stream);
+  }
+  hipError_t e = launch_ebe_apply<T>(L.g, (const T*)L.E, x, x, y, 0, c->stream);
+  if (e != hipSuccess || !(c->model.gamma_cip > 0.0)) return e;
+  return launch_cip_level<T>(L.g, L.S, x, y, 1.0, c->cipG, c->stream);
 }
 
 hipError_t build_tangent_cache(pns_ctx* c) {
@@ -423,25 +439,35 @@ int vanka_setup_impl(pns_ctx* c, const uint16_t* masks) {
   PNS_HIP(c, launch_element_matrices(L0.g, c->model, u0, c->Es0, s));
   PNS_HIP(c, launch_element_matrices(L0.g, c->model, u1, c->Es1, s));
   PNS_HIP(c, launch_element_matrices(L0.g, c->model, c->urep, c->Esr, s));
+  // CIP face matrices: at each Radau node's velocity (level-0 operator, with
+  // tau w_mu) and at t_rep (time-diagonal patches, unscaled)
+  const bool cip = c->model.gamma_cip > 0.0;
+  if (cip) {
+    PNS_HIP(c, launch_cip_face_matrices(L0.g, c->model, u0, L0.g.nv, 2, c->disc.tau * kWt[0],
+                                        c->disc.tau * kWt[1], L0.S, s));
+    PNS_HIP(c, launch_cip_face_matrices(L0.g, c->model, c->urep, 0, 1, 1.0, 1.0, c->Sr, s));
+  }
   if (c->patch_kind == PNS_PATCH_SURROGATE) {
     // level 0: surrogate patches, all state-dependent coefficients at t_rep
-    PNS_HIP(c, launch_fine_patches<T>(L0.g, c->disc.tau, c->Esr, masks ? c->masks : nullptr,
-                                      (T*)L0.inv, c->status, s));
+    PNS_HIP(c, launch_fine_patches<T>(L0.g, c->disc.tau, c->Esr, cip ? c->Sr : nullptr,
+                                      masks ? c->masks : nullptr, (T*)L0.inv, c->status, s));
   } else {
     // level 0: exact patches, each Radau node with its own spatial matrices
     PNS_HIP(c, launch_exact_fine_patches<T>(L0.g, c->disc.tau, c->Es0, c->Es1,
-                                            masks ? c->masks : nullptr, (T*)L0.inv, c->status,
-                                            s));
+                                            cip ? L0.S : nullptr, masks ? c->masks : nullptr,
+                                            (T*)L0.inv, c->status, s));
   }
-  // coarse levels: Galerkin element matrices, exact patches
+  // coarse levels: Galerkin element matrices and CIP face matrices, exact patches
   for (int l = 1; l < c->nlev; ++l) {
     Level& L = c->lev[l];
     if (l == 1)
       PNS_HIP(c, launch_galerkin_from_fine(L.g, c->disc.tau, c->Es0, c->Es1, L.E64, s));
     else
       PNS_HIP(c, launch_galerkin(L.g, c->lev[l - 1].E64, L.E64, s));
+    if (cip) PNS_HIP(c, launch_cip_restrict(L.g, c->lev[l - 1].g, c->lev[l - 1].S, L.S, s));
     PNS_HIP(c, launch_transpose_convert<T>(L.g.nc, L.E64, (T*)L.E, s));
-    PNS_HIP(c, launch_level_patches<T>(L.g, L.E64, (T*)L.inv, c->status, s));
+    PNS_HIP(c, launch_level_patches<T>(L.g, L.E64, cip ? L.S : nullptr, (T*)L.inv, c->status,
+                                       s));
   }
   // coarsest level: dense operator, pinned, inverted
   Level& Lc = c->lev[c->nlev - 1];
@@ -461,6 +487,7 @@ int vanka_setup_impl(pns_ctx* c, const uint16_t* masks) {
   const int64_t n = Lc.g.nst;
   PNS_HIP(c, hipMemsetAsync(c->Adense, 0, (size_t)n * n * 8, s));
   PNS_HIP(c, launch_coarse_assemble(Lc.g, Lc.E64, c->Adense, s));
+  if (cip) PNS_HIP(c, launch_cip_dense(Lc.g, Lc.S, c->Adense, s));
   c->pin[0] = Lc.g.nv;
   c->pin[1] = Lc.g.ns + Lc.g.nv;
   // pin indices must be in device memory for the pin kernel
@@ -601,15 +628,17 @@ hipError_t static_scratch(hipStream_t stream, void** out) {
 }
 
 // Bytes of static scratch one smoothing call on `level` uses: the defect, the
-// 2D level-0 tile-edge partial sums, the 3D per-cell result slots.
+// 2D level-0 tile-edge partial sums, the 2D CIP per-face values, the 3D
+// per-cell result slots.
 size_t static_scratch_need(const pns_ctx* c, int level) {
   auto up = [](size_t b) { return (b + kAlign - 1) / kAlign * kAlign; };
   const Level& L = c->lev[level];
   size_t need = up(L.g.nst * c->es);
   if (c->dim == 3)
     need += up(L.g.nc * 170 * c->es);
-  else if (level == 0)
-    need += up(cell_apply_edge_doubles(L.g) * 8);
+  else
+    need += (level == 0 ? up(cell_apply_edge_doubles(L.g) * 8) : 0) +
+            (c->model.gamma_cip > 0.0 ? up(cip_face_doubles(L.g) * 8) : 0);
   return need;
 }
 
@@ -626,6 +655,7 @@ int pns::make_model(const pns_model* md, Model* m, std::string* err) {
   if (md->lin < 0 || md->lin > 2) return fail_msg(err, PNS_EINVAL, "unknown linearisation kind");
   if (md->nitsche_q_sign != 1 && md->nitsche_q_sign != -1)
     return fail_msg(err, PNS_EINVAL, "nitsche_q_sign must be +1 or -1");
+  if (!(md->gamma_cip >= 0.0)) return fail_msg(err, PNS_EINVAL, "gamma_cip must be >= 0");
   m->p = md->p;
   m->delta2 = md->delta * md->delta;
   m->nu = md->nu;
@@ -638,6 +668,7 @@ int pns::make_model(const pns_model* md, Model* m, std::string* err) {
   m->qsign = (double)md->nitsche_q_sign;
   m->lin = md->lin;
   m->convection = md->convection ? 1 : 0;
+  m->gamma_cip = md->gamma_cip;
   return PNS_OK;
 }
 
@@ -760,6 +791,8 @@ int pns_set_state(pns_ctx* ctx, const pns_model* md, const double* u_k) {
   Model m;
   const int rc = make_model(md, &m, &ctx->err);
   if (rc != PNS_OK) return rc;
+  if (ctx->dim == 3 && m.gamma_cip > 0.0)
+    return fail(ctx, PNS_EUNSUPPORTED, "CIP stabilisation is built for quadrilaterals only");
   ctx->model = m;
   ctx->drop_graph();
   const Grid& g0 = ctx->lev[0].g;
@@ -931,10 +964,15 @@ int pns_vanka_smooth_static(pns_ctx* ctx, int level, int n_sweeps, double omega,
   PNS_HIP(ctx, static_scratch(ctx->stream, &base));
   const Level& L = ctx->lev[level];
   const size_t res_bytes = (L.g.nst * ctx->es + kAlign - 1) / kAlign * kAlign;
+  const size_t edge_bytes =
+      (ctx->dim == 2 && level == 0)
+          ? (cell_apply_edge_doubles(L.g) * 8 + kAlign - 1) / kAlign * kAlign
+          : 0;
   SmoothScratch sc;
   sc.res = base;
   sc.edge = (ctx->dim == 2 && level == 0) ? (double*)((char*)base + res_bytes) : nullptr;
   sc.slot = ctx->dim == 3 ? (void*)((char*)base + res_bytes) : nullptr;
+  sc.cip = ctx->dim == 2 ? (double*)((char*)base + res_bytes + edge_bytes) : nullptr;
   if (ctx->es == 8)
     PNS_HIP(ctx, smooth<double>(ctx, level, n_sweeps, omega, (const double*)r, (double*)d, false,
                                 &sc));

@@ -19,6 +19,8 @@ struct Level {
   void* res = nullptr;    // defect
   void* r = nullptr;      // level right-hand side (levels >= 1)
   void* d = nullptr;      // level correction (levels >= 1)
+  double* S = nullptr;    // 2D CIP face matrices of the level operator (3x3 per face
+                          // and Radau node; level 0: at u_k, scaled by tau w_mu)
 };
 
 constexpr size_t kAlign = 256;
@@ -68,6 +70,8 @@ struct pns_ctx {
   int patch_kind = PNS_PATCH_SURROGATE;  // finest-level patch matrices
   void* tcache = nullptr;  // per-point tangent coefficients of level 0
   double* edge2 = nullptr;  // 2D action: per-tile partial sums on shared tile edges
+  double* cipG = nullptr;   // 2D CIP: per-face weighted jumps
+  double* Sr = nullptr;     // 2D CIP face matrices at t_rep (time-diagonal patches)
   void* E3 = nullptr;      // 3D: per-cell results of the action (170 per cell)
   // 3D FP64 residual: state copy, left-trace term, per-cell slots of the action
   double* r3u = nullptr;

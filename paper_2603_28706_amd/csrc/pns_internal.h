@@ -53,6 +53,7 @@ constexpr double kBackIm = 2.0 * kSqrt2;
 struct Model {
   double p, delta2, nu, nu_inf, expo;  // expo = (p-2)/2
   double sigma_max, etaD, gamma1, gamma2, qsign;
+  double gamma_cip;  // CIP weight (0: off)
   int lin, convection;
 };
 
@@ -210,20 +211,22 @@ template <typename T>
 hipError_t launch_convert(int64_t n, const double* in, T* out, hipStream_t s);
 // level-0 surrogate patches in time-diagonal form: complex 21x21 inverses
 // (interleaved re, im; column-major), from the spatial matrices Es at t_rep
+// and the CIP face matrices Sr at t_rep (nm = 1, unscaled; NULL: no CIP)
 template <typename T>
-hipError_t launch_fine_patches(const Grid& g, double tau, const double* Es, const uint16_t* masks,
-                               T* inv, int* status, hipStream_t s);
+hipError_t launch_fine_patches(const Grid& g, double tau, const double* Es, const double* Sr,
+                               const uint16_t* masks, T* inv, int* status, hipStream_t s);
 // level-0 exact patches (real 42x42 inverses) from the spatial matrices at the
-// two Radau nodes
+// two Radau nodes and the CIP face matrices S (nm = 2, scaled by tau w_mu; NULL:
+// no CIP)
 template <typename T>
 hipError_t launch_exact_fine_patches(const Grid& g, double tau, const double* Es0,
-                                     const double* Es1, const uint16_t* masks, T* inv,
-                                     int* status, hipStream_t s);
+                                     const double* Es1, const double* S, const uint16_t* masks,
+                                     T* inv, int* status, hipStream_t s);
 template <typename T>
 hipError_t launch_transpose_convert(int64_t ncells, const double* E, T* Et, hipStream_t s);
 template <typename T>
-hipError_t launch_level_patches(const Grid& g, const double* E, T* inv, int* status,
-                                hipStream_t s);
+hipError_t launch_level_patches(const Grid& g, const double* E, const double* S, T* inv,
+                                int* status, hipStream_t s);
 hipError_t launch_galerkin_from_fine(const Grid& gc, double tau, const double* Es0,
                                      const double* Es1, double* Ec, hipStream_t s);
 hipError_t launch_galerkin(const Grid& gc, const double* Ef, double* Ec, hipStream_t s);
@@ -275,6 +278,85 @@ hipError_t launch_residual(const Grid& g, const Model& m, double tau, const doub
 hipError_t launch_load2(const Grid& g, double tau, const double* f_qp, double* F, hipStream_t s);
 hipError_t launch_load3(const Grid3& g, double tau, const double* f_qp, double* F, hipStream_t s);
 hipError_t launch_add(int64_t n, const double* x, double* y, hipStream_t s);
+
+// cip.hip: CIP stabilisation on the interior faces of a quadrilateral mesh,
+// y += sign * tau w_mu s_CIP(uw_mu; x_mu, .) (sign = +1 action, -1 defect /
+// residual); uw_mu = uw + mu * uw_stride (velocity of Radau node mu), G a
+// scratch buffer of cip_face_doubles(g) doubles
+int64_t cip_face_doubles(const Grid& g);
+template <typename T>
+hipError_t launch_cip(const Grid& g, const Model& m, double tau, const T* uw, int64_t uw_stride,
+                      const T* x, T* y, double sign, double* G, hipStream_t s);
+
+// CIP in the multigrid operators.  Across a face at node column X (or row Y)
+// the jump of the normal derivative of a continuous Q2 field is, per node row
+// a of the face's cells, j_a = ih sum_o d4(o) x(X + o, a), o = -2..2; the face
+// term is then x^T F v with F = (ih d4)(ih d4)^T (x) S, S a symmetric 3 x 3
+// matrix over the face's node rows (per Radau node and the same for both
+// velocity components).  A Galerkin product P^T F P keeps this form on the
+// coarse faces: the fine jump functional applied to a coarse Q2 field is the
+// coarse one, faces inside a coarse cell drop out (the coarse field is smooth
+// there), and S_coarse sums Py^T S Py over the two fine faces on a coarse
+// face, Py the quadratic interpolation along it.  S storage: cip_s_doubles(g)
+// per Radau node, S[(f * nm + mu) * 9 + 3 a + b] with nm = 2 (one per Radau
+// node) or 1, faces numbered as for launch_cip.
+int64_t cip_face_count(const Grid& g);
+// level 0: S_mu = scale_mu gamma h_F^2 |F| sum_q w_q |uw_mu . n_F| phi_a phi_b
+// at the face points, uw_mu = uw + mu * uw_stride, mu < nm
+hipError_t launch_cip_face_matrices(const Grid& g, const Model& m, const double* uw,
+                                    int64_t uw_stride, int nm, double scale0, double scale1,
+                                    double* S, hipStream_t s);
+// coarse-level S (nm = 2) from those of the next finer level
+hipError_t launch_cip_restrict(const Grid& gc, const Grid& gf, const double* Sf, double* Sc,
+                               hipStream_t s);
+// y += sign * F x on a level with stored S (nm = 2); G scratch as for launch_cip
+template <typename T>
+hipError_t launch_cip_level(const Grid& g, const double* S, const T* x, T* y, double sign,
+                            double* G, hipStream_t s);
+// adds the face terms to the rows of the dense space-time operator A (n = g.nst)
+hipError_t launch_cip_dense(const Grid& g, const double* S, double* A, hipStream_t s);
+
+__host__ __device__ inline double cip_d4(int o) {  // o = node column - face column, -2..2
+  return o == 0 ? 6.0 : ((o == 1 || o == -1) ? -4.0 : 1.0);
+}
+
+// Entry of the face part between velocity unknowns of one component and one
+// Radau node at nodes (xa, ya) and (xb, yb): the sum over the faces whose
+// 5 x 3 node stencil holds both.
+__device__ inline double cip_pair(const Grid& g, const double* __restrict__ S, int nm, int mu,
+                                  int xa, int ya, int xb, int yb) {
+  const int64_t nV = (int64_t)(g.nx - 1) * g.ny;
+  double v = 0.0;
+  const int xlo = (xa > xb ? xa : xb) - 2, xhi = (xa < xb ? xa : xb) + 2;
+  const int ylo = (ya > yb ? ya : yb) - 2, yhi = (ya < yb ? ya : yb) + 2;
+  // vertical faces: node column X = 2 cx, cx = 1 .. nx-1; cell row cy holding both rows
+  for (int X = xlo + (xlo & 1); X <= xhi; X += 2) {
+    const int cx = X / 2;
+    if (cx < 1 || cx > g.nx - 1) continue;
+    const double dd = cip_d4(xa - X) * cip_d4(xb - X) * g.ihx * g.ihx;
+    for (int cy = (ya < yb ? ya : yb) / 2 - 1; cy <= (ya < yb ? ya : yb) / 2; ++cy) {
+      if (cy < 0 || cy >= g.ny) continue;
+      const int a = ya - 2 * cy, b = yb - 2 * cy;
+      if (a < 0 || a > 2 || b < 0 || b > 2) continue;
+      const int64_t f = (int64_t)cy * (g.nx - 1) + cx - 1;
+      v += dd * S[(f * nm + mu) * 9 + 3 * a + b];
+    }
+  }
+  // horizontal faces: node row Y = 2 cy, cy = 1 .. ny-1; cell column cx holding both columns
+  for (int Y = ylo + (ylo & 1); Y <= yhi; Y += 2) {
+    const int cy = Y / 2;
+    if (cy < 1 || cy > g.ny - 1) continue;
+    const double dd = cip_d4(ya - Y) * cip_d4(yb - Y) * g.ihy * g.ihy;
+    for (int cx = (xa < xb ? xa : xb) / 2 - 1; cx <= (xa < xb ? xa : xb) / 2; ++cx) {
+      if (cx < 0 || cx >= g.nx) continue;
+      const int a = xa - 2 * cx, b = xb - 2 * cx;
+      if (a < 0 || a > 2 || b < 0 || b > 2) continue;
+      const int64_t f = nV + (int64_t)(cy - 1) * g.nx + cx;
+      v += dd * S[(f * nm + mu) * 9 + 3 * a + b];
+    }
+  }
+  return v;
+}
 
 // krylov.hip: vector kernels of the slab solve (FP64)
 int dot_partials();  // partial sums per vector of launch_multi_dot

@@ -244,9 +244,22 @@ __device__ __forceinline__ bool dropped(uint16_t mask, int l) {
   return i < 18 && !((mask >> (i % 9)) & 1u);
 }
 
-// One wave (64 lanes) assembles and inverts one 42x42 patch matrix.
+// CIP face part between patch unknowns l and m of cell (cx, cy): velocity
+// unknowns of the same Radau node and component only (S: per Radau node, nm
+// of them; nm = 1 for the time-diagonal form)
+__device__ __forceinline__ double patch_cip(const Grid& g, const double* S, int nm, int cx, int cy,
+                                            int l, int m) {
+  const int mu = l / kNs, i = l % kNs, nu = m / kNs, j = m % kNs;
+  if (!S || mu != nu || i >= 18 || j >= 18 || i / 9 != j / 9) return 0.0;
+  const int a = i % 9, b = j % 9;
+  return cip_pair(g, S, nm, nm == 1 ? 0 : mu, 2 * cx + a % 3, 2 * cy + a / 3, 2 * cx + b % 3,
+                  2 * cy + b / 3);
+}
+
+// One wave (64 lanes) assembles and inverts one 42x42 patch matrix (cell
+// terms from `entry`, CIP face terms from S when it is not null).
 template <typename T, typename Entry>
-__global__ __launch_bounds__(64) void patch_kernel(Grid g, Entry entry,
+__global__ __launch_bounds__(64) void patch_kernel(Grid g, Entry entry, const double* __restrict__ S,
                                                    const uint16_t* __restrict__ masks,
                                                    T* __restrict__ inv, int* status) {
   __shared__ double A[kNst][2 * kNst + 1];
@@ -271,6 +284,7 @@ __global__ __launch_bounds__(64) void patch_kernel(Grid g, Entry entry,
           if (rr < 0 || cc < 0) continue;
           v += entry((int64_t)ny_ * g.nx + nx_, rr, cc);
         }
+      v += patch_cip(g, S, 2, cx, cy, r, c);
     }
     A[r][c] = v;
     A[r][kNst + c] = (r == c) ? 1.0 : 0.0;
@@ -336,6 +350,7 @@ __global__ __launch_bounds__(64) void patch_kernel(Grid g, Entry entry,
 template <typename T>
 __global__ __launch_bounds__(64) void patch_complex_kernel(Grid g, double tau,
                                                            const double* __restrict__ Es,
+                                                           const double* __restrict__ Sr,
                                                            const uint16_t* __restrict__ masks,
                                                            T* __restrict__ inv, int* status) {
   __shared__ double Ar[kNs][2 * kNs + 1], Ai[kNs][2 * kNs + 1];
@@ -363,6 +378,7 @@ __global__ __launch_bounds__(64) void patch_complex_kernel(Grid g, double tau,
           jv += Es[nb * (kNs * kNs) + rr * kNs + cc];
           if (rr < 18 && cc < 18 && rr / 9 == cc / 9) mv += cell_mass(g, rr % 9, cc % 9);
         }
+      jv += patch_cip(g, Sr, 1, cx, cy, r, c);
       cr = kLamRe * mv + tau * jv;
       ci = kLamIm * mv;
     }
@@ -835,19 +851,19 @@ hipError_t launch_convert(int64_t n, const double* in, T* out, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t launch_fine_patches(const Grid& g, double tau, const double* Es, const uint16_t* masks,
-                               T* inv, int* status, hipStream_t s) {
+hipError_t launch_fine_patches(const Grid& g, double tau, const double* Es, const double* Sr,
+                               const uint16_t* masks, T* inv, int* status, hipStream_t s) {
   hipLaunchKernelGGL(patch_complex_kernel<T>, dim3((unsigned)g.nc), dim3(64), 0, s, g, tau, Es,
-                     masks, inv, status);
+                     Sr, masks, inv, status);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_exact_fine_patches(const Grid& g, double tau, const double* Es0,
-                                     const double* Es1, const uint16_t* masks, T* inv,
-                                     int* status, hipStream_t s) {
+                                     const double* Es1, const double* S, const uint16_t* masks,
+                                     T* inv, int* status, hipStream_t s) {
   FineEntry e{g, tau, Es0, Es1};
-  hipLaunchKernelGGL((patch_kernel<T, FineEntry>), dim3((unsigned)g.nc), dim3(64), 0, s, g, e,
+  hipLaunchKernelGGL((patch_kernel<T, FineEntry>), dim3((unsigned)g.nc), dim3(64), 0, s, g, e, S,
                      masks, inv, status);
   return hipGetLastError();
 }
@@ -861,10 +877,10 @@ hipError_t launch_transpose_convert(int64_t ncells, const double* E, T* Et, hipS
 }
 
 template <typename T>
-hipError_t launch_level_patches(const Grid& g, const double* E, T* inv, int* status,
-                                hipStream_t s) {
+hipError_t launch_level_patches(const Grid& g, const double* E, const double* S, T* inv,
+                                int* status, hipStream_t s) {
   StoredEntry e{E};
-  hipLaunchKernelGGL((patch_kernel<T, StoredEntry>), dim3((unsigned)g.nc), dim3(64), 0, s, g, e,
+  hipLaunchKernelGGL((patch_kernel<T, StoredEntry>), dim3((unsigned)g.nc), dim3(64), 0, s, g, e, S,
                      (const uint16_t*)nullptr, inv, status);
   return hipGetLastError();
 }
@@ -937,21 +953,21 @@ hipError_t coarse_invert(int64_t n, double* A, double* work, int* piv, int* stat
 
 template hipError_t launch_convert<double>(int64_t, const double*, double*, hipStream_t);
 template hipError_t launch_convert<float>(int64_t, const double*, float*, hipStream_t);
-template hipError_t launch_fine_patches<double>(const Grid&, double, const double*, const uint16_t*,
-                                                double*, int*, hipStream_t);
-template hipError_t launch_fine_patches<float>(const Grid&, double, const double*, const uint16_t*,
-                                               float*, int*, hipStream_t);
+template hipError_t launch_fine_patches<double>(const Grid&, double, const double*, const double*,
+                                                const uint16_t*, double*, int*, hipStream_t);
+template hipError_t launch_fine_patches<float>(const Grid&, double, const double*, const double*,
+                                               const uint16_t*, float*, int*, hipStream_t);
 template hipError_t launch_exact_fine_patches<double>(const Grid&, double, const double*,
-                                                      const double*, const uint16_t*, double*,
-                                                      int*, hipStream_t);
+                                                      const double*, const double*,
+                                                      const uint16_t*, double*, int*, hipStream_t);
 template hipError_t launch_exact_fine_patches<float>(const Grid&, double, const double*,
-                                                     const double*, const uint16_t*, float*, int*,
-                                                     hipStream_t);
+                                                     const double*, const double*,
+                                                     const uint16_t*, float*, int*, hipStream_t);
 template hipError_t launch_transpose_convert<double>(int64_t, const double*, double*, hipStream_t);
 template hipError_t launch_transpose_convert<float>(int64_t, const double*, float*, hipStream_t);
-template hipError_t launch_level_patches<double>(const Grid&, const double*, double*, int*,
-                                                 hipStream_t);
-template hipError_t launch_level_patches<float>(const Grid&, const double*, float*, int*,
-                                                hipStream_t);
+template hipError_t launch_level_patches<double>(const Grid&, const double*, const double*,
+                                                 double*, int*, hipStream_t);
+template hipError_t launch_level_patches<float>(const Grid&, const double*, const double*, float*,
+                                                int*, hipStream_t);
 
 }  // namespace pns

@@ -141,6 +141,8 @@ struct Solver {
       if (rc != PNS_OK) return rc;
     } else {
       PNS_HIP(c, launch_residual(g, model, c->disc.tau, U, vprev, R, s));
+      if (model.gamma_cip > 0.0)
+        PNS_HIP(c, launch_cip<double>(g, model, c->disc.tau, U, g.ns, U, R, -1.0, c->cipG, s));
     }
     if (c->load) PNS_HIP(c, launch_add(W.n, c->load, R, s));
     return PNS_OK;
@@ -283,11 +285,17 @@ int pns_residual(pns_ctx* ctx, const pns_model* md, const double* U, const doubl
   Model m;
   const int rc = make_model(md, &m, &ctx->err);
   if (rc != PNS_OK) return rc;
+  if (ctx->dim == 3 && m.gamma_cip > 0.0)
+    return fail(ctx, PNS_EUNSUPPORTED, "CIP stabilisation is built for quadrilaterals only");
   if (ctx->dim == 3) {
     const int rc = residual3d(ctx, m, U, vprev, R);
     if (rc != PNS_OK) return rc;
   } else {
-    PNS_HIP(ctx, launch_residual(ctx->lev[0].g, m, ctx->disc.tau, U, vprev, R, ctx->stream));
+    const Grid& g0 = ctx->lev[0].g;
+    PNS_HIP(ctx, launch_residual(g0, m, ctx->disc.tau, U, vprev, R, ctx->stream));
+    if (m.gamma_cip > 0.0)
+      PNS_HIP(ctx, launch_cip<double>(g0, m, ctx->disc.tau, U, g0.ns, U, R, -1.0, ctx->cipG,
+                                      ctx->stream));
   }
   if (ctx->load) PNS_HIP(ctx, launch_add(ctx->lev[0].g.nst, ctx->load, R, ctx->stream));
   return PNS_OK;

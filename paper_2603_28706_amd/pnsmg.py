@@ -46,7 +46,7 @@ class pns_model(ctypes.Structure):
                 ("nu_inf", ctypes.c_double), ("gamma1", ctypes.c_double),
                 ("gamma2", ctypes.c_double), ("sigma_max", ctypes.c_double),
                 ("convection", ctypes.c_int), ("nitsche_q_sign", ctypes.c_int),
-                ("lin", ctypes.c_int)]
+                ("lin", ctypes.c_int), ("gamma_cip", ctypes.c_double)]
 
 
 class pns_solve_params(ctypes.Structure):
@@ -381,7 +381,7 @@ def model_struct(model: dict):
         float(model.get("nu_inf", 0.0)), float(model.get("gamma1", 40.0)),
         float(model.get("gamma2", 40.0)), float(model.get("sigma_max", 1.0)),
         int(model.get("convection", 1)), int(model.get("qsign", 1)),
-        int(model.get("lin", MODIFIED_NEWTON)))
+        int(model.get("lin", MODIFIED_NEWTON)), float(model.get("gamma_cip", 0.0)))
 
 
 def masks_to_bits(masks):

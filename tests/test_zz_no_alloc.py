@@ -48,18 +48,19 @@ def test_static_smooth_rejects_levels_beyond_the_scratch_limit():
     L.pns_ctx_destroy(h2)
 
 
-# (cells of the first call, cells of the second, smaller, call, levels)
+# (cells of the first call, cells of the second, smaller, call, levels, CIP weight)
 CASES = [
-    ((48, 40), (16, 8), 2, pnsmg.FP64),
-    ((48, 40), (16, 8), 2, pnsmg.FP32),
-    ((4, 4, 4), (2, 2, 2), 2, pnsmg.FP64),
-    ((4, 4, 4), (2, 2, 2), 2, pnsmg.FP32),
+    ((48, 40), (16, 8), 2, pnsmg.FP64, 0.0),
+    ((48, 40), (16, 8), 2, pnsmg.FP32, 0.0),
+    ((48, 40), (16, 8), 2, pnsmg.FP64, 0.5),
+    ((4, 4, 4), (2, 2, 2), 2, pnsmg.FP64, 0.0),
+    ((4, 4, 4), (2, 2, 2), 2, pnsmg.FP32, 0.0),
 ]
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("big,small,levels,prec", CASES)
-def test_static_smooth_equals_workspace_smooth(big, small, levels, prec):
+@pytest.mark.parametrize("big,small,levels,prec,cip", CASES)
+def test_static_smooth_equals_workspace_smooth(big, small, levels, prec, cip):
     if not torch.cuda.is_available():
         pytest.skip("needs a GPU")
     tol = 1e-13 if prec == pnsmg.FP64 else 1e-5
@@ -69,7 +70,8 @@ def test_static_smooth_equals_workspace_smooth(big, small, levels, prec):
         ctx = pnsmg.Context(n, n_levels=levels, precision=prec, tau=0.01)
         nv = ctx.sizes(0)["nv"]
         uk = inputs.uniform(500 + call, 2 * nv)
-        ctx.pns_set_state(MODEL, torch.tensor(uk, dtype=torch.float64, device="cuda"))
+        ctx.pns_set_state(dict(MODEL, gamma_cip=cip),
+                          torch.tensor(uk, dtype=torch.float64, device="cuda"))
         ctx.pns_vanka_setup()
         # the coarsest 3D level holds the dense inverse (no patches)
         lv_list = [0] if len(n) == 3 else list(range(levels))
