@@ -64,6 +64,7 @@ class _CProblem(ctypes.Structure):
         ("sigma_max", ctypes.c_double),
         ("convection", ctypes.c_int), ("qsign", ctypes.c_int), ("lin", ctypes.c_int),
         ("gamma_cip", ctypes.c_double),
+        ("ghat", ctypes.c_void_p), ("gnode", ctypes.c_void_p),
     ]
 
 
@@ -94,6 +95,7 @@ def lib():
         L.orc_apply.argtypes = [P, dp, dp, dp]
         L.orc_apply_threads.argtypes = [P, dp, dp, dp, ctypes.c_int]
         L.orc_element_form.argtypes = [P, ctypes.c_int, dp, dp, dp, dp]
+        L.orc_element_lift.argtypes = [P, ctypes.c_int, dp]
         L.orc_residual.argtypes = [P, dp, dp, dp, dp]
         L.orc_load.argtypes = [P, dp, dp]
         L.orc_cip_count.argtypes = [P]
@@ -102,7 +104,8 @@ def lib():
         L.orc_cip_face.restype = None
         for f in ("orc_stress", "orc_tangent", "orc_local_dofs", "orc_element_matrix",
                   "orc_element_mass", "orc_all_element_matrices", "orc_apply",
-                  "orc_apply_threads", "orc_element_form", "orc_residual", "orc_load"):
+                  "orc_apply_threads", "orc_element_form", "orc_element_lift", "orc_residual",
+                  "orc_load"):
             getattr(L, f).restype = None
         _lib = L
     return _lib
@@ -208,6 +211,9 @@ class Problem:
     qsign: int = 1
     lin: int = MODIFIED_NEWTON
     gamma_cip: float = 0.0
+    # Dirichlet lifting ghat_D (eq. def-b-gam): a Q2 velocity field per Radau
+    # node, nt * nv values; its trace is g_D.  None: homogeneous data.
+    lifting: object = dcfield(default=None, repr=False, compare=False)
     _c: object = dcfield(default=None, repr=False, compare=False)
 
     @property
@@ -238,12 +244,24 @@ class Problem:
         s.convection = int(fields["convection"])
         s.qsign = int(fields["qsign"])
         s.lin = int(fields["lin"])
+        lift = fields.get("lifting")
+        if lift is not None:
+            # the array stays referenced by the Problem for the call's lifetime
+            assert lift.dtype == np.float64 and lift.flags.c_contiguous
+            assert lift.size == nt * d * int(np.prod([2 * m + 1 for m in fields["n"]]))
+            s.ghat = lift.ctypes.data
         return s
 
     def with_(self, **kw) -> "Problem":
         d = {k: v for k, v in self.__dict__.items() if k != "_c"}
         d.update(kw)
+        if d.get("lifting") is not None:
+            d["lifting"] = _f64(d["lifting"])
         return Problem(**d)
+
+    def __post_init__(self):
+        if self.lifting is not None:
+            self.lifting = _f64(self.lifting)
 
     # sizes
     @property
@@ -279,8 +297,23 @@ class Problem:
         return tuple((self.hi[k] - self.lo[k]) / self.n[k] for k in range(self.dim))
 
 
-def _cs(prob: Problem, **kw):
-    return ctypes.byref(prob.cstruct(**kw))
+def _cs(prob: Problem, gnode=None, **kw):
+    """C view of the problem; `gnode`: the lifting of the one time node an
+    element-level routine works on (d * num_nodes values, kept alive by the
+    caller), None: zero."""
+    s = prob.cstruct(**kw)
+    if gnode is not None:
+        assert gnode.dtype == np.float64 and gnode.flags.c_contiguous and gnode.size == prob.nv
+        s.gnode = gnode.ctypes.data
+    return ctypes.byref(s)
+
+
+def lifting_blocks(prob: Problem):
+    """The lifting of every Radau node (None for homogeneous data)."""
+    if prob.lifting is None:
+        return [None] * prob.nt
+    return [np.ascontiguousarray(prob.lifting[m * prob.nv:(m + 1) * prob.nv])
+            for m in range(prob.nt)]
 
 
 # ------------------------------------------------------- pointwise (L0)
@@ -312,12 +345,15 @@ def local_dofs(prob: Problem):
     return out
 
 
-def element_matrices(prob: Problem, u_spatial, **kw):
-    """All cell matrices of J_mu at velocity state u (length d*num_nodes)."""
+def element_matrices(prob: Problem, u_spatial, g_spatial=None, **kw):
+    """All cell matrices of J_mu at velocity state u (length d*num_nodes), the
+    Nitsche coefficients frozen at the lifting g_spatial of the same time node
+    (None: zero)."""
     u = _f64(u_spatial)
     assert u.size == prob.nv
+    g = _f64(g_spatial) if g_spatial is not None else None
     E = np.zeros((prob.num_cells, prob.nloc, prob.nloc))
-    lib().orc_all_element_matrices(_cs(prob, **kw), _dp(u), _dp(E))
+    lib().orc_all_element_matrices(_cs(prob, gnode=g, **kw), _dp(u), _dp(E))
     return E
 
 
@@ -351,11 +387,12 @@ def cip_matrix(prob: Problem, u_weight):
                          shape=(prob.ns, prob.ns))
 
 
-def assemble_spatial(prob: Problem, u_spatial, **kw):
+def assemble_spatial(prob: Problem, u_spatial, g_spatial=None, **kw):
     """Assembled spatial block J_mu (ns x ns, CSR) at velocity state u: the
-    element matrices plus, with gamma_CIP > 0, the CIP form with its weight
-    lagged at u (eq. Amu-decomp)."""
-    E = element_matrices(prob, u_spatial, **kw)
+    element matrices (Nitsche coefficients frozen at the lifting g_spatial)
+    plus, with gamma_CIP > 0, the CIP form with its weight lagged at u
+    (eq. Amu-decomp)."""
+    E = element_matrices(prob, u_spatial, g_spatial, **kw)
     dofs = local_dofs(prob)
     rows = np.repeat(dofs, prob.nloc, axis=1).ravel()
     cols = np.tile(dofs, (1, prob.nloc)).ravel()
@@ -384,12 +421,15 @@ def assemble_velocity_mass(prob: Problem):
                          shape=(prob.ns, prob.ns))
 
 
-def assemble_slab(prob: Problem, uk_blocks, **kw):
+def assemble_slab(prob: Problem, uk_blocks, g_blocks=None, **kw):
     """J_n = [K_t (x) M_x, 0; 0, 0] + (tau M_t (x) I) diag(J_1..J_{k+1}),
-    eq. (slab-underint-jac).  uk_blocks: nt velocity states."""
+    eq. (slab-underint-jac).  uk_blocks: nt velocity states; g_blocks: the
+    lifting per time node (default: the problem's)."""
     _, Mt, Kt, _ = time_matrices(prob.k_time)
     Mx = assemble_velocity_mass(prob)
-    Js = [assemble_spatial(prob, uk_blocks[m], **kw) for m in range(prob.nt)]
+    if g_blocks is None:
+        g_blocks = lifting_blocks(prob)
+    Js = [assemble_spatial(prob, uk_blocks[m], g_blocks[m], **kw) for m in range(prob.nt)]
     blocks = [[None] * prob.nt for _ in range(prob.nt)]
     for i in range(prob.nt):
         for j in range(prob.nt):
@@ -463,8 +503,9 @@ def load_vector(prob: Problem, f_qp):
 
 
 def residual(prob: Problem, U, vprev=None, ulag=None, load=None, **kw):
-    """Slab residual R_n(U), eq. (slab-underint), g_D = 0; `load` is the
-    volume-force vector of `load_vector` (None: f = 0)."""
+    """Slab residual R_n(U), eq. (slab-underint), with the Dirichlet data of
+    the problem's lifting (None: g_D = 0); `load` is the volume-force vector of
+    `load_vector` (None: f = 0)."""
     U = _f64(U)
     R = np.zeros(prob.nst)
     vp = _f64(vprev) if vprev is not None else None
@@ -584,9 +625,12 @@ def representative_velocity(prob: Problem, uk, t_rep: float = 0.5):
 
 def assemble_surrogate(prob: Problem, uk, t_rep: float = 0.5):
     """Finest-level operator whose spatial blocks are all frozen at t_rep,
-    eq. (surrogate-diag): diag(J_1..J_{k+1}) -> I (x) J(u_rep)."""
+    eq. (surrogate-diag): diag(J_1..J_{k+1}) -> I (x) J(u_rep), the Nitsche
+    coefficients at the lifting's value at t_rep."""
     ur = representative_velocity(prob, uk, t_rep)
-    return assemble_slab(prob, [ur] * prob.nt)
+    gr = (representative_velocity(prob, prob.lifting, t_rep) if prob.lifting is not None
+          else None)
+    return assemble_slab(prob, [ur] * prob.nt, [gr] * prob.nt)
 
 
 def patch_matrices(A, patches):
@@ -781,9 +825,12 @@ def apply_rows(prob: Problem, uk, x, rows, **kw):
     uk = _f64(uk)
     x = _f64(x)
     rows = np.asarray(rows, dtype=np.int64)
+    assert prob.gamma_cip == 0.0, "apply_rows covers the cell terms only (no CIP)"
     _, _, Kt, _ = time_matrices(prob.k_time)
     _, w = radau_right(prob.k_time)
+    gbl = lifting_blocks(prob)
     cs = _cs(prob, **kw)
+    csm = [_cs(prob, gnode=gbl[m], **kw) for m in range(prob.nt)]
     nb = 3 ** prob.dim
     nloc = prob.nloc
     ld = np.zeros(prob.nloc, dtype=np.int32)
@@ -798,7 +845,7 @@ def apply_rows(prob: Problem, uk, x, rows, **kw):
             for m in range(prob.nt):
                 uloc = _f64(uk[m * prob.nv + dofs[:prob.dim * nb]])
                 E = np.zeros((nloc, nloc))
-                lib().orc_element_matrix(cs, int(c), _dp(uloc), _dp(E))
+                lib().orc_element_matrix(csm[m], int(c), _dp(uloc), _dp(E))
                 Es.append(E)
             M = np.zeros((nb, nb))
             lib().orc_element_mass(cs, int(c), _dp(M))

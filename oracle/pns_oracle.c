@@ -23,9 +23,13 @@
  * by the local vector.
  *
  * Readings where the paper is silent (each one listed in the design notes):
- *   - homogeneous Dirichlet data on all of the boundary, lifting g_D = 0, so the
- *     frozen Nitsche coefficients are eta_D = nu_inf + nu*delta^(p-2) and
- *     DS(0)B = eta_D B;
+ *   - Dirichlet data on all of the boundary, given by a lifting ghat_D: a Q2
+ *     velocity field per Radau node (NULL: homogeneous data).  g_D is its
+ *     trace; the frozen Nitsche coefficients of eq. (def-b-gam) are eta(G) and
+ *     the exact stress derivative DS(G) at G = D ghat_D, evaluated at each face
+ *     point from the boundary cell's field (G = 0 for homogeneous data:
+ *     eta_D = nu_inf + nu*delta^(p-2), DS(0)B = eta_D B); the right-hand side
+ *     carries B_gamma(g_D, w) of eq. (disc-residual);
  *   - 3-point Gauss-Legendre per direction on cells and faces;
  *   - P1disc basis {1, (x_k - c_k)/h_k};
  *   - h_F = cell size normal to the face;
@@ -59,6 +63,9 @@ typedef struct {
   int qsign;          /* +1 or -1, see header */
   int lin;            /* ORC_PICARD / ORC_EXACT_NEWTON / ORC_MODIFIED_NEWTON */
   double gamma_cip;   /* CIP weight gamma_CIP of eq. (scip-def); 0 = off */
+  const double* ghat; /* Dirichlet lifting, nt blocks of d*num_nodes; NULL = 0 */
+  const double* gnode;/* the lifting of the one time node an element-level call
+                         works on (d*num_nodes); NULL = 0 */
 } orc_problem;
 
 /* ---------------------------------------------------------------- sizes */
@@ -295,21 +302,40 @@ static double vol_J(const orc_problem* P, const field* u, const double* A, const
   return s;
 }
 
+/* B^s and B^r of eq. (def-b-gam) for the field x (value xv) and the test w,
+ * coefficients frozen at G = D ghat_D:
+ *   - (DS(G)(Dw) n).x + qsign (x.n) w_pi + gamma1 eta(G)/hF (x.w) + gamma2/hF (x.n)(w.n) */
+static double nitsche_sr(const orc_problem* P, const double* G, const double* n, double hF,
+                         const double* xv, const field* w) {
+  int d = P->dim;
+  double Dw[9], DSw[9];
+  symgrad(d, w->G, Dw);
+  orc_tangent(P, ORC_EXACT_NEWTON, G, Dw, DSw);
+  double xn = vdot(d, xv, n), wn = vdot(d, w->v, n), xw = vdot(d, xv, w->v);
+  double s = 0.0;
+  for (int i = 0; i < d; ++i) {
+    double Dn = 0.0;
+    for (int j = 0; j < d; ++j) Dn += DSw[i * d + j] * n[j];
+    s -= Dn * xv[i];
+  }
+  s += (double)P->qsign * xn * w->q;
+  s += P->gamma1 * eta_of(P, ddot(d, G, G)) / hF * xw + P->gamma2 / hF * xn * wn;
+  return s;
+}
+
 /* Boundary integrand of J_mu on a Dirichlet face with outward normal n, face
- * size hF:
+ * size hF, frozen Nitsche coefficients at G = D ghat_D:
  *   (x.n)(u.w) + (u.n)(x.w)   [Newton] / (u.n)(x.w) [Picard]  convective flux, eq. (Defc)
  *   - (T(Dx) n).w + x_pi (n.w)                  -<(S(Du) - pi I) n, w>, eq. (def-a-gam)
  *   - (ulag.n)^- (x.w)                          B^c, factor lagged
- *   - eta_D (Dw n).x + qsign (x.n) w_pi         B^s with D S(0) = eta_D I
- *   + gamma1 eta_D / hF (x.w) + gamma2 / hF (x.n)(w.n)   B^r                     */
+ *   - (DS(G)(Dw) n).x + qsign (x.n) w_pi        B^s
+ *   + gamma1 eta(G) / hF (x.w) + gamma2 / hF (x.n)(w.n)   B^r                   */
 static double face_J(const orc_problem* P, const field* u, const double* A, const double* n,
-                     double hF, const field* x, const field* w) {
+                     double hF, const double* G, const field* x, const field* w) {
   int d = P->dim;
-  double etaD = eta_of(P, 0.0);
-  double Bx[9], T[9], Dw[9];
+  double Bx[9], T[9];
   symgrad(d, x->G, Bx);
   orc_tangent(P, P->lin, A, Bx, T);
-  symgrad(d, w->G, Dw);
   double un = vdot(d, u->v, n), xn = vdot(d, x->v, n), wn = vdot(d, w->v, n);
   double xw = vdot(d, x->v, w->v);
   double s = 0.0;
@@ -320,17 +346,12 @@ static double face_J(const orc_problem* P, const field* u, const double* A, cons
     s -= neg * xw;
   }
   for (int i = 0; i < d; ++i) {
-    double Tn = 0.0, Dwn = 0.0;
-    for (int j = 0; j < d; ++j) {
-      Tn += T[i * d + j] * n[j];
-      Dwn += Dw[i * d + j] * n[j];
-    }
+    double Tn = 0.0;
+    for (int j = 0; j < d; ++j) Tn += T[i * d + j] * n[j];
     s -= Tn * w->v[i];
-    s -= etaD * Dwn * x->v[i];
   }
   s += x->q * wn;
-  s += (double)P->qsign * xn * w->q;
-  s += P->gamma1 * etaD / hF * xw + P->gamma2 / hF * xn * wn;
+  s += nitsche_sr(P, G, n, hF, x->v, w);
   return s;
 }
 
@@ -383,13 +404,28 @@ static int face_rule(const orc_problem* P, const cellgeo* g, int k, int s, doubl
   return nq;
 }
 
+/* local values of the lifting P->gnode on the cell (0 without one) */
+static void lift_local(const orc_problem* P, int cell, double* gloc) {
+  int nb = ipow3(P->dim);
+  if (!P->gnode) {
+    memset(gloc, 0, sizeof(double) * P->dim * nb);
+    return;
+  }
+  int dofs[85];
+  orc_local_dofs(P, cell, dofs);
+  for (int i = 0; i < P->dim * nb; ++i) gloc[i] = P->gnode[dofs[i]];
+}
+
 /* Element matrix of J_mu on one cell: E[i*nloc + j] = J_mu(trial j, test i),
- * state given by the local velocity values u[c*nb + a]. */
+ * state given by the local velocity values u[c*nb + a]; Nitsche coefficients
+ * frozen at the lifting P->gnode. */
 void orc_element_matrix(const orc_problem* P, int cell, const double* u, double* E) {
   cellgeo g;
   cell_setup(P, cell, &g);
   int d = g.d, nloc = orc_local_size(P);
   memset(E, 0, sizeof(double) * nloc * nloc);
+  double gloc[81];
+  lift_local(P, cell, gloc);
   double xi[27][3], w[27];
   field* fx = (field*)malloc(sizeof(field) * nloc);
   /* volume */
@@ -413,14 +449,16 @@ void orc_element_matrix(const orc_problem* P, int cell, const double* u, double*
       for (int q = 0; q < nf; ++q) {
         basis_at B;
         eval_basis(&g, xi[q], &B);
-        field us;
+        field us, gs;
         state_field(&g, &B, u, &us);
-        double A[9];
+        state_field(&g, &B, gloc, &gs);
+        double A[9], G[9];
         symgrad(d, us.G, A);
+        symgrad(d, gs.G, G);
         for (int j = 0; j < nloc; ++j) unit_field(&g, &B, j, &fx[j]);
         for (int i = 0; i < nloc; ++i)
           for (int j = 0; j < nloc; ++j)
-            E[i * nloc + j] += w[q] * face_J(P, &us, A, n, hF, &fx[j], &fx[i]);
+            E[i * nloc + j] += w[q] * face_J(P, &us, A, n, hF, G, &fx[j], &fx[i]);
       }
     }
   free(fx);
@@ -599,8 +637,10 @@ static void apply_cell(const orc_problem* P, int c, const double* uk, const doub
   orc_local_dofs(P, c, dofs);
   orc_element_mass(P, c, M);
   for (int mu = 0; mu < P->nt; ++mu) {
+    orc_problem Pm = *P;
+    Pm.gnode = P->ghat ? P->ghat + (size_t)mu * d * nn : NULL;
     gather_velocity(P, dofs, uk + (size_t)mu * d * nn, uloc);
-    orc_element_matrix(P, c, uloc, E);
+    orc_element_matrix(&Pm, c, uloc, E);
     const double* xm = x + (size_t)mu * ns;
     double* ym = y + (size_t)mu * ns;
     double scale = P->tau * P->wt[mu];
@@ -713,17 +753,16 @@ static double vol_A(const orc_problem* P, const field* u, const field* w) {
   return s;
 }
 
-/* boundary part of A_gamma on a Dirichlet face, g_D = 0:
+/* boundary part of A_gamma on a Dirichlet face, Nitsche coefficients frozen
+ * at G = D ghat_D:
  *   (u.n)(u.w) - (S(Du) n).w + pi (n.w) - (ulag.n)^- (u.w)
- *   - eta_D (Dw n).u + qsign (u.n) w_pi + gamma1 eta_D/hF (u.w) + gamma2/hF (u.n)(w.n) */
+ *   - (DS(G)(Dw) n).u + qsign (u.n) w_pi + gamma1 eta(G)/hF (u.w) + gamma2/hF (u.n)(w.n) */
 static double face_A(const orc_problem* P, const field* u, const field* ulag, const double* n,
-                     double hF, const field* w) {
+                     double hF, const double* G, const field* w) {
   int d = P->dim;
-  double etaD = eta_of(P, 0.0);
-  double A[9], S[9], Dw[9];
+  double A[9], S[9];
   symgrad(d, u->G, A);
   orc_stress(P, A, S);
-  symgrad(d, w->G, Dw);
   double un = vdot(d, u->v, n), wn = vdot(d, w->v, n), uw = vdot(d, u->v, w->v);
   double s = 0.0;
   if (P->convection) {
@@ -732,18 +771,27 @@ static double face_A(const orc_problem* P, const field* u, const field* ulag, co
     s -= 0.5 * (fabs(ln) - ln) * uw;
   }
   for (int i = 0; i < d; ++i) {
-    double Sn = 0.0, Dwn = 0.0;
-    for (int j = 0; j < d; ++j) {
-      Sn += S[i * d + j] * n[j];
-      Dwn += Dw[i * d + j] * n[j];
-    }
+    double Sn = 0.0;
+    for (int j = 0; j < d; ++j) Sn += S[i * d + j] * n[j];
     s -= Sn * w->v[i];
-    s -= etaD * Dwn * u->v[i];
   }
   s += u->q * wn;
-  s += (double)P->qsign * un * w->q;
-  s += P->gamma1 * etaD / hF * uw + P->gamma2 / hF * un * wn;
+  s += nitsche_sr(P, G, n, hF, u->v, w);
   return s;
+}
+
+/* B_gamma(g_D, w) of eq. (def-b-gam) at a face point, g the lifting's value
+ * there (its trace), G = D ghat_D:
+ *   - (g.n)^- (g.w) [with convection] + B^s(g, w) + B^r(g, w)              */
+static double face_B(const orc_problem* P, const double* g, const double* n, double hF,
+                     const double* G, const field* w) {
+  int d = P->dim;
+  double s = 0.0;
+  if (P->convection) {
+    double gn = vdot(d, g, n);
+    s -= 0.5 * (fabs(gn) - gn) * vdot(d, g, w->v);
+  }
+  return s + nitsche_sr(P, G, n, hF, g, w);
 }
 
 /* Local vector of A_gamma at state (u, pi) on one cell: F[i] = A_gamma(u,pi)(test i).
@@ -755,6 +803,8 @@ void orc_element_form(const orc_problem* P, int cell, const double* uloc, const 
   cell_setup(P, cell, &g);
   int d = g.d, nloc = orc_local_size(P);
   memset(F, 0, sizeof(double) * nloc);
+  double gloc[81];
+  lift_local(P, cell, gloc);
   double xi[27][3], w[27];
   int nq = volume_rule(&g, xi, w);
   for (int q = 0; q < nq; ++q) {
@@ -776,23 +826,58 @@ void orc_element_form(const orc_problem* P, int cell, const double* uloc, const 
       for (int q = 0; q < nf; ++q) {
         basis_at B;
         eval_basis(&g, xi[q], &B);
-        field us, ul;
+        field us, ul, gs;
         state_field(&g, &B, uloc, &us);
         state_field(&g, &B, lagloc, &ul);
+        state_field(&g, &B, gloc, &gs);
         for (int j = 0; j <= d; ++j) us.q += ploc[j] * B.psi[j];
+        double G[9];
+        symgrad(d, gs.G, G);
         for (int i = 0; i < nloc; ++i) {
           field fw;
           unit_field(&g, &B, i, &fw);
-          F[i] += w[q] * face_A(P, &us, &ul, n, hF, &fw);
+          F[i] += w[q] * face_A(P, &us, &ul, n, hF, G, &fw);
+        }
+      }
+    }
+}
+
+/* Local vector of B_gamma(g_D, .) on one cell (zero unless the cell has a
+ * boundary face and P->gnode is set): F[i] = B_gamma(g_D, test i). */
+void orc_element_lift(const orc_problem* P, int cell, double* F) {
+  cellgeo g;
+  cell_setup(P, cell, &g);
+  int d = g.d, nloc = orc_local_size(P);
+  memset(F, 0, sizeof(double) * nloc);
+  if (!P->gnode) return;
+  double gloc[81];
+  lift_local(P, cell, gloc);
+  double xi[27][3], w[27];
+  for (int k = 0; k < d; ++k)
+    for (int s = 0; s < 2; ++s) {
+      double n[3], hF;
+      int nf = face_rule(P, &g, k, s, xi, w, n, &hF);
+      for (int q = 0; q < nf; ++q) {
+        basis_at B;
+        eval_basis(&g, xi[q], &B);
+        field gs;
+        state_field(&g, &B, gloc, &gs);
+        double G[9];
+        symgrad(d, gs.G, G);
+        for (int i = 0; i < nloc; ++i) {
+          field fw;
+          unit_field(&g, &B, i, &fw);
+          F[i] += w[q] * face_B(P, gs.v, n, hF, G, &fw);
         }
       }
     }
 }
 
 /* Slab residual, eq. (slab-underint), right-hand side minus left-hand side with
- * f = 0 and g_D = 0:
- *   R_v,mu = -( sum_nu Kt[mu][nu] M_x V_nu - mt[mu] M_x vprev ) - tau wt[mu] A_gamma(U_mu)_v
- *   R_p,mu = - tau wt[mu] A_gamma(U_mu)_p
+ * f = 0 and the Dirichlet data of the lifting P->ghat (NULL: g_D = 0):
+ *   R_v,mu = -( sum_nu Kt[mu][nu] M_x V_nu - mt[mu] M_x vprev )
+ *            + tau wt[mu] (B_gamma(g_D(t_mu)) - A_gamma(U_mu))_v
+ *   R_p,mu = tau wt[mu] (B_gamma(g_D(t_mu)) - A_gamma(U_mu))_p
  * U: nt spatial blocks; vprev: left trace (velocity, d*num_nodes), may be NULL
  * (zero); ulag: nt velocity blocks for the inflow factor, NULL = U itself. */
 void orc_residual(const orc_problem* P, const double* U, const double* vprev, const double* ulag,
@@ -816,9 +901,15 @@ void orc_residual(const orc_problem* P, const double* U, const double* vprev, co
       } else {
         memcpy(lloc, uloc, sizeof(double) * d * nb);
       }
-      orc_element_form(P, c, uloc, ploc, lloc, F);
+      orc_problem Pm = *P;
+      Pm.gnode = P->ghat ? P->ghat + (size_t)mu * d * nn : NULL;
+      orc_element_form(&Pm, c, uloc, ploc, lloc, F);
       double scale = P->tau * P->wt[mu];
       for (int i = 0; i < nloc; ++i) Rm[dofs[i]] -= scale * F[i];
+      if (Pm.gnode) {
+        orc_element_lift(&Pm, c, F);
+        for (int i = 0; i < nloc; ++i) Rm[dofs[i]] += scale * F[i];
+      }
       for (int cc = 0; cc < d; ++cc)
         for (int a = 0; a < nb; ++a) {
           double s = 0.0;
