@@ -363,6 +363,22 @@ int pns_load_vector(pns_ctx* ctx, const double* f_qp_dev, double* F_dev);
  * default) for f = 0.  pns_march adds the same F to each of its slabs. */
 int pns_set_load(pns_ctx* ctx, const double* F_dev);
 
+/* Inhomogeneous Dirichlet data (Sec. 3.2, eq. def-b-gam; the B_gamma(g_D, .)
+ * term of eq. disc-residual).  ghat_dev (FP64, device, caller-owned, read at
+ * every use): a lifting ghat_D of the data as a Q2 velocity field per Radau
+ * node, 2 N_v values (node 0's velocity layout, then node 1's) on the level-0
+ * mesh; g_D is its trace on the boundary.  The viscous Nitsche coefficients
+ * are frozen at G = D ghat_D, evaluated at each boundary face point from the
+ * boundary cell's field: eta(G) in the penalty and the exact stress
+ * derivative DS(G) in the symmetry term, in the Jacobian action, the residual,
+ * the patches and the Galerkin coarse operators (the surrogate patches take
+ * the lifting at the slab midpoint); the residual adds B_gamma(g_D, .) (inflow,
+ * symmetry and penalty terms at the trace).  NULL (the default): homogeneous
+ * data, eta_D = eta(0).  A smoother built before the call is invalidated
+ * (pns_vanka_setup again).  Quadrilaterals only: PNS_EUNSUPPORTED on a
+ * hexahedral context.  Serving requests use homogeneous data. */
+int pns_set_dirichlet(pns_ctx* ctx, const double* ghat_dev);
+
 /* Parameters of pns_solve. */
 typedef struct {
   int max_newton;     /* nonlinear iterations */

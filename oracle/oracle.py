@@ -735,7 +735,9 @@ def prolongation(coarse: Problem, fine: Problem):
 
 
 def coarse_problem(prob: Problem) -> Problem:
-    return prob.with_(n=tuple(m // 2 for m in prob.n))
+    """The mesh of the next coarser level (its operators are Galerkin products
+    of the finest one, so it carries no Dirichlet lifting of its own)."""
+    return prob.with_(n=tuple(m // 2 for m in prob.n), lifting=None)
 
 
 @dataclass

@@ -89,6 +89,7 @@ size_t layout(pns_ctx* c, bool bind) {
     return (off + kAlign - 1) / kAlign * kAlign;
   }
   c->urep = (double*)take(g0.nv * 8);
+  c->lrep = (double*)take(g0.nv * 8);
   c->Es0 = (double*)take(g0.nc * kNs * kNs * 8);
   c->Es1 = (double*)take(g0.nc * kNs * kNs * 8);
   c->Esr = (double*)take(g0.nc * kNs * kNs * 8);
@@ -436,9 +437,16 @@ int vanka_setup_impl(pns_ctx* c, const uint16_t* masks) {
   }
   const double* u0 = c->uk64;
   const double* u1 = c->uk64 + L0.g.nv;
-  PNS_HIP(c, launch_element_matrices(L0.g, c->model, u0, c->Es0, s));
-  PNS_HIP(c, launch_element_matrices(L0.g, c->model, u1, c->Es1, s));
-  PNS_HIP(c, launch_element_matrices(L0.g, c->model, c->urep, c->Esr, s));
+  // Nitsche coefficients frozen at the lifting of each Radau node, at t_rep for
+  // the surrogate patches
+  const double* gl0 = c->lift;
+  const double* gl1 = c->lift ? c->lift + L0.g.nv : nullptr;
+  if (c->lift)
+    PNS_HIP(c, launch_state_combine(L0.g.nv, gl0, gl1, kXiMid[0], kXiMid[1], c->lrep, s));
+  PNS_HIP(c, launch_element_matrices(L0.g, c->model, u0, gl0, c->Es0, s));
+  PNS_HIP(c, launch_element_matrices(L0.g, c->model, u1, gl1, c->Es1, s));
+  PNS_HIP(c, launch_element_matrices(L0.g, c->model, c->urep, c->lift ? c->lrep : nullptr,
+                                     c->Esr, s));
   // CIP face matrices: at each Radau node's velocity (level-0 operator, with
   // tau w_mu) and at t_rep (time-diagonal patches, unscaled)
   const bool cip = c->model.gamma_cip > 0.0;
@@ -669,6 +677,7 @@ int pns::make_model(const pns_model* md, Model* m, std::string* err) {
   m->lin = md->lin;
   m->convection = md->convection ? 1 : 0;
   m->gamma_cip = md->gamma_cip;
+  m->lift = nullptr;  // the context's lifting is attached by the caller
   return PNS_OK;
 }
 
@@ -793,6 +802,7 @@ int pns_set_state(pns_ctx* ctx, const pns_model* md, const double* u_k) {
   if (rc != PNS_OK) return rc;
   if (ctx->dim == 3 && m.gamma_cip > 0.0)
     return fail(ctx, PNS_EUNSUPPORTED, "CIP stabilisation is built for quadrilaterals only");
+  m.lift = ctx->lift;
   ctx->model = m;
   ctx->drop_graph();
   const Grid& g0 = ctx->lev[0].g;
@@ -884,6 +894,17 @@ int pns_load_vector(pns_ctx* ctx, const double* f_qp, double* F) {
 int pns_set_load(pns_ctx* ctx, const double* F) {
   if (!ctx) return PNS_EINVAL;
   ctx->load = F;
+  return PNS_OK;
+}
+
+int pns_set_dirichlet(pns_ctx* ctx, const double* ghat) {
+  if (!ctx) return PNS_EINVAL;
+  if (ghat && ctx->dim == 3)
+    return fail(ctx, PNS_EUNSUPPORTED, "inhomogeneous Dirichlet data is built for quadrilaterals");
+  ctx->lift = ghat;
+  ctx->model.lift = ghat;
+  ctx->drop_graph();
+  ctx->has_smoother = false;  // the patches and coarse operators depend on it
   return PNS_OK;
 }
 

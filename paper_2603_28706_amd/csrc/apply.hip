@@ -148,8 +148,14 @@ __device__ __forceinline__ void face_point(const Model& m, const Grid& g, double
   const double xi = xface ? (side == 0 ? 0.0 : 1.0) : gq;
   const double et = xface ? gq : (side == 2 ? 0.0 : 1.0);
   const double ihF = xface ? g.ihx : g.ihy;  // 1 / h_F, h_F the cell size normal to the face
-  const T etaD = (T)m.etaD;
-  const T pen1 = (T)(m.gamma1 * m.etaD * ihF);
+  // frozen Nitsche coefficients at G = D ghat_D (G = 0: eta_D, no rank-one part)
+  double Gl00 = 0.0, Gl01 = 0.0, Gl11 = 0.0, etaG = m.etaD, kG = 0.0;
+  if (m.lift) {
+    double l0, l1;
+    lift_at2(m, g, mu, cx, cy, xi, et, l0, l1, Gl00, Gl01, Gl11);
+    frozen_coef(m, Gl00, Gl01, Gl11, etaG, kG);
+  }
+  const T pen1 = (T)(m.gamma1 * etaG * ihF);
   const T pen2 = (T)(m.gamma2 * ihF);
   const T n0 = (T)nxv, n1 = (T)nyv;
   const int NX = 2 * g.nx + 1;
@@ -219,10 +225,13 @@ __device__ __forceinline__ void face_point(const Model& m, const Grid& g, double
   }
   F0 *= sW;
   F1 *= sW;
-  // -eta_D (Dw n).x  ->  coefficient of d_j w_i : -eta_D (x_i n_j + x_j n_i)/2
-  const T c = -sW * etaD * (T)0.5;
-  const T G00 = c * (X[0] * n0 + X[0] * n0), G01 = c * (X[0] * n1 + X[1] * n0);
-  const T G10 = c * (X[1] * n0 + X[0] * n1), G11 = c * (X[1] * n1 + X[1] * n1);
+  // -(DS(G)(Dw) n).x = -Dw : DS(G)(sym(x (x) n))  ->  coefficient of d_j w_i:
+  // -(eta(G) S + k (G:S) G)_ij with S = sym(x (x) n)
+  const T S00 = X[0] * n0, S01 = (T)0.5 * (X[0] * n1 + X[1] * n0), S11 = X[1] * n1;
+  const T kGS = (T)kG * ((T)Gl00 * S00 + (T)2 * (T)Gl01 * S01 + (T)Gl11 * S11);
+  const T eG = (T)etaG;
+  const T G00 = -sW * (eG * S00 + kGS * (T)Gl00), G01 = -sW * (eG * S01 + kGS * (T)Gl01);
+  const T G10 = G01, G11 = -sW * (eG * S11 + kGS * (T)Gl11);
 #pragma unroll
   for (int ay = 0; ay < 3; ++ay)
 #pragma unroll

@@ -55,6 +55,9 @@ struct Model {
   double sigma_max, etaD, gamma1, gamma2, qsign;
   double gamma_cip;  // CIP weight (0: off)
   int lin, convection;
+  // Dirichlet lifting of the level-0 mesh: Q2 velocity per Radau node (stride
+  // nv of that mesh), FP64, or nullptr for homogeneous data (eq. def-b-gam)
+  const double* lift;
 };
 
 struct Grid {
@@ -62,6 +65,44 @@ struct Grid {
   double hx, hy, ihx, ihy;
   int64_t nn, nc, nv, ns, nst;  // nodes, cells, velocity, spatial, space-time
 };
+
+// Frozen Nitsche coefficients of eq. def-b-gam at G = D ghat_D: eta(G) and the
+// coefficient k of the exact stress derivative DS(G)B = eta(G) B + k (G:B) G,
+// k = (p-2) nu (delta^2 + |G|^2)^((p-4)/2); for G = 0, eta_D and 0.
+__host__ __device__ inline void frozen_coef(const Model& m, double g00, double g01, double g11,
+                                            double& eta, double& k) {
+  const double D2 = m.delta2 + g00 * g00 + 2.0 * g01 * g01 + g11 * g11;
+  const double mu = m.nu * pow(D2, m.expo);
+  eta = m.nu_inf + mu;
+  k = (m.p - 2.0) * mu / D2;
+}
+
+// Value and symmetric gradient of the lifting of Radau node mu at the point
+// (xi, et) of cell (cx, cy) of the 2D level-0 mesh g.
+__device__ inline void lift_at2(const Model& m, const Grid& g, int mu, int cx, int cy, double xi,
+                                double et, double& v0, double& v1, double& G00, double& G01,
+                                double& G11) {
+  const double* gm = m.lift + (int64_t)mu * g.nv;
+  const int NX = 2 * g.nx + 1;
+  double g00 = 0.0, g01 = 0.0, g10 = 0.0, g11 = 0.0;
+  v0 = v1 = 0.0;
+  for (int ay = 0; ay < 3; ++ay)
+    for (int ax = 0; ax < 3; ++ax) {
+      const double bx = q2v(ax, xi), by = q2v(ay, et);
+      const double ph = bx * by, px = q2d(ax, xi) * g.ihx * by, py = bx * q2d(ay, et) * g.ihy;
+      const int64_t gn = (int64_t)(2 * cy + ay) * NX + (2 * cx + ax);
+      const double l0 = gm[gn], l1 = gm[g.nn + gn];
+      v0 += l0 * ph;
+      v1 += l1 * ph;
+      g00 += l0 * px;
+      g01 += l0 * py;
+      g10 += l1 * px;
+      g11 += l1 * py;
+    }
+  G00 = g00;
+  G01 = 0.5 * (g01 + g10);
+  G11 = g11;
+}
 
 inline Grid make_grid(int nx, int ny, double lx, double ly) {
   Grid g;
@@ -203,8 +244,10 @@ hipError_t launch_prolong_add3(const Grid3& gf, const Grid3& gc, const T* dc, T*
 hipError_t launch_coarse_assemble3(const Grid3& g, const double* E, double* A, hipStream_t s);
 
 // setup.hip
-hipError_t launch_element_matrices(const Grid& g, const Model& m, const double* u, double* Es,
-                                   hipStream_t s);
+// spatial cell matrices at velocity u, Nitsche coefficients frozen at the
+// lifting gl of the same time (same layout; nullptr: homogeneous data)
+hipError_t launch_element_matrices(const Grid& g, const Model& m, const double* u,
+                                   const double* gl, double* Es, hipStream_t s);
 hipError_t launch_state_combine(int64_t n, const double* u0, const double* u1, double a0,
                                 double a1, double* out, hipStream_t s);
 template <typename T>

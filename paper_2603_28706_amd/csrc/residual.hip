@@ -1,12 +1,15 @@
 // Nonlinear slab residual in FP64 (Sec. 5.2 eq. slab-underint, with f = 0 and
-// homogeneous Dirichlet data imposed by Nitsche's method, eq. def-b-gam):
-//   R_v,mu = -( sum_nu K_t[mu][nu] M_x u_nu - m_t[mu] M_x v_prev ) - tau w_mu A_gamma(U_mu)_v
-//   R_p,mu = - tau w_mu A_gamma(U_mu)_p
+// Dirichlet data imposed by Nitsche's method, eq. def-b-gam, eq. disc-residual):
+//   R_v,mu = -( sum_nu K_t[mu][nu] M_x u_nu - m_t[mu] M_x v_prev )
+//            + tau w_mu (B_gamma(g_D) - A_gamma(U_mu))_v
+//   R_p,mu = tau w_mu (B_gamma(g_D) - A_gamma(U_mu))_p
 // with the volume form S(Du):Dw - (u (x) u):grad w - (div w) pi - (div u) w_pi
 // (Sec. 3.2 eq. pns-form) and on the boundary
-//   (u.n)(u.w) - (u.n)^- (u.w) - (S(Du) n).w + pi (n.w) - eta_D (Dw n).u
-//   + q_sign (u.n) w_pi + gamma1 eta_D / h_F (u.w) + gamma2 / h_F (u.n)(w.n),
-// the inflow factor (u.n)^- evaluated at U itself.
+//   (u.n)(u.w) - (u.n)^- (u.w) - (S(Du) n).w + pi (n.w) - (DS(G)(Dw) n).u
+//   + q_sign (u.n) w_pi + gamma1 eta(G) / h_F (u.w) + gamma2 / h_F (u.n)(w.n),
+// the inflow factor (u.n)^- evaluated at U itself, G = D ghat_D of the lifting
+// (0 without one); B_gamma(g_D) is the same boundary form at the lifting's
+// trace g with its own inflow factor, so the linear Nitsche terms act on u - g.
 //
 // Same tiling as the Jacobian action: one workgroup of 256 threads per tile of
 // 15 x 7 owned cells plus the low-side halo cells, U's velocity (both Radau
@@ -71,19 +74,33 @@ __device__ __forceinline__ void residual_face_point(const Model& m, const Grid& 
   const double eta = viscosity(m, a00, a01, a11);
   const double sW = tau * (mu ? kWt[1] : kWt[0]) * wq * (xface ? g.hy : g.hx);
   const double un = X[0] * n0 + X[1] * n1;
-  const double pen1 = m.gamma1 * m.etaD * ihF, pen2 = m.gamma2 * ihF;
-  double F0 = -eta * (a00 * n0 + a01 * n1) + pi * n0 + pen1 * X[0] + pen2 * un * n0;
-  double F1 = -eta * (a01 * n0 + a11 * n1) + pi * n1 + pen1 * X[1] + pen2 * un * n1;
+  // the lifting's trace and the frozen Nitsche coefficients at its gradient
+  double l0 = 0.0, l1 = 0.0, Gl00 = 0.0, Gl01 = 0.0, Gl11 = 0.0, etaG = m.etaD, kG = 0.0;
+  if (m.lift) {
+    lift_at2(m, g, mu, cx, cy, xi, et, l0, l1, Gl00, Gl01, Gl11);
+    frozen_coef(m, Gl00, Gl01, Gl11, etaG, kG);
+  }
+  const double e0 = X[0] - l0, e1 = X[1] - l1, en = e0 * n0 + e1 * n1;  // u - g
+  const double pen1 = m.gamma1 * etaG * ihF, pen2 = m.gamma2 * ihF;
+  double F0 = -eta * (a00 * n0 + a01 * n1) + pi * n0 + pen1 * e0 + pen2 * en * n0;
+  double F1 = -eta * (a01 * n0 + a11 * n1) + pi * n1 + pen1 * e1 + pen2 * en * n1;
   if (m.convection) {
     const double neg = 0.5 * (fabs(un) - un);
     F0 += (un - neg) * X[0];
     F1 += (un - neg) * X[1];
+    const double ln = l0 * n0 + l1 * n1;   // B^c(g_D, w) of the right-hand side
+    const double lneg = 0.5 * (fabs(ln) - ln);
+    F0 += lneg * l0;
+    F1 += lneg * l1;
   }
   F0 *= sW;
   F1 *= sW;
-  const double c = -sW * m.etaD * 0.5;
-  const double G00 = c * (2.0 * X[0] * n0), G01 = c * (X[0] * n1 + X[1] * n0);
-  const double G10 = G01, G11 = c * (2.0 * X[1] * n1);
+  // -(DS(G)(Dw) n).(u - g): coefficient of d_j w_i, -(eta(G) S + k (G:S) G)_ij,
+  // S = sym((u - g) (x) n)
+  const double S00 = e0 * n0, S01 = 0.5 * (e0 * n1 + e1 * n0), S11 = e1 * n1;
+  const double kGS = kG * (Gl00 * S00 + 2.0 * Gl01 * S01 + Gl11 * S11);
+  const double G00 = -sW * (etaG * S00 + kGS * Gl00), G01 = -sW * (etaG * S01 + kGS * Gl01);
+  const double G10 = G01, G11 = -sW * (etaG * S11 + kGS * Gl11);
 #pragma unroll
   for (int ay = 0; ay < 3; ++ay)
 #pragma unroll
@@ -93,7 +110,7 @@ __device__ __forceinline__ void residual_face_point(const Model& m, const Grid& 
       atomicAdd(&acc[2 * mu + 1][ly0 + ay][lx0 + ax], F1 * ph + G10 * px + G11 * py);
     }
   if (pa) {
-    const double P = sW * m.qsign * un;
+    const double P = sW * m.qsign * en;
     atomicAdd(&pa[0], P);
     atomicAdd(&pa[1], P * (xi - 0.5));
     atomicAdd(&pa[2], P * (et - 0.5));

@@ -41,6 +41,8 @@ __device__ __forceinline__ double cell_mass(const Grid& g, int a, int b) {
 struct Pt {
   double xi, et, W, n0, n1, hF;  // reference point, weight, normal (0 inside)
   double u0, u1, a00, a01, a11, eta, kap;
+  // boundary points: frozen Nitsche coefficients at G = D ghat_D
+  double G00, G01, G11, etaG, kG;
 };
 
 struct Fld {
@@ -100,18 +102,26 @@ __device__ double pair_integrand(const Model& m, const Pt& P, const Fld& x, cons
       s -= 0.5 * (fabs(un) - un) * xw;
     }
     s -= (T00 * n0 + T01 * n1) * w.v0 + (T01 * n0 + T11 * n1) * w.v1;
-    s -= m.etaD * ((d00 * n0 + d01 * n1) * x.v0 + (d01 * n0 + d11 * n1) * x.v1);
+    // -(DS(G)(Dw) n).x, DS(G)(Dw) = eta(G) Dw + k (G:Dw) G
+    const double gd = P.G00 * d00 + 2.0 * P.G01 * d01 + P.G11 * d11;
+    const double e00 = P.etaG * d00 + P.kG * gd * P.G00;
+    const double e01 = P.etaG * d01 + P.kG * gd * P.G01;
+    const double e11 = P.etaG * d11 + P.kG * gd * P.G11;
+    s -= (e00 * n0 + e01 * n1) * x.v0 + (e01 * n0 + e11 * n1) * x.v1;
     s += x.q * wn;
     s += m.qsign * xn * w.q;
-    s += m.gamma1 * m.etaD / P.hF * xw + m.gamma2 / P.hF * xn * wn;
+    s += m.gamma1 * P.etaG / P.hF * xw + m.gamma2 / P.hF * xn * wn;
   }
   return P.W * s;
 }
 
+// gl: the Dirichlet lifting at the same time as u (same layout), or nullptr
 __global__ __launch_bounds__(256) void element_matrix_kernel(Grid g, Model m,
                                                              const double* __restrict__ u,
+                                                             const double* __restrict__ gl,
                                                              double* __restrict__ Es) {
   __shared__ double ul[18];
+  __shared__ double gll[18];
   __shared__ Pt pts[21];
   const int64_t cell = blockIdx.x;
   const int cx = (int)(cell % g.nx), cy = (int)(cell / g.nx);
@@ -119,7 +129,9 @@ __global__ __launch_bounds__(256) void element_matrix_kernel(Grid g, Model m,
   const int NX = 2 * g.nx + 1;
   if (t < 18) {
     const int comp = t / 9, a = t % 9;
-    ul[t] = u[(int64_t)comp * g.nn + (int64_t)(2 * cy + a / 3) * NX + 2 * cx + a % 3];
+    const int64_t gi = (int64_t)comp * g.nn + (int64_t)(2 * cy + a / 3) * NX + 2 * cx + a % 3;
+    ul[t] = u[gi];
+    gll[t] = gl ? gl[gi] : 0.0;
   }
   // point list: 9 volume points, then 3 per boundary face
   int nfaces = 0;
@@ -172,6 +184,23 @@ __global__ __launch_bounds__(256) void element_matrix_kernel(Grid g, Model m,
       }
     }
     P.kap = k;
+    P.G00 = P.G01 = P.G11 = 0.0;
+    P.etaG = m.etaD;
+    P.kG = 0.0;
+    if (gl && t >= 9) {
+      double h00 = 0, h01 = 0, h10 = 0, h11 = 0;
+      for (int a = 0; a < 9; ++a) {
+        const int ax = a % 3, ay = a / 3;
+        const double px = q2d(ax, P.xi) / g.hx * q2v(ay, P.et);
+        const double py = q2v(ax, P.xi) * q2d(ay, P.et) / g.hy;
+        h00 += gll[a] * px; h01 += gll[a] * py;
+        h10 += gll[9 + a] * px; h11 += gll[9 + a] * py;
+      }
+      P.G00 = h00;
+      P.G01 = 0.5 * (h01 + h10);
+      P.G11 = h11;
+      frozen_coef(m, P.G00, P.G01, P.G11, P.etaG, P.kG);
+    }
     pts[t] = P;
   }
   __syncthreads();
@@ -830,9 +859,10 @@ hipError_t launch_form_fine_st(const Grid& g, double tau, const double* Es0, con
   return hipGetLastError();
 }
 
-hipError_t launch_element_matrices(const Grid& g, const Model& m, const double* u, double* Es,
-                                   hipStream_t s) {
-  hipLaunchKernelGGL(element_matrix_kernel, dim3((unsigned)g.nc), dim3(256), 0, s, g, m, u, Es);
+hipError_t launch_element_matrices(const Grid& g, const Model& m, const double* u,
+                                   const double* gl, double* Es, hipStream_t s) {
+  hipLaunchKernelGGL(element_matrix_kernel, dim3((unsigned)g.nc), dim3(256), 0, s, g, m, u, gl,
+                     Es);
   return hipGetLastError();
 }
 

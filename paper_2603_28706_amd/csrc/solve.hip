@@ -287,6 +287,7 @@ int pns_residual(pns_ctx* ctx, const pns_model* md, const double* U, const doubl
   if (rc != PNS_OK) return rc;
   if (ctx->dim == 3 && m.gamma_cip > 0.0)
     return fail(ctx, PNS_EUNSUPPORTED, "CIP stabilisation is built for quadrilaterals only");
+  m.lift = ctx->lift;
   if (ctx->dim == 3) {
     const int rc = residual3d(ctx, m, U, vprev, R);
     if (rc != PNS_OK) return rc;
@@ -328,6 +329,7 @@ int pns_solve(pns_ctx* ctx, const pns_model* md, const double* vprev, double* U,
   S.md = md;
   int rc = make_model(md, &S.model, &ctx->err);
   if (rc != PNS_OK) return rc;
+  S.model.lift = ctx->lift;
   S.vprev = vprev;
   S.g = ctx->lev[0].g;
   S.s = ctx->stream;

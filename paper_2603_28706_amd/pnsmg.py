@@ -130,6 +130,7 @@ def lib():
         L.pns_residual.argtypes = [_vp, pp(pns_model), _vp, _vp, _vp]
         L.pns_load_vector.argtypes = [_vp, _vp, _vp]
         L.pns_set_load.argtypes = [_vp, _vp]
+        L.pns_set_dirichlet.argtypes = [_vp, _vp]
         L.pns_solve_workspace_bytes.argtypes = [_vp, i]
         L.pns_solve_workspace_bytes.restype = ctypes.c_size_t
         L.pns_solve.argtypes = [_vp, pp(pns_model), _vp, _vp, pp(pns_solve_params), _vp,
@@ -327,6 +328,17 @@ class Context:
             return
         self._load = F
         self._check(lib().pns_set_load(self.h, self._f64(F, self.sizes(0)["nst"])))
+
+    def pns_set_dirichlet(self, ghat):
+        """Dirichlet data from a lifting: FP64 device tensor of 2 N_v values (the
+        Q2 velocity field at each Radau node; kept alive by the caller); None:
+        homogeneous data."""
+        if ghat is None:
+            self._lift = None
+            self._check(lib().pns_set_dirichlet(self.h, None))
+            return
+        self._lift = ghat
+        self._check(lib().pns_set_dirichlet(self.h, self._f64(ghat, 2 * self.sizes(0)["nv"])))
 
     def pns_solve_workspace_bytes(self, restart):
         return lib().pns_solve_workspace_bytes(self.h, int(restart))
