@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpnsmg.so")
 SOURCES = ["api.hip", "apply.hip", "apply3d.hip", "setup.hip", "smooth3d.hip", "mg3d.hip", "smooth.hip", "residual.hip", "krylov.hip",
-           "solve.hip", "serve.hip", "load.hip", "cip.hip"]
+           "solve.hip", "serve.hip", "load.hip", "cip.hip", "lift.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-munsafe-fp-atomics",

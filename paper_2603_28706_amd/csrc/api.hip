@@ -89,7 +89,8 @@ size_t layout(pns_ctx* c, bool bind) {
     return (off + kAlign - 1) / kAlign * kAlign;
   }
   c->urep = (double*)take(g0.nv * 8);
-  c->lrep = (double*)take(g0.nv * 8);
+  c->ltab = (double*)take(lift_table_doubles(g0) * 8);
+  c->ltab_r = (double*)take(lift_table_doubles(g0) * 8);
   c->Es0 = (double*)take(g0.nc * kNs * kNs * 8);
   c->Es1 = (double*)take(g0.nc * kNs * kNs * 8);
   c->Esr = (double*)take(g0.nc * kNs * kNs * 8);
@@ -437,16 +438,11 @@ int vanka_setup_impl(pns_ctx* c, const uint16_t* masks) {
   }
   const double* u0 = c->uk64;
   const double* u1 = c->uk64 + L0.g.nv;
-  // Nitsche coefficients frozen at the lifting of each Radau node, at t_rep for
-  // the surrogate patches
-  const double* gl0 = c->lift;
-  const double* gl1 = c->lift ? c->lift + L0.g.nv : nullptr;
-  if (c->lift)
-    PNS_HIP(c, launch_state_combine(L0.g.nv, gl0, gl1, kXiMid[0], kXiMid[1], c->lrep, s));
-  PNS_HIP(c, launch_element_matrices(L0.g, c->model, u0, gl0, c->Es0, s));
-  PNS_HIP(c, launch_element_matrices(L0.g, c->model, u1, gl1, c->Es1, s));
-  PNS_HIP(c, launch_element_matrices(L0.g, c->model, c->urep, c->lift ? c->lrep : nullptr,
-                                     c->Esr, s));
+  // with Dirichlet data, the Nitsche coefficients of each Radau node's lifting,
+  // and at t_rep for the surrogate patches (time slots 0, 1, 2 of the table)
+  PNS_HIP(c, launch_element_matrices(L0.g, c->model, u0, 0, c->Es0, s));
+  PNS_HIP(c, launch_element_matrices(L0.g, c->model, u1, 1, c->Es1, s));
+  PNS_HIP(c, launch_element_matrices(L0.g, c->model, c->urep, 2, c->Esr, s));
   // CIP face matrices: at each Radau node's velocity (level-0 operator, with
   // tau w_mu) and at t_rep (time-diagonal patches, unscaled)
   const bool cip = c->model.gamma_cip > 0.0;
@@ -791,6 +787,7 @@ int pns_bind_workspace(pns_ctx* ctx, void* ws, size_t bytes) {
   ctx->drop_graph();
   layout(ctx, true);
   ctx->has_state = ctx->has_smoother = false;
+  ctx->model.lift = nullptr;  // the boundary tables moved with the workspace
   return PNS_OK;
 }
 
@@ -802,7 +799,11 @@ int pns_set_state(pns_ctx* ctx, const pns_model* md, const double* u_k) {
   if (rc != PNS_OK) return rc;
   if (ctx->dim == 3 && m.gamma_cip > 0.0)
     return fail(ctx, PNS_EUNSUPPORTED, "CIP stabilisation is built for quadrilaterals only");
-  m.lift = ctx->lift;
+  m.lift = nullptr;
+  if (ctx->lift) {
+    PNS_HIP(ctx, launch_lift_table(ctx->lev[0].g, m, ctx->lift, ctx->ltab, ctx->stream));
+    m.lift = ctx->ltab;
+  }
   ctx->model = m;
   ctx->drop_graph();
   const Grid& g0 = ctx->lev[0].g;
@@ -901,8 +902,13 @@ int pns_set_dirichlet(pns_ctx* ctx, const double* ghat) {
   if (!ctx) return PNS_EINVAL;
   if (ghat && ctx->dim == 3)
     return fail(ctx, PNS_EUNSUPPORTED, "inhomogeneous Dirichlet data is built for quadrilaterals");
+  if (ghat && !ctx->ws) return fail(ctx, PNS_EWORKSPACE, "no workspace bound");
   ctx->lift = ghat;
-  ctx->model.lift = ghat;
+  ctx->model.lift = nullptr;
+  if (ghat && ctx->has_state) {  // the action sees the data at once
+    PNS_HIP(ctx, launch_lift_table(ctx->lev[0].g, ctx->model, ghat, ctx->ltab, ctx->stream));
+    ctx->model.lift = ctx->ltab;
+  }
   ctx->drop_graph();
   ctx->has_smoother = false;  // the patches and coarse operators depend on it
   return PNS_OK;

@@ -148,12 +148,16 @@ __device__ __forceinline__ void face_point(const Model& m, const Grid& g, double
   const double xi = xface ? (side == 0 ? 0.0 : 1.0) : gq;
   const double et = xface ? gq : (side == 2 ? 0.0 : 1.0);
   const double ihF = xface ? g.ihx : g.ihy;  // 1 / h_F, h_F the cell size normal to the face
-  // frozen Nitsche coefficients at G = D ghat_D (G = 0: eta_D, no rank-one part)
+  // frozen Nitsche coefficients at G = D ghat_D from the boundary table (no
+  // data: eta_D, no rank-one part)
   double Gl00 = 0.0, Gl01 = 0.0, Gl11 = 0.0, etaG = m.etaD, kG = 0.0;
   if (m.lift) {
-    double l0, l1;
-    lift_at2(m, g, mu, cx, cy, xi, et, l0, l1, Gl00, Gl01, Gl11);
-    frozen_coef(m, Gl00, Gl01, Gl11, etaG, kG);
+    const double* lt = m.lift + lift_index(g, side, xface ? cy : cx, q, mu);
+    Gl00 = lt[2];
+    Gl01 = lt[3];
+    Gl11 = lt[4];
+    etaG = lt[5];
+    kG = lt[6];
   }
   const T pen1 = (T)(m.gamma1 * etaG * ihF);
   const T pen2 = (T)(m.gamma2 * ihF);

@@ -83,10 +83,12 @@ struct pns_ctx {
   float sweep_ms[16][16] = {};
   // volume-force vector added to every slab residual (pns_set_load), or NULL
   const double* load = nullptr;
-  // Dirichlet lifting per Radau node (pns_set_dirichlet), or NULL; its value at
-  // the slab midpoint for the surrogate patches (2D)
+  // Dirichlet lifting per Radau node (pns_set_dirichlet, caller-owned), or NULL;
+  // its boundary tables (2D): for the state's model (action, smoother) and for
+  // the model of the last residual evaluation
   const double* lift = nullptr;
-  double* lrep = nullptr;
+  double* ltab = nullptr;
+  double* ltab_r = nullptr;
   // pns_solve's Jacobian action with x and u_k stored in BF16 (3D FP32
   // contexts, pns_set_jacobian_precision)
   bool jac_bf16 = false;

@@ -55,8 +55,8 @@ struct Model {
   double sigma_max, etaD, gamma1, gamma2, qsign;
   double gamma_cip;  // CIP weight (0: off)
   int lin, convection;
-  // Dirichlet lifting of the level-0 mesh: Q2 velocity per Radau node (stride
-  // nv of that mesh), FP64, or nullptr for homogeneous data (eq. def-b-gam)
+  // Dirichlet data of the level-0 mesh as a table over its boundary face points
+  // (launch_lift_table), or nullptr for homogeneous data (eq. def-b-gam)
   const double* lift;
 };
 
@@ -77,31 +77,19 @@ __host__ __device__ inline void frozen_coef(const Model& m, double g00, double g
   k = (m.p - 2.0) * mu / D2;
 }
 
-// Value and symmetric gradient of the lifting of Radau node mu at the point
-// (xi, et) of cell (cx, cy) of the 2D level-0 mesh g.
-__device__ inline void lift_at2(const Model& m, const Grid& g, int mu, int cx, int cy, double xi,
-                                double et, double& v0, double& v1, double& G00, double& G01,
-                                double& G11) {
-  const double* gm = m.lift + (int64_t)mu * g.nv;
-  const int NX = 2 * g.nx + 1;
-  double g00 = 0.0, g01 = 0.0, g10 = 0.0, g11 = 0.0;
-  v0 = v1 = 0.0;
-  for (int ay = 0; ay < 3; ++ay)
-    for (int ax = 0; ax < 3; ++ax) {
-      const double bx = q2v(ax, xi), by = q2v(ay, et);
-      const double ph = bx * by, px = q2d(ax, xi) * g.ihx * by, py = bx * q2d(ay, et) * g.ihy;
-      const int64_t gn = (int64_t)(2 * cy + ay) * NX + (2 * cx + ax);
-      const double l0 = gm[gn], l1 = gm[g.nn + gn];
-      v0 += l0 * ph;
-      v1 += l1 * ph;
-      g00 += l0 * px;
-      g01 += l0 * py;
-      g10 += l1 * px;
-      g11 += l1 * py;
-    }
-  G00 = g00;
-  G01 = 0.5 * (g01 + g10);
-  G11 = g11;
+// Dirichlet data at the boundary face points of the 2D level-0 mesh: per
+// point (side 0: x = lo, 1: x = hi, 2: y = lo, 3: y = hi; cell j along the
+// side; Gauss point q) and time slot s (0, 1: the Radau nodes, 2: the slab
+// midpoint t_rep), kLiftVals values: the lifting's value (g0, g1), its
+// symmetric gradient G (G00, G01, G11) and the frozen coefficients eta(G),
+// k(G) of frozen_coef.
+constexpr int kLiftVals = 7;
+__host__ __device__ inline int64_t lift_index(const Grid& g, int side, int j, int q, int s) {
+  const int L = g.nx > g.ny ? g.nx : g.ny;
+  return ((((int64_t)side * L + j) * 3 + q) * 3 + s) * kLiftVals;
+}
+inline int64_t lift_table_doubles(const Grid& g) {
+  return lift_index(g, 4, 0, 0, 0);
 }
 
 inline Grid make_grid(int nx, int ny, double lx, double ly) {
@@ -244,10 +232,11 @@ hipError_t launch_prolong_add3(const Grid3& gf, const Grid3& gc, const T* dc, T*
 hipError_t launch_coarse_assemble3(const Grid3& g, const double* E, double* A, hipStream_t s);
 
 // setup.hip
-// spatial cell matrices at velocity u, Nitsche coefficients frozen at the
-// lifting gl of the same time (same layout; nullptr: homogeneous data)
-hipError_t launch_element_matrices(const Grid& g, const Model& m, const double* u,
-                                   const double* gl, double* Es, hipStream_t s);
+// spatial cell matrices at velocity u; with Dirichlet data (m.lift) the
+// Nitsche coefficients of time slot lslot of its table (0, 1: Radau nodes, 2:
+// the slab midpoint)
+hipError_t launch_element_matrices(const Grid& g, const Model& m, const double* u, int lslot,
+                                   double* Es, hipStream_t s);
 hipError_t launch_state_combine(int64_t n, const double* u0, const double* u1, double a0,
                                 double a1, double* out, hipStream_t s);
 template <typename T>
@@ -321,6 +310,11 @@ hipError_t launch_residual(const Grid& g, const Model& m, double tau, const doub
 hipError_t launch_load2(const Grid& g, double tau, const double* f_qp, double* F, hipStream_t s);
 hipError_t launch_load3(const Grid3& g, double tau, const double* f_qp, double* F, hipStream_t s);
 hipError_t launch_add(int64_t n, const double* x, double* y, hipStream_t s);
+
+// lift.hip: the boundary table of the Dirichlet data (see lift_index) from a
+// lifting given as a Q2 velocity field per Radau node (stride g.nv)
+hipError_t launch_lift_table(const Grid& g, const Model& m, const double* ghat, double* table,
+                             hipStream_t s);
 
 // cip.hip: CIP stabilisation on the interior faces of a quadrilateral mesh,
 // y += sign * tau w_mu s_CIP(uw_mu; x_mu, .) (sign = +1 action, -1 defect /

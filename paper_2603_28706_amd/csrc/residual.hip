@@ -77,8 +77,14 @@ __device__ __forceinline__ void residual_face_point(const Model& m, const Grid& 
   // the lifting's trace and the frozen Nitsche coefficients at its gradient
   double l0 = 0.0, l1 = 0.0, Gl00 = 0.0, Gl01 = 0.0, Gl11 = 0.0, etaG = m.etaD, kG = 0.0;
   if (m.lift) {
-    lift_at2(m, g, mu, cx, cy, xi, et, l0, l1, Gl00, Gl01, Gl11);
-    frozen_coef(m, Gl00, Gl01, Gl11, etaG, kG);
+    const double* lt = m.lift + lift_index(g, side, xface ? cy : cx, q, mu);
+    l0 = lt[0];
+    l1 = lt[1];
+    Gl00 = lt[2];
+    Gl01 = lt[3];
+    Gl11 = lt[4];
+    etaG = lt[5];
+    kG = lt[6];
   }
   const double e0 = X[0] - l0, e1 = X[1] - l1, en = e0 * n0 + e1 * n1;  // u - g
   const double pen1 = m.gamma1 * etaG * ihF, pen2 = m.gamma2 * ihF;

@@ -115,13 +115,13 @@ __device__ double pair_integrand(const Model& m, const Pt& P, const Fld& x, cons
   return P.W * s;
 }
 
-// gl: the Dirichlet lifting at the same time as u (same layout), or nullptr
+// lslot: time slot of the Dirichlet data table (m.lift) matching u (0, 1: the
+// Radau nodes, 2: the slab midpoint); ignored without data
 __global__ __launch_bounds__(256) void element_matrix_kernel(Grid g, Model m,
                                                              const double* __restrict__ u,
-                                                             const double* __restrict__ gl,
+                                                             int lslot,
                                                              double* __restrict__ Es) {
   __shared__ double ul[18];
-  __shared__ double gll[18];
   __shared__ Pt pts[21];
   const int64_t cell = blockIdx.x;
   const int cx = (int)(cell % g.nx), cy = (int)(cell / g.nx);
@@ -129,9 +129,7 @@ __global__ __launch_bounds__(256) void element_matrix_kernel(Grid g, Model m,
   const int NX = 2 * g.nx + 1;
   if (t < 18) {
     const int comp = t / 9, a = t % 9;
-    const int64_t gi = (int64_t)comp * g.nn + (int64_t)(2 * cy + a / 3) * NX + 2 * cx + a % 3;
-    ul[t] = u[gi];
-    gll[t] = gl ? gl[gi] : 0.0;
+    ul[t] = u[(int64_t)comp * g.nn + (int64_t)(2 * cy + a / 3) * NX + 2 * cx + a % 3];
   }
   // point list: 9 volume points, then 3 per boundary face
   int nfaces = 0;
@@ -187,19 +185,14 @@ __global__ __launch_bounds__(256) void element_matrix_kernel(Grid g, Model m,
     P.G00 = P.G01 = P.G11 = 0.0;
     P.etaG = m.etaD;
     P.kG = 0.0;
-    if (gl && t >= 9) {
-      double h00 = 0, h01 = 0, h10 = 0, h11 = 0;
-      for (int a = 0; a < 9; ++a) {
-        const int ax = a % 3, ay = a / 3;
-        const double px = q2d(ax, P.xi) / g.hx * q2v(ay, P.et);
-        const double py = q2v(ax, P.xi) * q2d(ay, P.et) / g.hy;
-        h00 += gll[a] * px; h01 += gll[a] * py;
-        h10 += gll[9 + a] * px; h11 += gll[9 + a] * py;
-      }
-      P.G00 = h00;
-      P.G01 = 0.5 * (h01 + h10);
-      P.G11 = h11;
-      frozen_coef(m, P.G00, P.G01, P.G11, P.etaG, P.kG);
+    if (m.lift && t >= 9) {
+      const int side = faces[(t - 9) / 3];
+      const double* lt = m.lift + lift_index(g, side, side < 2 ? cy : cx, (t - 9) % 3, lslot);
+      P.G00 = lt[2];
+      P.G01 = lt[3];
+      P.G11 = lt[4];
+      P.etaG = lt[5];
+      P.kG = lt[6];
     }
     pts[t] = P;
   }
@@ -859,9 +852,9 @@ hipError_t launch_form_fine_st(const Grid& g, double tau, const double* Es0, con
   return hipGetLastError();
 }
 
-hipError_t launch_element_matrices(const Grid& g, const Model& m, const double* u,
-                                   const double* gl, double* Es, hipStream_t s) {
-  hipLaunchKernelGGL(element_matrix_kernel, dim3((unsigned)g.nc), dim3(256), 0, s, g, m, u, gl,
+hipError_t launch_element_matrices(const Grid& g, const Model& m, const double* u, int lslot,
+                                   double* Es, hipStream_t s) {
+  hipLaunchKernelGGL(element_matrix_kernel, dim3((unsigned)g.nc), dim3(256), 0, s, g, m, u, lslot,
                      Es);
   return hipGetLastError();
 }

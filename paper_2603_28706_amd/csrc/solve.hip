@@ -287,7 +287,11 @@ int pns_residual(pns_ctx* ctx, const pns_model* md, const double* U, const doubl
   if (rc != PNS_OK) return rc;
   if (ctx->dim == 3 && m.gamma_cip > 0.0)
     return fail(ctx, PNS_EUNSUPPORTED, "CIP stabilisation is built for quadrilaterals only");
-  m.lift = ctx->lift;
+  m.lift = nullptr;
+  if (ctx->lift) {
+    PNS_HIP(ctx, launch_lift_table(ctx->lev[0].g, m, ctx->lift, ctx->ltab_r, ctx->stream));
+    m.lift = ctx->ltab_r;
+  }
   if (ctx->dim == 3) {
     const int rc = residual3d(ctx, m, U, vprev, R);
     if (rc != PNS_OK) return rc;
@@ -329,7 +333,11 @@ int pns_solve(pns_ctx* ctx, const pns_model* md, const double* vprev, double* U,
   S.md = md;
   int rc = make_model(md, &S.model, &ctx->err);
   if (rc != PNS_OK) return rc;
-  S.model.lift = ctx->lift;
+  S.model.lift = nullptr;
+  if (ctx->lift) {
+    PNS_HIP(ctx, launch_lift_table(ctx->lev[0].g, S.model, ctx->lift, ctx->ltab_r, ctx->stream));
+    S.model.lift = ctx->ltab_r;
+  }
   S.vprev = vprev;
   S.g = ctx->lev[0].g;
   S.s = ctx->stream;
