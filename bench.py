@@ -503,6 +503,34 @@ def solve_latency(n, seeds, rtol=1e-8):
     return out
 
 
+def exact_setup3d(n=32, reps=3):
+    """Time of the FP64 smoother setup with exact finest-level patches on n^3
+    hexahedra, 4 levels (the setup a 3D slab-solve refresh repeats): cell
+    matrices, n^3 level-0 170 x 170 patch inversions (blocked Gauss-Jordan on
+    the FP64 matrix cores), Galerkin products, coarse patches, the dense
+    coarsest inverse.  State: the 3D sin-series velocity (seed 301)."""
+    import torch
+
+    from paper_2603_28706_amd import inputs, pnsmg
+
+    ctx = pnsmg.Context((n, n, n), n_levels=4, precision=pnsmg.FP64, patch_kind=pnsmg.PATCH_EXACT)
+    uk = torch.tensor(inputs.sin_series_velocity((n, n, n), seed=301,
+                                                 t_nodes=[0.01 / 3, 0.01]), device="cuda")
+    ctx.pns_set_state(dict(MODEL3D, lin=2), uk)
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.pns_vanka_setup()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    print(f"[bench] exact 3D setup {n}^3: {[round(t * 1e3, 1) for t in ts]} ms", file=sys.stderr,
+          flush=True)
+    del ctx
+    torch.cuda.empty_cache()
+    return dict(patches_level0=n ** 3, setup_ms_median=round(1e3 * sorted(ts)[len(ts) // 2], 2))
+
+
 def solve3d_latency(n=32, rtol=1e-8, max_newton=60, rho=0.9):
     """Time to rtol of the 3D slab solve on n^3 hexahedra (the 3D workload:
     p = 1.3, delta = 1e-3, nu = 1, nu_inf = 1e-3, modified Newton, left trace
@@ -716,11 +744,16 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain streaming kernel of known size (counter calibration)")
     ap.add_argument("--lin", type=int, default=2, help="0 Picard, 1 exact Newton, 2 modified Newton")
+    ap.add_argument("--setup3d-only", action="store_true",
+                    help="only time --steps exact-patch 3D setups (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.setup3d_only:
+        print(json.dumps({"exact_setup3d": exact_setup3d(32, max(1, args.steps))}), flush=True)
+        return
     res = run(args)
     f64, f32 = res["fp64"], res["fp32"]
     t_ap = f64["apply_s_mean"]
@@ -778,6 +811,11 @@ def main():
             **{k: ({kk: round(vv, 4) for kk, vv in v.items()} if isinstance(v, dict) else v)
                for k, v in a3.items()}}
     if args.solve3d_n and not args.apply_only:
+        line["exact_setup3d"] = {
+            "workload": (f"FP64 4-level smoother setup with exact finest-level patches on "
+                         f"{args.solve3d_n}^3 hexahedra (170 x 170 patch inversions on the "
+                         f"FP64 matrix cores), the 3D workload's state"),
+            **exact_setup3d(args.solve3d_n)}
         s3 = solve3d_latency(args.solve3d_n)
         line["solve3d_time_to_1e-8_s"] = {
             "workload": (f"3D {args.solve3d_n}^3 slab solve, p=1.3 delta=1e-3 nu0=1 nu_inf=1e-3, "
