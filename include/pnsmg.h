@@ -212,10 +212,20 @@ int pns_set_jacobian_precision(pns_ctx* ctx, int precision);
  * convection, pressure coupling, boundary flux and Nitsche terms) at u_k of
  * Radau node mu.  Matrix-free; x, y in the context precision, canonical
  * layout, must not alias.  On quadrilaterals the cell contributions inside
- * a tile are summed with LDS atomics, so the last bits of y may vary from
- * call to call; on hexahedra every sum has a fixed order (bitwise
- * reproducible). */
+ * a tile are summed with LDS atomics by default, so the last bits of y may
+ * vary from call to call (pns_set_reproducible selects a fixed order); on
+ * hexahedra every sum has a fixed order (bitwise reproducible). */
 int pns_cell_apply(pns_ctx* ctx, const void* x_dev, void* y_dev);
+
+/* Summation order of the quadrilateral action, defect and FP64 residual
+ * (a property of the implementation, not of the method): on = 1 sums the
+ * cell contributions of each tile in a fixed order (the four parity classes
+ * of cells one after the other, boundary faces side by side), so repeated
+ * calls on the same inputs give bitwise equal results; on = 0 (the default)
+ * uses LDS atomics, which is faster.  Both agree with the oracle to rounding.
+ * Hexahedral contexts always sum in a fixed order.  PNS_EINVAL for on other
+ * than 0 or 1. */
+int pns_set_reproducible(pns_ctx* ctx, int on);
 
 /* Same operator as pns_cell_apply, y = b - J_n x (the global defect). */
 int pns_cell_defect(pns_ctx* ctx, const void* b_dev, const void* x_dev, void* y_dev);
@@ -374,9 +384,13 @@ int pns_set_load(pns_ctx* ctx, const double* F_dev);
  * the patches and the Galerkin coarse operators (the surrogate patches take
  * the lifting at the slab midpoint); the residual adds B_gamma(g_D, .) (inflow,
  * symmetry and penalty terms at the trace).  NULL (the default): homogeneous
- * data, eta_D = eta(0).  A smoother built before the call is invalidated
- * (pns_vanka_setup again).  Quadrilaterals only: PNS_EUNSUPPORTED on a
- * hexahedral context.  Serving requests use homogeneous data. */
+ * data, eta_D = eta(0).  The lifting is evaluated at the boundary face points
+ * (a small table in the workspace) for the model of pns_set_state and of each
+ * pns_residual / pns_solve call, so it is read again at each of those calls.
+ * A smoother built before the call is invalidated (pns_vanka_setup again).
+ * Needs a bound workspace (PNS_EWORKSPACE); rebinding one clears the state, not
+ * the registration.  Quadrilaterals only: PNS_EUNSUPPORTED on a hexahedral
+ * context.  Serving requests use homogeneous data. */
 int pns_set_dirichlet(pns_ctx* ctx, const double* ghat_dev);
 
 /* Parameters of pns_solve. */

@@ -673,7 +673,8 @@ int pns::make_model(const pns_model* md, Model* m, std::string* err) {
   m->lin = md->lin;
   m->convection = md->convection ? 1 : 0;
   m->gamma_cip = md->gamma_cip;
-  m->lift = nullptr;  // the context's lifting is attached by the caller
+  m->lift = nullptr;  // the context's lifting and summation mode are attached by the caller
+  m->ordered = 0;
   return PNS_OK;
 }
 
@@ -804,6 +805,7 @@ int pns_set_state(pns_ctx* ctx, const pns_model* md, const double* u_k) {
     PNS_HIP(ctx, launch_lift_table(ctx->lev[0].g, m, ctx->lift, ctx->ltab, ctx->stream));
     m.lift = ctx->ltab;
   }
+  m.ordered = ctx->ordered ? 1 : 0;
   ctx->model = m;
   ctx->drop_graph();
   const Grid& g0 = ctx->lev[0].g;
@@ -895,6 +897,15 @@ int pns_load_vector(pns_ctx* ctx, const double* f_qp, double* F) {
 int pns_set_load(pns_ctx* ctx, const double* F) {
   if (!ctx) return PNS_EINVAL;
   ctx->load = F;
+  return PNS_OK;
+}
+
+int pns_set_reproducible(pns_ctx* ctx, int on) {
+  if (!ctx) return PNS_EINVAL;
+  if (on != 0 && on != 1) return fail(ctx, PNS_EINVAL, "on must be 0 or 1");
+  ctx->ordered = on == 1;
+  ctx->model.ordered = on;
+  ctx->drop_graph();
   return PNS_OK;
 }
 

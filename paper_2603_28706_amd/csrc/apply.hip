@@ -132,7 +132,7 @@ __device__ __forceinline__ double swap_pair(double v) {
 // penalties (eq. def-b-gam).  The test coefficients are contracted against the
 // 9 nodes of the cell and added to the tile's LDS sums (velocity: acc, at the
 // cell's node box offset lx0 / ly0; pressure: pa, or nothing for pa == nullptr).
-template <typename T, int LIN, bool CONV>
+template <typename T, int LIN, bool CONV, bool ATOMIC>
 __device__ __forceinline__ void face_point(const Model& m, const Grid& g, double tau, int side,
                                            int q, int mu, int cx, int cy, const T (*Xs)[BY][BX],
                                            int lx0, int ly0, const T* __restrict__ uk,
@@ -241,14 +241,15 @@ __device__ __forceinline__ void face_point(const Model& m, const Grid& g, double
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       const T ph = vx[ax] * vy[ay], px = dx[ax] * vy[ay], py = vx[ax] * dy[ay];
-      atomicAdd(&acc[2 * mu][ly0 + ay][lx0 + ax], (double)(F0 * ph + G00 * px + G01 * py));
-      atomicAdd(&acc[2 * mu + 1][ly0 + ay][lx0 + ax], (double)(F1 * ph + G10 * px + G11 * py));
+      lds_add<ATOMIC>(&acc[2 * mu][ly0 + ay][lx0 + ax], (double)(F0 * ph + G00 * px + G01 * py));
+      lds_add<ATOMIC>(&acc[2 * mu + 1][ly0 + ay][lx0 + ax],
+                      (double)(F1 * ph + G10 * px + G11 * py));
     }
   if (pa) {
     const T P = sW * (T)m.qsign * xn;
-    atomicAdd(&pa[0], (double)P);
-    atomicAdd(&pa[1], (double)(P * (T)(xi - 0.5)));
-    atomicAdd(&pa[2], (double)(P * (T)(et - 0.5)));
+    lds_add<ATOMIC>(&pa[0], (double)P);
+    lds_add<ATOMIC>(&pa[1], (double)(P * (T)(xi - 0.5)));
+    lds_add<ATOMIC>(&pa[2], (double)(P * (T)(et - 0.5)));
   }
 }
 
@@ -297,7 +298,9 @@ __global__ __launch_bounds__(256) void tangent_cache_kernel(Grid g, Model m, dou
   c[5] = (T)(sW * U1);
 }
 
-template <typename T, int LIN, bool CONV, int MODE, bool CACHED>
+// ORDERED: the cell contributions of a tile sum in a fixed order (parity
+// classes one after the other, faces side by side) instead of with LDS atomics
+template <typename T, int LIN, bool CONV, int MODE, bool CACHED, bool ORDERED>
 __global__ __launch_bounds__(kThreads, (waves_per_simd<T, CACHED>())) void cell_apply_kernel(Grid g, Model m, double tau,
                                                               const T* __restrict__ uk,
                                                               const T* __restrict__ cache,
@@ -483,8 +486,25 @@ __global__ __launch_bounds__(kThreads, (waves_per_simd<T, CACHED>())) void cell_
           S2b[ax] += bv * G11;
         }
       }
-      // this row's share of the nodal results: B[qy][ay] S1[ax] + D[qy][ay] S2[ax]
-      if (valid) {
+      // this row's share of the nodal results: B[qy][ay] S1[ax] + D[qy][ay] S2[ax];
+      // in the ordered mode the four parity classes add one after the other
+      // (cells of one class share no node), so every node sums in a fixed order
+      if (ORDERED) {
+        for (int c = 0; c < 4; ++c) {
+          if (valid && color == c) {
+#pragma unroll
+            for (int ay = 0; ay < 3; ++ay) {
+              const T bv = row_v<T>(qy, ay), bd = row_d<T>(qy, ay);
+#pragma unroll
+              for (int ax = 0; ax < 3; ++ax) {
+                acc[2 * mu][ly0 + ay][lx0 + ax] += (double)(bv * S1a[ax] + bd * S2a[ax]);
+                acc[2 * mu + 1][ly0 + ay][lx0 + ax] += (double)(bv * S1b[ax] + bd * S2b[ax]);
+              }
+            }
+          }
+          __syncthreads();
+        }
+      } else if (valid) {
 #pragma unroll
         for (int ay = 0; ay < 3; ++ay) {
           const T bv = row_v<T>(qy, ay), bd = row_d<T>(qy, ay);
@@ -510,10 +530,9 @@ __global__ __launch_bounds__(kThreads, (waves_per_simd<T, CACHED>())) void cell_
   // part's.  Only tiles at the boundary of the rectangle have any.
   const int hxe = min(HX - OFF, g.nx - cx0), hye = min(HY - OFF, g.ny - cy0);  // owned cells
   if (cx0 == 0 || cy0 == 0 || cx0 + hxe == g.nx || cy0 + hye == g.ny) {
-    for (int p = t; p < 4 * HX * 6; p += kThreads) {
-      const int side = p / (HX * 6), r = p % (HX * 6);
-      const int j = r / 6, q = (r >> 1) % 3, fmu = r & 1;
-      int fhx, fhy;  // evaluated-cell coordinates in the tile
+    // the face cell of point p (side, cell j along it): tile coordinates, or
+    // false if it is not evaluated here
+    auto face_cell = [&](int side, int j, int& fhx, int& fhy, int& fcx, int& fcy) {
       if (side < 2) {
         fhx = (side == 0 ? 0 : g.nx - 1) - cx0 + OFF;
         fhy = j;
@@ -521,14 +540,38 @@ __global__ __launch_bounds__(kThreads, (waves_per_simd<T, CACHED>())) void cell_
         fhx = j;
         fhy = (side == 2 ? 0 : g.ny - 1) - cy0 + OFF;
       }
-      const int fcx = cx0 - OFF + fhx, fcy = cy0 - OFF + fhy;
-      if (fhx < 0 || fhx >= HX || fhy < 0 || fhy >= HY || fcx < 0 || fcy < 0 || fcx >= g.nx ||
-          fcy >= g.ny)
-        continue;
-      // a halo cell contributes to the tile's nodes but not to its pressure rows
-      const bool own = fhx >= OFF && fhy >= OFF;
-      face_point<T, LIN, CONV>(m, g, tau, side, q, fmu, fcx, fcy, Xs, 2 * fhx, 2 * fhy, uk, x,
-                               acc, own ? pacc[fmu][fhy * HX + fhx] : nullptr);
+      fcx = cx0 - OFF + fhx;
+      fcy = cy0 - OFF + fhy;
+      return !(fhx < 0 || fhx >= HX || fhy < 0 || fhy >= HY || fcx < 0 || fcy < 0 ||
+               fcx >= g.nx || fcy >= g.ny);
+    };
+    if (!ORDERED) {
+      for (int p = t; p < 4 * HX * 6; p += kThreads) {
+        const int side = p / (HX * 6), r = p % (HX * 6);
+        const int j = r / 6, q = (r >> 1) % 3, fmu = r & 1;
+        int fhx, fhy, fcx, fcy;
+        if (!face_cell(side, j, fhx, fhy, fcx, fcy)) continue;
+        // a halo cell contributes to the tile's nodes but not to its pressure rows
+        const bool own = fhx >= OFF && fhy >= OFF;
+        face_point<T, LIN, CONV, true>(m, g, tau, side, q, fmu, fcx, fcy, Xs, 2 * fhx, 2 * fhy,
+                                       uk, x, acc, own ? pacc[fmu][fhy * HX + fhx] : nullptr);
+      }
+    } else {
+      // fixed order: side by side, cells of one parity along the side at a
+      // time (neighbours share nodes), the three points of a cell in turn
+      for (int side = 0; side < 4; ++side)
+        for (int par = 0; par < 2; ++par) {
+          const int j = 2 * (t >> 1) + par, fmu = t & 1;
+          int fhx, fhy, fcx, fcy;
+          if (t < HX * 2 && j < HX && face_cell(side, j, fhx, fhy, fcx, fcy)) {
+            const bool own = fhx >= OFF && fhy >= OFF;
+            for (int q = 0; q < 3; ++q)
+              face_point<T, LIN, CONV, false>(m, g, tau, side, q, fmu, fcx, fcy, Xs, 2 * fhx,
+                                              2 * fhy, uk, x, acc,
+                                              own ? pacc[fmu][fhy * HX + fhx] : nullptr);
+          }
+          __syncthreads();
+        }
     }
     __syncthreads();
   }
@@ -654,12 +697,21 @@ hipError_t launch4(const Grid& g, const Model& m, double tau, const T* uk, const
   constexpr int OFF = halo_tiles<T, CACHED>() ? 1 : 0;
   const int tx = (g.nx + HX - OFF - 1) / (HX - OFF), ty = (g.ny + HY - OFF - 1) / (HY - OFF);
   dim3 grid(tx * ty), block(kThreads);
-  if (mode == 0)
-    hipLaunchKernelGGL((cell_apply_kernel<T, LIN, CONV, 0, CACHED>), grid, block, 0, s, g, m, tau,
-                       uk, cache, x, b, y, edge, tx);
-  else
-    hipLaunchKernelGGL((cell_apply_kernel<T, LIN, CONV, 1, CACHED>), grid, block, 0, s, g, m, tau,
-                       uk, cache, x, b, y, edge, tx);
+  if (m.ordered) {
+    if (mode == 0)
+      hipLaunchKernelGGL((cell_apply_kernel<T, LIN, CONV, 0, CACHED, true>), grid, block, 0, s, g,
+                         m, tau, uk, cache, x, b, y, edge, tx);
+    else
+      hipLaunchKernelGGL((cell_apply_kernel<T, LIN, CONV, 1, CACHED, true>), grid, block, 0, s, g,
+                         m, tau, uk, cache, x, b, y, edge, tx);
+  } else {
+    if (mode == 0)
+      hipLaunchKernelGGL((cell_apply_kernel<T, LIN, CONV, 0, CACHED, false>), grid, block, 0, s,
+                         g, m, tau, uk, cache, x, b, y, edge, tx);
+    else
+      hipLaunchKernelGGL((cell_apply_kernel<T, LIN, CONV, 1, CACHED, false>), grid, block, 0, s,
+                         g, m, tau, uk, cache, x, b, y, edge, tx);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || OFF) return e;
   const int nvl = tx - 1, nhl = ty - 1;

@@ -89,6 +89,8 @@ struct pns_ctx {
   const double* lift = nullptr;
   double* ltab = nullptr;
   double* ltab_r = nullptr;
+  // 2D action and residual in a fixed summation order (pns_set_reproducible)
+  bool ordered = false;
   // pns_solve's Jacobian action with x and u_k stored in BF16 (3D FP32
   // contexts, pns_set_jacobian_precision)
   bool jac_bf16 = false;

@@ -58,7 +58,19 @@ struct Model {
   // Dirichlet data of the level-0 mesh as a table over its boundary face points
   // (launch_lift_table), or nullptr for homogeneous data (eq. def-b-gam)
   const double* lift;
+  // 2D action and residual: sum the cell contributions of a tile in a fixed
+  // order (bitwise reproducible) instead of with LDS atomics
+  int ordered;
 };
+
+// LDS accumulation: atomic, or a plain add where the caller orders the adds
+template <bool ATOMIC>
+__device__ __forceinline__ void lds_add(double* p, double v) {
+  if (ATOMIC)
+    atomicAdd(p, v);
+  else
+    *p += v;
+}
 
 struct Grid {
   int nx, ny;

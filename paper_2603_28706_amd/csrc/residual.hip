@@ -36,6 +36,7 @@ __device__ __forceinline__ double viscosity(const Model& m, double a00, double a
 }
 
 // one point q of a boundary face of a cell (node box offset lx0 / ly0 in the tile)
+template <bool ATOMIC>
 __device__ __forceinline__ void residual_face_point(const Model& m, const Grid& g, double tau,
                                                     int side, int q, int mu, int cx, int cy,
                                                     const double (*Xs)[BY][BX], int lx0, int ly0,
@@ -112,17 +113,18 @@ __device__ __forceinline__ void residual_face_point(const Model& m, const Grid& 
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       const double ph = vx[ax] * vy[ay], px = dx[ax] * vy[ay], py = vx[ax] * dy[ay];
-      atomicAdd(&acc[2 * mu][ly0 + ay][lx0 + ax], F0 * ph + G00 * px + G01 * py);
-      atomicAdd(&acc[2 * mu + 1][ly0 + ay][lx0 + ax], F1 * ph + G10 * px + G11 * py);
+      lds_add<ATOMIC>(&acc[2 * mu][ly0 + ay][lx0 + ax], F0 * ph + G00 * px + G01 * py);
+      lds_add<ATOMIC>(&acc[2 * mu + 1][ly0 + ay][lx0 + ax], F1 * ph + G10 * px + G11 * py);
     }
   if (pa) {
     const double P = sW * m.qsign * en;
-    atomicAdd(&pa[0], P);
-    atomicAdd(&pa[1], P * (xi - 0.5));
-    atomicAdd(&pa[2], P * (et - 0.5));
+    lds_add<ATOMIC>(&pa[0], P);
+    lds_add<ATOMIC>(&pa[1], P * (xi - 0.5));
+    lds_add<ATOMIC>(&pa[2], P * (et - 0.5));
   }
 }
 
+template <bool ORDERED>
 __global__ __launch_bounds__(kThreads, 2) void residual_kernel(Grid g, Model m, double tau,
                                                                const double* __restrict__ U,
                                                                const double* __restrict__ vprev,
@@ -169,6 +171,11 @@ __global__ __launch_bounds__(kThreads, 2) void residual_kernel(Grid g, Model m, 
   const bool valid = cx >= 0 && cy >= 0 && cx < g.nx && cy < g.ny;
   const int lx0 = 2 * hx, ly0 = 2 * hy;
   const int lc = hy * HX + hx;
+  // ordered mode: this cell's nodal sums, added class by class after the rows
+  double racc[2][9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) racc[0][i] = racc[1][i] = 0.0;
+  (void)racc;
   if (valid) {
     const int other = 1 - mu;
     const double kself = mu ? kKt[1][1] : kKt[0][0], koth = mu ? kKt[1][0] : kKt[0][1];
@@ -254,21 +261,39 @@ __global__ __launch_bounds__(kThreads, 2) void residual_kernel(Grid g, Model m, 
         const double bv = q2v(ay, gyq), bd = q2d(ay, gyq);
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-          atomicAdd(&acc[2 * mu][ly0 + ay][lx0 + ax], bv * S1a[ax] + bd * S2a[ax]);
-          atomicAdd(&acc[2 * mu + 1][ly0 + ay][lx0 + ax], bv * S1b[ax] + bd * S2b[ax]);
+          const double r0 = bv * S1a[ax] + bd * S2a[ax], r1 = bv * S1b[ax] + bd * S2b[ax];
+          if (ORDERED) {
+            racc[0][3 * ay + ax] += r0;
+            racc[1][3 * ay + ax] += r1;
+          } else {
+            atomicAdd(&acc[2 * mu][ly0 + ay][lx0 + ax], r0);
+            atomicAdd(&acc[2 * mu + 1][ly0 + ay][lx0 + ax], r1);
+          }
         }
       }
     }
 #pragma unroll
     for (int j = 0; j < 3; ++j) pacc[mu][lc][j] = op[j];
   }
+  if (ORDERED) {
+    // the four parity classes one after the other (cells of one class share
+    // no node): every node sums in a fixed order
+    for (int c = 0; c < 4; ++c) {
+      if (valid && color == c) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          acc[2 * mu][ly0 + i / 3][lx0 + i % 3] += racc[0][i];
+          acc[2 * mu + 1][ly0 + i / 3][lx0 + i % 3] += racc[1][i];
+        }
+      }
+      __syncthreads();
+    }
+  }
   __syncthreads();
 
   if (cx0 == 0 || cy0 == 0 || cx0 + TX >= g.nx || cy0 + TY >= g.ny) {
-    for (int p = t; p < 4 * HX * 6; p += kThreads) {
-      const int side = p / (HX * 6), r = p % (HX * 6);
-      const int j = r / 6, q = (r >> 1) % 3, fmu = r & 1;
-      int fhx, fhy;
+    // the face cell of (side, cell j along it) in tile coordinates, or false
+    auto face_cell = [&](int side, int j, int& fhx, int& fhy, int& fcx, int& fcy) {
       if (side < 2) {
         fhx = (side == 0 ? 0 : g.nx - 1) - cx0 + 1;
         fhy = j;
@@ -276,12 +301,35 @@ __global__ __launch_bounds__(kThreads, 2) void residual_kernel(Grid g, Model m, 
         fhx = j;
         fhy = (side == 2 ? 0 : g.ny - 1) - cy0 + 1;
       }
-      const int fcx = cx0 - 1 + fhx, fcy = cy0 - 1 + fhy;
-      if (fhx < 0 || fhx >= HX || fhy < 0 || fhy >= HY || fcx < 0 || fcy < 0 || fcx >= g.nx ||
-          fcy >= g.ny)
-        continue;
-      residual_face_point(m, g, tau, side, q, fmu, fcx, fcy, Xs, 2 * fhx, 2 * fhy, U, acc,
-                          (fhx >= 1 && fhy >= 1) ? pacc[fmu][fhy * HX + fhx] : nullptr);
+      fcx = cx0 - 1 + fhx;
+      fcy = cy0 - 1 + fhy;
+      return !(fhx < 0 || fhx >= HX || fhy < 0 || fhy >= HY || fcx < 0 || fcy < 0 ||
+               fcx >= g.nx || fcy >= g.ny);
+    };
+    if (!ORDERED) {
+      for (int p = t; p < 4 * HX * 6; p += kThreads) {
+        const int side = p / (HX * 6), r = p % (HX * 6);
+        const int j = r / 6, q = (r >> 1) % 3, fmu = r & 1;
+        int fhx, fhy, fcx, fcy;
+        if (!face_cell(side, j, fhx, fhy, fcx, fcy)) continue;
+        residual_face_point<true>(m, g, tau, side, q, fmu, fcx, fcy, Xs, 2 * fhx, 2 * fhy, U,
+                                  acc, (fhx >= 1 && fhy >= 1) ? pacc[fmu][fhy * HX + fhx] : nullptr);
+      }
+    } else {
+      // side by side, cells of one parity along the side at a time, the three
+      // points of a cell in turn
+      for (int side = 0; side < 4; ++side)
+        for (int par = 0; par < 2; ++par) {
+          const int j = 2 * (t >> 1) + par, fmu = t & 1;
+          int fhx, fhy, fcx, fcy;
+          if (t < HX * 2 && j < HX && face_cell(side, j, fhx, fhy, fcx, fcy))
+            for (int q = 0; q < 3; ++q)
+              residual_face_point<false>(m, g, tau, side, q, fmu, fcx, fcy, Xs, 2 * fhx, 2 * fhy,
+                                         U, acc,
+                                         (fhx >= 1 && fhy >= 1) ? pacc[fmu][fhy * HX + fhx]
+                                                                : nullptr);
+          __syncthreads();
+        }
     }
     __syncthreads();
   }
@@ -312,8 +360,12 @@ __global__ __launch_bounds__(kThreads, 2) void residual_kernel(Grid g, Model m, 
 hipError_t launch_residual(const Grid& g, const Model& m, double tau, const double* U,
                            const double* vprev, double* R, hipStream_t s) {
   const int tx = (g.nx + TX - 1) / TX, ty = (g.ny + TY - 1) / TY;
-  hipLaunchKernelGGL(residual_kernel, dim3(tx * ty), dim3(kThreads), 0, s, g, m, tau, U, vprev, R,
-                     tx);
+  if (m.ordered)
+    hipLaunchKernelGGL(residual_kernel<true>, dim3(tx * ty), dim3(kThreads), 0, s, g, m, tau, U,
+                       vprev, R, tx);
+  else
+    hipLaunchKernelGGL(residual_kernel<false>, dim3(tx * ty), dim3(kThreads), 0, s, g, m, tau, U,
+                       vprev, R, tx);
   return hipGetLastError();
 }
 

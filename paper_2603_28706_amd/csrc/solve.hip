@@ -292,6 +292,7 @@ int pns_residual(pns_ctx* ctx, const pns_model* md, const double* U, const doubl
     PNS_HIP(ctx, launch_lift_table(ctx->lev[0].g, m, ctx->lift, ctx->ltab_r, ctx->stream));
     m.lift = ctx->ltab_r;
   }
+  m.ordered = ctx->ordered ? 1 : 0;
   if (ctx->dim == 3) {
     const int rc = residual3d(ctx, m, U, vprev, R);
     if (rc != PNS_OK) return rc;
@@ -338,6 +339,7 @@ int pns_solve(pns_ctx* ctx, const pns_model* md, const double* vprev, double* U,
     PNS_HIP(ctx, launch_lift_table(ctx->lev[0].g, S.model, ctx->lift, ctx->ltab_r, ctx->stream));
     S.model.lift = ctx->ltab_r;
   }
+  S.model.ordered = ctx->ordered ? 1 : 0;
   S.vprev = vprev;
   S.g = ctx->lev[0].g;
   S.s = ctx->stream;

@@ -131,6 +131,7 @@ def lib():
         L.pns_load_vector.argtypes = [_vp, _vp, _vp]
         L.pns_set_load.argtypes = [_vp, _vp]
         L.pns_set_dirichlet.argtypes = [_vp, _vp]
+        L.pns_set_reproducible.argtypes = [_vp, i]
         L.pns_solve_workspace_bytes.argtypes = [_vp, i]
         L.pns_solve_workspace_bytes.restype = ctypes.c_size_t
         L.pns_solve.argtypes = [_vp, pp(pns_model), _vp, _vp, pp(pns_solve_params), _vp,
@@ -328,6 +329,9 @@ class Context:
             return
         self._load = F
         self._check(lib().pns_set_load(self.h, self._f64(F, self.sizes(0)["nst"])))
+
+    def pns_set_reproducible(self, on):
+        self._check(lib().pns_set_reproducible(self.h, int(on)))
 
     def pns_set_dirichlet(self, ghat):
         """Dirichlet data from a lifting: FP64 device tensor of 2 N_v values (the
