@@ -427,6 +427,16 @@ def run(args):
         torch.cuda.synchronize()
         t_cached = ea.elapsed_time(eb) * 1e-3 / n_rep
         ctx.pns_set_apply_mode(pnsmg.APPLY_RECOMPUTE)
+        # back-to-back applies in the fixed summation order (reported alongside)
+        ctx.pns_set_reproducible(1)
+        ctx.pns_cell_apply(x, y)
+        ea.record(stream)
+        for _ in range(n_rep):
+            ctx.pns_cell_apply(x, y)
+        eb.record(stream)
+        torch.cuda.synchronize()
+        t_ordered = ea.elapsed_time(eb) * 1e-3 / n_rep
+        ctx.pns_set_reproducible(0)
         # the same V-cycle replayed from one captured HIP graph (reported alongside)
         t_vc_graph = None
         if not args.apply_only:
@@ -449,6 +459,7 @@ def run(args):
             apply_s_mean=float(np.mean(t_apply)), apply_s_median=float(np.median(t_apply)),
             apply_s_p10=float(np.percentile(t_apply, 10)),
             apply_s_p90=float(np.percentile(t_apply, 90)), apply_s_cached=t_cached,
+            apply_s_ordered=t_ordered,
             vcycle_s_median=float(np.median(t_vc)) if not args.apply_only else None,
             vcycle_s_graph=t_vc_graph, setup_s=t_setup, bytes=algorithmic_bytes(sz, elem))
         print(f"[bench] {name}: apply {np.mean(t_apply) * 1e6:.1f} us mean in step "
@@ -787,6 +798,8 @@ def main():
                                       ("apply_s_p10", "apply_s_median", "apply_s_p90")],
         "apply_us_cached_tangent_fp64_fp32": [round(f64["apply_s_cached"] * 1e6, 3),
                                               round(f32["apply_s_cached"] * 1e6, 3)],
+        "apply_us_reproducible_fp64_fp32": [round(f64["apply_s_ordered"] * 1e6, 3),
+                                            round(f32["apply_s_ordered"] * 1e6, 3)],
         "apply_hbm_gbs_fp64": round(f64["bytes"] / t_ap / 1e9, 1),
         "vcycle_s_fp64": f64["vcycle_s_median"],
         "vcycle_s_fp32": f32["vcycle_s_median"],

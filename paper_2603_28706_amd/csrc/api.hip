@@ -442,7 +442,8 @@ int vanka_setup_impl(pns_ctx* c, const uint16_t* masks) {
   // and at t_rep for the surrogate patches (time slots 0, 1, 2 of the table)
   PNS_HIP(c, launch_element_matrices(L0.g, c->model, u0, 0, c->Es0, s));
   PNS_HIP(c, launch_element_matrices(L0.g, c->model, u1, 1, c->Es1, s));
-  PNS_HIP(c, launch_element_matrices(L0.g, c->model, c->urep, 2, c->Esr, s));
+  if (c->patch_kind == PNS_PATCH_SURROGATE)  // the midpoint matrices feed only those patches
+    PNS_HIP(c, launch_element_matrices(L0.g, c->model, c->urep, 2, c->Esr, s));
   // CIP face matrices: at each Radau node's velocity (level-0 operator, with
   // tau w_mu) and at t_rep (time-diagonal patches, unscaled)
   const bool cip = c->model.gamma_cip > 0.0;

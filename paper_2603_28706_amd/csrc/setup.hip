@@ -26,14 +26,23 @@ __device__ __forceinline__ int64_t st_global_index(const Grid& g, int cx, int cy
   return (int64_t)mu * g.ns + g.nv + 3 * ((int64_t)cy * g.nx + cx) + (i - 18);
 }
 
-// scalar Q2 mass matrix of a cell, by the 3x3 Gauss rule
-__device__ __forceinline__ double cell_mass(const Grid& g, int a, int b) {
+// scalar Q2 mass matrix of the reference cell, by the 3x3 Gauss rule (times
+// h_x h_y: the cell's)
+__device__ __forceinline__ double ref_mass(int a, int b) {
   double s = 0.0;
   for (int qy = 0; qy < 3; ++qy)
     for (int qx = 0; qx < 3; ++qx)
       s += kGW[qx] * kGW[qy] * q2v(a % 3, kGP[qx]) * q2v(a / 3, kGP[qy]) * q2v(b % 3, kGP[qx]) *
            q2v(b / 3, kGP[qy]);
-  return s * g.hx * g.hy;
+  return s;
+}
+__device__ __forceinline__ double cell_mass(const Grid& g, int a, int b) {
+  return ref_mass(a, b) * g.hx * g.hy;
+}
+// the 81 reference values into LDS once per workgroup (the patch kernels read
+// them for every entry and neighbour)
+__device__ __forceinline__ void fill_ref_mass(double* M) {
+  for (int e = threadIdx.x; e < 81; e += blockDim.x) M[e] = ref_mass(e / 9, e % 9);
 }
 
 // ----------------------------------------------------------- cell matrices
@@ -231,10 +240,14 @@ struct FineEntry {
   double tau;
   const double* Es_a;  // spatial matrices used at Radau node 0
   const double* Es_b;  // ... at Radau node 1
+  const double* mref = nullptr;  // reference mass in LDS (fill_ref_mass), or computed
+  __device__ void set_mass(const double* m) { mref = m; }
   __device__ double operator()(int64_t cell, int r, int c) const {
     const int mu = r / kNs, i = r % kNs, nu = c / kNs, j = c % kNs;
     double v = 0.0;
-    if (i < 18 && j < 18 && i / 9 == j / 9) v = kKt[mu][nu] * cell_mass(g, i % 9, j % 9);
+    if (i < 18 && j < 18 && i / 9 == j / 9)
+      v = kKt[mu][nu] * (mref ? mref[(i % 9) * 9 + j % 9] * g.hx * g.hy
+                              : cell_mass(g, i % 9, j % 9));
     if (mu == nu) {
       const double* E = (mu == 0 ? Es_a : Es_b) + cell * (kNs * kNs);
       v += tau * kWt[mu] * E[i * kNs + j];
@@ -245,6 +258,7 @@ struct FineEntry {
 
 struct StoredEntry {
   const double* E;  // 42 x 42 per cell
+  __device__ void set_mass(const double*) {}
   __device__ double operator()(int64_t cell, int r, int c) const {
     return E[cell * (kNst * kNst) + r * kNst + c];
   }
@@ -286,12 +300,15 @@ __global__ __launch_bounds__(64) void patch_kernel(Grid g, Entry entry, const do
                                                    T* __restrict__ inv, int* status) {
   __shared__ double A[kNst][2 * kNst + 1];
   __shared__ double fac[kNst];
-  __shared__ double red_v[64];
-  __shared__ int red_i[64];
+  __shared__ double Mref[81];
   const int64_t K = blockIdx.x;
   const int cx = (int)(K % g.nx), cy = (int)(K / g.nx);
   const int t = threadIdx.x;
   const uint16_t mask = masks ? masks[K] : (uint16_t)0x1ff;
+  fill_ref_mass(Mref);
+  __syncthreads();
+  Entry ent = entry;
+  ent.set_mass(Mref);
   for (int e = t; e < kNst * kNst; e += 64) {
     const int r = e / kNst, c = e % kNst;
     double v = 0.0;
@@ -304,7 +321,7 @@ __global__ __launch_bounds__(64) void patch_kernel(Grid g, Entry entry, const do
           if (nx_ < 0 || ny_ < 0 || nx_ >= g.nx || ny_ >= g.ny) continue;
           const int rr = map_to_neighbour(r, ox, oy), cc = map_to_neighbour(c, ox, oy);
           if (rr < 0 || cc < 0) continue;
-          v += entry((int64_t)ny_ * g.nx + nx_, rr, cc);
+          v += ent((int64_t)ny_ * g.nx + nx_, rr, cc);
         }
       v += patch_cip(g, S, 2, cx, cy, r, c);
     }
@@ -312,33 +329,28 @@ __global__ __launch_bounds__(64) void patch_kernel(Grid g, Entry entry, const do
     A[r][kNst + c] = (r == c) ? 1.0 : 0.0;
   }
   __syncthreads();
+  // Gauss-Jordan with partial pivoting on [A | I]; lane t owns columns t and
+  // t + 64 of the augmented matrix, the pivot comes from a wave reduction
   bool singular = false;
   for (int k = 0; k < kNst; ++k) {
-    // pivot: largest |A[r][k]|, r >= k
+    // pivot: largest |A[r][k]|, r >= k (the lowest row among equal values)
     double bv = -1.0;
     int bi = k;
     if (t >= k && t < kNst) {
       bv = fabs(A[t][k]);
       bi = t;
     }
-    red_v[t] = bv;
-    red_i[t] = bi;
-    __syncthreads();
     for (int off = 32; off > 0; off >>= 1) {
-      if (t < off) {
-        const double ov = red_v[t + off];
-        const int oi = red_i[t + off];
-        if (ov > red_v[t] || (ov == red_v[t] && oi < red_i[t])) {
-          red_v[t] = ov;
-          red_i[t] = oi;
-        }
+      const double ov = __shfl_xor(bv, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
       }
-      __syncthreads();
     }
-    const int p = red_i[0];
-    const double pmax = red_v[0];
+    const int p = bi;
+    if (!(bv > 0.0)) singular = true;
     __syncthreads();
-    if (!(pmax > 0.0)) singular = true;
     for (int c = t; c < 2 * kNst; c += 64) {
       const double tmp = A[k][c];
       A[k][c] = A[p][c];
@@ -346,12 +358,14 @@ __global__ __launch_bounds__(64) void patch_kernel(Grid g, Entry entry, const do
     }
     __syncthreads();
     const double piv = singular ? 1.0 : A[k][k];
+    __syncthreads();
     for (int c = t; c < 2 * kNst; c += 64) A[k][c] /= piv;
     if (t < kNst) fac[t] = (t == k) ? 0.0 : A[t][k];
     __syncthreads();
-    for (int e = t; e < kNst * 2 * kNst; e += 64) {
-      const int r = e / (2 * kNst), c = e % (2 * kNst);
-      if (r != k) A[r][c] -= fac[r] * A[k][c];
+    for (int c = t; c < 2 * kNst; c += 64) {
+      const double akc = A[k][c];
+      for (int r = 0; r < kNst; ++r)
+        if (r != k) A[r][c] -= fac[r] * akc;
     }
     __syncthreads();
   }
@@ -377,12 +391,13 @@ __global__ __launch_bounds__(64) void patch_complex_kernel(Grid g, double tau,
                                                            T* __restrict__ inv, int* status) {
   __shared__ double Ar[kNs][2 * kNs + 1], Ai[kNs][2 * kNs + 1];
   __shared__ double fr[kNs], fi[kNs];
-  __shared__ double red_v[64];
-  __shared__ int red_i[64];
+  __shared__ double Mref[81];
   const int64_t K = blockIdx.x;
   const int cx = (int)(K % g.nx), cy = (int)(K / g.nx);
   const int t = threadIdx.x;
   const uint16_t mask = masks ? masks[K] : (uint16_t)0x1ff;
+  fill_ref_mass(Mref);
+  __syncthreads();
   for (int e = t; e < kNs * kNs; e += 64) {
     const int r = e / kNs, c = e % kNs;
     double cr = 0.0, ci = 0.0;
@@ -398,7 +413,8 @@ __global__ __launch_bounds__(64) void patch_complex_kernel(Grid g, double tau,
           if (rr < 0 || cc < 0) continue;
           const int64_t nb = (int64_t)ny_ * g.nx + nx_;
           jv += Es[nb * (kNs * kNs) + rr * kNs + cc];
-          if (rr < 18 && cc < 18 && rr / 9 == cc / 9) mv += cell_mass(g, rr % 9, cc % 9);
+          if (rr < 18 && cc < 18 && rr / 9 == cc / 9)
+            mv += Mref[(rr % 9) * 9 + cc % 9] * g.hx * g.hy;
         }
       jv += patch_cip(g, Sr, 1, cx, cy, r, c);
       cr = kLamRe * mv + tau * jv;
@@ -410,6 +426,8 @@ __global__ __launch_bounds__(64) void patch_complex_kernel(Grid g, double tau,
     Ai[r][kNs + c] = 0.0;
   }
   __syncthreads();
+  // complex Gauss-Jordan with partial pivoting on [C | I]; lane t owns column t
+  // of the augmented matrix, the pivot comes from a wave reduction
   bool singular = false;
   for (int k = 0; k < kNs; ++k) {
     double bv = -1.0;
@@ -418,24 +436,17 @@ __global__ __launch_bounds__(64) void patch_complex_kernel(Grid g, double tau,
       bv = Ar[t][k] * Ar[t][k] + Ai[t][k] * Ai[t][k];
       bi = t;
     }
-    red_v[t] = bv;
-    red_i[t] = bi;
-    __syncthreads();
     for (int off = 32; off > 0; off >>= 1) {
-      if (t < off) {
-        const double ov = red_v[t + off];
-        const int oi = red_i[t + off];
-        if (ov > red_v[t] || (ov == red_v[t] && oi < red_i[t])) {
-          red_v[t] = ov;
-          red_i[t] = oi;
-        }
+      const double ov = __shfl_xor(bv, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ov > bv || (ov == bv && oi < bi)) {
+        bv = ov;
+        bi = oi;
       }
-      __syncthreads();
     }
-    const int p = red_i[0];
-    const double pmax = red_v[0];
+    const int p = bi;
+    if (!(bv > 0.0)) singular = true;
     __syncthreads();
-    if (!(pmax > 0.0)) singular = true;
     for (int c = t; c < 2 * kNs; c += 64) {
       const double tr = Ar[k][c], ti = Ai[k][c];
       Ar[k][c] = Ar[p][c];
@@ -459,13 +470,13 @@ __global__ __launch_bounds__(64) void patch_complex_kernel(Grid g, double tau,
       fi[t] = (t == k) ? 0.0 : Ai[t][k];
     }
     __syncthreads();
-    for (int e = t; e < kNs * 2 * kNs; e += 64) {
-      const int r = e / (2 * kNs), c = e % (2 * kNs);
-      if (r != k) {
-        const double br = Ar[k][c], bi2 = Ai[k][c];
-        Ar[r][c] -= fr[r] * br - fi[r] * bi2;
-        Ai[r][c] -= fr[r] * bi2 + fi[r] * br;
-      }
+    for (int c = t; c < 2 * kNs; c += 64) {
+      const double br = Ar[k][c], bi2 = Ai[k][c];
+      for (int r = 0; r < kNs; ++r)
+        if (r != k) {
+          Ar[r][c] -= fr[r] * br - fi[r] * bi2;
+          Ai[r][c] -= fr[r] * bi2 + fi[r] * br;
+        }
     }
     __syncthreads();
   }
@@ -517,9 +528,14 @@ __global__ __launch_bounds__(256) void galerkin_kernel(Grid gc, Grid gf, Entry f
   __shared__ double Pf[kNst][kNst + 1];
   __shared__ double Ef[kNst][kNst + 1];
   __shared__ double Tm[kNst][kNst + 1];
+  __shared__ double Mref[81];
   const int64_t C = blockIdx.x;
   const int cx = (int)(C % gc.nx), cy = (int)(C / gc.nx);
   const int t = threadIdx.x;
+  fill_ref_mass(Mref);
+  __syncthreads();
+  Entry fe = fine_entry;
+  fe.set_mass(Mref);
   constexpr int kPer = (kNst * kNst + 255) / 256;
   double accv[kPer];
   for (int q = 0; q < kPer; ++q) accv[q] = 0.0;
@@ -529,7 +545,7 @@ __global__ __launch_bounds__(256) void galerkin_kernel(Grid gc, Grid gf, Entry f
     for (int e = t; e < kNst * kNst; e += 256) {
       const int r = e / kNst, c = e % kNst;
       Pf[r][c] = prolong_entry(r, c, ox, oy);
-      Ef[r][c] = fine_entry(f, r, c);
+      Ef[r][c] = fe(f, r, c);
     }
     __syncthreads();
     for (int e = t; e < kNst * kNst; e += 256) {  // Tm = Ef Pf
