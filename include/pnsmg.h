@@ -389,8 +389,9 @@ int pns_set_load(pns_ctx* ctx, const double* F_dev);
  * pns_residual / pns_solve call, so it is read again at each of those calls.
  * A smoother built before the call is invalidated (pns_vanka_setup again).
  * Needs a bound workspace (PNS_EWORKSPACE); rebinding one clears the state, not
- * the registration.  Quadrilaterals only: PNS_EUNSUPPORTED on a hexahedral
- * context.  Serving requests use homogeneous data. */
+ * the registration.  Quadrilaterals and hexahedra (the 3D action, residual,
+ * smoother and solve); PNS_EUNSUPPORTED in a BF16 context.  Serving requests
+ * use homogeneous data. */
 int pns_set_dirichlet(pns_ctx* ctx, const double* ghat_dev);
 
 /* Parameters of pns_solve. */

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "ctx.h"
+#include "hex3.h"
 
 using namespace pns;
 
@@ -50,6 +51,8 @@ size_t layout(pns_ctx* c, bool bind) {
     c->r3u = (double*)take(2 * g0.nv * 8);
     c->r3b = (double*)take(g0.nst * 8);
     c->r3slot = (double*)take(g0.nc * 170 * 8);
+    c->ltab = (double*)take(lift3_table_doubles(c->g3) * 8);
+    c->ltab_r = (double*)take(lift3_table_doubles(c->g3) * 8);
     if (c->nlev >= 2) {  // right-hand side and correction of graph-replayed V-cycles
       c->gr = take(g0.nst * es);
       c->gd = take(g0.nst * es);
@@ -384,12 +387,12 @@ int vanka_setup3d(pns_ctx* c) {
   if (!exact) {
     // level 0: surrogate patches, all state-dependent coefficients at t_rep;
     // Esr is the buffer of Es0, so this comes first (stream order)
-    PNS_HIP(c, launch_element_matrices3d(g0, c->model, c->urep, c->Esr, s));
+    PNS_HIP(c, launch_element_matrices3d(g0, c->model, c->urep, 2, c->Esr, s));
     PNS_HIP(c, launch_patches3d<T>(g0, c->disc.tau, c->Esr, (T*)c->lev[0].inv, c->status, s));
   }
   if (c->nlev >= 2 || exact) {
-    PNS_HIP(c, launch_element_matrices3d(g0, c->model, c->uk64, c->Es0, s));
-    PNS_HIP(c, launch_element_matrices3d(g0, c->model, c->uk64 + g0.nv, c->Es1, s));
+    PNS_HIP(c, launch_element_matrices3d(g0, c->model, c->uk64, 0, c->Es0, s));
+    PNS_HIP(c, launch_element_matrices3d(g0, c->model, c->uk64 + g0.nv, 1, c->Es1, s));
   }
   if (exact) {
     // level 0: exact patches, each Radau node with its own spatial matrices
@@ -803,7 +806,10 @@ int pns_set_state(pns_ctx* ctx, const pns_model* md, const double* u_k) {
     return fail(ctx, PNS_EUNSUPPORTED, "CIP stabilisation is built for quadrilaterals only");
   m.lift = nullptr;
   if (ctx->lift) {
-    PNS_HIP(ctx, launch_lift_table(ctx->lev[0].g, m, ctx->lift, ctx->ltab, ctx->stream));
+    if (ctx->dim == 3)
+      PNS_HIP(ctx, launch_lift3_table(ctx->g3, m, ctx->lift, ctx->ltab, ctx->stream));
+    else
+      PNS_HIP(ctx, launch_lift_table(ctx->lev[0].g, m, ctx->lift, ctx->ltab, ctx->stream));
     m.lift = ctx->ltab;
   }
   m.ordered = ctx->ordered ? 1 : 0;
@@ -912,13 +918,16 @@ int pns_set_reproducible(pns_ctx* ctx, int on) {
 
 int pns_set_dirichlet(pns_ctx* ctx, const double* ghat) {
   if (!ctx) return PNS_EINVAL;
-  if (ghat && ctx->dim == 3)
-    return fail(ctx, PNS_EUNSUPPORTED, "inhomogeneous Dirichlet data is built for quadrilaterals");
+  if (ghat && ctx->prec == PNS_BF16)
+    return fail(ctx, PNS_EUNSUPPORTED, "BF16 contexts have the action only");
   if (ghat && !ctx->ws) return fail(ctx, PNS_EWORKSPACE, "no workspace bound");
   ctx->lift = ghat;
   ctx->model.lift = nullptr;
   if (ghat && ctx->has_state) {  // the action sees the data at once
-    PNS_HIP(ctx, launch_lift_table(ctx->lev[0].g, ctx->model, ghat, ctx->ltab, ctx->stream));
+    if (ctx->dim == 3)
+      PNS_HIP(ctx, launch_lift3_table(ctx->g3, ctx->model, ghat, ctx->ltab, ctx->stream));
+    else
+      PNS_HIP(ctx, launch_lift_table(ctx->lev[0].g, ctx->model, ghat, ctx->ltab, ctx->stream));
     ctx->model.lift = ctx->ltab;
   }
   ctx->drop_graph();

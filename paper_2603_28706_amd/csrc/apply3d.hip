@@ -38,7 +38,7 @@
 #include <type_traits>
 
 #include "devmath.h"
-#include "pns_internal.h"
+#include "hex3.h"
 
 namespace pns {
 namespace {
@@ -539,7 +539,21 @@ __global__ __launch_bounds__(64) void face3d_kernel(Grid3 g, Model m, double tau
                         (double)ld<T>(pv + 2) * (xi[1] - 0.5) + (double)ld<T>(pv + 3) * (xi[2] - 0.5);
       const double un = U[0] * n[0] + U[1] * n[1] + U[2] * n[2];
       const double xn = X[0] * n[0] + X[1] * n[1] + X[2] * n[2];
-      const double pen1 = m.gamma1 * m.etaD * ihF, pen2 = m.gamma2 * ihF;
+      // frozen Nitsche coefficients at G = D ghat_D from the boundary table (no
+      // data: eta_D, no rank-one part)
+      double etaG = m.etaD, kG = 0.0, Gl[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+      if (m.lift) {
+        const double* lt = m.lift + lift3_index(g, sd, cc[k1], cc[k2], qa, mu);
+        sym3(lt + 3, Gl);
+        etaG = lt[9];
+        kG = lt[10];
+      }
+      double GS = 0.0;  // G : sym(x (x) n)
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) GS += Gl[i][j] * X[i] * n[j];
+      const double pen1 = m.gamma1 * etaG * ihF, pen2 = m.gamma2 * ihF;
       double* cf = coef[mu][qa];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
@@ -554,10 +568,11 @@ __global__ __launch_bounds__(64) void face3d_kernel(Grid3 g, Model m, double tau
           if (LIN != PNS_PICARD) F += xn * U[i];
         }
         cf[i] = sW * F;
-        // symmetry term -eta_D (D(w) n).x as a coefficient of d_j w_i
+        // symmetry term -(DS(G)(D w) n).x as a coefficient of d_j w_i:
+        // -(eta(G) S + k (G:S) G)_ij with S = sym(x (x) n)
 #pragma unroll
         for (int j = 0; j < 3; ++j)
-          cf[3 + 3 * i + j] = -sW * m.etaD * 0.5 * (X[i] * n[j] + X[j] * n[i]);
+          cf[3 + 3 * i + j] = -sW * (etaG * 0.5 * (X[i] * n[j] + X[j] * n[i]) + kG * GS * Gl[i][j]);
       }
       cf[12] = sW * m.qsign * xn;  // coefficient of the pressure test
     }

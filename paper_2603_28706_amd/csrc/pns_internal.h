@@ -200,8 +200,8 @@ hipError_t launch_gather3(const Grid3& g, const T* E, const T* b, T* y, hipStrea
 // time-diagonal form).  Es: nc * 85 * 85 FP64 spatial cell matrices at the
 // state u; inv: nc complex 85 x 85 inverses (2 * 85 * 85 values per patch,
 // colour-major patch order); status bit 0 set on a zero pivot.
-hipError_t launch_element_matrices3d(const Grid3& g, const Model& m, const double* u, double* Es,
-                                     hipStream_t s);
+hipError_t launch_element_matrices3d(const Grid3& g, const Model& m, const double* u, int lslot,
+                                     double* Es, hipStream_t s);
 template <typename T>
 hipError_t launch_patches3d(const Grid3& g, double tau, const double* Es, T* inv, int* status,
                             hipStream_t s);
@@ -327,6 +327,13 @@ hipError_t launch_add(int64_t n, const double* x, double* y, hipStream_t s);
 // lifting given as a Q2 velocity field per Radau node (stride g.nv)
 hipError_t launch_lift_table(const Grid& g, const Model& m, const double* ghat, double* table,
                              hipStream_t s);
+// hexahedra: the boundary table (lift3_index in hex3.h) and the data term
+// -tau w_mu B_gamma(g_D, .) into the action's per-cell result slots E (170
+// per cell, every cell written)
+hipError_t launch_lift3_table(const Grid3& g, const Model& m, const double* ghat, double* table,
+                              hipStream_t s);
+hipError_t launch_lift3_rhs(const Grid3& g, const Model& m, double tau, const double* table,
+                            double* E, hipStream_t s);
 
 // cip.hip: CIP stabilisation on the interior faces of a quadrilateral mesh,
 // y += sign * tau w_mu s_CIP(uw_mu; x_mu, .) (sign = +1 action, -1 defect /

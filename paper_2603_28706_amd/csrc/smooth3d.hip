@@ -44,21 +44,16 @@ struct Pt3 {
   double u[3];    // state
   double A[3][3]; // symmetric gradient of the state
   double eta, kap;
+  double GD[6];   // boundary points: G = D ghat_D (00, 01, 02, 11, 12, 22)
+  double etaG, kG;
 };
 
-// value and physical gradient of the Q2 basis function of node a at xi
-__device__ __forceinline__ void basis3(const Grid3& g, int a, const double xi[3], double& ph,
-                                       double gr[3]) {
-  const int ax = a % 3, ay = (a / 3) % 3, az = a / 9;
-  const double vx = q2v(ax, xi[0]), vy = q2v(ay, xi[1]), vz = q2v(az, xi[2]);
-  ph = vx * vy * vz;
-  gr[0] = q2d(ax, xi[0]) * g.ihx * vy * vz;
-  gr[1] = vx * q2d(ay, xi[1]) * g.ihy * vz;
-  gr[2] = vx * vy * q2d(az, xi[2]) * g.ihz;
-}
 
+// lslot: time slot of the Dirichlet data table (m.lift) matching u (0, 1: the
+// Radau nodes, 2: the slab midpoint); ignored without data
 __global__ __launch_bounds__(256) void element_matrix3d_kernel(Grid3 g, Model m,
                                                                const double* __restrict__ u,
+                                                               int lslot,
                                                                double* __restrict__ Es) {
   __shared__ double ul[kNv3];
   __shared__ Pt3 pts[kMaxPts];
@@ -126,6 +121,17 @@ __global__ __launch_bounds__(256) void element_matrix3d_kernel(Grid3 g, Model m,
       }
     }
     P.kap = kp;
+    for (int e = 0; e < 6; ++e) P.GD[e] = 0.0;
+    P.etaG = m.etaD;
+    P.kG = 0.0;
+    if (m.lift && t >= 27) {
+      const int sd = sides[(t - 27) / 9], qa = (t - 27) % 9;
+      const int k = sd >> 1, k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+      const double* lt = m.lift + lift3_index(g, sd, ci[k1], ci[k2], qa, lslot);
+      for (int e = 0; e < 6; ++e) P.GD[e] = lt[3 + e];
+      P.etaG = lt[9];
+      P.kG = lt[10];
+    }
     pts[t] = P;
   }
   __syncthreads();
@@ -169,6 +175,12 @@ __global__ __launch_bounds__(256) void element_matrix3d_kernel(Grid3 g, Model m,
           const double gbn = gb[0] * n[0] + gb[1] * n[1] + gb[2] * n[2];
           double An[3];
           for (int i = 0; i < 3; ++i) An[i] = P.A[i][0] * n[0] + P.A[i][1] * n[1] + P.A[i][2] * n[2];
+          double GL[3][3], Gga[3], Gn[3];
+          sym3(P.GD, GL);
+          for (int i = 0; i < 3; ++i) {
+            Gga[i] = GL[i][0] * ga[0] + GL[i][1] * ga[1] + GL[i][2] * ga[2];
+            Gn[i] = GL[i][0] * n[0] + GL[i][1] * n[1] + GL[i][2] * n[2];
+          }
           const double pab = pa * pb;
           for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j) {
@@ -181,10 +193,10 @@ __global__ __launch_bounds__(256) void element_matrix3d_kernel(Grid3 g, Model m,
               }
               // -(T(D x) n) . w
               v -= pa * (P.eta * 0.5 * (dij * gbn + gb[i] * n[j]) + P.kap * Agb[j] * An[i]);
-              // -eta_D (D w n) . x
-              v -= m.etaD * pb * 0.5 * (dij * gan + ga[j] * n[i]);
+              // -(DS(G)(D w) n) . x, DS(G)(D w) = eta(G) D w + k (G : D w) G
+              v -= pb * (P.etaG * 0.5 * (dij * gan + ga[j] * n[i]) + P.kG * Gga[i] * Gn[j]);
               // penalties
-              v += m.gamma1 * m.etaD * P.ihF * dij * pab + m.gamma2 * P.ihF * pb * n[j] * pa * n[i];
+              v += m.gamma1 * P.etaG * P.ihF * dij * pab + m.gamma2 * P.ihF * pb * n[j] * pa * n[i];
               blk[i][j] += P.W * v;
             }
         }
@@ -428,9 +440,10 @@ __global__ __launch_bounds__(kSweepThreads) void patch_sweep3_kernel(
 
 }  // namespace
 
-hipError_t launch_element_matrices3d(const Grid3& g, const Model& m, const double* u, double* Es,
-                                     hipStream_t s) {
-  hipLaunchKernelGGL(element_matrix3d_kernel, dim3((unsigned)g.nc), dim3(256), 0, s, g, m, u, Es);
+hipError_t launch_element_matrices3d(const Grid3& g, const Model& m, const double* u, int lslot,
+                                     double* Es, hipStream_t s) {
+  hipLaunchKernelGGL(element_matrix3d_kernel, dim3((unsigned)g.nc), dim3(256), 0, s, g, m, u, lslot,
+                     Es);
   return hipGetLastError();
 }
 

@@ -97,6 +97,12 @@ int residual3d(pns_ctx* c, const Model& m, const double* U, const double* vprev,
   } else {
     PNS_HIP(c, launch_fill<double>(g.nst, 0.0, c->r3b, s));
   }
+  if (m.lift) {
+    // b += B_gamma(g_D, .): the data term per cell into the slots, gathered as
+    // b - sum with slots holding its negative
+    PNS_HIP(c, launch_lift3_rhs(g, m, c->disc.tau, m.lift, c->r3slot, s));
+    PNS_HIP(c, launch_gather3<double>(g, c->r3slot, c->r3b, c->r3b, s));
+  }
   PNS_HIP(c, hipMemcpyAsync(c->r3u, U, g.nv * 8, hipMemcpyDeviceToDevice, s));
   PNS_HIP(c, hipMemcpyAsync(c->r3u + g.nv, U + g.ns, g.nv * 8, hipMemcpyDeviceToDevice, s));
   Model mp = m;
@@ -289,7 +295,10 @@ int pns_residual(pns_ctx* ctx, const pns_model* md, const double* U, const doubl
     return fail(ctx, PNS_EUNSUPPORTED, "CIP stabilisation is built for quadrilaterals only");
   m.lift = nullptr;
   if (ctx->lift) {
-    PNS_HIP(ctx, launch_lift_table(ctx->lev[0].g, m, ctx->lift, ctx->ltab_r, ctx->stream));
+    if (ctx->dim == 3)
+      PNS_HIP(ctx, launch_lift3_table(ctx->g3, m, ctx->lift, ctx->ltab_r, ctx->stream));
+    else
+      PNS_HIP(ctx, launch_lift_table(ctx->lev[0].g, m, ctx->lift, ctx->ltab_r, ctx->stream));
     m.lift = ctx->ltab_r;
   }
   m.ordered = ctx->ordered ? 1 : 0;
@@ -336,7 +345,11 @@ int pns_solve(pns_ctx* ctx, const pns_model* md, const double* vprev, double* U,
   if (rc != PNS_OK) return rc;
   S.model.lift = nullptr;
   if (ctx->lift) {
-    PNS_HIP(ctx, launch_lift_table(ctx->lev[0].g, S.model, ctx->lift, ctx->ltab_r, ctx->stream));
+    if (ctx->dim == 3)
+      PNS_HIP(ctx, launch_lift3_table(ctx->g3, S.model, ctx->lift, ctx->ltab_r, ctx->stream));
+    else
+      PNS_HIP(ctx, launch_lift_table(ctx->lev[0].g, S.model, ctx->lift, ctx->ltab_r,
+                                     ctx->stream));
     S.model.lift = ctx->ltab_r;
   }
   S.model.ordered = ctx->ordered ? 1 : 0;

@@ -68,6 +68,11 @@ def test_workspace_query_and_state_errors_without_device():
     L.pns_ctx_destroy(h)
 
 
+def lift3(nx, ny, nz):
+    """Bytes of one hexahedral Dirichlet-data table."""
+    return 2 * (ny * nz + nx * nz + nx * ny) * 9 * 3 * 11 * 8
+
+
 def test_3d_context_layout_and_rejections():
     """A hexahedral context: unknown counts of Q2^3 / P1disc x dG(1); the
     workspace holds the state, the per-cell results of the action and the
@@ -91,7 +96,10 @@ def test_3d_context_layout_and_rejections():
     kE = 170 * 170
     # state, action slots, residual buffers, midpoint state, one set of
     # spatial cell matrices, defect, complex 85 x 85 patch inverses
+    # (and two Dirichlet-data tables: 9 points x 3 time slots x 11 values per
+    # boundary face)
     base = 2 * nv * (es + 8) + 32768 * 170 * es + 2 * nv * 8 + nst * 8 + 32768 * 170 * 8
+    base += 2 * lift3(32, 32, 32)
     need = base + nv * 8 + 16 + 32768 * 85 * 85 * 8 + nst * es + 32768 * 2 * 85 * 85 * es
     assert need <= nbytes < need + 4096
     # exact patches: both Radau nodes' cell matrices, real 170 x 170 inverses
@@ -153,7 +161,8 @@ def test_3d_context_layout_and_rejections():
             + 33574 * 8 + 512 * 2 * 85 * 85 * 8
             + 4886 * 8 * 3 + 64 * kE * 16 + 64 * kE * 8
             + 814 * 8 * 3 + 8 * kE * 16
-            + 814 * 814 * 8 + (3 * 64 * 814 + 4 * 13 + 8) * 8 + 814 * 4)
+            + 814 * 814 * 8 + (3 * 64 * 814 + 4 * 13 + 8) * 8 + 814 * 4
+            + 2 * lift3(8, 8, 8))
     assert need <= L.pns_workspace_bytes(h) < need + 8192
     L.pns_ctx_destroy(h)
     # BF16: hexahedral action only (state in BF16, action slots in FP32)
@@ -178,7 +187,8 @@ def test_3d_context_layout_and_rejections():
     nc = 24
     nst = 2 * (3 * nn + 4 * nc)
     need = (2 * 3 * nn * (4 + 8) + nc * 170 * 4 + 3 * nn * 8 + nc * 85 * 85 * 8 + 16
-            + nc * 2 * 85 * 85 * 4 + nst * 4 + 2 * 3 * nn * 8 + nst * 8 + nc * 170 * 8)
+            + nc * 2 * 85 * 85 * 4 + nst * 4 + 2 * 3 * nn * 8 + nst * 8 + nc * 170 * 8
+            + 2 * lift3(4, 2, 3))
     assert need <= L.pns_workspace_bytes(h) < need + 4096
     L.pns_ctx_destroy(h)
 
