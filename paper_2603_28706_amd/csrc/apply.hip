@@ -327,20 +327,39 @@ __global__ __launch_bounds__(kThreads, (waves_per_simd<T, CACHED>())) void cell_
   const int NX = 2 * g.nx + 1;
   const int gx0 = 2 * (cx0 - OFF), gy0 = 2 * (cy0 - OFF);  // node box origin
 
-  // stage x (and u_k) of the node box, zero the sums
-  for (int i = t; i < 4 * BY * BX; i += kThreads) {
-    const int f = i / (BY * BX), r = i % (BY * BX);
-    const int ly = r / BX, lx = r % BX;
-    const int gx = gx0 + lx, gy = gy0 + ly;
-    T xv = 0, uv = 0;
-    if (gx >= 0 && gy >= 0 && gx <= 2 * g.nx && gy <= 2 * g.ny) {
-      const int64_t gn = (int64_t)gy * NX + gx;
-      xv = x[(int64_t)(f >> 1) * g.ns + (int64_t)(f & 1) * g.nn + gn];
-      if (!CACHED) uv = uk[(int64_t)(f >> 1) * g.nv + (int64_t)(f & 1) * g.nn + gn];
+  // stage x (and u_k) of the node box, zero the sums.  Every load of the
+  // thread is issued before the first LDS store (addresses clamped into the
+  // mesh, values outside it replaced by zero), so the thread waits for one
+  // memory round trip instead of one per box slice.
+  {
+    constexpr int kSlices = (4 * BY * BX + kThreads - 1) / kThreads;
+    T xv[kSlices], uv[kSlices];
+#pragma unroll
+    for (int s = 0; s < kSlices; ++s) {
+      const int i = min(t + s * kThreads, 4 * BY * BX - 1);
+      const int f = i / (BY * BX), r = i % (BY * BX);
+      const int ly = r / BX, lx = r % BX;
+      const int gx = gx0 + lx, gy = gy0 + ly;
+      const bool in = gx >= 0 && gy >= 0 && gx <= 2 * g.nx && gy <= 2 * g.ny;
+      const int64_t gn = (int64_t)min(max(gy, 0), 2 * g.ny) * NX + min(max(gx, 0), 2 * g.nx);
+      const T xl = x[(int64_t)(f >> 1) * g.ns + (int64_t)(f & 1) * g.nn + gn];
+      xv[s] = in ? xl : (T)0;
+      if (!CACHED) {
+        const T ul = uk[(int64_t)(f >> 1) * g.nv + (int64_t)(f & 1) * g.nn + gn];
+        uv[s] = in ? ul : (T)0;
+      }
     }
-    Xs[f][ly][lx] = xv;
-    if (!CACHED) Us[f][ly][lx] = uv;
-    acc[f][ly][lx] = 0.0;
+#pragma unroll
+    for (int s = 0; s < kSlices; ++s) {
+      const int i = t + s * kThreads;
+      if (i < 4 * BY * BX) {
+        const int f = i / (BY * BX), r = i % (BY * BX);
+        const int ly = r / BX, lx = r % BX;
+        Xs[f][ly][lx] = xv[s];
+        if (!CACHED) Us[f][ly][lx] = uv[s];
+        acc[f][ly][lx] = 0.0;
+      }
+    }
   }
   __syncthreads();
 
@@ -576,15 +595,31 @@ __global__ __launch_bounds__(kThreads, (waves_per_simd<T, CACHED>())) void cell_
     __syncthreads();
   }
 
+  // Write-out.  In the defect the thread's loads of b for every slice are
+  // issued before the first store (invalid slices read b[0]), so it waits for
+  // one memory round trip instead of one per slice.
   // pressure rows of the owned cells
-  for (int i = t; i < 2 * kCells * 3; i += kThreads) {
-    const int pmu = i / (kCells * 3), r = i % (kCells * 3);
-    const int c = r / 3, j = r % 3;
-    const int ccx = cx0 - OFF + c % HX, ccy = cy0 - OFF + c / HX;
-    if (ccx >= cx0 && ccy >= cy0 && ccx < g.nx && ccy < g.ny) {
-      const int64_t idx = (int64_t)pmu * g.ns + g.nv + 3 * ((int64_t)ccy * g.nx + ccx) + j;
-      const double v = pacc[pmu][c][j];
-      y[idx] = MODE ? (T)((double)b[idx] - v) : (T)v;
+  {
+    constexpr int kP = (2 * kCells * 3 + kThreads - 1) / kThreads;
+    int64_t pidx[kP];
+    T pb[kP];
+#pragma unroll
+    for (int s = 0; s < kP; ++s) {
+      const int i = t + s * kThreads;
+      const int pmu = i / (kCells * 3), r = i % (kCells * 3);
+      const int c = r / 3, j = r % 3;
+      const int ccx = cx0 - OFF + c % HX, ccy = cy0 - OFF + c / HX;
+      const bool own = i < 2 * kCells * 3 && ccx >= cx0 && ccy >= cy0 && ccx < g.nx && ccy < g.ny;
+      pidx[s] = own ? (int64_t)pmu * g.ns + g.nv + 3 * ((int64_t)ccy * g.nx + ccx) + j : -1;
+      if (MODE) pb[s] = b[own ? pidx[s] : 0];
+    }
+#pragma unroll
+    for (int s = 0; s < kP; ++s) {
+      if (pidx[s] >= 0) {
+        const int r = (t + s * kThreads) % (kCells * 3);
+        const double v = pacc[(t + s * kThreads) / (kCells * 3)][r / 3][r % 3];
+        y[pidx[s]] = MODE ? (T)((double)pb[s] - v) : (T)v;
+      }
     }
   }
   if constexpr (HALO) {
@@ -593,14 +628,26 @@ __global__ __launch_bounds__(kThreads, (waves_per_simd<T, CACHED>())) void cell_
     const int gx_end = (cx0 + hxe >= g.nx) ? 2 * g.nx + 1 : 2 * (cx0 + hxe);
     const int gy_end = (cy0 + hye >= g.ny) ? 2 * g.ny + 1 : 2 * (cy0 + hye);
     const int nox = gx_end - 2 * cx0, noy = gy_end - 2 * cy0;
-    for (int i = t; i < 4 * (2 * HY - 1) * 32; i += kThreads) {
+    constexpr int kN = 4 * (2 * HY - 1) * 32, kV = (kN + kThreads - 1) / kThreads;
+    int64_t vidx[kV];
+    T vb[kV];
+#pragma unroll
+    for (int sl = 0; sl < kV; ++sl) {
+      const int i = t + sl * kThreads;
       const int s = i / ((2 * HY - 1) * 32), r = i % ((2 * HY - 1) * 32);
       const int ox = r % 32, oy = r / 32;
-      if (ox < nox && oy < noy) {
-        const int64_t gn = (int64_t)(2 * cy0 + oy) * NX + (2 * cx0 + ox);
-        const int64_t idx = (int64_t)(s >> 1) * g.ns + (int64_t)(s & 1) * g.nn + gn;
-        const double v = acc[s][oy + 2][ox + 2];
-        y[idx] = MODE ? (T)((double)b[idx] - v) : (T)v;
+      const bool own = i < kN && ox < nox && oy < noy;
+      const int64_t gn = (int64_t)(2 * cy0 + oy) * NX + (2 * cx0 + ox);
+      vidx[sl] = own ? (int64_t)(s >> 1) * g.ns + (int64_t)(s & 1) * g.nn + gn : -1;
+      if (MODE) vb[sl] = b[own ? vidx[sl] : 0];
+    }
+#pragma unroll
+    for (int sl = 0; sl < kV; ++sl) {
+      if (vidx[sl] >= 0) {
+        const int i = t + sl * kThreads;
+        const int s = i / ((2 * HY - 1) * 32), r = i % ((2 * HY - 1) * 32);
+        const double v = acc[s][r / 32 + 2][r % 32 + 2];
+        y[vidx[sl]] = MODE ? (T)((double)vb[sl] - v) : (T)v;
       }
     }
   } else {
@@ -608,19 +655,32 @@ __global__ __launch_bounds__(kThreads, (waves_per_simd<T, CACHED>())) void cell_
     // with another tile as partial sums, to the tile's slice of the edge buffer
     double* te = edge + (int64_t)tile * 4 * kPerim;
     const bool shl = cx0 > 0, shr = cx0 + hxe < g.nx, shb = cy0 > 0, sht = cy0 + hye < g.ny;
-    for (int i = t; i < 4 * BY * BX; i += kThreads) {
+    constexpr int kN = 4 * BY * BX, kV = (kN + kThreads - 1) / kThreads;
+    int64_t vidx[kV];  // y index, -1: shared edge node or outside the owned box
+    T vb[kV];
+#pragma unroll
+    for (int sl = 0; sl < kV; ++sl) {
+      const int i = t + sl * kThreads;
       const int s = i / (BY * BX), r = i % (BY * BX);
       const int ly = r / BX, lx = r % BX;
-      if (lx > 2 * hxe || ly > 2 * hye) continue;
-      const double v = acc[s][ly][lx];
+      const bool in = i < kN && lx <= 2 * hxe && ly <= 2 * hye;
       const bool shared = (lx == 0 && shl) || (lx == 2 * hxe && shr) || (ly == 0 && shb) ||
                           (ly == 2 * hye && sht);
-      if (shared) {
+      const int64_t gn = (int64_t)(gy0 + ly) * NX + (gx0 + lx);
+      vidx[sl] = in && !shared ? (int64_t)(s >> 1) * g.ns + (int64_t)(s & 1) * g.nn + gn : -1;
+      if (MODE) vb[sl] = b[vidx[sl] >= 0 ? vidx[sl] : 0];
+    }
+#pragma unroll
+    for (int sl = 0; sl < kV; ++sl) {
+      const int i = t + sl * kThreads;
+      const int s = i / (BY * BX), r = i % (BY * BX);
+      const int ly = r / BX, lx = r % BX;
+      if (i >= kN || lx > 2 * hxe || ly > 2 * hye) continue;
+      const double v = acc[s][ly][lx];
+      if (vidx[sl] < 0) {
         te[s * kPerim + perim_index(lx, ly)] = v;
       } else {
-        const int64_t gn = (int64_t)(gy0 + ly) * NX + (gx0 + lx);
-        const int64_t idx = (int64_t)(s >> 1) * g.ns + (int64_t)(s & 1) * g.nn + gn;
-        y[idx] = MODE ? (T)((double)b[idx] - v) : (T)v;
+        y[vidx[sl]] = MODE ? (T)((double)vb[sl] - v) : (T)v;
       }
     }
   }

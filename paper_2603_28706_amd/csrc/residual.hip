@@ -143,23 +143,37 @@ __global__ __launch_bounds__(kThreads, 2) void residual_kernel(Grid g, Model m, 
   const int NX = 2 * g.nx + 1;
   const int gx0 = 2 * (cx0 - 1), gy0 = 2 * (cy0 - 1);
 
-  for (int i = t; i < 6 * BY * BX; i += kThreads) {
-    const int f = i / (BY * BX), r = i % (BY * BX);
-    const int ly = r / BX, lx = r % BX;
-    const int gx = gx0 + lx, gy = gy0 + ly;
-    double v = 0.0;
-    if (gx >= 0 && gy >= 0 && gx <= 2 * g.nx && gy <= 2 * g.ny) {
-      const int64_t gn = (int64_t)gy * NX + gx;
-      if (f < 4)
-        v = U[(int64_t)(f >> 1) * g.ns + (int64_t)(f & 1) * g.nn + gn];
-      else if (vprev)
-        v = vprev[(int64_t)(f - 4) * g.nn + gn];
+  // staging: every load of the thread issued before the first LDS store
+  // (addresses clamped into the mesh, values outside it replaced by zero)
+  {
+    constexpr int kN = 6 * BY * BX, kSlices = (kN + kThreads - 1) / kThreads;
+    double v[kSlices];
+#pragma unroll
+    for (int s = 0; s < kSlices; ++s) {
+      const int i = min(t + s * kThreads, kN - 1);
+      const int f = i / (BY * BX), r = i % (BY * BX);
+      const int ly = r / BX, lx = r % BX;
+      const int gx = gx0 + lx, gy = gy0 + ly;
+      const bool in = gx >= 0 && gy >= 0 && gx <= 2 * g.nx && gy <= 2 * g.ny && (f < 4 || vprev);
+      const int64_t gn = (int64_t)min(max(gy, 0), 2 * g.ny) * NX + min(max(gx, 0), 2 * g.nx);
+      const double* src = f < 4 ? U + (int64_t)(f >> 1) * g.ns + (int64_t)(f & 1) * g.nn
+                                : (vprev ? vprev + (int64_t)(f - 4) * g.nn : U);
+      const double l = src[gn];
+      v[s] = in ? l : 0.0;
     }
-    if (f < 4) {
-      Xs[f][ly][lx] = v;
-      acc[f][ly][lx] = 0.0;
-    } else {
-      Vs[f - 4][ly][lx] = v;
+#pragma unroll
+    for (int s = 0; s < kSlices; ++s) {
+      const int i = t + s * kThreads;
+      if (i < kN) {
+        const int f = i / (BY * BX), r = i % (BY * BX);
+        const int ly = r / BX, lx = r % BX;
+        if (f < 4) {
+          Xs[f][ly][lx] = v[s];
+          acc[f][ly][lx] = 0.0;
+        } else {
+          Vs[f - 4][ly][lx] = v[s];
+        }
+      }
     }
   }
   __syncthreads();
