@@ -132,12 +132,14 @@ __device__ __forceinline__ double swap_pair(double v) {
 // penalties (eq. def-b-gam).  The test coefficients are contracted against the
 // 9 nodes of the cell and added to the tile's LDS sums (velocity: acc, at the
 // cell's node box offset lx0 / ly0; pressure: pa, or nothing for pa == nullptr).
-template <typename T, int LIN, bool CONV, bool ATOMIC>
+// u_k is read from the tile's LDS copy Us when the variant stages one, else
+// from memory.
+template <typename T, int LIN, bool CONV, bool ATOMIC, bool LDS_U>
 __device__ __forceinline__ void face_point(const Model& m, const Grid& g, double tau, int side,
                                            int q, int mu, int cx, int cy, const T (*Xs)[BY][BX],
-                                           int lx0, int ly0, const T* __restrict__ uk,
-                                           const T* __restrict__ x, double (*acc)[BY][BX],
-                                           double* pa) {
+                                           const T (*Us)[BY][BX], int lx0, int ly0,
+                                           const T* __restrict__ uk, const T* __restrict__ x,
+                                           double (*acc)[BY][BX], double* pa) {
   // side: 0 x=0 (n=-e_x), 1 x=1 (n=+e_x), 2 y=0 (n=-e_y), 3 y=1 (n=+e_y)
   const bool xface = side < 2;
   const double nxv = xface ? (side == 0 ? -1.0 : 1.0) : 0.0;
@@ -150,6 +152,10 @@ __device__ __forceinline__ void face_point(const Model& m, const Grid& g, double
   const double ihF = xface ? g.ihx : g.ihy;  // 1 / h_F, h_F the cell size normal to the face
   // frozen Nitsche coefficients at G = D ghat_D from the boundary table (no
   // data: eta_D, no rank-one part)
+  const int64_t cell = (int64_t)cy * g.nx + cx;
+  // the pressure coefficients of x first: their load overlaps the rest
+  const T* pv = x + (int64_t)mu * g.ns + g.nv + 3 * cell;
+  const T xp0 = pv[0], xp1 = pv[1], xp2 = pv[2];
   double Gl00 = 0.0, Gl01 = 0.0, Gl11 = 0.0, etaG = m.etaD, kG = 0.0;
   if (m.lift) {
     const double* lt = m.lift + lift_index(g, side, xface ? cy : cx, q, mu);
@@ -164,7 +170,6 @@ __device__ __forceinline__ void face_point(const Model& m, const Grid& g, double
   const T n0 = (T)nxv, n1 = (T)nyv;
   const int NX = 2 * g.nx + 1;
   const T* um = uk + (int64_t)mu * g.nv;
-  const int64_t cell = (int64_t)cy * g.nx + cx;
   T vx[3], vy[3], dx[3], dy[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -181,8 +186,15 @@ __device__ __forceinline__ void face_point(const Model& m, const Grid& g, double
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       const T ph = vx[ax] * vy[ay], px = dx[ax] * vy[ay], py = vx[ax] * dy[ay];
-      const int64_t gn = (int64_t)(2 * cy + ay) * NX + (2 * cx + ax);
-      const T u0 = um[gn], u1 = um[g.nn + gn];
+      T u0, u1;
+      if (LDS_U) {
+        u0 = Us[2 * mu][ly0 + ay][lx0 + ax];
+        u1 = Us[2 * mu + 1][ly0 + ay][lx0 + ax];
+      } else {
+        const int64_t gn = (int64_t)(2 * cy + ay) * NX + (2 * cx + ax);
+        u0 = um[gn];
+        u1 = um[g.nn + gn];
+      }
       U[0] += u0 * ph; U[1] += u1 * ph;
       GU[0][0] += u0 * px; GU[0][1] += u0 * py;
       GU[1][0] += u1 * px; GU[1][1] += u1 * py;
@@ -205,8 +217,7 @@ __device__ __forceinline__ void face_point(const Model& m, const Grid& g, double
       GX[0][0] += x0 * px; GX[0][1] += x0 * py;
       GX[1][0] += x1 * px; GX[1][1] += x1 * py;
     }
-  const T* pv = x + (int64_t)mu * g.ns + g.nv + 3 * cell;
-  const T xp = pv[0] + pv[1] * (T)(xi - 0.5) + pv[2] * (T)(et - 0.5);
+  const T xp = xp0 + xp1 * (T)(xi - 0.5) + xp2 * (T)(et - 0.5);
   const T b00 = GX[0][0], b01 = (T)0.5 * (GX[0][1] + GX[1][0]), b11 = GX[1][1];
   const T ab = a00 * b00 + (T)2 * a01 * b01 + a11 * b11;
   const T T00 = eta * b00 + kap * ab * a00;
@@ -565,15 +576,25 @@ __global__ __launch_bounds__(kThreads, (waves_per_simd<T, CACHED>())) void cell_
                fcx >= g.nx || fcy >= g.ny);
     };
     if (!ORDERED) {
-      for (int p = t; p < 4 * HX * 6; p += kThreads) {
-        const int side = p / (HX * 6), r = p % (HX * 6);
+      // the points of the sides this tile touches, numbered consecutively
+      // (HY x 3 x 2 on an x side, HX x 3 x 2 on a y side), one per thread
+      // unless the tile touches more than two sides
+      const bool touch[4] = {cx0 == 0, cx0 + hxe == g.nx, cy0 == 0, cy0 + hye == g.ny};
+      int first[5];
+      first[0] = 0;
+#pragma unroll
+      for (int sd = 0; sd < 4; ++sd) first[sd + 1] = first[sd] + (touch[sd] ? (sd < 2 ? HY : HX) * 6 : 0);
+      for (int p = t; p < first[4]; p += kThreads) {
+        const int side = p < first[1] ? 0 : (p < first[2] ? 1 : (p < first[3] ? 2 : 3));
+        const int r = p - first[side];
         const int j = r / 6, q = (r >> 1) % 3, fmu = r & 1;
         int fhx, fhy, fcx, fcy;
         if (!face_cell(side, j, fhx, fhy, fcx, fcy)) continue;
         // a halo cell contributes to the tile's nodes but not to its pressure rows
         const bool own = fhx >= OFF && fhy >= OFF;
-        face_point<T, LIN, CONV, true>(m, g, tau, side, q, fmu, fcx, fcy, Xs, 2 * fhx, 2 * fhy,
-                                       uk, x, acc, own ? pacc[fmu][fhy * HX + fhx] : nullptr);
+        face_point<T, LIN, CONV, true, !CACHED>(m, g, tau, side, q, fmu, fcx, fcy, Xs, Us,
+                                                2 * fhx, 2 * fhy, uk, x, acc,
+                                                own ? pacc[fmu][fhy * HX + fhx] : nullptr);
       }
     } else {
       // fixed order: side by side, cells of one parity along the side at a
@@ -585,9 +606,9 @@ __global__ __launch_bounds__(kThreads, (waves_per_simd<T, CACHED>())) void cell_
           if (t < HX * 2 && j < HX && face_cell(side, j, fhx, fhy, fcx, fcy)) {
             const bool own = fhx >= OFF && fhy >= OFF;
             for (int q = 0; q < 3; ++q)
-              face_point<T, LIN, CONV, false>(m, g, tau, side, q, fmu, fcx, fcy, Xs, 2 * fhx,
-                                              2 * fhy, uk, x, acc,
-                                              own ? pacc[fmu][fhy * HX + fhx] : nullptr);
+              face_point<T, LIN, CONV, false, !CACHED>(m, g, tau, side, q, fmu, fcx, fcy, Xs,
+                                                       Us, 2 * fhx, 2 * fhy, uk, x, acc,
+                                                       own ? pacc[fmu][fhy * HX + fhx] : nullptr);
           }
           __syncthreads();
         }
