@@ -86,6 +86,7 @@ size_t layout(pns_ctx* c, bool bind) {
     if (c->has_coarse) {
       const int64_t n = c->lev.back().g.nst;
       c->Adense = (double*)take((size_t)n * n * 8);
+      if (es == 4) c->Adense32 = (float*)take((size_t)n * n * 4);
       c->gjwork = (double*)take((size_t)coarse_invert_work_doubles(n) * 8);
       c->gjpiv = (int*)take((size_t)n * sizeof(int));
     }
@@ -121,6 +122,7 @@ size_t layout(pns_ctx* c, bool bind) {
     if (coarsest && c->has_coarse) {
       const int64_t n = L.g.nst;
       c->Adense = (double*)take((size_t)n * n * 8);
+      if (es == 4) c->Adense32 = (float*)take((size_t)n * n * 4);
       c->gjwork = (double*)take((size_t)coarse_invert_work_doubles(n) * 8);
       c->gjpiv = (int*)take((size_t)n * sizeof(int));
     }
@@ -263,7 +265,10 @@ hipError_t vcycle_level(pns_ctx* c, int l, int nu1, int nu2, double omega, const
   hipError_t e;
   if (l == c->nlev - 1) {
     const int npin = 2;
-    return launch_dense_gemv<T>(L.g.nst, c->Adense, r, d, c->pin, npin, c->stream);
+    // the inverse in the context's precision: FP32 contexts read its FP32 copy
+    const T* A = sizeof(T) == 8 ? (const T*)(const void*)c->Adense
+                                : (const T*)(const void*)c->Adense32;
+    return launch_dense_gemv<T>(L.g.nst, A, r, d, c->pin, npin, c->stream);
   }
   if ((e = launch_fill<T>(L.g.nst, (T)0, d, c->stream)) != hipSuccess) return e;
   if ((e = smooth<T>(c, l, nu1, omega, r, d, true)) != hipSuccess) return e;
@@ -421,6 +426,7 @@ int vanka_setup3d(pns_ctx* c) {
     PNS_HIP(c, hipStreamSynchronize(s));
     PNS_HIP(c, launch_pin(n, c->Adense, (const int64_t*)c->gjwork, 2, s));
     PNS_HIP(c, coarse_invert(n, c->Adense, c->gjwork, c->gjpiv, c->status, s));
+    if (c->Adense32) PNS_HIP(c, launch_convert<float>(n * n, c->Adense, c->Adense32, s));
   }
   PNS_HIP(c, hipMemcpyAsync(&st, c->status, sizeof(int), hipMemcpyDeviceToHost, s));
   PNS_HIP(c, hipStreamSynchronize(s));
@@ -503,6 +509,7 @@ int vanka_setup_impl(pns_ctx* c, const uint16_t* masks) {
   PNS_HIP(c, hipStreamSynchronize(s));
   PNS_HIP(c, launch_pin(n, c->Adense, (const int64_t*)c->gjwork, 2, s));
   PNS_HIP(c, coarse_invert(n, c->Adense, c->gjwork, c->gjpiv, c->status, s));
+  if (c->Adense32) PNS_HIP(c, launch_convert<float>(n * n, c->Adense, c->Adense32, s));
   PNS_HIP(c, hipMemcpyAsync(&st, c->status, sizeof(int), hipMemcpyDeviceToHost, s));
   PNS_HIP(c, hipStreamSynchronize(s));
   if (st & 1) return fail(c, PNS_ESINGULAR, "a patch matrix has a zero pivot");

@@ -62,6 +62,7 @@ struct pns_ctx {
   int* status = nullptr;
   // coarsest level (dense inverse when it is small enough)
   double* Adense = nullptr;
+  float* Adense32 = nullptr;  // FP32 copy of the coarsest inverse (FP32 contexts)
   double* gjwork = nullptr;
   int* gjpiv = nullptr;
   int64_t pin[2] = {-1, -1};

@@ -308,7 +308,7 @@ template <typename T>
 hipError_t launch_prolong_add(const Grid& gf, const Grid& gc, const T* dc, T* df,
                               hipStream_t s);
 template <typename T>
-hipError_t launch_dense_gemv(int64_t n, const double* Ainv, const T* r, T* d,
+hipError_t launch_dense_gemv(int64_t n, const T* Ainv, const T* r, T* d,
                              const int64_t* pin, int npin, hipStream_t s);
 template <typename T>
 hipError_t launch_fill(int64_t n, T v, T* y, hipStream_t s);

@@ -276,27 +276,26 @@ __global__ void prolong_add_kernel(Grid gf, Grid gc, const T* __restrict__ dc, T
   df[r] = (T)((double)df[r] + acc);
 }
 
-// d = Ainv r~, r~ = r with the pinned entries zeroed; one wave per row, 16-byte
-// loads of the row (n is even, so every row starts 16-byte aligned), four
-// loads in flight
+// d = Ainv r~, r~ = r with the pinned entries zeroed, the inverse stored in the
+// precision T of the vectors; one wave per row, pair loads of the row and of r
+// (n is even, so every row starts pair-aligned), eight loads in flight, sums
+// in FP64
 template <typename T>
-__global__ __launch_bounds__(256) void dense_gemv_kernel(int64_t n, const double* __restrict__ Ainv,
+__global__ __launch_bounds__(256) void dense_gemv_kernel(int64_t n, const T* __restrict__ Ainv,
                                                          const T* __restrict__ r, T* __restrict__ d,
                                                          int64_t pin0, int64_t pin1) {
-  // one wave per row, 16-byte loads of the row and of r, 8 loads in flight;
   // the pinned entries of r count as zero: their products are taken out once
   using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
   const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= n) return;
-  const double2* A = reinterpret_cast<const double2*>(Ainv + row * n);
+  const T2* A = reinterpret_cast<const T2*>(Ainv + row * n);
   const T2* r2 = reinterpret_cast<const T2*>(r);
   double acc0 = 0.0, acc1 = 0.0;
   const int64_t npair = n >> 1;
   int64_t q = lane;
   for (; q + 448 < npair; q += 512) {
-    double2 a[8];
-    T2 b[8];
+    T2 a[8], b[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       a[u] = A[q + 64 * u];
@@ -304,22 +303,22 @@ __global__ __launch_bounds__(256) void dense_gemv_kernel(int64_t n, const double
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      acc0 += a[u].x * (double)b[u].x;
-      acc1 += a[u].y * (double)b[u].y;
+      acc0 += (double)a[u].x * (double)b[u].x;
+      acc1 += (double)a[u].y * (double)b[u].y;
     }
   }
   for (; q < npair; q += 64) {
-    const double2 a = A[q];
+    const T2 a = A[q];
     const T2 b = r2[q];
-    acc0 += a.x * (double)b.x;
-    acc1 += a.y * (double)b.y;
+    acc0 += (double)a.x * (double)b.x;
+    acc1 += (double)a.y * (double)b.y;
   }
   double acc = acc0 + acc1;
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
   if (lane == 0) {
-    const double* Ar = Ainv + row * n;
-    if (pin0 >= 0) acc -= Ar[pin0] * (double)r[pin0];
-    if (pin1 >= 0) acc -= Ar[pin1] * (double)r[pin1];
+    const T* Ar = Ainv + row * n;
+    if (pin0 >= 0) acc -= (double)Ar[pin0] * (double)r[pin0];
+    if (pin1 >= 0) acc -= (double)Ar[pin1] * (double)r[pin1];
     d[row] = (T)acc;
   }
 }
@@ -457,10 +456,10 @@ hipError_t launch_prolong_add(const Grid& gf, const Grid& gc, const T* dc, T* df
 }
 
 template <typename T>
-hipError_t launch_dense_gemv(int64_t n, const double* Ainv, const T* r, T* d, const int64_t* pin,
+hipError_t launch_dense_gemv(int64_t n, const T* Ainv, const T* r, T* d, const int64_t* pin,
                              int npin, hipStream_t s) {
-  // space-time sizes are 2 ns: rows are 16-byte aligned; r is read in pairs
-  if ((n & 1) || ((uintptr_t)r % (2 * sizeof(T))) != 0 || ((uintptr_t)Ainv % 16) != 0)
+  // space-time sizes are 2 ns: rows are pair-aligned; A and r are read in pairs
+  if ((n & 1) || ((uintptr_t)r % (2 * sizeof(T))) != 0 || ((uintptr_t)Ainv % (2 * sizeof(T))) != 0)
     return hipErrorInvalidValue;
   const int64_t p0 = npin > 0 ? pin[0] : -1, p1 = npin > 1 ? pin[1] : -1;
   hipLaunchKernelGGL(dense_gemv_kernel<T>, dim3(nblk(n, 4)), dim3(256), 0, s, n, Ainv, r, d, p0,
@@ -482,7 +481,7 @@ hipError_t launch_fill(int64_t n, T v, T* y, hipStream_t s) {
   template hipError_t launch_restrict<T>(const Grid&, const Grid&, const T*, T*, hipStream_t);  \
   template hipError_t launch_prolong_add<T>(const Grid&, const Grid&, const T*, T*,             \
                                             hipStream_t);                                        \
-  template hipError_t launch_dense_gemv<T>(int64_t, const double*, const T*, T*, const int64_t*, \
+  template hipError_t launch_dense_gemv<T>(int64_t, const T*, const T*, T*, const int64_t*,     \
                                            int, hipStream_t);                                    \
   template hipError_t launch_fill<T>(int64_t, T, T*, hipStream_t);                               \
   template hipError_t launch_patch_sweep_c<T>(const Grid&, const T*, const T*, T*, double, int, \

@@ -332,3 +332,22 @@ def test_jacobian_precision_selection_without_device():
         assert rc == pnsmg.PNS_OK
         assert L.pns_set_jacobian_precision(h, pnsmg.BF16) == pnsmg.PNS_EUNSUPPORTED
         L.pns_ctx_destroy(h)
+
+
+def test_fp32_contexts_hold_an_fp32_copy_of_the_coarsest_inverse():
+    """The dense coarsest inverse is formed in FP64; an FP32 context keeps an
+    FP32 copy of it, which its V-cycles read (n^2 x 4 more bytes)."""
+    L = pnsmg.lib()
+    out = (ctypes.c_int64 * 4)()
+    ws = {}
+    for prec in (pnsmg.FP64, pnsmg.FP32):
+        rc, h = _create(n=(32, 32), levels=2, prec=prec)
+        assert rc == pnsmg.PNS_OK
+        assert L.pns_level_sizes(h, 1, out) == 0
+        n = out[0]
+        ws[prec] = L.pns_workspace_bytes(h)
+        L.pns_ctx_destroy(h)
+    assert n == 2 * (2 * 33 ** 2 + 3 * 256)
+    # every other buffer of the FP32 context is at most as large as in FP64
+    assert ws[pnsmg.FP64] >= n * n * 8
+    assert ws[pnsmg.FP32] >= n * n * 12 and ws[pnsmg.FP32] > ws[pnsmg.FP64]
