@@ -786,56 +786,128 @@ __global__ void gj_rowswap_copy_kernel(int64_t n, int64_t k0, int kb, double* __
   for (int q = 0; q < kb; ++q) T[(int64_t)q * n + j] = A[(k0 + q) * n + j];
 }
 
-// A[:,C] = [0 on rows K; A[O,C]] + P T   (64 x 64 output tile per workgroup)
+// A[:,C] = [0 on rows K; A[O,C]] + P T on the FP64 matrix cores.  64 x 64
+// output tile per workgroup (in the compressed column space that skips the
+// panel), each wave a 32 x 32 quarter held as 2 x 2 accumulator tiles of
+// v_mfma_f64_16x16x4f64: in a 16 x 16 tile lane l holds rows l/16 + 4 r
+// (r = 0..3) of column l%16; the A operand of a 16 x 4 block is row l%16,
+// k = l/16, the B operand of a 4 x 16 block k = l/16, column l%16.  The old
+// entries (zero on the rows K) are loaded first into registers of their own
+// and added after the products, so their latency overlaps the staging and the
+// matrix-core work; the tile's rows of P and columns of T pass through LDS in
+// chunks of 16 k,
+// double-buffered: the loads of chunk c + 1 are in flight while the matrix
+// cores work on chunk c (zero beyond kb and beyond the matrix).  32 KB of LDS
+// and a small register budget let several workgroups share a CU.
+// Tile order: workgroups are dealt round-robin to the 8 XCDs, so each XCD is
+// given a contiguous run of a sequence that walks all row tiles for a group
+// of kGjGc column tiles at a time (kGjGc consecutive tiles share a row tile):
+// the group's T tiles stay in the XCD's L2 and each P tile is fetched once
+// per group instead of once per tile.
+typedef double gj_d4 __attribute__((ext_vector_type(4)));
+constexpr int kGjKc = 16;  // k per staged chunk
+constexpr int kGjGc = 8;   // column tiles per group
+
 __global__ __launch_bounds__(256) void gj_update_kernel(int64_t n, int64_t k0, int kb,
                                                         double* __restrict__ A,
                                                         const double* __restrict__ P,
-                                                        const double* __restrict__ T) {
-  __shared__ double As[kGjNb][64 + 1];
-  __shared__ double Bs[kGjNb][64 + 1];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  const int64_t row0 = (int64_t)blockIdx.x * 64;
-  const int64_t m = n - kb;
-  const int64_t ccol0 = (int64_t)blockIdx.y * 64;  // in the compressed column space
-  for (int e = threadIdx.x; e < kb * 64; e += 256) {
-    const int k = e / 64, i = e % 64;
-    const int64_t r = row0 + i;
-    As[k][i] = r < n ? P[(int64_t)k * n + r] : 0.0;
-    const int64_t cc = ccol0 + i;
-    const int64_t col = cc < k0 ? cc : cc + kb;
-    Bs[k][i] = cc < m ? T[(int64_t)k * n + col] : 0.0;
-  }
-  __syncthreads();
-  double acc[4][4];
+                                                        const double* __restrict__ T,
+                                                        int row_tiles, int col_groups,
+                                                        int col_tiles) {
+  __shared__ double As[2][kGjKc][64];  // [buffer][k][row of the tile]
+  __shared__ double Bs[2][kGjKc][64];  // [buffer][k][column of the tile]
+  const int64_t seq = (int64_t)row_tiles * col_groups * kGjGc;
+  const int64_t per_xcd = (seq + 7) >> 3;
+  const int64_t pos = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (pos >= seq) return;
+  const int64_t grp = pos / ((int64_t)row_tiles * kGjGc), rem = pos % ((int64_t)row_tiles * kGjGc);
+  const int64_t ctile = grp * kGjGc + rem % kGjGc, rtile = rem / kGjGc;
+  if (ctile >= col_tiles) return;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int lr = l >> 4, lc = l & 15;
+  const int wr = w >> 1, wc = w & 1;
+  const int64_t row0 = rtile * 64;
+  const int64_t m = n - kb;  // > 0: the update is launched only then
+  const int64_t ccol0 = ctile * 64;
+  // column of A for a compressed column (clamped into [0, m))
+  auto acol = [&](int64_t cc) -> int64_t {
+    const int64_t c = cc < m ? cc : m - 1;
+    return c < k0 ? c : c + kb;
+  };
+  double Aold[2][2][4];
+  gj_d4 C[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int I = 0; I < 2; ++I)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  for (int k = 0; k < kb; ++k) {
-    double a[4], b[4];
+    for (int J = 0; J < 2; ++J) {
+      const int64_t col = acol(ccol0 + 32 * wc + 16 * J + lc);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = As[k][ty * 4 + i];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) b[j] = Bs[k][tx * 4 + j];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int64_t r = row0 + ty * 4 + i;
-    if (r >= n) continue;
-    const bool inK = r >= k0 && r < k0 + kb;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int64_t cc = ccol0 + tx * 4 + j;
-      if (cc >= m) continue;
-      const int64_t col = cc < k0 ? cc : cc + kb;
-      double* a = A + r * n + col;
-      *a = inK ? acc[i][j] : *a + acc[i][j];
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = row0 + 32 * wr + 16 * I + lr + 4 * r;
+        Aold[I][J][r] = A[(row < n ? row : n - 1) * n + col];
+        C[I][J][r] = 0.0;
+      }
     }
+  // this thread's share of a chunk: entries e = t + 256 u of the 16 x 64
+  // blocks of P and T
+  constexpr int kU = kGjKc * 64 / 256;
+  const int i0 = t & 63;
+  const int64_t r_ld = row0 + i0, cc_ld = ccol0 + i0;
+  const int64_t r_cl = r_ld < n ? r_ld : n - 1;
+  const int64_t c_cl = acol(cc_ld);
+  double pa[kU], tb[kU];
+  auto load_chunk = [&](int ch) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int k = ch * kGjKc + (t >> 6) + 4 * u;
+      const int kc = k < kb ? k : kb - 1;
+      const double pv = P[(int64_t)kc * n + r_cl];
+      const double tv = T[(int64_t)kc * n + c_cl];
+      pa[u] = (k < kb && r_ld < n) ? pv : 0.0;
+      tb[u] = (k < kb && cc_ld < m) ? tv : 0.0;
+    }
+  };
+  auto store_chunk = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      As[buf][(t >> 6) + 4 * u][i0] = pa[u];
+      Bs[buf][(t >> 6) + 4 * u][i0] = tb[u];
+    }
+  };
+  const int nch = (kb + kGjKc - 1) / kGjKc;
+  load_chunk(0);
+  store_chunk(0);
+  __syncthreads();
+  for (int ch = 0; ch < nch; ++ch) {
+    const int buf = ch & 1;
+    if (ch + 1 < nch) load_chunk(ch + 1);
+#pragma unroll
+    for (int q = 0; q < kGjKc / 4; ++q) {
+      const int k = 4 * q + lr;
+      const double a0 = As[buf][k][32 * wr + lc], a1 = As[buf][k][32 * wr + 16 + lc];
+      const double b0 = Bs[buf][k][32 * wc + lc], b1 = Bs[buf][k][32 * wc + 16 + lc];
+      C[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, C[0][0], 0, 0, 0);
+      C[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, C[0][1], 0, 0, 0);
+      C[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, C[1][0], 0, 0, 0);
+      C[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, C[1][1], 0, 0, 0);
+    }
+    if (ch + 1 < nch) store_chunk(buf ^ 1);
+    __syncthreads();
   }
+#pragma unroll
+  for (int I = 0; I < 2; ++I)
+#pragma unroll
+    for (int J = 0; J < 2; ++J) {
+      const int64_t cc = ccol0 + 32 * wc + 16 * J + lc;
+      if (cc >= m) continue;
+      const int64_t col = acol(cc);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = row0 + 32 * wr + 16 * I + lr + 4 * r;
+        const bool inK = row >= k0 && row < k0 + kb;
+        if (row < n) A[row * n + col] = inK ? C[I][J][r] : Aold[I][J][r] + C[I][J][r];
+      }
+    }
 }
 
 // columns back in reverse pivot order (thread per row)
@@ -979,9 +1051,12 @@ hipError_t coarse_invert(int64_t n, double* A, double* work, int* piv, int* stat
     const int64_t m = n - kb;
     if (m > 0) {
       hipLaunchKernelGGL(gj_rowswap_copy_kernel, dim3(nb), dim3(256), 0, s, n, k0, kb, A, piv, T);
-      dim3 grid((unsigned)((n + 63) / 64), (unsigned)((m + 63) / 64));
-      hipLaunchKernelGGL(gj_update_kernel, grid, dim3(256), 0, s, n, k0, kb, A, (const double*)Pf,
-                         (const double*)T);
+      const int rt = (int)((n + 63) / 64), ct = (int)((m + 63) / 64);
+      const int cg = (ct + kGjGc - 1) / kGjGc;
+      const int64_t seq = (int64_t)rt * cg * kGjGc;
+      const unsigned nwg = (unsigned)(((seq + 7) >> 3) * 8);
+      hipLaunchKernelGGL(gj_update_kernel, dim3(nwg), dim3(256), 0, s, n, k0, kb, A,
+                         (const double*)Pf, (const double*)T, rt, cg, ct);
     }
     hipLaunchKernelGGL(gj_panel_out_kernel, dim3(nb), dim3(256), 0, s, n, k0, kb, A,
                        (const double*)Pf);
