@@ -453,6 +453,24 @@ def run(args):
             torch.cuda.synchronize()
             t_vc_graph = float(np.median([a.elapsed_time(b) for a, b in tg])) * 1e-3
             ctx.pns_set_vcycle_graph(0)
+        # the benchmarked V-cycle as a stationary iteration x <- x + V(b - A x) on a
+        # consistent system b = A x_true from x = 0 (the operator has the constant
+        # pressure as null vector, so b is taken in its range): geometric mean of
+        # the residual reduction per V-cycle over 10 V-cycles, and the last ratio
+        rho_vc = None
+        if not args.apply_only:
+            xt = torch.tensor(inputs.uniform(204, sz["nst"]), dtype=ctx.dtype, device=dev)
+            bt, xs, res = ctx.vector(), ctx.vector(), ctx.vector()
+            ctx.pns_cell_apply(xt, bt)
+            res.copy_(bt)
+            norms = [float(torch.linalg.vector_norm(res.double()))]
+            for _ in range(10):
+                ctx.pns_vcycle(2, 2, OMEGA, res, d)
+                xs += d
+                ctx.pns_cell_defect(bt, xs, res)
+                norms.append(float(torch.linalg.vector_norm(res.double())))
+            rho_vc = dict(mean=(norms[-1] / norms[0]) ** 0.1, last=norms[-1] / norms[-2])
+            del xt, bt, xs, res
         elem = 8 if prec == pnsmg.FP64 else 4
         results[name] = dict(
             nst=sz["nst"], cells=sz["cells"], wall_s=wall, ms_per_step=wall / args.steps * 1e3,
@@ -461,7 +479,8 @@ def run(args):
             apply_s_p90=float(np.percentile(t_apply, 90)), apply_s_cached=t_cached,
             apply_s_ordered=t_ordered,
             vcycle_s_median=float(np.median(t_vc)) if not args.apply_only else None,
-            vcycle_s_graph=t_vc_graph, setup_s=t_setup, bytes=algorithmic_bytes(sz, elem))
+            vcycle_s_graph=t_vc_graph, setup_s=t_setup, bytes=algorithmic_bytes(sz, elem),
+            vcycle_rho=rho_vc)
         print(f"[bench] {name}: apply {np.mean(t_apply) * 1e6:.1f} us mean in step "
               f"(p50 {np.median(t_apply) * 1e6:.1f}), cached tangent {t_cached * 1e6:.1f} us "
               f"back-to-back; V-cycle "
@@ -806,6 +825,13 @@ def main():
         "vcycle_s_graph_fp64_fp32": [f64["vcycle_s_graph"], f32["vcycle_s_graph"]],
         "setup_s_fp64": f64["setup_s"],
         "setup_s_fp32": f32["setup_s"],
+        # residual reduction per V-cycle used as a stationary iteration on a
+        # consistent system (geometric mean over 10, last ratio), FP64 / FP32
+        "vcycle_residual_reduction": None if args.apply_only else {
+            "mean_fp64_fp32": [round(f64["vcycle_rho"]["mean"], 4),
+                               round(f32["vcycle_rho"]["mean"], 4)],
+            "last_fp64_fp32": [round(f64["vcycle_rho"]["last"], 4),
+                               round(f32["vcycle_rho"]["last"], 4)]},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3),
                      "peak": FP64_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / FP64_VALU_PEAK_TFLOPS, 4),

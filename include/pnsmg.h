@@ -522,6 +522,10 @@ int pns_server_create(int slots, void* arena_dev, size_t arena_bytes, pns_server
 
 /* Queue a request (Sec. 6-6.2 slab solve, as pns_solve); the request struct and
  * v_prev_host are copied, U_host must stay valid until the request is DONE.
+ * The solve starts from U = 0; if that attempt stops with PNS_ENOTCONV, a
+ * second one starts from the left trace at both Radau nodes (zero pressure),
+ * and the result's status, residuals and iterate are the second attempt's,
+ * its iteration counts the sums over both.
  * *ticket identifies it.  PNS_EINVAL if the request is invalid,
  * PNS_EWORKSPACE if its footprint exceeds the whole arena. */
 int pns_solve_request(pns_server* srv, const pns_request* req, uint64_t* ticket);

@@ -168,19 +168,33 @@ int run_request(Req* r, hipStream_t s, pns_solve_info* info) {
   if ((rc = pns_bind_workspace(c, ws, r->sz.ws)) == PNS_OK &&
       (rc = pns_set_patch_kind(c, q.patch_kind)) == PNS_OK &&
       (rc = pns_set_vcycle_graph(c, q.vcycle_graph ? 1 : 0)) == PNS_OK) {
-    // initial guess: the left trace at both Radau nodes, zero pressure; the
-    // host copy of the left trace is released once it is on the device
+    // the host copy of the left trace is released once it is on the device
     bool ok = hipMemcpyAsync(vp, r->vprev.data(), nv * 8, hipMemcpyHostToDevice, s) == hipSuccess &&
               hipStreamSynchronize(s) == hipSuccess;
     std::vector<double>().swap(r->vprev);
     r->q.v_prev_host = nullptr;
-    ok = ok && hipMemsetAsync(U, 0, r->sz.nst * 8, s) == hipSuccess &&
-         hipMemcpyAsync(U, vp, nv * 8, hipMemcpyDeviceToDevice, s) == hipSuccess &&
-         hipMemcpyAsync(U + ns, vp, nv * 8, hipMemcpyDeviceToDevice, s) == hipSuccess;
+    // first attempt from U = 0 (the first linearisation then has a uniform
+    // viscosity); if it stops with PNS_ENOTCONV, a second attempt starts from
+    // the left trace at both Radau nodes with zero pressure
+    ok = ok && hipMemsetAsync(U, 0, r->sz.nst * 8, s) == hipSuccess;
     if (!ok) {
       rc = PNS_EHIP;
     } else {
       rc = pns_solve(c, &q.model, vp, U, &q.params, work, r->sz.solve, info);
+      if (rc == PNS_ENOTCONV) {
+        pns_solve_info first = *info;
+        if (hipMemsetAsync(U, 0, r->sz.nst * 8, s) != hipSuccess ||
+            hipMemcpyAsync(U, vp, nv * 8, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(U + ns, vp, nv * 8, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+          rc = PNS_EHIP;
+        } else {
+          rc = pns_solve(c, &q.model, vp, U, &q.params, work, r->sz.solve, info);
+          info->newton_iterations += first.newton_iterations;
+          info->krylov_iterations += first.krylov_iterations;
+          info->smoother_setups += first.smoother_setups;
+          info->backtracks += first.backtracks;
+        }
+      }
       if (rc == PNS_OK || rc == PNS_ENOTCONV || rc == PNS_ENONFINITE) {
         if (hipMemcpyAsync(q.U_host, U, r->sz.nst * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)

@@ -1,12 +1,14 @@
 """GPU tests of the request server (continuous batching of independent slab
 solves) through the C-ABI.
 
-Each served result is compared with a direct pns_solve of the same request
-and with the same request served inside a mix: both reach the same stopping
-test along the same iteration path, so they agree far below the solve
-tolerance (the only difference is the summation order of LDS sums inside the
-Jacobian action); 1e-9 relative is required.  The oracle's residual of a
-served result must meet the stopping test.
+A served request starts from U = 0 and, if that attempt stops with
+PNS_ENOTCONV, once more from the left trace.  Each served result is compared
+with a direct pns_solve of the same request from the same initial guess and
+with the same request served inside a mix: both reach the same stopping test
+along the same iteration path, so they agree far below the solve tolerance
+(the only difference is the summation order of LDS sums inside the Jacobian
+action); 1e-9 relative is required.  The oracle's residual of a served result
+must meet the stopping test.
 """
 import time
 
@@ -39,15 +41,17 @@ def request(n, seed, levels, precision=pnsmg.FP64, model=MODEL, **params):
     return q, vprev, U
 
 
-def direct_solve(n, seed, levels, precision=pnsmg.FP64, model=MODEL):
+def direct_solve(n, seed, levels, precision=pnsmg.FP64, model=MODEL, from_trace=False,
+                 patch_kind=None, **params):
     vprev = inputs.sin_series_velocity(n, seed=seed, t_nodes=[0.0])
-    ctx = pnsmg.Context(n, n_levels=levels, precision=precision)
+    ctx = pnsmg.Context(n, n_levels=levels, precision=precision, patch_kind=patch_kind)
     sz = ctx.sizes(0)
     U0 = np.zeros(sz["nst"])
-    U0[:sz["nv"]] = vprev
-    U0[sz["ns"]:sz["ns"] + sz["nv"]] = vprev
+    if from_trace:
+        U0[:sz["nv"]] = vprev
+        U0[sz["ns"]:sz["ns"] + sz["nv"]] = vprev
     U = torch.tensor(U0, device="cuda")
-    rc, info = ctx.pns_solve(model, torch.tensor(vprev, device="cuda"), U)
+    rc, info = ctx.pns_solve(model, torch.tensor(vprev, device="cuda"), U, **params)
     torch.cuda.synchronize()
     return rc, info, U.cpu().numpy()
 
@@ -71,10 +75,41 @@ def test_served_result_equals_direct_solve_and_oracle_residual():
     assert rel(U, Ud) <= 1e-9
     prob = O.Problem(n=n, p=MODEL["p"], delta=MODEL["delta"], nu=MODEL["nu"],
                      nu_inf=MODEL["nu_inf"], lin=O.MODIFIED_NEWTON)
-    r0 = O.mass_norm(prob, O.residual(prob, O.state_from_velocity(
-        prob, np.concatenate([vprev, vprev])), vprev))
+    r0 = O.mass_norm(prob, O.residual(prob, np.zeros(prob.nst), vprev))
     r = O.mass_norm(prob, O.residual(prob, U, vprev))
     assert r <= 1.05 * 1e-8 * r0
+
+
+def test_request_that_stalls_from_zero_is_solved_from_the_left_trace():
+    """A low-p request whose solve from U = 0 needs more Newton steps than the
+    limit, while the one from the left trace needs fewer: the server's second
+    attempt returns the trace-started solve (same iterate), with the iteration
+    counts of both attempts summed."""
+    n, seed, levels = (32, 32), 503, 3
+    model = dict(MODEL, p=1.2216916515341412, delta=0.007985874701397328,
+                 nu_inf=0.0008305981091400222, nu=1.0)
+    prm = dict(omega=0.2, rho=0.5, max_krylov=150)
+    kind = pnsmg.PATCH_EXACT
+    rc0, info0, _ = direct_solve(n, seed, levels, model=model, patch_kind=kind, max_newton=60, **prm)
+    rct, infot, _ = direct_solve(n, seed, levels, model=model, from_trace=True, patch_kind=kind,
+                                 max_newton=60, **prm)
+    print("from zero", rc0, info0, "from the trace", rct, infot)
+    assert rc0 == pnsmg.PNS_OK and rct == pnsmg.PNS_OK
+    assert infot["newton_iterations"] < info0["newton_iterations"]
+    limit = info0["newton_iterations"] - 1
+    rcz, infoz, _ = direct_solve(n, seed, levels, model=model, patch_kind=kind,
+                                 max_newton=limit, **prm)
+    rct2, infot2, Ut = direct_solve(n, seed, levels, model=model, from_trace=True,
+                                    patch_kind=kind, max_newton=limit, **prm)
+    assert rcz == pnsmg.PNS_ENOTCONV and rct2 == pnsmg.PNS_OK
+    srv = pnsmg.Server(slots=1, arena_bytes=256 << 20)
+    q, vprev, U = request(n, seed, levels, model=model, patch_kind=kind, max_newton=limit, **prm)
+    res = srv.wait(srv.submit(q, keep=(vprev, U)))
+    srv.close()
+    print("served", res)
+    assert res["status"] == pnsmg.PNS_OK
+    assert res["newton_iterations"] == infoz["newton_iterations"] + infot2["newton_iterations"]
+    assert rel(U, Ut) <= 1e-9
 
 
 def test_result_is_the_same_alone_and_in_a_mix():
