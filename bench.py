@@ -491,6 +491,51 @@ def run(args):
     return results
 
 
+def vcycle_marked(args):
+    """The benchmarked V-cycle alone (FP64, then FP32): smoother setup, 5
+    warm-up V-cycles, then args.steps V-cycles between two launches of
+    torch.flip, which mark them in a kernel trace.  Returns the event-timed
+    median per V-cycle and precision."""
+    import numpy as np
+    import torch
+
+    from paper_2603_28706_amd import inputs, pnsmg
+
+    dev = torch.device("cuda:0")
+    n = (args.n, args.n)
+    uk = torch.tensor(inputs.sin_series_velocity(n, seed=201, t_nodes=[0.01 / 3, 0.01]),
+                      dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    out = {}
+    for prec, name in ((pnsmg.FP64, "fp64"), (pnsmg.FP32, "fp32")):
+        ctx = pnsmg.Context(n, n_levels=args.levels, precision=prec, tau=0.01, device="cuda:0")
+        ctx.pns_set_state(dict(MODEL, lin=args.lin), uk)
+        ctx.pns_vanka_setup()
+        sz = ctx.sizes(0)
+        r = torch.tensor(inputs.uniform(203, sz["nst"]), dtype=ctx.dtype, device=dev)
+        d = ctx.vector()
+        for _ in range(5):
+            ctx.pns_vcycle(2, 2, OMEGA, r, d)
+        mark = torch.arange(8, device=dev)
+        torch.cuda.synchronize()
+        torch.flip(mark, dims=[0])
+        evs = []
+        for _ in range(args.steps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            ctx.pns_vcycle(2, 2, OMEGA, r, d)
+            b.record(stream)
+            evs.append((a, b))
+        torch.flip(mark, dims=[0])
+        torch.cuda.synchronize()
+        out[name] = {"vcycles": args.steps,
+                     "median_ms": float(np.median([a.elapsed_time(b) for a, b in evs]))}
+        print(f"[bench] marked V-cycles {name}: {out[name]}", file=sys.stderr, flush=True)
+        del ctx
+        torch.cuda.empty_cache()
+    return out
+
+
 def solve_latency(n, seeds, rtol=1e-8):
     """Time-to-rtol of independent slab solves (Newton-FGMRES, one V-cycle per
     Krylov step) at n x n, one per seed of the left-trace velocity, in FP64
@@ -776,6 +821,10 @@ def main():
     ap.add_argument("--lin", type=int, default=2, help="0 Picard, 1 exact Newton, 2 modified Newton")
     ap.add_argument("--setup3d-only", action="store_true",
                     help="only time --steps exact-patch 3D setups (profiling runs)")
+    ap.add_argument("--vcycle-only", action="store_true",
+                    help="only the 256^2 4-level V-cycles, FP64 then FP32: setup, 5 warm-up "
+                         "V-cycles, then --steps V-cycles between two torch.flip launches "
+                         "that mark them in a kernel trace (per-phase breakdown runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -783,6 +832,9 @@ def main():
         sys.exit(2)
     if args.setup3d_only:
         print(json.dumps({"exact_setup3d": exact_setup3d(32, max(1, args.steps))}), flush=True)
+        return
+    if args.vcycle_only:
+        print(json.dumps({"vcycle_marked": vcycle_marked(args)}), flush=True)
         return
     res = run(args)
     f64, f32 = res["fp64"], res["fp32"]
