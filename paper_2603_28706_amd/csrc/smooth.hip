@@ -277,49 +277,67 @@ __global__ void prolong_add_kernel(Grid gf, Grid gc, const T* __restrict__ dc, T
 }
 
 // d = Ainv r~, r~ = r with the pinned entries zeroed, the inverse stored in the
-// precision T of the vectors; one wave per row, pair loads of the row and of r
-// (n is even, so every row starts pair-aligned), eight loads in flight, sums
-// in FP64
+// precision T of the vectors; one wave per kGemvRows consecutive rows, so each
+// load of r serves kGemvRows rows (r is re-read from cache once per row group,
+// not once per row); pair loads of the rows and of r (n is even, so every row
+// starts pair-aligned), four steps in flight, sums in FP64
+constexpr int kGemvRows = 4;
+
 template <typename T>
 __global__ __launch_bounds__(256) void dense_gemv_kernel(int64_t n, const T* __restrict__ Ainv,
                                                          const T* __restrict__ r, T* __restrict__ d,
                                                          int64_t pin0, int64_t pin1) {
   // the pinned entries of r count as zero: their products are taken out once
   using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kGemvRows;
   const int lane = threadIdx.x & 63;
-  if (row >= n) return;
-  const T2* A = reinterpret_cast<const T2*>(Ainv + row * n);
+  if (row0 >= n) return;
+  // rows past the end repeat the last row (their results are not stored)
+  const T2* A[kGemvRows];
+#pragma unroll
+  for (int k = 0; k < kGemvRows; ++k)
+    A[k] = reinterpret_cast<const T2*>(Ainv + (row0 + k < n ? row0 + k : n - 1) * n);
   const T2* r2 = reinterpret_cast<const T2*>(r);
-  double acc0 = 0.0, acc1 = 0.0;
+  double acc[kGemvRows][2];
+#pragma unroll
+  for (int k = 0; k < kGemvRows; ++k) acc[k][0] = acc[k][1] = 0.0;
   const int64_t npair = n >> 1;
   int64_t q = lane;
-  for (; q + 448 < npair; q += 512) {
-    T2 a[8], b[8];
+  for (; q + 192 < npair; q += 256) {
+    T2 b[4], a[4][kGemvRows];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      a[u] = A[q + 64 * u];
+    for (int u = 0; u < 4; ++u) {
       b[u] = r2[q + 64 * u];
+#pragma unroll
+      for (int k = 0; k < kGemvRows; ++k) a[u][k] = A[k][q + 64 * u];
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      acc0 += (double)a[u].x * (double)b[u].x;
-      acc1 += (double)a[u].y * (double)b[u].y;
-    }
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < kGemvRows; ++k) {
+        acc[k][0] += (double)a[u][k].x * (double)b[u].x;
+        acc[k][1] += (double)a[u][k].y * (double)b[u].y;
+      }
   }
   for (; q < npair; q += 64) {
-    const T2 a = A[q];
     const T2 b = r2[q];
-    acc0 += (double)a.x * (double)b.x;
-    acc1 += (double)a.y * (double)b.y;
+#pragma unroll
+    for (int k = 0; k < kGemvRows; ++k) {
+      const T2 a = A[k][q];
+      acc[k][0] += (double)a.x * (double)b.x;
+      acc[k][1] += (double)a.y * (double)b.y;
+    }
   }
-  double acc = acc0 + acc1;
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-  if (lane == 0) {
-    const T* Ar = Ainv + row * n;
-    if (pin0 >= 0) acc -= (double)Ar[pin0] * (double)r[pin0];
-    if (pin1 >= 0) acc -= (double)Ar[pin1] * (double)r[pin1];
-    d[row] = (T)acc;
+#pragma unroll
+  for (int k = 0; k < kGemvRows; ++k) {
+    double s = acc[k][0] + acc[k][1];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0 && row0 + k < n) {
+      const T* Ar = Ainv + (row0 + k) * n;
+      if (pin0 >= 0) s -= (double)Ar[pin0] * (double)r[pin0];
+      if (pin1 >= 0) s -= (double)Ar[pin1] * (double)r[pin1];
+      d[row0 + k] = (T)s;
+    }
   }
 }
 
@@ -462,8 +480,8 @@ hipError_t launch_dense_gemv(int64_t n, const T* Ainv, const T* r, T* d, const i
   if ((n & 1) || ((uintptr_t)r % (2 * sizeof(T))) != 0 || ((uintptr_t)Ainv % (2 * sizeof(T))) != 0)
     return hipErrorInvalidValue;
   const int64_t p0 = npin > 0 ? pin[0] : -1, p1 = npin > 1 ? pin[1] : -1;
-  hipLaunchKernelGGL(dense_gemv_kernel<T>, dim3(nblk(n, 4)), dim3(256), 0, s, n, Ainv, r, d, p0,
-                     p1);
+  hipLaunchKernelGGL(dense_gemv_kernel<T>, dim3(nblk(n, 4 * kGemvRows)), dim3(256), 0, s, n, Ainv,
+                     r, d, p0, p1);
   return hipGetLastError();
 }
 
