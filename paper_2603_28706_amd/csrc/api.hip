@@ -190,7 +190,7 @@ hipError_t defect(pns_ctx* c, int l, const T* b, const T* x, T* y,
     return launch_cip<T>(L.g, c->model, c->disc.tau, (const T*)c->uk, L.g.nv, x, y, -1.0,
                          sc ? sc->cip : c->cipG, c->stream);
   }
-  hipError_t e = launch_ebe_apply<T>(L.g, (const T*)L.E, x, b, y, 1, c->stream);
+  hipError_t e = launch_ebe_apply<T>(L.g, (const T*)L.E, x, b, y, 1, c->sweep_var[l], c->stream);
   if (e != hipSuccess || !(c->model.gamma_cip > 0.0)) return e;
   return launch_cip_level<T>(L.g, L.S, x, y, -1.0, sc ? sc->cip : c->cipG, c->stream);
 }
@@ -211,7 +211,7 @@ hipError_t apply_level(pns_ctx* c, int l, const T* x, T* y) {
     return launch_cip<T>(L.g, c->model, c->disc.tau, (const T*)c->uk, L.g.nv, x, y, 1.0, c->cipG,
                          c->stream);
   }
-  hipError_t e = launch_ebe_apply<T>(L.g, (const T*)L.E, x, x, y, 0, c->stream);
+  hipError_t e = launch_ebe_apply<T>(L.g, (const T*)L.E, x, x, y, 0, c->sweep_var[l], c->stream);
   if (e != hipSuccess || !(c->model.gamma_cip > 0.0)) return e;
   return launch_cip_level<T>(L.g, L.S, x, y, 1.0, c->cipG, c->stream);
 }
@@ -479,7 +479,7 @@ int vanka_setup_impl(pns_ctx* c, const uint16_t* masks) {
     else
       PNS_HIP(c, launch_galerkin(L.g, c->lev[l - 1].E64, L.E64, s));
     if (cip) PNS_HIP(c, launch_cip_restrict(L.g, c->lev[l - 1].g, c->lev[l - 1].S, L.S, s));
-    PNS_HIP(c, launch_transpose_convert<T>(L.g.nc, L.E64, (T*)L.E, s));
+    PNS_HIP(c, launch_transpose_convert<T>(L.g, L.E64, (T*)L.E, s));
     PNS_HIP(c, launch_level_patches<T>(L.g, L.E64, cip ? L.S : nullptr, (T*)L.inv, c->status,
                                        s));
   }

@@ -266,8 +266,12 @@ template <typename T>
 hipError_t launch_exact_fine_patches(const Grid& g, double tau, const double* Es0,
                                      const double* Es1, const double* S, const uint16_t* masks,
                                      T* inv, int* status, hipStream_t s);
+// E (row-major per cell, cell order) -> Et: transposed (column-major per
+// cell) in the context precision, stored at patch_slot(g, cx, cy), the order of
+// the patch inverses, so that the element-by-element action can stream them
+// with the sweep kernels
 template <typename T>
-hipError_t launch_transpose_convert(int64_t ncells, const double* E, T* Et, hipStream_t s);
+hipError_t launch_transpose_convert(const Grid& g, const double* E, T* Et, hipStream_t s);
 template <typename T>
 hipError_t launch_level_patches(const Grid& g, const double* E, const double* S, T* inv,
                                 int* status, hipStream_t s);
@@ -285,9 +289,12 @@ hipError_t coarse_invert(int64_t n, double* A, double* work, int* piv, int* stat
                          hipStream_t s);
 
 // smooth.hip
+// coarse-level action with the transposed element matrices in patch-slot
+// order (mode 0: y = A x, mode 1: y = b - A x), through the real-patch sweep
+// kernel of variant `variant`
 template <typename T>
 hipError_t launch_ebe_apply(const Grid& g, const T* E, const T* x, const T* b, T* y, int mode,
-                            hipStream_t s);
+                            int variant, hipStream_t s);
 // additive Vanka step with sweep variant `variant` (real 42x42 or complex 21x21
 // patches); variants differ in workgroup size, loads in flight and rows per
 // lane, not in what they compute

@@ -491,14 +491,15 @@ __global__ __launch_bounds__(64) void patch_complex_kernel(Grid g, double tau,
 }
 
 template <typename T>
-__global__ void transpose_convert_kernel(int64_t ncells, const double* __restrict__ E,
+__global__ void transpose_convert_kernel(Grid g, const double* __restrict__ E,
                                          T* __restrict__ Et) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= ncells * kNst * kNst) return;
+  if (i >= g.nc * kNst * kNst) return;
   const int64_t c = i / (kNst * kNst);
   const int e = (int)(i % (kNst * kNst));
   const int col = e / kNst, row = e % kNst;  // output index = col*42 + row
-  Et[i] = (T)E[c * (kNst * kNst) + row * kNst + col];
+  const int64_t slot = patch_slot(g, (int)(c % g.nx), (int)(c / g.nx));
+  Et[slot * (kNst * kNst) + e] = (T)E[c * (kNst * kNst) + row * kNst + col];
 }
 
 // ---------------------------------------------------------------- Galerkin
@@ -980,10 +981,10 @@ hipError_t launch_exact_fine_patches(const Grid& g, double tau, const double* Es
 }
 
 template <typename T>
-hipError_t launch_transpose_convert(int64_t ncells, const double* E, T* Et, hipStream_t s) {
-  const int64_t n = ncells * kNst * kNst;
+hipError_t launch_transpose_convert(const Grid& g, const double* E, T* Et, hipStream_t s) {
+  const int64_t n = g.nc * kNst * kNst;
   hipLaunchKernelGGL(transpose_convert_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                     s, ncells, E, Et);
+                     s, g, E, Et);
   return hipGetLastError();
 }
 
@@ -1077,8 +1078,8 @@ template hipError_t launch_exact_fine_patches<double>(const Grid&, double, const
 template hipError_t launch_exact_fine_patches<float>(const Grid&, double, const double*,
                                                      const double*, const double*,
                                                      const uint16_t*, float*, int*, hipStream_t);
-template hipError_t launch_transpose_convert<double>(int64_t, const double*, double*, hipStream_t);
-template hipError_t launch_transpose_convert<float>(int64_t, const double*, float*, hipStream_t);
+template hipError_t launch_transpose_convert<double>(const Grid&, const double*, double*, hipStream_t);
+template hipError_t launch_transpose_convert<float>(const Grid&, const double*, float*, hipStream_t);
 template hipError_t launch_level_patches<double>(const Grid&, const double*, const double*,
                                                  double*, int*, hipStream_t);
 template hipError_t launch_level_patches<float>(const Grid&, const double*, const double*, float*,

@@ -1,8 +1,9 @@
 // Per-iteration smoother and transfer kernels (Sec. 6.3):
-// * coarse-level operator action with Galerkin element matrices: one wave per
-//   cell, transposed (column-major) element matrices streamed with coalesced
-//   loads, four colour launches (cells of one parity class share no unknown)
-//   adding into y initialised to 0 or b;
+// * coarse-level operator action with Galerkin element matrices: the
+//   transposed (column-major) element matrices are stored like the patch
+//   inverses, so the sweep kernels below stream them (omega = +-1), four colour
+//   launches (cells of one parity class share no unknown) adding into y
+//   initialised to 0 or b;
 // * additive Vanka update d += omega sum_K R_K^T A_K^{-1} R_K res,
 //   eq. (stmg-vanka-update): the stored patch inverses streamed column by
 //   column (level 0: complex 21x21 time-diagonal form, three patches per wave;
@@ -28,37 +29,6 @@ __device__ __forceinline__ int64_t gidx(const Grid& g, int cx, int cy, int l) {
            (2 * cx + a % 3);
   }
   return (int64_t)mu * g.ns + g.nv + 3 * ((int64_t)cy * g.nx + cx) + (i - 18);
-}
-
-// one wave per cell of the colour class (px, py): lane r < 42 forms row r of
-// E_c x_c from the transposed element matrix (coalesced column loads) and adds
-// sign * row into y; cells of one class share no unknown
-template <typename T>
-__global__ __launch_bounds__(256) void ebe_color_kernel(Grid g, const T* __restrict__ Et,
-                                                        const T* __restrict__ x,
-                                                        T* __restrict__ y, T sign, int px, int py,
-                                                        int ncx, int ncy) {
-  __shared__ T xs[4][kNst];
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t pid = (int64_t)blockIdx.x * 4 + w;
-  const bool active = pid < (int64_t)ncx * ncy;
-  int cx = 0, cy = 0;
-  int64_t gi = 0;
-  if (active) {
-    cx = px + 2 * (int)(pid % ncx);
-    cy = py + 2 * (int)(pid / ncx);
-    if (lane < kNst) {
-      gi = gidx(g, cx, cy, lane);
-      xs[w][lane] = x[gi];
-    }
-  }
-  __syncthreads();
-  if (!active || lane >= kNst) return;
-  const T* A = Et + ((int64_t)cy * g.nx + cx) * (kNst * kNst);
-  T acc = 0;
-#pragma unroll 6
-  for (int j = 0; j < kNst; ++j) acc += A[j * kNst + lane] * xs[w][j];
-  y[gi] += sign * acc;
 }
 
 // Real 42x42 patches, one wave per patch of the colour class (px, py), lane r
@@ -351,27 +321,6 @@ inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
 
-// E: transposed element matrices (column-major per cell); mode 0: y = A x,
-// mode 1: y = b - A x
-template <typename T>
-hipError_t launch_ebe_apply(const Grid& g, const T* E, const T* x, const T* b, T* y, int mode,
-                            hipStream_t s) {
-  if (mode == 0)
-    hipLaunchKernelGGL(fill_kernel<T>, dim3(nblk(g.nst, 256)), dim3(256), 0, s, g.nst, (T)0, y);
-  else
-    hipLaunchKernelGGL(copy_kernel<T>, dim3(nblk(g.nst, 256)), dim3(256), 0, s, g.nst, b, y);
-  const T sign = mode == 0 ? (T)1 : (T)-1;
-  for (int c = 0; c < 4; ++c) {
-    const int px = c & 1, py = c >> 1;
-    const int ncx = (g.nx - px + 1) / 2, ncy = (g.ny - py + 1) / 2;
-    const int64_t np = (int64_t)ncx * ncy;
-    if (np == 0) continue;
-    hipLaunchKernelGGL(ebe_color_kernel<T>, dim3(nblk(np, 4)), dim3(256), 0, s, g, E, x, y, sign,
-                       px, py, ncx, ncy);
-  }
-  return hipGetLastError();
-}
-
 template <typename T>
 hipError_t launch_copy(int64_t n, const T* x, T* y, hipStream_t s) {
   hipLaunchKernelGGL(copy_kernel<T>, dim3(nblk(n, 256)), dim3(256), 0, s, n, x, y);
@@ -460,6 +409,23 @@ hipError_t launch_patch_sweep_c(const Grid& g, const T* inv, const T* res, T* d,
   return complex_variants<T>()[variant].fn(g, inv, res, d, omega, s);
 }
 
+// Coarse-level action from the transposed element matrices, stored per cell
+// at its patch slot: y = 0 (mode 0) or b (mode 1), then y += sign E_c x_c per
+// cell, which is the additive patch step with the element matrices in place of
+// the inverses (omega = sign), in the four colour passes of the level's sweep
+// variant (cells of one colour share no unknown)
+template <typename T>
+hipError_t launch_ebe_apply(const Grid& g, const T* E, const T* x, const T* b, T* y, int mode,
+                            int variant, hipStream_t s) {
+  if (mode == 0)
+    hipLaunchKernelGGL(fill_kernel<T>, dim3(nblk(g.nst, 256)), dim3(256), 0, s, g.nst, (T)0, y);
+  else
+    hipLaunchKernelGGL(copy_kernel<T>, dim3(nblk(g.nst, 256)), dim3(256), 0, s, g.nst, b, y);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return real_variants<T>()[variant].fn(g, E, x, y, mode == 0 ? 1.0 : -1.0, s);
+}
+
 template <typename T>
 hipError_t launch_restrict(const Grid& gf, const Grid& gc, const T* rf, T* rc, hipStream_t s) {
   hipLaunchKernelGGL(restrict_kernel<T>, dim3(nblk(gc.nst, 256)), dim3(256), 0, s, gf, gc, rf, rc);
@@ -493,7 +459,7 @@ hipError_t launch_fill(int64_t n, T v, T* y, hipStream_t s) {
 
 #define PNS_INST(T)                                                                              \
   template hipError_t launch_ebe_apply<T>(const Grid&, const T*, const T*, const T*, T*, int,   \
-                                          hipStream_t);                                          \
+                                          int, hipStream_t);                                     \
   template hipError_t launch_patch_sweep<T>(const Grid&, const T*, const T*, T*, double, int,   \
                                             hipStream_t);                                        \
   template hipError_t launch_restrict<T>(const Grid&, const Grid&, const T*, T*, hipStream_t);  \
