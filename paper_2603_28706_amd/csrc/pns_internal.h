@@ -280,10 +280,13 @@ hipError_t launch_galerkin_from_fine(const Grid& gc, double tau, const double* E
 hipError_t launch_galerkin(const Grid& gc, const double* Ef, double* Ec, hipStream_t s);
 hipError_t launch_coarse_assemble(const Grid& g, const double* E, double* Adense,
                                   hipStream_t s);
-// doubles of work coarse_invert needs: two n x 64 panel copies, the 64 x n row
-// block, per-block pivot candidates of the panel steps (value and row, twice)
+// panel width of the blocked coarse Gauss-Jordan inversion
+constexpr int kGjNb = 128;
+// doubles of work coarse_invert needs: two n x kGjNb panel copies, the
+// kGjNb x n row block, per-block pivot candidates of the panel steps (value
+// and row, twice)
 inline int64_t coarse_invert_work_doubles(int64_t n) {
-  return 3 * 64 * n + 4 * ((n + 63) / 64) + 8;
+  return 3 * (int64_t)kGjNb * n + 4 * ((n + 63) / 64) + 8;
 }
 hipError_t coarse_invert(int64_t n, double* A, double* work, int* piv, int* status,
                          hipStream_t s);

@@ -638,7 +638,6 @@ __global__ void pin_kernel(int64_t n, double* A, const int64_t* pin, int npin) {
 // every other column is updated as A[:,C] = [0 on rows K; A[O,C]] + P T, which
 // is the block form of the Gauss-Jordan step; (4) the panel is written back.
 // At the end the columns are permuted back in reverse pivot order.
-constexpr int kGjNb = 64;
 
 __global__ void gj_panel_in_kernel(int64_t n, int64_t k0, int kb, const double* __restrict__ A,
                                    double* __restrict__ P) {

@@ -161,7 +161,7 @@ def test_3d_context_layout_and_rejections():
             + 33574 * 8 + 512 * 2 * 85 * 85 * 8
             + 4886 * 8 * 3 + 64 * kE * 16 + 64 * kE * 8
             + 814 * 8 * 3 + 8 * kE * 16
-            + 814 * 814 * 8 + (3 * 64 * 814 + 4 * 13 + 8) * 8 + 814 * 4
+            + 814 * 814 * 8 + (3 * 128 * 814 + 4 * 13 + 8) * 8 + 814 * 4
             + 2 * lift3(8, 8, 8))
     assert need <= L.pns_workspace_bytes(h) < need + 8192
     L.pns_ctx_destroy(h)
