@@ -769,6 +769,135 @@ __global__ __launch_bounds__(256) void gj_panel_step_kernel(
   }
 }
 
+// Small matrices (n <= kGjSmallRows, e.g. an 8 x 8 coarsest level): the
+// elimination of a whole panel of kb <= kGjSmallNb columns in one workgroup,
+// the panel held in registers (rows t and t + 1024 of thread t), instead of
+// one launch per column.  Same pivot rule (largest |entry| over the rows
+// r >= c, ties to the smaller row) and the same exchange step as
+// gj_panel_step_kernel, column after column with workgroup barriers; the
+// panel is read from A and written, eliminated, to P (column-major n x kb).
+constexpr int kGjSmallNb = 16;
+constexpr int kGjSmallThreads = 1024;
+constexpr int kGjSmallR = 2;
+constexpr int64_t kGjSmallRows = (int64_t)kGjSmallThreads * kGjSmallR;
+
+// argmax of |value| over the wave, ties to the smaller row; carries the value
+__device__ __forceinline__ void wave_argmax_val(double& a, int& i, double& val) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const double oa = __shfl_xor(a, off);
+    const int oi = __shfl_xor(i, off);
+    const double ov = __shfl_xor(val, off);
+    if (oa > a || (oa == a && oi < i)) {
+      a = oa;
+      i = oi;
+      val = ov;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kGjSmallThreads) void gj_panel_small_kernel(
+    int64_t n, int64_t k0, int kb, const double* __restrict__ A, double* __restrict__ P,
+    int* __restrict__ piv, int* __restrict__ status) {
+  __shared__ double wa[kGjSmallThreads / 64], wvl[kGjSmallThreads / 64];
+  __shared__ int wi[kGjSmallThreads / 64];
+  __shared__ double oc[kGjSmallNb], op[kGjSmallNb];
+  __shared__ double s_pv;
+  __shared__ int s_p;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  double v[kGjSmallR][kGjSmallNb];
+  int64_t row[kGjSmallR];
+#pragma unroll
+  for (int i = 0; i < kGjSmallR; ++i) {
+    row[i] = t + (int64_t)i * kGjSmallThreads;
+#pragma unroll
+    for (int j = 0; j < kGjSmallNb; ++j)
+      v[i][j] = (row[i] < n && j < kb) ? A[row[i] * n + k0 + j] : 0.0;
+  }
+#pragma unroll
+  for (int jc = 0; jc < kGjSmallNb; ++jc) {
+    if (jc < kb) {  // uniform over the workgroup
+    const int64_t c = k0 + jc;
+    // pivot: largest |entry| of column jc over the rows r >= c
+    double a = -1.0, val = 0.0;
+    int bi = (int)c;
+#pragma unroll
+    for (int i = 0; i < kGjSmallR; ++i) {
+      if (row[i] < n && row[i] >= c) {
+        const double x = fabs(v[i][jc]);
+        if (x > a || (x == a && row[i] < bi)) {
+          a = x;
+          bi = (int)row[i];
+          val = v[i][jc];
+        }
+      }
+    }
+    wave_argmax_val(a, bi, val);
+    if (lane == 0) {
+      wa[w] = a;
+      wi[w] = bi;
+      wvl[w] = val;
+    }
+    __syncthreads();
+    if (t < 64) {
+      double aa = t < kGjSmallThreads / 64 ? wa[t] : -1.0;
+      int ii = t < kGjSmallThreads / 64 ? wi[t] : (int)c;
+      double vv = t < kGjSmallThreads / 64 ? wvl[t] : 0.0;
+      wave_argmax_val(aa, ii, vv);
+      if (t == 0) {
+        const bool sing = !(aa > 0.0);
+        s_p = sing ? (int)c : ii;
+        s_pv = sing ? 1.0 : vv;
+        piv[c] = s_p;
+        if (sing) atomicOr(status, 2);
+      }
+    }
+    __syncthreads();
+    const int64_t p = s_p;
+    // old rows c and p of the panel
+#pragma unroll
+    for (int i = 0; i < kGjSmallR; ++i) {
+      if (row[i] == c) {
+#pragma unroll
+        for (int j = 0; j < kGjSmallNb; ++j) oc[j] = v[i][j];
+      }
+      if (row[i] == p) {
+#pragma unroll
+        for (int j = 0; j < kGjSmallNb; ++j) op[j] = v[i][j];
+      }
+    }
+    __syncthreads();
+    const double dinv = 1.0 / s_pv;
+#pragma unroll
+    for (int i = 0; i < kGjSmallR; ++i) {
+      if (row[i] >= n) continue;
+      const bool isc = row[i] == c, isp = row[i] == p;
+      const double f = isp ? oc[jc] : v[i][jc];
+#pragma unroll
+      for (int j = 0; j < kGjSmallNb; ++j) {
+        const double nc = (j == jc ? 1.0 : op[j]) * dinv;
+        double out;
+        if (isc) {
+          out = nc;
+        } else {
+          double base = isp ? oc[j] : v[i][j];
+          if (j == jc) base = 0.0;
+          out = base - f * nc;
+        }
+        v[i][j] = out;
+      }
+    }
+    __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kGjSmallR; ++i) {
+    if (row[i] >= n) continue;
+#pragma unroll
+    for (int j = 0; j < kGjSmallNb; ++j)
+      if (j < kb) P[(int64_t)j * n + row[i]] = v[i][j];
+  }
+}
+
 // row swaps of the panel applied to column j (outside the panel), in order;
 // then T = rows K of that column
 __global__ void gj_rowswap_copy_kernel(int64_t n, int64_t k0, int kb, double* __restrict__ A,
@@ -1036,18 +1165,28 @@ hipError_t coarse_invert(int64_t n, double* A, double* work, int* piv, int* stat
   int* bi[2] = {(int*)(work + (int64_t)3 * kGjNb * n + 2 * nblk),
                 (int*)(work + (int64_t)3 * kGjNb * n + 2 * nblk) + nblk};
   const unsigned nb = (unsigned)((n + 255) / 256);
-  for (int64_t k0 = 0; k0 < n; k0 += kGjNb) {
-    const int kb = (int)((n - k0) < kGjNb ? (n - k0) : kGjNb);
-    hipLaunchKernelGGL(gj_panel_in_kernel, dim3(nb), dim3(256), 0, s, n, k0, kb, A, P[0]);
-    hipLaunchKernelGGL(gj_partials0_kernel, dim3((unsigned)nblk), dim3(64), 0, s, n, k0,
-                       (const double*)P[0], bv[0], bi[0]);
-    for (int jc = 0; jc < kb; ++jc) {
-      const int a = jc & 1, b = a ^ 1;
-      hipLaunchKernelGGL(gj_panel_step_kernel, dim3((unsigned)nblk), dim3(256), 0, s, n, k0, kb, jc,
-                         (const double*)P[a], P[b], (const double*)bv[a], (const int*)bi[a], bv[b],
-                         bi[b], nblk, piv, status);
+  // small matrices: narrow panels eliminated in one workgroup each
+  const bool small = n <= kGjSmallRows;
+  const int width = small ? kGjSmallNb : kGjNb;
+  for (int64_t k0 = 0; k0 < n; k0 += width) {
+    const int kb = (int)((n - k0) < width ? (n - k0) : width);
+    double* Pf;
+    if (small) {
+      hipLaunchKernelGGL(gj_panel_small_kernel, dim3(1), dim3(kGjSmallThreads), 0, s, n, k0, kb,
+                         (const double*)A, P[0], piv, status);
+      Pf = P[0];
+    } else {
+      hipLaunchKernelGGL(gj_panel_in_kernel, dim3(nb), dim3(256), 0, s, n, k0, kb, A, P[0]);
+      hipLaunchKernelGGL(gj_partials0_kernel, dim3((unsigned)nblk), dim3(64), 0, s, n, k0,
+                         (const double*)P[0], bv[0], bi[0]);
+      for (int jc = 0; jc < kb; ++jc) {
+        const int a = jc & 1, b = a ^ 1;
+        hipLaunchKernelGGL(gj_panel_step_kernel, dim3((unsigned)nblk), dim3(256), 0, s, n, k0, kb,
+                           jc, (const double*)P[a], P[b], (const double*)bv[a], (const int*)bi[a],
+                           bv[b], bi[b], nblk, piv, status);
+      }
+      Pf = P[kb & 1];
     }
-    double* Pf = P[kb & 1];
     const int64_t m = n - kb;
     if (m > 0) {
       hipLaunchKernelGGL(gj_rowswap_copy_kernel, dim3(nb), dim3(256), 0, s, n, k0, kb, A, piv, T);
