@@ -298,9 +298,9 @@ template <typename T, typename Entry>
 __global__ __launch_bounds__(64) void patch_kernel(Grid g, Entry entry, const double* __restrict__ S,
                                                    const uint16_t* __restrict__ masks,
                                                    T* __restrict__ inv, int* status) {
-  __shared__ double A[kNst][2 * kNst + 1];
-  __shared__ double fac[kNst];
+  __shared__ double A[kNst][kNst + 1];
   __shared__ double Mref[81];
+  __shared__ int s_piv[kNst];  // lane (row of the patch matrix) that is the pivot of step k
   const int64_t K = blockIdx.x;
   const int cx = (int)(K % g.nx), cy = (int)(K / g.nx);
   const int t = threadIdx.x;
@@ -326,56 +326,62 @@ __global__ __launch_bounds__(64) void patch_kernel(Grid g, Entry entry, const do
       v += patch_cip(g, S, 2, cx, cy, r, c);
     }
     A[r][c] = v;
-    A[r][kNst + c] = (r == c) ? 1.0 : 0.0;
   }
   __syncthreads();
-  // Gauss-Jordan with partial pivoting on [A | I]; lane t owns columns t and
-  // t + 64 of the augmented matrix, the pivot comes from a wave reduction
+  // Gauss-Jordan with partial pivoting, the rows in registers: lane t < 42
+  // holds row t.  Pivot rows are marked, not exchanged (lane p_k is the pivot
+  // of step k: largest |entry| of the current column among the rows not yet
+  // used, ties to the smaller row), and every step shifts each row left by
+  // one column and appends the new column of the inverse, so the current
+  // column is always element 0.  At the end lane p_k holds row k of the
+  // inverse, and register column j is its column p_j.
+  const bool act = t < kNst;
+  double row[kNst];
+#pragma unroll
+  for (int c = 0; c < kNst; ++c) row[c] = act ? A[t][c] : 0.0;
+  bool used = !act;
+  int mystep = 0;
   bool singular = false;
   for (int k = 0; k < kNst; ++k) {
-    // pivot: largest |A[r][k]|, r >= k (the lowest row among equal values)
-    double bv = -1.0;
-    int bi = k;
-    if (t >= k && t < kNst) {
-      bv = fabs(A[t][k]);
-      bi = t;
-    }
+    double a = used ? -1.0 : fabs(row[0]);
+    int bi = used ? 64 : t;
     for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(bv, off);
+      const double oa = __shfl_xor(a, off);
       const int oi = __shfl_xor(bi, off);
-      if (ov > bv || (ov == bv && oi < bi)) {
-        bv = ov;
+      if (oa > a || (oa == a && oi < bi)) {
+        a = oa;
         bi = oi;
       }
     }
-    const int p = bi;
-    if (!(bv > 0.0)) singular = true;
-    __syncthreads();
-    for (int c = t; c < 2 * kNst; c += 64) {
-      const double tmp = A[k][c];
-      A[k][c] = A[p][c];
-      A[p][c] = tmp;
+    const int p = __builtin_amdgcn_readfirstlane(bi);
+    if (!(a > 0.0)) singular = true;
+    if (t == p) {
+      used = true;
+      mystep = k;
     }
-    __syncthreads();
-    const double piv = singular ? 1.0 : A[k][k];
-    __syncthreads();
-    for (int c = t; c < 2 * kNst; c += 64) A[k][c] /= piv;
-    if (t < kNst) fac[t] = (t == k) ? 0.0 : A[t][k];
-    __syncthreads();
-    for (int c = t; c < 2 * kNst; c += 64) {
-      const double akc = A[k][c];
-      for (int r = 0; r < kNst; ++r)
-        if (r != k) A[r][c] -= fac[r] * akc;
+    if (t == 0) s_piv[k] = p;
+    const double pv = singular ? 1.0 : __shfl(row[0], p);
+    const double dinv = 1.0 / pv;
+    const double f = row[0];
+    const bool isp = t == p;
+#pragma unroll
+    for (int j = 1; j < kNst; ++j) {
+      const double pj = __shfl(row[j], p);
+      row[j - 1] = isp ? row[j] * dinv : row[j] - f * (pj * dinv);
     }
-    __syncthreads();
+    row[kNst - 1] = isp ? dinv : -f * dinv;
   }
+  __syncthreads();
   if (singular && t == 0) atomicOr(status, 1);
   // store the inverse column-major, dropped rows/columns zeroed
   T* out = inv + patch_slot(g, cx, cy) * (kNst * kNst);
-  for (int e = t; e < kNst * kNst; e += 64) {
-    const int c = e / kNst, r = e % kNst;
-    const bool z = dropped(mask, r) || dropped(mask, c);
-    out[e] = z ? (T)0 : (T)A[r][kNst + c];
+  if (act) {
+#pragma unroll
+    for (int j = 0; j < kNst; ++j) {
+      const int col = s_piv[j];
+      const bool z = dropped(mask, mystep) || dropped(mask, col);
+      out[col * kNst + mystep] = z ? (T)0 : (T)row[j];
+    }
   }
 }
 
