@@ -639,7 +639,8 @@ __global__ void pin_kernel(int64_t n, double* A, const int64_t* pin, int npin) {
 // Blocked Gauss-Jordan inversion, in place, partial row pivoting.
 // Panels of kGjNb columns K: (1) the panel is copied to a contiguous
 // column-major buffer P (n x kb) and eliminated column by column over all
-// rows (one launch per column, below); (2) its row swaps
+// rows (one launch per column, below; for n <= kGjSmallRows panels of
+// kGjSmallNb columns are eliminated in one workgroup instead); (2) its row swaps
 // are applied to every other column; (3) with T = rows K of the other columns,
 // every other column is updated as A[:,C] = [0 on rows K; A[O,C]] + P T, which
 // is the block form of the Gauss-Jordan step; (4) the panel is written back.
