@@ -106,6 +106,8 @@ size_t layout(pns_ctx* c, bool bind) {
   c->gr = take(g0.nst * es);
   c->gd = take(g0.nst * es);
   c->status = (int*)take(sizeof(int) * 4);
+  // 42 results per cell of the largest coarse level
+  if (c->nlev >= 2) c->slot2 = take(c->lev[1].g.nc * kNst * es);
   for (int l = 0; l < c->nlev; ++l) {
     Level& L = c->lev[l];
     const bool coarsest = (l == c->nlev - 1);
@@ -172,6 +174,14 @@ struct SmoothScratch {
   double* cip;
 };
 
+// The coarse 2D levels sum their patch results through per-patch slots and a
+// node gather (two launches a step); level 0 keeps the colour launches.
+template <typename T>
+T* coarse_slot(const pns_ctx* c, int l, const SmoothScratch* sc) {
+  if (c->dim == 3 || l == 0) return nullptr;
+  return (T*)(sc ? sc->slot : c->slot2);
+}
+
 template <typename T>
 hipError_t defect(pns_ctx* c, int l, const T* b, const T* x, T* y,
                   const SmoothScratch* sc = nullptr) {
@@ -190,7 +200,8 @@ hipError_t defect(pns_ctx* c, int l, const T* b, const T* x, T* y,
     return launch_cip<T>(L.g, c->model, c->disc.tau, (const T*)c->uk, L.g.nv, x, y, -1.0,
                          sc ? sc->cip : c->cipG, c->stream);
   }
-  hipError_t e = launch_ebe_apply<T>(L.g, (const T*)L.E, x, b, y, 1, c->sweep_var[l], c->stream);
+  hipError_t e = launch_ebe_apply<T>(L.g, (const T*)L.E, x, b, y, 1, c->sweep_var[l],
+                                     coarse_slot<T>(c, l, sc), c->stream);
   if (e != hipSuccess || !(c->model.gamma_cip > 0.0)) return e;
   return launch_cip_level<T>(L.g, L.S, x, y, -1.0, sc ? sc->cip : c->cipG, c->stream);
 }
@@ -211,7 +222,8 @@ hipError_t apply_level(pns_ctx* c, int l, const T* x, T* y) {
     return launch_cip<T>(L.g, c->model, c->disc.tau, (const T*)c->uk, L.g.nv, x, y, 1.0, c->cipG,
                          c->stream);
   }
-  hipError_t e = launch_ebe_apply<T>(L.g, (const T*)L.E, x, x, y, 0, c->sweep_var[l], c->stream);
+  hipError_t e = launch_ebe_apply<T>(L.g, (const T*)L.E, x, x, y, 0, c->sweep_var[l],
+                                     coarse_slot<T>(c, l, nullptr), c->stream);
   if (e != hipSuccess || !(c->model.gamma_cip > 0.0)) return e;
   return launch_cip_level<T>(L.g, L.S, x, y, 1.0, c->cipG, c->stream);
 }
@@ -253,7 +265,8 @@ hipError_t smooth(pns_ctx* c, int l, int nsweeps, double omega, const T* r, T* d
                        ? launch_patch_sweep_c<T>(L.g, (const T*)L.inv, res, d, omega,
                                                  c->sweep_var[l], c->stream)
                        : launch_patch_sweep<T>(L.g, (const T*)L.inv, res, d, omega,
-                                               c->sweep_var[l], c->stream);
+                                               c->sweep_var[l], coarse_slot<T>(c, l, sc),
+                                               c->stream);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -290,16 +303,17 @@ hipError_t vcycle_level(pns_ctx* c, int l, int nu1, int nu2, double omega, const
 }
 
 // Autotuner of the patch sweeps: on every level, each variant of that level's
-// patch form runs one additive step (4 colour launches) on zero vectors, once
-// to warm up and three times timed with events on the context stream; the
-// fastest is kept.  The variants compute the same step, so the choice changes
-// the time and the summation order within a patch only.  The choice depends on
-// the level's shape, not on its data: it is made once per (cells in x, cells
-// in y, patch form, precision) in a process and reused by later setups and
-// contexts (smoother refreshes inside a solve, served requests).
+// patch form runs one additive step (level 0: 4 colour launches; coarse levels:
+// slot launch + gather) on zero vectors, once to warm up and three times timed
+// with events on the context stream; the fastest is kept.  The variants compute
+// the same step, so the choice changes the time and the summation order within
+// a patch only.  The choice depends on the level's shape, not on its data: it
+// is made once per (cells in x, cells in y, patch form, precision, colour or
+// slot form) in a process and reused by later setups and contexts (smoother
+// refreshes inside a solve, served requests).
 struct TunedShapes {
   std::mutex mu;
-  std::map<std::tuple<int, int, int, int>, int> best;
+  std::map<std::tuple<int, int, int, int, int>, int> best;
 };
 TunedShapes& tuned_shapes() {
   static TunedShapes t;
@@ -315,13 +329,13 @@ int autotune_sweeps(pns_ctx* c) {
     bool all = true;
     for (int l = 0; l < c->nlev && all; ++l) {
       const Grid& g = c->lev[l].g;
-      auto it = ts.best.find({g.nx, g.ny, complex_patches(c, l) ? 1 : 0, (int)c->es});
+      auto it = ts.best.find({g.nx, g.ny, complex_patches(c, l) ? 1 : 0, (int)c->es, l >= 1 ? 1 : 0});
       if (it == ts.best.end()) all = false;
     }
     if (all) {
       for (int l = 0; l < c->nlev; ++l) {
         const Grid& g = c->lev[l].g;
-        c->sweep_var[l] = ts.best[{g.nx, g.ny, complex_patches(c, l) ? 1 : 0, (int)c->es}];
+        c->sweep_var[l] = ts.best[{g.nx, g.ny, complex_patches(c, l) ? 1 : 0, (int)c->es, l >= 1 ? 1 : 0}];
       }
       return PNS_OK;
     }
@@ -348,7 +362,8 @@ int autotune_sweeps(pns_ctx* c) {
     for (int v = 0; v < nv && rc == PNS_OK; ++v) {
       auto run = [&]() {
         return cx ? launch_patch_sweep_c<T>(L.g, (const T*)L.inv, res, d, 1.0, v, c->stream)
-                  : launch_patch_sweep<T>(L.g, (const T*)L.inv, res, d, 1.0, v, c->stream);
+                  : launch_patch_sweep<T>(L.g, (const T*)L.inv, res, d, 1.0, v,
+                                          coarse_slot<T>(c, l, nullptr), c->stream);
       };
       float ms = 0.0f;
       if (run() != hipSuccess || hipEventRecord(e0, c->stream) != hipSuccess ||
@@ -373,7 +388,7 @@ int autotune_sweeps(pns_ctx* c) {
     std::lock_guard<std::mutex> lk(ts.mu);
     for (int l = 0; l < c->nlev; ++l) {
       const Grid& g = c->lev[l].g;
-      ts.best[{g.nx, g.ny, complex_patches(c, l) ? 1 : 0, (int)c->es}] = c->sweep_var[l];
+      ts.best[{g.nx, g.ny, complex_patches(c, l) ? 1 : 0, (int)c->es, l >= 1 ? 1 : 0}] = c->sweep_var[l];
     }
   }
   return rc;
@@ -652,7 +667,7 @@ size_t static_scratch_need(const pns_ctx* c, int level) {
   if (c->dim == 3)
     need += up(L.g.nc * 170 * c->es);
   else
-    need += (level == 0 ? up(cell_apply_edge_doubles(L.g) * 8) : 0) +
+    need += (level == 0 ? up(cell_apply_edge_doubles(L.g) * 8) : up(L.g.nc * kNst * c->es)) +
             (c->model.gamma_cip > 0.0 ? up(cip_face_doubles(L.g) * 8) : 0);
   return need;
 }
@@ -1023,11 +1038,15 @@ int pns_vanka_smooth_static(pns_ctx* ctx, int level, int n_sweeps, double omega,
       (ctx->dim == 2 && level == 0)
           ? (cell_apply_edge_doubles(L.g) * 8 + kAlign - 1) / kAlign * kAlign
           : 0;
+  const size_t slot_bytes =
+      (ctx->dim == 2 && level >= 1) ? (L.g.nc * kNst * ctx->es + kAlign - 1) / kAlign * kAlign
+                                    : 0;
   SmoothScratch sc;
   sc.res = base;
   sc.edge = (ctx->dim == 2 && level == 0) ? (double*)((char*)base + res_bytes) : nullptr;
-  sc.slot = ctx->dim == 3 ? (void*)((char*)base + res_bytes) : nullptr;
-  sc.cip = ctx->dim == 2 ? (double*)((char*)base + res_bytes + edge_bytes) : nullptr;
+  // 3D: per-cell results of the action; 2D coarse levels: per-patch results
+  sc.slot = (ctx->dim == 3 || level >= 1) ? (void*)((char*)base + res_bytes) : nullptr;
+  sc.cip = ctx->dim == 2 ? (double*)((char*)base + res_bytes + edge_bytes + slot_bytes) : nullptr;
   if (ctx->es == 8)
     PNS_HIP(ctx, smooth<double>(ctx, level, n_sweeps, omega, (const double*)r, (double*)d, false,
                                 &sc));

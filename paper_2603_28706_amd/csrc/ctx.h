@@ -74,6 +74,7 @@ struct pns_ctx {
   double* cipG = nullptr;   // 2D CIP: per-face weighted jumps
   double* Sr = nullptr;     // 2D CIP face matrices at t_rep (time-diagonal patches)
   void* E3 = nullptr;      // 3D: per-cell results of the action (170 per cell)
+  void* slot2 = nullptr;   // 2D: per-patch results of the coarse-level sweeps and actions
   // 3D FP64 residual: state copy, left-trace term, per-cell slots of the action
   double* r3u = nullptr;
   double* r3b = nullptr;

@@ -294,16 +294,18 @@ hipError_t coarse_invert(int64_t n, double* A, double* work, int* piv, int* stat
 // smooth.hip
 // coarse-level action with the transposed element matrices in patch-slot
 // order (mode 0: y = A x, mode 1: y = b - A x), through the real-patch sweep
-// kernel of variant `variant`
+// kernel of variant `variant`; with `slot` (nc x 42 values of scratch) one
+// launch over all cells and a node gather, else four colour launches
 template <typename T>
 hipError_t launch_ebe_apply(const Grid& g, const T* E, const T* x, const T* b, T* y, int mode,
-                            int variant, hipStream_t s);
+                            int variant, T* slot, hipStream_t s);
 // additive Vanka step with sweep variant `variant` (real 42x42 or complex 21x21
 // patches); variants differ in workgroup size, loads in flight and rows per
-// lane, not in what they compute
+// lane, not in what they compute; real patches with `slot` (nc x 42 values of
+// scratch) sum through the per-patch slots and the node gather
 template <typename T>
 hipError_t launch_patch_sweep(const Grid& g, const T* inv, const T* res, T* d, double omega,
-                              int variant, hipStream_t s);
+                              int variant, T* slot, hipStream_t s);
 template <typename T>
 hipError_t launch_patch_sweep_c(const Grid& g, const T* inv, const T* res, T* d, double omega,
                                 int variant, hipStream_t s);

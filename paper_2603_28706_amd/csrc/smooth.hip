@@ -1,16 +1,19 @@
 // Per-iteration smoother and transfer kernels (Sec. 6.3):
 // * coarse-level operator action with Galerkin element matrices: the
 //   transposed (column-major) element matrices are stored like the patch
-//   inverses, so the sweep kernels below stream them (omega = +-1), four colour
-//   launches (cells of one parity class share no unknown) adding into y
-//   initialised to 0 or b;
+//   inverses, so the sweep kernels below stream them (omega = +-1);
 // * additive Vanka update d += omega sum_K R_K^T A_K^{-1} R_K res,
 //   eq. (stmg-vanka-update): the stored patch inverses streamed column by
 //   column (level 0: complex 21x21 time-diagonal form, three patches per wave;
-//   real 42x42: one patch per wave, or three with two rows per lane), four
-//   colour launches so that patches updating d at the same time share no
-//   unknown; each form comes in variants of workgroup size and loads in
-//   flight, among which the smoother setup picks the fastest on the device;
+//   real 42x42: one patch per wave, or three with two rows per lane); each
+//   form comes in variants of workgroup size and loads in flight, among which
+//   the smoother setup picks the fastest on the device;
+// * two ways to sum the per-patch results: four colour launches adding into
+//   the vector (patches of one parity class share no unknown), or one launch
+//   over every patch writing its 42 results to the patch's slot, then a node
+//   gather summing the slots of the cells around each unknown in a fixed order
+//   (two launches instead of four, used on the coarse levels, where the colour
+//   launches are short);
 // * restriction P^T and prolongation P of the nested Q2 / P1disc spaces;
 // * dense coarsest solve with the stored inverse.
 #include <type_traits>
@@ -31,9 +34,53 @@ __device__ __forceinline__ int64_t gidx(const Grid& g, int cx, int cy, int l) {
   return (int64_t)mu * g.ns + g.nv + 3 * ((int64_t)cy * g.nx + cx) + (i - 18);
 }
 
-// Real 42x42 patches, one wave per patch of the colour class (px, py), lane r
-// < 42 forms row r; WAVES patches per workgroup, UNROLL column loads in flight.
-template <typename T, int WAVES, int UNROLL>
+// Cell of the patch stored at position q (0 <= q < nc) of the colour-major
+// order of patch_slot: the inverse of that cell.
+__device__ __forceinline__ void slot_cell(const Grid& g, int64_t q, int& cx, int& cy) {
+  const int64_t ncx0 = (g.nx + 1) / 2, ncx1 = g.nx / 2, ncy0 = (g.ny + 1) / 2;
+  int px = 0, py = 0;
+  int64_t w = ncx0;
+  if (q >= ncx0 * ncy0) {
+    q -= ncx0 * ncy0;
+    if (q < ncx1 * ncy0) {
+      px = 1;
+      w = ncx1;
+    } else {
+      q -= ncx1 * ncy0;
+      if (q < ncx0 * (g.ny / 2)) {
+        py = 1;
+      } else {
+        q -= ncx0 * (g.ny / 2);
+        px = py = 1;
+        w = ncx1;
+      }
+    }
+  }
+  cx = px + 2 * (int)(q % w);
+  cy = py + 2 * (int)(q / w);
+}
+
+// Patch of a launch: in a colour launch the pid-th cell of the colour class
+// (px, py); in a slot launch (SLOT) the cell whose inverse sits at position
+// pid, every patch of the level in one launch.
+template <bool SLOT>
+__device__ __forceinline__ bool launch_cell(const Grid& g, int64_t pid, int px, int py, int ncx,
+                                            int ncy, int& cx, int& cy) {
+  if (SLOT) {
+    if (pid >= g.nc) return false;
+    slot_cell(g, pid, cx, cy);
+    return true;
+  }
+  if (pid >= (int64_t)ncx * ncy) return false;
+  cx = px + 2 * (int)(pid % ncx);
+  cy = py + 2 * (int)(pid / ncx);
+  return true;
+}
+
+// Real 42x42 patches, one wave per patch, lane r < 42 forms row r; WAVES
+// patches per workgroup, UNROLL column loads in flight.  Colour launch: d[gi]
+// += omega * row; slot launch: out[42 pid + r] = omega * row.
+template <typename T, int WAVES, int UNROLL, bool SLOT>
 __global__ __launch_bounds__(64 * WAVES) void patch_sweep_kernel(Grid g, const T* __restrict__ inv,
                                                                  const T* __restrict__ res,
                                                                  T* __restrict__ d, T omega,
@@ -42,16 +89,12 @@ __global__ __launch_bounds__(64 * WAVES) void patch_sweep_kernel(Grid g, const T
   __shared__ T rhs[WAVES][kNst];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t pid = (int64_t)blockIdx.x * WAVES + w;
-  const bool active = pid < (int64_t)ncx * ncy;
   int cx = 0, cy = 0;
+  const bool active = launch_cell<SLOT>(g, pid, px, py, ncx, ncy, cx, cy);
   int64_t gi = 0;
-  if (active) {
-    cx = px + 2 * (int)(pid % ncx);
-    cy = py + 2 * (int)(pid / ncx);
-    if (lane < kNst) {
-      gi = gidx(g, cx, cy, lane);
-      rhs[w][lane] = res[gi];
-    }
+  if (active && lane < kNst) {
+    gi = gidx(g, cx, cy, lane);
+    rhs[w][lane] = res[gi];
   }
   __syncthreads();
   if (!active || lane >= kNst) return;
@@ -59,13 +102,16 @@ __global__ __launch_bounds__(64 * WAVES) void patch_sweep_kernel(Grid g, const T
   T acc = 0;
 #pragma unroll UNROLL
   for (int j = 0; j < kNst; ++j) acc += A[j * kNst + lane] * rhs[w][j];
-  d[gi] += omega * acc;
+  if (SLOT)
+    d[pid * kNst + lane] = omega * acc;
+  else
+    d[gi] += omega * acc;
 }
 
 // Real 42x42 patches, three patches per wave, lane 21 p + i forms rows 2i and
 // 2i + 1 of patch p from paired loads (63 of 64 lanes busy); WAVES waves per
-// workgroup, UNROLL column loads in flight.
-template <typename T, int WAVES, int UNROLL>
+// workgroup, UNROLL column loads in flight; colour or slot launch as above.
+template <typename T, int WAVES, int UNROLL, bool SLOT>
 __global__ __launch_bounds__(64 * WAVES) void patch_sweep2_kernel(Grid g, const T* __restrict__ inv,
                                                                   const T* __restrict__ res,
                                                                   T* __restrict__ d, T omega,
@@ -76,12 +122,10 @@ __global__ __launch_bounds__(64 * WAVES) void patch_sweep2_kernel(Grid g, const 
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int p = lane / 21, i = lane % 21;
   const int64_t pid = ((int64_t)blockIdx.x * WAVES + w) * 3 + p;
-  const bool active = lane < 63 && pid < (int64_t)ncx * ncy;
   int cx = 0, cy = 0;
+  const bool active = lane < 63 && launch_cell<SLOT>(g, pid, px, py, ncx, ncy, cx, cy);
   int64_t g0 = 0, g1 = 0;
   if (active) {
-    cx = px + 2 * (int)(pid % ncx);
-    cy = py + 2 * (int)(pid / ncx);
     g0 = gidx(g, cx, cy, 2 * i);
     g1 = gidx(g, cx, cy, 2 * i + 1);
     rhs[w][p][2 * i] = res[g0];
@@ -99,8 +143,13 @@ __global__ __launch_bounds__(64 * WAVES) void patch_sweep2_kernel(Grid g, const 
     a0 += c.x * r;
     a1 += c.y * r;
   }
-  d[g0] += omega * a0;
-  d[g1] += omega * a1;
+  if (SLOT) {
+    d[pid * kNst + 2 * i] = omega * a0;
+    d[pid * kNst + 2 * i + 1] = omega * a1;
+  } else {
+    d[g0] += omega * a0;
+    d[g1] += omega * a1;
+  }
 }
 
 // level-0 patches in time-diagonal form (complex 21x21 inverse): three
@@ -146,6 +195,51 @@ template <typename T>
 __global__ void copy_kernel(int64_t n, const T* __restrict__ x, T* __restrict__ y) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] = x[i];
+}
+
+// y = base + sum of the slot values of every cell whose patch holds the
+// unknown (base = 0 when null; y may be base): a velocity node on a cell
+// corner is in up to four patches, on an edge in up to two, inside a cell in
+// one; a pressure coefficient in its cell's.  Cells are visited row by row, so
+// the order of the sum is fixed.
+template <typename T>
+__global__ __launch_bounds__(256) void slot_gather_kernel(Grid g, const T* __restrict__ slot,
+                                                          const T* base, T* y) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= g.nst) return;
+  const int mu = (int)(r / g.ns);
+  const int64_t s = r % g.ns;
+  double acc = base ? (double)base[r] : 0.0;
+  if (s < g.nv) {
+    const int comp = (int)(s / g.nn);
+    const int64_t node = s % g.nn;
+    const int NX = 2 * g.nx + 1;
+    const int ix = (int)(node % NX), iy = (int)(node / NX);
+    // cells touching the node along each axis and the node's local index there
+    int cxs[2], axs[2], cys[2], ays[2], ncx = 0, ncy = 0;
+    if (ix & 1) {
+      cxs[0] = ix >> 1; axs[0] = 1; ncx = 1;
+    } else {
+      if (ix > 0) { cxs[ncx] = (ix >> 1) - 1; axs[ncx] = 2; ++ncx; }
+      if (ix < 2 * g.nx) { cxs[ncx] = ix >> 1; axs[ncx] = 0; ++ncx; }
+    }
+    if (iy & 1) {
+      cys[0] = iy >> 1; ays[0] = 1; ncy = 1;
+    } else {
+      if (iy > 0) { cys[ncy] = (iy >> 1) - 1; ays[ncy] = 2; ++ncy; }
+      if (iy < 2 * g.ny) { cys[ncy] = iy >> 1; ays[ncy] = 0; ++ncy; }
+    }
+    const int loc = mu * kNs + comp * 9;
+    for (int b = 0; b < ncy; ++b)
+      for (int a = 0; a < ncx; ++a)
+        acc += (double)slot[patch_slot(g, cxs[a], cys[b]) * kNst + loc + 3 * ays[b] + axs[a]];
+  } else {
+    const int64_t cell = (s - g.nv) / 3;
+    const int j = (int)((s - g.nv) % 3);
+    const int cx = (int)(cell % g.nx), cy = (int)(cell / g.nx);
+    acc += (double)slot[patch_slot(g, cx, cy) * kNst + mu * kNs + 18 + j];
+  }
+  y[r] = (T)acc;
 }
 
 __device__ __forceinline__ double w1d(int I, int i) {
@@ -345,21 +439,51 @@ hipError_t sweep_colours(K kern, int threads, int ppb, const Grid& g, const T* i
   return hipGetLastError();
 }
 
+// One slot launch over every patch of the level (PPB patches per workgroup),
+// writing omega A_K^{-1} R_K res to the patch slots, then the node gather y =
+// base + sum of the slots.
+template <typename T, typename K>
+hipError_t sweep_slots(K kern, int threads, int ppb, const Grid& g, const T* inv, const T* res,
+                       const T* base, T* y, double omega, T* slot, hipStream_t s) {
+  if (g.nc > 0)
+    hipLaunchKernelGGL(kern, dim3(nblk(g.nc, ppb)), dim3(threads), 0, s, g, inv, res, slot,
+                       (T)omega, 0, 0, 0, 0);
+  hipLaunchKernelGGL(slot_gather_kernel<T>, dim3(nblk(g.nst, 256)), dim3(256), 0, s, g,
+                     (const T*)slot, base, y);
+  return hipGetLastError();
+}
+
+// Launchers of the variants: four colour launches adding into d (slot null),
+// or the slot launch and gather with d = base + sum (slot non-null; base is d
+// for a sweep, b or null for the coarse-level action).
 template <typename T, int W, int U>
-hipError_t sweep_r1(const Grid& g, const T* inv, const T* res, T* d, double omega, hipStream_t s) {
-  return sweep_colours<T>(patch_sweep_kernel<T, W, U>, 64 * W, W, g, inv, res, d, omega, s);
+hipError_t sweep_r1(const Grid& g, const T* inv, const T* res, const T* base, T* d, double omega,
+                    T* slot, hipStream_t s) {
+  if (slot)
+    return sweep_slots<T>(patch_sweep_kernel<T, W, U, true>, 64 * W, W, g, inv, res, base, d,
+                          omega, slot, s);
+  return sweep_colours<T>(patch_sweep_kernel<T, W, U, false>, 64 * W, W, g, inv, res, d, omega, s);
 }
 template <typename T, int W, int U>
-hipError_t sweep_r2(const Grid& g, const T* inv, const T* res, T* d, double omega, hipStream_t s) {
-  return sweep_colours<T>(patch_sweep2_kernel<T, W, U>, 64 * W, 3 * W, g, inv, res, d, omega, s);
+hipError_t sweep_r2(const Grid& g, const T* inv, const T* res, const T* base, T* d, double omega,
+                    T* slot, hipStream_t s) {
+  if (slot)
+    return sweep_slots<T>(patch_sweep2_kernel<T, W, U, true>, 64 * W, 3 * W, g, inv, res, base,
+                          d, omega, slot, s);
+  return sweep_colours<T>(patch_sweep2_kernel<T, W, U, false>, 64 * W, 3 * W, g, inv, res, d,
+                          omega, s);
 }
 template <typename T, int W, int U>
-hipError_t sweep_c(const Grid& g, const T* inv, const T* res, T* d, double omega, hipStream_t s) {
+hipError_t sweep_c(const Grid& g, const T* inv, const T* res, const T* base, T* d, double omega,
+                   T* slot, hipStream_t s) {
+  // the complex form lives on level 0 only, which keeps the colour launches
+  if (slot) return hipErrorInvalidValue;
   return sweep_colours<T>(patch_sweep_c_kernel<T, W, U>, 64 * W, 3 * W, g, inv, res, d, omega, s);
 }
 
 template <typename T>
-using SweepFn = hipError_t (*)(const Grid&, const T*, const T*, T*, double, hipStream_t);
+using SweepFn = hipError_t (*)(const Grid&, const T*, const T*, const T*, T*, double, T*,
+                               hipStream_t);
 
 // variant tables: {launcher, waves per workgroup, column loads in flight, rows per lane}
 template <typename T>
@@ -399,31 +523,34 @@ void sweep_variant_shape(bool complex_form, int v, int out[3]) {
 
 template <typename T>
 hipError_t launch_patch_sweep(const Grid& g, const T* inv, const T* res, T* d, double omega,
-                              int variant, hipStream_t s) {
-  return real_variants<T>()[variant].fn(g, inv, res, d, omega, s);
+                              int variant, T* slot, hipStream_t s) {
+  return real_variants<T>()[variant].fn(g, inv, res, d, d, omega, slot, s);
 }
 
 template <typename T>
 hipError_t launch_patch_sweep_c(const Grid& g, const T* inv, const T* res, T* d, double omega,
                                 int variant, hipStream_t s) {
-  return complex_variants<T>()[variant].fn(g, inv, res, d, omega, s);
+  return complex_variants<T>()[variant].fn(g, inv, res, d, d, omega, nullptr, s);
 }
 
 // Coarse-level action from the transposed element matrices, stored per cell
-// at its patch slot: y = 0 (mode 0) or b (mode 1), then y += sign E_c x_c per
-// cell, which is the additive patch step with the element matrices in place of
-// the inverses (omega = sign), in the four colour passes of the level's sweep
-// variant (cells of one colour share no unknown)
+// at its patch slot: y = 0 (mode 0) or b (mode 1), plus sign E_c x_c summed
+// over the cells, which is the additive patch step with the element matrices
+// in place of the inverses (omega = sign) in the level's sweep variant: with
+// the per-cell slots and the node gather (slot non-null), else y set first and
+// the four colour passes adding into it (cells of one colour share no unknown)
 template <typename T>
 hipError_t launch_ebe_apply(const Grid& g, const T* E, const T* x, const T* b, T* y, int mode,
-                            int variant, hipStream_t s) {
+                            int variant, T* slot, hipStream_t s) {
+  const double sign = mode == 0 ? 1.0 : -1.0;
+  if (slot) return real_variants<T>()[variant].fn(g, E, x, mode == 0 ? nullptr : b, y, sign, slot, s);
   if (mode == 0)
     hipLaunchKernelGGL(fill_kernel<T>, dim3(nblk(g.nst, 256)), dim3(256), 0, s, g.nst, (T)0, y);
   else
     hipLaunchKernelGGL(copy_kernel<T>, dim3(nblk(g.nst, 256)), dim3(256), 0, s, g.nst, b, y);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return real_variants<T>()[variant].fn(g, E, x, y, mode == 0 ? 1.0 : -1.0, s);
+  return real_variants<T>()[variant].fn(g, E, x, y, y, sign, nullptr, s);
 }
 
 template <typename T>
@@ -459,9 +586,9 @@ hipError_t launch_fill(int64_t n, T v, T* y, hipStream_t s) {
 
 #define PNS_INST(T)                                                                              \
   template hipError_t launch_ebe_apply<T>(const Grid&, const T*, const T*, const T*, T*, int,   \
-                                          int, hipStream_t);                                     \
+                                          int, T*, hipStream_t);                                 \
   template hipError_t launch_patch_sweep<T>(const Grid&, const T*, const T*, T*, double, int,   \
-                                            hipStream_t);                                        \
+                                            T*, hipStream_t);                                    \
   template hipError_t launch_restrict<T>(const Grid&, const Grid&, const T*, T*, hipStream_t);  \
   template hipError_t launch_prolong_add<T>(const Grid&, const Grid&, const T*, T*,             \
                                             hipStream_t);                                        \
