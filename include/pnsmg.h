@@ -264,7 +264,8 @@ int pns_vanka_smooth(pns_ctx* ctx, int level, int n_sweeps, double omega, const 
  * pns_vanka_smooth (same kernels, same arguments, d updated in place), with
  * the buffers that are neither inputs nor outputs -- the defect r - A_l d of
  * each step, the tile-edge partial sums of the quadrilateral level-0 action,
- * the per-cell result slots of the hexahedral actions -- taken from a static
+ * the per-patch result slots of the quadrilateral coarse levels, the per-cell
+ * result slots of the hexahedral actions -- taken from a static
  * device array of the library (64 MiB, one per GPU, held until the process
  * ends) instead of the bound workspace.  Allocates nothing: no hipMalloc, no
  * allocating library call.  Nothing in that array has to start at zero (every
@@ -273,7 +274,8 @@ int pns_vanka_smooth(pns_ctx* ctx, int level, int n_sweeps, double omega, const 
  * threads, or a pns_vanka_smooth_static of another context still running)
  * race; serialise them.  PNS_EINVAL, before any device work, when the level
  * needs more than 64 MiB of scratch (the defect is N_st values of the context
- * precision, plus 2D level 0: 3 KB per 16 x 8 tile; 3D: 170 values per cell;
+ * precision, plus 2D level 0: 3 KB per 16 x 8 tile; 2D coarser levels: 42
+ * values per cell; 3D: 170 values per cell;
  * e.g. a 256 x 256 FP64 level 0 needs 13.2 MB, 512 x 512 FP64 53 MB, 32^3
  * FP64 60 MB), otherwise the errors of pns_vanka_smooth. */
 int pns_vanka_smooth_static(pns_ctx* ctx, int level, int n_sweeps, double omega,
