@@ -266,7 +266,7 @@ hipError_t smooth(pns_ctx* c, int l, int nsweeps, double omega, const T* r, T* d
                                                  c->sweep_var[l], c->stream)
                        : launch_patch_sweep<T>(L.g, (const T*)L.inv, res, d, omega,
                                                c->sweep_var[l], coarse_slot<T>(c, l, sc),
-                                               c->stream);
+                                               c->stream, s == 0 && d_is_zero);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -283,7 +283,11 @@ hipError_t vcycle_level(pns_ctx* c, int l, int nu1, int nu2, double omega, const
                                 : (const T*)(const void*)c->Adense32;
     return launch_dense_gemv<T>(L.g.nst, A, r, d, c->pin, npin, c->stream);
   }
-  if ((e = launch_fill<T>(L.g.nst, (T)0, d, c->stream)) != hipSuccess) return e;
+  // d starts at zero; on a coarse level the first sweep's gather writes all of
+  // it, so only level 0 (colour launches adding into d) needs the fill
+  const bool first_sweep_sets_d = nu1 > 0 && coarse_slot<T>(c, l, nullptr) && l > 0;
+  if (!first_sweep_sets_d && (e = launch_fill<T>(L.g.nst, (T)0, d, c->stream)) != hipSuccess)
+    return e;
   if ((e = smooth<T>(c, l, nu1, omega, r, d, true)) != hipSuccess) return e;
   const T* res = r;
   if (nu1 > 0) {

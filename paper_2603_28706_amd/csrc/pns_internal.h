@@ -302,10 +302,11 @@ hipError_t launch_ebe_apply(const Grid& g, const T* E, const T* x, const T* b, T
 // additive Vanka step with sweep variant `variant` (real 42x42 or complex 21x21
 // patches); variants differ in workgroup size, loads in flight and rows per
 // lane, not in what they compute; real patches with `slot` (nc x 42 values of
-// scratch) sum through the per-patch slots and the node gather
+// scratch) sum through the per-patch slots and the node gather, which with
+// d_zero (d known to be zero on entry) writes d without reading it
 template <typename T>
 hipError_t launch_patch_sweep(const Grid& g, const T* inv, const T* res, T* d, double omega,
-                              int variant, T* slot, hipStream_t s);
+                              int variant, T* slot, hipStream_t s, bool d_zero = false);
 template <typename T>
 hipError_t launch_patch_sweep_c(const Grid& g, const T* inv, const T* res, T* d, double omega,
                                 int variant, hipStream_t s);

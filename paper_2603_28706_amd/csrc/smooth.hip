@@ -345,7 +345,7 @@ __global__ void prolong_add_kernel(Grid gf, Grid gc, const T* __restrict__ dc, T
 // load of r serves kGemvRows rows (r is re-read from cache once per row group,
 // not once per row); pair loads of the rows and of r (n is even, so every row
 // starts pair-aligned), four steps in flight, sums in FP64
-constexpr int kGemvRows = 4;
+constexpr int kGemvRows = 8;
 
 template <typename T>
 __global__ __launch_bounds__(256) void dense_gemv_kernel(int64_t n, const T* __restrict__ Ainv,
@@ -523,8 +523,10 @@ void sweep_variant_shape(bool complex_form, int v, int out[3]) {
 
 template <typename T>
 hipError_t launch_patch_sweep(const Grid& g, const T* inv, const T* res, T* d, double omega,
-                              int variant, T* slot, hipStream_t s) {
-  return real_variants<T>()[variant].fn(g, inv, res, d, d, omega, slot, s);
+                              int variant, T* slot, hipStream_t s, bool d_zero) {
+  // slot form with d = 0 on entry: the gather writes d = sum of the slots
+  return real_variants<T>()[variant].fn(g, inv, res, (slot && d_zero) ? nullptr : d, d, omega,
+                                        slot, s);
 }
 
 template <typename T>
@@ -588,7 +590,7 @@ hipError_t launch_fill(int64_t n, T v, T* y, hipStream_t s) {
   template hipError_t launch_ebe_apply<T>(const Grid&, const T*, const T*, const T*, T*, int,   \
                                           int, T*, hipStream_t);                                 \
   template hipError_t launch_patch_sweep<T>(const Grid&, const T*, const T*, T*, double, int,   \
-                                            T*, hipStream_t);                                    \
+                                            T*, hipStream_t, bool);                              \
   template hipError_t launch_restrict<T>(const Grid&, const Grid&, const T*, T*, hipStream_t);  \
   template hipError_t launch_prolong_add<T>(const Grid&, const Grid&, const T*, T*,             \
                                             hipStream_t);                                        \
